@@ -1,0 +1,397 @@
+/*
+ * Oracle BSDF: the OpenPBR subset used by the path tracer, in FP64.
+ *
+ * The paper adopts the OpenPBR uber-shader (Sec. 4) and supports metallic,
+ * glossy and diffuse surfaces with importance sampling toward the mirror
+ * direction for metals and around the normal for diffuse (Sec. 5.1.3).  It
+ * gives no formulas; the ones below are this project's reading, built from
+ * published models:
+ *
+ *   roughness r -> alpha = r^2; anisotropy a: alpha_t = alpha*sqrt(2/(1+(1-a)^2)),
+ *     alpha_b = (1-a)*alpha_t, both clamped >= 1e-4 (OpenPBR mapping);
+ *     a lobe with r < 1e-3 is a delta lobe.
+ *   GGX D, Smith Lambda, height-correlated G2 = 1/(1+L(o)+L(i)) (Heitz 2014),
+ *     visible-normal sampling (Heitz 2018).
+ *   Dielectric Fresnel: exact unpolarised form (Walter et al. 2007, eq. 22).
+ *   Metal Fresnel: OpenPBR F82-tint.
+ *   Lobes: C coat (dielectric GGX reflection), M metal, I dielectric interface
+ *   (GGX reflection + rough refraction, Walter et al. 2007 eq. 21, with the
+ *   1/eta^2 radiance factor), D Lambert attenuated by the interface Fresnel.
+ *   f = C + [(1-cw) + cw*coat_color*(1-Fc(|mu_i|))(1-Fc(mu_o))]
+ *           * [metalness*M + (1-metalness)*(I + D)].
+ *   Lobe choice pmf at mu_o: w_C = cw*Fc, w_M = Tc*metalness*sw*lum(F82),
+ *   w_I = Tc*(1-metalness)*(Fd + tw*(1-Fd)), w_D = Tc*(1-metalness)*(1-tw)*(1-Fd)*lum(bw*bc),
+ *   Tc = 1 - cw*Fc(mu_o), Fd = sw*F(mu_o, eta).
+ *   Non-delta sampling weight: f_nd*|cos|/sum_k P_k pdf_k (one-sample MIS over lobes).
+ *
+ * Frame: local +z is the surface normal flipped to the side of wo, so mu_o > 0.
+ */
+#include <string.h>
+
+#include "oracle_internal.h"
+
+double ofresnel_diel(double c, double eta) {
+  /* Walter et al. 2007 eq. 22 with c = |cos| on the incident side, eta = n_t/n_i */
+  c = fabs(c);
+  double g2 = eta * eta - 1.0 + c * c;
+  if (g2 < 0.0) return 1.0;
+  double g = sqrt(g2);
+  double a = (g - c) / (g + c);
+  double b = (c * (g + c) - 1.0) / (c * (g - c) + 1.0);
+  return 0.5 * a * a * (1.0 + b * b);
+}
+
+void of82(const omat* m, double mu, double F[3]) {
+  /* OpenPBR F82-tint: Schlick S(mu) corrected so that F(1/7) = specular_color * S(1/7) */
+  const double mb = 1.0 / 7.0;
+  double om = 1.0 - mu;
+  double om5 = om * om * om * om * om;
+  double omb = 1.0 - mb;
+  double omb5 = omb * omb * omb * omb * omb, omb6 = omb5 * omb;
+  for (int c = 0; c < 3; ++c) {
+    double F0 = m->base_weight * m->base_color[c];
+    double S = F0 + (1.0 - F0) * om5;
+    double Sb = F0 + (1.0 - F0) * omb5;
+    double b = Sb * (1.0 - m->spec_color[c]) / (mb * omb6);
+    double v = S - mu * om5 * om * b;
+    F[c] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+  }
+}
+
+double oggx_D(double at, double ab, v3 m) {
+  if (m.z <= 0.0) return 0.0;
+  double x = m.x / at, y = m.y / ab;
+  double k = x * x + y * y + m.z * m.z;
+  return 1.0 / (O_PI * at * ab * k * k);
+}
+
+double oggx_lambda(double at, double ab, v3 w) {
+  double z2 = w.z * w.z;
+  if (z2 == 0.0) return INFINITY;
+  double a2 = (at * at * w.x * w.x + ab * ab * w.y * w.y) / z2;
+  return 0.5 * (-1.0 + sqrt(1.0 + a2));
+}
+
+v3 oggx_vndf_sample(double at, double ab, v3 wo, double u1, double u2) {
+  /* Heitz 2018: sample the visible hemisphere of the stretched configuration */
+  v3 Vh = vnorm(V(at * wo.x, ab * wo.y, wo.z));
+  double lensq = Vh.x * Vh.x + Vh.y * Vh.y;
+  v3 T1 = lensq > 0.0 ? vmul(V(-Vh.y, Vh.x, 0.0), 1.0 / sqrt(lensq)) : V(1.0, 0.0, 0.0);
+  v3 T2 = vcross(Vh, T1);
+  double r = sqrt(u1);
+  double phi = 2.0 * O_PI * u2;
+  double t1 = r * cos(phi), t2 = r * sin(phi);
+  double s = 0.5 * (1.0 + Vh.z);
+  t2 = (1.0 - s) * sqrt(1.0 - t1 * t1) + s * t2;
+  double tz = 1.0 - t1 * t1 - t2 * t2;
+  v3 Nh = vadd(vadd(vmul(T1, t1), vmul(T2, t2)), vmul(Vh, sqrt(tz > 0.0 ? tz : 0.0)));
+  return vnorm(V(at * Nh.x, ab * Nh.y, Nh.z > 0.0 ? Nh.z : 0.0));
+}
+
+double oggx_vndf_pdf(double at, double ab, v3 wo, v3 m) {
+  /* density of m: G1(wo) max(0, wo.m) D(m) / wo.z */
+  double wm = vdot(wo, m);
+  if (wm <= 0.0 || wo.z <= 0.0) return 0.0;
+  double G1 = 1.0 / (1.0 + oggx_lambda(at, ab, wo));
+  return G1 * wm * oggx_D(at, ab, m) / wo.z;
+}
+
+static double clampa(double a) { return a < 1e-4 ? 1e-4 : a; }
+
+void obsdf_setup(const omat* m, int entering, double mu_o, obsdf* b) {
+  b->m = *m;
+  b->entering = entering;
+  b->eta = (m->trans_weight > 0.0 && !entering) ? 1.0 / m->spec_ior : m->spec_ior;
+  double r = m->spec_rough, a = m->spec_aniso;
+  double alpha = r * r;
+  double at = alpha * sqrt(2.0 / (1.0 + (1.0 - a) * (1.0 - a)));
+  b->at = clampa(at);
+  b->ab = clampa((1.0 - a) * at);
+  b->spec_delta = r < 1e-3;
+  b->ac = clampa(m->coat_rough * m->coat_rough);
+  b->coat_delta = m->coat_rough < 1e-3;
+  double cw = m->coat_weight, mt = m->metalness, tw = m->trans_weight, sw = m->spec_weight;
+  double Fc = ofresnel_diel(mu_o, m->coat_ior);
+  double Tc = 1.0 - cw * Fc;
+  double Fd = sw * ofresnel_diel(mu_o, b->eta);
+  double F82[3];
+  of82(m, mu_o, F82);
+  double bwbc[3] = {m->base_weight * m->base_color[0], m->base_weight * m->base_color[1],
+                    m->base_weight * m->base_color[2]};
+  double w[4];
+  w[LOBE_C] = cw * Fc;
+  w[LOBE_M] = Tc * mt * sw * lum3(F82);
+  w[LOBE_I] = Tc * (1.0 - mt) * (Fd + tw * (1.0 - Fd));
+  w[LOBE_D] = Tc * (1.0 - mt) * (1.0 - tw) * (1.0 - Fd) * lum3(bwbc);
+  double sum = w[0] + w[1] + w[2] + w[3];
+  b->absorbed = !(sum > 0.0);
+  for (int k = 0; k < 4; ++k) b->P[k] = b->absorbed ? 0.0 : w[k] / sum;
+}
+
+int obsdf_has_nondelta(const obsdf* b) {
+  double s = b->P[LOBE_D];
+  if (!b->coat_delta) s += b->P[LOBE_C];
+  if (!b->spec_delta) s += b->P[LOBE_M] + b->P[LOBE_I];
+  return s > 0.0;
+}
+
+/* (1-cw) + cw*coat_color*(1-Fc(|mu_i|))*(1-Fc(mu_o)) */
+static void coat_layer(const obsdf* b, double mu_i, double mu_o, double L[3]) {
+  double cw = b->m.coat_weight;
+  double Fi = ofresnel_diel(fabs(mu_i), b->m.coat_ior), Fo = ofresnel_diel(mu_o, b->m.coat_ior);
+  for (int c = 0; c < 3; ++c) L[c] = (1.0 - cw) + cw * b->m.coat_color[c] * (1.0 - Fi) * (1.0 - Fo);
+}
+
+static double G2(double at, double ab, v3 wo, v3 wi) {
+  return 1.0 / (1.0 + oggx_lambda(at, ab, wo) + oggx_lambda(at, ab, wi));
+}
+
+/* half vector of a refraction pair: normalize(wo + eta*wi), oriented to +z */
+static v3 refr_half(v3 wo, v3 wi, double eta) {
+  v3 h = vnorm(vadd(wo, vmul(wi, eta)));
+  if (h.z < 0.0) h = vmul(h, -1.0);
+  return h;
+}
+
+/* Non-delta BSDF value f(wo, wi) and the one-sample mixture pdf sum_k P_k pdf_k(wi). */
+void obsdf_eval(const obsdf* b, v3 wo, v3 wi, double f[3], double* pdf) {
+  f[0] = f[1] = f[2] = 0.0;
+  *pdf = 0.0;
+  double mu_o = wo.z, mu_i = wi.z;
+  if (b->absorbed || mu_o <= 0.0 || mu_i == 0.0) return;
+  const omat* m = &b->m;
+  double mt = m->metalness, tw = m->trans_weight, sw = m->spec_weight, cw = m->coat_weight;
+  double L[3];
+  coat_layer(b, mu_i, mu_o, L);
+  if (mu_i > 0.0) {
+    v3 h = vnorm(vadd(wo, wi));
+    double oh = vdot(wo, h);
+    double fc = 0.0, pc = 0.0;
+    if (!b->coat_delta && cw > 0.0) {
+      double Dc = oggx_D(b->ac, b->ac, h);
+      fc = cw * ofresnel_diel(oh, m->coat_ior) * Dc * G2(b->ac, b->ac, wo, wi) / (4.0 * mu_o * mu_i);
+      pc = oggx_vndf_pdf(b->ac, b->ac, wo, h) / (4.0 * oh);
+    }
+    double fm[3] = {0, 0, 0}, fi = 0.0, pm = 0.0, pi = 0.0;
+    if (!b->spec_delta) {
+      double D = oggx_D(b->at, b->ab, h);
+      double g = G2(b->at, b->ab, wo, wi);
+      double pv = oggx_vndf_pdf(b->at, b->ab, wo, h) / (4.0 * oh);
+      double F82[3];
+      of82(m, oh, F82);
+      for (int c = 0; c < 3; ++c) fm[c] = sw * F82[c] * D * g / (4.0 * mu_o * mu_i);
+      double Fi = ofresnel_diel(oh, b->eta);
+      fi = sw * Fi * D * g / (4.0 * mu_o * mu_i);
+      pm = pv;
+      double denom = Fi + tw * (1.0 - Fi);
+      pi = denom > 0.0 ? (Fi / denom) * pv : 0.0;
+    }
+    double Fdi = ofresnel_diel(mu_i, b->eta), Fdo = ofresnel_diel(mu_o, b->eta);
+    double kd = (1.0 - tw) * (1.0 - sw * Fdi) * (1.0 - sw * Fdo) / O_PI;
+    for (int c = 0; c < 3; ++c) {
+      double fd = kd * m->base_weight * m->base_color[c];
+      f[c] = fc + L[c] * (mt * fm[c] + (1.0 - mt) * (fi + fd));
+    }
+    *pdf = b->P[LOBE_C] * pc + b->P[LOBE_M] * pm + b->P[LOBE_I] * pi + b->P[LOBE_D] * (mu_i / O_PI);
+  } else {
+    if (b->spec_delta || tw <= 0.0) return;
+    double eta = b->eta;
+    v3 h = refr_half(wo, wi, eta);
+    double oh = vdot(wo, h), ih = vdot(wi, h);
+    if (oh <= 0.0 || ih >= 0.0) return;
+    double F = ofresnel_diel(oh, eta);
+    double s = ih + oh / eta;
+    double denom = s * s;
+    double D = oggx_D(b->at, b->ab, h);
+    double g = G2(b->at, b->ab, wo, wi);
+    double bt = tw * (1.0 - F) * D * g * fabs(ih) * fabs(oh) / (denom * fabs(mu_i) * mu_o) / (eta * eta);
+    for (int c = 0; c < 3; ++c) {
+      double tint = b->entering ? m->trans_color[c] : 1.0;
+      f[c] = L[c] * (1.0 - mt) * bt * tint;
+    }
+    double dn = F + tw * (1.0 - F);
+    double pr = dn > 0.0 ? F / dn : 0.0;
+    *pdf = b->P[LOBE_I] * (1.0 - pr) * oggx_vndf_pdf(b->at, b->ab, wo, h) * fabs(ih) / denom;
+  }
+}
+
+static v3 reflect_about(v3 wo, v3 m) { return vsub(vmul(m, 2.0 * vdot(wo, m)), wo); }
+
+/* refraction of wo through microfacet m (wo.m > 0), eta = n_t/n_i; returns 0 on TIR */
+static int refract_about(v3 wo, v3 m, double eta, v3* wi) {
+  double c = vdot(wo, m);
+  double k = 1.0 - (1.0 - c * c) / (eta * eta);
+  if (k < 0.0) return 0;
+  *wi = vadd(vmul(wo, -1.0 / eta), vmul(m, c / eta - sqrt(k)));
+  return 1;
+}
+
+/*
+ * Sample a direction: lobe by u_lobe against the cumulative pmf (C, M, I, D;
+ * if rounding leaves u_lobe past the last bucket, the last lobe with
+ * nonzero probability is taken), microfacet or cosine direction from
+ * (u1, u2), reflect-vs-refract from u_rt.  Lobe codes: 0 coat, 1 metal,
+ * 2 interface reflection, 3 interface refraction, 4 diffuse.
+ */
+int obsdf_sample(const obsdf* b, v3 wo, double u_lobe, double u1, double u2, double u_rt, v3* wi,
+                 double weight[3], double* pdf, int* delta, int* refract, int* lobe_code) {
+  weight[0] = weight[1] = weight[2] = 0.0;
+  *pdf = 0.0;
+  *delta = 0;
+  *refract = 0;
+  *lobe_code = -1;
+  double mu_o = wo.z;
+  if (b->absorbed || mu_o <= 0.0) return 0;
+  const omat* m = &b->m;
+  int lobe = -1, last = -1;
+  double acc = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    if (b->P[k] > 0.0) {
+      last = k;
+      if (lobe < 0 && u_lobe < acc + b->P[k]) lobe = k;
+    }
+    acc += b->P[k];
+  }
+  if (lobe < 0) lobe = last;
+  if (lobe < 0) return 0;
+  double mt = m->metalness, tw = m->trans_weight, sw = m->spec_weight, cw = m->coat_weight;
+  v3 d;
+  if (lobe == LOBE_C) {
+    *lobe_code = 0;
+    if (b->coat_delta) {
+      *wi = V(-wo.x, -wo.y, wo.z);
+      double w = cw * ofresnel_diel(mu_o, m->coat_ior) / b->P[LOBE_C];
+      weight[0] = weight[1] = weight[2] = w;
+      *delta = 1;
+      return 1;
+    }
+    v3 h = oggx_vndf_sample(b->ac, b->ac, wo, u1, u2);
+    d = reflect_about(wo, h);
+    if (d.z <= 0.0) return 0;
+  } else if (lobe == LOBE_M) {
+    *lobe_code = 1;
+    if (b->spec_delta) {
+      *wi = V(-wo.x, -wo.y, wo.z);
+      double L[3], F[3];
+      coat_layer(b, mu_o, mu_o, L);
+      of82(m, mu_o, F);
+      for (int c = 0; c < 3; ++c) weight[c] = L[c] * mt * sw * F[c] / b->P[LOBE_M];
+      *delta = 1;
+      return 1;
+    }
+    v3 h = oggx_vndf_sample(b->at, b->ab, wo, u1, u2);
+    d = reflect_about(wo, h);
+    if (d.z <= 0.0) return 0;
+  } else if (lobe == LOBE_I) {
+    double eta = b->eta;
+    if (b->spec_delta) {
+      double F = ofresnel_diel(mu_o, eta);
+      double dn = F + tw * (1.0 - F);
+      double pr = dn > 0.0 ? F / dn : 0.0;
+      double L[3];
+      *delta = 1;
+      if (u_rt < pr) {
+        *lobe_code = 2;
+        *wi = V(-wo.x, -wo.y, wo.z);
+        coat_layer(b, mu_o, mu_o, L);
+        for (int c = 0; c < 3; ++c) weight[c] = L[c] * (1.0 - mt) * sw * F / (b->P[LOBE_I] * pr);
+        return 1;
+      }
+      *lobe_code = 3;
+      v3 t;
+      if (!refract_about(wo, V(0, 0, 1), eta, &t)) return 0;
+      *wi = t;
+      *refract = 1;
+      coat_layer(b, t.z, mu_o, L);
+      for (int c = 0; c < 3; ++c) {
+        double tint = b->entering ? m->trans_color[c] : 1.0;
+        weight[c] = L[c] * (1.0 - mt) * tw * tint * (1.0 - F) / (eta * eta) / (b->P[LOBE_I] * (1.0 - pr));
+      }
+      return 1;
+    }
+    v3 h = oggx_vndf_sample(b->at, b->ab, wo, u1, u2);
+    double F = ofresnel_diel(vdot(wo, h), eta);
+    double dn = F + tw * (1.0 - F);
+    double pr = dn > 0.0 ? F / dn : 0.0;
+    if (u_rt < pr) {
+      *lobe_code = 2;
+      d = reflect_about(wo, h);
+      if (d.z <= 0.0) return 0;
+    } else {
+      *lobe_code = 3;
+      if (!refract_about(wo, h, eta, &d)) return 0;
+      if (d.z >= 0.0) return 0;
+      *refract = 1;
+    }
+  } else {
+    *lobe_code = 4;
+    double r = sqrt(u1), phi = 2.0 * O_PI * u2;
+    double z = 1.0 - u1;
+    d = V(r * cos(phi), r * sin(phi), sqrt(z > 0.0 ? z : 0.0));
+    if (d.z <= 0.0) return 0;
+  }
+  double f[3], p;
+  obsdf_eval(b, wo, d, f, &p);
+  if (!(p > 0.0)) return 0;
+  *wi = d;
+  *pdf = p;
+  for (int c = 0; c < 3; ++c) weight[c] = f[c] * fabs(d.z) / p;
+  return 1;
+}
+
+/* ------------------------------------------------------- C-ABI probes -- */
+
+static v3 v3from(const double* a) { return V(a[0], a[1], a[2]); }
+
+int oracle_bsdf_eval(const float* mat, int32_t entering, const double wo[3], const double wi[3],
+                     double f[3], double* pdf) {
+  omat m;
+  omat_from_floats(mat, &m);
+  obsdf b;
+  obsdf_setup(&m, entering, wo[2], &b);
+  obsdf_eval(&b, v3from(wo), v3from(wi), f, pdf);
+  return 0;
+}
+
+int oracle_bsdf_sample(const float* mat, int32_t entering, const double wo[3], const double u[4],
+                       double wi[3], double weight[3], double* pdf, int32_t* flags, int32_t* lobe) {
+  omat m;
+  omat_from_floats(mat, &m);
+  obsdf b;
+  obsdf_setup(&m, entering, wo[2], &b);
+  v3 w = V(0, 0, 0);
+  int dl, rf, lc;
+  int ok = obsdf_sample(&b, v3from(wo), u[0], u[1], u[2], u[3], &w, weight, pdf, &dl, &rf, &lc);
+  wi[0] = w.x; wi[1] = w.y; wi[2] = w.z;
+  *flags = (dl ? 1 : 0) | (rf ? 2 : 0);
+  *lobe = lc;
+  return ok;
+}
+
+void oracle_lobe_pmf(const float* mat, int32_t entering, double mu_o, double pmf[4]) {
+  omat m;
+  omat_from_floats(mat, &m);
+  obsdf b;
+  obsdf_setup(&m, entering, mu_o, &b);
+  memcpy(pmf, b.P, sizeof(double) * 4);
+}
+
+double oracle_fresnel_dielectric(double cos_i, double eta) { return ofresnel_diel(cos_i, eta); }
+
+void oracle_fresnel_f82(const float* mat, double mu, double F[3]) {
+  omat m;
+  omat_from_floats(mat, &m);
+  of82(&m, mu, F);
+}
+
+double oracle_ggx_D(double at, double ab, const double m[3]) { return oggx_D(at, ab, v3from(m)); }
+double oracle_ggx_G1(double at, double ab, const double w[3]) {
+  return 1.0 / (1.0 + oggx_lambda(at, ab, v3from(w)));
+}
+void oracle_ggx_vndf_sample(double at, double ab, const double wo[3], double u1, double u2, double m[3]) {
+  v3 r = oggx_vndf_sample(at, ab, v3from(wo), u1, u2);
+  m[0] = r.x; m[1] = r.y; m[2] = r.z;
+}
+double oracle_ggx_vndf_pdf(double at, double ab, const double wo[3], const double m[3]) {
+  return oggx_vndf_pdf(at, ab, v3from(wo), v3from(m));
+}

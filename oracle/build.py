@@ -1,0 +1,29 @@
+"""Compile the FP64 oracle (plain C) into oracle/liboracle.so with gcc.
+
+Test infrastructure: the library is loaded only by the tests, the smoke
+check and the benchmark's CPU-baseline leg.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ["philox.c", "geometry.c", "bsdf.c", "lights.c", "integrator.c"]
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    # -ffp-contract=off: the single-precision closest-hit reference must not fuse multiply-adds
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+           "-Wall", "-Wno-unused-function", "-o", LIB + ".tmp"]
+    cmd += [os.path.join(HERE, s) for s in SOURCES]
+    cmd += ["-lm", "-lpthread"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)

@@ -1,0 +1,206 @@
+/*
+ * pt.h -- C ABI of the MI355X path tracer (libpt.so, HIP for gfx950).
+ *
+ * The library estimates, per pixel, the Monte Carlo integral of the
+ * rendering equation (paper Sec. 1.1): camera rays (Sec. 5.1.2), closest
+ * hits through a BVH of axis-aligned boxes built on the CPU (Sec. 5.1.1),
+ * OpenPBR surface shading with importance sampling and Russian roulette
+ * (Sec. 4, Sec. 5.1.3), next-event estimation with multiple importance
+ * sampling, and per-pixel averaging of the samples (Sec. 5.1.3).  The paper
+ * splits the work into a CPU set-up done once per scene and GPU sampling
+ * repeated per frame (Sec. 5.1); the calls below follow that split.
+ *
+ * Conventions
+ *  - Every call returns pt_status and never throws.  On error the scene is
+ *    left unchanged and pt_last_error() (thread-local) explains why.
+ *  - Host input arrays are copied during the call; the caller keeps
+ *    ownership and may free them on return.
+ *  - Device pointers (out_rgb32f, rays, hits, ...) are caller-owned memory
+ *    on the scene's device, allocated for example as torch tensors.
+ *  - Work is enqueued on the scene's stream; calls that return results
+ *    synchronise that stream before returning, so device faults surface as
+ *    PT_ERR_DEVICE.
+ *  - Output radiance is linear RGB; row 0 is the top of the image.
+ *  - No call is safe to run concurrently on the same scene.
+ */
+#ifndef PT_H
+#define PT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pt_status {
+  PT_OK = 0,
+  PT_ERR_INVALID_ARG = -1,  /* a pointer, count, index or parameter is out of range */
+  PT_ERR_OUT_OF_MEMORY = -2,
+  PT_ERR_DEVICE = -3,       /* a HIP call failed (message has the HIP error string) */
+  PT_ERR_UNSUPPORTED = -4,  /* a valid parameter combination this build does not implement */
+  PT_ERR_STATE = -5         /* e.g. render before pt_build_bvh / pt_upload_materials */
+} pt_status;
+
+typedef struct pt_scene pt_scene; /* opaque; owns every device allocation it makes */
+
+/* A triangle mesh (host pointers).  Triangles are the paper's geometry
+ * (Sec. 5.1.1); winding defines the front face: the geometric normal is
+ * normalize(cross(v1 - v0, v2 - v0)).  Zero-area triangles are accepted and
+ * never hit. */
+typedef struct pt_mesh {
+  const float* vertices;        /* [n_vertices][3], finite */
+  int64_t n_vertices;
+  const int32_t* indices;       /* [n_triangles][3], each in [0, n_vertices) */
+  int64_t n_triangles;          /* >= 1 */
+  const int32_t* material_ids;  /* [n_triangles]; may be NULL if every instance overrides */
+} pt_mesh;
+
+/* A placement of a mesh (two-level hierarchy).  object_to_world is a
+ * row-major 3x4 rigid transform (rotation | translation). */
+typedef struct pt_instance {
+  float object_to_world[12];
+  int32_t mesh;
+  int32_t material_override;  /* -1: use the mesh's per-triangle ids */
+} pt_instance;
+
+/* OpenPBR parameters (Sec. 4), linear RGB; 27 floats in this order. */
+typedef struct pt_openpbr_material {
+  float base_weight, base_color[3], base_metalness, base_diffuse_roughness;
+  float specular_weight, specular_color[3], specular_roughness, specular_roughness_anisotropy,
+      specular_ior;
+  float transmission_weight, transmission_color[3];
+  float coat_weight, coat_color[3], coat_roughness, coat_ior;
+  float emission_luminance, emission_color[3];
+} pt_openpbr_material;
+
+/* Pinhole camera (Sec. 5.1.2): vertical field of view in degrees, aspect width/height. */
+typedef struct pt_camera {
+  float eye[3], look_at[3], up[3];
+  float vfov_deg;
+  int32_t width, height;
+} pt_camera;
+
+typedef struct pt_stats {
+  int64_t extension_rays;    /* closest-hit rays traced since the last reset */
+  int64_t shadow_rays;       /* any-hit rays traced since the last reset */
+  int64_t nonfinite_dropped; /* contributions dropped because they were not finite */
+  int64_t samples;           /* path samples started */
+  double ms_extend;          /* summed kernel time of the closest-hit kernel (profiling on) */
+  int64_t launches_extend;   /* its launch count (profiling on) */
+  double ms_total;           /* summed time of all sampling passes (profiling on) */
+  int64_t node_visits;       /* BVH node fetches of closest-hit rays (counting on) */
+  int64_t tri_tests;         /* triangle tests of closest-hit rays (counting on) */
+  int64_t shadow_node_visits;/* BVH node fetches of shadow rays (counting on) */
+  int64_t shadow_tri_tests;  /* triangle tests of shadow rays (counting on) */
+} pt_stats;
+
+/* Create a scene bound to HIP device `hip_device` and stream `hip_stream`
+ * (a hipStream_t, or NULL for the default stream).  Allocates nothing on the
+ * device yet.  Errors: INVALID_ARG (out == NULL), DEVICE. */
+pt_status pt_scene_create(int32_t hip_device, void* hip_stream, pt_scene** out);
+
+/* Release the scene and its device memory.  NULL-safe. */
+void pt_scene_destroy(pt_scene* scene);
+
+/* Build the acceleration structure on the CPU (Sec. 5.1.1: boxes grouped so
+ * that every child lies inside its parent) and upload it.  With
+ * n_instances == 0 the meshes are concatenated into one world-space mesh
+ * and primitive ids number the concatenation; otherwise each instance
+ * places meshes[mesh] and primitive ids are per mesh.
+ * Errors: INVALID_ARG (NULL pointers, counts <= 0, indices out of range,
+ * non-finite vertices or transforms, mesh index out of range), OUT_OF_MEMORY, DEVICE. */
+pt_status pt_build_bvh(pt_scene* scene, const pt_mesh* meshes, int32_t n_meshes,
+                       const pt_instance* instances, int32_t n_instances);
+
+/* Upload the OpenPBR materials (Sec. 4).  Errors: INVALID_ARG (n <= 0,
+ * negative or non-finite parameters, IOR <= 0, weights outside [0,1]),
+ * UNSUPPORTED (base_diffuse_roughness != 0, coat together with transmission). */
+pt_status pt_upload_materials(pt_scene* scene, const pt_openpbr_material* materials, int32_t n);
+
+/* Set the environment: an equirectangular RGB32F image [h][w][3] (y up,
+ * theta = acos(d_y), phi = atan2(d_x, -d_z), column = (phi/2pi + 1/2) w,
+ * row = theta/pi h), or NULL for none.  Builds its sampling tables.
+ * Errors: INVALID_ARG (w or h <= 0, negative or non-finite texels). */
+pt_status pt_set_environment(pt_scene* scene, const float* rgb32f, int32_t w, int32_t h);
+
+/* Render: reset the FP64 per-pixel sums, accumulate samples [0, spp) of
+ * every pixel with paths of at most max_depth scattering events, and write
+ * the per-pixel mean to out_rgb32f (device, [height][width][3] float).
+ * seed keys the Philox stream.  Errors: INVALID_ARG (camera, spp <= 0,
+ * max_depth outside [0, 64], out == NULL), STATE (no BVH or materials,
+ * a material id >= the material count), DEVICE. */
+pt_status pt_render(pt_scene* scene, const pt_camera* camera, int32_t spp, int32_t max_depth,
+                    uint64_t seed, float* out_rgb32f);
+
+/* Progressive rendering (Sec. 5.1.4 shows the running mean after every
+ * sampling iteration): add samples [first_sample, first_sample + n_samples)
+ * to the FP64 sums.  The sums are reset when the camera's width or height
+ * changes or by pt_reset_accumulation.  Splitting a range into several calls
+ * gives bit-identical sums. */
+pt_status pt_accumulate(pt_scene* scene, const pt_camera* camera, int32_t first_sample,
+                        int32_t n_samples, int32_t max_depth, uint64_t seed);
+pt_status pt_reset_accumulation(pt_scene* scene);
+
+/* Write sum / samples_accumulated to out_rgb32f (device, [h][w][3] float),
+ * and optionally copy the raw FP64 sums to out_sum_f64 (device, [h][w][3]
+ * double, or NULL).  Errors: STATE if nothing was accumulated. */
+pt_status pt_resolve(pt_scene* scene, float* out_rgb32f, double* out_sum_f64);
+
+/* Per-path output for parity checks: render samples [first_sample,
+ * first_sample + spp) of the pixels in the crop (x0, y0, w, h) of the
+ * camera's image and write each path's radiance to per_sample_rgb (device,
+ * [h][w][spp][3] float) and its event signature to signature (device,
+ * [h][w][spp] uint64, FNV-1a 64 over the path's events).  Uses the same
+ * kernels as pt_render with the signature bookkeeping switched on. */
+pt_status pt_render_debug(pt_scene* scene, const pt_camera* camera, int32_t x0, int32_t y0,
+                          int32_t w, int32_t h, int32_t first_sample, int32_t spp,
+                          int32_t max_depth, uint64_t seed, float* per_sample_rgb,
+                          uint64_t* signature);
+
+/* Closest hit of n rays (device, [n][8] float: ox, oy, oz, tmin, dx, dy, dz,
+ * tmax) written to hits (device, [n][6] uint32: t bits, instance, primitive,
+ * b1 bits, b2 bits, 1 if hit; a miss is +inf, 0xFFFFFFFF, 0xFFFFFFFF, 0, 0, 0).
+ * brute_force != 0 tests every triangle instead of walking the BVH.  Ties
+ * in t resolve to the smallest (instance, primitive). */
+pt_status pt_trace_closest(pt_scene* scene, const float* rays, int64_t n, uint32_t* hits,
+                           int32_t brute_force);
+
+/* Statistics since the last pt_reset_stats. */
+pt_status pt_get_stats(pt_scene* scene, pt_stats* out);
+pt_status pt_reset_stats(pt_scene* scene);
+
+/* Kernel timing with HIP events on the scene's stream (0 off, 1 on), and
+ * node-visit / triangle-test counting (0 off, 1 on; uses a counting variant
+ * of the traversal kernels). */
+pt_status pt_set_profiling(pt_scene* scene, int32_t timing, int32_t counting);
+
+/* ---- host-only BVH access (no device needed) ---- */
+typedef struct pt_bvh_host pt_bvh_host;
+typedef struct pt_bvh_info {
+  int64_t n_nodes;        /* 128-byte BVH4 nodes */
+  int64_t n_tris;         /* 48-byte triangle records in leaf order */
+  int32_t depth;          /* nodes on the longest root-to-leaf path */
+  int32_t max_leaf_tris;
+  double sah_cost;
+  double build_ms;
+} pt_bvh_info;
+/* Build the BVH4 of one mesh on the host (the same builder pt_build_bvh uses). */
+pt_status pt_bvh_host_build(const pt_mesh* mesh, pt_bvh_host** out);
+pt_status pt_bvh_host_info(const pt_bvh_host* bvh, pt_bvh_info* info);
+/* Copy nodes (n_nodes * 128 bytes) and triangles (n_tris * 48 bytes) to host memory. */
+pt_status pt_bvh_host_copy(const pt_bvh_host* bvh, void* nodes, void* tris);
+/* Closest hit on the host through the BVH4 (same traversal code as the GPU,
+ * compiled for the CPU).  rays/hits as for pt_trace_closest, host memory. */
+pt_status pt_bvh_host_trace(const pt_bvh_host* bvh, const float* rays, int64_t n, uint32_t* hits);
+void pt_bvh_host_destroy(pt_bvh_host* bvh);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char* pt_last_error(void);
+
+/* Library version string. */
+const char* pt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

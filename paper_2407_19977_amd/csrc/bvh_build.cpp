@@ -1,0 +1,320 @@
+// Host BVH builder (paper Sec. 5.1.1: the CPU groups adjacent primitives in
+// axis-aligned boxes so that every child lies inside its parent; Table 1
+// times this set-up stage).
+//
+// 1. Binned SAH (32 bins per axis on centroid bounds, traversal cost 1,
+//    triangle cost 1) builds a binary tree with at most 4 triangles per leaf;
+//    large subtrees are built on parallel threads.
+// 2. The binary tree is collapsed into a 4-wide tree: a node repeatedly
+//    opens its largest-area internal child until it has four children.
+// 3. Nodes are written in depth-first order as 128-byte records with the four
+//    child boxes stored structure-of-arrays; triangles are written in leaf
+//    order as 48-byte records.
+// Boxes are the exact float min/max of the triangle vertices, so every
+// triangle lies inside each box on its path.
+#include "bvh_build.h"
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <future>
+#include <limits>
+
+namespace pt {
+namespace {
+
+struct Box {
+  float lo[3], hi[3];
+  void clear() {
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::numeric_limits<float>::infinity();
+      hi[k] = -std::numeric_limits<float>::infinity();
+    }
+  }
+  void grow(const Box& b) {
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::min(lo[k], b.lo[k]);
+      hi[k] = std::max(hi[k], b.hi[k]);
+    }
+  }
+  void grow(const float* p) {
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::min(lo[k], p[k]);
+      hi[k] = std::max(hi[k], p[k]);
+    }
+  }
+  double area() const {
+    double dx = (double)hi[0] - lo[0], dy = (double)hi[1] - lo[1], dz = (double)hi[2] - lo[2];
+    if (!(dx >= 0) || !(dy >= 0) || !(dz >= 0)) return 0.0;
+    return 2.0 * (dx * dy + dy * dz + dz * dx);
+  }
+};
+
+struct BNode {
+  Box box;
+  int32_t left = -1, right = -1;
+  int32_t first = 0, count = 0;  // count > 0: leaf
+};
+
+constexpr int kBins = 32;
+
+struct Builder {
+  const std::vector<Box>* tb;
+  const std::vector<float>* cen;  // [n][3]
+  std::vector<int32_t> idx;
+  std::vector<BNode> nodes;
+  std::atomic<int32_t> next{0};
+
+  int32_t alloc() { return next.fetch_add(1); }
+
+  int32_t build(int32_t first, int32_t count, int level) {
+    int32_t id = alloc();
+    BNode nd;
+    Box cb;
+    nd.box.clear();
+    cb.clear();
+    for (int32_t i = first; i < first + count; ++i) {
+      int32_t t = idx[i];
+      nd.box.grow((*tb)[t]);
+      cb.grow(&(*cen)[3 * (size_t)t]);
+    }
+    int best_axis = -1, best_bin = -1;
+    double best_cost = std::numeric_limits<double>::infinity();
+    double parent_area = nd.box.area();
+    for (int ax = 0; ax < 3 && count > 1; ++ax) {
+      float ext = cb.hi[ax] - cb.lo[ax];
+      if (!(ext > 0.0f)) continue;
+      Box bb[kBins];
+      int32_t bc[kBins];
+      for (int b = 0; b < kBins; ++b) {
+        bb[b].clear();
+        bc[b] = 0;
+      }
+      double scale = kBins / (double)ext;
+      for (int32_t i = first; i < first + count; ++i) {
+        int32_t t = idx[i];
+        int b = (int)(((double)(*cen)[3 * (size_t)t + ax] - cb.lo[ax]) * scale);
+        b = std::min(std::max(b, 0), kBins - 1);
+        bb[b].grow((*tb)[t]);
+        bc[b]++;
+      }
+      double ra[kBins];
+      int32_t rc[kBins];
+      Box acc;
+      acc.clear();
+      int32_t n = 0;
+      for (int b = kBins - 1; b > 0; --b) {
+        acc.grow(bb[b]);
+        n += bc[b];
+        ra[b] = acc.area();
+        rc[b] = n;
+      }
+      acc.clear();
+      n = 0;
+      for (int b = 0; b < kBins - 1; ++b) {
+        acc.grow(bb[b]);
+        n += bc[b];
+        if (n == 0 || rc[b + 1] == 0) continue;
+        double cost = acc.area() * n + ra[b + 1] * rc[b + 1];
+        if (cost < best_cost) {
+          best_cost = cost;
+          best_axis = ax;
+          best_bin = b;
+        }
+      }
+    }
+    // leaf if small and splitting does not pay (SAH with traversal cost 1, triangle cost 1)
+    double leaf_cost = (double)count;
+    double split_cost = parent_area > 0 ? 1.0 + best_cost / parent_area : 1.0 + count;
+    bool make_leaf = count <= 1 || (count <= kMaxLeafTris && (best_axis < 0 || leaf_cost <= split_cost));
+    if (make_leaf) {
+      nd.first = first;
+      nd.count = count;
+      nodes[id] = nd;
+      return id;
+    }
+    int32_t mid;
+    if (best_axis >= 0) {
+      float ext = cb.hi[best_axis] - cb.lo[best_axis];
+      double scale = kBins / (double)ext;
+      int ax = best_axis, sb = best_bin;
+      auto it = std::partition(idx.begin() + first, idx.begin() + first + count, [&](int32_t t) {
+        int b = (int)(((double)(*cen)[3 * (size_t)t + ax] - cb.lo[ax]) * scale);
+        b = std::min(std::max(b, 0), kBins - 1);
+        return b <= sb;
+      });
+      mid = (int32_t)(it - idx.begin());
+      if (mid == first || mid == first + count) mid = first + count / 2;
+    } else {
+      // all centroids coincide: split the range in half
+      mid = first + count / 2;
+    }
+    int32_t l, r;
+    if (count > 50000 && level < 6) {
+      auto fl = std::async(std::launch::async, [&] { return build(first, mid - first, level + 1); });
+      r = build(mid, first + count - mid, level + 1);
+      l = fl.get();
+    } else {
+      l = build(first, mid - first, level + 1);
+      r = build(mid, first + count - mid, level + 1);
+    }
+    nd.left = l;
+    nd.right = r;
+    nd.count = 0;
+    nodes[id] = nd;
+    return id;
+  }
+};
+
+struct Collapser {
+  const std::vector<BNode>* bn;
+  const std::vector<int32_t>* idx;
+  std::vector<BVHNode> out;
+  int max_depth = 0;
+  int max_leaf = 0;
+  double sah = 0.0;
+  double root_area = 1.0;
+
+  static void set_box(BVHNode& n, int c, const Box& b) {
+    n.lo_x[c] = b.lo[0]; n.hi_x[c] = b.hi[0];
+    n.lo_y[c] = b.lo[1]; n.hi_y[c] = b.hi[1];
+    n.lo_z[c] = b.lo[2]; n.hi_z[c] = b.hi[2];
+  }
+
+  uint32_t emit(int32_t b, int depth) {
+    const std::vector<BNode>& B = *bn;
+    int32_t kids[4];
+    int nk = 0;
+    if (B[b].count > 0) {
+      kids[nk++] = b;  // a lone leaf under a single-child root
+    } else {
+      kids[nk++] = B[b].left;
+      kids[nk++] = B[b].right;
+      while (nk < 4) {
+        int pick = -1;
+        double pa = -1.0;
+        for (int i = 0; i < nk; ++i) {
+          if (B[kids[i]].count == 0 && B[kids[i]].box.area() > pa) {
+            pa = B[kids[i]].box.area();
+            pick = i;
+          }
+        }
+        if (pick < 0) break;
+        int32_t c = kids[pick];
+        // open the child in place so siblings keep their spatial order
+        for (int i = nk; i > pick + 1; --i) kids[i] = kids[i - 1];
+        kids[pick] = B[c].left;
+        kids[pick + 1] = B[c].right;
+        nk++;
+      }
+    }
+    uint32_t id = (uint32_t)out.size();
+    out.emplace_back();
+    max_depth = std::max(max_depth, depth);
+    sah += B[b].box.area() / root_area;
+    BVHNode n;
+    std::memset(&n, 0, sizeof(n));
+    for (int c = 0; c < 4; ++c) {
+      n.lo_x[c] = n.lo_y[c] = n.lo_z[c] = 0.0f;
+      n.hi_x[c] = n.hi_y[c] = n.hi_z[c] = 0.0f;
+      n.child[c] = kEmpty;
+    }
+    n.meta[0] = (uint32_t)nk;
+    for (int c = 0; c < nk; ++c) {
+      const BNode& k = B[kids[c]];
+      set_box(n, c, k.box);
+      if (k.count > 0) {
+        n.child[c] = make_leaf((uint32_t)k.first, (uint32_t)k.count);
+        max_leaf = std::max(max_leaf, (int)k.count);
+        max_depth = std::max(max_depth, depth + 1);
+        sah += k.box.area() / root_area * k.count;
+      } else {
+        n.child[c] = 0;  // patched below (emit appends to `out`)
+      }
+    }
+    for (int c = 0; c < nk; ++c) {
+      const BNode& k = B[kids[c]];
+      if (k.count == 0) n.child[c] = emit(kids[c], depth + 1);
+    }
+    out[id] = n;
+    return id;
+  }
+};
+
+}  // namespace
+
+bool build_bvh4(const float* verts, const uint32_t* prim_ids, const uint32_t* mat_ids, int64_t n, Bvh4& out,
+                std::string& err) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (n <= 0) {
+    err = "a BVH needs at least one triangle";
+    return false;
+  }
+  if (n >= (int64_t)kLeafFirstMask) {
+    err = "too many triangles for one BVH (limit 2^27 - 1)";
+    return false;
+  }
+  std::vector<Box> tb((size_t)n);
+  std::vector<float> cen(3 * (size_t)n);
+  Box all;
+  all.clear();
+  for (int64_t t = 0; t < n; ++t) {
+    Box b;
+    b.clear();
+    for (int v = 0; v < 3; ++v) {
+      const float* p = verts + 9 * t + 3 * v;
+      for (int k = 0; k < 3; ++k) {
+        if (!std::isfinite(p[k])) {
+          err = "non-finite vertex";
+          return false;
+        }
+      }
+      b.grow(p);
+    }
+    tb[(size_t)t] = b;
+    all.grow(b);
+    for (int k = 0; k < 3; ++k) cen[3 * (size_t)t + k] = 0.5f * (b.lo[k] + b.hi[k]);
+  }
+  Builder B;
+  B.tb = &tb;
+  B.cen = &cen;
+  B.idx.resize((size_t)n);
+  for (int64_t i = 0; i < n; ++i) B.idx[(size_t)i] = (int32_t)i;
+  B.nodes.resize(2 * (size_t)n + 1);
+  int32_t root = B.build(0, (int32_t)n, 0);
+  B.nodes.resize((size_t)B.next.load());
+
+  Collapser C;
+  C.bn = &B.nodes;
+  C.idx = &B.idx;
+  C.root_area = std::max(B.nodes[root].box.area(), 1e-30);
+  C.out.reserve((size_t)n / 2 + 16);
+  C.emit(root, 1);
+  out.nodes = std::move(C.out);
+  out.depth = C.max_depth;
+  out.max_leaf = C.max_leaf;
+  out.sah_cost = C.sah;
+  out.tris.resize((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t t = B.idx[(size_t)i];
+    const float* p = verts + 9 * (size_t)t;
+    TriRec r;
+    r.a = make_float4(p[0], p[1], p[2], 0.0f);
+    r.b = make_float4(p[3], p[4], p[5], 0.0f);
+    r.c = make_float4(p[6], p[7], p[8], 0.0f);
+    uint32_t pid = prim_ids[t], mid = mat_ids[t];
+    std::memcpy(&r.a.w, &pid, 4);
+    std::memcpy(&r.b.w, &mid, 4);
+    out.tris[(size_t)i] = r;
+  }
+  for (int k = 0; k < 3; ++k) {
+    out.lo[k] = all.lo[k];
+    out.hi[k] = all.hi[k];
+  }
+  out.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return true;
+}
+
+}  // namespace pt

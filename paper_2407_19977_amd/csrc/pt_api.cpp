@@ -1,0 +1,891 @@
+// C ABI of the path tracer: scene set-up on the host (paper Sec. 5.1.1) and
+// sampling passes on the GPU (Sec. 5.1.2 - 5.1.3).  See include/pt.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "pt_internal.h"
+#include "pt_trace.h"
+
+using namespace pt;
+
+namespace {
+
+thread_local std::string g_err;
+
+pt_status fail(pt_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define PT_HIP(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(PT_ERR_DEVICE, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                                  \
+  } while (0)
+
+// Owning device allocation.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t alloc(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&p, n ? n : 16);
+    if (e == hipSuccess) bytes = n;
+    return e;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+hipError_t upload(DevBuf& b, const void* src, size_t n, hipStream_t st) {
+  hipError_t e = b.alloc(n);
+  if (e != hipSuccess) return e;
+  if (n) e = hipMemcpyAsync(b.p, src, n, hipMemcpyHostToDevice, st);
+  return e;
+}
+
+double lumd(double r, double g, double b) { return 0.2126 * r + 0.7152 * g + 0.0722 * b; }
+
+bool finite_all(const float* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+struct pt_scene {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  // geometry
+  bool has_bvh = false;
+  DevBuf nodes, tris;
+  uint32_t n_tris = 0;
+  int bvh_depth = 0;
+  float tmin = 0.0f;
+  int32_t max_mat_id = -1;
+  std::vector<float> host_tri_verts;  // [n][9] world space, prim order
+  std::vector<int32_t> host_tri_mat;  // [n], prim order
+  // materials
+  bool has_mats = false;
+  std::vector<pt_openpbr_material> host_mats;
+  DevBuf mats;
+  uint32_t class_mask = 0;
+  // environment
+  int env_w = 0, env_h = 0;
+  DevBuf env, env_row_pmf, env_row_cdf, env_col_pmf, env_col_cdf;
+  // lights
+  bool lights_dirty = true;
+  DevBuf lights, light_cdf, tri_light;
+  int32_t n_lights = 0;
+  float p_env = 0.0f;
+  // path state
+  int64_t capacity = 0;
+  DevBuf ray_o, ray_d, hit, beta, L, flags, q_ray[2], q_cls[kNumClasses], sh_o, sh_d, sh_c, counts, stats, sig,
+      dbg_nee, dbg_tail, spill;
+  // accumulation
+  DevBuf sum;
+  int acc_w = 0, acc_h = 0;
+  int64_t acc_samples = 0;
+  // profiling
+  bool timing = false, counting = false;
+  double ms_extend = 0.0, ms_total = 0.0;
+  int64_t launches_extend = 0;
+  int64_t samples = 0;
+  std::vector<hipEvent_t> events;
+};
+
+namespace {
+
+pt_status check_scene(pt_scene* s) {
+  if (!s) return fail(PT_ERR_INVALID_ARG, "scene is NULL");
+  return PT_OK;
+}
+
+pt_status set_device(pt_scene* s) {
+  PT_HIP(hipSetDevice(s->device));
+  return PT_OK;
+}
+
+pt_status ensure_lights(pt_scene* s) {
+  if (!s->lights_dirty) return PT_OK;
+  const int64_t n = s->n_tris;
+  std::vector<int32_t> tri_light((size_t)std::max<int64_t>(n, 1), -1);
+  struct Tmp {
+    LightTri t;
+    double w;
+  };
+  std::vector<Tmp> list;
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t mid = s->host_tri_mat[(size_t)i];
+    const pt_openpbr_material& m = s->host_mats[(size_t)mid];
+    double Le[3] = {(double)m.emission_luminance * m.emission_color[0],
+                    (double)m.emission_luminance * m.emission_color[1],
+                    (double)m.emission_luminance * m.emission_color[2]};
+    if (!(m.emission_luminance > 0.0f) || !(lumd(m.emission_color[0], m.emission_color[1], m.emission_color[2]) > 0.0))
+      continue;
+    const float* v = &s->host_tri_verts[9 * (size_t)i];
+    double e1[3], e2[3];
+    for (int k = 0; k < 3; ++k) {
+      e1[k] = (double)v[3 + k] - v[k];
+      e2[k] = (double)v[6 + k] - v[k];
+    }
+    double c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    double len = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    Tmp t;
+    std::memset(&t, 0, sizeof(t));
+    double area = 0.5 * len;
+    t.t.p0 = make_float4(v[0], v[1], v[2], (float)area);
+    t.t.p1 = make_float4(v[3], v[4], v[5], 0.0f);
+    t.t.p2 = make_float4(v[6], v[7], v[8], 0.0f);
+    t.t.ng = len > 0 ? make_float4((float)(c[0] / len), (float)(c[1] / len), (float)(c[2] / len), 0.0f)
+                     : make_float4(0, 0, 0, 0);
+    t.t.Le = make_float4((float)Le[0], (float)Le[1], (float)Le[2], 0.0f);
+    t.w = area * lumd(Le[0], Le[1], Le[2]);
+    tri_light[(size_t)i] = (int32_t)list.size();
+    list.push_back(t);
+  }
+  double wsum = 0.0;
+  for (auto& t : list) wsum += t.w;
+  bool has_tri = !list.empty() && wsum > 0.0;
+  bool has_env = s->env_w > 0;
+  double p_env = !has_env ? 0.0 : (has_tri ? 0.5 : 1.0);
+  std::vector<LightTri> lt;
+  std::vector<float> cdf(list.size() + 1, 0.0f);
+  double acc = 0.0;
+  for (size_t k = 0; k < list.size(); ++k) {
+    LightTri t = list[k].t;
+    t.p1.w = has_tri ? (float)((1.0 - p_env) * list[k].w / wsum) : 0.0f;
+    lt.push_back(t);
+    acc += list[k].w;
+    cdf[k + 1] = has_tri ? (float)(acc / wsum) : 0.0f;
+  }
+  if (has_tri) cdf[list.size()] = 1.0f;
+  if (!has_tri) {
+    lt.clear();
+    std::fill(tri_light.begin(), tri_light.end(), -1);
+  }
+  s->n_lights = (int32_t)lt.size();
+  s->p_env = (float)p_env;
+  PT_HIP(upload(s->lights, lt.data(), lt.size() * sizeof(LightTri), s->stream));
+  PT_HIP(upload(s->light_cdf, cdf.data(), cdf.size() * sizeof(float), s->stream));
+  PT_HIP(upload(s->tri_light, tri_light.data(), tri_light.size() * sizeof(int32_t), s->stream));
+  PT_HIP(hipStreamSynchronize(s->stream));
+  s->lights_dirty = false;
+  return PT_OK;
+}
+
+pt_status ensure_paths(pt_scene* s, int64_t n) {
+  if (n <= s->capacity) return PT_OK;
+  size_t f4 = (size_t)n * sizeof(float4), u4 = (size_t)n * sizeof(uint32_t);
+  PT_HIP(s->ray_o.alloc(f4));
+  PT_HIP(s->ray_d.alloc(f4));
+  PT_HIP(s->hit.alloc(f4));
+  PT_HIP(s->beta.alloc(f4));
+  PT_HIP(s->L.alloc(f4));
+  PT_HIP(s->flags.alloc(u4));
+  for (int i = 0; i < 2; ++i) PT_HIP(s->q_ray[i].alloc(u4));
+  for (int i = 0; i < kNumClasses; ++i) PT_HIP(s->q_cls[i].alloc(u4));
+  PT_HIP(s->sh_o.alloc(f4));
+  PT_HIP(s->sh_d.alloc(f4));
+  PT_HIP(s->sh_c.alloc(f4));
+  PT_HIP(s->sig.alloc((size_t)n * sizeof(uint64_t)));
+  PT_HIP(s->dbg_nee.alloc(u4));
+  PT_HIP(s->dbg_tail.alloc(u4));
+  s->capacity = n;
+  return PT_OK;
+}
+
+int grid_for(int64_t n) {
+  int64_t b = (n + kBlock - 1) / kBlock;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 2048));
+}
+
+pt_status ensure_counters(pt_scene* s) {
+  if (!s->counts.p) {
+    PT_HIP(s->counts.alloc(kNumCounts * sizeof(uint32_t)));
+    PT_HIP(hipMemsetAsync(s->counts.p, 0, kNumCounts * sizeof(uint32_t), s->stream));
+  }
+  if (!s->stats.p) {
+    PT_HIP(s->stats.alloc(kNumStats * sizeof(unsigned long long)));
+    PT_HIP(launch_zero_u64(s->stats.as<unsigned long long>(), kNumStats, s->stream));
+  }
+  return PT_OK;
+}
+
+pt_status ensure_spill(pt_scene* s, int grid_trace) {
+  int cap = 3 * std::max(s->bvh_depth, 1) + 4;
+  size_t per = cap > kLdsStack ? (size_t)(cap - kLdsStack) : 1;
+  size_t bytes = per * (size_t)grid_trace * kBlock * sizeof(uint2);
+  PT_HIP(s->spill.alloc(bytes));
+  return PT_OK;
+}
+
+SceneDev scene_dev(pt_scene* s, int grid_trace) {
+  SceneDev S;
+  std::memset(&S, 0, sizeof(S));
+  S.nodes = s->nodes.as<BVHNode>();
+  S.tris = s->tris.as<TriRec>();
+  S.n_tris = s->n_tris;
+  S.root = 0;
+  S.mats = s->mats.as<MatRec>();
+  S.tri_light = s->tri_light.as<int32_t>();
+  S.lights = s->lights.as<LightTri>();
+  S.light_cdf = s->light_cdf.as<float>();
+  S.n_lights = s->n_lights;
+  S.p_env = s->p_env;
+  S.env = s->env.as<float4>();
+  S.env_row_pmf = s->env_row_pmf.as<float>();
+  S.env_row_cdf = s->env_row_cdf.as<float>();
+  S.env_col_pmf = s->env_col_pmf.as<float>();
+  S.env_col_cdf = s->env_col_cdf.as<float>();
+  S.env_w = s->env_w;
+  S.env_h = s->env_h;
+  S.tmin = s->tmin;
+  S.axis[0] = 0.0f;
+  S.axis[1] = 0.0f;
+  S.axis[2] = 1.0f;
+  S.spill = s->spill.as<uint2>();
+  S.stack_cap = 3 * std::max(s->bvh_depth, 1) + 4;
+  S.spill_stride = (uint32_t)grid_trace * kBlock;
+  return S;
+}
+
+PathsDev paths_dev(pt_scene* s, int64_t n, int x0, int y0, int w) {
+  PathsDev P;
+  std::memset(&P, 0, sizeof(P));
+  P.ray_o = s->ray_o.as<float4>();
+  P.ray_d = s->ray_d.as<float4>();
+  P.hit = s->hit.as<float4>();
+  P.beta = s->beta.as<float4>();
+  P.L = s->L.as<float4>();
+  P.flags = s->flags.as<uint32_t>();
+  for (int i = 0; i < 2; ++i) P.q_ray[i] = s->q_ray[i].as<uint32_t>();
+  for (int i = 0; i < kNumClasses; ++i) P.q_cls[i] = s->q_cls[i].as<uint32_t>();
+  P.sh_o = s->sh_o.as<float4>();
+  P.sh_d = s->sh_d.as<float4>();
+  P.sh_c = s->sh_c.as<float4>();
+  P.counts = s->counts.as<uint32_t>();
+  P.stats = s->stats.as<unsigned long long>();
+  P.sig = s->sig.as<uint64_t>();
+  P.dbg_nee = s->dbg_nee.as<uint32_t>();
+  P.dbg_tail = s->dbg_tail.as<uint32_t>();
+  P.n = (int32_t)n;
+  P.x0 = x0;
+  P.y0 = y0;
+  P.w = w;
+  return P;
+}
+
+pt_status make_camera(const pt_camera* c, CamDev& C) {
+  if (!c) return fail(PT_ERR_INVALID_ARG, "camera is NULL");
+  if (c->width <= 0 || c->height <= 0) return fail(PT_ERR_INVALID_ARG, "camera width/height must be > 0");
+  if ((int64_t)c->width * c->height > (int64_t)1 << 28) return fail(PT_ERR_INVALID_ARG, "image too large");
+  if (!(c->vfov_deg > 0.0f && c->vfov_deg < 180.0f)) return fail(PT_ERR_INVALID_ARG, "vfov_deg must be in (0, 180)");
+  if (!finite_all(c->eye, 3) || !finite_all(c->look_at, 3) || !finite_all(c->up, 3))
+    return fail(PT_ERR_INVALID_ARG, "camera vectors must be finite");
+  double F[3], R[3], U[3];
+  for (int k = 0; k < 3; ++k) F[k] = (double)c->look_at[k] - c->eye[k];
+  double fl = std::sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
+  if (!(fl > 0)) return fail(PT_ERR_INVALID_ARG, "look_at equals eye");
+  for (int k = 0; k < 3; ++k) F[k] /= fl;
+  double up[3] = {c->up[0], c->up[1], c->up[2]};
+  R[0] = F[1] * up[2] - F[2] * up[1];
+  R[1] = F[2] * up[0] - F[0] * up[2];
+  R[2] = F[0] * up[1] - F[1] * up[0];
+  double rl = std::sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+  if (!(rl > 0)) return fail(PT_ERR_INVALID_ARG, "up is parallel to the view direction");
+  for (int k = 0; k < 3; ++k) R[k] /= rl;
+  U[0] = R[1] * F[2] - R[2] * F[1];
+  U[1] = R[2] * F[0] - R[0] * F[2];
+  U[2] = R[0] * F[1] - R[1] * F[0];
+  for (int k = 0; k < 3; ++k) {
+    C.eye[k] = c->eye[k];
+    C.R[k] = (float)R[k];
+    C.U[k] = (float)U[k];
+    C.F[k] = (float)F[k];
+  }
+  C.tan_half = (float)std::tan(0.5 * (double)c->vfov_deg * M_PI / 180.0);
+  C.aspect = (float)((double)c->width / (double)c->height);
+  C.W = c->width;
+  C.H = c->height;
+  return PT_OK;
+}
+
+pt_status ready_to_render(pt_scene* s) {
+  if (!s->has_bvh) return fail(PT_ERR_STATE, "pt_build_bvh has not been called");
+  if (!s->has_mats) return fail(PT_ERR_STATE, "pt_upload_materials has not been called");
+  if (s->max_mat_id >= (int32_t)s->host_mats.size())
+    return fail(PT_ERR_STATE, "material id %d >= material count %d", s->max_mat_id, (int)s->host_mats.size());
+  return ensure_lights(s);
+}
+
+// Run sampling passes over the tile (x0, y0, w, h) of the camera's image.
+pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h, int first, int n, int max_depth,
+                     uint64_t seed, double* sum, float* per_sample, uint64_t* sigs, int spp_total) {
+  int64_t N = (int64_t)w * h;
+  pt_status r = ensure_paths(s, N);
+  if (r) return r;
+  r = ensure_counters(s);
+  if (r) return r;
+  int grid = grid_for(N), grid_trace = grid_for(N);
+  r = ensure_spill(s, grid_trace);
+  if (r) return r;
+  SceneDev S = scene_dev(s, grid_trace);
+  PathsDev P = paths_dev(s, N, x0, y0, w);
+  PassArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.k0 = (uint32_t)seed;
+  A.k1 = (uint32_t)(seed >> 32);
+  A.max_depth = max_depth;
+  A.grid = grid;
+  A.grid_trace = grid_trace;
+  A.debug = per_sample != nullptr;
+  A.count = s->counting;
+  A.class_mask = s->class_mask | (1u << kClsMiss);
+  int nev = 2 * (max_depth + 1) + 2;
+  if (s->timing) {
+    while ((int)s->events.size() < nev) {
+      hipEvent_t e;
+      PT_HIP(hipEventCreate(&e));
+      s->events.push_back(e);
+    }
+    A.ext_events = s->events.data() + 2;
+  }
+  for (int k = 0; k < n; ++k) {
+    A.sample = (uint32_t)(first + k);
+    if (s->timing) PT_HIP(hipEventRecord(s->events[0], s->stream));
+    PT_HIP(launch_pass(S, P, C, A, s->stream));
+    PT_HIP(launch_accumulate(P, sum, C.W, per_sample, sigs, spp_total, k, s->stream));
+    if (s->timing) {
+      PT_HIP(hipEventRecord(s->events[1], s->stream));
+      PT_HIP(hipEventSynchronize(s->events[1]));
+      float ms = 0.0f;
+      PT_HIP(hipEventElapsedTime(&ms, s->events[0], s->events[1]));
+      s->ms_total += ms;
+      for (int b = 0; b <= max_depth; ++b) {
+        PT_HIP(hipEventElapsedTime(&ms, A.ext_events[2 * b], A.ext_events[2 * b + 1]));
+        s->ms_extend += ms;
+        s->launches_extend++;
+      }
+    }
+  }
+  s->samples += (int64_t)n * N;
+  return PT_OK;
+}
+
+pt_status check_render_args(int spp, int max_depth) {
+  if (spp <= 0) return fail(PT_ERR_INVALID_ARG, "spp must be > 0");
+  if (max_depth < 0 || max_depth > 64) return fail(PT_ERR_INVALID_ARG, "max_depth must be in [0, 64]");
+  return PT_OK;
+}
+
+pt_status ensure_accum(pt_scene* s, int W, int H) {
+  if (s->acc_w != W || s->acc_h != H || !s->sum.p) {
+    PT_HIP(s->sum.alloc((size_t)W * H * 3 * sizeof(double)));
+    PT_HIP(launch_zero_f64(s->sum.as<double>(), (int64_t)W * H * 3, s->stream));
+    s->acc_w = W;
+    s->acc_h = H;
+    s->acc_samples = 0;
+  }
+  return PT_OK;
+}
+
+pt_status sync(pt_scene* s) {
+  PT_HIP(hipStreamSynchronize(s->stream));
+  PT_HIP(hipGetLastError());
+  return PT_OK;
+}
+
+pt_status validate_material(const pt_openpbr_material& m, int i) {
+  const float* f = reinterpret_cast<const float*>(&m);
+  for (int k = 0; k < 27; ++k) {
+    if (!std::isfinite(f[k]) || f[k] < 0.0f) return fail(PT_ERR_INVALID_ARG, "material %d: parameter %d is negative or not finite", i, k);
+  }
+  const float unit[] = {m.base_weight, m.base_metalness, m.specular_weight, m.specular_roughness,
+                        m.specular_roughness_anisotropy, m.transmission_weight, m.coat_weight, m.coat_roughness};
+  for (float u : unit)
+    if (u > 1.0f) return fail(PT_ERR_INVALID_ARG, "material %d: weights and roughness must be in [0, 1]", i);
+  if (!(m.specular_ior > 0.0f) || !(m.coat_ior > 0.0f)) return fail(PT_ERR_INVALID_ARG, "material %d: IOR must be > 0", i);
+  if (m.base_diffuse_roughness != 0.0f)
+    return fail(PT_ERR_UNSUPPORTED, "material %d: base_diffuse_roughness != 0 is not supported", i);
+  if (m.coat_weight > 0.0f && m.transmission_weight > 0.0f)
+    return fail(PT_ERR_UNSUPPORTED, "material %d: coat together with transmission is not supported", i);
+  return PT_OK;
+}
+
+MatRec make_matrec(const pt_openpbr_material& m) {
+  MatRec r;
+  std::memset(&r, 0, sizeof(r));
+  for (int c = 0; c < 3; ++c) {
+    r.base_color[c] = m.base_color[c];
+    r.spec_color[c] = m.specular_color[c];
+    r.trans_color[c] = m.transmission_color[c];
+    r.coat_color[c] = m.coat_color[c];
+    r.Le[c] = (float)((double)m.emission_luminance * m.emission_color[c]);
+  }
+  r.base_weight = m.base_weight;
+  r.metalness = m.base_metalness;
+  r.spec_weight = m.specular_weight;
+  r.spec_ior = m.specular_ior;
+  r.trans_weight = m.transmission_weight;
+  r.coat_weight = m.coat_weight;
+  r.coat_ior = m.coat_ior;
+  r.bwbc_lum = (float)lumd((double)m.base_weight * m.base_color[0], (double)m.base_weight * m.base_color[1],
+                           (double)m.base_weight * m.base_color[2]);
+  double rr = m.specular_roughness, a = m.specular_roughness_anisotropy;
+  double alpha = rr * rr;
+  double at = alpha * std::sqrt(2.0 / (1.0 + (1.0 - a) * (1.0 - a)));
+  r.at = (float)std::max(at, 1e-4);
+  r.ab = (float)std::max((1.0 - a) * at, 1e-4);
+  r.ac = (float)std::max((double)m.coat_roughness * m.coat_roughness, 1e-4);
+  uint32_t fl = 0;
+  if (m.specular_roughness < 1e-3f) fl |= kMatSpecDelta;
+  if (m.coat_roughness < 1e-3f) fl |= kMatCoatDelta;
+  if (m.emission_luminance > 0.0f && lumd(m.emission_color[0], m.emission_color[1], m.emission_color[2]) > 0.0)
+    fl |= kMatEmissive;
+  r.flags = fl;
+  // class: the smallest lobe set that contains every lobe the material can use
+  bool hasC = m.coat_weight > 0.0f;
+  bool hasM = m.base_metalness > 0.0f && m.specular_weight > 0.0f;
+  bool hasI = m.base_metalness < 1.0f && (m.specular_weight > 0.0f || m.transmission_weight > 0.0f);
+  bool hasD = m.base_metalness < 1.0f && m.transmission_weight < 1.0f && r.bwbc_lum > 0.0f;
+  bool hasT = m.base_metalness < 1.0f && m.transmission_weight > 0.0f;
+  int cls;
+  if (!hasC && !hasM && !hasI && !hasD) cls = kClsAbsorb;
+  else if (!hasC && !hasM && !hasI) cls = kClsDiffuse;
+  else if (!hasC && !hasI && !hasD) cls = kClsMetal;
+  else if (!hasM && !hasT) cls = kClsPlastic;
+  else if (!hasC && !hasM) cls = kClsGlass;
+  else cls = kClsGeneral;
+  r.cls = cls;
+  return r;
+}
+
+}  // namespace
+
+// =============================================================== C ABI ====
+extern "C" {
+
+const char* pt_last_error(void) { return g_err.c_str(); }
+
+const char* pt_version(void) { return "pt 0.1 (gfx950 wavefront path tracer)"; }
+
+pt_status pt_scene_create(int32_t hip_device, void* hip_stream, pt_scene** out) {
+  if (!out) return fail(PT_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return fail(PT_ERR_DEVICE, "hipGetDeviceCount failed: %s", hipGetErrorString(e));
+  if (hip_device < 0 || hip_device >= n) return fail(PT_ERR_INVALID_ARG, "device %d out of range [0, %d)", hip_device, n);
+  std::unique_ptr<pt_scene> s(new (std::nothrow) pt_scene());
+  if (!s) return fail(PT_ERR_OUT_OF_MEMORY, "out of host memory");
+  s->device = hip_device;
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  pt_status r = set_device(s.get());
+  if (r) return r;
+  *out = s.release();
+  return PT_OK;
+}
+
+void pt_scene_destroy(pt_scene* s) {
+  if (!s) return;
+  (void)hipSetDevice(s->device);
+  (void)hipStreamSynchronize(s->stream);
+  for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
+  delete s;
+}
+
+pt_status pt_build_bvh(pt_scene* s, const pt_mesh* meshes, int32_t n_meshes, const pt_instance* instances,
+                       int32_t n_instances) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (!meshes || n_meshes <= 0) return fail(PT_ERR_INVALID_ARG, "meshes must be non-NULL with n_meshes > 0");
+  if (n_instances < 0 || (n_instances > 0 && !instances)) return fail(PT_ERR_INVALID_ARG, "bad instances");
+  if (n_instances > 0) return fail(PT_ERR_UNSUPPORTED, "instanced scenes are not supported by this build yet");
+  int64_t total = 0;
+  for (int i = 0; i < n_meshes; ++i) {
+    const pt_mesh& m = meshes[i];
+    if (!m.vertices || !m.indices || m.n_vertices <= 0 || m.n_triangles <= 0)
+      return fail(PT_ERR_INVALID_ARG, "mesh %d: NULL arrays or empty counts", i);
+    if (!m.material_ids) return fail(PT_ERR_INVALID_ARG, "mesh %d: material_ids is NULL and nothing overrides it", i);
+    if (!finite_all(m.vertices, (size_t)m.n_vertices * 3)) return fail(PT_ERR_INVALID_ARG, "mesh %d: non-finite vertex", i);
+    for (int64_t t = 0; t < m.n_triangles * 3; ++t)
+      if (m.indices[t] < 0 || m.indices[t] >= m.n_vertices)
+        return fail(PT_ERR_INVALID_ARG, "mesh %d: index %lld out of range", i, (long long)m.indices[t]);
+    for (int64_t t = 0; t < m.n_triangles; ++t)
+      if (m.material_ids[t] < 0) return fail(PT_ERR_INVALID_ARG, "mesh %d: negative material id", i);
+    total += m.n_triangles;
+  }
+  if (total >= (int64_t)kLeafFirstMask) return fail(PT_ERR_INVALID_ARG, "too many triangles");
+  std::vector<float> verts((size_t)total * 9);
+  std::vector<int32_t> mat((size_t)total);
+  std::vector<uint32_t> prim((size_t)total), matu((size_t)total);
+  int64_t t = 0;
+  int32_t max_mat = -1;
+  for (int i = 0; i < n_meshes; ++i) {
+    const pt_mesh& m = meshes[i];
+    for (int64_t k = 0; k < m.n_triangles; ++k, ++t) {
+      for (int v = 0; v < 3; ++v) {
+        int32_t vi = m.indices[3 * k + v];
+        for (int c = 0; c < 3; ++c) verts[9 * (size_t)t + 3 * v + c] = m.vertices[3 * (size_t)vi + c];
+      }
+      mat[(size_t)t] = m.material_ids[k];
+      matu[(size_t)t] = (uint32_t)m.material_ids[k];
+      prim[(size_t)t] = (uint32_t)t;
+      max_mat = std::max(max_mat, m.material_ids[k]);
+    }
+  }
+  Bvh4 bvh;
+  std::string err;
+  if (!build_bvh4(verts.data(), prim.data(), matu.data(), total, bvh, err)) return fail(PT_ERR_INVALID_ARG, "%s", err.c_str());
+  r = set_device(s);
+  if (r) return r;
+  PT_HIP(upload(s->nodes, bvh.nodes.data(), bvh.nodes.size() * sizeof(BVHNode), s->stream));
+  PT_HIP(upload(s->tris, bvh.tris.data(), bvh.tris.size() * sizeof(TriRec), s->stream));
+  PT_HIP(hipStreamSynchronize(s->stream));
+  double dx = (double)bvh.hi[0] - bvh.lo[0], dy = (double)bvh.hi[1] - bvh.lo[1], dz = (double)bvh.hi[2] - bvh.lo[2];
+  s->tmin = (float)(1e-5 * std::sqrt(dx * dx + dy * dy + dz * dz));
+  s->n_tris = (uint32_t)total;
+  s->bvh_depth = bvh.depth;
+  s->max_mat_id = max_mat;
+  s->host_tri_verts.swap(verts);
+  s->host_tri_mat.swap(mat);
+  s->has_bvh = true;
+  s->lights_dirty = true;
+  return PT_OK;
+}
+
+pt_status pt_upload_materials(pt_scene* s, const pt_openpbr_material* m, int32_t n) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (!m || n <= 0) return fail(PT_ERR_INVALID_ARG, "materials must be non-NULL with n > 0");
+  std::vector<MatRec> recs((size_t)n);
+  uint32_t mask = 0;
+  for (int i = 0; i < n; ++i) {
+    r = validate_material(m[i], i);
+    if (r) return r;
+    recs[(size_t)i] = make_matrec(m[i]);
+    mask |= 1u << recs[(size_t)i].cls;
+  }
+  r = set_device(s);
+  if (r) return r;
+  PT_HIP(upload(s->mats, recs.data(), recs.size() * sizeof(MatRec), s->stream));
+  PT_HIP(hipStreamSynchronize(s->stream));
+  s->host_mats.assign(m, m + n);
+  s->class_mask = mask;
+  s->has_mats = true;
+  s->lights_dirty = true;
+  return PT_OK;
+}
+
+pt_status pt_set_environment(pt_scene* s, const float* rgb, int32_t w, int32_t h) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  r = set_device(s);
+  if (r) return r;
+  if (!rgb) {
+    s->env_w = s->env_h = 0;
+    s->lights_dirty = true;
+    return PT_OK;
+  }
+  if (w <= 0 || h <= 0) return fail(PT_ERR_INVALID_ARG, "environment size must be > 0");
+  size_t n = (size_t)w * h;
+  for (size_t i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(rgb[i]) || rgb[i] < 0.0f) return fail(PT_ERR_INVALID_ARG, "environment texel %zu is negative or not finite", i / 3);
+  // piecewise-constant sampling tables: texel weight lum * sin(theta at the row centre)
+  std::vector<float4> tex(n);
+  std::vector<double> colw(n);
+  std::vector<double> roww((size_t)h);
+  double total = 0.0;
+  for (int y = 0; y < h; ++y) {
+    double st = std::sin(M_PI * (y + 0.5) / h);
+    double rs = 0.0;
+    for (int x = 0; x < w; ++x) {
+      size_t i = (size_t)y * w + x;
+      tex[i] = make_float4(rgb[3 * i], rgb[3 * i + 1], rgb[3 * i + 2], 0.0f);
+      double wt = lumd(rgb[3 * i], rgb[3 * i + 1], rgb[3 * i + 2]) * st;
+      colw[i] = wt;
+      rs += wt;
+    }
+    roww[(size_t)y] = rs;
+    total += rs;
+  }
+  if (!(total > 0.0)) {  // a black environment is the same as none
+    s->env_w = s->env_h = 0;
+    s->lights_dirty = true;
+    return PT_OK;
+  }
+  std::vector<float> col_pmf(n), col_cdf((size_t)h * (w + 1)), row_pmf((size_t)h), row_cdf((size_t)h + 1);
+  for (int y = 0; y < h; ++y) {
+    double rs = roww[(size_t)y];
+    double acc = 0.0;
+    float* cdf = &col_cdf[(size_t)y * (w + 1)];
+    cdf[0] = 0.0f;
+    for (int x = 0; x < w; ++x) {
+      size_t i = (size_t)y * w + x;
+      acc += colw[i];
+      col_pmf[i] = rs > 0.0 ? (float)(colw[i] / rs) : 0.0f;
+      cdf[x + 1] = rs > 0.0 ? (float)(acc / rs) : 0.0f;
+    }
+    if (rs > 0.0) cdf[w] = 1.0f;
+  }
+  double acc = 0.0;
+  row_cdf[0] = 0.0f;
+  for (int y = 0; y < h; ++y) {
+    row_pmf[(size_t)y] = (float)(roww[(size_t)y] / total);
+    acc += roww[(size_t)y];
+    row_cdf[(size_t)y + 1] = (float)(acc / total);
+  }
+  row_cdf[(size_t)h] = 1.0f;
+  PT_HIP(upload(s->env, tex.data(), n * sizeof(float4), s->stream));
+  PT_HIP(upload(s->env_col_pmf, col_pmf.data(), n * sizeof(float), s->stream));
+  PT_HIP(upload(s->env_col_cdf, col_cdf.data(), col_cdf.size() * sizeof(float), s->stream));
+  PT_HIP(upload(s->env_row_pmf, row_pmf.data(), row_pmf.size() * sizeof(float), s->stream));
+  PT_HIP(upload(s->env_row_cdf, row_cdf.data(), row_cdf.size() * sizeof(float), s->stream));
+  PT_HIP(hipStreamSynchronize(s->stream));
+  s->env_w = w;
+  s->env_h = h;
+  s->lights_dirty = true;
+  return PT_OK;
+}
+
+pt_status pt_reset_accumulation(pt_scene* s) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  r = set_device(s);
+  if (r) return r;
+  if (s->sum.p) PT_HIP(launch_zero_f64(s->sum.as<double>(), (int64_t)s->acc_w * s->acc_h * 3, s->stream));
+  s->acc_samples = 0;
+  return sync(s);
+}
+
+pt_status pt_accumulate(pt_scene* s, const pt_camera* cam, int32_t first, int32_t n, int32_t max_depth,
+                        uint64_t seed) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  CamDev C;
+  if ((r = make_camera(cam, C))) return r;
+  if ((r = check_render_args(n, max_depth))) return r;
+  if (first < 0) return fail(PT_ERR_INVALID_ARG, "first_sample must be >= 0");
+  if ((r = set_device(s))) return r;
+  if ((r = ready_to_render(s))) return r;
+  if ((r = ensure_accum(s, C.W, C.H))) return r;
+  if ((r = run_passes(s, C, 0, 0, C.W, C.H, first, n, max_depth, seed, s->sum.as<double>(), nullptr, nullptr, n)))
+    return r;
+  s->acc_samples += n;
+  return sync(s);
+}
+
+pt_status pt_resolve(pt_scene* s, float* out, double* out_sum) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (!out) return fail(PT_ERR_INVALID_ARG, "out_rgb32f is NULL");
+  if (s->acc_samples <= 0) return fail(PT_ERR_STATE, "nothing accumulated");
+  if ((r = set_device(s))) return r;
+  int64_t nv = (int64_t)s->acc_w * s->acc_h * 3;
+  PT_HIP(launch_resolve(s->sum.as<double>(), out, nv, 1.0 / (double)s->acc_samples, s->stream));
+  if (out_sum) PT_HIP(hipMemcpyAsync(out_sum, s->sum.p, (size_t)nv * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+  return sync(s);
+}
+
+pt_status pt_render(pt_scene* s, const pt_camera* cam, int32_t spp, int32_t max_depth, uint64_t seed, float* out) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  CamDev C;
+  if ((r = make_camera(cam, C))) return r;
+  if ((r = check_render_args(spp, max_depth))) return r;
+  if (!out) return fail(PT_ERR_INVALID_ARG, "out_rgb32f is NULL");
+  if ((r = set_device(s))) return r;
+  if ((r = ready_to_render(s))) return r;
+  if ((r = ensure_accum(s, C.W, C.H))) return r;
+  PT_HIP(launch_zero_f64(s->sum.as<double>(), (int64_t)C.W * C.H * 3, s->stream));
+  s->acc_samples = 0;
+  if ((r = run_passes(s, C, 0, 0, C.W, C.H, 0, spp, max_depth, seed, s->sum.as<double>(), nullptr, nullptr, spp)))
+    return r;
+  s->acc_samples = spp;
+  PT_HIP(launch_resolve(s->sum.as<double>(), out, (int64_t)C.W * C.H * 3, 1.0 / (double)spp, s->stream));
+  return sync(s);
+}
+
+pt_status pt_render_debug(pt_scene* s, const pt_camera* cam, int32_t x0, int32_t y0, int32_t w, int32_t h,
+                          int32_t first, int32_t spp, int32_t max_depth, uint64_t seed, float* per_sample,
+                          uint64_t* sig) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  CamDev C;
+  if ((r = make_camera(cam, C))) return r;
+  if ((r = check_render_args(spp, max_depth))) return r;
+  if (!per_sample || !sig) return fail(PT_ERR_INVALID_ARG, "output pointers are NULL");
+  if (first < 0) return fail(PT_ERR_INVALID_ARG, "first_sample must be >= 0");
+  if (w <= 0 || h <= 0 || x0 < 0 || y0 < 0 || x0 + w > C.W || y0 + h > C.H)
+    return fail(PT_ERR_INVALID_ARG, "crop outside the image");
+  if ((r = set_device(s))) return r;
+  if ((r = ready_to_render(s))) return r;
+  if ((r = run_passes(s, C, x0, y0, w, h, first, spp, max_depth, seed, nullptr, per_sample, sig, spp))) return r;
+  return sync(s);
+}
+
+pt_status pt_trace_closest(pt_scene* s, const float* rays, int64_t n, uint32_t* hits, int32_t brute) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (n < 0 || (n > 0 && (!rays || !hits))) return fail(PT_ERR_INVALID_ARG, "bad rays/hits");
+  if (!s->has_bvh) return fail(PT_ERR_STATE, "pt_build_bvh has not been called");
+  if (n == 0) return PT_OK;
+  if ((r = set_device(s))) return r;
+  int grid = trace_grid_blocks();
+  if ((r = ensure_spill(s, grid))) return r;
+  SceneDev S = scene_dev(s, grid);
+  PT_HIP(launch_trace_rays(S, rays, n, hits, brute != 0, grid, s->stream));
+  return sync(s);
+}
+
+pt_status pt_get_stats(pt_scene* s, pt_stats* o) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (!o) return fail(PT_ERR_INVALID_ARG, "out is NULL");
+  std::memset(o, 0, sizeof(*o));
+  if (s->stats.p) {
+    if ((r = set_device(s))) return r;
+    unsigned long long v[kNumStats];
+    PT_HIP(hipMemcpyAsync(v, s->stats.p, sizeof(v), hipMemcpyDeviceToHost, s->stream));
+    PT_HIP(hipStreamSynchronize(s->stream));
+    o->extension_rays = (int64_t)v[kStatExt];
+    o->shadow_rays = (int64_t)v[kStatShadow];
+    o->nonfinite_dropped = (int64_t)v[kStatNonFinite];
+    o->node_visits = (int64_t)v[kStatNodes];
+    o->tri_tests = (int64_t)v[kStatTris];
+    o->shadow_node_visits = (int64_t)v[kStatShadowNodes];
+    o->shadow_tri_tests = (int64_t)v[kStatShadowTris];
+    if (v[kStatOverflow]) return fail(PT_ERR_DEVICE, "traversal stack overflow in %llu workgroups", v[kStatOverflow]);
+  }
+  o->samples = s->samples;
+  o->ms_extend = s->ms_extend;
+  o->launches_extend = s->launches_extend;
+  o->ms_total = s->ms_total;
+  return PT_OK;
+}
+
+pt_status pt_reset_stats(pt_scene* s) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if ((r = set_device(s))) return r;
+  if ((r = ensure_counters(s))) return r;
+  PT_HIP(launch_zero_u64(s->stats.as<unsigned long long>(), kNumStats, s->stream));
+  s->ms_extend = s->ms_total = 0.0;
+  s->launches_extend = 0;
+  s->samples = 0;
+  return sync(s);
+}
+
+pt_status pt_set_profiling(pt_scene* s, int32_t timing, int32_t counting) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  s->timing = timing != 0;
+  s->counting = counting != 0;
+  return PT_OK;
+}
+
+// ------------------------------------------------------- host-only BVH
+struct pt_bvh_host {
+  Bvh4 b;
+};
+
+pt_status pt_bvh_host_build(const pt_mesh* m, pt_bvh_host** out) {
+  if (!m || !out) return fail(PT_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  if (!m->vertices || !m->indices || m->n_vertices <= 0 || m->n_triangles <= 0)
+    return fail(PT_ERR_INVALID_ARG, "NULL arrays or empty counts");
+  int64_t n = m->n_triangles;
+  std::vector<float> verts((size_t)n * 9);
+  std::vector<uint32_t> prim((size_t)n), mat((size_t)n);
+  for (int64_t t = 0; t < n; ++t) {
+    for (int v = 0; v < 3; ++v) {
+      int32_t vi = m->indices[3 * t + v];
+      if (vi < 0 || vi >= m->n_vertices) return fail(PT_ERR_INVALID_ARG, "index out of range");
+      for (int c = 0; c < 3; ++c) verts[9 * (size_t)t + 3 * v + c] = m->vertices[3 * (size_t)vi + c];
+    }
+    prim[(size_t)t] = (uint32_t)t;
+    mat[(size_t)t] = m->material_ids ? (uint32_t)m->material_ids[t] : 0u;
+  }
+  std::unique_ptr<pt_bvh_host> h(new (std::nothrow) pt_bvh_host());
+  if (!h) return fail(PT_ERR_OUT_OF_MEMORY, "out of host memory");
+  std::string err;
+  if (!build_bvh4(verts.data(), prim.data(), mat.data(), n, h->b, err)) return fail(PT_ERR_INVALID_ARG, "%s", err.c_str());
+  *out = h.release();
+  return PT_OK;
+}
+
+pt_status pt_bvh_host_info(const pt_bvh_host* h, pt_bvh_info* info) {
+  if (!h || !info) return fail(PT_ERR_INVALID_ARG, "NULL argument");
+  info->n_nodes = (int64_t)h->b.nodes.size();
+  info->n_tris = (int64_t)h->b.tris.size();
+  info->depth = h->b.depth;
+  info->max_leaf_tris = h->b.max_leaf;
+  info->sah_cost = h->b.sah_cost;
+  info->build_ms = h->b.build_ms;
+  return PT_OK;
+}
+
+pt_status pt_bvh_host_copy(const pt_bvh_host* h, void* nodes, void* tris) {
+  if (!h || !nodes || !tris) return fail(PT_ERR_INVALID_ARG, "NULL argument");
+  std::memcpy(nodes, h->b.nodes.data(), h->b.nodes.size() * sizeof(BVHNode));
+  std::memcpy(tris, h->b.tris.data(), h->b.tris.size() * sizeof(TriRec));
+  return PT_OK;
+}
+
+pt_status pt_bvh_host_trace(const pt_bvh_host* h, const float* rays, int64_t n, uint32_t* hits) {
+  if (!h || n < 0 || (n > 0 && (!rays || !hits))) return fail(PT_ERR_INVALID_ARG, "bad arguments");
+  for (int64_t i = 0; i < n; ++i) {
+    const float* R = rays + 8 * i;
+    RayPre r = ray_prepare(R[0], R[1], R[2], R[4], R[5], R[6]);
+    Hit best;
+    hit_clear(best);
+    HostStack st;
+    uint32_t nv = 0, nt = 0;
+    traverse_bvh<false, false>(h->b.nodes.data(), h->b.tris.data(), 0u, r, R[3], R[7], 0u, 0xFFFFFFFFu, 0xFFFFFFFFu,
+                               best, st, nv, nt);
+    if (st.overflow) return fail(PT_ERR_DEVICE, "host traversal stack overflow");
+    uint32_t* H = hits + 6 * i;
+    bool hit = best.tri != 0xFFFFFFFFu;
+    H[0] = f2u(best.t);
+    H[1] = hit ? best.inst : 0xFFFFFFFFu;
+    H[2] = hit ? best.prim : 0xFFFFFFFFu;
+    H[3] = hit ? f2u(best.b1) : 0u;
+    H[4] = hit ? f2u(best.b2) : 0u;
+    H[5] = hit ? 1u : 0u;
+  }
+  return PT_OK;
+}
+
+void pt_bvh_host_destroy(pt_bvh_host* h) { delete h; }
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// Internal declarations of the path-tracer library: device parameter blocks,
+// the scene object behind the C ABI, and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pt.h"
+#include "bvh_build.h"
+#include "pt_layout.h"
+
+namespace pt {
+
+constexpr int kBlock = 256;     // threads per workgroup (4 waves of 64)
+constexpr int kLdsStack = 16;   // traversal stack entries per lane kept in LDS
+
+// Scene data the kernels read (all device pointers).
+struct SceneDev {
+  const BVHNode* nodes;
+  const TriRec* tris;
+  uint32_t n_tris;
+  uint32_t root;
+  const MatRec* mats;
+  const int32_t* tri_light;  // light index by primitive id, -1 if not emissive
+  const LightTri* lights;
+  const float* light_cdf;    // [n_lights + 1]
+  int32_t n_lights;
+  float p_env;               // probability of sampling the environment
+  const float4* env;         // [h][w] rgb + unused
+  const float* env_row_pmf;  // [h]
+  const float* env_row_cdf;  // [h + 1]
+  const float* env_col_pmf;  // [h][w]
+  const float* env_col_cdf;  // [h][w + 1]
+  int32_t env_w, env_h;
+  float tmin;                // self-intersection offset: 1e-5 x scene diagonal
+  float axis[3];             // object +z axis in world space (shading tangent)
+  uint2* spill;              // traversal stack spill, [cap - kLdsStack][grid threads]
+  int32_t stack_cap;         // total stack entries per lane
+  uint32_t spill_stride;     // grid threads of the traversal kernels
+};
+
+// Camera basis computed on the host in double and rounded to float.
+struct CamDev {
+  float eye[3], R[3], U[3], F[3];
+  float tan_half, aspect;
+  int32_t W, H;
+};
+
+// Wavefront path state, structure-of-arrays, indexed by path slot.
+struct PathsDev {
+  float4* ray_o;       // o.xyz, skip primitive (bits)
+  float4* ray_d;       // d.xyz, skip instance (bits)
+  float4* hit;         // t, b1, b2, triangle record index (bits; 0xFFFFFFFF = miss)
+  float4* beta;        // throughput rgb, pdf of the last BSDF sample
+  float4* L;           // radiance rgb, eta scale (product of eta^2 over refractions)
+  uint32_t* flags;     // bit 0: last bounce was a delta lobe
+  uint32_t* q_ray[2];  // extension queues (double-buffered)
+  uint32_t* q_cls[kNumClasses];
+  float4* sh_o;        // shadow ray o.xyz, tmax
+  float4* sh_d;        // d.xyz, path slot (bits)
+  float4* sh_c;        // contribution rgb, skip primitive (bits)
+  uint32_t* counts;    // [0..1] ray queues, [2..2+kNumClasses) classes, [2+kNumClasses] shadow
+  unsigned long long* stats;  // see kStat*
+  uint64_t* sig;       // path signatures (debug)
+  uint32_t* dbg_nee;   // pending next-event light id (debug)
+  uint32_t* dbg_tail;  // pending lobe / roulette / end events (debug)
+  int32_t n;           // number of path slots
+  int32_t x0, y0, w;   // slot -> pixel (x0 + slot % w, y0 + slot / w)
+};
+
+enum {
+  kStatExt = 0,
+  kStatShadow = 1,
+  kStatNonFinite = 2,
+  kStatNodes = 3,
+  kStatTris = 4,
+  kStatOverflow = 5,
+  kStatShadowNodes = 6,
+  kStatShadowTris = 7,
+  kNumStats = 8
+};
+constexpr int kCountShadow = 2 + kNumClasses;
+constexpr int kNumCounts = 16;
+
+// ---- kernel launchers (pt_kernels.hip) ----
+struct PassArgs {
+  uint32_t sample;
+  uint32_t k0, k1;  // Philox key
+  int max_depth;
+  int grid;         // workgroups of the persistent kernels
+  int grid_trace;   // workgroups of the traversal kernels
+  bool debug;
+  bool count;
+  uint32_t class_mask;  // material classes present (bit per class)
+  hipEvent_t* ext_events;  // 2 per bounce when timing, else nullptr
+};
+
+hipError_t launch_pass(const SceneDev& S, const PathsDev& P, const CamDev& C, const PassArgs& A,
+                       hipStream_t st);
+hipError_t launch_accumulate(const PathsDev& P, double* sum, int W, float* per_sample, uint64_t* sig_out,
+                             int spp_total, int sample_index, hipStream_t st);
+hipError_t launch_resolve(const double* sum, float* out, int64_t n_values, double inv_spp, hipStream_t st);
+hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
+hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st);
+hipError_t launch_trace_rays(const SceneDev& S, const float* rays, int64_t n, uint32_t* hits, bool brute,
+                             int grid, hipStream_t st);
+int trace_grid_blocks();
+
+}  // namespace pt

@@ -1,0 +1,662 @@
+// Wavefront path-tracing kernels for gfx950 (wave64).
+//
+// One sampling pass traces one path per slot (one sample of every pixel of
+// the tile) through the loop
+//   generate -> [reset -> extend -> shade<class>... -> connect] x (max_depth+1) -> accumulate
+// Queues live in HBM and are compacted per wavefront: a ballot of the
+// lanes that append, a popcount, one atomic per wave on the queue tail and
+// a lane-prefix (mbcnt) for the slot.  Queue lengths never leave the device:
+// every kernel is launched over a fixed grid and strides over the length it
+// reads from the counter array.
+#include <hip/hip_runtime.h>
+
+#include "pt_internal.h"
+#include "pt_shade.h"
+#include "pt_trace.h"
+
+namespace pt {
+
+// ------------------------------------------------------------ wave helpers
+__device__ inline uint32_t lane_id() { return __lane_id(); }
+
+__device__ inline uint32_t lane_prefix(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Append `value` to queue q (tail at *count) for the lanes with `pred`;
+// one atomic per wave.  Returns the slot written (or 0xFFFFFFFF).
+__device__ inline uint32_t wave_append(bool pred, uint32_t* count) {
+  uint64_t m = __ballot(pred);
+  if (m == 0) return 0xFFFFFFFFu;
+  uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
+  base = __shfl(base, (int)leader);
+  return pred ? base + lane_prefix(m) : 0xFFFFFFFFu;
+}
+
+// ------------------------------------------------------------- signatures
+constexpr uint64_t kFnvOffset = 0xcbf29ce484222325ull;
+constexpr uint64_t kFnvPrime = 0x100000001b3ull;
+
+__device__ inline uint64_t sig_word(uint64_t h, uint32_t w) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    h ^= (uint64_t)((w >> (8 * i)) & 0xFFu);
+    h *= kFnvPrime;
+  }
+  return h;
+}
+
+// Tail events of a vertex, kept until the shadow ray of that vertex is
+// resolved: lobe code (8 bits, 0xFF none), roulette (2 bits: 0 none,
+// 1 survived, 2 killed), end reason (3 bits, 7 none).
+__device__ inline uint32_t tail_pack(int lobe, int rr, int end) {
+  return ((uint32_t)(lobe & 0xFF)) | ((uint32_t)rr << 8) | ((uint32_t)(end & 7) << 10);
+}
+__device__ inline uint64_t sig_tail(uint64_t h, uint32_t tail) {
+  uint32_t lobe = tail & 0xFFu, rr = (tail >> 8) & 3u, end = (tail >> 10) & 7u;
+  if (lobe != 0xFFu) { h = sig_word(h, 3); h = sig_word(h, lobe); }
+  if (rr != 0u) { h = sig_word(h, 4); h = sig_word(h, rr == 2u ? 1u : 0u); }
+  if (end != 7u) { h = sig_word(h, 6); h = sig_word(h, end); }
+  return h;
+}
+
+// ----------------------------------------------------------------- stacks
+// Traversal stack: the first kLdsStack entries of each lane in LDS (entry
+// e of lane l at [e][l], conflict-free), deeper entries in a global spill
+// area.  The capacity (3 x BVH depth + 4) bounds a depth-first walk that
+// pushes at most three siblings per level.
+struct DevStack {
+  uint32_t* lref;
+  float* lkey;
+  uint2* spill;
+  uint32_t sstride;
+  int sp, cap;
+  bool overflow;
+  __device__ inline void push(uint32_t r, float k) {
+    if (sp < kLdsStack) {
+      lref[sp * kBlock] = r;
+      lkey[sp * kBlock] = k;
+    } else if (sp < cap) {
+      spill[(size_t)(sp - kLdsStack) * sstride] = make_uint2(r, f2u(k));
+    } else {
+      overflow = true;
+      return;
+    }
+    sp++;
+  }
+  __device__ inline uint32_t pop(float& k) {
+    --sp;
+    if (sp < kLdsStack) {
+      k = lkey[sp * kBlock];
+      return lref[sp * kBlock];
+    }
+    uint2 v = spill[(size_t)(sp - kLdsStack) * sstride];
+    k = u2f(v.y);
+    return v.x;
+  }
+  __device__ inline bool empty() const { return sp == 0; }
+};
+
+// ------------------------------------------------------------------ lights
+__device__ inline int env_texel(const SceneDev& S, V3 d, float& sin_t) {
+  float y = fminf(fmaxf(d.y, -1.0f), 1.0f);
+  float th = acosf(y), ph = atan2f(d.x, -d.z);
+  float u = ph * (0.5f / kPi) + 0.5f, v = th * (1.0f / kPi);
+  int c = (int)floorf(u * (float)S.env_w), r = (int)floorf(v * (float)S.env_h);
+  c = min(max(c, 0), S.env_w - 1);
+  r = min(max(r, 0), S.env_h - 1);
+  sin_t = sqrtf(fmaxf(0.0f, 1.0f - y * y));
+  return r * S.env_w + c;
+}
+
+__device__ inline float env_pdf_texel(const SceneDev& S, int texel, float sin_t) {
+  int r = texel / S.env_w;
+  float P = S.env_row_pmf[r] * S.env_col_pmf[texel];
+  if (!(sin_t > 0.0f)) return 0.0f;
+  return (float)S.env_w * (float)S.env_h * P / (2.0f * kPi * kPi * sin_t);
+}
+
+// bucket i with cdf[i] <= u < cdf[i+1], skipping empty buckets
+__device__ inline int cdf_invert(const float* cdf, int n, float u) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (cdf[mid] <= u) lo = mid;
+    else hi = mid;
+  }
+  int i = lo;
+  while (i < n - 1 && !(cdf[i + 1] > cdf[i])) i++;
+  while (i > 0 && !(cdf[i + 1] > cdf[i])) i--;
+  return i;
+}
+
+struct LightSample {
+  V3 wl;
+  float dist, pdf;
+  V3 Le;
+  uint32_t id;
+  bool ok;
+};
+
+__device__ inline LightSample sample_light(const SceneDev& S, V3 p, float usel, float u1, float u2) {
+  LightSample ls;
+  ls.ok = false;
+  ls.pdf = 0.0f;
+  ls.dist = 0.0f;
+  ls.Le = v3(0.0f, 0.0f, 0.0f);
+  ls.wl = v3(0.0f, 0.0f, 1.0f);
+  ls.id = 0xFFFFFFFFu;
+  if (S.p_env <= 0.0f && S.n_lights == 0) return ls;
+  if (usel < S.p_env) {
+    int W = S.env_w, H = S.env_h;
+    int r = cdf_invert(S.env_row_cdf, H, u1);
+    float pr = S.env_row_pmf[r];
+    float du = pr > 0.0f ? (u1 - S.env_row_cdf[r]) / pr : 0.5f;
+    const float* ccdf = S.env_col_cdf + (size_t)r * (W + 1);
+    int c = cdf_invert(ccdf, W, u2);
+    float pc = S.env_col_pmf[(size_t)r * W + c];
+    float dv = pc > 0.0f ? (u2 - ccdf[c]) / pc : 0.5f;
+    float uu = ((float)c + dv) / (float)W, vv = ((float)r + du) / (float)H;
+    float th = kPi * vv, ph = 2.0f * kPi * (uu - 0.5f);
+    float st, ct, sp, cp;
+    sincosf(th, &st, &ct);
+    sincosf(ph, &sp, &cp);
+    ls.wl = v3(st * sp, ct, -st * cp);
+    ls.dist = INFINITY;
+    ls.id = 0x80000000u | (uint32_t)(r * W + c);
+    if (!(st > 0.0f)) return ls;
+    float P = pr * pc;
+    ls.pdf = S.p_env * (float)W * (float)H * P / (2.0f * kPi * kPi * st);
+    float4 e = S.env[(size_t)r * W + c];
+    ls.Le = v3(e.x, e.y, e.z);
+    ls.ok = ls.pdf > 0.0f;
+    return ls;
+  }
+  float ut = S.p_env > 0.0f ? (usel - S.p_env) / (1.0f - S.p_env) : usel;
+  int k = cdf_invert(S.light_cdf, S.n_lights, ut);
+  ls.id = (uint32_t)k;
+  const LightTri& L = S.lights[k];
+  float sq = sqrtf(u1);
+  float b0 = 1.0f - sq, b1 = u2 * sq;
+  V3 q = v3(L.p0.x, L.p0.y, L.p0.z) * b0 + v3(L.p1.x, L.p1.y, L.p1.z) * b1 +
+         v3(L.p2.x, L.p2.y, L.p2.z) * (1.0f - b0 - b1);
+  V3 to = q - p;
+  float d2 = dot(to, to);
+  float dd = sqrtf(d2);
+  if (!(dd > 0.0f)) return ls;
+  ls.wl = to * (1.0f / dd);
+  ls.dist = dd;
+  float cl = -dot(v3(L.ng.x, L.ng.y, L.ng.z), ls.wl);
+  if (cl <= 0.0f) return ls;
+  ls.pdf = L.p1.w * d2 / (cl * L.p0.w);
+  ls.Le = v3(L.Le.x, L.Le.y, L.Le.z);
+  ls.ok = ls.pdf > 0.0f;
+  return ls;
+}
+
+__device__ inline float pow_heuristic(float a, float b) {
+  float a2 = a * a, b2 = b * b;
+  return a2 + b2 > 0.0f ? a2 / (a2 + b2) : 0.0f;
+}
+
+__device__ inline bool finite3(V3 c) { return isfinite(c.x) && isfinite(c.y) && isfinite(c.z); }
+
+// ---------------------------------------------------------------- generate
+template <bool DEBUG>
+__global__ __launch_bounds__(kBlock) void k_generate(PathsDev P, CamDev C, uint32_t sample, uint32_t k0,
+                                                     uint32_t k1) {
+  int n = P.n;
+  for (int slot = blockIdx.x * kBlock + threadIdx.x; slot < n; slot += gridDim.x * kBlock) {
+    int px = P.x0 + slot % P.w, py = P.y0 + slot / P.w;
+    uint32_t pix = (uint32_t)py * (uint32_t)C.W + (uint32_t)px;
+    U4 r = philox(pix, sample, 0u, 0u, k0, k1);
+    float fx = (float)px + u01(r.x), fy = (float)py + u01(r.y);
+    float x = (2.0f * fx / (float)C.W - 1.0f) * C.tan_half * C.aspect;
+    float y = (1.0f - 2.0f * fy / (float)C.H) * C.tan_half;
+    V3 d = normalize(v3(C.R[0], C.R[1], C.R[2]) * x + v3(C.U[0], C.U[1], C.U[2]) * y + v3(C.F[0], C.F[1], C.F[2]));
+    P.ray_o[slot] = make_float4(C.eye[0], C.eye[1], C.eye[2], u2f(0xFFFFFFFFu));
+    P.ray_d[slot] = make_float4(d.x, d.y, d.z, u2f(0xFFFFFFFFu));
+    P.beta[slot] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
+    P.L[slot] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+    P.flags[slot] = 1u;
+    P.q_ray[0][slot] = (uint32_t)slot;
+    if (DEBUG) P.sig[slot] = kFnvOffset;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) P.counts[0] = (uint32_t)n;
+}
+
+__global__ void k_reset_counts(uint32_t* counts, int next_queue) {
+  int i = threadIdx.x;
+  if (i >= 2 && i <= kCountShadow) counts[i] = 0u;
+  if (i == next_queue) counts[i] = 0u;
+}
+
+// ------------------------------------------------------------------ extend
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock) void k_extend(SceneDev S, PathsDev P, int cur) {
+  __shared__ uint32_t s_ref[kLdsStack * kBlock];
+  __shared__ float s_key[kLdsStack * kBlock];
+  const uint32_t count = P.counts[cur];
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&P.stats[kStatExt], (unsigned long long)count);
+  const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
+  uint32_t nvis = 0, ntri = 0;
+  bool overflow = false;
+  for (uint32_t base = blockIdx.x * kBlock; base < count; base += gridDim.x * kBlock) {
+    uint32_t i = base + threadIdx.x;
+    bool active = i < count;
+    int cls = -1;
+    uint32_t slot = 0;
+    if (active) {
+      slot = P.q_ray[cur][i];
+      float4 o = P.ray_o[slot], d = P.ray_d[slot];
+      RayPre r = ray_prepare(o.x, o.y, o.z, d.x, d.y, d.z);
+      Hit h;
+      hit_clear(h);
+      DevStack st{s_ref + threadIdx.x, s_key + threadIdx.x, S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
+      traverse_bvh<false, COUNT>(S.nodes, S.tris, S.root, r, S.tmin, INFINITY, 0u, f2u(d.w), f2u(o.w), h, st,
+                                 nvis, ntri);
+      overflow |= st.overflow;
+      if (h.tri != 0xFFFFFFFFu) {
+        P.hit[slot] = make_float4(h.t, h.b1, h.b2, u2f(h.tri));
+        cls = S.mats[h.mat].cls;
+      } else {
+        P.hit[slot] = make_float4(INFINITY, 0.0f, 0.0f, u2f(0xFFFFFFFFu));
+        cls = kClsMiss;
+      }
+    }
+    // bin the path into its material class queue, one ballot per class present in the wave
+    uint64_t remaining = __ballot(active);
+    while (remaining) {
+      uint32_t leader = (uint32_t)__ffsll((unsigned long long)remaining) - 1u;
+      int c = __shfl(cls, (int)leader);
+      bool mine = active && cls == c;
+      uint32_t pos = wave_append(mine, &P.counts[2 + c]);
+      if (mine) P.q_cls[c][pos] = slot;
+      remaining &= ~__ballot(mine);
+    }
+  }
+  if (COUNT) {
+    atomicAdd(&P.stats[kStatNodes], (unsigned long long)nvis);
+    atomicAdd(&P.stats[kStatTris], (unsigned long long)ntri);
+  }
+  if (overflow) atomicAdd(&P.stats[kStatOverflow], 1ull);
+}
+
+// ------------------------------------------------------------------- shade
+template <int CLS, bool DEBUG>
+__global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b, int max_depth, int next,
+                                                  uint32_t sample, uint32_t k0, uint32_t k1, uint32_t img_w) {
+  const uint32_t count = P.counts[2 + CLS];
+  for (uint32_t base = blockIdx.x * kBlock; base < count; base += gridDim.x * kBlock) {
+    uint32_t i = base + threadIdx.x;
+    bool active = i < count;
+    bool cont = false, shadow = false;
+    uint32_t slot = 0;
+    float4 sh_o = make_float4(0, 0, 0, 0), sh_d = make_float4(0, 0, 0, 0), sh_c = make_float4(0, 0, 0, 0);
+    if (active) {
+      slot = P.q_cls[CLS][i];
+      float4 rd = P.ray_d[slot];
+      float4 be = P.beta[slot];
+      float4 Lr = P.L[slot];
+      uint32_t flags = P.flags[slot];
+      V3 beta = v3(be.x, be.y, be.z);
+      V3 L = v3(Lr.x, Lr.y, Lr.z);
+      float pdf_prev = be.w, eta_scale = Lr.w;
+      bool prev_delta = (flags & 1u) != 0u;
+      V3 d = v3(rd.x, rd.y, rd.z);
+      uint64_t sig = DEBUG ? P.sig[slot] : 0ull;
+      unsigned long long nonfinite = 0;
+      if (CLS == kClsMiss) {
+        if (S.env_w > 0) {
+          float st;
+          int texel = env_texel(S, d, st);
+          if (DEBUG) { sig = sig_word(sig, 2); sig = sig_word(sig, (uint32_t)texel); }
+          float4 e = S.env[texel];
+          float w = 1.0f;
+          if (!prev_delta) w = pow_heuristic(pdf_prev, S.p_env * env_pdf_texel(S, texel, st));
+          if (w > 0.0f) {
+            V3 c = v3(beta.x * w * e.x, beta.y * w * e.y, beta.z * w * e.z);
+            if (finite3(c)) L = L + c;
+            else nonfinite++;
+          }
+        } else if (DEBUG) {
+          sig = sig_word(sig, 2);
+          sig = sig_word(sig, 0xFFFFFFFFu);
+        }
+        if (DEBUG) { sig = sig_word(sig, 6); sig = sig_word(sig, 0); }
+        P.L[slot] = make_float4(L.x, L.y, L.z, eta_scale);
+        if (DEBUG) P.sig[slot] = sig;
+      } else {
+        float4 hv = P.hit[slot];
+        float4 ro = P.ray_o[slot];
+        const TriRec tr = S.tris[f2u(hv.w)];
+        uint32_t prim = f2u(tr.a.w), mid = f2u(tr.b.w);
+        const MatRec& m = S.mats[mid];
+        if (DEBUG) { sig = sig_word(sig, 1); sig = sig_word(sig, 0u); sig = sig_word(sig, prim); }
+        V3 p0 = v3(tr.a.x, tr.a.y, tr.a.z), p1 = v3(tr.b.x, tr.b.y, tr.b.z), p2 = v3(tr.c.x, tr.c.y, tr.c.z);
+        float b1 = hv.y, b2 = hv.z;
+        V3 p = p0 * (1.0f - b1 - b2) + p1 * b1 + p2 * b2;
+        V3 ng = normalize(cross(p1 - p0, p2 - p0));
+        V3 wo_w = d * -1.0f;
+        float cos_ng = dot(ng, wo_w);
+        (void)ro;
+        // emission (front face only), MIS-weighted against light sampling
+        if ((m.flags & kMatEmissive) && cos_ng > 0.0f) {
+          float w = 1.0f;
+          if (!prev_delta) {
+            int k = S.tri_light[prim];
+            float pl = 0.0f;
+            if (k >= 0 && S.n_lights > 0) {
+              const LightTri& Lt = S.lights[k];
+              pl = Lt.p1.w * hv.x * hv.x / (cos_ng * Lt.p0.w);
+            }
+            w = pow_heuristic(pdf_prev, pl);
+          }
+          if (w > 0.0f) {
+            V3 c = v3(beta.x * w * m.Le[0], beta.y * w * m.Le[1], beta.z * w * m.Le[2]);
+            if (finite3(c)) L = L + c;
+            else nonfinite++;
+          }
+        }
+        int lobe_ev = -1, rr_ev = 0, end_ev = 7;
+        bool pending = false;
+        uint32_t nee_id = 0xFFFFFFFFu, nee_out = 3u;
+        bool nee_done = false;
+        if (b == max_depth) {
+          end_ev = 1;
+        } else {
+          bool entering = cos_ng > 0.0f;
+          V3 n = entering ? ng : ng * -1.0f;
+          V3 t, bt;
+          make_frame(n, v3(S.axis[0], S.axis[1], S.axis[2]), t, bt);
+          V3 wo = v3(dot(wo_w, t), dot(wo_w, bt), dot(wo_w, n));
+          Bsdf B = bsdf_setup<CLS>(m, entering, wo.z);
+          if (wo.z <= 0.0f) B.absorbed = true;
+          Rng rng{(uint32_t)(P.y0 + slot / P.w) * img_w + (uint32_t)(P.x0 + slot % P.w), sample, k0, k1};
+          U4 r0 = rng.block((uint32_t)b, 0u), r1 = rng.block((uint32_t)b, 1u);
+          // next-event estimation
+          if (!B.absorbed && bsdf_has_nondelta<CLS>(m, B)) {
+            nee_done = true;
+            U4 r2 = rng.block((uint32_t)b, 2u);
+            LightSample ls = sample_light(S, p, u01(r1.w), u01(r2.x), u01(r2.y));
+            nee_id = ls.id;
+            if (ls.ok) {
+              V3 wil = v3(dot(ls.wl, t), dot(ls.wl, bt), dot(ls.wl, n));
+              float pb;
+              V3 f = bsdf_eval<CLS>(m, B, wo, wil, pb);
+              float w = pow_heuristic(ls.pdf, pb);
+              float k = fabsf(wil.z) * w / ls.pdf;
+              V3 c = v3(beta.x * f.x * ls.Le.x * k, beta.y * f.y * ls.Le.y * k, beta.z * f.z * ls.Le.z * k);
+              if (c.x != 0.0f || c.y != 0.0f || c.z != 0.0f) {
+                shadow = true;
+                pending = true;
+                float tmax = isinf(ls.dist) ? INFINITY : (1.0f - 1e-4f) * ls.dist;
+                sh_o = make_float4(p.x, p.y, p.z, tmax);
+                sh_d = make_float4(ls.wl.x, ls.wl.y, ls.wl.z, u2f(slot));
+                sh_c = make_float4(c.x, c.y, c.z, u2f(prim));
+              } else {
+                nee_out = 2u;
+              }
+            }
+          }
+          // BSDF sampling
+          BsdfSample bs = bsdf_sample<CLS>(m, B, wo, u01(r0.z), u01(r1.x), u01(r1.y), u01(r1.z));
+          lobe_ev = bs.lobe;
+          if (!bs.ok || (bs.weight.x == 0.0f && bs.weight.y == 0.0f && bs.weight.z == 0.0f)) {
+            end_ev = 2;
+          } else {
+            beta = v3(beta.x * bs.weight.x, beta.y * bs.weight.y, beta.z * bs.weight.z);
+            prev_delta = bs.delta;
+            pdf_prev = bs.pdf;
+            if (bs.refract) eta_scale *= B.eta * B.eta;
+            bool killed = false;
+            if (b >= 1) {
+              float q = fmaxf(fmaxf(beta.x, beta.y), beta.z) * eta_scale;
+              if (q < 1.0f) {
+                killed = u01(r0.w) >= q;
+                rr_ev = killed ? 2 : 1;
+                if (!killed) beta = beta * (1.0f / q);
+              }
+            }
+            if (killed) {
+              end_ev = 3;
+            } else {
+              V3 dn = normalize(t * bs.wi.x + bt * bs.wi.y + n * bs.wi.z);
+              P.ray_o[slot] = make_float4(p.x, p.y, p.z, u2f(prim));
+              P.ray_d[slot] = make_float4(dn.x, dn.y, dn.z, u2f(0u));
+              P.beta[slot] = make_float4(beta.x, beta.y, beta.z, pdf_prev);
+              P.flags[slot] = prev_delta ? 1u : 0u;
+              cont = true;
+            }
+          }
+        }
+        P.L[slot] = make_float4(L.x, L.y, L.z, eta_scale);
+        if (DEBUG) {
+          uint32_t tail = tail_pack(lobe_ev, rr_ev, end_ev);
+          if (pending) {
+            P.dbg_nee[slot] = nee_id;
+            P.dbg_tail[slot] = tail;
+          } else {
+            if (nee_done) {
+              sig = sig_word(sig, 5);
+              sig = sig_word(sig, nee_id);
+              sig = sig_word(sig, nee_out);
+            }
+            sig = sig_tail(sig, tail);
+          }
+          P.sig[slot] = sig;
+        }
+      }
+      if (nonfinite) atomicAdd(&P.stats[kStatNonFinite], nonfinite);
+    }
+    uint32_t qpos = wave_append(cont, &P.counts[next]);
+    if (cont) P.q_ray[next][qpos] = slot;
+    uint32_t spos = wave_append(shadow, &P.counts[kCountShadow]);
+    if (shadow) {
+      P.sh_o[spos] = sh_o;
+      P.sh_d[spos] = sh_d;
+      P.sh_c[spos] = sh_c;
+    }
+  }
+}
+
+// ----------------------------------------------------------------- connect
+template <bool DEBUG, bool COUNT>
+__global__ __launch_bounds__(kBlock) void k_connect(SceneDev S, PathsDev P) {
+  __shared__ uint32_t s_ref[kLdsStack * kBlock];
+  __shared__ float s_key[kLdsStack * kBlock];
+  const uint32_t count = P.counts[kCountShadow];
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&P.stats[kStatShadow], (unsigned long long)count);
+  const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
+  uint32_t nvis = 0, ntri = 0;
+  bool overflow = false;
+  unsigned long long nonfinite = 0;
+  for (uint32_t i = gtid; i < count; i += gridDim.x * kBlock) {
+    float4 o = P.sh_o[i], d = P.sh_d[i], c = P.sh_c[i];
+    uint32_t slot = f2u(d.w);
+    RayPre r = ray_prepare(o.x, o.y, o.z, d.x, d.y, d.z);
+    Hit h;
+    hit_clear(h);
+    DevStack st{s_ref + threadIdx.x, s_key + threadIdx.x, S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
+    bool occ = traverse_bvh<true, COUNT>(S.nodes, S.tris, S.root, r, S.tmin, o.w, 0u, 0u, f2u(c.w), h, st, nvis,
+                                         ntri);
+    overflow |= st.overflow;
+    if (!occ) {
+      V3 cc = v3(c.x, c.y, c.z);
+      if (finite3(cc)) {
+        float4 L = P.L[slot];
+        P.L[slot] = make_float4(L.x + cc.x, L.y + cc.y, L.z + cc.z, L.w);
+      } else {
+        nonfinite++;
+      }
+    }
+    if (DEBUG) {
+      uint64_t sig = P.sig[slot];
+      sig = sig_word(sig, 5);
+      sig = sig_word(sig, P.dbg_nee[slot]);
+      sig = sig_word(sig, occ ? 1u : 0u);
+      sig = sig_tail(sig, P.dbg_tail[slot]);
+      P.sig[slot] = sig;
+    }
+  }
+  if (COUNT) {
+    atomicAdd(&P.stats[kStatShadowNodes], (unsigned long long)nvis);
+    atomicAdd(&P.stats[kStatShadowTris], (unsigned long long)ntri);
+  }
+  if (nonfinite) atomicAdd(&P.stats[kStatNonFinite], nonfinite);
+  if (overflow) atomicAdd(&P.stats[kStatOverflow], 1ull);
+}
+
+// -------------------------------------------------------------- accumulate
+// FP64 per-pixel running sums: one writer per pixel per pass, no atomics.
+__global__ __launch_bounds__(kBlock) void k_accumulate(PathsDev P, double* sum, int W, float* per_sample,
+                                                       uint64_t* sig_out, int spp_total, int sample_index) {
+  for (int slot = blockIdx.x * kBlock + threadIdx.x; slot < P.n; slot += gridDim.x * kBlock) {
+    float4 L = P.L[slot];
+    if (sum) {
+      int px = P.x0 + slot % P.w, py = P.y0 + slot / P.w;
+      double* s = sum + 3 * ((size_t)py * W + px);
+      s[0] += (double)L.x;
+      s[1] += (double)L.y;
+      s[2] += (double)L.z;
+    }
+    if (per_sample) {
+      size_t o = (size_t)slot * spp_total + sample_index;
+      per_sample[3 * o] = L.x;
+      per_sample[3 * o + 1] = L.y;
+      per_sample[3 * o + 2] = L.z;
+      sig_out[o] = P.sig[slot];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_resolve(const double* sum, float* out, int64_t n, double inv) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    out[i] = (float)(sum[i] * inv);
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_f64(double* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) p[i] = 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_u64(unsigned long long* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) p[i] = 0ull;
+}
+
+// ------------------------------------------------------- ray query kernels
+template <bool BRUTE>
+__global__ __launch_bounds__(kBlock) void k_trace_rays(SceneDev S, const float* rays, int64_t n, uint32_t* hits) {
+  __shared__ uint32_t s_ref[kLdsStack * kBlock];
+  __shared__ float s_key[kLdsStack * kBlock];
+  const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
+  for (int64_t i = gtid; i < n; i += (int64_t)gridDim.x * kBlock) {
+    const float* R = rays + 8 * i;
+    RayPre r = ray_prepare(R[0], R[1], R[2], R[4], R[5], R[6]);
+    Hit h;
+    hit_clear(h);
+    uint32_t nv = 0, nt = 0;
+    if (BRUTE) {
+      brute_force<false>(S.tris, S.n_tris, r, R[3], R[7], 0u, h, nt);
+    } else {
+      DevStack st{s_ref + threadIdx.x, s_key + threadIdx.x, S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
+      traverse_bvh<false, false>(S.nodes, S.tris, S.root, r, R[3], R[7], 0u, 0xFFFFFFFFu, 0xFFFFFFFFu, h, st, nv, nt);
+    }
+    uint32_t* H = hits + 6 * i;
+    bool hit = h.tri != 0xFFFFFFFFu;
+    H[0] = f2u(h.t);
+    H[1] = hit ? h.inst : 0xFFFFFFFFu;
+    H[2] = hit ? h.prim : 0xFFFFFFFFu;
+    H[3] = hit ? f2u(h.b1) : 0u;
+    H[4] = hit ? f2u(h.b2) : 0u;
+    H[5] = hit ? 1u : 0u;
+  }
+}
+
+// --------------------------------------------------------------- launchers
+int trace_grid_blocks() { return 2048; }
+
+template <bool DEBUG>
+static hipError_t shade_all(const SceneDev& S, const PathsDev& P, const PassArgs& A, int b, int next, uint32_t W,
+                            hipStream_t st) {
+  dim3 g(A.grid), blk(kBlock);
+#define PT_SHADE(C)                                                                                     \
+  if (A.class_mask & (1u << C))                                                                         \
+    hipLaunchKernelGGL((k_shade<C, DEBUG>), g, blk, 0, st, S, P, b, A.max_depth, next, A.sample, A.k0, \
+                       A.k1, W);
+  PT_SHADE(kClsMiss)
+  PT_SHADE(kClsAbsorb)
+  PT_SHADE(kClsDiffuse)
+  PT_SHADE(kClsMetal)
+  PT_SHADE(kClsPlastic)
+  PT_SHADE(kClsGlass)
+  PT_SHADE(kClsGeneral)
+#undef PT_SHADE
+  return hipGetLastError();
+}
+
+hipError_t launch_pass(const SceneDev& S, const PathsDev& P, const CamDev& C, const PassArgs& A, hipStream_t st) {
+  dim3 blk(kBlock);
+  if (A.debug) hipLaunchKernelGGL((k_generate<true>), dim3(A.grid), blk, 0, st, P, C, A.sample, A.k0, A.k1);
+  else hipLaunchKernelGGL((k_generate<false>), dim3(A.grid), blk, 0, st, P, C, A.sample, A.k0, A.k1);
+  for (int b = 0; b <= A.max_depth; ++b) {
+    int cur = b & 1, next = cur ^ 1;
+    hipLaunchKernelGGL(k_reset_counts, dim3(1), dim3(64), 0, st, P.counts, next);
+    if (A.ext_events) hipEventRecord(A.ext_events[2 * b], st);
+    if (A.count) hipLaunchKernelGGL((k_extend<true>), dim3(A.grid_trace), blk, 0, st, S, P, cur);
+    else hipLaunchKernelGGL((k_extend<false>), dim3(A.grid_trace), blk, 0, st, S, P, cur);
+    if (A.ext_events) hipEventRecord(A.ext_events[2 * b + 1], st);
+    hipError_t e = A.debug ? shade_all<true>(S, P, A, b, next, (uint32_t)C.W, st)
+                           : shade_all<false>(S, P, A, b, next, (uint32_t)C.W, st);
+    if (e != hipSuccess) return e;
+    if (b < A.max_depth) {
+      if (A.debug) {
+        if (A.count) hipLaunchKernelGGL((k_connect<true, true>), dim3(A.grid_trace), blk, 0, st, S, P);
+        else hipLaunchKernelGGL((k_connect<true, false>), dim3(A.grid_trace), blk, 0, st, S, P);
+      } else {
+        if (A.count) hipLaunchKernelGGL((k_connect<false, true>), dim3(A.grid_trace), blk, 0, st, S, P);
+        else hipLaunchKernelGGL((k_connect<false, false>), dim3(A.grid_trace), blk, 0, st, S, P);
+      }
+    }
+  }
+  return hipGetLastError();
+}
+
+static int blocks_for(int64_t n) {
+  int64_t b = (n + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > 4096) b = 4096;
+  return (int)b;
+}
+
+hipError_t launch_accumulate(const PathsDev& P, double* sum, int W, float* per_sample, uint64_t* sig_out,
+                             int spp_total, int sample_index, hipStream_t st) {
+  hipLaunchKernelGGL(k_accumulate, dim3(blocks_for(P.n)), dim3(kBlock), 0, st, P, sum, W, per_sample, sig_out,
+                     spp_total, sample_index);
+  return hipGetLastError();
+}
+
+hipError_t launch_resolve(const double* sum, float* out, int64_t n, double inv, hipStream_t st) {
+  hipLaunchKernelGGL(k_resolve, dim3(blocks_for(n)), dim3(kBlock), 0, st, sum, out, n, inv);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_f64, dim3(blocks_for(n)), dim3(kBlock), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(blocks_for(n)), dim3(kBlock), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_rays(const SceneDev& S, const float* rays, int64_t n, uint32_t* hits, bool brute, int grid,
+                             hipStream_t st) {
+  if (brute) hipLaunchKernelGGL((k_trace_rays<true>), dim3(grid), dim3(kBlock), 0, st, S, rays, n, hits);
+  else hipLaunchKernelGGL((k_trace_rays<false>), dim3(grid), dim3(kBlock), 0, st, S, rays, n, hits);
+  return hipGetLastError();
+}
+
+}  // namespace pt

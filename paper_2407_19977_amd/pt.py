@@ -1,0 +1,251 @@
+"""Thin ctypes binding of libpt.so (include/pt.h), same names as the C ABI.
+
+Argument marshalling only: every step of the path runs in the HIP library.
+Device buffers are torch tensors on the scene's GPU; their data pointers
+cross the boundary.  If libpt.so is missing this module raises at import:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpt.so")
+
+PT_OK = 0
+STATUS = {0: "PT_OK", -1: "PT_ERR_INVALID_ARG", -2: "PT_ERR_OUT_OF_MEMORY", -3: "PT_ERR_DEVICE",
+          -4: "PT_ERR_UNSUPPORTED", -5: "PT_ERR_STATE"}
+
+
+class PtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class pt_mesh(C.Structure):
+    _fields_ = [("vertices", C.c_void_p), ("n_vertices", C.c_int64), ("indices", C.c_void_p),
+                ("n_triangles", C.c_int64), ("material_ids", C.c_void_p)]
+
+
+class pt_instance(C.Structure):
+    _fields_ = [("object_to_world", C.c_float * 12), ("mesh", C.c_int32), ("material_override", C.c_int32)]
+
+
+class pt_camera(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("look_at", C.c_float * 3), ("up", C.c_float * 3),
+                ("vfov_deg", C.c_float), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class pt_stats(C.Structure):
+    _fields_ = [("extension_rays", C.c_int64), ("shadow_rays", C.c_int64), ("nonfinite_dropped", C.c_int64),
+                ("samples", C.c_int64), ("ms_extend", C.c_double), ("launches_extend", C.c_int64),
+                ("ms_total", C.c_double), ("node_visits", C.c_int64), ("tri_tests", C.c_int64),
+                ("shadow_node_visits", C.c_int64), ("shadow_tri_tests", C.c_int64)]
+
+
+class pt_bvh_info(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_tris", C.c_int64), ("depth", C.c_int32),
+                ("max_leaf_tris", C.c_int32), ("sah_cost", C.c_double), ("build_ms", C.c_double)]
+
+
+# every symbol declared in include/pt.h, with its ctypes signature
+_SIGS = {
+    "pt_scene_create": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "pt_scene_destroy": (None, [C.c_void_p]),
+    "pt_build_bvh": (C.c_int, [C.c_void_p, C.POINTER(pt_mesh), C.c_int32, C.POINTER(pt_instance), C.c_int32]),
+    "pt_upload_materials": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "pt_set_environment": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]),
+    "pt_render": (C.c_int, [C.c_void_p, C.POINTER(pt_camera), C.c_int32, C.c_int32, C.c_uint64, C.c_void_p]),
+    "pt_accumulate": (C.c_int, [C.c_void_p, C.POINTER(pt_camera), C.c_int32, C.c_int32, C.c_int32, C.c_uint64]),
+    "pt_reset_accumulation": (C.c_int, [C.c_void_p]),
+    "pt_resolve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pt_render_debug": (C.c_int, [C.c_void_p, C.POINTER(pt_camera), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                  C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p]),
+    "pt_trace_closest": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32]),
+    "pt_get_stats": (C.c_int, [C.c_void_p, C.POINTER(pt_stats)]),
+    "pt_reset_stats": (C.c_int, [C.c_void_p]),
+    "pt_set_profiling": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "pt_bvh_host_build": (C.c_int, [C.POINTER(pt_mesh), C.POINTER(C.c_void_p)]),
+    "pt_bvh_host_info": (C.c_int, [C.c_void_p, C.POINTER(pt_bvh_info)]),
+    "pt_bvh_host_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pt_bvh_host_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "pt_bvh_host_destroy": (None, [C.c_void_p]),
+    "pt_last_error": (C.c_char_p, []),
+    "pt_version": (C.c_char_p, []),
+}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+_lib = C.CDLL(LIB_PATH)
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def lib():
+    return _lib
+
+
+def _check(status: int):
+    if status != PT_OK:
+        raise PtError(status, _lib.pt_last_error().decode())
+
+
+def last_error() -> str:
+    return _lib.pt_last_error().decode()
+
+
+def version() -> str:
+    return _lib.pt_version().decode()
+
+
+def camera_struct(cam) -> pt_camera:
+    c = pt_camera()
+    c.eye[:] = [float(x) for x in cam.eye]
+    c.look_at[:] = [float(x) for x in cam.look_at]
+    c.up[:] = [float(x) for x in cam.up]
+    c.vfov_deg = float(cam.vfov_deg)
+    c.width = int(cam.width)
+    c.height = int(cam.height)
+    return c
+
+
+def _mesh_structs(meshes, keep):
+    arr = (pt_mesh * len(meshes))()
+    for i, m in enumerate(meshes):
+        v = np.ascontiguousarray(m.vertices, dtype=np.float32)
+        idx = np.ascontiguousarray(m.indices, dtype=np.int32)
+        mid = None if m.material_ids is None else np.ascontiguousarray(m.material_ids, dtype=np.int32)
+        keep += [v, idx, mid]
+        arr[i].vertices = v.ctypes.data
+        arr[i].n_vertices = v.shape[0]
+        arr[i].indices = idx.ctypes.data
+        arr[i].n_triangles = idx.shape[0]
+        arr[i].material_ids = None if mid is None else mid.ctypes.data
+    return arr
+
+
+class PtScene:
+    """A pt_scene on one GPU.  Device buffers are torch tensors."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch  # noqa: F401  (device memory and streams)
+        self.device = device
+        h = C.c_void_p()
+        s = None if stream is None else C.c_void_p(stream)
+        _check(_lib.pt_scene_create(device, s, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.pt_scene_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    # -- set-up
+    def build_bvh(self, meshes, instances=()):
+        keep = []
+        arr = _mesh_structs(meshes, keep)
+        ni = len(instances)
+        ia = (pt_instance * max(1, ni))()
+        for i, ins in enumerate(instances):
+            ia[i].object_to_world[:] = [float(x) for x in np.asarray(ins.object_to_world, np.float32).reshape(12)]
+            ia[i].mesh = int(ins.mesh)
+            ia[i].material_override = int(ins.material_override)
+        _check(_lib.pt_build_bvh(self.h, arr, len(meshes), ia, ni))
+
+    def upload_materials(self, materials: np.ndarray):
+        m = np.ascontiguousarray(materials, dtype=np.float32).reshape(-1, 27)
+        _check(_lib.pt_upload_materials(self.h, m.ctypes.data, m.shape[0]))
+
+    def set_environment(self, env: Optional[np.ndarray]):
+        if env is None:
+            _check(_lib.pt_set_environment(self.h, None, 0, 0))
+            return
+        e = np.ascontiguousarray(env, dtype=np.float32)
+        _check(_lib.pt_set_environment(self.h, e.ctypes.data, e.shape[1], e.shape[0]))
+
+    # -- sampling
+    def render(self, camera, spp, max_depth, seed, out):
+        _check(_lib.pt_render(self.h, C.byref(camera_struct(camera)), spp, max_depth, seed, out.data_ptr()))
+        return out
+
+    def accumulate(self, camera, first_sample, n_samples, max_depth, seed):
+        _check(_lib.pt_accumulate(self.h, C.byref(camera_struct(camera)), first_sample, n_samples, max_depth, seed))
+
+    def reset_accumulation(self):
+        _check(_lib.pt_reset_accumulation(self.h))
+
+    def resolve(self, out, out_sum=None):
+        _check(_lib.pt_resolve(self.h, out.data_ptr(), None if out_sum is None else out_sum.data_ptr()))
+        return out
+
+    def render_debug(self, camera, x0, y0, w, h, first_sample, spp, max_depth, seed, per_sample, sigs):
+        _check(_lib.pt_render_debug(self.h, C.byref(camera_struct(camera)), x0, y0, w, h, first_sample, spp,
+                                    max_depth, seed, per_sample.data_ptr(), sigs.data_ptr()))
+
+    def trace_closest(self, rays, hits, brute_force=False):
+        _check(_lib.pt_trace_closest(self.h, rays.data_ptr(), rays.shape[0], hits.data_ptr(),
+                                     1 if brute_force else 0))
+        return hits
+
+    def stats(self) -> dict:
+        st = pt_stats()
+        _check(_lib.pt_get_stats(self.h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in pt_stats._fields_}
+
+    def reset_stats(self):
+        _check(_lib.pt_reset_stats(self.h))
+
+    def set_profiling(self, timing: bool, counting: bool = False):
+        _check(_lib.pt_set_profiling(self.h, 1 if timing else 0, 1 if counting else 0))
+
+
+def scene_from(scene, device: int = 0, stream=None) -> PtScene:
+    """Upload a scenes.Scene (geometry, materials, environment) to a new PtScene."""
+    s = PtScene(device, stream)
+    s.build_bvh(scene.meshes, scene.instances)
+    s.upload_materials(scene.materials)
+    s.set_environment(scene.env)
+    return s
+
+
+# ------------------------------------------------------------ host BVH --
+class HostBvh:
+    """pt_bvh_host_*: the BVH4 of one mesh built and walked on the CPU."""
+
+    def __init__(self, mesh):
+        keep = []
+        arr = _mesh_structs([mesh], keep)
+        h = C.c_void_p()
+        _check(_lib.pt_bvh_host_build(arr, C.byref(h)))
+        self.h = h
+        info = pt_bvh_info()
+        _check(_lib.pt_bvh_host_info(self.h, C.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in pt_bvh_info._fields_}
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.pt_bvh_host_destroy(self.h)
+            self.h = None
+
+    def arrays(self):
+        """(nodes uint8 [n,128], tris uint8 [n,48])"""
+        nodes = np.zeros((self.info["n_nodes"], 128), dtype=np.uint8)
+        tris = np.zeros((self.info["n_tris"], 48), dtype=np.uint8)
+        _check(_lib.pt_bvh_host_copy(self.h, nodes.ctypes.data, tris.ctypes.data))
+        return nodes, tris
+
+    def trace(self, rays: np.ndarray) -> np.ndarray:
+        rays = np.ascontiguousarray(rays, dtype=np.float32)
+        hits = np.zeros((rays.shape[0], 6), dtype=np.uint32)
+        _check(_lib.pt_bvh_host_trace(self.h, rays.ctypes.data, rays.shape[0], hits.ctypes.data))
+        return hits

@@ -13,8 +13,11 @@ with HIP events on the library's stream, and the FP64 oracle timed on the
 host's cores on a bounded sample of the same workload.
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -26,7 +29,31 @@ HBM_PEAK_GBS = 8000.0
 NODE_BYTES, TRI_BYTES, RAY_BYTES, HIT_BYTES = 128, 48, 32, 16
 
 
-def cpu_baseline(sc, spp_cpu=8, crop=(704, 396, 512, 288)):
+def kernel_source_hash() -> str:
+    """sha256 over the HIP kernel sources (file name + bytes, sorted)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2407_19977_amd", "csrc")
+    for p in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(os.path.basename(p).encode())
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_extend launch from the committed counter summary, or
+    None when the kernel sources changed since those counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_extend_spheres_1080p.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    t = re.search(r"^traffic_bytes_per_launch: (\d+)", txt, re.M)
+    h = re.search(r"^kernel_source_sha256: ([0-9a-f]+)", txt, re.M)
+    if not t or not h or h.group(1) != kernel_source_hash():
+        return None
+    return int(t.group(1))
+
+
+def cpu_baseline(sc, spp_cpu=12, crop=(0, 0, 1920, 1080)):
     """The oracle as it stands, on a centre crop of the same scene."""
     from oracle import oracle as O
     try:
@@ -41,7 +68,7 @@ def cpu_baseline(sc, spp_cpu=8, crop=(704, 396, 512, 288)):
     st = r["stats"]
     rays = st["extension_rays"] + st["shadow_rays"]
     return {"value": rays / dt / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
-            "sample": f"{crop[2]}x{crop[3]} centre crop of the 1920x1080 frame at {spp_cpu} spp, depth "
+            "sample": f"{crop[2]}x{crop[3]} pixels from ({crop[0]},{crop[1]}) of the 1920x1080 frame at {spp_cpu} spp, depth "
                       f"{sc.max_depth}, full 1.31M-triangle scene; {rays} rays in {dt:.2f} s "
                       f"({crop[2] * crop[3] * spp_cpu / dt:.3g} samples/s)"}
 
@@ -54,6 +81,8 @@ def main():
     ap.add_argument("--spp", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-count", action="store_true", help="skip the node-visit counting pass")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -70,6 +99,13 @@ def main():
     torch.cuda.set_device(0)
     s = pt.scene_from(sc, device=0)
     out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda:0")
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         s.render(cam, sc.spp, sc.max_depth, sc.seed, out)
@@ -105,7 +141,7 @@ def main():
         avg_ms = st["ms_extend"] / st["launches_extend"]
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                     "kernel": "k_extend (BVH4 closest hit)",
                     "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": round(avg_ms, 4),
                     "node_visits_per_ray": round(counts["node_visits"] / max(1, counts["extension_rays"]), 2),

@@ -28,6 +28,7 @@
  *   end      6, reason (0 miss, 1 max depth, 2 absorbed, 3 roulette)
  */
 #include <pthread.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -96,6 +97,7 @@ int oracle_trace_path(const oracle_scene* s, const oracle_camera* cam, int32_t p
                       double rgb[3], uint64_t* sig_out, oracle_stats* st) {
   int est = opt ? opt->estimator : ORACLE_MIS;
   int rr_on = opt ? opt->russian_roulette : 1;
+  int verbose = opt ? opt->verbose : 0;
   uint32_t pix = (uint32_t)(py * cam->width + px);
   uint32_t smp = (uint32_t)sample;
   uint64_t sig = FNV_OFFSET;
@@ -158,6 +160,9 @@ int oracle_trace_path(const oracle_scene* s, const oracle_camera* cam, int32_t p
     }
     v3 wo_w = vmul(d, -1.0);
     double cos_ng = vdot(ng, wo_w);
+    if (verbose)
+      fprintf(stderr, "b=%d hit inst=%d prim=%d t=%.9g p=(%.9g %.9g %.9g) ng=(%.6g %.6g %.6g) cos=%.6g beta=(%.6g %.6g %.6g)\n",
+              b, h.inst, h.prim, h.t, p.x, p.y, p.z, ng.x, ng.y, ng.z, cos_ng, beta[0], beta[1], beta[2]);
     int32_t mid = I->mat_override >= 0 ? I->mat_override : M->mat[h.prim];
     const omat* mat = &s->mats[mid];
     /* emission, front face only */
@@ -203,6 +208,9 @@ int oracle_trace_path(const oracle_scene* s, const oracle_camera* cam, int32_t p
         obsdf_eval(&B, wo, wil, f, &pb);
         double w = est == ORACLE_MIS ? pow_heur(pl, pb) : 1.0;
         double k = fabs(wil.z) * w / pl;
+        if (verbose)
+          fprintf(stderr, "  nee light=%lld dist=%.9g pdfL=%.9g pdfB=%.9g w=%.6g cos_i=%.6g f=(%.6g %.6g %.6g)\n",
+                  (long long)lid, dist, pl, pb, w, wil.z, f[0], f[1], f[2]);
         double c[3] = {beta[0] * f[0] * Le[0] * k, beta[1] * f[1] * Le[1] * k, beta[2] * f[2] * Le[2] * k};
         if (c[0] != 0.0 || c[1] != 0.0 || c[2] != 0.0) {
           double tmax = isinf(dist) ? INFINITY : (1.0 - 1e-4) * dist;

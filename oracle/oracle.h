@@ -56,6 +56,7 @@ typedef struct {
   int32_t estimator;     /* ORACLE_MIS / ORACLE_BSDF_ONLY / ORACLE_NEE_ONLY */
   int32_t russian_roulette; /* 1 = on (default), 0 = off */
   int32_t n_threads;     /* <= 0: one */
+  int32_t verbose;       /* 1: print every vertex of oracle_trace_path to stderr (debugging) */
 } oracle_options;
 
 typedef struct {

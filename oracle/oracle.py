@@ -48,7 +48,8 @@ class OCamera(C.Structure):
 
 
 class OOptions(C.Structure):
-    _fields_ = [("estimator", C.c_int32), ("russian_roulette", C.c_int32), ("n_threads", C.c_int32)]
+    _fields_ = [("estimator", C.c_int32), ("russian_roulette", C.c_int32), ("n_threads", C.c_int32),
+                ("verbose", C.c_int32)]
 
 
 class OStats(C.Structure):
@@ -285,9 +286,9 @@ class OracleScene:
         assert rc == 0
         return hits
 
-    def trace_path(self, px, py, sample, max_depth, seed=0, estimator=MIS, rr=True, camera=None):
+    def trace_path(self, px, py, sample, max_depth, seed=0, estimator=MIS, rr=True, camera=None, verbose=False):
         cam = camera_struct(camera or self.camera)
-        opt = OOptions(estimator, 1 if rr else 0, 1)
+        opt = OOptions(estimator, 1 if rr else 0, 1, 1 if verbose else 0)
         rgb = (C.c_double * 3)()
         sig = C.c_uint64()
         st = OStats()
@@ -304,7 +305,7 @@ class OracleScene:
         cam = camera_struct(cam_py)
         x0, y0, w, h = crop if crop is not None else (0, 0, cam_py.width, cam_py.height)
         nt = n_threads or min(16, os.cpu_count() or 1)
-        opt = OOptions(estimator, 1 if rr else 0, nt)
+        opt = OOptions(estimator, 1 if rr else 0, nt, 0)
         s = np.zeros((h, w, 3), dtype=np.float64)
         ps = np.zeros((h, w, spp, 3), dtype=np.float64) if per_sample else None
         sg = np.zeros((h, w, spp), dtype=np.uint64) if per_sample else None

@@ -186,6 +186,11 @@ typedef struct pt_bvh_info {
 } pt_bvh_info;
 /* Build the BVH4 of one mesh on the host (the same builder pt_build_bvh uses). */
 pt_status pt_bvh_host_build(const pt_mesh* mesh, pt_bvh_host** out);
+/* Build the two-level hierarchy of an instanced scene on the host (the same
+ * code pt_build_bvh runs for n_instances > 0); nodes / triangles then refer
+ * to the concatenated per-mesh BVHs. */
+pt_status pt_bvh_host_build_instanced(const pt_mesh* meshes, int32_t n_meshes, const pt_instance* instances,
+                                      int32_t n_instances, pt_bvh_host** out);
 pt_status pt_bvh_host_info(const pt_bvh_host* bvh, pt_bvh_info* info);
 /* Copy nodes (n_nodes * 128 bytes) and triangles (n_tris * 48 bytes) to host memory. */
 pt_status pt_bvh_host_copy(const pt_bvh_host* bvh, void* nodes, void* tris);

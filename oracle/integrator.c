@@ -8,7 +8,8 @@
  *   closest hit through the BVH (Sec. 5.1.1);
  *   emission with MIS weight; next-event estimation with the power
  *   heuristic (Veach 1997); BSDF sampling (Sec. 5.1.3: importance sampling);
- *   Russian roulette from the second scattering event on (Sec. 5.1.3);
+ *   Russian roulette from the second scattering event on, continuing with
+ *   probability q = max_c(beta_c) * eta_scale when q < 0.995 (Sec. 5.1.3);
  *   the pixel value is the mean of its samples (Sec. 5.1.3).
  *
  * Per bounce b the uniforms are dimensions of (pixel, sample, b):
@@ -24,7 +25,7 @@
  *            (0 unoccluded, 1 occluded, 2 not traced because the
  *             contribution is zero, 3 no light sample)
  *   lobe     3, lobe code
- *   rr       4, 0 survived / 1 terminated   (only when q < 1)
+ *   rr       4, 0 survived / 1 terminated   (only when q < 0.995)
  *   end      6, reason (0 miss, 1 max depth, 2 absorbed, 3 roulette)
  */
 #include <pthread.h>
@@ -252,7 +253,7 @@ int oracle_trace_path(const oracle_scene* s, const oracle_camera* cam, int32_t p
       if (beta[1] > q) q = beta[1];
       if (beta[2] > q) q = beta[2];
       q *= eta_scale;
-      if (q < 1.0) {
+      if (q < 0.995) { /* roulette only below 0.995: q within rounding of 1 never decides an event */
         double ur = ouniform(seed, pix, smp, (uint32_t)b, 3);
         int killed = ur >= q;
         sig_word(&sig, 4);

@@ -92,8 +92,14 @@ struct pt_scene {
   int bvh_depth = 0;
   float tmin = 0.0f;
   int32_t max_mat_id = -1;
-  std::vector<float> host_tri_verts;  // [n][9] world space, prim order
-  std::vector<int32_t> host_tri_mat;  // [n], prim order
+  std::vector<float> host_tri_verts;  // [n][9] world space, prim order (single level)
+  std::vector<int32_t> host_tri_mat;  // [n], prim order (single level)
+  // two-level hierarchy
+  bool two_level = false;
+  DevBuf insts, tlas, tlas_items, light_map, mesh_tri_first, mesh_tri_count;
+  std::vector<InstRec> host_insts;
+  std::vector<std::vector<float>> host_mesh_verts;   // per mesh [n][9], object space, prim order
+  std::vector<std::vector<int32_t>> host_mesh_mat;   // per mesh [n]
   // materials
   bool has_mats = false;
   std::vector<pt_openpbr_material> host_mats;
@@ -109,8 +115,8 @@ struct pt_scene {
   float p_env = 0.0f;
   // path state
   int64_t capacity = 0;
-  DevBuf ray_o, ray_d, hit, beta, L, flags, q_ray[2], q_cls[kNumClasses], sh_o, sh_d, sh_c, counts, stats, sig,
-      dbg_nee, dbg_tail, spill;
+  DevBuf ray_o, ray_d, hit, hit_inst, beta, L, flags, q_ray[2], q_cls[kNumClasses], sh_o, sh_d, sh_c, sh_inst,
+      counts, stats, sig, dbg_nee, dbg_tail, spill;
   // accumulation
   DevBuf sum;
   int acc_w = 0, acc_h = 0;
@@ -135,43 +141,86 @@ pt_status set_device(pt_scene* s) {
   return PT_OK;
 }
 
+bool mat_emits(const pt_openpbr_material& m) {
+  return m.emission_luminance > 0.0f && lumd(m.emission_color[0], m.emission_color[1], m.emission_color[2]) > 0.0;
+}
+
+struct LightTmp {
+  LightTri t;
+  double w;
+};
+
+// v: world-space vertices (double) of an emissive triangle
+void push_light(std::vector<LightTmp>& list, const double* v, const pt_openpbr_material& m) {
+  double Le[3] = {(double)m.emission_luminance * m.emission_color[0],
+                  (double)m.emission_luminance * m.emission_color[1],
+                  (double)m.emission_luminance * m.emission_color[2]};
+  double e1[3], e2[3];
+  for (int k = 0; k < 3; ++k) {
+    e1[k] = v[3 + k] - v[k];
+    e2[k] = v[6 + k] - v[k];
+  }
+  double c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+  double len = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+  LightTmp t;
+  std::memset(&t, 0, sizeof(t));
+  double area = 0.5 * len;
+  t.t.p0 = make_float4((float)v[0], (float)v[1], (float)v[2], (float)area);
+  t.t.p1 = make_float4((float)v[3], (float)v[4], (float)v[5], 0.0f);
+  t.t.p2 = make_float4((float)v[6], (float)v[7], (float)v[8], 0.0f);
+  t.t.ng = len > 0 ? make_float4((float)(c[0] / len), (float)(c[1] / len), (float)(c[2] / len), 0.0f)
+                   : make_float4(0, 0, 0, 0);
+  t.t.Le = make_float4((float)Le[0], (float)Le[1], (float)Le[2], 0.0f);
+  t.w = area * lumd(Le[0], Le[1], Le[2]);
+  list.push_back(t);
+}
+
 pt_status ensure_lights(pt_scene* s) {
   if (!s->lights_dirty) return PT_OK;
-  const int64_t n = s->n_tris;
-  std::vector<int32_t> tri_light((size_t)std::max<int64_t>(n, 1), -1);
-  struct Tmp {
-    LightTri t;
-    double w;
-  };
-  std::vector<Tmp> list;
-  for (int64_t i = 0; i < n; ++i) {
-    int32_t mid = s->host_tri_mat[(size_t)i];
-    const pt_openpbr_material& m = s->host_mats[(size_t)mid];
-    double Le[3] = {(double)m.emission_luminance * m.emission_color[0],
-                    (double)m.emission_luminance * m.emission_color[1],
-                    (double)m.emission_luminance * m.emission_color[2]};
-    if (!(m.emission_luminance > 0.0f) || !(lumd(m.emission_color[0], m.emission_color[1], m.emission_color[2]) > 0.0))
-      continue;
-    const float* v = &s->host_tri_verts[9 * (size_t)i];
-    double e1[3], e2[3];
-    for (int k = 0; k < 3; ++k) {
-      e1[k] = (double)v[3 + k] - v[k];
-      e2[k] = (double)v[6 + k] - v[k];
+  std::vector<LightTmp> list;
+  std::vector<int32_t> tri_light(1, -1), lmap(1, -1);
+  if (!s->two_level) {
+    const int64_t n = s->n_tris;
+    tri_light.assign((size_t)std::max<int64_t>(n, 1), -1);
+    for (int64_t i = 0; i < n; ++i) {
+      const pt_openpbr_material& m = s->host_mats[(size_t)s->host_tri_mat[(size_t)i]];
+      if (!mat_emits(m)) continue;
+      const float* v = &s->host_tri_verts[9 * (size_t)i];
+      double vd[9];
+      for (int k = 0; k < 9; ++k) vd[k] = v[k];
+      tri_light[(size_t)i] = (int32_t)list.size();
+      push_light(list, vd, m);
     }
-    double c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
-    double len = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
-    Tmp t;
-    std::memset(&t, 0, sizeof(t));
-    double area = 0.5 * len;
-    t.t.p0 = make_float4(v[0], v[1], v[2], (float)area);
-    t.t.p1 = make_float4(v[3], v[4], v[5], 0.0f);
-    t.t.p2 = make_float4(v[6], v[7], v[8], 0.0f);
-    t.t.ng = len > 0 ? make_float4((float)(c[0] / len), (float)(c[1] / len), (float)(c[2] / len), 0.0f)
-                     : make_float4(0, 0, 0, 0);
-    t.t.Le = make_float4((float)Le[0], (float)Le[1], (float)Le[2], 0.0f);
-    t.w = area * lumd(Le[0], Le[1], Le[2]);
-    tri_light[(size_t)i] = (int32_t)list.size();
-    list.push_back(t);
+  } else {
+    // lights in instance order, then primitive order; each instance with emitters gets a
+    // primitive -> light table
+    lmap.clear();
+    for (size_t i = 0; i < s->host_insts.size(); ++i) {
+      InstRec& I = s->host_insts[i];
+      I.light_map = -1;
+      const std::vector<float>& mv = s->host_mesh_verts[I.mesh];
+      const std::vector<int32_t>& mm = s->host_mesh_mat[I.mesh];
+      size_t nt = mm.size();
+      for (size_t t = 0; t < nt; ++t) {
+        int32_t mid = I.mat_override >= 0 ? I.mat_override : mm[t];
+        const pt_openpbr_material& m = s->host_mats[(size_t)mid];
+        if (!mat_emits(m)) continue;
+        if (I.light_map < 0) {
+          I.light_map = (int32_t)lmap.size();
+          lmap.resize(lmap.size() + nt, -1);
+        }
+        double vd[9];
+        const float* q = I.o2w;
+        for (int v = 0; v < 3; ++v) {
+          double x = mv[9 * t + 3 * v], y = mv[9 * t + 3 * v + 1], z = mv[9 * t + 3 * v + 2];
+          for (int r = 0; r < 3; ++r)
+            vd[3 * v + r] = (double)q[4 * r] * x + (double)q[4 * r + 1] * y + (double)q[4 * r + 2] * z + (double)q[4 * r + 3];
+        }
+        lmap[(size_t)I.light_map + t] = (int32_t)list.size();
+        push_light(list, vd, m);
+      }
+    }
+    if (lmap.empty()) lmap.push_back(-1);
   }
   double wsum = 0.0;
   for (auto& t : list) wsum += t.w;
@@ -192,12 +241,16 @@ pt_status ensure_lights(pt_scene* s) {
   if (!has_tri) {
     lt.clear();
     std::fill(tri_light.begin(), tri_light.end(), -1);
+    std::fill(lmap.begin(), lmap.end(), -1);
   }
   s->n_lights = (int32_t)lt.size();
   s->p_env = (float)p_env;
   PT_HIP(upload(s->lights, lt.data(), lt.size() * sizeof(LightTri), s->stream));
   PT_HIP(upload(s->light_cdf, cdf.data(), cdf.size() * sizeof(float), s->stream));
   PT_HIP(upload(s->tri_light, tri_light.data(), tri_light.size() * sizeof(int32_t), s->stream));
+  PT_HIP(upload(s->light_map, lmap.data(), lmap.size() * sizeof(int32_t), s->stream));
+  if (s->two_level)
+    PT_HIP(upload(s->insts, s->host_insts.data(), s->host_insts.size() * sizeof(InstRec), s->stream));
   PT_HIP(hipStreamSynchronize(s->stream));
   s->lights_dirty = false;
   return PT_OK;
@@ -209,6 +262,8 @@ pt_status ensure_paths(pt_scene* s, int64_t n) {
   PT_HIP(s->ray_o.alloc(f4));
   PT_HIP(s->ray_d.alloc(f4));
   PT_HIP(s->hit.alloc(f4));
+  PT_HIP(s->hit_inst.alloc(u4));
+  PT_HIP(s->sh_inst.alloc(u4));
   PT_HIP(s->beta.alloc(f4));
   PT_HIP(s->L.alloc(f4));
   PT_HIP(s->flags.alloc(u4));
@@ -276,6 +331,13 @@ SceneDev scene_dev(pt_scene* s, int grid_trace) {
   S.spill = s->spill.as<uint2>();
   S.stack_cap = 3 * std::max(s->bvh_depth, 1) + 4;
   S.spill_stride = (uint32_t)grid_trace * kBlock;
+  S.insts = s->insts.as<InstRec>();
+  S.n_insts = (uint32_t)s->host_insts.size();
+  S.tlas = s->tlas.as<BVHNode>();
+  S.tlas_items = s->tlas_items.as<uint32_t>();
+  S.light_map = s->light_map.as<int32_t>();
+  S.mesh_tri_first = s->mesh_tri_first.as<uint32_t>();
+  S.mesh_tri_count = s->mesh_tri_count.as<uint32_t>();
   return S;
 }
 
@@ -285,6 +347,8 @@ PathsDev paths_dev(pt_scene* s, int64_t n, int x0, int y0, int w) {
   P.ray_o = s->ray_o.as<float4>();
   P.ray_d = s->ray_d.as<float4>();
   P.hit = s->hit.as<float4>();
+  P.hit_inst = s->hit_inst.as<uint32_t>();
+  P.sh_inst = s->sh_inst.as<uint32_t>();
   P.beta = s->beta.as<float4>();
   P.L = s->L.as<float4>();
   P.flags = s->flags.as<uint32_t>();
@@ -370,6 +434,7 @@ pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h,
   A.grid_trace = grid_trace;
   A.debug = per_sample != nullptr;
   A.count = s->counting;
+  A.two_level = s->two_level;
   A.class_mask = s->class_mask | (1u << kClsMiss);
   int nev = 2 * (max_depth + 1) + 2;
   if (s->timing) {
@@ -490,6 +555,177 @@ MatRec make_matrec(const pt_openpbr_material& m) {
   return r;
 }
 
+// Append a mesh BVH to the shared node / triangle arrays, re-basing its refs.
+uint32_t append_bvh(const Bvh4& b, std::vector<BVHNode>& nodes, std::vector<TriRec>& tris) {
+  uint32_t node_off = (uint32_t)nodes.size(), tri_off = (uint32_t)tris.size();
+  for (BVHNode n : b.nodes) {
+    for (int c = 0; c < 4; ++c) {
+      uint32_t r = n.child[c];
+      if (r == kEmpty) continue;
+      n.child[c] = ref_is_leaf(r) ? make_leaf(leaf_first(r) + tri_off, leaf_count(r)) : r + node_off;
+    }
+    nodes.push_back(n);
+  }
+  tris.insert(tris.end(), b.tris.begin(), b.tris.end());
+  return node_off;
+}
+
+// Two-level hierarchy: one BVH4 per mesh in object space, a top-level BVH4 over
+// instance world boxes (computed from the transformed vertices in double and
+// widened), rigid inverses in double rounded to float.
+struct TwoLevel {
+  std::vector<BVHNode> nodes;
+  std::vector<TriRec> tris;
+  Bvh4 top;
+  std::vector<uint32_t> items, tfirst, tcount;
+  std::vector<InstRec> insts;
+  std::vector<std::vector<float>> mverts;
+  std::vector<std::vector<int32_t>> mmat;
+  float tmin = 0.0f;
+  int depth = 0;
+  int32_t max_mat = -1;
+};
+
+pt_status build_two_level_host(const pt_mesh* meshes, int32_t n_meshes, const pt_instance* instances,
+                               int32_t n_instances, TwoLevel& out) {
+  std::vector<std::vector<float>> mverts((size_t)n_meshes);
+  std::vector<std::vector<int32_t>> mmat((size_t)n_meshes);
+  std::vector<BVHNode> nodes;
+  std::vector<TriRec> tris;
+  std::vector<uint32_t> root((size_t)n_meshes), tfirst((size_t)n_meshes), tcount((size_t)n_meshes);
+  int blas_depth = 0;
+  for (int i = 0; i < n_meshes; ++i) {
+    const pt_mesh& m = meshes[i];
+    std::vector<float>& v = mverts[(size_t)i];
+    v.resize((size_t)m.n_triangles * 9);
+    mmat[(size_t)i].assign((size_t)m.n_triangles, 0);
+    std::vector<uint32_t> prim((size_t)m.n_triangles), mat((size_t)m.n_triangles, 0u);
+    for (int64_t t = 0; t < m.n_triangles; ++t) {
+      for (int k = 0; k < 3; ++k) {
+        int32_t vi = m.indices[3 * t + k];
+        for (int c = 0; c < 3; ++c) v[9 * (size_t)t + 3 * k + c] = m.vertices[3 * (size_t)vi + c];
+      }
+      prim[(size_t)t] = (uint32_t)t;
+      if (m.material_ids) {
+        mmat[(size_t)i][(size_t)t] = m.material_ids[t];
+        mat[(size_t)t] = (uint32_t)m.material_ids[t];
+      }
+    }
+    Bvh4 b;
+    std::string err;
+    if (!build_bvh4(v.data(), prim.data(), mat.data(), m.n_triangles, b, err))
+      return fail(PT_ERR_INVALID_ARG, "mesh %d: %s", i, err.c_str());
+    tfirst[(size_t)i] = (uint32_t)tris.size();
+    tcount[(size_t)i] = (uint32_t)m.n_triangles;
+    root[(size_t)i] = append_bvh(b, nodes, tris);
+    blas_depth = std::max(blas_depth, b.depth);
+    if (tris.size() >= (size_t)kLeafFirstMask) return fail(PT_ERR_INVALID_ARG, "too many unique triangles");
+  }
+  std::vector<InstRec> insts((size_t)n_instances);
+  std::vector<float> boxes((size_t)n_instances * 9);
+  double slo[3] = {INFINITY, INFINITY, INFINITY}, shi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int32_t max_mat = -1;
+  for (int i = 0; i < n_instances; ++i) {
+    const pt_instance& in = instances[i];
+    InstRec& I = insts[(size_t)i];
+    std::memset(&I, 0, sizeof(I));
+    const float* M = in.object_to_world;
+    double R[3][3], T[3];
+    for (int r = 0; r < 3; ++r) {
+      for (int c = 0; c < 3; ++c) R[r][c] = M[4 * r + c];
+      T[r] = M[4 * r + 3];
+    }
+    for (int k = 0; k < 12; ++k) I.o2w[k] = M[k];
+    for (int r = 0; r < 3; ++r) {
+      for (int c = 0; c < 3; ++c) I.w2o[4 * r + c] = (float)R[c][r];
+      I.w2o[4 * r + 3] = (float)(-(R[0][r] * T[0] + R[1][r] * T[1] + R[2][r] * T[2]));
+    }
+    I.blas_root = root[(size_t)in.mesh];
+    I.mat_override = in.material_override;
+    I.light_map = -1;
+    I.mesh = (uint32_t)in.mesh;
+    if (in.material_override >= 0) {
+      max_mat = std::max(max_mat, in.material_override);
+    } else {
+      for (int32_t id : mmat[(size_t)in.mesh]) max_mat = std::max(max_mat, id);
+    }
+    // world box of the transformed vertices
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const std::vector<float>& v = mverts[(size_t)in.mesh];
+    for (size_t q = 0; q < v.size(); q += 3) {
+      double x = v[q], y = v[q + 1], z = v[q + 2];
+      for (int r = 0; r < 3; ++r) {
+        double w = R[r][0] * x + R[r][1] * y + R[r][2] * z + T[r];
+        lo[r] = std::min(lo[r], w);
+        hi[r] = std::max(hi[r], w);
+      }
+    }
+    for (int r = 0; r < 3; ++r) {
+      slo[r] = std::min(slo[r], lo[r]);
+      shi[r] = std::max(shi[r], hi[r]);
+      // widen: the triangle test runs on a single-precision object-space ray
+      double pad = 1e-5 * (1.0 + std::fabs(lo[r]) + std::fabs(hi[r]) + (hi[r] - lo[r]));
+      float l = (float)(lo[r] - pad), h = (float)(hi[r] + pad);
+      boxes[9 * (size_t)i + r] = l;
+      boxes[9 * (size_t)i + 3 + r] = h;
+      boxes[9 * (size_t)i + 6 + r] = l;
+    }
+  }
+  // top level over the instance boxes (a box is fed as the triangle (lo, hi, lo))
+  std::vector<uint32_t> ids((size_t)n_instances), zero((size_t)n_instances, 0u);
+  for (int i = 0; i < n_instances; ++i) ids[(size_t)i] = (uint32_t)i;
+  Bvh4 top;
+  std::string err;
+  if (!build_bvh4(boxes.data(), ids.data(), zero.data(), n_instances, top, err))
+    return fail(PT_ERR_INVALID_ARG, "top level: %s", err.c_str());
+  std::vector<uint32_t> items((size_t)n_instances);
+  for (int i = 0; i < n_instances; ++i) std::memcpy(&items[(size_t)i], &top.tris[(size_t)i].a.w, 4);
+  double dx = shi[0] - slo[0], dy = shi[1] - slo[1], dz = shi[2] - slo[2];
+  out.tmin = (float)(1e-5 * std::sqrt(dx * dx + dy * dy + dz * dz));
+  out.depth = top.depth + blas_depth;
+  out.max_mat = max_mat;
+  out.nodes.swap(nodes);
+  out.tris.swap(tris);
+  out.top = std::move(top);
+  out.items.swap(items);
+  out.tfirst.swap(tfirst);
+  out.tcount.swap(tcount);
+  out.insts.swap(insts);
+  out.mverts.swap(mverts);
+  out.mmat.swap(mmat);
+  return PT_OK;
+}
+
+pt_status build_two_level(pt_scene* s, const pt_mesh* meshes, int32_t n_meshes, const pt_instance* instances,
+                          int32_t n_instances) {
+  TwoLevel T;
+  pt_status r = build_two_level_host(meshes, n_meshes, instances, n_instances, T);
+  if (r) return r;
+  r = set_device(s);
+  if (r) return r;
+  PT_HIP(upload(s->nodes, T.nodes.data(), T.nodes.size() * sizeof(BVHNode), s->stream));
+  PT_HIP(upload(s->tris, T.tris.data(), T.tris.size() * sizeof(TriRec), s->stream));
+  PT_HIP(upload(s->tlas, T.top.nodes.data(), T.top.nodes.size() * sizeof(BVHNode), s->stream));
+  PT_HIP(upload(s->tlas_items, T.items.data(), T.items.size() * sizeof(uint32_t), s->stream));
+  PT_HIP(upload(s->insts, T.insts.data(), T.insts.size() * sizeof(InstRec), s->stream));
+  PT_HIP(upload(s->mesh_tri_first, T.tfirst.data(), T.tfirst.size() * sizeof(uint32_t), s->stream));
+  PT_HIP(upload(s->mesh_tri_count, T.tcount.data(), T.tcount.size() * sizeof(uint32_t), s->stream));
+  PT_HIP(hipStreamSynchronize(s->stream));
+  s->tmin = T.tmin;
+  s->n_tris = (uint32_t)T.tris.size();
+  s->bvh_depth = T.depth;
+  s->max_mat_id = T.max_mat;
+  s->host_tri_verts.clear();
+  s->host_tri_mat.clear();
+  s->host_insts.swap(T.insts);
+  s->host_mesh_verts.swap(T.mverts);
+  s->host_mesh_mat.swap(T.mmat);
+  s->two_level = true;
+  s->has_bvh = true;
+  s->lights_dirty = true;
+  return PT_OK;
+}
+
 }  // namespace
 
 // =============================================================== C ABI ====
@@ -530,21 +766,31 @@ pt_status pt_build_bvh(pt_scene* s, const pt_mesh* meshes, int32_t n_meshes, con
   if (r) return r;
   if (!meshes || n_meshes <= 0) return fail(PT_ERR_INVALID_ARG, "meshes must be non-NULL with n_meshes > 0");
   if (n_instances < 0 || (n_instances > 0 && !instances)) return fail(PT_ERR_INVALID_ARG, "bad instances");
-  if (n_instances > 0) return fail(PT_ERR_UNSUPPORTED, "instanced scenes are not supported by this build yet");
+  for (int i = 0; i < n_instances; ++i) {
+    const pt_instance& in = instances[i];
+    if (in.mesh < 0 || in.mesh >= n_meshes) return fail(PT_ERR_INVALID_ARG, "instance %d: mesh %d out of range", i, in.mesh);
+    if (!finite_all(in.object_to_world, 12)) return fail(PT_ERR_INVALID_ARG, "instance %d: non-finite transform", i);
+    if (in.material_override < -1) return fail(PT_ERR_INVALID_ARG, "instance %d: bad material override", i);
+    if (in.material_override < 0 && !meshes[in.mesh].material_ids)
+      return fail(PT_ERR_INVALID_ARG, "instance %d: mesh %d has no material ids and no override", i, in.mesh);
+  }
   int64_t total = 0;
   for (int i = 0; i < n_meshes; ++i) {
     const pt_mesh& m = meshes[i];
     if (!m.vertices || !m.indices || m.n_vertices <= 0 || m.n_triangles <= 0)
       return fail(PT_ERR_INVALID_ARG, "mesh %d: NULL arrays or empty counts", i);
-    if (!m.material_ids) return fail(PT_ERR_INVALID_ARG, "mesh %d: material_ids is NULL and nothing overrides it", i);
+    if (!m.material_ids && n_instances == 0)
+      return fail(PT_ERR_INVALID_ARG, "mesh %d: material_ids is NULL and nothing overrides it", i);
     if (!finite_all(m.vertices, (size_t)m.n_vertices * 3)) return fail(PT_ERR_INVALID_ARG, "mesh %d: non-finite vertex", i);
     for (int64_t t = 0; t < m.n_triangles * 3; ++t)
       if (m.indices[t] < 0 || m.indices[t] >= m.n_vertices)
         return fail(PT_ERR_INVALID_ARG, "mesh %d: index %lld out of range", i, (long long)m.indices[t]);
-    for (int64_t t = 0; t < m.n_triangles; ++t)
-      if (m.material_ids[t] < 0) return fail(PT_ERR_INVALID_ARG, "mesh %d: negative material id", i);
+    if (m.material_ids)
+      for (int64_t t = 0; t < m.n_triangles; ++t)
+        if (m.material_ids[t] < 0) return fail(PT_ERR_INVALID_ARG, "mesh %d: negative material id", i);
     total += m.n_triangles;
   }
+  if (n_instances > 0) return build_two_level(s, meshes, n_meshes, instances, n_instances);
   if (total >= (int64_t)kLeafFirstMask) return fail(PT_ERR_INVALID_ARG, "too many triangles");
   std::vector<float> verts((size_t)total * 9);
   std::vector<int32_t> mat((size_t)total);
@@ -579,6 +825,10 @@ pt_status pt_build_bvh(pt_scene* s, const pt_mesh* meshes, int32_t n_meshes, con
   s->max_mat_id = max_mat;
   s->host_tri_verts.swap(verts);
   s->host_tri_mat.swap(mat);
+  s->host_insts.clear();
+  s->host_mesh_verts.clear();
+  s->host_mesh_mat.clear();
+  s->two_level = false;
   s->has_bvh = true;
   s->lights_dirty = true;
   return PT_OK;
@@ -764,7 +1014,7 @@ pt_status pt_trace_closest(pt_scene* s, const float* rays, int64_t n, uint32_t* 
   int grid = trace_grid_blocks();
   if ((r = ensure_spill(s, grid))) return r;
   SceneDev S = scene_dev(s, grid);
-  PT_HIP(launch_trace_rays(S, rays, n, hits, brute != 0, grid, s->stream));
+  PT_HIP(launch_trace_rays(S, rays, n, hits, brute != 0, s->two_level, grid, s->stream));
   return sync(s);
 }
 
@@ -817,7 +1067,33 @@ pt_status pt_set_profiling(pt_scene* s, int32_t timing, int32_t counting) {
 // ------------------------------------------------------- host-only BVH
 struct pt_bvh_host {
   Bvh4 b;
+  bool two = false;
+  TwoLevel T;
 };
+
+pt_status pt_bvh_host_build_instanced(const pt_mesh* meshes, int32_t n_meshes, const pt_instance* instances,
+                                      int32_t n_instances, pt_bvh_host** out) {
+  if (!meshes || !instances || !out || n_meshes <= 0 || n_instances <= 0) return fail(PT_ERR_INVALID_ARG, "bad arguments");
+  *out = nullptr;
+  for (int i = 0; i < n_meshes; ++i) {
+    const pt_mesh& m = meshes[i];
+    if (!m.vertices || !m.indices || m.n_vertices <= 0 || m.n_triangles <= 0)
+      return fail(PT_ERR_INVALID_ARG, "mesh %d: NULL arrays or empty counts", i);
+    for (int64_t t = 0; t < m.n_triangles * 3; ++t)
+      if (m.indices[t] < 0 || m.indices[t] >= m.n_vertices) return fail(PT_ERR_INVALID_ARG, "mesh %d: index out of range", i);
+  }
+  for (int i = 0; i < n_instances; ++i) {
+    if (instances[i].mesh < 0 || instances[i].mesh >= n_meshes) return fail(PT_ERR_INVALID_ARG, "instance %d: bad mesh", i);
+    if (!finite_all(instances[i].object_to_world, 12)) return fail(PT_ERR_INVALID_ARG, "instance %d: non-finite", i);
+  }
+  std::unique_ptr<pt_bvh_host> h(new (std::nothrow) pt_bvh_host());
+  if (!h) return fail(PT_ERR_OUT_OF_MEMORY, "out of host memory");
+  pt_status r = build_two_level_host(meshes, n_meshes, instances, n_instances, h->T);
+  if (r) return r;
+  h->two = true;
+  *out = h.release();
+  return PT_OK;
+}
 
 pt_status pt_bvh_host_build(const pt_mesh* m, pt_bvh_host** out) {
   if (!m || !out) return fail(PT_ERR_INVALID_ARG, "NULL argument");
@@ -846,6 +1122,15 @@ pt_status pt_bvh_host_build(const pt_mesh* m, pt_bvh_host** out) {
 
 pt_status pt_bvh_host_info(const pt_bvh_host* h, pt_bvh_info* info) {
   if (!h || !info) return fail(PT_ERR_INVALID_ARG, "NULL argument");
+  if (h->two) {
+    info->n_nodes = (int64_t)h->T.nodes.size();
+    info->n_tris = (int64_t)h->T.tris.size();
+    info->depth = h->T.depth;
+    info->max_leaf_tris = kMaxLeafTris;
+    info->sah_cost = 0.0;
+    info->build_ms = 0.0;
+    return PT_OK;
+  }
   info->n_nodes = (int64_t)h->b.nodes.size();
   info->n_tris = (int64_t)h->b.tris.size();
   info->depth = h->b.depth;
@@ -857,8 +1142,10 @@ pt_status pt_bvh_host_info(const pt_bvh_host* h, pt_bvh_info* info) {
 
 pt_status pt_bvh_host_copy(const pt_bvh_host* h, void* nodes, void* tris) {
   if (!h || !nodes || !tris) return fail(PT_ERR_INVALID_ARG, "NULL argument");
-  std::memcpy(nodes, h->b.nodes.data(), h->b.nodes.size() * sizeof(BVHNode));
-  std::memcpy(tris, h->b.tris.data(), h->b.tris.size() * sizeof(TriRec));
+  const std::vector<BVHNode>& n = h->two ? h->T.nodes : h->b.nodes;
+  const std::vector<TriRec>& t = h->two ? h->T.tris : h->b.tris;
+  std::memcpy(nodes, n.data(), n.size() * sizeof(BVHNode));
+  std::memcpy(tris, t.data(), t.size() * sizeof(TriRec));
   return PT_OK;
 }
 
@@ -871,8 +1158,13 @@ pt_status pt_bvh_host_trace(const pt_bvh_host* h, const float* rays, int64_t n, 
     hit_clear(best);
     HostStack st;
     uint32_t nv = 0, nt = 0;
-    traverse_bvh<false, false>(h->b.nodes.data(), h->b.tris.data(), 0u, r, R[3], R[7], 0u, 0xFFFFFFFFu, 0xFFFFFFFFu,
-                               best, st, nv, nt);
+    if (h->two)
+      traverse_two_level<false, false>(h->T.top.nodes.data(), h->T.items.data(), h->T.insts.data(),
+                                       h->T.nodes.data(), h->T.tris.data(), r, R[3], R[7], 0xFFFFFFFFu, 0xFFFFFFFFu,
+                                       best, st, nv, nt);
+    else
+      traverse_bvh<false, false>(h->b.nodes.data(), h->b.tris.data(), 0u, r, R[3], R[7], 0u, 0xFFFFFFFFu,
+                                 0xFFFFFFFFu, best, st, nv, nt);
     if (st.overflow) return fail(PT_ERR_DEVICE, "host traversal stack overflow");
     uint32_t* H = hits + 6 * i;
     bool hit = best.tri != 0xFFFFFFFFu;

@@ -36,7 +36,15 @@ struct SceneDev {
   const float* env_col_cdf;  // [h][w + 1]
   int32_t env_w, env_h;
   float tmin;                // self-intersection offset: 1e-5 x scene diagonal
-  float axis[3];             // object +z axis in world space (shading tangent)
+  float axis[3];             // object +z axis in world space (shading tangent, single level)
+  // two-level hierarchy (instances); unused for a single world-space mesh
+  const InstRec* insts;
+  uint32_t n_insts;
+  const BVHNode* tlas;
+  const uint32_t* tlas_items;     // instance ids in top-level leaf order
+  const int32_t* light_map;       // per instance with emitters: primitive -> light index
+  const uint32_t* mesh_tri_first; // first triangle record of each mesh (brute force)
+  const uint32_t* mesh_tri_count;
   uint2* spill;              // traversal stack spill, [cap - kLdsStack][grid threads]
   int32_t stack_cap;         // total stack entries per lane
   uint32_t spill_stride;     // grid threads of the traversal kernels
@@ -54,6 +62,7 @@ struct PathsDev {
   float4* ray_o;       // o.xyz, skip primitive (bits)
   float4* ray_d;       // d.xyz, skip instance (bits)
   float4* hit;         // t, b1, b2, triangle record index (bits; 0xFFFFFFFF = miss)
+  uint32_t* hit_inst;  // instance of the hit (two-level scenes)
   float4* beta;        // throughput rgb, pdf of the last BSDF sample
   float4* L;           // radiance rgb, eta scale (product of eta^2 over refractions)
   uint32_t* flags;     // bit 0: last bounce was a delta lobe
@@ -62,6 +71,7 @@ struct PathsDev {
   float4* sh_o;        // shadow ray o.xyz, tmax
   float4* sh_d;        // d.xyz, path slot (bits)
   float4* sh_c;        // contribution rgb, skip primitive (bits)
+  uint32_t* sh_inst;   // skip instance
   uint32_t* counts;    // [0..1] ray queues, [2..2+kNumClasses) classes, [2+kNumClasses] shadow
   unsigned long long* stats;  // see kStat*
   uint64_t* sig;       // path signatures (debug)
@@ -94,6 +104,7 @@ struct PassArgs {
   int grid_trace;   // workgroups of the traversal kernels
   bool debug;
   bool count;
+  bool two_level;
   uint32_t class_mask;  // material classes present (bit per class)
   hipEvent_t* ext_events;  // 2 per bounce when timing, else nullptr
 };
@@ -106,7 +117,7 @@ hipError_t launch_resolve(const double* sum, float* out, int64_t n_values, doubl
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st);
 hipError_t launch_trace_rays(const SceneDev& S, const float* rays, int64_t n, uint32_t* hits, bool brute,
-                             int grid, hipStream_t st);
+                             bool two_level, int grid, hipStream_t st);
 int trace_grid_blocks();
 
 }  // namespace pt

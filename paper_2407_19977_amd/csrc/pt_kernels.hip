@@ -96,7 +96,7 @@ struct DevStack {
     k = u2f(v.y);
     return v.x;
   }
-  __device__ inline bool empty() const { return sp == 0; }
+  __device__ inline int size() const { return sp; }
 };
 
 // ------------------------------------------------------------------ lights
@@ -234,7 +234,20 @@ __global__ void k_reset_counts(uint32_t* counts, int next_queue) {
 }
 
 // ------------------------------------------------------------------ extend
-template <bool COUNT>
+// Closest hit of one ray, single world-space BVH or two-level hierarchy.
+template <bool ANY, bool COUNT, bool TWO>
+__device__ inline bool trace_ray(const SceneDev& S, float ox, float oy, float oz, float dx, float dy, float dz,
+                                 float tmin, float tmax, uint32_t skip_inst, uint32_t skip_prim, Hit& h,
+                                 DevStack& st, uint32_t& nvis, uint32_t& ntri) {
+  RayPre r = ray_prepare(ox, oy, oz, dx, dy, dz);
+  if (TWO)
+    return traverse_two_level<ANY, COUNT>(S.tlas, S.tlas_items, S.insts, S.nodes, S.tris, r, tmin, tmax, skip_inst,
+                                          skip_prim, h, st, nvis, ntri);
+  return traverse_bvh<ANY, COUNT>(S.nodes, S.tris, S.root, r, tmin, tmax, 0u, skip_inst, skip_prim, h, st, nvis,
+                                  ntri);
+}
+
+template <bool COUNT, bool TWO>
 __global__ __launch_bounds__(kBlock) void k_extend(SceneDev S, PathsDev P, int cur) {
   __shared__ uint32_t s_ref[kLdsStack * kBlock];
   __shared__ float s_key[kLdsStack * kBlock];
@@ -251,16 +264,21 @@ __global__ __launch_bounds__(kBlock) void k_extend(SceneDev S, PathsDev P, int c
     if (active) {
       slot = P.q_ray[cur][i];
       float4 o = P.ray_o[slot], d = P.ray_d[slot];
-      RayPre r = ray_prepare(o.x, o.y, o.z, d.x, d.y, d.z);
       Hit h;
       hit_clear(h);
       DevStack st{s_ref + threadIdx.x, s_key + threadIdx.x, S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
-      traverse_bvh<false, COUNT>(S.nodes, S.tris, S.root, r, S.tmin, INFINITY, 0u, f2u(d.w), f2u(o.w), h, st,
-                                 nvis, ntri);
+      trace_ray<false, COUNT, TWO>(S, o.x, o.y, o.z, d.x, d.y, d.z, S.tmin, INFINITY, f2u(d.w), f2u(o.w), h, st,
+                                   nvis, ntri);
       overflow |= st.overflow;
       if (h.tri != 0xFFFFFFFFu) {
         P.hit[slot] = make_float4(h.t, h.b1, h.b2, u2f(h.tri));
-        cls = S.mats[h.mat].cls;
+        uint32_t mid = h.mat;
+        if (TWO) {
+          P.hit_inst[slot] = h.inst;
+          int32_t ov = S.insts[h.inst].mat_override;
+          if (ov >= 0) mid = (uint32_t)ov;
+        }
+        cls = S.mats[mid].cls;
       } else {
         P.hit[slot] = make_float4(INFINITY, 0.0f, 0.0f, u2f(0xFFFFFFFFu));
         cls = kClsMiss;
@@ -285,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_extend(SceneDev S, PathsDev P, int c
 }
 
 // ------------------------------------------------------------------- shade
-template <int CLS, bool DEBUG>
+template <int CLS, bool DEBUG, bool TWO>
 __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b, int max_depth, int next,
                                                   uint32_t sample, uint32_t k0, uint32_t k1, uint32_t img_w) {
   const uint32_t count = P.counts[2 + CLS];
@@ -295,6 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b,
     bool cont = false, shadow = false;
     uint32_t slot = 0;
     float4 sh_o = make_float4(0, 0, 0, 0), sh_d = make_float4(0, 0, 0, 0), sh_c = make_float4(0, 0, 0, 0);
+    uint32_t sh_inst = 0;
     if (active) {
       slot = P.q_cls[CLS][i];
       float4 rd = P.ray_d[slot];
@@ -330,23 +349,39 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b,
         if (DEBUG) P.sig[slot] = sig;
       } else {
         float4 hv = P.hit[slot];
-        float4 ro = P.ray_o[slot];
         const TriRec tr = S.tris[f2u(hv.w)];
         uint32_t prim = f2u(tr.a.w), mid = f2u(tr.b.w);
-        const MatRec& m = S.mats[mid];
-        if (DEBUG) { sig = sig_word(sig, 1); sig = sig_word(sig, 0u); sig = sig_word(sig, prim); }
+        uint32_t inst = 0;
         V3 p0 = v3(tr.a.x, tr.a.y, tr.a.z), p1 = v3(tr.b.x, tr.b.y, tr.b.z), p2 = v3(tr.c.x, tr.c.y, tr.c.z);
         float b1 = hv.y, b2 = hv.z;
         V3 p = p0 * (1.0f - b1 - b2) + p1 * b1 + p2 * b2;
-        V3 ng = normalize(cross(p1 - p0, p2 - p0));
+        V3 nc = cross(p1 - p0, p2 - p0);
+        V3 axis = v3(S.axis[0], S.axis[1], S.axis[2]);
+        int light_of_prim = -1;
+        if (TWO) {
+          inst = P.hit_inst[slot];
+          const InstRec& I = S.insts[inst];
+          if (I.mat_override >= 0) mid = (uint32_t)I.mat_override;
+          const float* q = I.o2w;
+          p = v3(q[0] * p.x + q[1] * p.y + q[2] * p.z + q[3], q[4] * p.x + q[5] * p.y + q[6] * p.z + q[7],
+                 q[8] * p.x + q[9] * p.y + q[10] * p.z + q[11]);
+          nc = v3(q[0] * nc.x + q[1] * nc.y + q[2] * nc.z, q[4] * nc.x + q[5] * nc.y + q[6] * nc.z,
+                  q[8] * nc.x + q[9] * nc.y + q[10] * nc.z);
+          axis = v3(q[2], q[6], q[10]);
+          if (I.light_map >= 0) light_of_prim = S.light_map[I.light_map + (int)prim];
+        } else {
+          light_of_prim = S.tri_light[prim];
+        }
+        const MatRec& m = S.mats[mid];
+        if (DEBUG) { sig = sig_word(sig, 1); sig = sig_word(sig, inst); sig = sig_word(sig, prim); }
+        V3 ng = normalize(nc);
         V3 wo_w = d * -1.0f;
         float cos_ng = dot(ng, wo_w);
-        (void)ro;
         // emission (front face only), MIS-weighted against light sampling
         if ((m.flags & kMatEmissive) && cos_ng > 0.0f) {
           float w = 1.0f;
           if (!prev_delta) {
-            int k = S.tri_light[prim];
+            int k = light_of_prim;
             float pl = 0.0f;
             if (k >= 0 && S.n_lights > 0) {
               const LightTri& Lt = S.lights[k];
@@ -370,7 +405,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b,
           bool entering = cos_ng > 0.0f;
           V3 n = entering ? ng : ng * -1.0f;
           V3 t, bt;
-          make_frame(n, v3(S.axis[0], S.axis[1], S.axis[2]), t, bt);
+          make_frame(n, axis, t, bt);
           V3 wo = v3(dot(wo_w, t), dot(wo_w, bt), dot(wo_w, n));
           Bsdf B = bsdf_setup<CLS>(m, entering, wo.z);
           if (wo.z <= 0.0f) B.absorbed = true;
@@ -396,6 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b,
                 sh_o = make_float4(p.x, p.y, p.z, tmax);
                 sh_d = make_float4(ls.wl.x, ls.wl.y, ls.wl.z, u2f(slot));
                 sh_c = make_float4(c.x, c.y, c.z, u2f(prim));
+                sh_inst = inst;
               } else {
                 nee_out = 2u;
               }
@@ -414,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b,
             bool killed = false;
             if (b >= 1) {
               float q = fmaxf(fmaxf(beta.x, beta.y), beta.z) * eta_scale;
-              if (q < 1.0f) {
+              if (q < 0.995f) {  // no roulette within rounding of q = 1
                 killed = u01(r0.w) >= q;
                 rr_ev = killed ? 2 : 1;
                 if (!killed) beta = beta * (1.0f / q);
@@ -425,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b,
             } else {
               V3 dn = normalize(t * bs.wi.x + bt * bs.wi.y + n * bs.wi.z);
               P.ray_o[slot] = make_float4(p.x, p.y, p.z, u2f(prim));
-              P.ray_d[slot] = make_float4(dn.x, dn.y, dn.z, u2f(0u));
+              P.ray_d[slot] = make_float4(dn.x, dn.y, dn.z, u2f(inst));
               P.beta[slot] = make_float4(beta.x, beta.y, beta.z, pdf_prev);
               P.flags[slot] = prev_delta ? 1u : 0u;
               cont = true;
@@ -458,12 +494,13 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b,
       P.sh_o[spos] = sh_o;
       P.sh_d[spos] = sh_d;
       P.sh_c[spos] = sh_c;
+      if (TWO) P.sh_inst[spos] = sh_inst;
     }
   }
 }
 
 // ----------------------------------------------------------------- connect
-template <bool DEBUG, bool COUNT>
+template <bool DEBUG, bool COUNT, bool TWO>
 __global__ __launch_bounds__(kBlock) void k_connect(SceneDev S, PathsDev P) {
   __shared__ uint32_t s_ref[kLdsStack * kBlock];
   __shared__ float s_key[kLdsStack * kBlock];
@@ -476,12 +513,12 @@ __global__ __launch_bounds__(kBlock) void k_connect(SceneDev S, PathsDev P) {
   for (uint32_t i = gtid; i < count; i += gridDim.x * kBlock) {
     float4 o = P.sh_o[i], d = P.sh_d[i], c = P.sh_c[i];
     uint32_t slot = f2u(d.w);
-    RayPre r = ray_prepare(o.x, o.y, o.z, d.x, d.y, d.z);
     Hit h;
     hit_clear(h);
     DevStack st{s_ref + threadIdx.x, s_key + threadIdx.x, S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
-    bool occ = traverse_bvh<true, COUNT>(S.nodes, S.tris, S.root, r, S.tmin, o.w, 0u, 0u, f2u(c.w), h, st, nvis,
-                                         ntri);
+    uint32_t skip_inst = TWO ? P.sh_inst[i] : 0u;
+    bool occ = trace_ray<true, COUNT, TWO>(S, o.x, o.y, o.z, d.x, d.y, d.z, S.tmin, o.w, skip_inst, f2u(c.w), h, st,
+                                           nvis, ntri);
     overflow |= st.overflow;
     if (!occ) {
       V3 cc = v3(c.x, c.y, c.z);
@@ -546,22 +583,24 @@ __global__ __launch_bounds__(kBlock) void k_zero_u64(unsigned long long* p, int6
 }
 
 // ------------------------------------------------------- ray query kernels
-template <bool BRUTE>
+template <bool BRUTE, bool TWO>
 __global__ __launch_bounds__(kBlock) void k_trace_rays(SceneDev S, const float* rays, int64_t n, uint32_t* hits) {
   __shared__ uint32_t s_ref[kLdsStack * kBlock];
   __shared__ float s_key[kLdsStack * kBlock];
   const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
   for (int64_t i = gtid; i < n; i += (int64_t)gridDim.x * kBlock) {
     const float* R = rays + 8 * i;
-    RayPre r = ray_prepare(R[0], R[1], R[2], R[4], R[5], R[6]);
     Hit h;
     hit_clear(h);
     uint32_t nv = 0, nt = 0;
     if (BRUTE) {
-      brute_force<false>(S.tris, S.n_tris, r, R[3], R[7], 0u, h, nt);
+      RayPre r = ray_prepare(R[0], R[1], R[2], R[4], R[5], R[6]);
+      if (TWO) brute_force_two_level(S.insts, S.n_insts, S.tris, S.mesh_tri_first, S.mesh_tri_count, r, R[3], R[7], h);
+      else brute_force<false>(S.tris, S.n_tris, r, R[3], R[7], 0u, h, nt);
     } else {
       DevStack st{s_ref + threadIdx.x, s_key + threadIdx.x, S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
-      traverse_bvh<false, false>(S.nodes, S.tris, S.root, r, R[3], R[7], 0u, 0xFFFFFFFFu, 0xFFFFFFFFu, h, st, nv, nt);
+      trace_ray<false, false, TWO>(S, R[0], R[1], R[2], R[4], R[5], R[6], R[3], R[7], 0xFFFFFFFFu, 0xFFFFFFFFu, h,
+                                   st, nv, nt);
     }
     uint32_t* H = hits + 6 * i;
     bool hit = h.tri != 0xFFFFFFFFu;
@@ -577,13 +616,13 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays(SceneDev S, const float* 
 // --------------------------------------------------------------- launchers
 int trace_grid_blocks() { return 2048; }
 
-template <bool DEBUG>
+template <bool DEBUG, bool TWO>
 static hipError_t shade_all(const SceneDev& S, const PathsDev& P, const PassArgs& A, int b, int next, uint32_t W,
                             hipStream_t st) {
   dim3 g(A.grid), blk(kBlock);
 #define PT_SHADE(C)                                                                                     \
   if (A.class_mask & (1u << C))                                                                         \
-    hipLaunchKernelGGL((k_shade<C, DEBUG>), g, blk, 0, st, S, P, b, A.max_depth, next, A.sample, A.k0, \
+    hipLaunchKernelGGL((k_shade<C, DEBUG, TWO>), g, blk, 0, st, S, P, b, A.max_depth, next, A.sample, A.k0, \
                        A.k1, W);
   PT_SHADE(kClsMiss)
   PT_SHADE(kClsAbsorb)
@@ -596,31 +635,38 @@ static hipError_t shade_all(const SceneDev& S, const PathsDev& P, const PassArgs
   return hipGetLastError();
 }
 
-hipError_t launch_pass(const SceneDev& S, const PathsDev& P, const CamDev& C, const PassArgs& A, hipStream_t st) {
+template <bool DEBUG, bool COUNT, bool TWO>
+static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev& C, const PassArgs& A,
+                              hipStream_t st) {
   dim3 blk(kBlock);
-  if (A.debug) hipLaunchKernelGGL((k_generate<true>), dim3(A.grid), blk, 0, st, P, C, A.sample, A.k0, A.k1);
-  else hipLaunchKernelGGL((k_generate<false>), dim3(A.grid), blk, 0, st, P, C, A.sample, A.k0, A.k1);
   for (int b = 0; b <= A.max_depth; ++b) {
     int cur = b & 1, next = cur ^ 1;
     hipLaunchKernelGGL(k_reset_counts, dim3(1), dim3(64), 0, st, P.counts, next);
     if (A.ext_events) hipEventRecord(A.ext_events[2 * b], st);
-    if (A.count) hipLaunchKernelGGL((k_extend<true>), dim3(A.grid_trace), blk, 0, st, S, P, cur);
-    else hipLaunchKernelGGL((k_extend<false>), dim3(A.grid_trace), blk, 0, st, S, P, cur);
+    hipLaunchKernelGGL((k_extend<COUNT, TWO>), dim3(A.grid_trace), blk, 0, st, S, P, cur);
     if (A.ext_events) hipEventRecord(A.ext_events[2 * b + 1], st);
-    hipError_t e = A.debug ? shade_all<true>(S, P, A, b, next, (uint32_t)C.W, st)
-                           : shade_all<false>(S, P, A, b, next, (uint32_t)C.W, st);
+    hipError_t e = shade_all<DEBUG, TWO>(S, P, A, b, next, (uint32_t)C.W, st);
     if (e != hipSuccess) return e;
-    if (b < A.max_depth) {
-      if (A.debug) {
-        if (A.count) hipLaunchKernelGGL((k_connect<true, true>), dim3(A.grid_trace), blk, 0, st, S, P);
-        else hipLaunchKernelGGL((k_connect<true, false>), dim3(A.grid_trace), blk, 0, st, S, P);
-      } else {
-        if (A.count) hipLaunchKernelGGL((k_connect<false, true>), dim3(A.grid_trace), blk, 0, st, S, P);
-        else hipLaunchKernelGGL((k_connect<false, false>), dim3(A.grid_trace), blk, 0, st, S, P);
-      }
-    }
+    if (b < A.max_depth) hipLaunchKernelGGL((k_connect<DEBUG, COUNT, TWO>), dim3(A.grid_trace), blk, 0, st, S, P);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_pass(const SceneDev& S, const PathsDev& P, const CamDev& C, const PassArgs& A, hipStream_t st) {
+  dim3 blk(kBlock);
+  if (A.debug) hipLaunchKernelGGL((k_generate<true>), dim3(A.grid), blk, 0, st, P, C, A.sample, A.k0, A.k1);
+  else hipLaunchKernelGGL((k_generate<false>), dim3(A.grid), blk, 0, st, P, C, A.sample, A.k0, A.k1);
+  const int sel = (A.debug ? 4 : 0) | (A.count ? 2 : 0) | (A.two_level ? 1 : 0);
+  switch (sel) {
+    case 0: return bounce_loop<false, false, false>(S, P, C, A, st);
+    case 1: return bounce_loop<false, false, true>(S, P, C, A, st);
+    case 2: return bounce_loop<false, true, false>(S, P, C, A, st);
+    case 3: return bounce_loop<false, true, true>(S, P, C, A, st);
+    case 4: return bounce_loop<true, false, false>(S, P, C, A, st);
+    case 5: return bounce_loop<true, false, true>(S, P, C, A, st);
+    case 6: return bounce_loop<true, true, false>(S, P, C, A, st);
+    default: return bounce_loop<true, true, true>(S, P, C, A, st);
+  }
 }
 
 static int blocks_for(int64_t n) {
@@ -652,10 +698,13 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_trace_rays(const SceneDev& S, const float* rays, int64_t n, uint32_t* hits, bool brute, int grid,
-                             hipStream_t st) {
-  if (brute) hipLaunchKernelGGL((k_trace_rays<true>), dim3(grid), dim3(kBlock), 0, st, S, rays, n, hits);
-  else hipLaunchKernelGGL((k_trace_rays<false>), dim3(grid), dim3(kBlock), 0, st, S, rays, n, hits);
+hipError_t launch_trace_rays(const SceneDev& S, const float* rays, int64_t n, uint32_t* hits, bool brute,
+                             bool two_level, int grid, hipStream_t st) {
+  dim3 g(grid), blk(kBlock);
+  if (brute && two_level) hipLaunchKernelGGL((k_trace_rays<true, true>), g, blk, 0, st, S, rays, n, hits);
+  else if (brute) hipLaunchKernelGGL((k_trace_rays<true, false>), g, blk, 0, st, S, rays, n, hits);
+  else if (two_level) hipLaunchKernelGGL((k_trace_rays<false, true>), g, blk, 0, st, S, rays, n, hits);
+  else hipLaunchKernelGGL((k_trace_rays<false, false>), g, blk, 0, st, S, rays, n, hits);
   return hipGetLastError();
 }
 

@@ -67,6 +67,20 @@ struct alignas(128) MatRec {
 static_assert(sizeof(MatRec) == 128, "material record is 128 bytes");
 constexpr uint32_t kMatSpecDelta = 1u, kMatCoatDelta = 2u, kMatEmissive = 4u;
 
+// Instance of a mesh in the two-level hierarchy, 128 bytes.  w2o is the
+// rigid inverse of o2w computed in double and rounded to float; rays enter
+// object space as o' = ((w0 ox + w1 oy) + w2 oz) + w3 per row (no FMA).
+struct alignas(128) InstRec {
+  float w2o[12];         // world -> object, row-major 3x4
+  float o2w[12];         // object -> world, row-major 3x4
+  uint32_t blas_root;    // node index of the mesh's BVH root
+  int32_t mat_override;  // -1: per-triangle material ids
+  int32_t light_map;     // offset of this instance's primitive -> light table, -1 if none
+  uint32_t mesh;
+  uint32_t pad[4];
+};
+static_assert(sizeof(InstRec) == 128, "instance record is 128 bytes");
+
 // Emissive triangle in world space (for next-event estimation).
 struct alignas(16) LightTri {
   float4 p0;   // xyz, area

@@ -184,12 +184,13 @@ __host__ __device__ inline void cswap(float& ka, uint32_t& ra, float& kb, uint32
 }
 
 // Walk one BVH4 from `root`.  Stack: push(ref, tnear), pop(ref, tnear),
-// empty(), ok().  ANY: return at the first accepted triangle (shadow rays).
+// size().  Entries below `base` belong to an enclosing walk and are left
+// alone.  ANY: return at the first accepted triangle (shadow rays).
 template <bool ANY, bool COUNT, class Stack>
 __host__ __device__ inline bool traverse_bvh(const BVHNode* __restrict__ nodes, const TriRec* __restrict__ tris,
                                              uint32_t root, const RayPre& r, float tmin, float tmax,
                                              uint32_t inst, uint32_t skip_inst, uint32_t skip_prim, Hit& best,
-                                             Stack& st, uint32_t& nvis, uint32_t& ntri) {
+                                             Stack& st, uint32_t& nvis, uint32_t& ntri, int base = 0) {
   uint32_t cur = root;
   bool found = false;
   while (true) {
@@ -222,7 +223,7 @@ __host__ __device__ inline bool traverse_bvh(const BVHNode* __restrict__ nodes, 
     }
     // pop the next entry that can still hold a closer hit
     cur = kEmpty;
-    while (!st.empty()) {
+    while (st.size() > base) {
       float k;
       uint32_t q = st.pop(k);
       if (k <= fminf(best.t, tmax)) {
@@ -231,6 +232,111 @@ __host__ __device__ inline bool traverse_bvh(const BVHNode* __restrict__ nodes, 
       }
     }
     if (cur == kEmpty) break;
+  }
+  return found;
+}
+
+// World -> object transform of a ray, in the fixed FP32 order
+// o'_r = ((w_r0 ox + w_r1 oy) + w_r2 oz) + w_r3,  d'_r = (w_r0 dx + w_r1 dy) + w_r2 dz.
+__host__ __device__ inline RayPre ray_to_object(const float* w, float ox, float oy, float oz, float dx, float dy,
+                                                float dz) {
+#pragma clang fp contract(off)
+  float o[3], d[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float* q = w + 4 * k;
+    o[k] = ((q[0] * ox + q[1] * oy) + q[2] * oz) + q[3];
+    d[k] = (q[0] * dx + q[1] * dy) + q[2] * dz;
+  }
+  return ray_prepare(o[0], o[1], o[2], d[0], d[1], d[2]);
+}
+
+// Two-level walk: a top-level BVH4 over instance world boxes whose leaves
+// list instance ids; at each instance the ray moves to object space and the
+// mesh's BVH is walked on top of the same stack.  t values are compared in
+// each instance's object space, as the single-precision definition does.
+template <bool ANY, bool COUNT, class Stack>
+__host__ __device__ inline bool traverse_two_level(const BVHNode* __restrict__ tlas,
+                                                   const uint32_t* __restrict__ tlas_items,
+                                                   const InstRec* __restrict__ insts,
+                                                   const BVHNode* __restrict__ nodes,
+                                                   const TriRec* __restrict__ tris, const RayPre& rw, float tmin,
+                                                   float tmax, uint32_t skip_inst, uint32_t skip_prim, Hit& best,
+                                                   Stack& st, uint32_t& nvis, uint32_t& ntri) {
+  uint32_t cur = 0;
+  bool found = false;
+  const int base = st.size();
+  while (true) {
+    if (cur != kEmpty && !ref_is_leaf(cur)) {
+      const BVHNode n = tlas[cur];
+      if (COUNT) nvis++;
+      float tn[4];
+      float tcur = fminf(best.t, tmax);
+      uint32_t m = node_slabs(n, rw, tmin, tcur, tn);
+      float k0 = (m & 1u) ? tn[0] : INFINITY, k1 = (m & 2u) ? tn[1] : INFINITY;
+      float k2 = (m & 4u) ? tn[2] : INFINITY, k3 = (m & 8u) ? tn[3] : INFINITY;
+      uint32_t r0 = (m & 1u) ? n.child[0] : kEmpty, r1 = (m & 2u) ? n.child[1] : kEmpty;
+      uint32_t r2 = (m & 4u) ? n.child[2] : kEmpty, r3 = (m & 8u) ? n.child[3] : kEmpty;
+      cswap(k0, r0, k1, r1);
+      cswap(k2, r2, k3, r3);
+      cswap(k0, r0, k2, r2);
+      cswap(k1, r1, k3, r3);
+      cswap(k1, r1, k2, r2);
+      if (r3 != kEmpty) st.push(r3, k3);
+      if (r2 != kEmpty) st.push(r2, k2);
+      if (r1 != kEmpty) st.push(r1, k1);
+      cur = r0;
+      continue;
+    }
+    if (cur != kEmpty) {
+      uint32_t first = leaf_first(cur), cnt = leaf_count(cur);
+      for (uint32_t j = 0; j < cnt; ++j) {
+        uint32_t inst = tlas_items[first + j];
+        const InstRec& I = insts[inst];
+        RayPre ro = ray_to_object(I.w2o, rw.ox, rw.oy, rw.oz, rw.dx, rw.dy, rw.dz);
+        if (traverse_bvh<ANY, COUNT>(nodes, tris, I.blas_root, ro, tmin, tmax, inst, skip_inst, skip_prim, best,
+                                     st, nvis, ntri, st.size())) {
+          found = true;
+          if (ANY) return true;
+        }
+      }
+    }
+    cur = kEmpty;
+    while (st.size() > base) {
+      float k;
+      uint32_t q = st.pop(k);
+      if (k <= fminf(best.t, tmax)) {
+        cur = q;
+        break;
+      }
+    }
+    if (cur == kEmpty) break;
+  }
+  return found;
+}
+
+// Brute force over every instance and every triangle of its mesh.
+__host__ __device__ inline bool brute_force_two_level(const InstRec* __restrict__ insts, uint32_t n_insts,
+                                                      const TriRec* __restrict__ tris,
+                                                      const uint32_t* __restrict__ mesh_tri_first,
+                                                      const uint32_t* __restrict__ mesh_tri_count, const RayPre& rw,
+                                                      float tmin, float tmax, Hit& best) {
+  bool found = false;
+  for (uint32_t i = 0; i < n_insts; ++i) {
+    const InstRec& I = insts[i];
+    RayPre ro = ray_to_object(I.w2o, rw.ox, rw.oy, rw.oz, rw.dx, rw.dy, rw.dz);
+    uint32_t first = mesh_tri_first[I.mesh], cnt = mesh_tri_count[I.mesh];
+    for (uint32_t k = 0; k < cnt; ++k) {
+      const TriRec tr = tris[first + k];
+      float t, b1, b2;
+      if (!tri_intersect(ro, tr.a, tr.b, tr.c, t, b1, b2)) continue;
+      if (!(t > tmin && t < tmax)) continue;
+      uint32_t prim = f2u(tr.a.w);
+      if (!hit_better(t, i, prim, best)) continue;
+      best.t = t; best.b1 = b1; best.b2 = b2; best.inst = i; best.prim = prim; best.tri = first + k;
+      best.mat = f2u(tr.b.w);
+      found = true;
+    }
   }
   return found;
 }
@@ -266,7 +372,7 @@ struct HostStack {
     ref[sp] = r; key[sp] = k; sp++;
   }
   uint32_t pop(float& k) { --sp; k = key[sp]; return ref[sp]; }
-  bool empty() const { return sp == 0; }
+  int size() const { return sp; }
 };
 
 }  // namespace pt

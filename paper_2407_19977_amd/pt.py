@@ -71,6 +71,8 @@ _SIGS = {
     "pt_reset_stats": (C.c_int, [C.c_void_p]),
     "pt_set_profiling": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "pt_bvh_host_build": (C.c_int, [C.POINTER(pt_mesh), C.POINTER(C.c_void_p)]),
+    "pt_bvh_host_build_instanced": (C.c_int, [C.POINTER(pt_mesh), C.c_int32, C.POINTER(pt_instance), C.c_int32,
+                                              C.POINTER(C.c_void_p)]),
     "pt_bvh_host_info": (C.c_int, [C.c_void_p, C.POINTER(pt_bvh_info)]),
     "pt_bvh_host_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pt_bvh_host_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
@@ -143,9 +145,9 @@ class PtScene:
         self.h = h
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and _lib is not None:
             _lib.pt_scene_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         self.close()
@@ -222,20 +224,30 @@ def scene_from(scene, device: int = 0, stream=None) -> PtScene:
 class HostBvh:
     """pt_bvh_host_*: the BVH4 of one mesh built and walked on the CPU."""
 
-    def __init__(self, mesh):
+    def __init__(self, mesh=None, meshes=None, instances=None):
+        """HostBvh(mesh): one world-space mesh; HostBvh(meshes=..., instances=...): two levels."""
         keep = []
-        arr = _mesh_structs([mesh], keep)
         h = C.c_void_p()
-        _check(_lib.pt_bvh_host_build(arr, C.byref(h)))
+        if instances:
+            arr = _mesh_structs(meshes, keep)
+            ia = (pt_instance * len(instances))()
+            for i, ins in enumerate(instances):
+                ia[i].object_to_world[:] = [float(x) for x in np.asarray(ins.object_to_world, np.float32).reshape(12)]
+                ia[i].mesh = int(ins.mesh)
+                ia[i].material_override = int(ins.material_override)
+            _check(_lib.pt_bvh_host_build_instanced(arr, len(meshes), ia, len(instances), C.byref(h)))
+        else:
+            arr = _mesh_structs([mesh], keep)
+            _check(_lib.pt_bvh_host_build(arr, C.byref(h)))
         self.h = h
         info = pt_bvh_info()
         _check(_lib.pt_bvh_host_info(self.h, C.byref(info)))
         self.info = {k: getattr(info, k) for k, _ in pt_bvh_info._fields_}
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and _lib is not None:
             _lib.pt_bvh_host_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def arrays(self):
         """(nodes uint8 [n,128], tris uint8 [n,48])"""

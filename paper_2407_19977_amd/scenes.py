@@ -376,6 +376,156 @@ def spheres(width=1920, height=1080, spp=64, max_depth=8, seed=0, level=5,
 
 
 # --------------------------------------------------------------------------
+# instanced CAD-like scene (~10.8M instanced triangles)
+# --------------------------------------------------------------------------
+
+def lathe(profile, n_seg: int, closed_loop: bool = False):
+    """Closed surface of revolution about +y from a 2-D profile [(r, y), ...].
+
+    An open profile must start and end on the axis (r = 0): those ends become
+    triangle fans.  A closed loop (e.g. a torus section) wraps around.  Rings
+    share vertices around the seam, so the mesh is watertight.  Triangles are
+    wound with outward normals for a counter-clockwise profile (r increasing
+    along the bottom).
+    """
+    prof = np.asarray(profile, dtype=np.float64)
+    ang = 2.0 * np.pi * np.arange(n_seg) / n_seg
+    ca, sa = np.cos(ang), np.sin(ang)
+    verts, rings = [], []
+    for (r, y) in prof:
+        if r == 0.0 and not closed_loop:
+            rings.append([len(verts)] * n_seg)
+            verts.append((0.0, y, 0.0))
+        else:
+            base = len(verts)
+            verts.extend(zip(r * ca, np.full(n_seg, y), r * sa))
+            rings.append(list(range(base, base + n_seg)))
+    tris = []
+    n_rings = len(rings)
+    last = n_rings if closed_loop else n_rings - 1
+    for i in range(last):
+        a, b = rings[i], rings[(i + 1) % n_rings]
+        for j in range(n_seg):
+            j1 = (j + 1) % n_seg
+            q = (a[j], a[j1], b[j1], b[j])
+            tri1, tri2 = (q[0], q[2], q[1]), (q[0], q[3], q[2])
+            for t in (tri1, tri2):
+                if len({t[0], t[1], t[2]}) == 3:
+                    tris.append(t)
+    return np.asarray(verts, dtype=np.float64), np.asarray(tris, dtype=np.int64)
+
+
+def _arc(cx, cy, rad, a0, a1, n):
+    t = np.linspace(a0, a1, n)
+    return [(cx + rad * np.cos(x), cy + rad * np.sin(x)) for x in t]
+
+
+def bevelled_cylinder(radius, height, bevel, n_seg, n_bevel, n_side):
+    """Cylinder with rounded (bevelled) rims, closed by flat caps."""
+    h = height / 2.0
+    prof = [(0.0, -h)]
+    prof += [(x, -h) for x in np.linspace(0.0, radius - bevel, 4)[1:]]
+    prof += _arc(radius - bevel, -h + bevel, bevel, -np.pi / 2, 0.0, n_bevel)[1:]
+    prof += [(radius, y) for y in np.linspace(-h + bevel, h - bevel, n_side)[1:-1]]
+    prof += _arc(radius - bevel, h - bevel, bevel, 0.0, np.pi / 2, n_bevel)
+    prof += [(x, h) for x in np.linspace(radius - bevel, 0.0, 4)[1:]]
+    return lathe(prof, n_seg)
+
+
+def torus(R, r, n_seg, n_ring):
+    prof = [(R + r * np.cos(a), r * np.sin(a)) for a in 2 * np.pi * np.arange(n_ring) / n_ring]
+    return lathe(prof, n_seg, closed_loop=True)
+
+
+def _quat_to_matrix(q):
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def _shoemake(u1, u2, u3):
+    """Uniform random rotation from three uniforms (Shoemake, Graphics Gems III)."""
+    a, b = np.sqrt(1 - u1), np.sqrt(u1)
+    return _quat_to_matrix((b * np.cos(2 * np.pi * u3), a * np.sin(2 * np.pi * u2),
+                            a * np.cos(2 * np.pi * u2), b * np.sin(2 * np.pi * u3)))
+
+
+def instanced(width=1920, height=1080, spp=256, max_depth=12, seed=0, env_size=(2048, 1024)) -> Scene:
+    """400 instances of 5 closed lathe meshes (bevelled cylinders and tori of
+    about 10k, 17.5k, 25k, 32.5k and 50k triangles, bounding radius <= 1.3)
+    on a jittered 20x20 grid of pitch 2.8, each lifted to y = radius + U[0,2]
+    and rotated uniformly at random: ~10.8M instanced triangles.  A ground
+    plane and four 2x2 quad lights (radiance 20, at y = 12 above (+-8, +-8))
+    are identity instances.
+
+    Materials per instance, labels shuffled 120 / 160 / 120 (PCG64(3) draws):
+    glass (transmission 1, IOR 1.5, roughness 0.02), brushed metal
+    (metalness 1, roughness 0.3, anisotropy 0.7, base_color U[.6,.95]^3),
+    coated plastic (base_color U[.1,.9]^3, roughness 0.4, coat 1 at IOR 1.5,
+    coat roughness 0.05).  Lighting: the sky of spheres() plus the quads.
+    """
+    rng = np.random.Generator(np.random.PCG64(3))
+    objs = [torus(0.9, 0.35, 100, 50),
+            bevelled_cylinder(0.8, 1.6, 0.12, 175, 12, 24),
+            torus(0.85, 0.4, 125, 100),
+            bevelled_cylinder(0.75, 1.8, 0.2, 250, 18, 27),
+            torus(0.9, 0.38, 200, 125)]
+    meshes = []
+    radius = []
+    for v, f in objs:
+        c = 0.5 * (v.min(0) + v.max(0))
+        v = v - c
+        radius.append(float(np.linalg.norm(v, axis=1).max()))
+        meshes.append(Mesh(v.astype(np.float32), f.astype(np.int32), np.zeros(len(f), np.int32)))
+    assert max(radius) <= 1.3
+    labels = np.array([0] * 120 + [1] * 160 + [2] * 120)
+    rng.shuffle(labels)
+    mats, insts = [], []
+    for k in range(400):
+        gx, gz = k % 20, k // 20
+        mesh_id = int(rng.integers(0, 5))
+        jit = rng.uniform(-0.1, 0.1, 2)
+        x = -26.6 + 2.8 * gx + jit[0]
+        z = -26.6 + 2.8 * gz + jit[1]
+        y = radius[mesh_id] + rng.uniform(0.0, 2.0)
+        R = _shoemake(*rng.uniform(size=3))
+        M = np.zeros((3, 4))
+        M[:, :3] = R
+        M[:, 3] = (x, y, z)
+        lab = labels[k]
+        if lab == 0:
+            mats.append(material(base_weight=0.0, transmission_weight=1.0, specular_ior=1.5,
+                                 specular_roughness=0.02))
+        elif lab == 1:
+            mats.append(material(base_color=tuple(rng.uniform(0.6, 0.95, 3)), base_metalness=1.0,
+                                 specular_roughness=0.3, specular_roughness_anisotropy=0.7))
+        else:
+            mats.append(material(base_color=tuple(rng.uniform(0.1, 0.9, 3)), specular_roughness=0.4,
+                                 coat_weight=1.0, coat_ior=1.5, coat_roughness=0.05))
+        insts.append(Instance(M.astype(np.float32), mesh_id, len(mats) - 1))
+    # ground (identity instance)
+    g = _MeshBuilder()
+    g.add_quad([-50, 0, -50], [50, 0, -50], [50, 0, 50], [-50, 0, 50], [0, 1, 0], 0)
+    meshes.append(g.mesh())
+    mats.append(lambert((0.5, 0.5, 0.5)))
+    eye = np.hstack([np.eye(3), np.zeros((3, 1))]).astype(np.float32)
+    insts.append(Instance(eye, 5, len(mats) - 1))
+    # four quad lights facing down (identity instance)
+    lq = _MeshBuilder()
+    for cx in (-8.0, 8.0):
+        for cz in (-8.0, 8.0):
+            lq.add_quad([cx - 1, 12, cz - 1], [cx + 1, 12, cz - 1], [cx + 1, 12, cz + 1], [cx - 1, 12, cz + 1],
+                        [0, -1, 0], 0)
+    meshes.append(lq.mesh())
+    mats.append(material(base_weight=0.0, specular_weight=0.0, emission_luminance=20.0))
+    insts.append(Instance(eye, 6, len(mats) - 1))
+    env = sky_env(*env_size)
+    cam = Camera((0.0, 14.0, 34.0), (0.0, 1.0, 0.0), (0.0, 1.0, 0.0), 40.0, width, height)
+    return Scene("instanced", meshes, insts, np.stack(mats), env, cam, spp, max_depth, seed)
+
+
+# --------------------------------------------------------------------------
 # test scenes with closed-form answers
 # --------------------------------------------------------------------------
 

@@ -51,6 +51,10 @@ def _spheres(P, O):
     return _pair(P, O, "spheres", scenes.spheres)
 
 
+def _instanced(P, O):
+    return _pair(P, O, "instanced", scenes.instanced)
+
+
 def _debug(s, cam, crop, first, spp, depth, seed=0):
     x0, y0, w, h = crop
     per = torch.empty((h, w, spp, 3), dtype=torch.float32, device="cuda:0")
@@ -138,6 +142,47 @@ def test_closest_hit_bit_exact(P, O, which, n, n_cpu):
     _say(f"[trace] {which}: {n_cpu} rays vs the oracle's FP32 brute force")
     ref = os_.closest_f32(rays[sel], n_threads=16)
     assert np.array_equal(a[sel], ref), np.argwhere((a[sel] != ref).any(1))[:5]
+
+
+def test_closest_hit_bit_exact_instanced(P, O):
+    """Two-level hierarchy: 400 rotated instances of 5 meshes + ground + lights."""
+    sc, s, os_ = _instanced(P, O)
+    r = np.random.Generator(np.random.PCG64(21))
+    n = 1 << 14
+    o = np.concatenate([r.uniform((-30, 0, -30), (30, 5, 30), size=(n // 2, 3)),
+                        np.tile(np.array(sc.camera.eye, np.float64), (n // 2, 1))])
+    d = r.normal(size=(n, 3))
+    d[n // 2:] = np.array(sc.camera.look_at) - np.array(sc.camera.eye) + r.normal(size=(n // 2, 3)) * 12.0
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rays = np.zeros((n, 8), np.float32)
+    rays[:, 0:3] = o
+    rays[:, 3] = os_.tmin
+    rays[:, 4:7] = d
+    rays[:, 7] = np.inf
+    _say(f"[trace] instanced: {n} rays, two-level BVH vs GPU brute force")
+    rd = torch.from_numpy(rays).to("cuda:0")
+    h_bvh = torch.empty((n, 6), dtype=torch.int32, device="cuda:0")
+    h_bf = torch.empty_like(h_bvh)
+    s.trace_closest(rd, h_bvh, brute_force=False)
+    s.trace_closest(rd, h_bf, brute_force=True)
+    a = h_bvh.cpu().numpy().view(np.uint32)
+    b = h_bf.cpu().numpy().view(np.uint32)
+    assert a[:, 5].sum() > n // 4
+    assert len(np.unique(a[a[:, 5] == 1, 1])) > 100  # many instances hit
+    assert np.array_equal(a, b), np.argwhere((a != b).any(1))[:5]
+    sel = r.choice(n, 256, replace=False)
+    _say("[trace] instanced: 256 rays vs the oracle's FP32 brute force")
+    ref = os_.closest_f32(rays[sel], n_threads=16)
+    assert np.array_equal(a[sel], ref), np.argwhere((a[sel] != ref).any(1))[:5]
+
+
+@pytest.mark.parametrize("crop,spp", [((936, 460, 48, 48), 4), ((400, 700, 33, 21), 3)])
+def test_instanced_crop_parity(P, O, crop, spp):
+    sc, s, os_ = _instanced(P, O)
+    _say(f"[parity] instanced crop {crop}, {spp} spp, depth 12")
+    g, gs = _debug(s, sc.camera, crop, 0, spp, 12)
+    ref = os_.render(spp, 12, crop=crop, per_sample=True, n_threads=16)
+    _compare(g, gs, ref, 0.98, f"instanced{crop}")
 
 
 # ------------------------------------------------------------ path parity --

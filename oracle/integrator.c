@@ -93,9 +93,12 @@ static int add_finite(double L[3], const double c[3], oracle_stats* st) {
   return 1;
 }
 
-int oracle_trace_path(const oracle_scene* s, const oracle_camera* cam, int32_t px, int32_t py,
-                      int32_t sample, int32_t max_depth, uint64_t seed, const oracle_options* opt,
-                      double rgb[3], uint64_t* sig_out, oracle_stats* st) {
+/* One path.  With rec_x != NULL, every vertex that reaches the scattering
+ * stage records its cache inputs, throughput and the radiance gathered so far
+ * (emission included, next-event estimation of that vertex not yet). */
+static int trace_impl(const oracle_scene* s, const oracle_camera* cam, int32_t px, int32_t py, int32_t sample,
+                      int32_t max_depth, uint64_t seed, const oracle_options* opt, double rgb[3], uint64_t* sig_out,
+                      oracle_stats* st, double* rec_x, double* rec_L, double* rec_beta, int32_t* rec_n) {
   int est = opt ? opt->estimator : ORACLE_MIS;
   int rr_on = opt ? opt->russian_roulette : 1;
   int verbose = opt ? opt->verbose : 0;
@@ -191,6 +194,26 @@ int oracle_trace_path(const oracle_scene* s, const oracle_camera* cam, int32_t p
     v3 t, bt;
     make_frame(I, n, &t, &bt);
     v3 wo = V(vdot(wo_w, t), vdot(wo_w, bt), vdot(wo_w, n));
+    if (opt && opt->nrc_weights && b == opt->nrc_bounce) {
+      /* the path ends in the radiance cache: outgoing radiance without emission */
+      double x[12], y[3];
+      onrc_inputs(s, p, wo_w, n, mat, x);
+      oracle_nrc_forward(opt->nrc_weights, x, opt->nrc_bf16, y);
+      double c[3] = {beta[0] * (y[0] > 0.0 ? y[0] : 0.0), beta[1] * (y[1] > 0.0 ? y[1] : 0.0),
+                     beta[2] * (y[2] > 0.0 ? y[2] : 0.0)};
+      add_finite(L, c, st);
+      sig_word(&sig, 6);
+      sig_word(&sig, 4);
+      break;
+    }
+    if (rec_x) {
+      onrc_inputs(s, p, wo_w, n, mat, rec_x + 12 * (*rec_n));
+      for (int c = 0; c < 3; ++c) {
+        rec_L[3 * (*rec_n) + c] = L[c];
+        rec_beta[3 * (*rec_n) + c] = beta[c];
+      }
+      (*rec_n)++;
+    }
     obsdf B;
     obsdf_setup(mat, entering, wo.z, &B);
     if (wo.z <= 0.0) B.absorbed = 1;
@@ -275,6 +298,41 @@ int oracle_trace_path(const oracle_scene* s, const oracle_camera* cam, int32_t p
   rgb[0] = L[0]; rgb[1] = L[1]; rgb[2] = L[2];
   if (sig_out) *sig_out = sig;
   return 0;
+}
+
+int oracle_trace_path(const oracle_scene* s, const oracle_camera* cam, int32_t px, int32_t py,
+                      int32_t sample, int32_t max_depth, uint64_t seed, const oracle_options* opt,
+                      double rgb[3], uint64_t* sig_out, oracle_stats* st) {
+  return trace_impl(s, cam, px, py, sample, max_depth, seed, opt, rgb, sig_out, st, NULL, NULL, NULL, NULL);
+}
+
+int oracle_training_records(const oracle_scene* s, const oracle_camera* cam, int32_t px, int32_t py,
+                            int32_t sample, int32_t max_depth, uint64_t seed, double* inputs, double* targets,
+                            int32_t* n) {
+  if (!s || !cam || !inputs || !targets || !n || max_depth < 0 || max_depth > 1024) return -1;
+  double rgb[3];
+  double* L = (double*)malloc(sizeof(double) * 3 * (size_t)(max_depth + 1));
+  double* B = (double*)malloc(sizeof(double) * 3 * (size_t)(max_depth + 1));
+  int32_t k = 0;
+  int rc = trace_impl(s, cam, px, py, sample, max_depth, seed, NULL, rgb, NULL, NULL, inputs, L, B, &k);
+  int32_t m = 0;
+  for (int32_t i = 0; rc == 0 && i < k; ++i) {
+    if (!(B[3 * i] != 0.0 && B[3 * i + 1] != 0.0 && B[3 * i + 2] != 0.0)) continue;
+    double tg[3];
+    int ok = 1;
+    for (int c = 0; c < 3; ++c) {
+      tg[c] = (rgb[c] - L[3 * i + c]) / B[3 * i + c];
+      if (!isfinite(tg[c])) ok = 0;
+    }
+    if (!ok) continue;
+    if (m != i) memmove(inputs + 12 * m, inputs + 12 * i, sizeof(double) * 12);
+    for (int c = 0; c < 3; ++c) targets[3 * m + c] = tg[c];
+    m++;
+  }
+  free(L);
+  free(B);
+  *n = m;
+  return rc;
 }
 
 /* ------------------------------------------------------------ render -- */

@@ -57,6 +57,9 @@ typedef struct {
   int32_t russian_roulette; /* 1 = on (default), 0 = off */
   int32_t n_threads;     /* <= 0: one */
   int32_t verbose;       /* 1: print every vertex of oracle_trace_path to stderr (debugging) */
+  const double* nrc_weights; /* radiance cache weights (20,672, see nrc.c) or NULL: plain paths */
+  int32_t nrc_bounce;    /* vertex index at which paths end in the cache (2) */
+  int32_t nrc_bf16;      /* 1: evaluate the cache with bfloat16 operands */
 } oracle_options;
 
 typedef struct {
@@ -108,6 +111,18 @@ int oracle_render(const oracle_scene* s, const oracle_camera* cam, int32_t x0, i
                   int32_t w, int32_t h, int32_t first_sample, int32_t n_samples, int32_t max_depth,
                   uint64_t seed, const oracle_options* opt, double* sum_rgb, double* per_sample,
                   uint64_t* sigs, oracle_stats* st);
+
+/* ---- radiance cache (nrc.c) ---- */
+double oracle_bf16_round(double x);
+void oracle_nrc_encode(const double x[12], double f[64]);
+void oracle_nrc_forward(const double* W, const double x[12], int32_t bf16, double y[3]);
+/* Training records of one path (plain tracer): for every vertex k < max_depth
+ * that scatters or absorbs, the 12 cache inputs and the target
+ * (L_end - L_k) / beta_k; vertices with a zero throughput channel are dropped.
+ * inputs [max_depth][12], targets [max_depth][3]; *n receives the count. */
+int oracle_training_records(const oracle_scene* s, const oracle_camera* cam, int32_t px, int32_t py,
+                            int32_t sample, int32_t max_depth, uint64_t seed, double* inputs, double* targets,
+                            int32_t* n);
 
 /* ---- BSDF and light-sampling probes (local shading frame, n = +z) ---- */
 /* mat: 27 floats.  entering: 1 if wo is on the front side of the geometric normal. */

@@ -49,7 +49,8 @@ class OCamera(C.Structure):
 
 class OOptions(C.Structure):
     _fields_ = [("estimator", C.c_int32), ("russian_roulette", C.c_int32), ("n_threads", C.c_int32),
-                ("verbose", C.c_int32)]
+                ("verbose", C.c_int32), ("nrc_weights", C.c_void_p), ("nrc_bounce", C.c_int32),
+                ("nrc_bf16", C.c_int32)]
 
 
 class OStats(C.Structure):
@@ -110,6 +111,14 @@ def _declare(L):
     L.oracle_env_pdf.restype = C.c_double
     L.oracle_env_radiance.argtypes = [C.c_void_p, _dp, _dp]
     L.oracle_env_radiance.restype = None
+    L.oracle_bf16_round.argtypes = [C.c_double]
+    L.oracle_bf16_round.restype = C.c_double
+    L.oracle_nrc_encode.argtypes = [_dp, _dp]
+    L.oracle_nrc_encode.restype = None
+    L.oracle_nrc_forward.argtypes = [_dp, _dp, C.c_int32, _dp]
+    L.oracle_nrc_forward.restype = None
+    L.oracle_training_records.argtypes = [C.c_void_p, C.POINTER(OCamera), C.c_int32, C.c_int32, C.c_int32,
+                                          C.c_int32, C.c_uint64, _dp, _dp, C.POINTER(C.c_int32)]
 
 
 def _d3(x):
@@ -198,6 +207,23 @@ def fresnel_f82(mat, mu):
     return np.array(F[:])
 
 
+def bf16_round(x):
+    return lib().oracle_bf16_round(float(x))
+
+
+def nrc_encode(x12):
+    f = (C.c_double * 64)()
+    lib().oracle_nrc_encode((C.c_double * 12)(*[float(v) for v in x12]), f)
+    return np.array(f[:])
+
+
+def nrc_forward(W, x12, bf16=False):
+    w = np.ascontiguousarray(W, dtype=np.float64)
+    y = (C.c_double * 3)()
+    lib().oracle_nrc_forward(w.ctypes.data_as(_dp), (C.c_double * 12)(*[float(v) for v in x12]), 1 if bf16 else 0, y)
+    return np.array(y[:])
+
+
 def ggx_D(at, ab, m):
     return lib().oracle_ggx_D(at, ab, _d3(m))
 
@@ -256,9 +282,9 @@ class OracleScene:
         self._keep = [mats]
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().oracle_scene_destroy(self.h)
-            self.h = None
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.oracle_scene_destroy(self.h)
+        self.h = None
 
     @property
     def tmin(self):
@@ -286,9 +312,12 @@ class OracleScene:
         assert rc == 0
         return hits
 
-    def trace_path(self, px, py, sample, max_depth, seed=0, estimator=MIS, rr=True, camera=None, verbose=False):
+    def trace_path(self, px, py, sample, max_depth, seed=0, estimator=MIS, rr=True, camera=None, verbose=False,
+                   nrc_weights=None, nrc_bounce=2, nrc_bf16=False):
         cam = camera_struct(camera or self.camera)
-        opt = OOptions(estimator, 1 if rr else 0, 1, 1 if verbose else 0)
+        w = None if nrc_weights is None else np.ascontiguousarray(nrc_weights, dtype=np.float64)
+        opt = OOptions(estimator, 1 if rr else 0, 1, 1 if verbose else 0, None if w is None else w.ctypes.data,
+                       nrc_bounce, 1 if nrc_bf16 else 0)
         rgb = (C.c_double * 3)()
         sig = C.c_uint64()
         st = OStats()
@@ -299,13 +328,15 @@ class OracleScene:
         return np.array(rgb[:]), int(sig.value)
 
     def render(self, spp, max_depth, seed=0, crop=None, first_sample=0, estimator=MIS, rr=True,
-               per_sample=False, n_threads=None, camera=None):
+               per_sample=False, n_threads=None, camera=None, nrc_weights=None, nrc_bounce=2, nrc_bf16=False):
         """Returns dict(sum [h,w,3] f64, mean, per_sample [h,w,n,3], sigs [h,w,n] u64, stats)."""
         cam_py = camera or self.camera
         cam = camera_struct(cam_py)
         x0, y0, w, h = crop if crop is not None else (0, 0, cam_py.width, cam_py.height)
         nt = n_threads or min(16, os.cpu_count() or 1)
-        opt = OOptions(estimator, 1 if rr else 0, nt, 0)
+        wts = None if nrc_weights is None else np.ascontiguousarray(nrc_weights, dtype=np.float64)
+        opt = OOptions(estimator, 1 if rr else 0, nt, 0, None if wts is None else wts.ctypes.data, nrc_bounce,
+                       1 if nrc_bf16 else 0)
         s = np.zeros((h, w, 3), dtype=np.float64)
         ps = np.zeros((h, w, spp, 3), dtype=np.float64) if per_sample else None
         sg = np.zeros((h, w, spp), dtype=np.uint64) if per_sample else None
@@ -318,6 +349,17 @@ class OracleScene:
         return dict(sum=s, mean=s / max(spp, 1), per_sample=ps, sigs=sg,
                     stats=dict(extension_rays=st.extension_rays, shadow_rays=st.shadow_rays,
                                dropped_nonfinite=st.dropped_nonfinite, threads=nt))
+
+    def training_records(self, px, py, sample, max_depth, seed=0, camera=None):
+        """Cache training records of one plain path: (inputs [k,12], targets [k,3])."""
+        cam = camera_struct(camera or self.camera)
+        x = np.zeros((max_depth + 1, 12))
+        t = np.zeros((max_depth + 1, 3))
+        n = C.c_int32()
+        rc = lib().oracle_training_records(self.h, C.byref(cam), px, py, sample, max_depth, seed, _dptr(x), _dptr(t),
+                                           C.byref(n))
+        assert rc == 0
+        return x[:n.value].copy(), t[:n.value].copy()
 
     def sample_light(self, p, usel, u1, u2):
         wl = (C.c_double * 3)()

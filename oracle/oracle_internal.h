@@ -143,6 +143,9 @@ int oclosest(const oracle_scene* s, v3 o, v3 d, double tmin, double tmax, int32_
 int ooccluded(const oracle_scene* s, v3 o, v3 d, double tmin, double tmax, int32_t skip_inst,
               int32_t skip_prim);
 
+/* ---- radiance cache ---- */
+void onrc_inputs(const oracle_scene* s, v3 p, v3 wo, v3 n, const omat* m, double x[12]);
+
 /* ---- random numbers ---- */
 double ouniform(uint64_t seed, uint32_t pixel, uint32_t sample, uint32_t bounce, uint32_t dim);
 

@@ -174,6 +174,86 @@ pt_status pt_reset_stats(pt_scene* scene);
  * of the traversal kernels). */
 pt_status pt_set_profiling(pt_scene* scene, int32_t timing, int32_t counting);
 
+/* ---- radiance cache ----
+ * The paper names neural radiance caching as the way to need fewer samples
+ * (Sec. 6.1, future work).  The cache here is a 64 -> 5 x 64 (ReLU) -> 3
+ * network without biases over a fixed 64-feature encoding of 12 vertex
+ * inputs (position in the scene box, outgoing direction and shading normal
+ * as spherical pairs, specular roughness, diffuse albedo, specular
+ * luminance), bfloat16 operands with FP32 sums, trained online with Adam
+ * on the relative L2 loss (y - t)^2 / (y^2 + 0.01) (denominator held
+ * constant).  Weights: W0..W4 (64 x 64) then W5 (3 x 64), row-major
+ * [out][in], 20,672 floats.
+ *
+ * With the cache configured, pt_render / pt_accumulate run every sample
+ * pass as one frame: the pass renders with the cache (once it has weights:
+ * set by pt_nrc_set_weights or learnt in an earlier frame), paths that reach
+ * vertex query_bounce below max_depth add beta * max(cache, 0) there and
+ * stop; then train_paths training paths (plain paths, sample index
+ * 2^31 + frame, pixels (k * floor(WH / train_paths) + o_frame) mod WH)
+ * record (inputs, (L_end - L_k) / beta_k) at their vertices, and
+ * steps_per_frame Adam steps run on batches of batch_size records drawn
+ * with replacement by Philox (see pt_nrc_train). */
+typedef struct pt_radiance_cache_config {
+  int32_t query_bounce;    /* vertex at which sampling paths end in the cache, >= 0 (2 by default) */
+  int32_t train_paths;     /* training paths per frame, [1, 2^24] (65536) */
+  int32_t batch_size;      /* records per Adam step, [1, 2^22] (16384) */
+  int32_t steps_per_frame; /* Adam steps per frame, [0, 64] (4) */
+  float learning_rate;     /* > 0 (1e-3) */
+  float beta1, beta2;      /* in [0, 1) (0.9, 0.99) */
+  float epsilon;           /* > 0 (1e-8) */
+  uint64_t init_seed;      /* Philox key of the He-uniform initial weights */
+} pt_radiance_cache_config;
+
+/* Configure (cfg != NULL) or switch off (cfg == NULL) the cache.  Weights
+ * start He-uniform: weight k of layer l is (2u - 1) sqrt(6/64), u the
+ * Philox uniform at counter (k, l, 0x4E5243, 0) under init_seed; Adam
+ * moments and step count start at zero; rendering does not use the cache
+ * until it has been trained or given weights.  Errors: INVALID_ARG for a
+ * field out of range, DEVICE. */
+pt_status pt_set_radiance_cache(pt_scene* scene, const pt_radiance_cache_config* cfg);
+
+/* Replace the weights (device, 20,672 floats, copied), reset the Adam state
+ * and let rendering use the cache.  Errors: STATE if not configured,
+ * INVALID_ARG if weights == NULL or n != 20672. */
+pt_status pt_nrc_set_weights(pt_scene* scene, const float* weights, int64_t n);
+
+/* Copy the FP32 master weights and the Adam moments (device, 20,672 floats
+ * each; any pointer may be NULL) and the number of Adam steps taken. */
+pt_status pt_nrc_get_weights(pt_scene* scene, float* weights, float* adam_m, float* adam_v, int64_t* step);
+
+/* Cache outputs of n inputs: inputs (device, [n][12] float) -> outputs
+ * (device, [n][3] float, unclamped).  The same kernel code answers the
+ * queries of the sampling passes. */
+pt_status pt_nrc_forward(pt_scene* scene, const float* inputs, int64_t n, float* outputs);
+
+/* Gradient of the mean loss over n samples (device inputs [n][12], targets
+ * [n][3]) with respect to the 20,672 weights, written to grad (device);
+ * loss (host, may be NULL) receives the mean loss.  No weights change.
+ * The sums over samples run in a fixed order, so repeated calls agree bit
+ * for bit.  Errors: INVALID_ARG for n outside [1, 2^22]. */
+pt_status pt_nrc_gradient(pt_scene* scene, const float* inputs, const float* targets, int32_t n, float* grad,
+                          double* loss);
+
+/* One frame's training on n given records (device inputs [n][12], targets
+ * [n][3]): steps_per_frame Adam steps; the batch of step s has batch_size
+ * samples, sample j taking record floor(m * n / 2^24) with m the top 24 bits
+ * of Philox word s mod 4 at counter (j, 2^31 + frame, 0x4E5253, s / 4) under
+ * seed.  mean_loss (host, may be NULL) receives the mean of the steps'
+ * losses (before each update).  Used by the frame loop on the records of
+ * the frame's training paths. */
+pt_status pt_nrc_train(pt_scene* scene, const float* inputs, const float* targets, int32_t n, int32_t frame,
+                       uint64_t seed, double* mean_loss);
+
+/* Trace the training paths of a frame and return their records, path by path
+ * in vertex order: inputs (device, [capacity][12]), targets (device,
+ * [capacity][3]), path_offsets (device, [train_paths] uint32, first record of
+ * each path, or NULL); *n_records receives the total, of which
+ * min(total, capacity) are written.  No weights change. */
+pt_status pt_nrc_training_records(pt_scene* scene, const pt_camera* camera, int32_t frame, int32_t max_depth,
+                                  uint64_t seed, float* inputs, float* targets, uint32_t* path_offsets,
+                                  int64_t capacity, int64_t* n_records);
+
 /* ---- host-only BVH access (no device needed) ---- */
 typedef struct pt_bvh_host pt_bvh_host;
 typedef struct pt_bvh_info {

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "pt_internal.h"
+#include "pt_nrc.h"
 #include "pt_trace.h"
 
 using namespace pt;
@@ -127,6 +128,21 @@ struct pt_scene {
   int64_t launches_extend = 0;
   int64_t samples = 0;
   std::vector<hipEvent_t> events;
+  // scene box (radiance-cache position input)
+  float box_lo[3] = {0.0f, 0.0f, 0.0f}, box_inv[3] = {0.0f, 0.0f, 0.0f};
+  // radiance cache
+  bool nrc_on = false;     // configured
+  bool nrc_ready = false;  // weights set or trained: sampling passes end paths in the cache
+  pt_radiance_cache_config nrc_cfg;
+  int64_t nrc_step = 0;    // Adam steps taken
+  DevBuf nrc_w, nrc_m, nrc_v, nrc_fwd, nrc_bwd;  // FP32 master weights, Adam moments, bf16 fragments
+  DevBuf nrc_q, q_nrc;                           // per-slot query records, query list
+  int64_t nrc_q_cap = 0;
+  DevBuf nrc_rec, nrc_off, nrc_n, nrc_X, nrc_T;  // training records, compaction
+  int64_t nrc_rec_cap = 0;
+  DevBuf nrc_Xb, nrc_Tb, nrc_a, nrc_g, nrc_loss, nrc_dw;  // one training step's workspace
+  int64_t nrc_ws_npad = 0;
+  int nrc_ws_split = 0;
 };
 
 namespace {
@@ -139,6 +155,15 @@ pt_status check_scene(pt_scene* s) {
 pt_status set_device(pt_scene* s) {
   PT_HIP(hipSetDevice(s->device));
   return PT_OK;
+}
+
+// Scene box from exact vertex bounds; an axis of zero extent maps to 0.
+void set_box(pt_scene* s, const double lo[3], const double hi[3]) {
+  for (int k = 0; k < 3; ++k) {
+    double e = hi[k] - lo[k];
+    s->box_lo[k] = (float)lo[k];
+    s->box_inv[k] = e > 0.0 ? (float)(1.0 / e) : 0.0f;
+  }
 }
 
 bool mat_emits(const pt_openpbr_material& m) {
@@ -338,6 +363,10 @@ SceneDev scene_dev(pt_scene* s, int grid_trace) {
   S.light_map = s->light_map.as<int32_t>();
   S.mesh_tri_first = s->mesh_tri_first.as<uint32_t>();
   S.mesh_tri_count = s->mesh_tri_count.as<uint32_t>();
+  for (int k = 0; k < 3; ++k) {
+    S.box_lo[k] = s->box_lo[k];
+    S.box_inv[k] = s->box_inv[k];
+  }
   return S;
 }
 
@@ -436,6 +465,18 @@ pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h,
   A.count = s->counting;
   A.two_level = s->two_level;
   A.class_mask = s->class_mask | (1u << kClsMiss);
+  A.nrc_bounce = -1;
+  if (s->nrc_on && s->nrc_ready) {
+    if (N > s->nrc_q_cap) {
+      PT_HIP(s->nrc_q.alloc((size_t)N * kNrcQueryFloats * sizeof(float)));
+      PT_HIP(s->q_nrc.alloc((size_t)N * sizeof(uint32_t)));
+      s->nrc_q_cap = N;
+    }
+    A.nrc_bounce = s->nrc_cfg.query_bounce;
+    A.nrc_fwd = s->nrc_fwd.as<uint4>();
+    P.nrc_q = s->nrc_q.as<float>();
+    P.q_nrc = s->q_nrc.as<uint32_t>();
+  }
   int nev = 2 * (max_depth + 1) + 2;
   if (s->timing) {
     while ((int)s->events.size() < nev) {
@@ -464,6 +505,183 @@ pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h,
     }
   }
   s->samples += (int64_t)n * N;
+  return PT_OK;
+}
+
+// ------------------------------------------------------------ radiance cache
+// He-uniform initial weights: weight k of layer l is (2u - 1) sqrt(6 / 64),
+// u the Philox uniform at counter (k, l, 0x4E5243, 0) under the key init_seed.
+void nrc_init_weights(uint64_t seed, std::vector<float>& w) {
+  w.assign(kNrcParams, 0.0f);
+  const double scale = std::sqrt(6.0 / 64.0);
+  int off = 0;
+  for (int l = 0; l < 6; ++l) {
+    int n = l < 5 ? 4096 : 3 * 64;
+    for (int k = 0; k < n; ++k) {
+      U4 r = philox((uint32_t)k, (uint32_t)l, 0x4E5243u, 0u, (uint32_t)seed, (uint32_t)(seed >> 32));
+      double u = (double)(r.x >> 8) * (1.0 / 16777216.0);
+      w[(size_t)(off + k)] = (float)((2.0 * u - 1.0) * scale);
+    }
+    off += n;
+  }
+}
+
+// Split of one training step's weight-gradient GEMM over sample ranges.
+void nrc_split(int64_t N, int& n_split, int64_t& npad) {
+  n_split = (int)std::min<int64_t>(64, std::max<int64_t>(1, (N + 1023) / 1024));
+  int64_t q = 32 * (int64_t)n_split;
+  npad = (N + q - 1) / q * q;
+}
+
+pt_status nrc_ensure_ws(pt_scene* s, int64_t N) {
+  int split;
+  int64_t npad;
+  nrc_split(N, split, npad);
+  if (npad > s->nrc_ws_npad) {
+    size_t store = (size_t)6 * 64 * (size_t)npad * sizeof(uint16_t);
+    PT_HIP(s->nrc_a.alloc(store));
+    PT_HIP(s->nrc_g.alloc(store));
+    PT_HIP(s->nrc_Xb.alloc((size_t)npad * 12 * sizeof(float)));
+    PT_HIP(s->nrc_Tb.alloc((size_t)npad * 3 * sizeof(float)));
+    s->nrc_ws_npad = npad;
+  }
+  if (split > s->nrc_ws_split) {
+    PT_HIP(s->nrc_dw.alloc((size_t)split * kNrcParams * sizeof(float)));
+    s->nrc_ws_split = split;
+  }
+  if (!s->nrc_loss.p) PT_HIP(s->nrc_loss.alloc(kNrcFbGrid * sizeof(float)));
+  return PT_OK;
+}
+
+// One step on N samples X [N][12], T [N][3] (device): gradient into the
+// partial buffers, then Adam (apply) or just the summed gradient (grad_out).
+pt_status nrc_step(pt_scene* s, const float* X, const float* T, int64_t N, float* grad_out, bool apply,
+                   int* grid_used) {
+  pt_status r = nrc_ensure_ws(s, N);
+  if (r) return r;
+  int split;
+  int64_t npad;
+  nrc_split(N, split, npad);
+  int64_t groups = npad / 16;
+  int grid_fb = (int)std::min<int64_t>(kNrcFbGrid, (groups + 3) / 4);
+  if (grid_used) *grid_used = grid_fb;
+  PT_HIP(nrc_launch_train(X, T, (int)N, (int)npad, split, s->nrc_fwd.as<uint4>(), s->nrc_bwd.as<uint4>(),
+                          s->nrc_a.as<uint16_t>(), s->nrc_g.as<uint16_t>(), s->nrc_loss.as<float>(), grid_fb,
+                          s->nrc_dw.as<float>(), s->stream));
+  const pt_radiance_cache_config& c = s->nrc_cfg;
+  if (apply) ++s->nrc_step;
+  PT_HIP(nrc_launch_adam(s->nrc_w.as<float>(), s->nrc_m.as<float>(), s->nrc_v.as<float>(), s->nrc_dw.as<float>(),
+                         split, grad_out, c.learning_rate, c.beta1, c.beta2, c.epsilon,
+                         (int)std::max<int64_t>(1, s->nrc_step), apply ? 1 : 0, s->stream));
+  if (apply) PT_HIP(nrc_launch_pack(s->nrc_w.as<float>(), s->nrc_fwd.as<uint4>(), s->nrc_bwd.as<uint4>(), s->stream));
+  return PT_OK;
+}
+
+pt_status nrc_read_loss(pt_scene* s, int grid, int64_t N, double* loss) {
+  std::vector<float> part((size_t)grid);
+  PT_HIP(hipMemcpyAsync(part.data(), s->nrc_loss.p, (size_t)grid * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+  PT_HIP(hipStreamSynchronize(s->stream));
+  double sum = 0.0;
+  for (float v : part) sum += v;
+  *loss = sum / (3.0 * (double)N);
+  return PT_OK;
+}
+
+// Training paths of a frame: path k starts at pixel (k * stride + o_f) mod WH,
+// stride = max(1, floor(WH / paths)), o_f = floor(m * WH / 2^24) with m the top
+// 24 bits of Philox word 0 at counter (0, 2^31 + frame, 0x4F4646, 0); sample
+// index 2^31 + frame.  Each path records (inputs, radiance so far, throughput)
+// at its vertices below max_depth; the targets are compacted path by path.
+pt_status nrc_trace_training(pt_scene* s, const CamDev& C, uint32_t frame, int max_depth, uint64_t seed,
+                             uint32_t* n_records) {
+  const int64_t n = s->nrc_cfg.train_paths;
+  pt_status r = ensure_paths(s, n);
+  if (r) return r;
+  if ((r = ensure_counters(s))) return r;
+  int grid = grid_for(n), grid_trace = grid_for(n);
+  if ((r = ensure_spill(s, grid_trace))) return r;
+  const int depth = std::max(1, max_depth);
+  if (n * depth > s->nrc_rec_cap) {
+    PT_HIP(s->nrc_rec.alloc((size_t)n * depth * kNrcRecFloats * sizeof(float)));
+    PT_HIP(s->nrc_X.alloc((size_t)n * depth * 12 * sizeof(float)));
+    PT_HIP(s->nrc_T.alloc((size_t)n * depth * 3 * sizeof(float)));
+    PT_HIP(s->nrc_off.alloc((size_t)n * sizeof(uint32_t)));
+    if (!s->nrc_n.p) PT_HIP(s->nrc_n.alloc(sizeof(uint32_t)));
+    s->nrc_rec_cap = n * depth;
+  }
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const uint64_t WH = (uint64_t)C.W * (uint64_t)C.H;
+  SceneDev S = scene_dev(s, grid_trace);
+  PathsDev P = paths_dev(s, n, 0, 0, 1);
+  P.pix_total = (uint32_t)WH;
+  P.pix_stride = (uint32_t)std::max<uint64_t>(1, WH / (uint64_t)n);
+  U4 u = philox(0u, 0x80000000u + frame, 0x4F4646u, 0u, k0, k1);
+  P.pix_off = (uint32_t)(((uint64_t)(u.x >> 8) * WH) >> 24);
+  P.rec = s->nrc_rec.as<float>();
+  P.rec_depth = max_depth;
+  PassArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.sample = 0x80000000u + frame;
+  A.k0 = k0;
+  A.k1 = k1;
+  A.max_depth = max_depth;
+  A.grid = grid;
+  A.grid_trace = grid_trace;
+  A.two_level = s->two_level;
+  A.class_mask = s->class_mask | (1u << kClsMiss);
+  A.nrc_bounce = -1;
+  PT_HIP(launch_pass(S, P, C, A, s->stream));
+  PT_HIP(nrc_launch_targets(P, (int)n, s->nrc_off.as<uint32_t>(), s->nrc_X.as<float>(), s->nrc_T.as<float>(),
+                            s->nrc_n.as<uint32_t>(), s->stream));
+  PT_HIP(hipMemcpyAsync(n_records, s->nrc_n.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
+  PT_HIP(hipStreamSynchronize(s->stream));
+  return PT_OK;
+}
+
+// The frame's Adam steps on batches drawn with replacement from n records X_all, T_all.
+pt_status nrc_train_records(pt_scene* s, const float* X_all, const float* T_all, const uint32_t* n_dev,
+                            uint32_t frame, uint64_t seed, double* mean_loss) {
+  const pt_radiance_cache_config& c = s->nrc_cfg;
+  const int B = c.batch_size;
+  pt_status r = nrc_ensure_ws(s, B);
+  if (r) return r;
+  double lsum = 0.0;
+  for (int step = 0; step < c.steps_per_frame; ++step) {
+    PT_HIP(nrc_launch_gather(X_all, T_all, n_dev, B, frame, step, (uint32_t)seed, (uint32_t)(seed >> 32),
+                             s->nrc_Xb.as<float>(), s->nrc_Tb.as<float>(), s->stream));
+    int grid = 0;
+    if ((r = nrc_step(s, s->nrc_Xb.as<float>(), s->nrc_Tb.as<float>(), B, nullptr, true, &grid))) return r;
+    if (mean_loss) {
+      double l = 0.0;
+      if ((r = nrc_read_loss(s, grid, B, &l))) return r;
+      lsum += l;
+    }
+  }
+  if (mean_loss) *mean_loss = c.steps_per_frame > 0 ? lsum / c.steps_per_frame : 0.0;
+  if (c.steps_per_frame > 0) s->nrc_ready = true;
+  return PT_OK;
+}
+
+pt_status nrc_train_frame(pt_scene* s, const CamDev& C, uint32_t frame, int max_depth, uint64_t seed) {
+  uint32_t n = 0;
+  pt_status r = nrc_trace_training(s, C, frame, max_depth, seed, &n);
+  if (r) return r;
+  if (n == 0) return PT_OK;  // nothing to learn from (e.g. every training path missed)
+  return nrc_train_records(s, s->nrc_X.as<float>(), s->nrc_T.as<float>(), s->nrc_n.as<uint32_t>(), frame, seed,
+                           nullptr);
+}
+
+// Sampling passes of the whole image into the FP64 sums; with the radiance
+// cache on, every pass is one frame: render, then train on that frame.
+pt_status render_samples(pt_scene* s, const CamDev& C, int first, int n, int max_depth, uint64_t seed) {
+  if (!s->nrc_on)
+    return run_passes(s, C, 0, 0, C.W, C.H, first, n, max_depth, seed, s->sum.as<double>(), nullptr, nullptr, n);
+  for (int k = 0; k < n; ++k) {
+    pt_status r = run_passes(s, C, 0, 0, C.W, C.H, first + k, 1, max_depth, seed, s->sum.as<double>(), nullptr,
+                             nullptr, 1);
+    if (r) return r;
+    if ((r = nrc_train_frame(s, C, (uint32_t)(first + k), max_depth, seed))) return r;
+  }
   return PT_OK;
 }
 
@@ -552,6 +770,13 @@ MatRec make_matrec(const pt_openpbr_material& m) {
   else if (!hasC && !hasM) cls = kClsGlass;
   else cls = kClsGeneral;
   r.cls = cls;
+  r.spec_rough = m.specular_roughness;
+  {  // exact unpolarised dielectric reflectance at normal incidence, c = 1
+    double eta = m.specular_ior, c = 1.0;
+    double g = std::sqrt(eta * eta - 1.0 + c * c);
+    double a = (g - c) / (g + c), b = (c * (g + c) - 1.0) / (c * (g - c) + 1.0);
+    r.f0_diel = (float)(0.5 * a * a * (1.0 + b * b));
+  }
   return r;
 }
 
@@ -584,6 +809,7 @@ struct TwoLevel {
   float tmin = 0.0f;
   int depth = 0;
   int32_t max_mat = -1;
+  double box_lo[3], box_hi[3];
 };
 
 pt_status build_two_level_host(const pt_mesh* meshes, int32_t n_meshes, const pt_instance* instances,
@@ -682,6 +908,10 @@ pt_status build_two_level_host(const pt_mesh* meshes, int32_t n_meshes, const pt
   for (int i = 0; i < n_instances; ++i) std::memcpy(&items[(size_t)i], &top.tris[(size_t)i].a.w, 4);
   double dx = shi[0] - slo[0], dy = shi[1] - slo[1], dz = shi[2] - slo[2];
   out.tmin = (float)(1e-5 * std::sqrt(dx * dx + dy * dy + dz * dz));
+  for (int k = 0; k < 3; ++k) {
+    out.box_lo[k] = slo[k];
+    out.box_hi[k] = shi[k];
+  }
   out.depth = top.depth + blas_depth;
   out.max_mat = max_mat;
   out.nodes.swap(nodes);
@@ -712,6 +942,7 @@ pt_status build_two_level(pt_scene* s, const pt_mesh* meshes, int32_t n_meshes, 
   PT_HIP(upload(s->mesh_tri_count, T.tcount.data(), T.tcount.size() * sizeof(uint32_t), s->stream));
   PT_HIP(hipStreamSynchronize(s->stream));
   s->tmin = T.tmin;
+  set_box(s, T.box_lo, T.box_hi);
   s->n_tris = (uint32_t)T.tris.size();
   s->bvh_depth = T.depth;
   s->max_mat_id = T.max_mat;
@@ -820,6 +1051,15 @@ pt_status pt_build_bvh(pt_scene* s, const pt_mesh* meshes, int32_t n_meshes, con
   PT_HIP(hipStreamSynchronize(s->stream));
   double dx = (double)bvh.hi[0] - bvh.lo[0], dy = (double)bvh.hi[1] - bvh.lo[1], dz = (double)bvh.hi[2] - bvh.lo[2];
   s->tmin = (float)(1e-5 * std::sqrt(dx * dx + dy * dy + dz * dz));
+  {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (size_t q = 0; q < verts.size(); q += 3)
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = std::min(lo[k], (double)verts[q + k]);
+        hi[k] = std::max(hi[k], (double)verts[q + k]);
+      }
+    set_box(s, lo, hi);
+  }
   s->n_tris = (uint32_t)total;
   s->bvh_depth = bvh.depth;
   s->max_mat_id = max_mat;
@@ -949,8 +1189,7 @@ pt_status pt_accumulate(pt_scene* s, const pt_camera* cam, int32_t first, int32_
   if ((r = set_device(s))) return r;
   if ((r = ready_to_render(s))) return r;
   if ((r = ensure_accum(s, C.W, C.H))) return r;
-  if ((r = run_passes(s, C, 0, 0, C.W, C.H, first, n, max_depth, seed, s->sum.as<double>(), nullptr, nullptr, n)))
-    return r;
+  if ((r = render_samples(s, C, first, n, max_depth, seed))) return r;
   s->acc_samples += n;
   return sync(s);
 }
@@ -979,8 +1218,7 @@ pt_status pt_render(pt_scene* s, const pt_camera* cam, int32_t spp, int32_t max_
   if ((r = ensure_accum(s, C.W, C.H))) return r;
   PT_HIP(launch_zero_f64(s->sum.as<double>(), (int64_t)C.W * C.H * 3, s->stream));
   s->acc_samples = 0;
-  if ((r = run_passes(s, C, 0, 0, C.W, C.H, 0, spp, max_depth, seed, s->sum.as<double>(), nullptr, nullptr, spp)))
-    return r;
+  if ((r = render_samples(s, C, 0, spp, max_depth, seed))) return r;
   s->acc_samples = spp;
   PT_HIP(launch_resolve(s->sum.as<double>(), out, (int64_t)C.W * C.H * 3, 1.0 / (double)spp, s->stream));
   return sync(s);
@@ -1001,6 +1239,142 @@ pt_status pt_render_debug(pt_scene* s, const pt_camera* cam, int32_t x0, int32_t
   if ((r = set_device(s))) return r;
   if ((r = ready_to_render(s))) return r;
   if ((r = run_passes(s, C, x0, y0, w, h, first, spp, max_depth, seed, nullptr, per_sample, sig, spp))) return r;
+  return sync(s);
+}
+
+// ------------------------------------------------------------ radiance cache
+pt_status pt_set_radiance_cache(pt_scene* s, const pt_radiance_cache_config* cfg) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (!cfg) {
+    s->nrc_on = false;
+    s->nrc_ready = false;
+    return PT_OK;
+  }
+  const pt_radiance_cache_config& c = *cfg;
+  if (c.query_bounce < 0) return fail(PT_ERR_INVALID_ARG, "query_bounce must be >= 0");
+  if (c.train_paths < 1 || c.train_paths > (1 << 24)) return fail(PT_ERR_INVALID_ARG, "train_paths must be in [1, 2^24]");
+  if (c.batch_size < 1 || c.batch_size > (1 << 22)) return fail(PT_ERR_INVALID_ARG, "batch_size must be in [1, 2^22]");
+  if (c.steps_per_frame < 0 || c.steps_per_frame > 64) return fail(PT_ERR_INVALID_ARG, "steps_per_frame must be in [0, 64]");
+  if (!(c.learning_rate > 0.0f) || !std::isfinite(c.learning_rate)) return fail(PT_ERR_INVALID_ARG, "learning_rate must be > 0");
+  if (!(c.beta1 >= 0.0f && c.beta1 < 1.0f) || !(c.beta2 >= 0.0f && c.beta2 < 1.0f))
+    return fail(PT_ERR_INVALID_ARG, "beta1 and beta2 must be in [0, 1)");
+  if (!(c.epsilon > 0.0f) || !std::isfinite(c.epsilon)) return fail(PT_ERR_INVALID_ARG, "epsilon must be > 0");
+  if ((r = set_device(s))) return r;
+  std::vector<float> w;
+  nrc_init_weights(c.init_seed, w);
+  const size_t bytes = kNrcParams * sizeof(float);
+  PT_HIP(upload(s->nrc_w, w.data(), bytes, s->stream));
+  std::vector<float> zero(kNrcParams, 0.0f);
+  PT_HIP(upload(s->nrc_m, zero.data(), bytes, s->stream));
+  PT_HIP(upload(s->nrc_v, zero.data(), bytes, s->stream));
+  if (!s->nrc_fwd.p) PT_HIP(s->nrc_fwd.alloc(kNrcFwdFrags * 64 * sizeof(uint4)));
+  if (!s->nrc_bwd.p) PT_HIP(s->nrc_bwd.alloc(kNrcBwdFrags * 64 * sizeof(uint4)));
+  PT_HIP(nrc_launch_pack(s->nrc_w.as<float>(), s->nrc_fwd.as<uint4>(), s->nrc_bwd.as<uint4>(), s->stream));
+  s->nrc_cfg = c;
+  s->nrc_step = 0;
+  s->nrc_on = true;
+  s->nrc_ready = false;
+  return sync(s);
+}
+
+pt_status pt_nrc_set_weights(pt_scene* s, const float* weights, int64_t n) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (!s->nrc_on) return fail(PT_ERR_STATE, "pt_set_radiance_cache has not been called");
+  if (!weights || n != kNrcParams) return fail(PT_ERR_INVALID_ARG, "weights must be %d device floats", kNrcParams);
+  if ((r = set_device(s))) return r;
+  PT_HIP(hipMemcpyAsync(s->nrc_w.p, weights, kNrcParams * sizeof(float), hipMemcpyDeviceToDevice, s->stream));
+  std::vector<float> zero(kNrcParams, 0.0f);
+  PT_HIP(hipMemcpyAsync(s->nrc_m.p, zero.data(), kNrcParams * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  PT_HIP(hipMemcpyAsync(s->nrc_v.p, zero.data(), kNrcParams * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  PT_HIP(nrc_launch_pack(s->nrc_w.as<float>(), s->nrc_fwd.as<uint4>(), s->nrc_bwd.as<uint4>(), s->stream));
+  s->nrc_step = 0;
+  s->nrc_ready = true;
+  return sync(s);
+}
+
+pt_status pt_nrc_get_weights(pt_scene* s, float* weights, float* adam_m, float* adam_v, int64_t* step) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (!s->nrc_on) return fail(PT_ERR_STATE, "pt_set_radiance_cache has not been called");
+  if ((r = set_device(s))) return r;
+  const size_t bytes = kNrcParams * sizeof(float);
+  if (weights) PT_HIP(hipMemcpyAsync(weights, s->nrc_w.p, bytes, hipMemcpyDeviceToDevice, s->stream));
+  if (adam_m) PT_HIP(hipMemcpyAsync(adam_m, s->nrc_m.p, bytes, hipMemcpyDeviceToDevice, s->stream));
+  if (adam_v) PT_HIP(hipMemcpyAsync(adam_v, s->nrc_v.p, bytes, hipMemcpyDeviceToDevice, s->stream));
+  if (step) *step = s->nrc_step;
+  return sync(s);
+}
+
+pt_status pt_nrc_forward(pt_scene* s, const float* inputs, int64_t n, float* outputs) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (!s->nrc_on) return fail(PT_ERR_STATE, "pt_set_radiance_cache has not been called");
+  if (n < 0 || n > ((int64_t)1 << 31)) return fail(PT_ERR_INVALID_ARG, "n must be in [0, 2^31]");
+  if (n == 0) return PT_OK;
+  if (!inputs || !outputs) return fail(PT_ERR_INVALID_ARG, "inputs and outputs must be non-NULL");
+  if ((r = set_device(s))) return r;
+  PT_HIP(nrc_launch_forward(inputs, n, s->nrc_fwd.as<uint4>(), outputs, s->stream));
+  return sync(s);
+}
+
+pt_status pt_nrc_gradient(pt_scene* s, const float* inputs, const float* targets, int32_t n, float* grad,
+                          double* loss) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (!s->nrc_on) return fail(PT_ERR_STATE, "pt_set_radiance_cache has not been called");
+  if (n < 1 || n > (1 << 22)) return fail(PT_ERR_INVALID_ARG, "n must be in [1, 2^22]");
+  if (!inputs || !targets || !grad) return fail(PT_ERR_INVALID_ARG, "inputs, targets and grad must be non-NULL");
+  if ((r = set_device(s))) return r;
+  int grid = 0;
+  if ((r = nrc_step(s, inputs, targets, n, grad, false, &grid))) return r;
+  if (loss) return nrc_read_loss(s, grid, n, loss);
+  return sync(s);
+}
+
+pt_status pt_nrc_train(pt_scene* s, const float* inputs, const float* targets, int32_t n, int32_t frame, uint64_t seed,
+                       double* mean_loss) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (!s->nrc_on) return fail(PT_ERR_STATE, "pt_set_radiance_cache has not been called");
+  if (n < 1) return fail(PT_ERR_INVALID_ARG, "n must be >= 1");
+  if (frame < 0) return fail(PT_ERR_INVALID_ARG, "frame must be >= 0");
+  if (!inputs || !targets) return fail(PT_ERR_INVALID_ARG, "inputs and targets must be non-NULL");
+  if ((r = set_device(s))) return r;
+  if (!s->nrc_n.p) PT_HIP(s->nrc_n.alloc(sizeof(uint32_t)));
+  uint32_t nn = (uint32_t)n;
+  PT_HIP(hipMemcpyAsync(s->nrc_n.p, &nn, sizeof(uint32_t), hipMemcpyHostToDevice, s->stream));
+  PT_HIP(hipStreamSynchronize(s->stream));
+  if ((r = nrc_train_records(s, inputs, targets, s->nrc_n.as<uint32_t>(), (uint32_t)frame, seed, mean_loss))) return r;
+  return sync(s);
+}
+
+pt_status pt_nrc_training_records(pt_scene* s, const pt_camera* cam, int32_t frame, int32_t max_depth, uint64_t seed,
+                                  float* inputs, float* targets, uint32_t* path_offsets, int64_t capacity,
+                                  int64_t* n_records) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (!s->nrc_on) return fail(PT_ERR_STATE, "pt_set_radiance_cache has not been called");
+  CamDev C;
+  if ((r = make_camera(cam, C))) return r;
+  if ((r = check_render_args(1, max_depth))) return r;
+  if (frame < 0) return fail(PT_ERR_INVALID_ARG, "frame must be >= 0");
+  if (capacity < 0 || (capacity > 0 && (!inputs || !targets)) || !n_records)
+    return fail(PT_ERR_INVALID_ARG, "bad output buffers");
+  if ((r = set_device(s))) return r;
+  if ((r = ready_to_render(s))) return r;
+  uint32_t n = 0;
+  if ((r = nrc_trace_training(s, C, (uint32_t)frame, max_depth, seed, &n))) return r;
+  int64_t m = std::min<int64_t>(n, capacity);
+  if (m > 0) {
+    PT_HIP(hipMemcpyAsync(inputs, s->nrc_X.p, (size_t)m * 12 * sizeof(float), hipMemcpyDeviceToDevice, s->stream));
+    PT_HIP(hipMemcpyAsync(targets, s->nrc_T.p, (size_t)m * 3 * sizeof(float), hipMemcpyDeviceToDevice, s->stream));
+  }
+  if (path_offsets)
+    PT_HIP(hipMemcpyAsync(path_offsets, s->nrc_off.p, (size_t)s->nrc_cfg.train_paths * sizeof(uint32_t),
+                          hipMemcpyDeviceToDevice, s->stream));
+  *n_records = n;
   return sync(s);
 }
 

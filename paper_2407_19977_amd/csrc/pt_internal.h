@@ -48,6 +48,8 @@ struct SceneDev {
   uint2* spill;              // traversal stack spill, [cap - kLdsStack][grid threads]
   int32_t stack_cap;         // total stack entries per lane
   uint32_t spill_stride;     // grid threads of the traversal kernels
+  float box_lo[3];           // scene box (radiance-cache position input)
+  float box_inv[3];          // 1 / box extent per axis (0 for a flat axis)
 };
 
 // Camera basis computed on the host in double and rounded to float.
@@ -79,6 +81,13 @@ struct PathsDev {
   uint32_t* dbg_tail;  // pending lobe / roulette / end events (debug)
   int32_t n;           // number of path slots
   int32_t x0, y0, w;   // slot -> pixel (x0 + slot % w, y0 + slot / w)
+  // training paths: slot -> pixel index (slot * pix_stride + pix_off) mod pix_total when pix_stride != 0
+  uint32_t pix_stride, pix_off, pix_total;
+  // radiance cache
+  float* nrc_q;        // query record per slot [n][16]: inputs x[12], beta rgb, unused
+  uint32_t* q_nrc;     // slots that queried the cache (count in counts[kCountQuery])
+  float* rec;          // training records [n][rec_depth][20] (nullptr: not a training pass)
+  int32_t rec_depth;
 };
 
 enum {
@@ -93,6 +102,7 @@ enum {
   kNumStats = 8
 };
 constexpr int kCountShadow = 2 + kNumClasses;
+constexpr int kCountQuery = kCountShadow + 1;
 constexpr int kNumCounts = 16;
 
 // ---- kernel launchers (pt_kernels.hip) ----
@@ -107,6 +117,8 @@ struct PassArgs {
   bool two_level;
   uint32_t class_mask;  // material classes present (bit per class)
   hipEvent_t* ext_events;  // 2 per bounce when timing, else nullptr
+  int nrc_bounce;          // vertex at which paths end in the radiance cache, -1: no cache
+  const uint4* nrc_fwd;    // packed forward weight fragments (when nrc_bounce >= 0)
 };
 
 hipError_t launch_pass(const SceneDev& S, const PathsDev& P, const CamDev& C, const PassArgs& A,
@@ -119,5 +131,20 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st);
 hipError_t launch_trace_rays(const SceneDev& S, const float* rays, int64_t n, uint32_t* hits, bool brute,
                              bool two_level, int grid, hipStream_t st);
 int trace_grid_blocks();
+
+// ---- radiance cache (pt_nrc.hip) ----
+hipError_t nrc_launch_pack(const float* w, uint4* fwd, uint4* bwd, hipStream_t st);
+hipError_t nrc_launch_forward(const float* x, int64_t n, const uint4* fwd, float* y, hipStream_t st);
+hipError_t nrc_launch_query(const PathsDev& P, const uint4* fwd, int grid, hipStream_t st);
+hipError_t nrc_launch_train(const float* X, const float* T, int N, int npad, int n_split, const uint4* fwd,
+                            const uint4* bwd, uint16_t* a_store, uint16_t* g_store, float* loss_part, int grid_fb,
+                            float* dw_part, hipStream_t st);
+hipError_t nrc_launch_adam(float* w, float* m, float* v, const float* dw_part, int n_split, float* grad_out, float lr,
+                           float b1, float b2, float eps, int step, int apply, hipStream_t st);
+hipError_t nrc_launch_targets(const PathsDev& P, int n_paths, uint32_t* offsets, float* X, float* T,
+                              uint32_t* n_out, hipStream_t st);
+hipError_t nrc_launch_gather(const float* X_all, const float* T_all, const uint32_t* n_all, int B, uint32_t frame,
+                             int step, uint32_t k0, uint32_t k1, float* Xb, float* Tb, hipStream_t st);
+constexpr int kNrcFbGrid = 256;  // workgroups of the forward+backward kernel
 
 }  // namespace pt

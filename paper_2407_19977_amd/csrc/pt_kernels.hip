@@ -10,7 +10,10 @@
 // reads from the counter array.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "pt_internal.h"
+#include "pt_nrc.h"
 #include "pt_shade.h"
 #include "pt_trace.h"
 
@@ -203,14 +206,21 @@ __device__ inline float pow_heuristic(float a, float b) {
 
 __device__ inline bool finite3(V3 c) { return isfinite(c.x) && isfinite(c.y) && isfinite(c.z); }
 
+// Pixel index (row-major) of a path slot: a tile of the image, or the
+// strided pixel set of the radiance cache's training paths.
+__device__ inline uint32_t slot_pixel(const PathsDev& P, uint32_t slot, uint32_t img_w) {
+  if (P.pix_stride) return (uint32_t)(((uint64_t)slot * P.pix_stride + P.pix_off) % P.pix_total);
+  return (uint32_t)(P.y0 + slot / P.w) * img_w + (uint32_t)(P.x0 + slot % P.w);
+}
+
 // ---------------------------------------------------------------- generate
 template <bool DEBUG>
 __global__ __launch_bounds__(kBlock) void k_generate(PathsDev P, CamDev C, uint32_t sample, uint32_t k0,
                                                      uint32_t k1) {
   int n = P.n;
   for (int slot = blockIdx.x * kBlock + threadIdx.x; slot < n; slot += gridDim.x * kBlock) {
-    int px = P.x0 + slot % P.w, py = P.y0 + slot / P.w;
-    uint32_t pix = (uint32_t)py * (uint32_t)C.W + (uint32_t)px;
+    uint32_t pix = slot_pixel(P, (uint32_t)slot, (uint32_t)C.W);
+    int px = (int)(pix % (uint32_t)C.W), py = (int)(pix / (uint32_t)C.W);
     U4 r = philox(pix, sample, 0u, 0u, k0, k1);
     float fx = (float)px + u01(r.x), fy = (float)py + u01(r.y);
     float x = (2.0f * fx / (float)C.W - 1.0f) * C.tan_half * C.aspect;
@@ -223,8 +233,13 @@ __global__ __launch_bounds__(kBlock) void k_generate(PathsDev P, CamDev C, uint3
     P.flags[slot] = 1u;
     P.q_ray[0][slot] = (uint32_t)slot;
     if (DEBUG) P.sig[slot] = kFnvOffset;
+    if (P.rec)
+      for (int r = 0; r < P.rec_depth; ++r) P.rec[((size_t)slot * P.rec_depth + r) * kNrcRecFloats + 18] = 0.0f;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) P.counts[0] = (uint32_t)n;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    P.counts[0] = (uint32_t)n;
+    P.counts[kCountQuery] = 0u;
+  }
 }
 
 __global__ void k_reset_counts(uint32_t* counts, int next_queue) {
@@ -305,12 +320,13 @@ __global__ __launch_bounds__(kBlock) void k_extend(SceneDev S, PathsDev P, int c
 // ------------------------------------------------------------------- shade
 template <int CLS, bool DEBUG, bool TWO>
 __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b, int max_depth, int next,
-                                                  uint32_t sample, uint32_t k0, uint32_t k1, uint32_t img_w) {
+                                                  uint32_t sample, uint32_t k0, uint32_t k1, uint32_t img_w,
+                                                  int nrc_bounce) {
   const uint32_t count = P.counts[2 + CLS];
   for (uint32_t base = blockIdx.x * kBlock; base < count; base += gridDim.x * kBlock) {
     uint32_t i = base + threadIdx.x;
     bool active = i < count;
-    bool cont = false, shadow = false;
+    bool cont = false, shadow = false, query = false;
     uint32_t slot = 0;
     float4 sh_o = make_float4(0, 0, 0, 0), sh_d = make_float4(0, 0, 0, 0), sh_c = make_float4(0, 0, 0, 0);
     uint32_t sh_inst = 0;
@@ -399,17 +415,37 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b,
         bool pending = false;
         uint32_t nee_id = 0xFFFFFFFFu, nee_out = 3u;
         bool nee_done = false;
+        bool entering = cos_ng > 0.0f;
+        V3 n = entering ? ng : ng * -1.0f;
         if (b == max_depth) {
           end_ev = 1;
+        } else if (b == nrc_bounce) {
+          // the path ends in the radiance cache: the query adds beta * cache(x) after the pass
+          float* qr = P.nrc_q + (size_t)slot * kNrcQueryFloats;
+          nrc_inputs(S.box_lo, S.box_inv, p, wo_w, n, m, qr);
+          qr[12] = beta.x;
+          qr[13] = beta.y;
+          qr[14] = beta.z;
+          query = true;
+          end_ev = 4;
         } else {
-          bool entering = cos_ng > 0.0f;
-          V3 n = entering ? ng : ng * -1.0f;
+          if (P.rec) {  // training record: inputs, radiance so far, throughput
+            float* rr = P.rec + ((size_t)slot * P.rec_depth + b) * kNrcRecFloats;
+            nrc_inputs(S.box_lo, S.box_inv, p, wo_w, n, m, rr);
+            rr[12] = L.x;
+            rr[13] = L.y;
+            rr[14] = L.z;
+            rr[15] = beta.x;
+            rr[16] = beta.y;
+            rr[17] = beta.z;
+            rr[18] = 1.0f;
+          }
           V3 t, bt;
           make_frame(n, axis, t, bt);
           V3 wo = v3(dot(wo_w, t), dot(wo_w, bt), dot(wo_w, n));
           Bsdf B = bsdf_setup<CLS>(m, entering, wo.z);
           if (wo.z <= 0.0f) B.absorbed = true;
-          Rng rng{(uint32_t)(P.y0 + slot / P.w) * img_w + (uint32_t)(P.x0 + slot % P.w), sample, k0, k1};
+          Rng rng{slot_pixel(P, slot, img_w), sample, k0, k1};
           U4 r0 = rng.block((uint32_t)b, 0u), r1 = rng.block((uint32_t)b, 1u);
           // next-event estimation
           if (!B.absorbed && bsdf_has_nondelta<CLS>(m, B)) {
@@ -489,6 +525,10 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b,
     }
     uint32_t qpos = wave_append(cont, &P.counts[next]);
     if (cont) P.q_ray[next][qpos] = slot;
+    if (b == nrc_bounce) {
+      uint32_t npos = wave_append(query, &P.counts[kCountQuery]);
+      if (query) P.q_nrc[npos] = slot;
+    }
     uint32_t spos = wave_append(shadow, &P.counts[kCountShadow]);
     if (shadow) {
       P.sh_o[spos] = sh_o;
@@ -623,7 +663,7 @@ static hipError_t shade_all(const SceneDev& S, const PathsDev& P, const PassArgs
 #define PT_SHADE(C)                                                                                     \
   if (A.class_mask & (1u << C))                                                                         \
     hipLaunchKernelGGL((k_shade<C, DEBUG, TWO>), g, blk, 0, st, S, P, b, A.max_depth, next, A.sample, A.k0, \
-                       A.k1, W);
+                       A.k1, W, A.nrc_bounce);
   PT_SHADE(kClsMiss)
   PT_SHADE(kClsAbsorb)
   PT_SHADE(kClsDiffuse)
@@ -648,6 +688,11 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
     hipError_t e = shade_all<DEBUG, TWO>(S, P, A, b, next, (uint32_t)C.W, st);
     if (e != hipSuccess) return e;
     if (b < A.max_depth) hipLaunchKernelGGL((k_connect<DEBUG, COUNT, TWO>), dim3(A.grid_trace), blk, 0, st, S, P);
+    if (b == A.nrc_bounce) {  // every path still alive ended in the cache at this vertex
+      hipError_t e2 = nrc_launch_query(P, A.nrc_fwd, std::min(A.grid, 1024), st);
+      if (e2 != hipSuccess) return e2;
+      break;
+    }
   }
   return hipGetLastError();
 }

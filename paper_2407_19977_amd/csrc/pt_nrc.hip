@@ -1,0 +1,492 @@
+// Radiance-cache kernels for gfx950: BF16 matrix-core inference and training.
+//
+// k_nrc_pack      FP32 master weights -> bf16 operand fragments (forward and
+//                 transposed for the backward pass), in the chained K order.
+// k_nrc_infer     encode + 6 layers per 16 queries per wave, weights in LDS.
+// k_nrc_fwd_bwd   forward with kept activations, relative-L2 loss gradient,
+//                 backward through the transposed fragments; writes layer
+//                 inputs and layer output gradients (bf16, [feature][sample]).
+// k_nrc_dw        dW_l = g_l^T a_l as a matrix-core GEMM over samples, split
+//                 over sample ranges; partial tiles in FP32.
+// k_nrc_adam      fixed-order sum of the partials, Adam with FP32 master weights.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "pt_internal.h"
+#include "pt_nrc.h"
+
+namespace pt {
+
+typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
+typedef float f32x4 __attribute__((__vector_size__(4 * sizeof(float))));
+
+__device__ inline bf16x8 as_bf16x8(uint4 u) { return __builtin_bit_cast(bf16x8, u); }
+
+__device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ inline uint32_t pack2(float a, float b) {
+  return (uint32_t)bf16_bits(a) | ((uint32_t)bf16_bits(b) << 16);
+}
+
+// B operand of a chained chunk from two result tiles, with ReLU.
+__device__ inline bf16x8 chain_relu(f32x4 lo, f32x4 hi) {
+  uint4 u;
+  u.x = pack2(fmaxf(lo[0], 0.0f), fmaxf(lo[1], 0.0f));
+  u.y = pack2(fmaxf(lo[2], 0.0f), fmaxf(lo[3], 0.0f));
+  u.z = pack2(fmaxf(hi[0], 0.0f), fmaxf(hi[1], 0.0f));
+  u.w = pack2(fmaxf(hi[2], 0.0f), fmaxf(hi[3], 0.0f));
+  return as_bf16x8(u);
+}
+
+__device__ inline float bf16x8_get(bf16x8 v, int j) { return (float)v[j]; }
+
+// --------------------------------------------------------------- packing
+__global__ void k_nrc_pack(const float* __restrict__ w, uint4* __restrict__ fwd, uint4* __restrict__ bwd) {
+  int id = blockIdx.x * blockDim.x + threadIdx.x;
+  int total = (kNrcFwdFrags + kNrcBwdFrags) * 64;
+  if (id >= total) return;
+  int frag = id / 64, lane = id % 64, g = lane / 16, r = lane % 16;
+  float v[8];
+  if (frag < kNrcFwdFrags) {
+    if (frag < 40) {
+      int l = frag / 8, t = (frag % 8) / 2, c = frag % 2;
+      for (int j = 0; j < 8; ++j) {
+        int in = l == 0 ? nrc_k_natural(c, g, j) : nrc_k_chained(c, g, j);
+        v[j] = w[nrc_widx(l, 16 * t + r, in)];
+      }
+    } else {
+      int c = frag - 40;
+      for (int j = 0; j < 8; ++j) v[j] = r < 3 ? w[nrc_widx(5, r, nrc_k_chained(c, g, j))] : 0.0f;
+    }
+  } else {
+    int f = frag - kNrcFwdFrags;
+    if (f < 32) {
+      int l = 1 + f / 8, t = (f % 8) / 2, c = f % 2;
+      for (int j = 0; j < 8; ++j) v[j] = w[nrc_widx(l, nrc_k_chained(c, g, j), 16 * t + r)];
+    } else {
+      int t = f - 32;
+      for (int j = 0; j < 8; ++j) {
+        int k = 8 * g + j;
+        v[j] = k < 3 ? w[nrc_widx(5, k, 16 * t + r)] : 0.0f;
+      }
+    }
+  }
+  uint4 u;
+  u.x = pack2(v[0], v[1]);
+  u.y = pack2(v[2], v[3]);
+  u.z = pack2(v[4], v[5]);
+  u.w = pack2(v[6], v[7]);
+  if (frag < kNrcFwdFrags) fwd[frag * 64 + lane] = u;
+  else bwd[(frag - kNrcFwdFrags) * 64 + lane] = u;
+}
+
+// Encoded input as the layer-0 B operand: lane (g, q) holds features 32c + 8g + j.
+__device__ inline void encode_operand(const float* x, int g, bool valid, bf16x8 B[2]) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    float f[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) f[j] = valid ? nrc_feature(nrc_k_natural(c, g, j), x) : 0.0f;
+    uint4 u;
+    u.x = pack2(f[0], f[1]);
+    u.y = pack2(f[2], f[3]);
+    u.z = pack2(f[4], f[5]);
+    u.w = pack2(f[6], f[7]);
+    B[c] = as_bf16x8(u);
+  }
+}
+
+// Five hidden layers and the output layer; returns the output tile (rows 0..2 valid in lanes g == 0).
+__device__ inline f32x4 mlp_forward(const uint4* __restrict__ sw, int lane, bf16x8 B[2], bf16x8* keep) {
+  if (keep) {
+    keep[0] = B[0];
+    keep[1] = B[1];
+  }
+#pragma unroll
+  for (int l = 0; l < 5; ++l) {
+    f32x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int c = 0; c < 2; ++c) acc[t] = mfma(as_bf16x8(sw[((l * 4 + t) * 2 + c) * 64 + lane]), B[c], acc[t]);
+    }
+    B[0] = chain_relu(acc[0], acc[1]);
+    B[1] = chain_relu(acc[2], acc[3]);
+    if (keep) {
+      keep[2 * (l + 1)] = B[0];
+      keep[2 * (l + 1) + 1] = B[1];
+    }
+  }
+  f32x4 out = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int c = 0; c < 2; ++c) out = mfma(as_bf16x8(sw[(40 + c) * 64 + lane]), B[c], out);
+  return out;
+}
+
+// ------------------------------------------------------------- inference
+// MODE 0: inputs x[n][12], outputs y[n][3].
+// MODE 1: the cache queries of a sampling pass: slot = q_nrc[i] for i < counts[kCountQuery];
+//         inputs nrc_q[slot][0..11], throughput nrc_q[slot][12..14]; L[slot] += beta * max(y, 0).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_nrc_infer(const float* __restrict__ xin, int64_t n_arg, PathsDev P,
+                                                   const uint4* __restrict__ fwd, float* __restrict__ out) {
+  __shared__ uint4 sw[kNrcFwdFrags * 64];
+  for (int i = threadIdx.x; i < kNrcFwdFrags * 64; i += blockDim.x) sw[i] = fwd[i];
+  __syncthreads();
+  const int64_t n = MODE == 1 ? (int64_t)P.counts[kCountQuery] : n_arg;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, g = lane / 16, q = lane % 16;
+  unsigned long long nonfinite = 0;
+  for (int64_t grp = (int64_t)blockIdx.x * 4 + wave; grp * 16 < n; grp += (int64_t)gridDim.x * 4) {
+    int64_t qi = grp * 16 + q;
+    bool valid = qi < n;
+    const float* r = nullptr;
+    uint32_t slot = 0;
+    if (valid) {
+      if (MODE == 0) {
+        r = xin + qi * 12;
+      } else {
+        slot = P.q_nrc[qi];
+        r = P.nrc_q + (size_t)slot * kNrcQueryFloats;
+      }
+    }
+    float x[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) x[k] = valid ? r[k] : 0.0f;
+    bf16x8 B[2];
+    encode_operand(x, g, valid, B);
+    f32x4 y = mlp_forward(sw, lane, B, nullptr);
+    if (valid && g == 0) {
+      if (MODE == 0) {
+        out[qi * 3 + 0] = y[0];
+        out[qi * 3 + 1] = y[1];
+        out[qi * 3 + 2] = y[2];
+      } else {
+        float cx = r[12] * fmaxf(y[0], 0.0f), cy = r[13] * fmaxf(y[1], 0.0f), cz = r[14] * fmaxf(y[2], 0.0f);
+        if (isfinite(cx) && isfinite(cy) && isfinite(cz)) {
+          float4 l = P.L[slot];
+          P.L[slot] = make_float4(l.x + cx, l.y + cy, l.z + cz, l.w);
+        } else {
+          nonfinite++;
+        }
+      }
+    }
+  }
+  if (MODE == 1 && nonfinite) atomicAdd(&P.stats[kStatNonFinite], nonfinite);
+}
+
+// -------------------------------------------------------- forward+backward
+// a_store[l][f][n] (l = 0..5 layer inputs) and g_store[l][f][n] (l = 0..5
+// gradients of the layer outputs), bf16, n padded to npad.  Samples at
+// n >= N are written as zeros.  loss_part[block] = sum of the block's loss terms.
+__global__ __launch_bounds__(256) void k_nrc_fwd_bwd(const float* __restrict__ X, const float* __restrict__ T,
+                                                     int N, int npad, const uint4* __restrict__ fwd,
+                                                     const uint4* __restrict__ bwd, uint16_t* __restrict__ a_store,
+                                                     uint16_t* __restrict__ g_store, float* __restrict__ loss_part) {
+  __shared__ uint4 sw[kNrcFwdFrags * 64];
+  __shared__ uint4 swt[kNrcBwdFrags * 64];
+  __shared__ float wave_loss[4];
+  for (int i = threadIdx.x; i < kNrcFwdFrags * 64; i += blockDim.x) sw[i] = fwd[i];
+  for (int i = threadIdx.x; i < kNrcBwdFrags * 64; i += blockDim.x) swt[i] = bwd[i];
+  __syncthreads();
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, g = lane / 16, q = lane % 16;
+  const float inv_count = 1.0f / (3.0f * (float)N);
+  float my_loss = 0.0f;
+  const size_t L = (size_t)64 * npad;  // one layer of a store
+  for (int grp = blockIdx.x * 4 + wave; grp * 16 < npad; grp += gridDim.x * 4) {
+    int qi = grp * 16 + q;
+    bool valid = qi < N;
+    float x[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) x[k] = valid ? X[(size_t)qi * 12 + k] : 0.0f;
+    bf16x8 keep[12];
+    bf16x8 B[2];
+    encode_operand(x, g, valid, B);
+    f32x4 y = mlp_forward(sw, lane, B, keep);
+    // layer inputs a_0..a_5
+#pragma unroll
+    for (int l = 0; l < 6; ++l)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          int f = l == 0 ? nrc_k_natural(c, g, j) : nrc_k_chained(c, g, j);
+          float v = valid ? bf16x8_get(keep[2 * l + c], j) : 0.0f;
+          a_store[l * L + (size_t)f * npad + qi] = bf16_bits(v);
+        }
+    // loss gradient (lanes g == 0 hold the three outputs of query q)
+    float dy[3] = {0.0f, 0.0f, 0.0f};
+    if (g == 0 && valid) {
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        float t = T[(size_t)qi * 3 + ch];
+        float d = y[ch] * y[ch] + 0.01f;
+        float r = y[ch] - t;
+        my_loss += r * r / d;
+        dy[ch] = 2.0f * r / d * inv_count;
+      }
+    }
+    uint4 gu;
+    gu.x = pack2(dy[0], dy[1]);
+    gu.y = pack2(dy[2], 0.0f);
+    gu.z = 0u;
+    gu.w = 0u;
+    bf16x8 G5 = as_bf16x8(gu);
+    if (g == 0) {
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) g_store[5 * L + (size_t)ch * npad + qi] = bf16_bits(dy[ch]);
+    }
+    // g_4 = (W5^T g_5) * [a_5 > 0]
+    f32x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = mfma(as_bf16x8(swt[(32 + t) * 64 + lane]), G5, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+    bf16x8 Gc[2];
+#pragma unroll
+    for (int lo = 4; lo >= 0; --lo) {
+      // mask with a_{lo+1} > 0, store g_lo, form the chained operand
+      float gv[4][4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float a = bf16x8_get(keep[2 * (lo + 1) + t / 2], (t % 2) * 4 + i);
+          gv[t][i] = a > 0.0f ? acc[t][i] : 0.0f;
+          g_store[lo * L + (size_t)(16 * t + 4 * g + i) * npad + qi] = bf16_bits(valid ? gv[t][i] : 0.0f);
+        }
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        uint4 u;
+        u.x = pack2(gv[2 * c][0], gv[2 * c][1]);
+        u.y = pack2(gv[2 * c][2], gv[2 * c][3]);
+        u.z = pack2(gv[2 * c + 1][0], gv[2 * c + 1][1]);
+        u.w = pack2(gv[2 * c + 1][2], gv[2 * c + 1][3]);
+        Gc[c] = as_bf16x8(u);
+      }
+      if (lo == 0) break;
+      // g_{lo-1} (pre-mask) = W_lo^T g_lo
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[t] = mfma(as_bf16x8(swt[(((lo - 1) * 4 + t) * 2 + c) * 64 + lane]), Gc[c], acc[t]);
+      }
+    }
+  }
+  // fixed-order block reduction of the loss
+  for (int off = 32; off > 0; off >>= 1) my_loss += __shfl_down(my_loss, off);
+  if (lane == 0) wave_loss[wave] = my_loss;
+  __syncthreads();
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = ((wave_loss[0] + wave_loss[1]) + wave_loss[2]) + wave_loss[3];
+}
+
+// ---------------------------------------------------------- weight grads
+// One wave per (tile, split): dW_l[16 to + .][16 ti + .] over samples of the split.
+__global__ __launch_bounds__(256) void k_nrc_dw(const uint16_t* __restrict__ a_store,
+                                                const uint16_t* __restrict__ g_store, int npad, int n_split,
+                                                float* __restrict__ dw_part) {
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, g = lane / 16, r = lane % 16;
+  const int wid = blockIdx.x * 4 + wave;
+  if (wid >= 84 * n_split) return;
+  const int tile = wid % 84, split = wid / 84;
+  int l, to, ti;
+  if (tile < 80) {
+    l = tile / 16;
+    to = (tile % 16) / 4;
+    ti = tile % 4;
+  } else {
+    l = 5;
+    to = 0;
+    ti = tile - 80;
+  }
+  const size_t L = (size_t)64 * npad;
+  const int per = npad / n_split;
+  const int n0 = split * per, n1 = n0 + per;
+  const uint16_t* ga = g_store + l * L + (size_t)(16 * to + r) * npad;
+  const uint16_t* aa = a_store + l * L + (size_t)(16 * ti + r) * npad;
+  const bool row_ok = l < 5 || r < 3;
+  f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k = n0; k < n1; k += 32) {
+    uint4 au = row_ok ? *reinterpret_cast<const uint4*>(ga + k + 8 * g) : make_uint4(0u, 0u, 0u, 0u);
+    uint4 bu = *reinterpret_cast<const uint4*>(aa + k + 8 * g);
+    acc = mfma(as_bf16x8(au), as_bf16x8(bu), acc);
+  }
+  float* dst = dw_part + (size_t)split * kNrcParams;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int o = 16 * to + 4 * g + i, in = 16 * ti + r;
+    if (l < 5 || o < 3) dst[nrc_widx(l, o, in)] = acc[i];
+  }
+}
+
+// ------------------------------------------------------------------ Adam
+__global__ __launch_bounds__(256) void k_nrc_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                                                  const float* __restrict__ dw_part, int n_split,
+                                                  float* __restrict__ grad_out, float lr, float b1, float b2,
+                                                  float eps, float c1, float c2, int apply) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kNrcParams) return;
+  float gsum = 0.0f;
+  for (int s = 0; s < n_split; ++s) gsum += dw_part[(size_t)s * kNrcParams + p];
+  if (grad_out) grad_out[p] = gsum;
+  if (!apply) return;
+  float mm = b1 * m[p] + (1.0f - b1) * gsum;
+  float vv = b2 * v[p] + (1.0f - b2) * gsum * gsum;
+  m[p] = mm;
+  v[p] = vv;
+  w[p] -= lr * (mm * c1) / (sqrtf(vv * c2) + eps);
+}
+
+// ------------------------------------------------------- training targets
+// Record r of training path k is valid when the path reached vertex r with
+// b < max_depth; its target is (L_end - L_r) / beta_r, dropped when a channel
+// of beta_r is zero or the target is not finite.  Offsets come from an
+// exclusive scan over paths, so the compacted list is in path-major, vertex
+// order whatever the scheduling.
+__device__ inline bool nrc_target(const float* rec, float4 Lend, float t[3]) {
+  if (rec[18] == 0.0f) return false;
+  const float Lr[3] = {rec[12], rec[13], rec[14]}, be[3] = {rec[15], rec[16], rec[17]};
+  const float Le[3] = {Lend.x, Lend.y, Lend.z};
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    ok = ok && be[c] != 0.0f;
+    t[c] = (Le[c] - Lr[c]) / be[c];
+    ok = ok && isfinite(t[c]);
+  }
+  return ok;
+}
+
+__global__ __launch_bounds__(256) void k_nrc_count(PathsDev P, int n_paths, uint32_t* __restrict__ counts) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_paths) return;
+  float4 Le = P.L[k];
+  uint32_t c = 0;
+  for (int r = 0; r < P.rec_depth; ++r) {
+    float t[3];
+    c += nrc_target(P.rec + ((size_t)k * P.rec_depth + r) * kNrcRecFloats, Le, t) ? 1u : 0u;
+  }
+  counts[k] = c;
+}
+
+// In-place exclusive scan of the per-path counts (one workgroup); total to *n_out.
+__global__ __launch_bounds__(1024) void k_nrc_scan(int n_paths, uint32_t* __restrict__ offsets,
+                                                   uint32_t* __restrict__ n_out) {
+  __shared__ uint32_t part[1024];
+  const int per = (n_paths + 1023) / 1024;
+  const int k0 = min(n_paths, (int)threadIdx.x * per), k1 = min(n_paths, k0 + per);
+  uint32_t local = 0;
+  for (int k = k0; k < k1; ++k) local += offsets[k];
+  part[threadIdx.x] = local;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive scan
+    uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t base = part[threadIdx.x] - local;
+  for (int k = k0; k < k1; ++k) {
+    uint32_t c = offsets[k];
+    offsets[k] = base;
+    base += c;
+  }
+  if (threadIdx.x == 1023) *n_out = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_nrc_compact(PathsDev P, int n_paths, const uint32_t* __restrict__ offsets,
+                                                     float* __restrict__ X, float* __restrict__ T) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_paths) return;
+  float4 Le = P.L[k];
+  uint32_t o = offsets[k];
+  for (int r = 0; r < P.rec_depth; ++r) {
+    const float* rec = P.rec + ((size_t)k * P.rec_depth + r) * kNrcRecFloats;
+    float t[3];
+    if (!nrc_target(rec, Le, t)) continue;
+    for (int i = 0; i < 12; ++i) X[(size_t)o * 12 + i] = rec[i];
+    for (int c = 0; c < 3; ++c) T[(size_t)o * 3 + c] = t[c];
+    ++o;
+  }
+}
+
+// Batch of step s of a frame: sample j takes record floor(m * n / 2^24), m the
+// top 24 bits of Philox word s % 4 at counter (j, 2^31 + frame, 0x4E5253, s / 4).
+__global__ __launch_bounds__(256) void k_nrc_gather(const float* __restrict__ X_all, const float* __restrict__ T_all,
+                                                    const uint32_t* __restrict__ n_all, int B, uint32_t frame,
+                                                    int step, uint32_t k0, uint32_t k1, float* __restrict__ Xb,
+                                                    float* __restrict__ Tb) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= B) return;
+  uint32_t n = *n_all;
+  if (n == 0u) {
+    for (int i = 0; i < 12; ++i) Xb[(size_t)j * 12 + i] = 0.0f;
+    for (int c = 0; c < 3; ++c) Tb[(size_t)j * 3 + c] = 0.0f;
+    return;
+  }
+  U4 r = philox((uint32_t)j, 0x80000000u + frame, 0x4E5253u, (uint32_t)step / 4u, k0, k1);
+  uint32_t w = (step % 4) == 0 ? r.x : (step % 4) == 1 ? r.y : (step % 4) == 2 ? r.z : r.w;
+  uint32_t idx = (uint32_t)(((uint64_t)(w >> 8) * n) >> 24);
+  for (int i = 0; i < 12; ++i) Xb[(size_t)j * 12 + i] = X_all[(size_t)idx * 12 + i];
+  for (int c = 0; c < 3; ++c) Tb[(size_t)j * 3 + c] = T_all[(size_t)idx * 3 + c];
+}
+
+// ------------------------------------------------------------- launchers
+hipError_t nrc_launch_pack(const float* w, uint4* fwd, uint4* bwd, hipStream_t st) {
+  int total = (kNrcFwdFrags + kNrcBwdFrags) * 64;
+  hipLaunchKernelGGL(k_nrc_pack, dim3((total + 255) / 256), dim3(256), 0, st, w, fwd, bwd);
+  return hipGetLastError();
+}
+
+hipError_t nrc_launch_forward(const float* x, int64_t n, const uint4* fwd, float* y, hipStream_t st) {
+  PathsDev P;
+  __builtin_memset(&P, 0, sizeof(P));
+  int64_t groups = (n + 15) / 16;
+  int grid = (int)std::max<int64_t>(1, std::min<int64_t>((groups + 3) / 4, 2048));
+  hipLaunchKernelGGL((k_nrc_infer<0>), dim3(grid), dim3(256), 0, st, x, n, P, fwd, y);
+  return hipGetLastError();
+}
+
+hipError_t nrc_launch_query(const PathsDev& P, const uint4* fwd, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_nrc_infer<1>), dim3(grid), dim3(256), 0, st, nullptr, (int64_t)0, P, fwd, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t nrc_launch_train(const float* X, const float* T, int N, int npad, int n_split, const uint4* fwd,
+                            const uint4* bwd, uint16_t* a_store, uint16_t* g_store, float* loss_part, int grid_fb,
+                            float* dw_part, hipStream_t st) {
+  hipLaunchKernelGGL(k_nrc_fwd_bwd, dim3(grid_fb), dim3(256), 0, st, X, T, N, npad, fwd, bwd, a_store, g_store,
+                     loss_part);
+  int waves = 84 * n_split;
+  hipLaunchKernelGGL(k_nrc_dw, dim3((waves + 3) / 4), dim3(256), 0, st, a_store, g_store, npad, n_split, dw_part);
+  return hipGetLastError();
+}
+
+hipError_t nrc_launch_adam(float* w, float* m, float* v, const float* dw_part, int n_split, float* grad_out, float lr,
+                           float b1, float b2, float eps, int step, int apply, hipStream_t st) {
+  float c1 = (float)(1.0 / (1.0 - std::pow((double)b1, (double)step)));
+  float c2 = (float)(1.0 / (1.0 - std::pow((double)b2, (double)step)));
+  hipLaunchKernelGGL(k_nrc_adam, dim3((kNrcParams + 255) / 256), dim3(256), 0, st, w, m, v, dw_part, n_split, grad_out,
+                     lr, b1, b2, eps, c1, c2, apply);
+  return hipGetLastError();
+}
+
+hipError_t nrc_launch_targets(const PathsDev& P, int n_paths, uint32_t* offsets, float* X, float* T,
+                              uint32_t* n_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_nrc_count, dim3((n_paths + 255) / 256), dim3(256), 0, st, P, n_paths, offsets);
+  hipLaunchKernelGGL(k_nrc_scan, dim3(1), dim3(1024), 0, st, n_paths, offsets, n_out);
+  hipLaunchKernelGGL(k_nrc_compact, dim3((n_paths + 255) / 256), dim3(256), 0, st, P, n_paths, offsets, X, T);
+  return hipGetLastError();
+}
+
+hipError_t nrc_launch_gather(const float* X_all, const float* T_all, const uint32_t* n_all, int B, uint32_t frame,
+                             int step, uint32_t k0, uint32_t k1, float* Xb, float* Tb, hipStream_t st) {
+  hipLaunchKernelGGL(k_nrc_gather, dim3((B + 255) / 256), dim3(256), 0, st, X_all, T_all, n_all, B, frame, step, k0,
+                     k1, Xb, Tb);
+  return hipGetLastError();
+}
+
+}  // namespace pt

@@ -53,6 +53,24 @@ class pt_bvh_info(C.Structure):
                 ("max_leaf_tris", C.c_int32), ("sah_cost", C.c_double), ("build_ms", C.c_double)]
 
 
+class pt_radiance_cache_config(C.Structure):
+    _fields_ = [("query_bounce", C.c_int32), ("train_paths", C.c_int32), ("batch_size", C.c_int32),
+                ("steps_per_frame", C.c_int32), ("learning_rate", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("epsilon", C.c_float), ("init_seed", C.c_uint64)]
+
+
+NRC_PARAMS = 5 * 64 * 64 + 3 * 64
+
+
+def cache_config(query_bounce=2, train_paths=1 << 16, batch_size=1 << 14, steps_per_frame=4, learning_rate=1e-3,
+                 beta1=0.9, beta2=0.99, epsilon=1e-8, init_seed=0):
+    c = pt_radiance_cache_config()
+    c.query_bounce, c.train_paths, c.batch_size, c.steps_per_frame = query_bounce, train_paths, batch_size, \
+        steps_per_frame
+    c.learning_rate, c.beta1, c.beta2, c.epsilon, c.init_seed = learning_rate, beta1, beta2, epsilon, init_seed
+    return c
+
+
 # every symbol declared in include/pt.h, with its ctypes signature
 _SIGS = {
     "pt_scene_create": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
@@ -70,6 +88,16 @@ _SIGS = {
     "pt_get_stats": (C.c_int, [C.c_void_p, C.POINTER(pt_stats)]),
     "pt_reset_stats": (C.c_int, [C.c_void_p]),
     "pt_set_profiling": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "pt_set_radiance_cache": (C.c_int, [C.c_void_p, C.POINTER(pt_radiance_cache_config)]),
+    "pt_nrc_set_weights": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "pt_nrc_get_weights": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]),
+    "pt_nrc_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "pt_nrc_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                  C.POINTER(C.c_double)]),
+    "pt_nrc_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_uint64,
+                               C.POINTER(C.c_double)]),
+    "pt_nrc_training_records": (C.c_int, [C.c_void_p, C.POINTER(pt_camera), C.c_int32, C.c_int32, C.c_uint64,
+                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
     "pt_bvh_host_build": (C.c_int, [C.POINTER(pt_mesh), C.POINTER(C.c_void_p)]),
     "pt_bvh_host_build_instanced": (C.c_int, [C.POINTER(pt_mesh), C.c_int32, C.POINTER(pt_instance), C.c_int32,
                                               C.POINTER(C.c_void_p)]),
@@ -193,6 +221,42 @@ class PtScene:
     def render_debug(self, camera, x0, y0, w, h, first_sample, spp, max_depth, seed, per_sample, sigs):
         _check(_lib.pt_render_debug(self.h, C.byref(camera_struct(camera)), x0, y0, w, h, first_sample, spp,
                                     max_depth, seed, per_sample.data_ptr(), sigs.data_ptr()))
+
+    # -- radiance cache (device tensors: float32 on the scene's GPU)
+    def set_radiance_cache(self, config=None):
+        _check(_lib.pt_set_radiance_cache(self.h, None if config is None else C.byref(config)))
+
+    def nrc_set_weights(self, w):
+        _check(_lib.pt_nrc_set_weights(self.h, w.data_ptr(), w.numel()))
+
+    def nrc_get_weights(self, w=None, m=None, v=None):
+        step = C.c_int64(0)
+        _check(_lib.pt_nrc_get_weights(self.h, None if w is None else w.data_ptr(),
+                                       None if m is None else m.data_ptr(), None if v is None else v.data_ptr(),
+                                       C.byref(step)))
+        return step.value
+
+    def nrc_forward(self, x, y):
+        _check(_lib.pt_nrc_forward(self.h, x.data_ptr(), x.shape[0], y.data_ptr()))
+        return y
+
+    def nrc_gradient(self, x, t, grad):
+        loss = C.c_double(0.0)
+        _check(_lib.pt_nrc_gradient(self.h, x.data_ptr(), t.data_ptr(), x.shape[0], grad.data_ptr(), C.byref(loss)))
+        return loss.value
+
+    def nrc_train(self, x, t, frame, seed):
+        loss = C.c_double(0.0)
+        _check(_lib.pt_nrc_train(self.h, x.data_ptr(), t.data_ptr(), x.shape[0], frame, seed, C.byref(loss)))
+        return loss.value
+
+    def nrc_training_records(self, camera, frame, max_depth, seed, x, t, offsets=None):
+        n = C.c_int64(0)
+        _check(_lib.pt_nrc_training_records(self.h, C.byref(camera_struct(camera)), frame, max_depth, seed,
+                                            x.data_ptr(), t.data_ptr(),
+                                            None if offsets is None else offsets.data_ptr(), x.shape[0],
+                                            C.byref(n)))
+        return n.value
 
     def trace_closest(self, rays, hits, brute_force=False):
         _check(_lib.pt_trace_closest(self.h, rays.data_ptr(), rays.shape[0], hits.data_ptr(),

@@ -16,6 +16,7 @@ import argparse
 import glob
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -73,6 +74,113 @@ def cpu_baseline(sc, spp_cpu=12, crop=(0, 0, 1920, 1080)):
                       f"({crop[2] * crop[3] * spp_cpu / dt:.3g} samples/s)"}
 
 
+CHECKPOINTS = (1, 2, 4, 8, 16, 32, 64, 128, 256)
+NRC_FLOP_PER_QUERY = 2 * (5 * 64 * 64 + 3 * 64)   # 41,344 multiply-adds x 2
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def _frames(s, cam, depth, seed, frames, ref, out, torch):
+    """Frames of 1 spp into the FP64 sums: cumulative ms and RMSE against ref at the checkpoints."""
+    s.reset_accumulation()
+    t = 0.0
+    rows = []
+    for k in range(frames):
+        t0 = time.perf_counter()
+        s.accumulate(cam, k, 1, depth, seed)  # returns after the stream has drained
+        t += time.perf_counter() - t0
+        if k + 1 in CHECKPOINTS:
+            s.resolve(out)
+            d = out.double() - ref
+            e = torch.sqrt(torch.mean(d * d)).item()
+            rel = torch.mean(d * d / (ref * ref + 0.01)).item()
+            rows.append((k + 1, t * 1e3, e, rel))
+    return rows
+
+
+def _time_to(rows, target, col=2):
+    """Time at which an error-vs-time curve (column col) first reaches target
+    (log-log interpolation from the previous checkpoint), or None."""
+    prev = None
+    for r in rows:
+        ms, e = r[1], r[col]
+        if e <= target:
+            if prev is None or prev[1] <= e:
+                return ms
+            (m0, e0) = prev
+            f = (math.log(target) - math.log(e0)) / (math.log(e) - math.log(e0))
+            return math.exp(math.log(m0) + f * (math.log(ms) - math.log(m0)))
+        prev = (ms, e)
+    return None
+
+
+def cache_experiment(pt, torch, sc, frames=256, ref_spp=4096):
+    """Plain vs radiance-cache rendering, frames of 1 spp, RMSE against a
+    ref_spp plain render with FP64 sums and an independent seed."""
+    cam = sc.camera
+    W, H, depth, seed = cam.width, cam.height, sc.max_depth, sc.seed
+    s = pt.scene_from(sc, device=0)
+    out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda:0")
+    acc = torch.empty((H, W, 3), dtype=torch.float64, device="cuda:0")
+    s.set_radiance_cache(None)
+    s.reset_accumulation()
+    chunk = 256
+    for k in range(0, ref_spp, chunk):
+        s.accumulate(cam, k, min(chunk, ref_spp - k), depth, seed + 1)
+    s.resolve(out, acc)
+    ref = acc / ref_spp
+    print(f"[cache] reference: {ref_spp} spp plain, seed {seed + 1}", file=sys.stderr, flush=True)
+    s.set_profiling(True, False)
+    s.reset_stats()
+    plain = _frames(s, cam, depth, seed, frames, ref, out, torch)
+    s.set_radiance_cache(pt.cache_config())
+    s.reset_stats()
+    nrc = _frames(s, cam, depth, seed, frames, ref, out, torch)
+    st = s.stats()
+    s.set_radiance_cache(None)
+    print(f"[cache] plain {plain[-1]}  cache {nrc[-1]}", file=sys.stderr, flush=True)
+    table = [{"spp": a[0], "plain_ms": round(a[1], 2), "plain_rmse": round(a[2], 6), "plain_relmse": round(a[3], 6),
+              "cache_ms": round(b[1], 2), "cache_rmse": round(b[2], 6), "cache_relmse": round(b[3], 6)}
+             for a, b in zip(plain, nrc)]
+    tte = []
+    for col, name in ((2, "RMSE"), (3, "relMSE")):
+        for target_spp in (4, 16, 64):
+            row = [r for r in plain if r[0] == target_spp]
+            if not row:
+                continue
+            t_plain, target = row[0][1], row[0][col]
+            t_nrc = _time_to(nrc, target, col)
+            tte.append({"target": f"plain {name} at {target_spp} spp", "value": round(target, 6),
+                        "plain_ms": round(t_plain, 2), "cache_ms": None if t_nrc is None else round(t_nrc, 2),
+                        "speedup": None if t_nrc is None else round(t_plain / t_nrc, 3)})
+    q_ms = st["ms_cache_query"]
+    achieved = st["cache_queries"] * NRC_FLOP_PER_QUERY / (q_ms * 1e-3) / 1e12 if q_ms > 0 else None
+    cfg = pt.cache_config()
+    train_samples = st["cache_adam_steps"] * cfg.batch_size
+    result = {
+        "workload": f"icosphere field {W}x{H}, depth {depth}, frames of 1 spp; cache: 64-feature encoding, "
+                    "5x64 ReLU MLP (bf16 matrix cores), query at vertex 2, 65,536 training paths and "
+                    "4 Adam steps of 16,384 records per frame",
+        "reference": f"{ref_spp} spp plain tracer, FP64 sums, seed {seed + 1}",
+        "rmse": table,
+        "time_to_equal_rmse": tte,
+        "ms_per_frame_plain": round(plain[-1][1] / frames, 3),
+        "ms_per_frame_cache": round(nrc[-1][1] / frames, 3),
+        "cache_queries_per_s": round(st["cache_queries"] / (nrc[-1][1] * 1e-3), 1),
+        "training_records_per_frame": st["cache_records"] // frames,
+        "training_samples_per_s": round(train_samples / (st["ms_cache_train"] * 1e-3), 1)
+        if st["ms_cache_train"] > 0 else None,
+        "ms_train_steps_per_frame": round(st["ms_cache_train"] / frames, 3),
+        "roofline": None if achieved is None else {
+            "bound": "mfma", "kernel": "k_nrc_infer<1> (cache queries: encoding + 6-layer bf16 MLP)",
+            "achieved": round(achieved, 2), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
+            "flop_per_query": NRC_FLOP_PER_QUERY, "queries": st["cache_queries"],
+            "avg_launch_ms": round(q_ms / frames, 4)},
+    }
+    s.close()
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +189,9 @@ def main():
     ap.add_argument("--spp", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-count", action="store_true", help="skip the node-visit counting pass")
+    ap.add_argument("--no-cache", action="store_true", help="skip the radiance-cache vs plain experiment")
+    ap.add_argument("--cache-frames", type=int, default=256)
+    ap.add_argument("--ref-spp", type=int, default=4096)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -160,7 +271,10 @@ def main():
         "nonfinite_dropped": st["nonfinite_dropped"],
         "roofline": roofline,
         "cpu_baseline": None,
+        "radiance_cache": None,
     }
+    if not args.no_cache:
+        result["radiance_cache"] = cache_experiment(pt, torch, sc, args.cache_frames, args.ref_spp)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(sc)
     print(json.dumps(result), flush=True)

@@ -92,6 +92,11 @@ typedef struct pt_stats {
   int64_t tri_tests;         /* triangle tests of closest-hit rays (counting on) */
   int64_t shadow_node_visits;/* BVH node fetches of shadow rays (counting on) */
   int64_t shadow_tri_tests;  /* triangle tests of shadow rays (counting on) */
+  int64_t cache_queries;     /* paths that ended in the radiance cache */
+  int64_t cache_records;     /* training records produced by training paths */
+  int64_t cache_adam_steps;  /* Adam steps taken since the cache was configured or given weights */
+  double ms_cache_query;     /* summed time of the cache-query kernel (profiling on) */
+  double ms_cache_train;     /* summed time of training: training paths, targets, steps (profiling on) */
 } pt_stats;
 
 /* Create a scene bound to HIP device `hip_device` and stream `hip_stream`

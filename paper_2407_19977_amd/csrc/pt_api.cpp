@@ -143,6 +143,8 @@ struct pt_scene {
   DevBuf nrc_Xb, nrc_Tb, nrc_a, nrc_g, nrc_loss, nrc_dw;  // one training step's workspace
   int64_t nrc_ws_npad = 0;
   int nrc_ws_split = 0;
+  int64_t nrc_records = 0;
+  double ms_cache_query = 0.0, ms_cache_train = 0.0;
 };
 
 namespace {
@@ -392,6 +394,7 @@ PathsDev paths_dev(pt_scene* s, int64_t n, int x0, int y0, int w) {
   P.dbg_nee = s->dbg_nee.as<uint32_t>();
   P.dbg_tail = s->dbg_tail.as<uint32_t>();
   P.n = (int32_t)n;
+  P.n_render = (int32_t)n;
   P.x0 = x0;
   P.y0 = y0;
   P.w = w;
@@ -441,19 +444,67 @@ pt_status ready_to_render(pt_scene* s) {
   return ensure_lights(s);
 }
 
+// Training paths of a frame appended to a pass as slots [n_render, n_render + paths):
+// path k starts at pixel (k * stride + o_f) mod WH, stride = max(1, floor(WH / paths)),
+// o_f = floor(m * WH / 2^24) with m the top 24 bits of Philox word 0 at counter
+// (0, 2^31 + frame, 0x4F4646, 0); sample index 2^31 + frame.  Each records
+// (inputs, radiance so far, throughput) at its vertices below max_depth.
+pt_status setup_training(pt_scene* s, const CamDev& C, PathsDev& P, int64_t n_render, uint32_t frame, int max_depth,
+                         uint64_t seed) {
+  const int64_t n = s->nrc_cfg.train_paths;
+  const int depth = std::max(1, max_depth);
+  if (n * depth > s->nrc_rec_cap) {
+    PT_HIP(s->nrc_rec.alloc((size_t)n * depth * kNrcRecFloats * sizeof(float)));
+    PT_HIP(s->nrc_X.alloc((size_t)n * depth * 12 * sizeof(float)));
+    PT_HIP(s->nrc_T.alloc((size_t)n * depth * 3 * sizeof(float)));
+    s->nrc_rec_cap = n * depth;
+  }
+  PT_HIP(s->nrc_off.alloc((size_t)n * sizeof(uint32_t)));
+  if (!s->nrc_n.p) PT_HIP(s->nrc_n.alloc(sizeof(uint32_t)));
+  const uint64_t WH = (uint64_t)C.W * (uint64_t)C.H;
+  P.n = (int32_t)(n_render + n);
+  P.n_render = (int32_t)n_render;
+  P.pix_total = (uint32_t)WH;
+  P.pix_stride = (uint32_t)std::max<uint64_t>(1, WH / (uint64_t)n);
+  U4 u = philox(0u, 0x80000000u + frame, 0x4F4646u, 0u, (uint32_t)seed, (uint32_t)(seed >> 32));
+  P.pix_off = (uint32_t)(((uint64_t)(u.x >> 8) * WH) >> 24);
+  P.train_sample = 0x80000000u + frame;
+  P.rec = s->nrc_rec.as<float>();
+  P.rec_depth = max_depth;
+  return PT_OK;
+}
+
+// Targets of the training paths of the last pass, compacted path by path; *n_records on the host.
+pt_status finish_training(pt_scene* s, const PathsDev& P, uint32_t* n_records) {
+  const int n = P.n - P.n_render;
+  PT_HIP(nrc_launch_targets(P, n, s->nrc_off.as<uint32_t>(), s->nrc_X.as<float>(), s->nrc_T.as<float>(),
+                            s->nrc_n.as<uint32_t>(), s->stream));
+  PT_HIP(hipMemcpyAsync(n_records, s->nrc_n.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
+  PT_HIP(hipStreamSynchronize(s->stream));
+  return PT_OK;
+}
+
+pt_status nrc_train_records(pt_scene* s, const float* X_all, const float* T_all, const uint32_t* n_dev,
+                            uint32_t frame, uint64_t seed, double* mean_loss);
+
 // Run sampling passes over the tile (x0, y0, w, h) of the camera's image.
+// With train (n == 1), the pass also carries the frame's training paths and
+// the cache learns from them afterwards.
 pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h, int first, int n, int max_depth,
-                     uint64_t seed, double* sum, float* per_sample, uint64_t* sigs, int spp_total) {
+                     uint64_t seed, double* sum, float* per_sample, uint64_t* sigs, int spp_total,
+                     bool train = false) {
   int64_t N = (int64_t)w * h;
-  pt_status r = ensure_paths(s, N);
+  int64_t slots = N + (train ? s->nrc_cfg.train_paths : 0);
+  pt_status r = ensure_paths(s, slots);
   if (r) return r;
   r = ensure_counters(s);
   if (r) return r;
-  int grid = grid_for(N), grid_trace = grid_for(N);
+  int grid = grid_for(slots), grid_trace = grid_for(slots);
   r = ensure_spill(s, grid_trace);
   if (r) return r;
   SceneDev S = scene_dev(s, grid_trace);
   PathsDev P = paths_dev(s, N, x0, y0, w);
+  if (train && (r = setup_training(s, C, P, N, (uint32_t)first, max_depth, seed))) return r;
   PassArgs A;
   std::memset(&A, 0, sizeof(A));
   A.k0 = (uint32_t)seed;
@@ -477,14 +528,15 @@ pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h,
     P.nrc_q = s->nrc_q.as<float>();
     P.q_nrc = s->q_nrc.as<uint32_t>();
   }
-  int nev = 2 * (max_depth + 1) + 2;
+  int nev = 2 * (max_depth + 1) + 4;
   if (s->timing) {
     while ((int)s->events.size() < nev) {
       hipEvent_t e;
       PT_HIP(hipEventCreate(&e));
       s->events.push_back(e);
     }
-    A.ext_events = s->events.data() + 2;
+    A.ext_events = s->events.data() + 4;
+    if (A.nrc_bounce >= 0) A.nrc_events = s->events.data() + 2;
   }
   for (int k = 0; k < n; ++k) {
     A.sample = (uint32_t)(first + k);
@@ -497,14 +549,34 @@ pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h,
       float ms = 0.0f;
       PT_HIP(hipEventElapsedTime(&ms, s->events[0], s->events[1]));
       s->ms_total += ms;
-      for (int b = 0; b <= max_depth; ++b) {
+      int last = max_depth;
+      if (A.nrc_bounce >= 0 && A.nrc_bounce < max_depth && P.n == P.n_render) last = A.nrc_bounce;  // stops there
+      for (int b = 0; b <= last; ++b) {
         PT_HIP(hipEventElapsedTime(&ms, A.ext_events[2 * b], A.ext_events[2 * b + 1]));
         s->ms_extend += ms;
         s->launches_extend++;
       }
+      if (A.nrc_events) {
+        PT_HIP(hipEventElapsedTime(&ms, A.nrc_events[0], A.nrc_events[1]));
+        s->ms_cache_query += ms;
+      }
     }
   }
   s->samples += (int64_t)n * N;
+  if (train) {
+    auto t0 = std::chrono::steady_clock::now();
+    uint32_t nrec = 0;
+    if ((r = finish_training(s, P, &nrec))) return r;
+    s->nrc_records += nrec;
+    if (nrec > 0 &&  // else nothing to learn from (e.g. every training path missed)
+        (r = nrc_train_records(s, s->nrc_X.as<float>(), s->nrc_T.as<float>(), s->nrc_n.as<uint32_t>(),
+                               (uint32_t)first, seed, nullptr)))
+      return r;
+    if (s->timing) {
+      PT_HIP(hipStreamSynchronize(s->stream));
+      s->ms_cache_train += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+  }
   return PT_OK;
 }
 
@@ -587,11 +659,7 @@ pt_status nrc_read_loss(pt_scene* s, int grid, int64_t N, double* loss) {
   return PT_OK;
 }
 
-// Training paths of a frame: path k starts at pixel (k * stride + o_f) mod WH,
-// stride = max(1, floor(WH / paths)), o_f = floor(m * WH / 2^24) with m the top
-// 24 bits of Philox word 0 at counter (0, 2^31 + frame, 0x4F4646, 0); sample
-// index 2^31 + frame.  Each path records (inputs, radiance so far, throughput)
-// at its vertices below max_depth; the targets are compacted path by path.
+// Trace only the training paths of a frame (no sampling paths) and compact their records.
 pt_status nrc_trace_training(pt_scene* s, const CamDev& C, uint32_t frame, int max_depth, uint64_t seed,
                              uint32_t* n_records) {
   const int64_t n = s->nrc_cfg.train_paths;
@@ -600,30 +668,14 @@ pt_status nrc_trace_training(pt_scene* s, const CamDev& C, uint32_t frame, int m
   if ((r = ensure_counters(s))) return r;
   int grid = grid_for(n), grid_trace = grid_for(n);
   if ((r = ensure_spill(s, grid_trace))) return r;
-  const int depth = std::max(1, max_depth);
-  if (n * depth > s->nrc_rec_cap) {
-    PT_HIP(s->nrc_rec.alloc((size_t)n * depth * kNrcRecFloats * sizeof(float)));
-    PT_HIP(s->nrc_X.alloc((size_t)n * depth * 12 * sizeof(float)));
-    PT_HIP(s->nrc_T.alloc((size_t)n * depth * 3 * sizeof(float)));
-    PT_HIP(s->nrc_off.alloc((size_t)n * sizeof(uint32_t)));
-    if (!s->nrc_n.p) PT_HIP(s->nrc_n.alloc(sizeof(uint32_t)));
-    s->nrc_rec_cap = n * depth;
-  }
-  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-  const uint64_t WH = (uint64_t)C.W * (uint64_t)C.H;
   SceneDev S = scene_dev(s, grid_trace);
-  PathsDev P = paths_dev(s, n, 0, 0, 1);
-  P.pix_total = (uint32_t)WH;
-  P.pix_stride = (uint32_t)std::max<uint64_t>(1, WH / (uint64_t)n);
-  U4 u = philox(0u, 0x80000000u + frame, 0x4F4646u, 0u, k0, k1);
-  P.pix_off = (uint32_t)(((uint64_t)(u.x >> 8) * WH) >> 24);
-  P.rec = s->nrc_rec.as<float>();
-  P.rec_depth = max_depth;
+  PathsDev P = paths_dev(s, 0, 0, 0, 1);
+  if ((r = setup_training(s, C, P, 0, frame, max_depth, seed))) return r;
   PassArgs A;
   std::memset(&A, 0, sizeof(A));
-  A.sample = 0x80000000u + frame;
-  A.k0 = k0;
-  A.k1 = k1;
+  A.sample = frame;
+  A.k0 = (uint32_t)seed;
+  A.k1 = (uint32_t)(seed >> 32);
   A.max_depth = max_depth;
   A.grid = grid;
   A.grid_trace = grid_trace;
@@ -631,11 +683,7 @@ pt_status nrc_trace_training(pt_scene* s, const CamDev& C, uint32_t frame, int m
   A.class_mask = s->class_mask | (1u << kClsMiss);
   A.nrc_bounce = -1;
   PT_HIP(launch_pass(S, P, C, A, s->stream));
-  PT_HIP(nrc_launch_targets(P, (int)n, s->nrc_off.as<uint32_t>(), s->nrc_X.as<float>(), s->nrc_T.as<float>(),
-                            s->nrc_n.as<uint32_t>(), s->stream));
-  PT_HIP(hipMemcpyAsync(n_records, s->nrc_n.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
-  PT_HIP(hipStreamSynchronize(s->stream));
-  return PT_OK;
+  return finish_training(s, P, n_records);
 }
 
 // The frame's Adam steps on batches drawn with replacement from n records X_all, T_all.
@@ -662,14 +710,6 @@ pt_status nrc_train_records(pt_scene* s, const float* X_all, const float* T_all,
   return PT_OK;
 }
 
-pt_status nrc_train_frame(pt_scene* s, const CamDev& C, uint32_t frame, int max_depth, uint64_t seed) {
-  uint32_t n = 0;
-  pt_status r = nrc_trace_training(s, C, frame, max_depth, seed, &n);
-  if (r) return r;
-  if (n == 0) return PT_OK;  // nothing to learn from (e.g. every training path missed)
-  return nrc_train_records(s, s->nrc_X.as<float>(), s->nrc_T.as<float>(), s->nrc_n.as<uint32_t>(), frame, seed,
-                           nullptr);
-}
 
 // Sampling passes of the whole image into the FP64 sums; with the radiance
 // cache on, every pass is one frame: render, then train on that frame.
@@ -678,9 +718,8 @@ pt_status render_samples(pt_scene* s, const CamDev& C, int first, int n, int max
     return run_passes(s, C, 0, 0, C.W, C.H, first, n, max_depth, seed, s->sum.as<double>(), nullptr, nullptr, n);
   for (int k = 0; k < n; ++k) {
     pt_status r = run_passes(s, C, 0, 0, C.W, C.H, first + k, 1, max_depth, seed, s->sum.as<double>(), nullptr,
-                             nullptr, 1);
+                             nullptr, 1, true);
     if (r) return r;
-    if ((r = nrc_train_frame(s, C, (uint32_t)(first + k), max_depth, seed))) return r;
   }
   return PT_OK;
 }
@@ -1409,12 +1448,17 @@ pt_status pt_get_stats(pt_scene* s, pt_stats* o) {
     o->tri_tests = (int64_t)v[kStatTris];
     o->shadow_node_visits = (int64_t)v[kStatShadowNodes];
     o->shadow_tri_tests = (int64_t)v[kStatShadowTris];
+    o->cache_queries = (int64_t)v[kStatQueries];
     if (v[kStatOverflow]) return fail(PT_ERR_DEVICE, "traversal stack overflow in %llu workgroups", v[kStatOverflow]);
   }
   o->samples = s->samples;
   o->ms_extend = s->ms_extend;
   o->launches_extend = s->launches_extend;
   o->ms_total = s->ms_total;
+  o->cache_records = s->nrc_records;
+  o->cache_adam_steps = s->nrc_step;
+  o->ms_cache_query = s->ms_cache_query;
+  o->ms_cache_train = s->ms_cache_train;
   return PT_OK;
 }
 
@@ -1427,6 +1471,8 @@ pt_status pt_reset_stats(pt_scene* s) {
   s->ms_extend = s->ms_total = 0.0;
   s->launches_extend = 0;
   s->samples = 0;
+  s->nrc_records = 0;
+  s->ms_cache_query = s->ms_cache_train = 0.0;
   return sync(s);
 }
 

@@ -79,10 +79,12 @@ struct PathsDev {
   uint64_t* sig;       // path signatures (debug)
   uint32_t* dbg_nee;   // pending next-event light id (debug)
   uint32_t* dbg_tail;  // pending lobe / roulette / end events (debug)
-  int32_t n;           // number of path slots
-  int32_t x0, y0, w;   // slot -> pixel (x0 + slot % w, y0 + slot / w)
-  // training paths: slot -> pixel index (slot * pix_stride + pix_off) mod pix_total when pix_stride != 0
-  uint32_t pix_stride, pix_off, pix_total;
+  int32_t n;           // number of path slots: n_render sampling paths, then training paths
+  int32_t n_render;
+  int32_t x0, y0, w;   // sampling path slot -> pixel (x0 + slot % w, y0 + slot / w)
+  // training path k = slot - n_render: pixel index (k * pix_stride + pix_off) mod pix_total,
+  // sample index train_sample
+  uint32_t pix_stride, pix_off, pix_total, train_sample;
   // radiance cache
   float* nrc_q;        // query record per slot [n][16]: inputs x[12], beta rgb, unused
   uint32_t* q_nrc;     // slots that queried the cache (count in counts[kCountQuery])
@@ -99,7 +101,8 @@ enum {
   kStatOverflow = 5,
   kStatShadowNodes = 6,
   kStatShadowTris = 7,
-  kNumStats = 8
+  kStatQueries = 8,
+  kNumStats = 9
 };
 constexpr int kCountShadow = 2 + kNumClasses;
 constexpr int kCountQuery = kCountShadow + 1;
@@ -119,6 +122,7 @@ struct PassArgs {
   hipEvent_t* ext_events;  // 2 per bounce when timing, else nullptr
   int nrc_bounce;          // vertex at which paths end in the radiance cache, -1: no cache
   const uint4* nrc_fwd;    // packed forward weight fragments (when nrc_bounce >= 0)
+  hipEvent_t* nrc_events;  // 2 events around the cache-query kernel when timing, else nullptr
 };
 
 hipError_t launch_pass(const SceneDev& S, const PathsDev& P, const CamDev& C, const PassArgs& A,

@@ -206,11 +206,16 @@ __device__ inline float pow_heuristic(float a, float b) {
 
 __device__ inline bool finite3(V3 c) { return isfinite(c.x) && isfinite(c.y) && isfinite(c.z); }
 
-// Pixel index (row-major) of a path slot: a tile of the image, or the
-// strided pixel set of the radiance cache's training paths.
+// Pixel index (row-major) and sample index of a path slot: a tile of the
+// image for sampling paths, the strided pixel set of the radiance cache's
+// training paths after them.
 __device__ inline uint32_t slot_pixel(const PathsDev& P, uint32_t slot, uint32_t img_w) {
-  if (P.pix_stride) return (uint32_t)(((uint64_t)slot * P.pix_stride + P.pix_off) % P.pix_total);
+  if (slot >= (uint32_t)P.n_render)
+    return (uint32_t)(((uint64_t)(slot - (uint32_t)P.n_render) * P.pix_stride + P.pix_off) % P.pix_total);
   return (uint32_t)(P.y0 + slot / P.w) * img_w + (uint32_t)(P.x0 + slot % P.w);
+}
+__device__ inline uint32_t slot_sample(const PathsDev& P, uint32_t slot, uint32_t sample) {
+  return slot >= (uint32_t)P.n_render ? P.train_sample : sample;
 }
 
 // ---------------------------------------------------------------- generate
@@ -221,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_generate(PathsDev P, CamDev C, uint3
   for (int slot = blockIdx.x * kBlock + threadIdx.x; slot < n; slot += gridDim.x * kBlock) {
     uint32_t pix = slot_pixel(P, (uint32_t)slot, (uint32_t)C.W);
     int px = (int)(pix % (uint32_t)C.W), py = (int)(pix / (uint32_t)C.W);
-    U4 r = philox(pix, sample, 0u, 0u, k0, k1);
+    U4 r = philox(pix, slot_sample(P, (uint32_t)slot, sample), 0u, 0u, k0, k1);
     float fx = (float)px + u01(r.x), fy = (float)py + u01(r.y);
     float x = (2.0f * fx / (float)C.W - 1.0f) * C.tan_half * C.aspect;
     float y = (1.0f - 2.0f * fy / (float)C.H) * C.tan_half;
@@ -233,8 +238,9 @@ __global__ __launch_bounds__(kBlock) void k_generate(PathsDev P, CamDev C, uint3
     P.flags[slot] = 1u;
     P.q_ray[0][slot] = (uint32_t)slot;
     if (DEBUG) P.sig[slot] = kFnvOffset;
-    if (P.rec)
-      for (int r = 0; r < P.rec_depth; ++r) P.rec[((size_t)slot * P.rec_depth + r) * kNrcRecFloats + 18] = 0.0f;
+    if (P.rec && slot >= P.n_render)
+      for (int r = 0; r < P.rec_depth; ++r)
+        P.rec[((size_t)(slot - P.n_render) * P.rec_depth + r) * kNrcRecFloats + 18] = 0.0f;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     P.counts[0] = (uint32_t)n;
@@ -419,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b,
         V3 n = entering ? ng : ng * -1.0f;
         if (b == max_depth) {
           end_ev = 1;
-        } else if (b == nrc_bounce) {
+        } else if (b == nrc_bounce && slot < (uint32_t)P.n_render) {
           // the path ends in the radiance cache: the query adds beta * cache(x) after the pass
           float* qr = P.nrc_q + (size_t)slot * kNrcQueryFloats;
           nrc_inputs(S.box_lo, S.box_inv, p, wo_w, n, m, qr);
@@ -429,8 +435,8 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b,
           query = true;
           end_ev = 4;
         } else {
-          if (P.rec) {  // training record: inputs, radiance so far, throughput
-            float* rr = P.rec + ((size_t)slot * P.rec_depth + b) * kNrcRecFloats;
+          if (P.rec && slot >= (uint32_t)P.n_render) {  // training record: inputs, radiance so far, throughput
+            float* rr = P.rec + ((size_t)(slot - P.n_render) * P.rec_depth + b) * kNrcRecFloats;
             nrc_inputs(S.box_lo, S.box_inv, p, wo_w, n, m, rr);
             rr[12] = L.x;
             rr[13] = L.y;
@@ -445,7 +451,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b,
           V3 wo = v3(dot(wo_w, t), dot(wo_w, bt), dot(wo_w, n));
           Bsdf B = bsdf_setup<CLS>(m, entering, wo.z);
           if (wo.z <= 0.0f) B.absorbed = true;
-          Rng rng{slot_pixel(P, slot, img_w), sample, k0, k1};
+          Rng rng{slot_pixel(P, slot, img_w), slot_sample(P, slot, sample), k0, k1};
           U4 r0 = rng.block((uint32_t)b, 0u), r1 = rng.block((uint32_t)b, 1u);
           // next-event estimation
           if (!B.absorbed && bsdf_has_nondelta<CLS>(m, B)) {
@@ -590,7 +596,7 @@ __global__ __launch_bounds__(kBlock) void k_connect(SceneDev S, PathsDev P) {
 // FP64 per-pixel running sums: one writer per pixel per pass, no atomics.
 __global__ __launch_bounds__(kBlock) void k_accumulate(PathsDev P, double* sum, int W, float* per_sample,
                                                        uint64_t* sig_out, int spp_total, int sample_index) {
-  for (int slot = blockIdx.x * kBlock + threadIdx.x; slot < P.n; slot += gridDim.x * kBlock) {
+  for (int slot = blockIdx.x * kBlock + threadIdx.x; slot < P.n_render; slot += gridDim.x * kBlock) {
     float4 L = P.L[slot];
     if (sum) {
       int px = P.x0 + slot % P.w, py = P.y0 + slot / P.w;
@@ -689,9 +695,11 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
     if (e != hipSuccess) return e;
     if (b < A.max_depth) hipLaunchKernelGGL((k_connect<DEBUG, COUNT, TWO>), dim3(A.grid_trace), blk, 0, st, S, P);
     if (b == A.nrc_bounce) {  // every path still alive ended in the cache at this vertex
+      if (A.nrc_events) hipEventRecord(A.nrc_events[0], st);
       hipError_t e2 = nrc_launch_query(P, A.nrc_fwd, std::min(A.grid, 1024), st);
+      if (A.nrc_events) hipEventRecord(A.nrc_events[1], st);
       if (e2 != hipSuccess) return e2;
-      break;
+      if (P.n == P.n_render) break;  // no training paths: nothing continues
     }
   }
   return hipGetLastError();
@@ -723,7 +731,7 @@ static int blocks_for(int64_t n) {
 
 hipError_t launch_accumulate(const PathsDev& P, double* sum, int W, float* per_sample, uint64_t* sig_out,
                              int spp_total, int sample_index, hipStream_t st) {
-  hipLaunchKernelGGL(k_accumulate, dim3(blocks_for(P.n)), dim3(kBlock), 0, st, P, sum, W, per_sample, sig_out,
+  hipLaunchKernelGGL(k_accumulate, dim3(blocks_for(P.n_render)), dim3(kBlock), 0, st, P, sum, W, per_sample, sig_out,
                      spp_total, sample_index);
   return hipGetLastError();
 }

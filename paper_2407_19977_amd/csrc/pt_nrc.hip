@@ -139,6 +139,7 @@ __global__ __launch_bounds__(256) void k_nrc_infer(const float* __restrict__ xin
   for (int i = threadIdx.x; i < kNrcFwdFrags * 64; i += blockDim.x) sw[i] = fwd[i];
   __syncthreads();
   const int64_t n = MODE == 1 ? (int64_t)P.counts[kCountQuery] : n_arg;
+  if (MODE == 1 && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&P.stats[kStatQueries], (unsigned long long)n);
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, g = lane / 16, q = lane % 16;
   unsigned long long nonfinite = 0;
   for (int64_t grp = (int64_t)blockIdx.x * 4 + wave; grp * 16 < n; grp += (int64_t)gridDim.x * 4) {
@@ -363,7 +364,7 @@ __device__ inline bool nrc_target(const float* rec, float4 Lend, float t[3]) {
 __global__ __launch_bounds__(256) void k_nrc_count(PathsDev P, int n_paths, uint32_t* __restrict__ counts) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_paths) return;
-  float4 Le = P.L[k];
+  float4 Le = P.L[P.n_render + k];
   uint32_t c = 0;
   for (int r = 0; r < P.rec_depth; ++r) {
     float t[3];
@@ -401,7 +402,7 @@ __global__ __launch_bounds__(256) void k_nrc_compact(PathsDev P, int n_paths, co
                                                      float* __restrict__ X, float* __restrict__ T) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_paths) return;
-  float4 Le = P.L[k];
+  float4 Le = P.L[P.n_render + k];
   uint32_t o = offsets[k];
   for (int r = 0; r < P.rec_depth; ++r) {
     const float* rec = P.rec + ((size_t)k * P.rec_depth + r) * kNrcRecFloats;

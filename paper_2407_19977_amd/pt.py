@@ -45,7 +45,9 @@ class pt_stats(C.Structure):
     _fields_ = [("extension_rays", C.c_int64), ("shadow_rays", C.c_int64), ("nonfinite_dropped", C.c_int64),
                 ("samples", C.c_int64), ("ms_extend", C.c_double), ("launches_extend", C.c_int64),
                 ("ms_total", C.c_double), ("node_visits", C.c_int64), ("tri_tests", C.c_int64),
-                ("shadow_node_visits", C.c_int64), ("shadow_tri_tests", C.c_int64)]
+                ("shadow_node_visits", C.c_int64), ("shadow_tri_tests", C.c_int64),
+                ("cache_queries", C.c_int64), ("cache_records", C.c_int64), ("cache_adam_steps", C.c_int64),
+                ("ms_cache_query", C.c_double), ("ms_cache_train", C.c_double)]
 
 
 class pt_bvh_info(C.Structure):

@@ -499,7 +499,7 @@ pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h,
   if (r) return r;
   r = ensure_counters(s);
   if (r) return r;
-  int grid = grid_for(slots), grid_trace = grid_for(slots);
+  int grid = grid_for(slots), grid_trace = traversal_grid(slots);
   r = ensure_spill(s, grid_trace);
   if (r) return r;
   SceneDev S = scene_dev(s, grid_trace);
@@ -666,7 +666,7 @@ pt_status nrc_trace_training(pt_scene* s, const CamDev& C, uint32_t frame, int m
   pt_status r = ensure_paths(s, n);
   if (r) return r;
   if ((r = ensure_counters(s))) return r;
-  int grid = grid_for(n), grid_trace = grid_for(n);
+  int grid = grid_for(n), grid_trace = traversal_grid(n);
   if ((r = ensure_spill(s, grid_trace))) return r;
   SceneDev S = scene_dev(s, grid_trace);
   PathsDev P = paths_dev(s, 0, 0, 0, 1);

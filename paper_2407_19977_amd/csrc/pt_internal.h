@@ -15,7 +15,13 @@
 namespace pt {
 
 constexpr int kBlock = 256;     // threads per workgroup (4 waves of 64)
-constexpr int kLdsStack = 16;   // traversal stack entries per lane kept in LDS
+#ifndef PT_LDS_STACK
+#define PT_LDS_STACK 12
+#endif
+#ifndef PT_DYNAMIC_FETCH
+#define PT_DYNAMIC_FETCH 0
+#endif
+constexpr int kLdsStack = PT_LDS_STACK;  // traversal stack entries per lane kept in LDS
 
 // Scene data the kernels read (all device pointers).
 struct SceneDev {
@@ -106,6 +112,8 @@ enum {
 };
 constexpr int kCountShadow = 2 + kNumClasses;
 constexpr int kCountQuery = kCountShadow + 1;
+constexpr int kCountFetchExt = kCountShadow + 2;  // work counters of the traversal kernels
+constexpr int kCountFetchShadow = kCountShadow + 3;
 constexpr int kNumCounts = 16;
 
 // ---- kernel launchers (pt_kernels.hip) ----
@@ -135,6 +143,7 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st);
 hipError_t launch_trace_rays(const SceneDev& S, const float* rays, int64_t n, uint32_t* hits, bool brute,
                              bool two_level, int grid, hipStream_t st);
 int trace_grid_blocks();
+int traversal_grid(int64_t rays);  // workgroups of k_extend / k_connect for a pass of `rays` paths
 
 // ---- radiance cache (pt_nrc.hip) ----
 hipError_t nrc_launch_pack(const float* w, uint4* fwd, uint4* bwd, hipStream_t st);

@@ -66,21 +66,25 @@ __device__ inline uint64_t sig_tail(uint64_t h, uint32_t tail) {
 }
 
 // ----------------------------------------------------------------- stacks
-// Traversal stack: the first kLdsStack entries of each lane in LDS (entry
-// e of lane l at [e][l], conflict-free), deeper entries in a global spill
-// area.  The capacity (3 x BVH depth + 4) bounds a depth-first walk that
-// pushes at most three siblings per level.
+// Traversal stack: the first kLdsStack entries of each lane in LDS as
+// (ref, key) pairs, entry e of lane l at [e][l] (one 8-byte access per push
+// or pop, conflict-free), deeper entries in a global spill area.  The LDS
+// pointer keeps its address space so pops are LDS reads, not flat loads.
+// The capacity (3 x BVH depth + 4) bounds a depth-first walk that pushes at
+// most three siblings per level.
+typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+__device__ inline unsigned long long stack_entry(uint32_t r, float k) {
+  return (unsigned long long)r | ((unsigned long long)f2u(k) << 32);
+}
 struct DevStack {
-  uint32_t* lref;
-  float* lkey;
+  lds_u64* lds;
   uint2* spill;
   uint32_t sstride;
   int sp, cap;
   bool overflow;
   __device__ inline void push(uint32_t r, float k) {
     if (sp < kLdsStack) {
-      lref[sp * kBlock] = r;
-      lkey[sp * kBlock] = k;
+      lds[sp * kBlock] = stack_entry(r, k);
     } else if (sp < cap) {
       spill[(size_t)(sp - kLdsStack) * sstride] = make_uint2(r, f2u(k));
     } else {
@@ -91,16 +95,20 @@ struct DevStack {
   }
   __device__ inline uint32_t pop(float& k) {
     --sp;
-    if (sp < kLdsStack) {
-      k = lkey[sp * kBlock];
-      return lref[sp * kBlock];
-    }
-    uint2 v = spill[(size_t)(sp - kLdsStack) * sstride];
-    k = u2f(v.y);
-    return v.x;
+    // the LDS read is unconditional (clamped index) so it stays an LDS access;
+    // the rare spill read replaces it
+    unsigned long long w = lds[(sp < kLdsStack ? sp : kLdsStack - 1) * kBlock];
+    if (sp >= kLdsStack)  // a relaxed atomic load is never merged with the LDS read into a flat load
+      w = __hip_atomic_load(reinterpret_cast<unsigned long long*>(spill + (size_t)(sp - kLdsStack) * sstride),
+                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    k = u2f((uint32_t)(w >> 32));
+    return (uint32_t)w;
   }
   __device__ inline int size() const { return sp; }
 };
+__device__ inline lds_u64* lds_stack_base(unsigned long long* shared_stack) {
+  return (lds_u64*)(shared_stack + threadIdx.x);
+}
 
 // ------------------------------------------------------------------ lights
 __device__ inline int env_texel(const SceneDev& S, V3 d, float& sin_t) {
@@ -251,7 +259,23 @@ __global__ __launch_bounds__(kBlock) void k_generate(PathsDev P, CamDev C, uint3
 __global__ void k_reset_counts(uint32_t* counts, int next_queue) {
   int i = threadIdx.x;
   if (i >= 2 && i <= kCountShadow) counts[i] = 0u;
+  if (i == kCountFetchExt || i == kCountFetchShadow) counts[i] = 0u;
   if (i == next_queue) counts[i] = 0u;
+}
+
+// Next batch of 64 work items for this wave: taken from a work counter
+// (waves that finish early take more) or, without dynamic fetching, the
+// wave's grid-stride sequence.  Wave-uniform.
+__device__ inline uint32_t next_batch(uint32_t* ctr, uint32_t& cursor) {
+#if PT_DYNAMIC_FETCH
+  uint32_t base = 0;
+  if (lane_id() == 0) base = atomicAdd(ctr, 64u);
+  return __shfl(base, 0);
+#else
+  uint32_t b = cursor;
+  cursor += gridDim.x * kBlock;
+  return b;
+#endif
 }
 
 // ------------------------------------------------------------------ extend
@@ -270,15 +294,16 @@ __device__ inline bool trace_ray(const SceneDev& S, float ox, float oy, float oz
 
 template <bool COUNT, bool TWO>
 __global__ __launch_bounds__(kBlock) void k_extend(SceneDev S, PathsDev P, int cur) {
-  __shared__ uint32_t s_ref[kLdsStack * kBlock];
-  __shared__ float s_key[kLdsStack * kBlock];
+  __shared__ unsigned long long s_stack[kLdsStack * kBlock];
   const uint32_t count = P.counts[cur];
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&P.stats[kStatExt], (unsigned long long)count);
   const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
   uint32_t nvis = 0, ntri = 0;
   bool overflow = false;
-  for (uint32_t base = blockIdx.x * kBlock; base < count; base += gridDim.x * kBlock) {
-    uint32_t i = base + threadIdx.x;
+  uint32_t cursor = blockIdx.x * kBlock + (threadIdx.x & ~63u);
+  for (uint32_t base = next_batch(&P.counts[kCountFetchExt], cursor); base < count;
+       base = next_batch(&P.counts[kCountFetchExt], cursor)) {
+    uint32_t i = base + lane_id();
     bool active = i < count;
     int cls = -1;
     uint32_t slot = 0;
@@ -287,7 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_extend(SceneDev S, PathsDev P, int c
       float4 o = P.ray_o[slot], d = P.ray_d[slot];
       Hit h;
       hit_clear(h);
-      DevStack st{s_ref + threadIdx.x, s_key + threadIdx.x, S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
+      DevStack st{lds_stack_base(s_stack), S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
       trace_ray<false, COUNT, TWO>(S, o.x, o.y, o.z, d.x, d.y, d.z, S.tmin, INFINITY, f2u(d.w), f2u(o.w), h, st,
                                    nvis, ntri);
       overflow |= st.overflow;
@@ -548,20 +573,23 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b,
 // ----------------------------------------------------------------- connect
 template <bool DEBUG, bool COUNT, bool TWO>
 __global__ __launch_bounds__(kBlock) void k_connect(SceneDev S, PathsDev P) {
-  __shared__ uint32_t s_ref[kLdsStack * kBlock];
-  __shared__ float s_key[kLdsStack * kBlock];
+  __shared__ unsigned long long s_stack[kLdsStack * kBlock];
   const uint32_t count = P.counts[kCountShadow];
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&P.stats[kStatShadow], (unsigned long long)count);
   const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
   uint32_t nvis = 0, ntri = 0;
   bool overflow = false;
   unsigned long long nonfinite = 0;
-  for (uint32_t i = gtid; i < count; i += gridDim.x * kBlock) {
+  uint32_t cursor = blockIdx.x * kBlock + (threadIdx.x & ~63u);
+  for (uint32_t base = next_batch(&P.counts[kCountFetchShadow], cursor); base < count;
+       base = next_batch(&P.counts[kCountFetchShadow], cursor)) {
+    uint32_t i = base + lane_id();
+    if (i >= count) continue;
     float4 o = P.sh_o[i], d = P.sh_d[i], c = P.sh_c[i];
     uint32_t slot = f2u(d.w);
     Hit h;
     hit_clear(h);
-    DevStack st{s_ref + threadIdx.x, s_key + threadIdx.x, S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
+    DevStack st{lds_stack_base(s_stack), S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
     uint32_t skip_inst = TWO ? P.sh_inst[i] : 0u;
     bool occ = trace_ray<true, COUNT, TWO>(S, o.x, o.y, o.z, d.x, d.y, d.z, S.tmin, o.w, skip_inst, f2u(c.w), h, st,
                                            nvis, ntri);
@@ -631,8 +659,7 @@ __global__ __launch_bounds__(kBlock) void k_zero_u64(unsigned long long* p, int6
 // ------------------------------------------------------- ray query kernels
 template <bool BRUTE, bool TWO>
 __global__ __launch_bounds__(kBlock) void k_trace_rays(SceneDev S, const float* rays, int64_t n, uint32_t* hits) {
-  __shared__ uint32_t s_ref[kLdsStack * kBlock];
-  __shared__ float s_key[kLdsStack * kBlock];
+  __shared__ unsigned long long s_stack[kLdsStack * kBlock];
   const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
   for (int64_t i = gtid; i < n; i += (int64_t)gridDim.x * kBlock) {
     const float* R = rays + 8 * i;
@@ -644,7 +671,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays(SceneDev S, const float* 
       if (TWO) brute_force_two_level(S.insts, S.n_insts, S.tris, S.mesh_tri_first, S.mesh_tri_count, r, R[3], R[7], h);
       else brute_force<false>(S.tris, S.n_tris, r, R[3], R[7], 0u, h, nt);
     } else {
-      DevStack st{s_ref + threadIdx.x, s_key + threadIdx.x, S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
+      DevStack st{lds_stack_base(s_stack), S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
       trace_ray<false, false, TWO>(S, R[0], R[1], R[2], R[4], R[5], R[6], R[3], R[7], 0xFFFFFFFFu, 0xFFFFFFFFu, h,
                                    st, nv, nt);
     }
@@ -661,6 +688,26 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays(SceneDev S, const float* 
 
 // --------------------------------------------------------------- launchers
 int trace_grid_blocks() { return 2048; }
+
+// With dynamic fetching one resident set of workgroups serves the whole
+// queue; the grid is what fits on the device at once.
+int traversal_grid(int64_t rays) {
+  int64_t need = std::max<int64_t>(1, (rays + kBlock - 1) / kBlock);
+#if PT_DYNAMIC_FETCH
+  static int resident = 0;
+  if (!resident) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_extend<false, false>, kBlock, 0) != hipSuccess || per < 1)
+      per = 1;
+    resident = std::max(1, cus * per);
+  }
+  return (int)std::min<int64_t>(need, resident);
+#else
+  return (int)std::min<int64_t>(need, 2048);
+#endif
+}
 
 template <bool DEBUG, bool TWO>
 static hipError_t shade_all(const SceneDev& S, const PathsDev& P, const PassArgs& A, int b, int next, uint32_t W,

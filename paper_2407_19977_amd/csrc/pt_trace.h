@@ -154,9 +154,11 @@ __host__ __device__ inline bool leaf_test(const TriRec* __restrict__ tris, uint3
     const TriRec tr = tris[first + j];
     if (COUNT) ntri++;
     uint32_t prim = f2u(tr.a.w);
-    if (inst == skip_inst && prim == skip_prim) continue;
+    // intersect before the origin-triangle check so the record's three loads
+    // issue together instead of waiting on the primitive id first
     float t, b1, b2;
-    if (!tri_intersect(r, tr.a, tr.b, tr.c, t, b1, b2)) continue;
+    bool hit = tri_intersect(r, tr.a, tr.b, tr.c, t, b1, b2);
+    if (!hit || (inst == skip_inst && prim == skip_prim)) continue;
     if (!(t > tmin && t < tmax)) continue;
     if (!hit_better(t, inst, prim, best)) continue;
     best.t = t;

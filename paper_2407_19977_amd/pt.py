@@ -113,6 +113,9 @@ _SIGS = {
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+# torch owns device memory and streams: load its HIP runtime first so that the
+# library binds to the same runtime instead of bringing a second one.
+import torch  # noqa: E402,F401
 _lib = C.CDLL(LIB_PATH)
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)

@@ -116,7 +116,7 @@ struct pt_scene {
   float p_env = 0.0f;
   // path state
   int64_t capacity = 0;
-  DevBuf ray_o, ray_d, hit, hit_inst, beta, L, flags, q_ray[2], q_cls[kNumClasses], sh_o, sh_d, sh_c, sh_inst,
+  DevBuf ray_o, ray_d, hit, hit_inst, cls, beta, L, flags, q_ray[2], q_cls[kNumClasses], sh_o, sh_d, sh_c, sh_inst,
       counts, stats, sig, dbg_nee, dbg_tail, spill;
   // accumulation
   DevBuf sum;
@@ -290,6 +290,7 @@ pt_status ensure_paths(pt_scene* s, int64_t n) {
   PT_HIP(s->ray_d.alloc(f4));
   PT_HIP(s->hit.alloc(f4));
   PT_HIP(s->hit_inst.alloc(u4));
+  PT_HIP(s->cls.alloc((size_t)n));
   PT_HIP(s->sh_inst.alloc(u4));
   PT_HIP(s->beta.alloc(f4));
   PT_HIP(s->L.alloc(f4));
@@ -304,6 +305,10 @@ pt_status ensure_paths(pt_scene* s, int64_t n) {
   PT_HIP(s->dbg_tail.alloc(u4));
   s->capacity = n;
   return PT_OK;
+}
+
+int bin_grid(int64_t n) {  // 1024 rays per workgroup iteration
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, 2048));
 }
 
 int grid_for(int64_t n) {
@@ -379,6 +384,7 @@ PathsDev paths_dev(pt_scene* s, int64_t n, int x0, int y0, int w) {
   P.ray_d = s->ray_d.as<float4>();
   P.hit = s->hit.as<float4>();
   P.hit_inst = s->hit_inst.as<uint32_t>();
+  P.cls = s->cls.as<uint8_t>();
   P.sh_inst = s->sh_inst.as<uint32_t>();
   P.beta = s->beta.as<float4>();
   P.L = s->L.as<float4>();
@@ -512,6 +518,7 @@ pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h,
   A.max_depth = max_depth;
   A.grid = grid;
   A.grid_trace = grid_trace;
+  A.grid_bin = bin_grid(slots);
   A.debug = per_sample != nullptr;
   A.count = s->counting;
   A.two_level = s->two_level;
@@ -679,6 +686,7 @@ pt_status nrc_trace_training(pt_scene* s, const CamDev& C, uint32_t frame, int m
   A.max_depth = max_depth;
   A.grid = grid;
   A.grid_trace = grid_trace;
+  A.grid_bin = bin_grid(n);
   A.two_level = s->two_level;
   A.class_mask = s->class_mask | (1u << kClsMiss);
   A.nrc_bounce = -1;
@@ -1420,11 +1428,11 @@ pt_status pt_nrc_training_records(pt_scene* s, const pt_camera* cam, int32_t fra
 pt_status pt_trace_closest(pt_scene* s, const float* rays, int64_t n, uint32_t* hits, int32_t brute) {
   pt_status r = check_scene(s);
   if (r) return r;
-  if (n < 0 || (n > 0 && (!rays || !hits))) return fail(PT_ERR_INVALID_ARG, "bad rays/hits");
+  if (n < 0 || n > 0x7FFFFFFF || (n > 0 && (!rays || !hits))) return fail(PT_ERR_INVALID_ARG, "bad rays/hits");
   if (!s->has_bvh) return fail(PT_ERR_STATE, "pt_build_bvh has not been called");
   if (n == 0) return PT_OK;
   if ((r = set_device(s))) return r;
-  int grid = trace_grid_blocks();
+  int grid = brute ? trace_grid_blocks() : traversal_grid(n);
   if ((r = ensure_spill(s, grid))) return r;
   SceneDev S = scene_dev(s, grid);
   PT_HIP(launch_trace_rays(S, rays, n, hits, brute != 0, s->two_level, grid, s->stream));

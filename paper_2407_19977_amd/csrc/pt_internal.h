@@ -18,9 +18,6 @@ constexpr int kBlock = 256;     // threads per workgroup (4 waves of 64)
 #ifndef PT_LDS_STACK
 #define PT_LDS_STACK 12
 #endif
-#ifndef PT_DYNAMIC_FETCH
-#define PT_DYNAMIC_FETCH 0
-#endif
 constexpr int kLdsStack = PT_LDS_STACK;  // traversal stack entries per lane kept in LDS
 
 // Scene data the kernels read (all device pointers).
@@ -71,6 +68,7 @@ struct PathsDev {
   float4* ray_d;       // d.xyz, skip instance (bits)
   float4* hit;         // t, b1, b2, triangle record index (bits; 0xFFFFFFFF = miss)
   uint32_t* hit_inst;  // instance of the hit (two-level scenes)
+  uint8_t* cls;        // material class of the hit (binning)
   float4* beta;        // throughput rgb, pdf of the last BSDF sample
   float4* L;           // radiance rgb, eta scale (product of eta^2 over refractions)
   uint32_t* flags;     // bit 0: last bounce was a delta lobe
@@ -112,8 +110,6 @@ enum {
 };
 constexpr int kCountShadow = 2 + kNumClasses;
 constexpr int kCountQuery = kCountShadow + 1;
-constexpr int kCountFetchExt = kCountShadow + 2;  // work counters of the traversal kernels
-constexpr int kCountFetchShadow = kCountShadow + 3;
 constexpr int kNumCounts = 16;
 
 // ---- kernel launchers (pt_kernels.hip) ----
@@ -123,6 +119,7 @@ struct PassArgs {
   int max_depth;
   int grid;         // workgroups of the persistent kernels
   int grid_trace;   // workgroups of the traversal kernels
+  int grid_bin;     // workgroups of the binning kernel
   bool debug;
   bool count;
   bool two_level;

@@ -259,93 +259,228 @@ __global__ __launch_bounds__(kBlock) void k_generate(PathsDev P, CamDev C, uint3
 __global__ void k_reset_counts(uint32_t* counts, int next_queue) {
   int i = threadIdx.x;
   if (i >= 2 && i <= kCountShadow) counts[i] = 0u;
-  if (i == kCountFetchExt || i == kCountFetchShadow) counts[i] = 0u;
   if (i == next_queue) counts[i] = 0u;
 }
 
-// Next batch of 64 work items for this wave: taken from a work counter
-// (waves that finish early take more) or, without dynamic fetching, the
-// wave's grid-stride sequence.  Wave-uniform.
-__device__ inline uint32_t next_batch(uint32_t* ctr, uint32_t& cursor) {
-#if PT_DYNAMIC_FETCH
-  uint32_t base = 0;
-  if (lane_id() == 0) base = atomicAdd(ctr, 64u);
-  return __shfl(base, 0);
-#else
-  uint32_t b = cursor;
-  cursor += gridDim.x * kBlock;
-  return b;
-#endif
+// ------------------------------------------------------------------ extend
+// Persistent lanes: each workgroup owns a contiguous share of the ray queue
+// and its lanes take rays from that share through an LDS counter.  A lane
+// advances its own walk one node or one leaf per loop iteration; when half
+// the wave is idle, the idle lanes take new rays, so the wave's SIMD lanes
+// stay busy instead of waiting for the longest ray of a fixed batch.  The
+// walk visits exactly what the recursive definition would (same culling and
+// child order), so the closest hit is unchanged bit for bit.
+constexpr uint32_t kNoInst = 0xFFFFFFFFu;
+
+struct LaneRay {
+  RayPre r;   // ray in the space of the current level
+  RayPre rw;  // world-space ray (two-level scenes)
+  float tmin, tmax;
+  uint32_t skip_inst, skip_prim;
+  uint32_t cur;    // next reference to process, kEmpty: pop
+  float cur_key;   // its entry distance
+  uint32_t inst;   // instance of the current mesh walk, kNoInst at the top level
+  int base;        // stack size when that mesh walk started
+  Hit best;
+};
+
+template <bool TWO>
+__device__ inline void lane_start(LaneRay& L, float ox, float oy, float oz, float dx, float dy, float dz, float tmin,
+                                  float tmax, uint32_t skip_inst, uint32_t skip_prim, uint32_t root) {
+  L.r = ray_prepare(ox, oy, oz, dx, dy, dz);
+  if (TWO) L.rw = L.r;
+  L.tmin = tmin;
+  L.tmax = tmax;
+  L.skip_inst = skip_inst;
+  L.skip_prim = skip_prim;
+  L.cur = root;
+  L.cur_key = -INFINITY;
+  L.inst = kNoInst;
+  L.base = 0;
+  hit_clear(L.best);
 }
 
-// ------------------------------------------------------------------ extend
-// Closest hit of one ray, single world-space BVH or two-level hierarchy.
+// One step of a lane's walk: visit one node, or test one leaf, then pop the
+// next entry that can still hold a closer hit.  In two-level scenes a
+// top-level leaf pushes its instances as entries (leaf bit, count 0,
+// instance id) that start a mesh walk on top of the stack.  Returns true when
+// the walk is over (ANY: also at the first accepted triangle).
 template <bool ANY, bool COUNT, bool TWO>
-__device__ inline bool trace_ray(const SceneDev& S, float ox, float oy, float oz, float dx, float dy, float dz,
-                                 float tmin, float tmax, uint32_t skip_inst, uint32_t skip_prim, Hit& h,
-                                 DevStack& st, uint32_t& nvis, uint32_t& ntri) {
-  RayPre r = ray_prepare(ox, oy, oz, dx, dy, dz);
-  if (TWO)
-    return traverse_two_level<ANY, COUNT>(S.tlas, S.tlas_items, S.insts, S.nodes, S.tris, r, tmin, tmax, skip_inst,
-                                          skip_prim, h, st, nvis, ntri);
-  return traverse_bvh<ANY, COUNT>(S.nodes, S.tris, S.root, r, tmin, tmax, 0u, skip_inst, skip_prim, h, st, nvis,
-                                  ntri);
+__device__ inline bool lane_step(const SceneDev& S, LaneRay& L, DevStack& st, uint32_t& nvis, uint32_t& ntri) {
+  const uint32_t cur = L.cur;
+  if (cur != kEmpty) {
+    if (!ref_is_leaf(cur)) {
+      const BVHNode* nodes = (TWO && L.inst == kNoInst) ? S.tlas : S.nodes;
+      const BVHNode n = nodes[cur];
+      if (COUNT) nvis++;
+      float tn[4];
+      float tcur = fminf(L.best.t, L.tmax);
+      uint32_t m = node_slabs(n, L.r, L.tmin, tcur, tn);
+      float k0 = (m & 1u) ? tn[0] : INFINITY, k1 = (m & 2u) ? tn[1] : INFINITY;
+      float k2 = (m & 4u) ? tn[2] : INFINITY, k3 = (m & 8u) ? tn[3] : INFINITY;
+      uint32_t r0 = (m & 1u) ? n.child[0] : kEmpty, r1 = (m & 2u) ? n.child[1] : kEmpty;
+      uint32_t r2 = (m & 4u) ? n.child[2] : kEmpty, r3 = (m & 8u) ? n.child[3] : kEmpty;
+      cswap(k0, r0, k1, r1);
+      cswap(k2, r2, k3, r3);
+      cswap(k0, r0, k2, r2);
+      cswap(k1, r1, k3, r3);
+      cswap(k1, r1, k2, r2);
+      if (r3 != kEmpty) st.push(r3, k3);
+      if (r2 != kEmpty) st.push(r2, k2);
+      if (r1 != kEmpty) st.push(r1, k1);
+      L.cur = r0;
+      L.cur_key = k0;
+      if (r0 != kEmpty) return false;
+    } else if (TWO && L.inst == kNoInst) {
+      const uint32_t first = leaf_first(cur), cnt = leaf_count(cur);
+      if (cnt == 0) {  // an instance entry: walk its mesh in object space
+        const InstRec& I = S.insts[first];
+        L.r = ray_to_object(I.w2o, L.rw.ox, L.rw.oy, L.rw.oz, L.rw.dx, L.rw.dy, L.rw.dz);
+        L.inst = first;
+        L.base = st.size();
+        L.cur = I.blas_root;
+        return false;
+      }
+      for (int j = (int)cnt - 1; j >= 0; --j) st.push(kLeafBit | S.tlas_items[first + j], L.cur_key);
+    } else {
+      if (leaf_test<ANY, COUNT>(S.tris, cur, L.r, L.tmin, L.tmax, TWO ? L.inst : 0u, L.skip_inst, L.skip_prim,
+                                L.best, ntri) && ANY)
+        return true;
+    }
+    L.cur = kEmpty;
+  }
+  while (true) {
+    if (TWO && L.inst != kNoInst && st.size() == L.base) {  // mesh walk over: back to the top level
+      L.inst = kNoInst;
+      L.r = L.rw;
+    }
+    if (st.size() == 0) return true;
+    float k;
+    uint32_t q = st.pop(k);
+    if (k <= fminf(L.best.t, L.tmax)) {
+      L.cur = q;
+      L.cur_key = k;
+      return false;
+    }
+  }
 }
+
+// The persistent-lane loop shared by the traversal kernels.  Src supplies
+// start(i, L) (load item i into the lane) and finish(i, L, found).
+template <bool ANY, bool COUNT, bool TWO, class Src>
+__device__ inline void persistent_trace(const SceneDev& S, Src& src, uint32_t count, unsigned long long* s_stack,
+                                        uint32_t* s_next, uint32_t& nvis, uint32_t& ntri, bool& overflow) {
+  const uint32_t per = (count + gridDim.x - 1) / gridDim.x;
+  const uint32_t b0 = min(count, blockIdx.x * per), b1 = min(count, b0 + per);
+  if (threadIdx.x == 0) *s_next = b0;
+  __syncthreads();
+  const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
+  DevStack st{lds_stack_base(s_stack), S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
+  LaneRay L;
+  bool busy = false, drained = false;
+  uint32_t item = 0;
+  while (true) {
+    const uint64_t idle = __ballot(!busy);
+    const uint32_t n_idle = (uint32_t)__popcll((unsigned long long)idle);
+    if (!drained && (n_idle >= 32u || n_idle == 64u)) {
+      uint32_t base = 0;
+      if (lane_id() == 0) base = atomicAdd(s_next, n_idle);
+      base = __shfl(base, 0);
+      if (base + n_idle >= b1) drained = true;
+      const uint32_t i = base + lane_prefix(idle);
+      if (!busy && i < b1) {
+        item = i;
+        st.sp = 0;
+        src.start(i, L);
+        busy = true;
+      }
+    }
+    if (__ballot(busy) == 0) break;
+    if (busy && lane_step<ANY, COUNT, TWO>(S, L, st, nvis, ntri)) {
+      src.finish(item, L, L.best.tri != 0xFFFFFFFFu);
+      busy = false;
+    }
+  }
+  overflow |= st.overflow;
+}
+
+template <bool TWO>
+struct ExtendSrc {
+  const SceneDev& S;
+  const PathsDev& P;
+  int cur;
+  __device__ inline void start(uint32_t i, LaneRay& L) {
+    uint32_t slot = P.q_ray[cur][i];
+    float4 o = P.ray_o[slot], d = P.ray_d[slot];
+    lane_start<TWO>(L, o.x, o.y, o.z, d.x, d.y, d.z, S.tmin, INFINITY, f2u(d.w), f2u(o.w), TWO ? 0u : S.root);
+  }
+  __device__ inline void finish(uint32_t i, const LaneRay& L, bool found) {
+    uint32_t slot = P.q_ray[cur][i];
+    int cls = kClsMiss;
+    if (found) {
+      P.hit[slot] = make_float4(L.best.t, L.best.b1, L.best.b2, u2f(L.best.tri));
+      uint32_t mid = L.best.mat;
+      if (TWO) {
+        P.hit_inst[slot] = L.best.inst;
+        int32_t ov = S.insts[L.best.inst].mat_override;
+        if (ov >= 0) mid = (uint32_t)ov;
+      }
+      cls = S.mats[mid].cls;
+    } else {
+      P.hit[slot] = make_float4(INFINITY, 0.0f, 0.0f, u2f(0xFFFFFFFFu));
+    }
+    P.cls[slot] = (uint8_t)cls;
+  }
+};
 
 template <bool COUNT, bool TWO>
 __global__ __launch_bounds__(kBlock) void k_extend(SceneDev S, PathsDev P, int cur) {
   __shared__ unsigned long long s_stack[kLdsStack * kBlock];
+  __shared__ uint32_t s_next;
   const uint32_t count = P.counts[cur];
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&P.stats[kStatExt], (unsigned long long)count);
-  const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
   uint32_t nvis = 0, ntri = 0;
   bool overflow = false;
-  uint32_t cursor = blockIdx.x * kBlock + (threadIdx.x & ~63u);
-  for (uint32_t base = next_batch(&P.counts[kCountFetchExt], cursor); base < count;
-       base = next_batch(&P.counts[kCountFetchExt], cursor)) {
-    uint32_t i = base + lane_id();
-    bool active = i < count;
-    int cls = -1;
-    uint32_t slot = 0;
-    if (active) {
-      slot = P.q_ray[cur][i];
-      float4 o = P.ray_o[slot], d = P.ray_d[slot];
-      Hit h;
-      hit_clear(h);
-      DevStack st{lds_stack_base(s_stack), S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
-      trace_ray<false, COUNT, TWO>(S, o.x, o.y, o.z, d.x, d.y, d.z, S.tmin, INFINITY, f2u(d.w), f2u(o.w), h, st,
-                                   nvis, ntri);
-      overflow |= st.overflow;
-      if (h.tri != 0xFFFFFFFFu) {
-        P.hit[slot] = make_float4(h.t, h.b1, h.b2, u2f(h.tri));
-        uint32_t mid = h.mat;
-        if (TWO) {
-          P.hit_inst[slot] = h.inst;
-          int32_t ov = S.insts[h.inst].mat_override;
-          if (ov >= 0) mid = (uint32_t)ov;
-        }
-        cls = S.mats[mid].cls;
-      } else {
-        P.hit[slot] = make_float4(INFINITY, 0.0f, 0.0f, u2f(0xFFFFFFFFu));
-        cls = kClsMiss;
-      }
-    }
-    // bin the path into its material class queue, one ballot per class present in the wave
-    uint64_t remaining = __ballot(active);
-    while (remaining) {
-      uint32_t leader = (uint32_t)__ffsll((unsigned long long)remaining) - 1u;
-      int c = __shfl(cls, (int)leader);
-      bool mine = active && cls == c;
-      uint32_t pos = wave_append(mine, &P.counts[2 + c]);
-      if (mine) P.q_cls[c][pos] = slot;
-      remaining &= ~__ballot(mine);
-    }
-  }
+  ExtendSrc<TWO> src{S, P, cur};
+  persistent_trace<false, COUNT, TWO>(S, src, count, s_stack, &s_next, nvis, ntri, overflow);
   if (COUNT) {
     atomicAdd(&P.stats[kStatNodes], (unsigned long long)nvis);
     atomicAdd(&P.stats[kStatTris], (unsigned long long)ntri);
   }
   if (overflow) atomicAdd(&P.stats[kStatOverflow], 1ull);
+}
+
+// Material binning of the rays just traced: a counting sort by class with
+// one atomic per class per workgroup (1024 rays).
+__global__ __launch_bounds__(kBlock) void k_bin(PathsDev P, int cur) {
+  __shared__ uint32_t s_cnt[kNumClasses], s_base[kNumClasses];
+  const uint32_t count = P.counts[cur];
+  for (uint32_t blk = blockIdx.x * (4u * kBlock); blk < count; blk += gridDim.x * (4u * kBlock)) {
+    if (threadIdx.x < kNumClasses) s_cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    uint32_t slot[4], pos[4];
+    int cls[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      uint32_t i = blk + k * kBlock + threadIdx.x;
+      cls[k] = -1;
+      if (i < count) {
+        slot[k] = P.q_ray[cur][i];
+        cls[k] = P.cls[slot[k]];
+        pos[k] = atomicAdd(&s_cnt[cls[k]], 1u);  // LDS
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumClasses) {
+      uint32_t c = s_cnt[threadIdx.x];
+      s_base[threadIdx.x] = c ? atomicAdd(&P.counts[2 + threadIdx.x], c) : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (cls[k] >= 0) P.q_cls[cls[k]][s_base[cls[k]] + pos[k]] = slot[k];
+    __syncthreads();
+  }
 }
 
 // ------------------------------------------------------------------- shade
@@ -571,34 +706,25 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b,
 }
 
 // ----------------------------------------------------------------- connect
-template <bool DEBUG, bool COUNT, bool TWO>
-__global__ __launch_bounds__(kBlock) void k_connect(SceneDev S, PathsDev P) {
-  __shared__ unsigned long long s_stack[kLdsStack * kBlock];
-  const uint32_t count = P.counts[kCountShadow];
-  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&P.stats[kStatShadow], (unsigned long long)count);
-  const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
-  uint32_t nvis = 0, ntri = 0;
-  bool overflow = false;
-  unsigned long long nonfinite = 0;
-  uint32_t cursor = blockIdx.x * kBlock + (threadIdx.x & ~63u);
-  for (uint32_t base = next_batch(&P.counts[kCountFetchShadow], cursor); base < count;
-       base = next_batch(&P.counts[kCountFetchShadow], cursor)) {
-    uint32_t i = base + lane_id();
-    if (i >= count) continue;
-    float4 o = P.sh_o[i], d = P.sh_d[i], c = P.sh_c[i];
-    uint32_t slot = f2u(d.w);
-    Hit h;
-    hit_clear(h);
-    DevStack st{lds_stack_base(s_stack), S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
-    uint32_t skip_inst = TWO ? P.sh_inst[i] : 0u;
-    bool occ = trace_ray<true, COUNT, TWO>(S, o.x, o.y, o.z, d.x, d.y, d.z, S.tmin, o.w, skip_inst, f2u(c.w), h, st,
-                                           nvis, ntri);
-    overflow |= st.overflow;
+template <bool DEBUG, bool TWO>
+struct ConnectSrc {
+  const SceneDev& S;
+  const PathsDev& P;
+  unsigned long long& nonfinite;
+  __device__ inline void start(uint32_t i, LaneRay& L) {
+    float4 o = P.sh_o[i], d = P.sh_d[i];
+    uint32_t skip_prim = f2u(P.sh_c[i].w);
+    if (TWO) lane_start<true>(L, o.x, o.y, o.z, d.x, d.y, d.z, S.tmin, o.w, P.sh_inst[i], skip_prim, 0u);
+    else lane_start<false>(L, o.x, o.y, o.z, d.x, d.y, d.z, S.tmin, o.w, 0u, skip_prim, S.root);
+  }
+  __device__ inline void finish(uint32_t i, const LaneRay& L, bool occ) {
+    uint32_t slot = f2u(P.sh_d[i].w);
     if (!occ) {
+      float4 c = P.sh_c[i];
       V3 cc = v3(c.x, c.y, c.z);
       if (finite3(cc)) {
-        float4 L = P.L[slot];
-        P.L[slot] = make_float4(L.x + cc.x, L.y + cc.y, L.z + cc.z, L.w);
+        float4 Lr = P.L[slot];
+        P.L[slot] = make_float4(Lr.x + cc.x, Lr.y + cc.y, Lr.z + cc.z, Lr.w);
       } else {
         nonfinite++;
       }
@@ -612,6 +738,19 @@ __global__ __launch_bounds__(kBlock) void k_connect(SceneDev S, PathsDev P) {
       P.sig[slot] = sig;
     }
   }
+};
+
+template <bool DEBUG, bool COUNT, bool TWO>
+__global__ __launch_bounds__(kBlock) void k_connect(SceneDev S, PathsDev P) {
+  __shared__ unsigned long long s_stack[kLdsStack * kBlock];
+  __shared__ uint32_t s_next;
+  const uint32_t count = P.counts[kCountShadow];
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&P.stats[kStatShadow], (unsigned long long)count);
+  uint32_t nvis = 0, ntri = 0;
+  bool overflow = false;
+  unsigned long long nonfinite = 0;
+  ConnectSrc<DEBUG, TWO> src{S, P, nonfinite};
+  persistent_trace<true, COUNT, TWO>(S, src, count, s_stack, &s_next, nvis, ntri, overflow);
   if (COUNT) {
     atomicAdd(&P.stats[kStatShadowNodes], (unsigned long long)nvis);
     atomicAdd(&P.stats[kStatShadowTris], (unsigned long long)ntri);
@@ -657,56 +796,73 @@ __global__ __launch_bounds__(kBlock) void k_zero_u64(unsigned long long* p, int6
 }
 
 // ------------------------------------------------------- ray query kernels
-template <bool BRUTE, bool TWO>
-__global__ __launch_bounds__(kBlock) void k_trace_rays(SceneDev S, const float* rays, int64_t n, uint32_t* hits) {
+// Closest hits of a ray array ([n][8]: o, tmin, d, tmax) -> [n][6] words.
+__device__ inline void write_hit(uint32_t* H, const Hit& h) {
+  bool hit = h.tri != 0xFFFFFFFFu;
+  H[0] = f2u(h.t);
+  H[1] = hit ? h.inst : 0xFFFFFFFFu;
+  H[2] = hit ? h.prim : 0xFFFFFFFFu;
+  H[3] = hit ? f2u(h.b1) : 0u;
+  H[4] = hit ? f2u(h.b2) : 0u;
+  H[5] = hit ? 1u : 0u;
+}
+
+template <bool TWO>
+struct RaysSrc {
+  const SceneDev& S;
+  const float* rays;
+  uint32_t* hits;
+  __device__ inline void start(uint32_t i, LaneRay& L) {
+    const float* R = rays + 8 * (size_t)i;
+    lane_start<TWO>(L, R[0], R[1], R[2], R[4], R[5], R[6], R[3], R[7], 0xFFFFFFFFu, 0xFFFFFFFFu, TWO ? 0u : S.root);
+  }
+  __device__ inline void finish(uint32_t i, const LaneRay& L, bool) { write_hit(hits + 6 * (size_t)i, L.best); }
+};
+
+template <bool TWO>
+__global__ __launch_bounds__(kBlock) void k_trace_rays(SceneDev S, const float* rays, uint32_t n, uint32_t* hits) {
   __shared__ unsigned long long s_stack[kLdsStack * kBlock];
-  const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
-  for (int64_t i = gtid; i < n; i += (int64_t)gridDim.x * kBlock) {
-    const float* R = rays + 8 * i;
+  __shared__ uint32_t s_next;
+  uint32_t nvis = 0, ntri = 0;
+  bool overflow = false;
+  RaysSrc<TWO> src{S, rays, hits};
+  persistent_trace<false, false, TWO>(S, src, n, s_stack, &s_next, nvis, ntri, overflow);
+}
+
+// The same definition by testing every triangle (and every instance).
+template <bool TWO>
+__global__ __launch_bounds__(kBlock) void k_trace_rays_brute(SceneDev S, const float* rays, uint32_t n,
+                                                             uint32_t* hits) {
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const float* R = rays + 8 * (size_t)i;
     Hit h;
     hit_clear(h);
-    uint32_t nv = 0, nt = 0;
-    if (BRUTE) {
-      RayPre r = ray_prepare(R[0], R[1], R[2], R[4], R[5], R[6]);
-      if (TWO) brute_force_two_level(S.insts, S.n_insts, S.tris, S.mesh_tri_first, S.mesh_tri_count, r, R[3], R[7], h);
-      else brute_force<false>(S.tris, S.n_tris, r, R[3], R[7], 0u, h, nt);
-    } else {
-      DevStack st{lds_stack_base(s_stack), S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
-      trace_ray<false, false, TWO>(S, R[0], R[1], R[2], R[4], R[5], R[6], R[3], R[7], 0xFFFFFFFFu, 0xFFFFFFFFu, h,
-                                   st, nv, nt);
-    }
-    uint32_t* H = hits + 6 * i;
-    bool hit = h.tri != 0xFFFFFFFFu;
-    H[0] = f2u(h.t);
-    H[1] = hit ? h.inst : 0xFFFFFFFFu;
-    H[2] = hit ? h.prim : 0xFFFFFFFFu;
-    H[3] = hit ? f2u(h.b1) : 0u;
-    H[4] = hit ? f2u(h.b2) : 0u;
-    H[5] = hit ? 1u : 0u;
+    uint32_t nt = 0;
+    RayPre r = ray_prepare(R[0], R[1], R[2], R[4], R[5], R[6]);
+    if (TWO) brute_force_two_level(S.insts, S.n_insts, S.tris, S.mesh_tri_first, S.mesh_tri_count, r, R[3], R[7], h);
+    else brute_force<false>(S.tris, S.n_tris, r, R[3], R[7], 0u, h, nt);
+    write_hit(hits + 6 * (size_t)i, h);
   }
 }
 
 // --------------------------------------------------------------- launchers
 int trace_grid_blocks() { return 2048; }
 
-// With dynamic fetching one resident set of workgroups serves the whole
-// queue; the grid is what fits on the device at once.
+// The traversal kernels keep one resident set of workgroups (persistent
+// lanes); more would only queue behind them.
 int traversal_grid(int64_t rays) {
   int64_t need = std::max<int64_t>(1, (rays + kBlock - 1) / kBlock);
-#if PT_DYNAMIC_FETCH
   static int resident = 0;
   if (!resident) {
     int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
       cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_extend<false, false>, kBlock, 0) != hipSuccess || per < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_extend<false, true>, kBlock, 0) != hipSuccess || per < 1)
       per = 1;
     resident = std::max(1, cus * per);
   }
   return (int)std::min<int64_t>(need, resident);
-#else
-  return (int)std::min<int64_t>(need, 2048);
-#endif
 }
 
 template <bool DEBUG, bool TWO>
@@ -738,6 +894,7 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
     if (A.ext_events) hipEventRecord(A.ext_events[2 * b], st);
     hipLaunchKernelGGL((k_extend<COUNT, TWO>), dim3(A.grid_trace), blk, 0, st, S, P, cur);
     if (A.ext_events) hipEventRecord(A.ext_events[2 * b + 1], st);
+    hipLaunchKernelGGL(k_bin, dim3(A.grid_bin), blk, 0, st, P, cur);
     hipError_t e = shade_all<DEBUG, TWO>(S, P, A, b, next, (uint32_t)C.W, st);
     if (e != hipSuccess) return e;
     if (b < A.max_depth) hipLaunchKernelGGL((k_connect<DEBUG, COUNT, TWO>), dim3(A.grid_trace), blk, 0, st, S, P);
@@ -801,10 +958,11 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st) {
 hipError_t launch_trace_rays(const SceneDev& S, const float* rays, int64_t n, uint32_t* hits, bool brute,
                              bool two_level, int grid, hipStream_t st) {
   dim3 g(grid), blk(kBlock);
-  if (brute && two_level) hipLaunchKernelGGL((k_trace_rays<true, true>), g, blk, 0, st, S, rays, n, hits);
-  else if (brute) hipLaunchKernelGGL((k_trace_rays<true, false>), g, blk, 0, st, S, rays, n, hits);
-  else if (two_level) hipLaunchKernelGGL((k_trace_rays<false, true>), g, blk, 0, st, S, rays, n, hits);
-  else hipLaunchKernelGGL((k_trace_rays<false, false>), g, blk, 0, st, S, rays, n, hits);
+  const uint32_t nn = (uint32_t)n;
+  if (brute && two_level) hipLaunchKernelGGL((k_trace_rays_brute<true>), g, blk, 0, st, S, rays, nn, hits);
+  else if (brute) hipLaunchKernelGGL((k_trace_rays_brute<false>), g, blk, 0, st, S, rays, nn, hits);
+  else if (two_level) hipLaunchKernelGGL((k_trace_rays<true>), g, blk, 0, st, S, rays, nn, hits);
+  else hipLaunchKernelGGL((k_trace_rays<false>), g, blk, 0, st, S, rays, nn, hits);
   return hipGetLastError();
 }
 

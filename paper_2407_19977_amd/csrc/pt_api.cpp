@@ -138,7 +138,7 @@ struct pt_scene {
   DevBuf nrc_w, nrc_m, nrc_v, nrc_fwd, nrc_bwd;  // FP32 master weights, Adam moments, bf16 fragments
   DevBuf nrc_q, q_nrc;                           // per-slot query records, query list
   int64_t nrc_q_cap = 0;
-  DevBuf nrc_rec, nrc_off, nrc_n, nrc_X, nrc_T;  // training records, compaction
+  DevBuf nrc_rec, nrc_off, nrc_bsum, nrc_n, nrc_X, nrc_T;  // training records, compaction
   int64_t nrc_rec_cap = 0;
   DevBuf nrc_Xb, nrc_Tb, nrc_a, nrc_g, nrc_loss, nrc_dw;  // one training step's workspace
   int64_t nrc_ws_npad = 0;
@@ -466,6 +466,7 @@ pt_status setup_training(pt_scene* s, const CamDev& C, PathsDev& P, int64_t n_re
     s->nrc_rec_cap = n * depth;
   }
   PT_HIP(s->nrc_off.alloc((size_t)n * sizeof(uint32_t)));
+  PT_HIP(s->nrc_bsum.alloc((size_t)((n + 255) / 256) * sizeof(uint32_t)));
   if (!s->nrc_n.p) PT_HIP(s->nrc_n.alloc(sizeof(uint32_t)));
   const uint64_t WH = (uint64_t)C.W * (uint64_t)C.H;
   P.n = (int32_t)(n_render + n);
@@ -483,8 +484,8 @@ pt_status setup_training(pt_scene* s, const CamDev& C, PathsDev& P, int64_t n_re
 // Targets of the training paths of the last pass, compacted path by path; *n_records on the host.
 pt_status finish_training(pt_scene* s, const PathsDev& P, uint32_t* n_records) {
   const int n = P.n - P.n_render;
-  PT_HIP(nrc_launch_targets(P, n, s->nrc_off.as<uint32_t>(), s->nrc_X.as<float>(), s->nrc_T.as<float>(),
-                            s->nrc_n.as<uint32_t>(), s->stream));
+  PT_HIP(nrc_launch_targets(P, n, s->nrc_off.as<uint32_t>(), s->nrc_bsum.as<uint32_t>(), s->nrc_X.as<float>(),
+                            s->nrc_T.as<float>(), s->nrc_n.as<uint32_t>(), s->stream));
   PT_HIP(hipMemcpyAsync(n_records, s->nrc_n.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
   PT_HIP(hipStreamSynchronize(s->stream));
   return PT_OK;

@@ -151,8 +151,8 @@ hipError_t nrc_launch_train(const float* X, const float* T, int N, int npad, int
                             float* dw_part, hipStream_t st);
 hipError_t nrc_launch_adam(float* w, float* m, float* v, const float* dw_part, int n_split, float* grad_out, float lr,
                            float b1, float b2, float eps, int step, int apply, hipStream_t st);
-hipError_t nrc_launch_targets(const PathsDev& P, int n_paths, uint32_t* offsets, float* X, float* T,
-                              uint32_t* n_out, hipStream_t st);
+hipError_t nrc_launch_targets(const PathsDev& P, int n_paths, uint32_t* offsets, uint32_t* block_sums, float* X,
+                              float* T, uint32_t* n_out, hipStream_t st);
 hipError_t nrc_launch_gather(const float* X_all, const float* T_all, const uint32_t* n_all, int B, uint32_t frame,
                              int step, uint32_t k0, uint32_t k1, float* Xb, float* Tb, hipStream_t st);
 constexpr int kNrcFbGrid = 256;  // workgroups of the forward+backward kernel

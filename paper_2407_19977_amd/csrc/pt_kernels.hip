@@ -271,6 +271,10 @@ __global__ void k_reset_counts(uint32_t* counts, int next_queue) {
 // walk visits exactly what the recursive definition would (same culling and
 // child order), so the closest hit is unchanged bit for bit.
 constexpr uint32_t kNoInst = 0xFFFFFFFFu;
+#ifndef PT_REFILL
+#define PT_REFILL 16
+#endif
+constexpr uint32_t kRefill = PT_REFILL;  // idle lanes that trigger a refill
 
 struct LaneRay {
   RayPre r;   // ray in the space of the current level
@@ -382,7 +386,7 @@ __device__ inline void persistent_trace(const SceneDev& S, Src& src, uint32_t co
   while (true) {
     const uint64_t idle = __ballot(!busy);
     const uint32_t n_idle = (uint32_t)__popcll((unsigned long long)idle);
-    if (!drained && (n_idle >= 32u || n_idle == 64u)) {
+    if (!drained && (n_idle >= kRefill || n_idle == 64u)) {
       uint32_t base = 0;
       if (lane_id() == 0) base = atomicAdd(s_next, n_idle);
       base = __shfl(base, 0);

@@ -361,29 +361,49 @@ __device__ inline bool nrc_target(const float* rec, float4 Lend, float t[3]) {
   return ok;
 }
 
-__global__ __launch_bounds__(256) void k_nrc_count(PathsDev P, int n_paths, uint32_t* __restrict__ counts) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n_paths) return;
-  float4 Le = P.L[P.n_render + k];
-  uint32_t c = 0;
-  for (int r = 0; r < P.rec_depth; ++r) {
-    float t[3];
-    c += nrc_target(P.rec + ((size_t)k * P.rec_depth + r) * kNrcRecFloats, Le, t) ? 1u : 0u;
+// Compaction in three kernels: per-path counts with per-workgroup sums, a
+// scan of the workgroup sums, and the in-workgroup scan + copy.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* s, uint32_t& total) {
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {  // Hillis-Steele inclusive scan
+    uint32_t u = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0u;
+    __syncthreads();
+    s[threadIdx.x] += u;
+    __syncthreads();
   }
-  counts[k] = c;
+  total = s[255];
+  return s[threadIdx.x] - v;
 }
 
-// In-place exclusive scan of the per-path counts (one workgroup); total to *n_out.
-__global__ __launch_bounds__(1024) void k_nrc_scan(int n_paths, uint32_t* __restrict__ offsets,
-                                                   uint32_t* __restrict__ n_out) {
+__global__ __launch_bounds__(256) void k_nrc_count(PathsDev P, int n_paths, uint32_t* __restrict__ counts,
+                                                   uint32_t* __restrict__ block_sums) {
+  __shared__ uint32_t s[256];
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t c = 0;
+  if (k < n_paths) {
+    float4 Le = P.L[P.n_render + k];
+    for (int r = 0; r < P.rec_depth; ++r) {
+      float t[3];
+      c += nrc_target(P.rec + ((size_t)k * P.rec_depth + r) * kNrcRecFloats, Le, t) ? 1u : 0u;
+    }
+    counts[k] = c;
+  }
+  uint32_t total;
+  block_exclusive_scan(c, s, total);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// In-place exclusive scan of the workgroup sums (one workgroup); total to *n_out.
+__global__ __launch_bounds__(1024) void k_nrc_scan(int n, uint32_t* __restrict__ sums, uint32_t* __restrict__ n_out) {
   __shared__ uint32_t part[1024];
-  const int per = (n_paths + 1023) / 1024;
-  const int k0 = min(n_paths, (int)threadIdx.x * per), k1 = min(n_paths, k0 + per);
+  const int per = (n + 1023) / 1024;
+  const int k0 = min(n, (int)threadIdx.x * per), k1 = min(n, k0 + per);
   uint32_t local = 0;
-  for (int k = k0; k < k1; ++k) local += offsets[k];
+  for (int k = k0; k < k1; ++k) local += sums[k];
   part[threadIdx.x] = local;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive scan
+  for (int off = 1; off < 1024; off <<= 1) {
     uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
     __syncthreads();
     part[threadIdx.x] += v;
@@ -391,25 +411,30 @@ __global__ __launch_bounds__(1024) void k_nrc_scan(int n_paths, uint32_t* __rest
   }
   uint32_t base = part[threadIdx.x] - local;
   for (int k = k0; k < k1; ++k) {
-    uint32_t c = offsets[k];
-    offsets[k] = base;
+    uint32_t c = sums[k];
+    sums[k] = base;
     base += c;
   }
   if (threadIdx.x == 1023) *n_out = part[1023];
 }
 
-__global__ __launch_bounds__(256) void k_nrc_compact(PathsDev P, int n_paths, const uint32_t* __restrict__ offsets,
-                                                     float* __restrict__ X, float* __restrict__ T) {
+__global__ __launch_bounds__(256) void k_nrc_compact(PathsDev P, int n_paths, uint32_t* __restrict__ offsets,
+                                                     const uint32_t* __restrict__ block_base, float* __restrict__ X,
+                                                     float* __restrict__ T) {
+  __shared__ uint32_t s[256];
   int k = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t c = k < n_paths ? offsets[k] : 0u;
+  uint32_t total;
+  uint32_t o = block_base[blockIdx.x] + block_exclusive_scan(c, s, total);
   if (k >= n_paths) return;
+  offsets[k] = o;
   float4 Le = P.L[P.n_render + k];
-  uint32_t o = offsets[k];
   for (int r = 0; r < P.rec_depth; ++r) {
     const float* rec = P.rec + ((size_t)k * P.rec_depth + r) * kNrcRecFloats;
     float t[3];
     if (!nrc_target(rec, Le, t)) continue;
     for (int i = 0; i < 12; ++i) X[(size_t)o * 12 + i] = rec[i];
-    for (int c = 0; c < 3; ++c) T[(size_t)o * 3 + c] = t[c];
+    for (int j = 0; j < 3; ++j) T[(size_t)o * 3 + j] = t[j];
     ++o;
   }
 }
@@ -475,11 +500,12 @@ hipError_t nrc_launch_adam(float* w, float* m, float* v, const float* dw_part, i
   return hipGetLastError();
 }
 
-hipError_t nrc_launch_targets(const PathsDev& P, int n_paths, uint32_t* offsets, float* X, float* T,
-                              uint32_t* n_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_nrc_count, dim3((n_paths + 255) / 256), dim3(256), 0, st, P, n_paths, offsets);
-  hipLaunchKernelGGL(k_nrc_scan, dim3(1), dim3(1024), 0, st, n_paths, offsets, n_out);
-  hipLaunchKernelGGL(k_nrc_compact, dim3((n_paths + 255) / 256), dim3(256), 0, st, P, n_paths, offsets, X, T);
+hipError_t nrc_launch_targets(const PathsDev& P, int n_paths, uint32_t* offsets, uint32_t* block_sums, float* X,
+                              float* T, uint32_t* n_out, hipStream_t st) {
+  const int nb = (n_paths + 255) / 256;
+  hipLaunchKernelGGL(k_nrc_count, dim3(nb), dim3(256), 0, st, P, n_paths, offsets, block_sums);
+  hipLaunchKernelGGL(k_nrc_scan, dim3(1), dim3(1024), 0, st, nb, block_sums, n_out);
+  hipLaunchKernelGGL(k_nrc_compact, dim3(nb), dim3(256), 0, st, P, n_paths, offsets, block_sums, X, T);
   return hipGetLastError();
 }
 

@@ -245,8 +245,10 @@ def main():
 
     roofline = None
     if counts is not None and st["launches_extend"] > 0:
+        # the wavefront closest-hit kernel only: the tail kernel's rays and visits are counted apart
+        ext_rays = counts["extension_rays"] - counts["tail_extension_rays"]
         ext_bytes = (counts["node_visits"] * NODE_BYTES + counts["tri_tests"] * TRI_BYTES +
-                     counts["extension_rays"] * (RAY_BYTES + HIT_BYTES))
+                     ext_rays * (RAY_BYTES + HIT_BYTES))
         launches_per_step = st["launches_extend"] / args.steps
         bytes_per_launch = ext_bytes / launches_per_step
         avg_ms = st["ms_extend"] / st["launches_extend"]
@@ -255,8 +257,11 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                     "kernel": "k_extend (BVH4 closest hit)",
                     "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": round(avg_ms, 4),
-                    "node_visits_per_ray": round(counts["node_visits"] / max(1, counts["extension_rays"]), 2),
-                    "tri_tests_per_ray": round(counts["tri_tests"] / max(1, counts["extension_rays"]), 2)}
+                    "node_visits_per_ray": round(counts["node_visits"] / max(1, ext_rays), 2),
+                    "tri_tests_per_ray": round(counts["tri_tests"] / max(1, ext_rays), 2),
+                    "tail_kernel": {"ms_per_step": round(st["ms_tail"] / args.steps, 3),
+                                    "launches_per_step": st["launches_tail"] / args.steps,
+                                    "extension_rays_per_step": st["tail_extension_rays"] // args.steps}}
 
     result = {
         "metric": METRIC, "value": round(mrays, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,

@@ -96,7 +96,12 @@ typedef struct pt_stats {
   int64_t cache_records;     /* training records produced by training paths */
   int64_t cache_adam_steps;  /* Adam steps taken since the cache was configured or given weights */
   double ms_cache_query;     /* summed time of the cache-query kernel (profiling on) */
-  double ms_cache_train;     /* summed time of training: training paths, targets, steps (profiling on) */
+  double ms_cache_train;     /* summed time of training: targets and Adam steps (profiling on) */
+  int64_t tail_extension_rays; /* closest-hit rays of the tail kernel (included in extension_rays) */
+  int64_t tail_node_visits;  /* their node fetches (counting on; not in node_visits) */
+  int64_t tail_tri_tests;    /* their triangle tests (counting on; not in tri_tests) */
+  double ms_tail;            /* summed time of the tail kernel (profiling on) */
+  int64_t launches_tail;     /* its launch count (profiling on) */
 } pt_stats;
 
 /* Create a scene bound to HIP device `hip_device` and stream `hip_stream`
@@ -258,6 +263,18 @@ pt_status pt_nrc_train(pt_scene* scene, const float* inputs, const float* target
 pt_status pt_nrc_training_records(pt_scene* scene, const pt_camera* camera, int32_t frame, int32_t max_depth,
                                   uint64_t seed, float* inputs, float* targets, uint32_t* path_offsets,
                                   int64_t capacity, int64_t* n_records);
+
+/* Tail hand-off of the sampling passes.  A pass runs the wavefront kernels
+ * (one launch per stage per bounce) while many paths are alive; from bounce
+ * min_bounce on, once at most max_fraction of the pass's paths are still
+ * alive, one persistent kernel runs all remaining vertices of every path
+ * (closest hit, shading, shadow ray, next ray) without a kernel boundary
+ * per bounce.  The decision reads one counter back per pass.  Results are
+ * identical either way (same arithmetic, same random numbers).  Defaults:
+ * min_bounce 3, max_fraction 0.125; max_fraction 0 (or min_bounce > 64)
+ * keeps the wavefront throughout.  Errors: INVALID_ARG for min_bounce < 0
+ * or max_fraction outside [0, 1]. */
+pt_status pt_set_tail(pt_scene* scene, int32_t min_bounce, double max_fraction);
 
 /* ---- host-only BVH access (no device needed) ---- */
 typedef struct pt_bvh_host pt_bvh_host;

@@ -145,6 +145,12 @@ struct pt_scene {
   int nrc_ws_split = 0;
   int64_t nrc_records = 0;
   double ms_cache_query = 0.0, ms_cache_train = 0.0;
+  // tail hand-off
+  int tail_min_bounce = 3;
+  double tail_fraction = 0.125;
+  uint32_t* tail_count = nullptr;  // pinned host word
+  double ms_tail = 0.0;
+  int64_t launches_tail = 0;
 };
 
 namespace {
@@ -536,15 +542,24 @@ pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h,
     P.nrc_q = s->nrc_q.as<float>();
     P.q_nrc = s->q_nrc.as<uint32_t>();
   }
-  int nev = 2 * (max_depth + 1) + 4;
+  int nev = 2 * (max_depth + 1) + 6;
+  if (!s->tail_count) PT_HIP(hipHostMalloc((void**)&s->tail_count, sizeof(uint32_t), hipHostMallocDefault));
+  if (s->tail_fraction > 0.0 && s->tail_min_bounce <= max_depth) {
+    A.tail_host_count = s->tail_count;
+    A.tail_min_bounce = s->tail_min_bounce;
+    A.tail_fraction = s->tail_fraction;
+  }
+  int wavefront_bounces = max_depth + 1;
+  A.wavefront_bounces = &wavefront_bounces;
   if (s->timing) {
     while ((int)s->events.size() < nev) {
       hipEvent_t e;
       PT_HIP(hipEventCreate(&e));
       s->events.push_back(e);
     }
-    A.ext_events = s->events.data() + 4;
+    A.ext_events = s->events.data() + 6;
     if (A.nrc_bounce >= 0) A.nrc_events = s->events.data() + 2;
+    A.tail_events = s->events.data() + 4;
   }
   for (int k = 0; k < n; ++k) {
     A.sample = (uint32_t)(first + k);
@@ -557,12 +572,17 @@ pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h,
       float ms = 0.0f;
       PT_HIP(hipEventElapsedTime(&ms, s->events[0], s->events[1]));
       s->ms_total += ms;
-      int last = max_depth;
-      if (A.nrc_bounce >= 0 && A.nrc_bounce < max_depth && P.n == P.n_render) last = A.nrc_bounce;  // stops there
+      int last = wavefront_bounces - 1;
+      if (A.nrc_bounce >= 0 && A.nrc_bounce < last && P.n == P.n_render) last = A.nrc_bounce;  // stops there
       for (int b = 0; b <= last; ++b) {
         PT_HIP(hipEventElapsedTime(&ms, A.ext_events[2 * b], A.ext_events[2 * b + 1]));
         s->ms_extend += ms;
         s->launches_extend++;
+      }
+      if (wavefront_bounces <= max_depth) {
+        PT_HIP(hipEventElapsedTime(&ms, A.tail_events[0], A.tail_events[1]));
+        s->ms_tail += ms;
+        s->launches_tail++;
       }
       if (A.nrc_events) {
         PT_HIP(hipEventElapsedTime(&ms, A.nrc_events[0], A.nrc_events[1]));
@@ -1036,6 +1056,7 @@ void pt_scene_destroy(pt_scene* s) {
   (void)hipSetDevice(s->device);
   (void)hipStreamSynchronize(s->stream);
   for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
+  if (s->tail_count) (void)hipHostFree(s->tail_count);
   delete s;
 }
 
@@ -1458,6 +1479,9 @@ pt_status pt_get_stats(pt_scene* s, pt_stats* o) {
     o->shadow_node_visits = (int64_t)v[kStatShadowNodes];
     o->shadow_tri_tests = (int64_t)v[kStatShadowTris];
     o->cache_queries = (int64_t)v[kStatQueries];
+    o->tail_extension_rays = (int64_t)v[kStatTailExt];
+    o->tail_node_visits = (int64_t)v[kStatTailNodes];
+    o->tail_tri_tests = (int64_t)v[kStatTailTris];
     if (v[kStatOverflow]) return fail(PT_ERR_DEVICE, "traversal stack overflow in %llu workgroups", v[kStatOverflow]);
   }
   o->samples = s->samples;
@@ -1468,6 +1492,8 @@ pt_status pt_get_stats(pt_scene* s, pt_stats* o) {
   o->cache_adam_steps = s->nrc_step;
   o->ms_cache_query = s->ms_cache_query;
   o->ms_cache_train = s->ms_cache_train;
+  o->ms_tail = s->ms_tail;
+  o->launches_tail = s->launches_tail;
   return PT_OK;
 }
 
@@ -1482,7 +1508,19 @@ pt_status pt_reset_stats(pt_scene* s) {
   s->samples = 0;
   s->nrc_records = 0;
   s->ms_cache_query = s->ms_cache_train = 0.0;
+  s->ms_tail = 0.0;
+  s->launches_tail = 0;
   return sync(s);
+}
+
+pt_status pt_set_tail(pt_scene* s, int32_t min_bounce, double max_fraction) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (min_bounce < 0) return fail(PT_ERR_INVALID_ARG, "min_bounce must be >= 0");
+  if (!(max_fraction >= 0.0 && max_fraction <= 1.0)) return fail(PT_ERR_INVALID_ARG, "max_fraction must be in [0, 1]");
+  s->tail_min_bounce = min_bounce;
+  s->tail_fraction = max_fraction;
+  return PT_OK;
 }
 
 pt_status pt_set_profiling(pt_scene* s, int32_t timing, int32_t counting) {

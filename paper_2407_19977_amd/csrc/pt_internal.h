@@ -16,7 +16,7 @@ namespace pt {
 
 constexpr int kBlock = 256;     // threads per workgroup (4 waves of 64)
 #ifndef PT_LDS_STACK
-#define PT_LDS_STACK 12
+#define PT_LDS_STACK 10
 #endif
 constexpr int kLdsStack = PT_LDS_STACK;  // traversal stack entries per lane kept in LDS
 
@@ -106,7 +106,10 @@ enum {
   kStatShadowNodes = 6,
   kStatShadowTris = 7,
   kStatQueries = 8,
-  kNumStats = 9
+  kStatTailExt = 9,     // closest-hit rays traced by the tail kernel (also in kStatExt)
+  kStatTailNodes = 10,  // their node visits and triangle tests (not in kStatNodes / kStatTris)
+  kStatTailTris = 11,
+  kNumStats = 12
 };
 constexpr int kCountShadow = 2 + kNumClasses;
 constexpr int kCountQuery = kCountShadow + 1;
@@ -128,6 +131,13 @@ struct PassArgs {
   int nrc_bounce;          // vertex at which paths end in the radiance cache, -1: no cache
   const uint4* nrc_fwd;    // packed forward weight fragments (when nrc_bounce >= 0)
   hipEvent_t* nrc_events;  // 2 events around the cache-query kernel when timing, else nullptr
+  // tail hand-off: from bounce tail_min_bounce on, when at most tail_fraction of the slots are
+  // still alive, one persistent kernel finishes the paths (tail_host_count: pinned host word)
+  uint32_t* tail_host_count;
+  int tail_min_bounce;
+  double tail_fraction;
+  hipEvent_t* tail_events;  // 2 events around the tail kernel when timing, else nullptr
+  int* wavefront_bounces;   // out: bounces run by the wavefront kernels (host)
 };
 
 hipError_t launch_pass(const SceneDev& S, const PathsDev& P, const CamDev& C, const PassArgs& A,
@@ -141,6 +151,7 @@ hipError_t launch_trace_rays(const SceneDev& S, const float* rays, int64_t n, ui
                              bool two_level, int grid, hipStream_t st);
 int trace_grid_blocks();
 int traversal_grid(int64_t rays);  // workgroups of k_extend / k_connect for a pass of `rays` paths
+int tail_grid(int grid_trace);     // workgroups of the tail kernel
 
 // ---- radiance cache (pt_nrc.hip) ----
 hipError_t nrc_launch_pack(const float* w, uint4* fwd, uint4* bwd, hipStream_t st);

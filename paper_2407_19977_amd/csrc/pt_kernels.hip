@@ -275,6 +275,14 @@ constexpr uint32_t kNoInst = 0xFFFFFFFFu;
 #define PT_REFILL 16
 #endif
 constexpr uint32_t kRefill = PT_REFILL;  // idle lanes that trigger a refill
+#ifndef PT_EXT_WAVES
+#define PT_EXT_WAVES 6
+#endif
+#ifndef PT_CONN_WAVES
+#define PT_CONN_WAVES 7
+#endif
+// minimum waves per SIMD the closest-hit and shadow-ray kernels are compiled for
+constexpr int kExtWaves = PT_EXT_WAVES, kConnWaves = PT_CONN_WAVES;
 
 struct LaneRay {
   RayPre r;   // ray in the space of the current level
@@ -438,7 +446,7 @@ struct ExtendSrc {
 };
 
 template <bool COUNT, bool TWO>
-__global__ __launch_bounds__(kBlock) void k_extend(SceneDev S, PathsDev P, int cur) {
+__global__ __launch_bounds__(kBlock, kExtWaves) void k_extend(SceneDev S, PathsDev P, int cur) {
   __shared__ unsigned long long s_stack[kLdsStack * kBlock];
   __shared__ uint32_t s_next;
   const uint32_t count = P.counts[cur];
@@ -488,225 +496,242 @@ __global__ __launch_bounds__(kBlock) void k_bin(PathsDev P, int cur) {
 }
 
 // ------------------------------------------------------------------- shade
+struct ShadeOut {
+  bool cont, shadow, query;  // next ray written / shadow ray below / path ended in the cache
+  float4 sh_o, sh_d, sh_c;   // shadow ray: o, tmax; d, path slot; contribution, skip primitive
+  uint32_t sh_inst;          // skip instance of the shadow ray
+};
+
+// Shade the hit (or miss) of path `slot` at vertex b: emission with MIS; at
+// the last vertex stop; at the cache vertex write a query and stop;
+// otherwise next-event estimation (a pre-weighted shadow ray), BSDF
+// sampling, Russian roulette and the next ray.
+template <int CLS, bool DEBUG, bool TWO>
+__device__ inline void shade_one(const SceneDev& S, const PathsDev& P, uint32_t slot, int b, int max_depth,
+                                 uint32_t sample, uint32_t k0, uint32_t k1, uint32_t img_w, int nrc_bounce,
+                                 ShadeOut& o, unsigned long long& nonfinite) {
+  o.cont = o.shadow = o.query = false;
+  float4 rd = P.ray_d[slot];
+  float4 be = P.beta[slot];
+  float4 Lr = P.L[slot];
+  uint32_t flags = P.flags[slot];
+  V3 beta = v3(be.x, be.y, be.z);
+  V3 L = v3(Lr.x, Lr.y, Lr.z);
+  float pdf_prev = be.w, eta_scale = Lr.w;
+  bool prev_delta = (flags & 1u) != 0u;
+  V3 d = v3(rd.x, rd.y, rd.z);
+  uint64_t sig = DEBUG ? P.sig[slot] : 0ull;
+  if (CLS == kClsMiss) {
+    if (S.env_w > 0) {
+      float st;
+      int texel = env_texel(S, d, st);
+      if (DEBUG) { sig = sig_word(sig, 2); sig = sig_word(sig, (uint32_t)texel); }
+      float4 e = S.env[texel];
+      float w = 1.0f;
+      if (!prev_delta) w = pow_heuristic(pdf_prev, S.p_env * env_pdf_texel(S, texel, st));
+      if (w > 0.0f) {
+        V3 c = v3(beta.x * w * e.x, beta.y * w * e.y, beta.z * w * e.z);
+        if (finite3(c)) L = L + c;
+        else nonfinite++;
+      }
+    } else if (DEBUG) {
+      sig = sig_word(sig, 2);
+      sig = sig_word(sig, 0xFFFFFFFFu);
+    }
+    if (DEBUG) { sig = sig_word(sig, 6); sig = sig_word(sig, 0); }
+    P.L[slot] = make_float4(L.x, L.y, L.z, eta_scale);
+    if (DEBUG) P.sig[slot] = sig;
+  } else {
+    float4 hv = P.hit[slot];
+    const TriRec tr = S.tris[f2u(hv.w)];
+    uint32_t prim = f2u(tr.a.w), mid = f2u(tr.b.w);
+    uint32_t inst = 0;
+    V3 p0 = v3(tr.a.x, tr.a.y, tr.a.z), p1 = v3(tr.b.x, tr.b.y, tr.b.z), p2 = v3(tr.c.x, tr.c.y, tr.c.z);
+    float b1 = hv.y, b2 = hv.z;
+    V3 p = p0 * (1.0f - b1 - b2) + p1 * b1 + p2 * b2;
+    V3 nc = cross(p1 - p0, p2 - p0);
+    V3 axis = v3(S.axis[0], S.axis[1], S.axis[2]);
+    int light_of_prim = -1;
+    if (TWO) {
+      inst = P.hit_inst[slot];
+      const InstRec& I = S.insts[inst];
+      if (I.mat_override >= 0) mid = (uint32_t)I.mat_override;
+      const float* q = I.o2w;
+      p = v3(q[0] * p.x + q[1] * p.y + q[2] * p.z + q[3], q[4] * p.x + q[5] * p.y + q[6] * p.z + q[7],
+             q[8] * p.x + q[9] * p.y + q[10] * p.z + q[11]);
+      nc = v3(q[0] * nc.x + q[1] * nc.y + q[2] * nc.z, q[4] * nc.x + q[5] * nc.y + q[6] * nc.z,
+              q[8] * nc.x + q[9] * nc.y + q[10] * nc.z);
+      axis = v3(q[2], q[6], q[10]);
+      if (I.light_map >= 0) light_of_prim = S.light_map[I.light_map + (int)prim];
+    } else {
+      light_of_prim = S.tri_light[prim];
+    }
+    const MatRec& m = S.mats[mid];
+    if (DEBUG) { sig = sig_word(sig, 1); sig = sig_word(sig, inst); sig = sig_word(sig, prim); }
+    V3 ng = normalize(nc);
+    V3 wo_w = d * -1.0f;
+    float cos_ng = dot(ng, wo_w);
+    // emission (front face only), MIS-weighted against light sampling
+    if ((m.flags & kMatEmissive) && cos_ng > 0.0f) {
+      float w = 1.0f;
+      if (!prev_delta) {
+        int k = light_of_prim;
+        float pl = 0.0f;
+        if (k >= 0 && S.n_lights > 0) {
+          const LightTri& Lt = S.lights[k];
+          pl = Lt.p1.w * hv.x * hv.x / (cos_ng * Lt.p0.w);
+        }
+        w = pow_heuristic(pdf_prev, pl);
+      }
+      if (w > 0.0f) {
+        V3 c = v3(beta.x * w * m.Le[0], beta.y * w * m.Le[1], beta.z * w * m.Le[2]);
+        if (finite3(c)) L = L + c;
+        else nonfinite++;
+      }
+    }
+    int lobe_ev = -1, rr_ev = 0, end_ev = 7;
+    bool pending = false;
+    uint32_t nee_id = 0xFFFFFFFFu, nee_out = 3u;
+    bool nee_done = false;
+    bool entering = cos_ng > 0.0f;
+    V3 n = entering ? ng : ng * -1.0f;
+    if (b == max_depth) {
+      end_ev = 1;
+    } else if (b == nrc_bounce && slot < (uint32_t)P.n_render) {
+      // the path ends in the radiance cache: the query adds beta * cache(x) after the pass
+      float* qr = P.nrc_q + (size_t)slot * kNrcQueryFloats;
+      nrc_inputs(S.box_lo, S.box_inv, p, wo_w, n, m, qr);
+      qr[12] = beta.x;
+      qr[13] = beta.y;
+      qr[14] = beta.z;
+      o.query = true;
+      end_ev = 4;
+    } else {
+      if (P.rec && slot >= (uint32_t)P.n_render) {  // training record: inputs, radiance so far, throughput
+        float* rr = P.rec + ((size_t)(slot - P.n_render) * P.rec_depth + b) * kNrcRecFloats;
+        nrc_inputs(S.box_lo, S.box_inv, p, wo_w, n, m, rr);
+        rr[12] = L.x;
+        rr[13] = L.y;
+        rr[14] = L.z;
+        rr[15] = beta.x;
+        rr[16] = beta.y;
+        rr[17] = beta.z;
+        rr[18] = 1.0f;
+      }
+      V3 t, bt;
+      make_frame(n, axis, t, bt);
+      V3 wo = v3(dot(wo_w, t), dot(wo_w, bt), dot(wo_w, n));
+      Bsdf B = bsdf_setup<CLS>(m, entering, wo.z);
+      if (wo.z <= 0.0f) B.absorbed = true;
+      Rng rng{slot_pixel(P, slot, img_w), slot_sample(P, slot, sample), k0, k1};
+      U4 r0 = rng.block((uint32_t)b, 0u), r1 = rng.block((uint32_t)b, 1u);
+      // next-event estimation
+      if (!B.absorbed && bsdf_has_nondelta<CLS>(m, B)) {
+        nee_done = true;
+        U4 r2 = rng.block((uint32_t)b, 2u);
+        LightSample ls = sample_light(S, p, u01(r1.w), u01(r2.x), u01(r2.y));
+        nee_id = ls.id;
+        if (ls.ok) {
+          V3 wil = v3(dot(ls.wl, t), dot(ls.wl, bt), dot(ls.wl, n));
+          float pb;
+          V3 f = bsdf_eval<CLS>(m, B, wo, wil, pb);
+          float w = pow_heuristic(ls.pdf, pb);
+          float k = fabsf(wil.z) * w / ls.pdf;
+          V3 c = v3(beta.x * f.x * ls.Le.x * k, beta.y * f.y * ls.Le.y * k, beta.z * f.z * ls.Le.z * k);
+          if (c.x != 0.0f || c.y != 0.0f || c.z != 0.0f) {
+            o.shadow = true;
+            pending = true;
+            float tmax = isinf(ls.dist) ? INFINITY : (1.0f - 1e-4f) * ls.dist;
+            o.sh_o = make_float4(p.x, p.y, p.z, tmax);
+            o.sh_d = make_float4(ls.wl.x, ls.wl.y, ls.wl.z, u2f(slot));
+            o.sh_c = make_float4(c.x, c.y, c.z, u2f(prim));
+            o.sh_inst = inst;
+          } else {
+            nee_out = 2u;
+          }
+        }
+      }
+      // BSDF sampling
+      BsdfSample bs = bsdf_sample<CLS>(m, B, wo, u01(r0.z), u01(r1.x), u01(r1.y), u01(r1.z));
+      lobe_ev = bs.lobe;
+      if (!bs.ok || (bs.weight.x == 0.0f && bs.weight.y == 0.0f && bs.weight.z == 0.0f)) {
+        end_ev = 2;
+      } else {
+        beta = v3(beta.x * bs.weight.x, beta.y * bs.weight.y, beta.z * bs.weight.z);
+        prev_delta = bs.delta;
+        pdf_prev = bs.pdf;
+        if (bs.refract) eta_scale *= B.eta * B.eta;
+        bool killed = false;
+        if (b >= 1) {
+          float q = fmaxf(fmaxf(beta.x, beta.y), beta.z) * eta_scale;
+          if (q < 0.995f) {  // no roulette within rounding of q = 1
+            killed = u01(r0.w) >= q;
+            rr_ev = killed ? 2 : 1;
+            if (!killed) beta = beta * (1.0f / q);
+          }
+        }
+        if (killed) {
+          end_ev = 3;
+        } else {
+          V3 dn = normalize(t * bs.wi.x + bt * bs.wi.y + n * bs.wi.z);
+          P.ray_o[slot] = make_float4(p.x, p.y, p.z, u2f(prim));
+          P.ray_d[slot] = make_float4(dn.x, dn.y, dn.z, u2f(inst));
+          P.beta[slot] = make_float4(beta.x, beta.y, beta.z, pdf_prev);
+          P.flags[slot] = prev_delta ? 1u : 0u;
+          o.cont = true;
+        }
+      }
+    }
+    P.L[slot] = make_float4(L.x, L.y, L.z, eta_scale);
+    if (DEBUG) {
+      uint32_t tail = tail_pack(lobe_ev, rr_ev, end_ev);
+      if (pending) {
+        P.dbg_nee[slot] = nee_id;
+        P.dbg_tail[slot] = tail;
+      } else {
+        if (nee_done) {
+          sig = sig_word(sig, 5);
+          sig = sig_word(sig, nee_id);
+          sig = sig_word(sig, nee_out);
+        }
+        sig = sig_tail(sig, tail);
+      }
+      P.sig[slot] = sig;
+    }
+  }
+}
+
 template <int CLS, bool DEBUG, bool TWO>
 __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b, int max_depth, int next,
                                                   uint32_t sample, uint32_t k0, uint32_t k1, uint32_t img_w,
                                                   int nrc_bounce) {
   const uint32_t count = P.counts[2 + CLS];
+  unsigned long long nonfinite = 0;
   for (uint32_t base = blockIdx.x * kBlock; base < count; base += gridDim.x * kBlock) {
     uint32_t i = base + threadIdx.x;
     bool active = i < count;
-    bool cont = false, shadow = false, query = false;
     uint32_t slot = 0;
-    float4 sh_o = make_float4(0, 0, 0, 0), sh_d = make_float4(0, 0, 0, 0), sh_c = make_float4(0, 0, 0, 0);
-    uint32_t sh_inst = 0;
+    ShadeOut o;
+    o.cont = o.shadow = o.query = false;
     if (active) {
       slot = P.q_cls[CLS][i];
-      float4 rd = P.ray_d[slot];
-      float4 be = P.beta[slot];
-      float4 Lr = P.L[slot];
-      uint32_t flags = P.flags[slot];
-      V3 beta = v3(be.x, be.y, be.z);
-      V3 L = v3(Lr.x, Lr.y, Lr.z);
-      float pdf_prev = be.w, eta_scale = Lr.w;
-      bool prev_delta = (flags & 1u) != 0u;
-      V3 d = v3(rd.x, rd.y, rd.z);
-      uint64_t sig = DEBUG ? P.sig[slot] : 0ull;
-      unsigned long long nonfinite = 0;
-      if (CLS == kClsMiss) {
-        if (S.env_w > 0) {
-          float st;
-          int texel = env_texel(S, d, st);
-          if (DEBUG) { sig = sig_word(sig, 2); sig = sig_word(sig, (uint32_t)texel); }
-          float4 e = S.env[texel];
-          float w = 1.0f;
-          if (!prev_delta) w = pow_heuristic(pdf_prev, S.p_env * env_pdf_texel(S, texel, st));
-          if (w > 0.0f) {
-            V3 c = v3(beta.x * w * e.x, beta.y * w * e.y, beta.z * w * e.z);
-            if (finite3(c)) L = L + c;
-            else nonfinite++;
-          }
-        } else if (DEBUG) {
-          sig = sig_word(sig, 2);
-          sig = sig_word(sig, 0xFFFFFFFFu);
-        }
-        if (DEBUG) { sig = sig_word(sig, 6); sig = sig_word(sig, 0); }
-        P.L[slot] = make_float4(L.x, L.y, L.z, eta_scale);
-        if (DEBUG) P.sig[slot] = sig;
-      } else {
-        float4 hv = P.hit[slot];
-        const TriRec tr = S.tris[f2u(hv.w)];
-        uint32_t prim = f2u(tr.a.w), mid = f2u(tr.b.w);
-        uint32_t inst = 0;
-        V3 p0 = v3(tr.a.x, tr.a.y, tr.a.z), p1 = v3(tr.b.x, tr.b.y, tr.b.z), p2 = v3(tr.c.x, tr.c.y, tr.c.z);
-        float b1 = hv.y, b2 = hv.z;
-        V3 p = p0 * (1.0f - b1 - b2) + p1 * b1 + p2 * b2;
-        V3 nc = cross(p1 - p0, p2 - p0);
-        V3 axis = v3(S.axis[0], S.axis[1], S.axis[2]);
-        int light_of_prim = -1;
-        if (TWO) {
-          inst = P.hit_inst[slot];
-          const InstRec& I = S.insts[inst];
-          if (I.mat_override >= 0) mid = (uint32_t)I.mat_override;
-          const float* q = I.o2w;
-          p = v3(q[0] * p.x + q[1] * p.y + q[2] * p.z + q[3], q[4] * p.x + q[5] * p.y + q[6] * p.z + q[7],
-                 q[8] * p.x + q[9] * p.y + q[10] * p.z + q[11]);
-          nc = v3(q[0] * nc.x + q[1] * nc.y + q[2] * nc.z, q[4] * nc.x + q[5] * nc.y + q[6] * nc.z,
-                  q[8] * nc.x + q[9] * nc.y + q[10] * nc.z);
-          axis = v3(q[2], q[6], q[10]);
-          if (I.light_map >= 0) light_of_prim = S.light_map[I.light_map + (int)prim];
-        } else {
-          light_of_prim = S.tri_light[prim];
-        }
-        const MatRec& m = S.mats[mid];
-        if (DEBUG) { sig = sig_word(sig, 1); sig = sig_word(sig, inst); sig = sig_word(sig, prim); }
-        V3 ng = normalize(nc);
-        V3 wo_w = d * -1.0f;
-        float cos_ng = dot(ng, wo_w);
-        // emission (front face only), MIS-weighted against light sampling
-        if ((m.flags & kMatEmissive) && cos_ng > 0.0f) {
-          float w = 1.0f;
-          if (!prev_delta) {
-            int k = light_of_prim;
-            float pl = 0.0f;
-            if (k >= 0 && S.n_lights > 0) {
-              const LightTri& Lt = S.lights[k];
-              pl = Lt.p1.w * hv.x * hv.x / (cos_ng * Lt.p0.w);
-            }
-            w = pow_heuristic(pdf_prev, pl);
-          }
-          if (w > 0.0f) {
-            V3 c = v3(beta.x * w * m.Le[0], beta.y * w * m.Le[1], beta.z * w * m.Le[2]);
-            if (finite3(c)) L = L + c;
-            else nonfinite++;
-          }
-        }
-        int lobe_ev = -1, rr_ev = 0, end_ev = 7;
-        bool pending = false;
-        uint32_t nee_id = 0xFFFFFFFFu, nee_out = 3u;
-        bool nee_done = false;
-        bool entering = cos_ng > 0.0f;
-        V3 n = entering ? ng : ng * -1.0f;
-        if (b == max_depth) {
-          end_ev = 1;
-        } else if (b == nrc_bounce && slot < (uint32_t)P.n_render) {
-          // the path ends in the radiance cache: the query adds beta * cache(x) after the pass
-          float* qr = P.nrc_q + (size_t)slot * kNrcQueryFloats;
-          nrc_inputs(S.box_lo, S.box_inv, p, wo_w, n, m, qr);
-          qr[12] = beta.x;
-          qr[13] = beta.y;
-          qr[14] = beta.z;
-          query = true;
-          end_ev = 4;
-        } else {
-          if (P.rec && slot >= (uint32_t)P.n_render) {  // training record: inputs, radiance so far, throughput
-            float* rr = P.rec + ((size_t)(slot - P.n_render) * P.rec_depth + b) * kNrcRecFloats;
-            nrc_inputs(S.box_lo, S.box_inv, p, wo_w, n, m, rr);
-            rr[12] = L.x;
-            rr[13] = L.y;
-            rr[14] = L.z;
-            rr[15] = beta.x;
-            rr[16] = beta.y;
-            rr[17] = beta.z;
-            rr[18] = 1.0f;
-          }
-          V3 t, bt;
-          make_frame(n, axis, t, bt);
-          V3 wo = v3(dot(wo_w, t), dot(wo_w, bt), dot(wo_w, n));
-          Bsdf B = bsdf_setup<CLS>(m, entering, wo.z);
-          if (wo.z <= 0.0f) B.absorbed = true;
-          Rng rng{slot_pixel(P, slot, img_w), slot_sample(P, slot, sample), k0, k1};
-          U4 r0 = rng.block((uint32_t)b, 0u), r1 = rng.block((uint32_t)b, 1u);
-          // next-event estimation
-          if (!B.absorbed && bsdf_has_nondelta<CLS>(m, B)) {
-            nee_done = true;
-            U4 r2 = rng.block((uint32_t)b, 2u);
-            LightSample ls = sample_light(S, p, u01(r1.w), u01(r2.x), u01(r2.y));
-            nee_id = ls.id;
-            if (ls.ok) {
-              V3 wil = v3(dot(ls.wl, t), dot(ls.wl, bt), dot(ls.wl, n));
-              float pb;
-              V3 f = bsdf_eval<CLS>(m, B, wo, wil, pb);
-              float w = pow_heuristic(ls.pdf, pb);
-              float k = fabsf(wil.z) * w / ls.pdf;
-              V3 c = v3(beta.x * f.x * ls.Le.x * k, beta.y * f.y * ls.Le.y * k, beta.z * f.z * ls.Le.z * k);
-              if (c.x != 0.0f || c.y != 0.0f || c.z != 0.0f) {
-                shadow = true;
-                pending = true;
-                float tmax = isinf(ls.dist) ? INFINITY : (1.0f - 1e-4f) * ls.dist;
-                sh_o = make_float4(p.x, p.y, p.z, tmax);
-                sh_d = make_float4(ls.wl.x, ls.wl.y, ls.wl.z, u2f(slot));
-                sh_c = make_float4(c.x, c.y, c.z, u2f(prim));
-                sh_inst = inst;
-              } else {
-                nee_out = 2u;
-              }
-            }
-          }
-          // BSDF sampling
-          BsdfSample bs = bsdf_sample<CLS>(m, B, wo, u01(r0.z), u01(r1.x), u01(r1.y), u01(r1.z));
-          lobe_ev = bs.lobe;
-          if (!bs.ok || (bs.weight.x == 0.0f && bs.weight.y == 0.0f && bs.weight.z == 0.0f)) {
-            end_ev = 2;
-          } else {
-            beta = v3(beta.x * bs.weight.x, beta.y * bs.weight.y, beta.z * bs.weight.z);
-            prev_delta = bs.delta;
-            pdf_prev = bs.pdf;
-            if (bs.refract) eta_scale *= B.eta * B.eta;
-            bool killed = false;
-            if (b >= 1) {
-              float q = fmaxf(fmaxf(beta.x, beta.y), beta.z) * eta_scale;
-              if (q < 0.995f) {  // no roulette within rounding of q = 1
-                killed = u01(r0.w) >= q;
-                rr_ev = killed ? 2 : 1;
-                if (!killed) beta = beta * (1.0f / q);
-              }
-            }
-            if (killed) {
-              end_ev = 3;
-            } else {
-              V3 dn = normalize(t * bs.wi.x + bt * bs.wi.y + n * bs.wi.z);
-              P.ray_o[slot] = make_float4(p.x, p.y, p.z, u2f(prim));
-              P.ray_d[slot] = make_float4(dn.x, dn.y, dn.z, u2f(inst));
-              P.beta[slot] = make_float4(beta.x, beta.y, beta.z, pdf_prev);
-              P.flags[slot] = prev_delta ? 1u : 0u;
-              cont = true;
-            }
-          }
-        }
-        P.L[slot] = make_float4(L.x, L.y, L.z, eta_scale);
-        if (DEBUG) {
-          uint32_t tail = tail_pack(lobe_ev, rr_ev, end_ev);
-          if (pending) {
-            P.dbg_nee[slot] = nee_id;
-            P.dbg_tail[slot] = tail;
-          } else {
-            if (nee_done) {
-              sig = sig_word(sig, 5);
-              sig = sig_word(sig, nee_id);
-              sig = sig_word(sig, nee_out);
-            }
-            sig = sig_tail(sig, tail);
-          }
-          P.sig[slot] = sig;
-        }
-      }
-      if (nonfinite) atomicAdd(&P.stats[kStatNonFinite], nonfinite);
+      shade_one<CLS, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, nrc_bounce, o, nonfinite);
     }
-    uint32_t qpos = wave_append(cont, &P.counts[next]);
-    if (cont) P.q_ray[next][qpos] = slot;
+    uint32_t qpos = wave_append(o.cont, &P.counts[next]);
+    if (o.cont) P.q_ray[next][qpos] = slot;
     if (b == nrc_bounce) {
-      uint32_t npos = wave_append(query, &P.counts[kCountQuery]);
-      if (query) P.q_nrc[npos] = slot;
+      uint32_t npos = wave_append(o.query, &P.counts[kCountQuery]);
+      if (o.query) P.q_nrc[npos] = slot;
     }
-    uint32_t spos = wave_append(shadow, &P.counts[kCountShadow]);
-    if (shadow) {
-      P.sh_o[spos] = sh_o;
-      P.sh_d[spos] = sh_d;
-      P.sh_c[spos] = sh_c;
-      if (TWO) P.sh_inst[spos] = sh_inst;
+    uint32_t spos = wave_append(o.shadow, &P.counts[kCountShadow]);
+    if (o.shadow) {
+      P.sh_o[spos] = o.sh_o;
+      P.sh_d[spos] = o.sh_d;
+      P.sh_c[spos] = o.sh_c;
+      if (TWO) P.sh_inst[spos] = o.sh_inst;
     }
   }
+  if (nonfinite) atomicAdd(&P.stats[kStatNonFinite], nonfinite);
 }
 
 // ----------------------------------------------------------------- connect
@@ -745,7 +770,7 @@ struct ConnectSrc {
 };
 
 template <bool DEBUG, bool COUNT, bool TWO>
-__global__ __launch_bounds__(kBlock) void k_connect(SceneDev S, PathsDev P) {
+__global__ __launch_bounds__(kBlock, kConnWaves) void k_connect(SceneDev S, PathsDev P) {
   __shared__ unsigned long long s_stack[kLdsStack * kBlock];
   __shared__ uint32_t s_next;
   const uint32_t count = P.counts[kCountShadow];
@@ -758,6 +783,147 @@ __global__ __launch_bounds__(kBlock) void k_connect(SceneDev S, PathsDev P) {
   if (COUNT) {
     atomicAdd(&P.stats[kStatShadowNodes], (unsigned long long)nvis);
     atomicAdd(&P.stats[kStatShadowTris], (unsigned long long)ntri);
+  }
+  if (nonfinite) atomicAdd(&P.stats[kStatNonFinite], nonfinite);
+  if (overflow) atomicAdd(&P.stats[kStatOverflow], 1ull);
+}
+
+// -------------------------------------------------------------------- tail
+// Once few paths remain, one persistent-lane kernel finishes them: a lane
+// takes a path and runs all its remaining vertices (closest hit, shading,
+// shadow ray, next ray) with no kernel boundary between vertices, so short
+// paths do not wait for the slowest ray of every later bounce.  Shading,
+// walks and signatures are the same code as the wavefront kernels'.
+template <bool DEBUG, bool TWO>
+__device__ inline void shade_any(int cls, const SceneDev& S, const PathsDev& P, uint32_t slot, int b, int max_depth,
+                                 uint32_t sample, uint32_t k0, uint32_t k1, uint32_t img_w, ShadeOut& o,
+                                 unsigned long long& nf) {
+  switch (cls) {
+    case kClsMiss: shade_one<kClsMiss, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, -1, o, nf); break;
+    case kClsAbsorb: shade_one<kClsAbsorb, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, -1, o, nf); break;
+    case kClsDiffuse: shade_one<kClsDiffuse, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, -1, o, nf); break;
+    case kClsMetal: shade_one<kClsMetal, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, -1, o, nf); break;
+    case kClsPlastic: shade_one<kClsPlastic, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, -1, o, nf); break;
+    case kClsGlass: shade_one<kClsGlass, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, -1, o, nf); break;
+    default: shade_one<kClsGeneral, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, -1, o, nf); break;
+  }
+}
+
+template <bool DEBUG, bool COUNT, bool TWO>
+__global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur, int b_first, int max_depth,
+                                                 uint32_t sample, uint32_t k0, uint32_t k1, uint32_t img_w) {
+  __shared__ unsigned long long s_stack[kLdsStack * kBlock];
+  __shared__ uint32_t s_next;
+  const uint32_t count = P.counts[cur];
+  const uint32_t per = (count + gridDim.x - 1) / gridDim.x;
+  const uint32_t q0 = min(count, blockIdx.x * per), q1 = min(count, q0 + per);
+  if (threadIdx.x == 0) s_next = q0;
+  __syncthreads();
+  const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
+  DevStack st{lds_stack_base(s_stack), S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
+  LaneRay L;
+  int phase = 0;  // 0 idle, 1 closest-hit walk, 2 shadow-ray walk
+  bool drained = false, cont = false;
+  uint32_t slot = 0;
+  int b = b_first;
+  float4 sh_c = make_float4(0, 0, 0, 0);
+  uint32_t n_ext = 0, n_sh = 0, nvis = 0, ntri = 0, svis = 0, stri = 0;
+  unsigned long long nonfinite = 0;
+  bool overflow = false;
+  auto start_closest = [&](void) {
+    float4 o = P.ray_o[slot], d = P.ray_d[slot];
+    st.sp = 0;
+    lane_start<TWO>(L, o.x, o.y, o.z, d.x, d.y, d.z, S.tmin, INFINITY, f2u(d.w), f2u(o.w), TWO ? 0u : S.root);
+    phase = 1;
+    n_ext++;
+  };
+  while (true) {
+    const uint64_t idle = __ballot(phase == 0);
+    const uint32_t n_idle = (uint32_t)__popcll((unsigned long long)idle);
+    if (!drained && (n_idle >= kRefill || n_idle == 64u)) {
+      uint32_t base = 0;
+      if (lane_id() == 0) base = atomicAdd(&s_next, n_idle);
+      base = __shfl(base, 0);
+      if (base + n_idle >= q1) drained = true;
+      const uint32_t i = base + lane_prefix(idle);
+      if (phase == 0 && i < q1) {
+        slot = P.q_ray[cur][i];
+        b = b_first;
+        start_closest();
+      }
+    }
+    if (__ballot(phase != 0) == 0) break;
+    if (phase == 1) {
+      if (lane_step<false, COUNT, TWO>(S, L, st, nvis, ntri)) {
+        overflow |= st.overflow;
+        int cls = kClsMiss;
+        if (L.best.tri != 0xFFFFFFFFu) {
+          P.hit[slot] = make_float4(L.best.t, L.best.b1, L.best.b2, u2f(L.best.tri));
+          uint32_t mid = L.best.mat;
+          if (TWO) {
+            P.hit_inst[slot] = L.best.inst;
+            int32_t ov = S.insts[L.best.inst].mat_override;
+            if (ov >= 0) mid = (uint32_t)ov;
+          }
+          cls = S.mats[mid].cls;
+        } else {
+          P.hit[slot] = make_float4(INFINITY, 0.0f, 0.0f, u2f(0xFFFFFFFFu));
+        }
+        ShadeOut o;
+        shade_any<DEBUG, TWO>(cls, S, P, slot, b, max_depth, sample, k0, k1, img_w, o, nonfinite);
+        if (o.shadow) {
+          st.sp = 0;
+          lane_start<TWO>(L, o.sh_o.x, o.sh_o.y, o.sh_o.z, o.sh_d.x, o.sh_d.y, o.sh_d.z, S.tmin, o.sh_o.w,
+                          TWO ? o.sh_inst : 0u, f2u(o.sh_c.w), TWO ? 0u : S.root);
+          sh_c = o.sh_c;
+          cont = o.cont;
+          phase = 2;
+          n_sh++;
+        } else if (o.cont) {
+          b++;
+          start_closest();
+        } else {
+          phase = 0;
+        }
+      }
+    } else if (phase == 2) {
+      if (lane_step<true, COUNT, TWO>(S, L, st, svis, stri)) {
+        overflow |= st.overflow;
+        const bool occ = L.best.tri != 0xFFFFFFFFu;
+        if (!occ) {
+          V3 cc = v3(sh_c.x, sh_c.y, sh_c.z);
+          if (finite3(cc)) {
+            float4 Lr = P.L[slot];
+            P.L[slot] = make_float4(Lr.x + cc.x, Lr.y + cc.y, Lr.z + cc.z, Lr.w);
+          } else {
+            nonfinite++;
+          }
+        }
+        if (DEBUG) {
+          uint64_t sig = P.sig[slot];
+          sig = sig_word(sig, 5);
+          sig = sig_word(sig, P.dbg_nee[slot]);
+          sig = sig_word(sig, occ ? 1u : 0u);
+          sig = sig_tail(sig, P.dbg_tail[slot]);
+          P.sig[slot] = sig;
+        }
+        if (cont) {
+          b++;
+          start_closest();
+        } else {
+          phase = 0;
+        }
+      }
+    }
+  }
+  atomicAdd(&P.stats[kStatExt], (unsigned long long)n_ext);
+  atomicAdd(&P.stats[kStatTailExt], (unsigned long long)n_ext);
+  atomicAdd(&P.stats[kStatShadow], (unsigned long long)n_sh);
+  if (COUNT) {
+    atomicAdd(&P.stats[kStatTailNodes], (unsigned long long)nvis);
+    atomicAdd(&P.stats[kStatTailTris], (unsigned long long)ntri);
+    atomicAdd(&P.stats[kStatShadowNodes], (unsigned long long)svis);
+    atomicAdd(&P.stats[kStatShadowTris], (unsigned long long)stri);
   }
   if (nonfinite) atomicAdd(&P.stats[kStatNonFinite], nonfinite);
   if (overflow) atomicAdd(&P.stats[kStatOverflow], 1ull);
@@ -852,6 +1018,22 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays_brute(SceneDev S, const f
 // --------------------------------------------------------------- launchers
 int trace_grid_blocks() { return 2048; }
 
+// Resident workgroups of the tail kernel (it holds far more registers).
+int tail_grid(int grid_trace) {
+  static int resident = 0;
+  if (!resident) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tail<true, true, true>, kBlock, 0) != hipSuccess ||
+        per < 1)
+      per = 1;
+    resident = std::max(1, cus * per);
+  }
+  return std::min(grid_trace, resident);
+}
+
 // The traversal kernels keep one resident set of workgroups (persistent
 // lanes); more would only queue behind them.
 int traversal_grid(int64_t rays) {
@@ -892,8 +1074,23 @@ template <bool DEBUG, bool COUNT, bool TWO>
 static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev& C, const PassArgs& A,
                               hipStream_t st) {
   dim3 blk(kBlock);
+  if (A.wavefront_bounces) *A.wavefront_bounces = A.max_depth + 1;
   for (int b = 0; b <= A.max_depth; ++b) {
     int cur = b & 1, next = cur ^ 1;
+    if (A.tail_host_count && b >= A.tail_min_bounce && b > A.nrc_bounce) {
+      // hand the remaining vertices to one persistent kernel once few paths are left
+      hipError_t e0 = hipMemcpyAsync(A.tail_host_count, &P.counts[cur], sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+      if (e0 == hipSuccess) e0 = hipStreamSynchronize(st);
+      if (e0 != hipSuccess) return e0;
+      if ((double)*A.tail_host_count <= A.tail_fraction * (double)P.n) {
+        if (A.wavefront_bounces) *A.wavefront_bounces = b;
+        if (A.tail_events) hipEventRecord(A.tail_events[0], st);
+        hipLaunchKernelGGL((k_tail<DEBUG, COUNT, TWO>), dim3(tail_grid(A.grid_trace)), blk, 0, st, S, P, cur, b, A.max_depth,
+                           A.sample, A.k0, A.k1, (uint32_t)C.W);
+        if (A.tail_events) hipEventRecord(A.tail_events[1], st);
+        break;
+      }
+    }
     hipLaunchKernelGGL(k_reset_counts, dim3(1), dim3(64), 0, st, P.counts, next);
     if (A.ext_events) hipEventRecord(A.ext_events[2 * b], st);
     hipLaunchKernelGGL((k_extend<COUNT, TWO>), dim3(A.grid_trace), blk, 0, st, S, P, cur);

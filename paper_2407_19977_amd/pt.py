@@ -47,7 +47,9 @@ class pt_stats(C.Structure):
                 ("ms_total", C.c_double), ("node_visits", C.c_int64), ("tri_tests", C.c_int64),
                 ("shadow_node_visits", C.c_int64), ("shadow_tri_tests", C.c_int64),
                 ("cache_queries", C.c_int64), ("cache_records", C.c_int64), ("cache_adam_steps", C.c_int64),
-                ("ms_cache_query", C.c_double), ("ms_cache_train", C.c_double)]
+                ("ms_cache_query", C.c_double), ("ms_cache_train", C.c_double),
+                ("tail_extension_rays", C.c_int64), ("tail_node_visits", C.c_int64), ("tail_tri_tests", C.c_int64),
+                ("ms_tail", C.c_double), ("launches_tail", C.c_int64)]
 
 
 class pt_bvh_info(C.Structure):
@@ -90,6 +92,7 @@ _SIGS = {
     "pt_get_stats": (C.c_int, [C.c_void_p, C.POINTER(pt_stats)]),
     "pt_reset_stats": (C.c_int, [C.c_void_p]),
     "pt_set_profiling": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "pt_set_tail": (C.c_int, [C.c_void_p, C.c_int32, C.c_double]),
     "pt_set_radiance_cache": (C.c_int, [C.c_void_p, C.POINTER(pt_radiance_cache_config)]),
     "pt_nrc_set_weights": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
     "pt_nrc_get_weights": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]),
@@ -275,6 +278,9 @@ class PtScene:
 
     def reset_stats(self):
         _check(_lib.pt_reset_stats(self.h))
+
+    def set_tail(self, min_bounce=3, max_fraction=0.125):
+        _check(_lib.pt_set_tail(self.h, int(min_bounce), float(max_fraction)))
 
     def set_profiling(self, timing: bool, counting: bool = False):
         _check(_lib.pt_set_profiling(self.h, 1 if timing else 0, 1 if counting else 0))

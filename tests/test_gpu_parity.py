@@ -208,6 +208,30 @@ def test_spheres_crop_parity(P, O, crop, spp):
     _compare(g, gs, ref, 0.99, f"spheres{crop}")
 
 
+@pytest.mark.parametrize("mode", ["wavefront", "tail-from-1"])
+@pytest.mark.parametrize("which", ["box", "spheres", "instanced"])
+def test_tail_hand_off_parity(P, O, which, mode):
+    """The persistent tail kernel and the per-bounce wavefront give the oracle's paths."""
+    make = {"box": _cornell, "spheres": _spheres, "instanced": _instanced}[which]
+    sc, s, os_ = make(P, O)
+    crop = {"box": (0, 0, 128, 128), "spheres": (900, 500, 40, 40), "instanced": (900, 480, 40, 40)}[which]
+    spp = {"box": 8, "spheres": 3, "instanced": 3}[which]
+    _say(f"[tail] {which} {crop} {spp} spp, {mode}")
+    if mode == "wavefront":
+        s.set_tail(0, 0.0)
+    else:
+        s.set_tail(1, 1.0)
+    try:
+        s.reset_stats()
+        g, gs = _debug(s, sc.camera, crop, 0, spp, sc.max_depth)
+        st = s.stats()
+    finally:
+        s.set_tail()
+    assert (st["tail_extension_rays"] > 0) == (mode != "wavefront")
+    ref = os_.render(spp, sc.max_depth, crop=crop, per_sample=True)
+    _compare(g, gs, ref, {"box": 0.999, "spheres": 0.99, "instanced": 0.98}[which], f"{which} {mode}")
+
+
 def test_progressive_accumulation_is_bitwise(P, O):
     sc, s, os_ = _cornell(P, O)
     _say("[progressive] [0,16) vs [0,5)+[5,16)")

@@ -181,6 +181,18 @@ def cache_experiment(pt, torch, sc, frames=256, ref_spp=4096):
     return result
 
 
+def tail_info(counts, st, steps):
+    """The persistent tail kernel (all vertices of the last few paths): time and closest-hit bytes."""
+    info = {"kernel": "k_tail (remaining vertices once few paths are alive)",
+            "ms_per_step": round(st["ms_tail"] / steps, 3), "launches_per_step": st["launches_tail"] / steps,
+            "extension_rays_per_step": st["tail_extension_rays"] // steps}
+    if st["ms_tail"] > 0 and counts is not None:
+        b = (counts["tail_node_visits"] * NODE_BYTES + counts["tail_tri_tests"] * TRI_BYTES +
+             counts["tail_extension_rays"] * (RAY_BYTES + HIT_BYTES))
+        info["closest_hit_gbs"] = round(b / (st["ms_tail"] / steps * 1e-3) / 1e9, 1)
+    return info
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,9 +271,7 @@ def main():
                     "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": round(avg_ms, 4),
                     "node_visits_per_ray": round(counts["node_visits"] / max(1, ext_rays), 2),
                     "tri_tests_per_ray": round(counts["tri_tests"] / max(1, ext_rays), 2),
-                    "tail_kernel": {"ms_per_step": round(st["ms_tail"] / args.steps, 3),
-                                    "launches_per_step": st["launches_tail"] / args.steps,
-                                    "extension_rays_per_step": st["tail_extension_rays"] // args.steps}}
+                    "tail_kernel": tail_info(counts, st, args.steps)}
 
     result = {
         "metric": METRIC, "value": round(mrays, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,

@@ -132,6 +132,10 @@ def cache_experiment(pt, torch, sc, frames=256, ref_spp=4096):
     s.set_profiling(True, False)
     s.reset_stats()
     plain = _frames(s, cam, depth, seed, frames, ref, out, torch)
+    # one untimed cache frame allocates the cache's buffers; configuring again resets weights and Adam state
+    s.set_radiance_cache(pt.cache_config())
+    s.reset_accumulation()
+    s.accumulate(cam, 0, 1, depth, seed)
     s.set_radiance_cache(pt.cache_config())
     s.reset_stats()
     nrc = _frames(s, cam, depth, seed, frames, ref, out, torch)

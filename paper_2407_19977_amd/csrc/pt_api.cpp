@@ -108,7 +108,7 @@ struct pt_scene {
   uint32_t class_mask = 0;
   // environment
   int env_w = 0, env_h = 0;
-  DevBuf env, env_row_pmf, env_row_cdf, env_col_pmf, env_col_cdf;
+  DevBuf env, env_row_pmf, env_row_cdf, env_col_pmf, env_col_cdf, env_row_guide, env_col_guide;
   // lights
   bool lights_dirty = true;
   DevBuf lights, light_cdf, tri_light;
@@ -360,6 +360,8 @@ SceneDev scene_dev(pt_scene* s, int grid_trace) {
   S.env_row_cdf = s->env_row_cdf.as<float>();
   S.env_col_pmf = s->env_col_pmf.as<float>();
   S.env_col_cdf = s->env_col_cdf.as<float>();
+  S.env_row_guide = s->env_row_guide.as<int32_t>();
+  S.env_col_guide = s->env_col_guide.as<int32_t>();
   S.env_w = s->env_w;
   S.env_h = s->env_h;
   S.tmin = s->tmin;
@@ -1225,6 +1227,21 @@ pt_status pt_set_environment(pt_scene* s, const float* rgb, int32_t w, int32_t h
     row_cdf[(size_t)y + 1] = (float)(acc / total);
   }
   row_cdf[(size_t)h] = 1.0f;
+  // guide tables: entry g = largest i < n with cdf[i] <= g / G
+  auto guide = [](const float* cdf, int nb, int G, int32_t* out) {
+    int i = 0;
+    for (int g = 0; g < G; ++g) {
+      float t = (float)g / (float)G;
+      while (i + 1 < nb && cdf[i + 1] <= t) ++i;
+      out[g] = i;
+    }
+  };
+  std::vector<int32_t> row_guide(kEnvRowGuide), col_guide((size_t)h * kEnvColGuide);
+  guide(row_cdf.data(), h, kEnvRowGuide, row_guide.data());
+  for (int y = 0; y < h; ++y)
+    guide(&col_cdf[(size_t)y * (w + 1)], w, kEnvColGuide, &col_guide[(size_t)y * kEnvColGuide]);
+  PT_HIP(upload(s->env_row_guide, row_guide.data(), row_guide.size() * sizeof(int32_t), s->stream));
+  PT_HIP(upload(s->env_col_guide, col_guide.data(), col_guide.size() * sizeof(int32_t), s->stream));
   PT_HIP(upload(s->env, tex.data(), n * sizeof(float4), s->stream));
   PT_HIP(upload(s->env_col_pmf, col_pmf.data(), n * sizeof(float), s->stream));
   PT_HIP(upload(s->env_col_cdf, col_cdf.data(), col_cdf.size() * sizeof(float), s->stream));

@@ -19,6 +19,8 @@ constexpr int kBlock = 256;     // threads per workgroup (4 waves of 64)
 #define PT_LDS_STACK 10
 #endif
 constexpr int kLdsStack = PT_LDS_STACK;  // traversal stack entries per lane kept in LDS
+constexpr int kEnvRowGuide = 1024;      // guide-table sizes of the environment CDFs (powers of two)
+constexpr int kEnvColGuide = 256;
 
 // Scene data the kernels read (all device pointers).
 struct SceneDev {
@@ -37,6 +39,8 @@ struct SceneDev {
   const float* env_row_cdf;  // [h + 1]
   const float* env_col_pmf;  // [h][w]
   const float* env_col_cdf;  // [h][w + 1]
+  const int32_t* env_row_guide;  // [kEnvRowGuide]: start of the search for u in [g/G, (g+1)/G)
+  const int32_t* env_col_guide;  // [h][kEnvColGuide]
   int32_t env_w, env_h;
   float tmin;                // self-intersection offset: 1e-5 x scene diagonal
   float axis[3];             // object +z axis in world space (shading tangent, single level)

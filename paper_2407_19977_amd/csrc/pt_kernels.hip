@@ -143,6 +143,24 @@ __device__ inline int cdf_invert(const float* cdf, int n, float u) {
   return i;
 }
 
+// The same bucket through a guide table: guide[g] is the largest i with
+// cdf[i] <= g/G, so for u in [g/G, (g+1)/G) the answer lies in
+// [guide[g], guide[g+1]] and the binary search starts there (u * G is exact:
+// u has 24 bits and G is a power of two).
+__device__ inline int cdf_invert_guided(const float* cdf, int n, float u, const int32_t* guide, int G) {
+  int g = min(G - 1, (int)(u * (float)G));
+  int lo = guide[g], hi = g + 1 < G ? min(n, guide[g + 1] + 1) : n;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (cdf[mid] <= u) lo = mid;
+    else hi = mid;
+  }
+  int i = lo;
+  while (i < n - 1 && !(cdf[i + 1] > cdf[i])) i++;
+  while (i > 0 && !(cdf[i + 1] > cdf[i])) i--;
+  return i;
+}
+
 struct LightSample {
   V3 wl;
   float dist, pdf;
@@ -162,11 +180,11 @@ __device__ inline LightSample sample_light(const SceneDev& S, V3 p, float usel, 
   if (S.p_env <= 0.0f && S.n_lights == 0) return ls;
   if (usel < S.p_env) {
     int W = S.env_w, H = S.env_h;
-    int r = cdf_invert(S.env_row_cdf, H, u1);
+    int r = cdf_invert_guided(S.env_row_cdf, H, u1, S.env_row_guide, kEnvRowGuide);
     float pr = S.env_row_pmf[r];
     float du = pr > 0.0f ? (u1 - S.env_row_cdf[r]) / pr : 0.5f;
     const float* ccdf = S.env_col_cdf + (size_t)r * (W + 1);
-    int c = cdf_invert(ccdf, W, u2);
+    int c = cdf_invert_guided(ccdf, W, u2, S.env_col_guide + (size_t)r * kEnvColGuide, kEnvColGuide);
     float pc = S.env_col_pmf[(size_t)r * W + c];
     float dv = pc > 0.0f ? (u2 - ccdf[c]) / pc : 0.5f;
     float uu = ((float)c + dv) / (float)W, vv = ((float)r + du) / (float)H;

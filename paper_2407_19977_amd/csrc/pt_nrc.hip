@@ -467,16 +467,33 @@ hipError_t nrc_launch_pack(const float* w, uint4* fwd, uint4* bwd, hipStream_t s
   return hipGetLastError();
 }
 
+// The inference kernel keeps all weight fragments in registers (one wave per
+// SIMD): launch one resident set of workgroups and let each wave stride over
+// the query groups, so the weights are staged once per workgroup.
+static int nrc_infer_grid() {
+  static int resident = 0;
+  if (!resident) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_nrc_infer<1>, 256, 0) != hipSuccess || per < 1) per = 1;
+    resident = std::max(1, cus * per);
+  }
+  return resident;
+}
+
 hipError_t nrc_launch_forward(const float* x, int64_t n, const uint4* fwd, float* y, hipStream_t st) {
   PathsDev P;
   __builtin_memset(&P, 0, sizeof(P));
   int64_t groups = (n + 15) / 16;
-  int grid = (int)std::max<int64_t>(1, std::min<int64_t>((groups + 3) / 4, 2048));
+  int grid = (int)std::max<int64_t>(1, std::min<int64_t>((groups + 3) / 4, nrc_infer_grid()));
   hipLaunchKernelGGL((k_nrc_infer<0>), dim3(grid), dim3(256), 0, st, x, n, P, fwd, y);
   return hipGetLastError();
 }
 
 hipError_t nrc_launch_query(const PathsDev& P, const uint4* fwd, int grid, hipStream_t st) {
+  grid = std::max(1, std::min(grid, nrc_infer_grid()));
   hipLaunchKernelGGL((k_nrc_infer<1>), dim3(grid), dim3(256), 0, st, nullptr, (int64_t)0, P, fwd, nullptr);
   return hipGetLastError();
 }

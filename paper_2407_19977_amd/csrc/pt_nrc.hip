@@ -28,8 +28,13 @@ __device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two floats to bfloat16 (round to nearest even) in one v_cvt_pk_bf16_f32;
+// for finite values the same bits as bf16_bits().
 __device__ inline uint32_t pack2(float a, float b) {
-  return (uint32_t)bf16_bits(a) | ((uint32_t)bf16_bits(b) << 16);
+  bf16x2 v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, v);
 }
 
 // B operand of a chained chunk from two result tiles, with ReLU.
@@ -84,20 +89,60 @@ __global__ void k_nrc_pack(const float* __restrict__ w, uint4* __restrict__ fwd,
   else bwd[(frag - kNrcFwdFrags) * 64 + lane] = u;
 }
 
-// Encoded input as the layer-0 B operand: lane (g, q) holds features 32c + 8g + j.
+// Encoded input as the layer-0 B operand: lane (g, q) holds features 32c + 8g + j
+// of query q.  The work is laid out so every lane runs the same instructions
+// (no per-lane branch on the feature index): chunk 0 is four sin/cos pairs
+// per lane, chunk 1 is two sin/cos pairs, two one-blob groups, the albedos
+// and the constants, selected by the lane group g.
+// Lane-dependent choice among registers, written as a sum of selects against
+// zero so the compiler keeps the inputs in registers (a select between two
+// array loads would become an indexed load from a stack copy).
+__device__ inline float pick3(int a, float v0, float v1, float v2) {
+  return ((a == 0 ? v0 : 0.0f) + (a == 1 ? v1 : 0.0f)) + (a == 2 ? v2 : 0.0f);
+}
+
 __device__ inline void encode_operand(const float* x, int g, bool valid, bf16x8 B[2]) {
+  float f0[8];
 #pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    float f[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) f[j] = valid ? nrc_feature(nrc_k_natural(c, g, j), x) : 0.0f;
-    uint4 u;
-    u.x = pack2(f[0], f[1]);
-    u.y = pack2(f[2], f[3]);
-    u.z = pack2(f[4], f[5]);
-    u.w = pack2(f[6], f[7]);
-    B[c] = as_bf16x8(u);
+  for (int m = 0; m < 4; ++m) {  // features 8g + 2m (sin) and 8g + 2m + 1 (cos)
+    const int f = 8 * g + 2 * m, a = f / 12, k = (f % 12) >> 1;
+    const float xa = pick3(a, x[0], x[1], x[2]);
+    const float w = xa * (float)(1 << k);
+    f0[2 * m] = sinpif(w);
+    f0[2 * m + 1] = cospif(w);
   }
+  // chunk 1: g = 0: sin/cos(16 pi x2), sin/cos(32 pi x2), blob(x3); g = 1: blob(x4), blob(x5);
+  //          g = 2: blob(x6), blob(1 - exp(-x7)); g = 3: x8..x11, 1, 0, 0, 0
+  const float r7 = 1.0f - expf(-x[7]);
+  const float s1 = pick3(g == 1 ? 0 : 1, x[4], x[6], 0.0f);
+  const float s2 = pick3(g == 0 ? 0 : (g == 1 ? 1 : 2), x[3], x[5], r7);
+  float lo[4], hi[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    lo[i] = nrc_one_blob(s1, i);
+    hi[i] = nrc_one_blob(s2, i);
+  }
+  const float w4 = x[2] * 16.0f, w5 = x[2] * 32.0f;
+  const float t0 = sinpif(w4), t1 = cospif(w4), t2 = sinpif(w5), t3 = cospif(w5);
+  float f1[8];
+  f1[0] = g == 0 ? t0 : (g == 3 ? x[8] : lo[0]);
+  f1[1] = g == 0 ? t1 : (g == 3 ? x[9] : lo[1]);
+  f1[2] = g == 0 ? t2 : (g == 3 ? x[10] : lo[2]);
+  f1[3] = g == 0 ? t3 : (g == 3 ? x[11] : lo[3]);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) f1[4 + i] = g == 3 ? (i == 0 ? 1.0f : 0.0f) : hi[i];
+  uint4 u0, u1;
+  u0.x = pack2(f0[0], f0[1]);
+  u0.y = pack2(f0[2], f0[3]);
+  u0.z = pack2(f0[4], f0[5]);
+  u0.w = pack2(f0[6], f0[7]);
+  u1.x = pack2(f1[0], f1[1]);
+  u1.y = pack2(f1[2], f1[3]);
+  u1.z = pack2(f1[4], f1[5]);
+  u1.w = pack2(f1[6], f1[7]);
+  if (!valid) u0 = u1 = make_uint4(0u, 0u, 0u, 0u);
+  B[0] = as_bf16x8(u0);
+  B[1] = as_bf16x8(u1);
 }
 
 // Five hidden layers and the output layer; returns the output tile (rows 0..2 valid in lanes g == 0).
@@ -132,9 +177,18 @@ __device__ inline f32x4 mlp_forward(const uint4* __restrict__ sw, int lane, bf16
 // MODE 0: inputs x[n][12], outputs y[n][3].
 // MODE 1: the cache queries of a sampling pass: slot = q_nrc[i] for i < counts[kCountQuery];
 //         inputs nrc_q[slot][0..11], throughput nrc_q[slot][12..14]; L[slot] += beta * max(y, 0).
+#ifndef PT_NRC_INFER_WAVES
+#define PT_NRC_INFER_WAVES 8
+#endif
+#ifndef PT_NRC_LDS_WEIGHTS
+#define PT_NRC_LDS_WEIGHTS 1
+#endif
+constexpr int kInferWaves = PT_NRC_INFER_WAVES;  // waves per workgroup (one weight copy in LDS each)
+
 template <int MODE>
-__global__ __launch_bounds__(256) void k_nrc_infer(const float* __restrict__ xin, int64_t n_arg, PathsDev P,
-                                                   const uint4* __restrict__ fwd, float* __restrict__ out) {
+__global__ __launch_bounds__(64 * kInferWaves) void k_nrc_infer(const float* __restrict__ xin, int64_t n_arg,
+                                                                PathsDev P, const uint4* __restrict__ fwd,
+                                                                float* __restrict__ out) {
   __shared__ uint4 sw[kNrcFwdFrags * 64];
   for (int i = threadIdx.x; i < kNrcFwdFrags * 64; i += blockDim.x) sw[i] = fwd[i];
   __syncthreads();
@@ -142,7 +196,10 @@ __global__ __launch_bounds__(256) void k_nrc_infer(const float* __restrict__ xin
   if (MODE == 1 && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&P.stats[kStatQueries], (unsigned long long)n);
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, g = lane / 16, q = lane % 16;
   unsigned long long nonfinite = 0;
-  for (int64_t grp = (int64_t)blockIdx.x * 4 + wave; grp * 16 < n; grp += (int64_t)gridDim.x * 4) {
+  for (int64_t grp = (int64_t)blockIdx.x * kInferWaves + wave; grp * 16 < n; grp += (int64_t)gridDim.x * kInferWaves) {
+#if PT_NRC_LDS_WEIGHTS
+    asm volatile("" ::: "memory");  // weights are read from LDS in every group, not held in registers
+#endif
     int64_t qi = grp * 16 + q;
     bool valid = qi < n;
     const float* r = nullptr;
@@ -477,7 +534,9 @@ static int nrc_infer_grid() {
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
       cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_nrc_infer<1>, 256, 0) != hipSuccess || per < 1) per = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_nrc_infer<1>, 64 * kInferWaves, 0) != hipSuccess ||
+        per < 1)
+      per = 1;
     resident = std::max(1, cus * per);
   }
   return resident;
@@ -487,14 +546,15 @@ hipError_t nrc_launch_forward(const float* x, int64_t n, const uint4* fwd, float
   PathsDev P;
   __builtin_memset(&P, 0, sizeof(P));
   int64_t groups = (n + 15) / 16;
-  int grid = (int)std::max<int64_t>(1, std::min<int64_t>((groups + 3) / 4, nrc_infer_grid()));
-  hipLaunchKernelGGL((k_nrc_infer<0>), dim3(grid), dim3(256), 0, st, x, n, P, fwd, y);
+  int grid = (int)std::max<int64_t>(1, std::min<int64_t>((groups + kInferWaves - 1) / kInferWaves, nrc_infer_grid()));
+  hipLaunchKernelGGL((k_nrc_infer<0>), dim3(grid), dim3(64 * kInferWaves), 0, st, x, n, P, fwd, y);
   return hipGetLastError();
 }
 
 hipError_t nrc_launch_query(const PathsDev& P, const uint4* fwd, int grid, hipStream_t st) {
   grid = std::max(1, std::min(grid, nrc_infer_grid()));
-  hipLaunchKernelGGL((k_nrc_infer<1>), dim3(grid), dim3(256), 0, st, nullptr, (int64_t)0, P, fwd, nullptr);
+  hipLaunchKernelGGL((k_nrc_infer<1>), dim3(grid), dim3(64 * kInferWaves), 0, st, nullptr, (int64_t)0, P, fwd,
+                     nullptr);
   return hipGetLastError();
 }
 

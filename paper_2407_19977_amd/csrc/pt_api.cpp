@@ -83,6 +83,13 @@ bool finite_all(const float* p, size_t n) {
 
 }  // namespace
 
+// Device buffers of one set of path slots (struct-of-arrays).
+struct PathBufs {
+  int64_t capacity = 0, nrc_q_cap = 0;
+  DevBuf ray_o, ray_d, hit, hit_inst, cls, beta, L, flags, q_ray[2], q_cls[kNumClasses], sh_o, sh_d, sh_c, sh_inst,
+      counts, sig, dbg_nee, dbg_tail, spill, nrc_q, q_nrc;
+};
+
 struct pt_scene {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -114,10 +121,13 @@ struct pt_scene {
   DevBuf lights, light_cdf, tri_light;
   int32_t n_lights = 0;
   float p_env = 0.0f;
-  // path state
-  int64_t capacity = 0;
-  DevBuf ray_o, ray_d, hit, hit_inst, cls, beta, L, flags, q_ray[2], q_cls[kNumClasses], sh_o, sh_d, sh_c, sh_inst,
-      counts, stats, sig, dbg_nee, dbg_tail, spill;
+  // path state: two sets, so that a pass's tail can run on the second stream
+  // while the next pass starts on the first
+  PathBufs pb[2];
+  DevBuf stats;
+  hipStream_t stream2 = nullptr;       // created on first use (default priority)
+  hipEvent_t ev_bulk[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
+  uint32_t* tail_counts = nullptr;     // pinned host words, one per set
   // accumulation
   DevBuf sum;
   int acc_w = 0, acc_h = 0;
@@ -127,7 +137,7 @@ struct pt_scene {
   double ms_extend = 0.0, ms_total = 0.0;
   int64_t launches_extend = 0;
   int64_t samples = 0;
-  std::vector<hipEvent_t> events;
+  std::vector<hipEvent_t> events[2];  // timing events per path set
   // scene box (radiance-cache position input)
   float box_lo[3] = {0.0f, 0.0f, 0.0f}, box_inv[3] = {0.0f, 0.0f, 0.0f};
   // radiance cache
@@ -136,8 +146,6 @@ struct pt_scene {
   pt_radiance_cache_config nrc_cfg;
   int64_t nrc_step = 0;    // Adam steps taken
   DevBuf nrc_w, nrc_m, nrc_v, nrc_fwd, nrc_bwd;  // FP32 master weights, Adam moments, bf16 fragments
-  DevBuf nrc_q, q_nrc;                           // per-slot query records, query list
-  int64_t nrc_q_cap = 0;
   DevBuf nrc_rec, nrc_off, nrc_bsum, nrc_n, nrc_X, nrc_T;  // training records, compaction
   int64_t nrc_rec_cap = 0;
   DevBuf nrc_Xb, nrc_Tb, nrc_a, nrc_g, nrc_loss, nrc_dw;  // one training step's workspace
@@ -148,7 +156,6 @@ struct pt_scene {
   // tail hand-off
   int tail_min_bounce = 3;
   double tail_fraction = 0.125;
-  uint32_t* tail_count = nullptr;  // pinned host word
   double ms_tail = 0.0;
   int64_t launches_tail = 0;
 };
@@ -289,27 +296,28 @@ pt_status ensure_lights(pt_scene* s) {
   return PT_OK;
 }
 
-pt_status ensure_paths(pt_scene* s, int64_t n) {
-  if (n <= s->capacity) return PT_OK;
+pt_status ensure_paths(pt_scene* s, int64_t n, int set = 0) {
+  PathBufs& B = s->pb[set];
+  if (n <= B.capacity) return PT_OK;
   size_t f4 = (size_t)n * sizeof(float4), u4 = (size_t)n * sizeof(uint32_t);
-  PT_HIP(s->ray_o.alloc(f4));
-  PT_HIP(s->ray_d.alloc(f4));
-  PT_HIP(s->hit.alloc(f4));
-  PT_HIP(s->hit_inst.alloc(u4));
-  PT_HIP(s->cls.alloc((size_t)n));
-  PT_HIP(s->sh_inst.alloc(u4));
-  PT_HIP(s->beta.alloc(f4));
-  PT_HIP(s->L.alloc(f4));
-  PT_HIP(s->flags.alloc(u4));
-  for (int i = 0; i < 2; ++i) PT_HIP(s->q_ray[i].alloc(u4));
-  for (int i = 0; i < kNumClasses; ++i) PT_HIP(s->q_cls[i].alloc(u4));
-  PT_HIP(s->sh_o.alloc(f4));
-  PT_HIP(s->sh_d.alloc(f4));
-  PT_HIP(s->sh_c.alloc(f4));
-  PT_HIP(s->sig.alloc((size_t)n * sizeof(uint64_t)));
-  PT_HIP(s->dbg_nee.alloc(u4));
-  PT_HIP(s->dbg_tail.alloc(u4));
-  s->capacity = n;
+  PT_HIP(B.ray_o.alloc(f4));
+  PT_HIP(B.ray_d.alloc(f4));
+  PT_HIP(B.hit.alloc(f4));
+  PT_HIP(B.hit_inst.alloc(u4));
+  PT_HIP(B.cls.alloc((size_t)n));
+  PT_HIP(B.sh_inst.alloc(u4));
+  PT_HIP(B.beta.alloc(f4));
+  PT_HIP(B.L.alloc(f4));
+  PT_HIP(B.flags.alloc(u4));
+  for (int i = 0; i < 2; ++i) PT_HIP(B.q_ray[i].alloc(u4));
+  for (int i = 0; i < kNumClasses; ++i) PT_HIP(B.q_cls[i].alloc(u4));
+  PT_HIP(B.sh_o.alloc(f4));
+  PT_HIP(B.sh_d.alloc(f4));
+  PT_HIP(B.sh_c.alloc(f4));
+  PT_HIP(B.sig.alloc((size_t)n * sizeof(uint64_t)));
+  PT_HIP(B.dbg_nee.alloc(u4));
+  PT_HIP(B.dbg_tail.alloc(u4));
+  B.capacity = n;
   return PT_OK;
 }
 
@@ -322,10 +330,11 @@ int grid_for(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, 2048));
 }
 
-pt_status ensure_counters(pt_scene* s) {
-  if (!s->counts.p) {
-    PT_HIP(s->counts.alloc(kNumCounts * sizeof(uint32_t)));
-    PT_HIP(hipMemsetAsync(s->counts.p, 0, kNumCounts * sizeof(uint32_t), s->stream));
+pt_status ensure_counters(pt_scene* s, int set = 0) {
+  PathBufs& B = s->pb[set];
+  if (!B.counts.p) {
+    PT_HIP(B.counts.alloc(kNumCounts * sizeof(uint32_t)));
+    PT_HIP(hipMemsetAsync(B.counts.p, 0, kNumCounts * sizeof(uint32_t), s->stream));
   }
   if (!s->stats.p) {
     PT_HIP(s->stats.alloc(kNumStats * sizeof(unsigned long long)));
@@ -334,15 +343,15 @@ pt_status ensure_counters(pt_scene* s) {
   return PT_OK;
 }
 
-pt_status ensure_spill(pt_scene* s, int grid_trace) {
+pt_status ensure_spill(pt_scene* s, int grid_trace, int set = 0) {
   int cap = 3 * std::max(s->bvh_depth, 1) + 4;
   size_t per = cap > kLdsStack ? (size_t)(cap - kLdsStack) : 1;
   size_t bytes = per * (size_t)grid_trace * kBlock * sizeof(uint2);
-  PT_HIP(s->spill.alloc(bytes));
+  PT_HIP(s->pb[set].spill.alloc(bytes));
   return PT_OK;
 }
 
-SceneDev scene_dev(pt_scene* s, int grid_trace) {
+SceneDev scene_dev(pt_scene* s, int grid_trace, int set = 0) {
   SceneDev S;
   std::memset(&S, 0, sizeof(S));
   S.nodes = s->nodes.as<BVHNode>();
@@ -368,7 +377,7 @@ SceneDev scene_dev(pt_scene* s, int grid_trace) {
   S.axis[0] = 0.0f;
   S.axis[1] = 0.0f;
   S.axis[2] = 1.0f;
-  S.spill = s->spill.as<uint2>();
+  S.spill = s->pb[set].spill.as<uint2>();
   S.stack_cap = 3 * std::max(s->bvh_depth, 1) + 4;
   S.spill_stride = (uint32_t)grid_trace * kBlock;
   S.insts = s->insts.as<InstRec>();
@@ -385,28 +394,29 @@ SceneDev scene_dev(pt_scene* s, int grid_trace) {
   return S;
 }
 
-PathsDev paths_dev(pt_scene* s, int64_t n, int x0, int y0, int w) {
+PathsDev paths_dev(pt_scene* s, int64_t n, int x0, int y0, int w, int set = 0) {
+  PathBufs& B = s->pb[set];
   PathsDev P;
   std::memset(&P, 0, sizeof(P));
-  P.ray_o = s->ray_o.as<float4>();
-  P.ray_d = s->ray_d.as<float4>();
-  P.hit = s->hit.as<float4>();
-  P.hit_inst = s->hit_inst.as<uint32_t>();
-  P.cls = s->cls.as<uint8_t>();
-  P.sh_inst = s->sh_inst.as<uint32_t>();
-  P.beta = s->beta.as<float4>();
-  P.L = s->L.as<float4>();
-  P.flags = s->flags.as<uint32_t>();
-  for (int i = 0; i < 2; ++i) P.q_ray[i] = s->q_ray[i].as<uint32_t>();
-  for (int i = 0; i < kNumClasses; ++i) P.q_cls[i] = s->q_cls[i].as<uint32_t>();
-  P.sh_o = s->sh_o.as<float4>();
-  P.sh_d = s->sh_d.as<float4>();
-  P.sh_c = s->sh_c.as<float4>();
-  P.counts = s->counts.as<uint32_t>();
+  P.ray_o = B.ray_o.as<float4>();
+  P.ray_d = B.ray_d.as<float4>();
+  P.hit = B.hit.as<float4>();
+  P.hit_inst = B.hit_inst.as<uint32_t>();
+  P.cls = B.cls.as<uint8_t>();
+  P.sh_inst = B.sh_inst.as<uint32_t>();
+  P.beta = B.beta.as<float4>();
+  P.L = B.L.as<float4>();
+  P.flags = B.flags.as<uint32_t>();
+  for (int i = 0; i < 2; ++i) P.q_ray[i] = B.q_ray[i].as<uint32_t>();
+  for (int i = 0; i < kNumClasses; ++i) P.q_cls[i] = B.q_cls[i].as<uint32_t>();
+  P.sh_o = B.sh_o.as<float4>();
+  P.sh_d = B.sh_d.as<float4>();
+  P.sh_c = B.sh_c.as<float4>();
+  P.counts = B.counts.as<uint32_t>();
   P.stats = s->stats.as<unsigned long long>();
-  P.sig = s->sig.as<uint64_t>();
-  P.dbg_nee = s->dbg_nee.as<uint32_t>();
-  P.dbg_tail = s->dbg_tail.as<uint32_t>();
+  P.sig = B.sig.as<uint64_t>();
+  P.dbg_nee = B.dbg_nee.as<uint32_t>();
+  P.dbg_tail = B.dbg_tail.as<uint32_t>();
   P.n = (int32_t)n;
   P.n_render = (int32_t)n;
   P.x0 = x0;
@@ -502,99 +512,170 @@ pt_status finish_training(pt_scene* s, const PathsDev& P, uint32_t* n_records) {
 pt_status nrc_train_records(pt_scene* s, const float* X_all, const float* T_all, const uint32_t* n_dev,
                             uint32_t frame, uint64_t seed, double* mean_loss);
 
+// Timing events of one pass (path set `set`): [0, 1] around the pass, [2, 3]
+// around the cache queries, [4, 5] around the tail kernel, then 2 per bounce.
+pt_status ensure_events(pt_scene* s, int set, int nev) {
+  while ((int)s->events[set].size() < nev) {
+    hipEvent_t e;
+    PT_HIP(hipEventCreate(&e));
+    s->events[set].push_back(e);
+  }
+  return PT_OK;
+}
+
+// Accumulate a finished pass's timing events into the profiling totals.
+pt_status read_pass_events(pt_scene* s, int set, int wavefront_bounces, int max_depth, bool queries, bool stops_at_query,
+                           int nrc_bounce) {
+  hipEvent_t* ev = s->events[set].data();
+  PT_HIP(hipEventSynchronize(ev[1]));
+  float ms = 0.0f;
+  PT_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+  s->ms_total += ms;
+  int last = wavefront_bounces - 1;
+  if (stops_at_query && nrc_bounce < last) last = nrc_bounce;
+  for (int b = 0; b <= last; ++b) {
+    PT_HIP(hipEventElapsedTime(&ms, ev[6 + 2 * b], ev[6 + 2 * b + 1]));
+    s->ms_extend += ms;
+    s->launches_extend++;
+  }
+  if (wavefront_bounces <= max_depth) {
+    PT_HIP(hipEventElapsedTime(&ms, ev[4], ev[5]));
+    s->ms_tail += ms;
+    s->launches_tail++;
+  }
+  if (queries) {
+    PT_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
+    s->ms_cache_query += ms;
+  }
+  return PT_OK;
+}
+
 // Run sampling passes over the tile (x0, y0, w, h) of the camera's image.
 // With train (n == 1), the pass also carries the frame's training paths and
-// the cache learns from them afterwards.
+// the cache learns from them afterwards.  Without training, consecutive
+// passes use the two path sets alternately: a pass's tail kernel and its
+// accumulation run on the second stream while the next pass's dense bounces
+// run on the scene's stream; the accumulations stay in pass order.
 pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h, int first, int n, int max_depth,
                      uint64_t seed, double* sum, float* per_sample, uint64_t* sigs, int spp_total,
                      bool train = false) {
   int64_t N = (int64_t)w * h;
   int64_t slots = N + (train ? s->nrc_cfg.train_paths : 0);
-  pt_status r = ensure_paths(s, slots);
-  if (r) return r;
-  r = ensure_counters(s);
-  if (r) return r;
+  const bool use_cache = s->nrc_on && s->nrc_ready;
+  const bool tail = s->tail_fraction > 0.0 && s->tail_min_bounce <= max_depth;
+  const bool overlap = !train && !use_cache && tail && n > 1;
+  const int nsets = overlap ? 2 : 1;
   int grid = grid_for(slots), grid_trace = traversal_grid(slots);
-  r = ensure_spill(s, grid_trace);
-  if (r) return r;
-  SceneDev S = scene_dev(s, grid_trace);
-  PathsDev P = paths_dev(s, N, x0, y0, w);
-  if (train && (r = setup_training(s, C, P, N, (uint32_t)first, max_depth, seed))) return r;
-  PassArgs A;
-  std::memset(&A, 0, sizeof(A));
-  A.k0 = (uint32_t)seed;
-  A.k1 = (uint32_t)(seed >> 32);
-  A.max_depth = max_depth;
-  A.grid = grid;
-  A.grid_trace = grid_trace;
-  A.grid_bin = bin_grid(slots);
-  A.debug = per_sample != nullptr;
-  A.count = s->counting;
-  A.two_level = s->two_level;
-  A.class_mask = s->class_mask | (1u << kClsMiss);
-  A.nrc_bounce = -1;
-  if (s->nrc_on && s->nrc_ready) {
-    if (N > s->nrc_q_cap) {
-      PT_HIP(s->nrc_q.alloc((size_t)N * kNrcQueryFloats * sizeof(float)));
-      PT_HIP(s->q_nrc.alloc((size_t)N * sizeof(uint32_t)));
-      s->nrc_q_cap = N;
+  pt_status r = PT_OK;
+  for (int set = 0; set < nsets; ++set) {
+    if ((r = ensure_paths(s, slots, set))) return r;
+    if ((r = ensure_counters(s, set))) return r;
+    if ((r = ensure_spill(s, grid_trace, set))) return r;
+  }
+  if (!s->tail_counts) PT_HIP(hipHostMalloc((void**)&s->tail_counts, 2 * sizeof(uint32_t), hipHostMallocDefault));
+  if (overlap) {
+    if (!s->stream2) PT_HIP(hipStreamCreateWithFlags(&s->stream2, hipStreamNonBlocking));
+    for (int k = 0; k < 2; ++k) {
+      if (!s->ev_bulk[k]) PT_HIP(hipEventCreateWithFlags(&s->ev_bulk[k], hipEventDisableTiming));
+      if (!s->ev_done[k]) PT_HIP(hipEventCreateWithFlags(&s->ev_done[k], hipEventDisableTiming));
     }
-    A.nrc_bounce = s->nrc_cfg.query_bounce;
-    A.nrc_fwd = s->nrc_fwd.as<uint4>();
-    P.nrc_q = s->nrc_q.as<float>();
-    P.q_nrc = s->q_nrc.as<uint32_t>();
   }
-  int nev = 2 * (max_depth + 1) + 6;
-  if (!s->tail_count) PT_HIP(hipHostMalloc((void**)&s->tail_count, sizeof(uint32_t), hipHostMallocDefault));
-  if (s->tail_fraction > 0.0 && s->tail_min_bounce <= max_depth) {
-    A.tail_host_count = s->tail_count;
-    A.tail_min_bounce = s->tail_min_bounce;
-    A.tail_fraction = s->tail_fraction;
-  }
-  int wavefront_bounces = max_depth + 1;
-  A.wavefront_bounces = &wavefront_bounces;
-  if (s->timing) {
-    while ((int)s->events.size() < nev) {
-      hipEvent_t e;
-      PT_HIP(hipEventCreate(&e));
-      s->events.push_back(e);
-    }
-    A.ext_events = s->events.data() + 6;
-    if (A.nrc_bounce >= 0) A.nrc_events = s->events.data() + 2;
-    A.tail_events = s->events.data() + 4;
-  }
+  const int nev = 6 + 2 * (max_depth + 1);
+  if (s->timing)
+    for (int set = 0; set < nsets; ++set)
+      if ((r = ensure_events(s, set, nev))) return r;
+  int wavefront[2] = {max_depth + 1, max_depth + 1};
+  bool tail_on_2[2] = {false, false};
+  int pending = -1;  // path set whose timing events are not read yet (overlap)
   for (int k = 0; k < n; ++k) {
+    const int set = overlap ? (k & 1) : 0;
+    SceneDev S = scene_dev(s, grid_trace, set);
+    PathsDev P = paths_dev(s, N, x0, y0, w, set);
+    if (train && (r = setup_training(s, C, P, N, (uint32_t)first, max_depth, seed))) return r;
+    PassArgs A;
+    std::memset(&A, 0, sizeof(A));
     A.sample = (uint32_t)(first + k);
-    if (s->timing) PT_HIP(hipEventRecord(s->events[0], s->stream));
+    A.k0 = (uint32_t)seed;
+    A.k1 = (uint32_t)(seed >> 32);
+    A.max_depth = max_depth;
+    A.grid = grid;
+    A.grid_trace = grid_trace;
+    A.grid_bin = bin_grid(slots);
+    A.debug = per_sample != nullptr;
+    A.count = s->counting;
+    A.two_level = s->two_level;
+    A.class_mask = s->class_mask | (1u << kClsMiss);
+    A.nrc_bounce = -1;
+    if (use_cache) {
+      PathBufs& B = s->pb[set];
+      if (N > B.nrc_q_cap) {
+        PT_HIP(B.nrc_q.alloc((size_t)N * kNrcQueryFloats * sizeof(float)));
+        PT_HIP(B.q_nrc.alloc((size_t)N * sizeof(uint32_t)));
+        B.nrc_q_cap = N;
+      }
+      A.nrc_bounce = s->nrc_cfg.query_bounce;
+      A.nrc_fwd = s->nrc_fwd.as<uint4>();
+      P.nrc_q = B.nrc_q.as<float>();
+      P.q_nrc = B.q_nrc.as<uint32_t>();
+    }
+    if (tail) {
+      A.tail_host_count = s->tail_counts + set;
+      A.tail_min_bounce = s->tail_min_bounce;
+      A.tail_fraction = s->tail_fraction;
+    }
+    A.wavefront_bounces = &wavefront[set];
+    tail_on_2[set] = false;
+    if (overlap) {
+      A.tail_stream = s->stream2;
+      A.tail_ready = s->ev_bulk[set];
+      A.tail_launched = &tail_on_2[set];
+    }
+    hipEvent_t* ev = s->timing ? s->events[set].data() : nullptr;
+    if (ev) {
+      A.ext_events = ev + 6;
+      if (A.nrc_bounce >= 0) A.nrc_events = ev + 2;
+      A.tail_events = ev + 4;
+    }
+    // the set's buffers are free once the pass that used them two passes ago has been accumulated
+    if (overlap && k >= 2) PT_HIP(hipStreamWaitEvent(s->stream, s->ev_done[set], 0));
+    if (ev) PT_HIP(hipEventRecord(ev[0], s->stream));
     PT_HIP(launch_pass(S, P, C, A, s->stream));
-    PT_HIP(launch_accumulate(P, sum, C.W, per_sample, sigs, spp_total, k, s->stream));
-    if (s->timing) {
-      PT_HIP(hipEventRecord(s->events[1], s->stream));
-      PT_HIP(hipEventSynchronize(s->events[1]));
-      float ms = 0.0f;
-      PT_HIP(hipEventElapsedTime(&ms, s->events[0], s->events[1]));
-      s->ms_total += ms;
-      int last = wavefront_bounces - 1;
-      if (A.nrc_bounce >= 0 && A.nrc_bounce < last && P.n == P.n_render) last = A.nrc_bounce;  // stops there
-      for (int b = 0; b <= last; ++b) {
-        PT_HIP(hipEventElapsedTime(&ms, A.ext_events[2 * b], A.ext_events[2 * b + 1]));
-        s->ms_extend += ms;
-        s->launches_extend++;
-      }
-      if (wavefront_bounces <= max_depth) {
-        PT_HIP(hipEventElapsedTime(&ms, A.tail_events[0], A.tail_events[1]));
-        s->ms_tail += ms;
-        s->launches_tail++;
-      }
-      if (A.nrc_events) {
-        PT_HIP(hipEventElapsedTime(&ms, A.nrc_events[0], A.nrc_events[1]));
-        s->ms_cache_query += ms;
+    hipStream_t acc = s->stream;
+    if (overlap) {
+      acc = s->stream2;
+      if (!tail_on_2[set]) {  // the pass finished on the first stream: order the accumulation after it
+        PT_HIP(hipEventRecord(s->ev_bulk[set], s->stream));
+        PT_HIP(hipStreamWaitEvent(s->stream2, s->ev_bulk[set], 0));
       }
     }
+    PT_HIP(launch_accumulate(P, sum, C.W, per_sample, sigs, spp_total, k, acc));
+    if (ev) PT_HIP(hipEventRecord(ev[1], acc));
+    if (overlap) PT_HIP(hipEventRecord(s->ev_done[set], s->stream2));
+    if (ev) {
+      if (overlap) {  // read the previous pass while this one runs
+        if (pending >= 0 &&
+            (r = read_pass_events(s, pending, wavefront[pending], max_depth, false, false, -1)))
+          return r;
+        pending = set;
+      } else if ((r = read_pass_events(s, set, wavefront[set], max_depth, A.nrc_bounce >= 0, P.n == P.n_render,
+                                       A.nrc_bounce))) {
+        return r;
+      }
+    }
+  }
+  if (overlap) {  // the scene's stream sees every pass done
+    PT_HIP(hipStreamWaitEvent(s->stream, s->ev_done[0], 0));
+    PT_HIP(hipStreamWaitEvent(s->stream, s->ev_done[1], 0));
+    if (pending >= 0 && (r = read_pass_events(s, pending, wavefront[pending], max_depth, false, false, -1))) return r;
   }
   s->samples += (int64_t)n * N;
   if (train) {
     auto t0 = std::chrono::steady_clock::now();
+    PathsDev P = paths_dev(s, N, x0, y0, w, 0);
+    P.n = (int32_t)slots;
+    P.n_render = (int32_t)N;
+    P.rec = s->nrc_rec.as<float>();
+    P.rec_depth = max_depth;
     uint32_t nrec = 0;
     if ((r = finish_training(s, P, &nrec))) return r;
     s->nrc_records += nrec;
@@ -1057,8 +1138,15 @@ void pt_scene_destroy(pt_scene* s) {
   if (!s) return;
   (void)hipSetDevice(s->device);
   (void)hipStreamSynchronize(s->stream);
-  for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
-  if (s->tail_count) (void)hipHostFree(s->tail_count);
+  if (s->stream2) (void)hipStreamSynchronize(s->stream2);
+  for (auto& v : s->events)
+    for (hipEvent_t e : v) (void)hipEventDestroy(e);
+  for (int k = 0; k < 2; ++k) {
+    if (s->ev_bulk[k]) (void)hipEventDestroy(s->ev_bulk[k]);
+    if (s->ev_done[k]) (void)hipEventDestroy(s->ev_done[k]);
+  }
+  if (s->stream2) (void)hipStreamDestroy(s->stream2);
+  if (s->tail_counts) (void)hipHostFree(s->tail_counts);
   delete s;
 }
 

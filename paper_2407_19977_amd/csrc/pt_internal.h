@@ -142,6 +142,9 @@ struct PassArgs {
   double tail_fraction;
   hipEvent_t* tail_events;  // 2 events around the tail kernel when timing, else nullptr
   int* wavefront_bounces;   // out: bounces run by the wavefront kernels (host)
+  hipStream_t tail_stream;  // if set, the tail kernel runs there after tail_ready (recorded here)
+  hipEvent_t tail_ready;
+  bool* tail_launched;      // out: the tail kernel was launched on tail_stream
 };
 
 hipError_t launch_pass(const SceneDev& S, const PathsDev& P, const CamDev& C, const PassArgs& A,

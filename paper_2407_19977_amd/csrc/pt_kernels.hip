@@ -1102,10 +1102,18 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
       if (e0 != hipSuccess) return e0;
       if ((double)*A.tail_host_count <= A.tail_fraction * (double)P.n) {
         if (A.wavefront_bounces) *A.wavefront_bounces = b;
-        if (A.tail_events) hipEventRecord(A.tail_events[0], st);
-        hipLaunchKernelGGL((k_tail<DEBUG, COUNT, TWO>), dim3(tail_grid(A.grid_trace)), blk, 0, st, S, P, cur, b, A.max_depth,
-                           A.sample, A.k0, A.k1, (uint32_t)C.W);
-        if (A.tail_events) hipEventRecord(A.tail_events[1], st);
+        hipStream_t ts = st;
+        if (A.tail_stream) {  // continue on the second stream; the caller's stream is free for the next pass
+          hipError_t e1 = hipEventRecord(A.tail_ready, st);
+          if (e1 == hipSuccess) e1 = hipStreamWaitEvent(A.tail_stream, A.tail_ready, 0);
+          if (e1 != hipSuccess) return e1;
+          ts = A.tail_stream;
+          if (A.tail_launched) *A.tail_launched = true;
+        }
+        if (A.tail_events) hipEventRecord(A.tail_events[0], ts);
+        hipLaunchKernelGGL((k_tail<DEBUG, COUNT, TWO>), dim3(tail_grid(A.grid_trace)), blk, 0, ts, S, P, cur, b,
+                           A.max_depth, A.sample, A.k0, A.k1, (uint32_t)C.W);
+        if (A.tail_events) hipEventRecord(A.tail_events[1], ts);
         break;
       }
     }

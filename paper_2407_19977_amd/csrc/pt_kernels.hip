@@ -1036,20 +1036,19 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays_brute(SceneDev S, const f
 // --------------------------------------------------------------- launchers
 int trace_grid_blocks() { return 2048; }
 
-// Resident workgroups of the tail kernel (it holds far more registers).
-int tail_grid(int grid_trace) {
-  static int resident = 0;
-  if (!resident) {
-    int dev = 0, cus = 0, per = 0;
+// Workgroups of the tail kernel: about three paths per lane, and at most one
+// workgroup per CU, so that a tail running beside the next pass's dense
+// bounces (second stream) leaves most of each CU to them.
+int tail_grid(int grid_trace, uint32_t paths) {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
       cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tail<true, true, true>, kBlock, 0) != hipSuccess ||
-        per < 1)
-      per = 1;
-    resident = std::max(1, cus * per);
   }
-  return std::min(grid_trace, resident);
+  int want = (int)std::min<uint64_t>((uint64_t)cus, std::max<uint64_t>(8, ((uint64_t)paths + 767) / 768));
+  return std::max(1, std::min(grid_trace, want));
 }
 
 // The traversal kernels keep one resident set of workgroups (persistent
@@ -1111,7 +1110,8 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
           if (A.tail_launched) *A.tail_launched = true;
         }
         if (A.tail_events) hipEventRecord(A.tail_events[0], ts);
-        hipLaunchKernelGGL((k_tail<DEBUG, COUNT, TWO>), dim3(tail_grid(A.grid_trace)), blk, 0, ts, S, P, cur, b,
+        hipLaunchKernelGGL((k_tail<DEBUG, COUNT, TWO>), dim3(tail_grid(A.grid_trace, *A.tail_host_count)), blk, 0, ts,
+                           S, P, cur, b,
                            A.max_depth, A.sample, A.k0, A.k1, (uint32_t)C.W);
         if (A.tail_events) hipEventRecord(A.tail_events[1], ts);
         break;

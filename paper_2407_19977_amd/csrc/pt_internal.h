@@ -158,7 +158,7 @@ hipError_t launch_trace_rays(const SceneDev& S, const float* rays, int64_t n, ui
                              bool two_level, int grid, hipStream_t st);
 int trace_grid_blocks();
 int traversal_grid(int64_t rays);  // workgroups of k_extend / k_connect for a pass of `rays` paths
-int tail_grid(int grid_trace, uint32_t paths);  // workgroups of the tail kernel for `paths` live paths
+int tail_grid(int grid_trace, uint32_t paths, bool beside);  // workgroups of the tail kernel
 
 // ---- radiance cache (pt_nrc.hip) ----
 hipError_t nrc_launch_pack(const float* w, uint4* fwd, uint4* bwd, hipStream_t st);

@@ -1036,17 +1036,23 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays_brute(SceneDev S, const f
 // --------------------------------------------------------------- launchers
 int trace_grid_blocks() { return 2048; }
 
-// Workgroups of the tail kernel: about three paths per lane, and at most one
-// workgroup per CU, so that a tail running beside the next pass's dense
-// bounces (second stream) leaves most of each CU to them.
-int tail_grid(int grid_trace, uint32_t paths) {
-  static int cus = 0;
+// Workgroups of the tail kernel.  Alone, every resident workgroup (about one
+// path per lane: the tail ends with its longest path).  Beside the next
+// pass's dense bounces (second stream), about three paths per lane and at
+// most one workgroup per CU, which leaves most of each CU to them.
+int tail_grid(int grid_trace, uint32_t paths, bool beside) {
+  static int cus = 0, resident = 0;
   if (!cus) {
-    int dev = 0;
+    int dev = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
       cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tail<true, true, true>, kBlock, 0) != hipSuccess ||
+        per < 1)
+      per = 1;
+    resident = cus * per;
   }
+  if (!beside) return std::max(1, std::min(grid_trace, resident));
   int want = (int)std::min<uint64_t>((uint64_t)cus, std::max<uint64_t>(8, ((uint64_t)paths + 767) / 768));
   return std::max(1, std::min(grid_trace, want));
 }
@@ -1110,7 +1116,7 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
           if (A.tail_launched) *A.tail_launched = true;
         }
         if (A.tail_events) hipEventRecord(A.tail_events[0], ts);
-        hipLaunchKernelGGL((k_tail<DEBUG, COUNT, TWO>), dim3(tail_grid(A.grid_trace, *A.tail_host_count)), blk, 0, ts,
+        hipLaunchKernelGGL((k_tail<DEBUG, COUNT, TWO>), dim3(tail_grid(A.grid_trace, *A.tail_host_count, A.tail_stream != nullptr)), blk, 0, ts,
                            S, P, cur, b,
                            A.max_depth, A.sample, A.k0, A.k1, (uint32_t)C.W);
         if (A.tail_events) hipEventRecord(A.tail_events[1], ts);

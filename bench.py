@@ -197,6 +197,54 @@ def tail_info(counts, st, steps):
     return info
 
 
+def instanced_4k(pt, torch, spp, ref_spp):
+    """The instanced scene at 3840x2160: plain tracer and radiance cache side by
+    side, each accumulated to `spp` samples (FP64 sums; the cache in frames of
+    1 spp), against a `ref_spp` plain render with an independent seed.
+    Prints progress to stderr; returns the JSON object of the comparison."""
+    from paper_2407_19977_amd import scenes
+    sc = scenes.instanced(width=3840, height=2160, spp=spp)
+    cam = sc.camera
+    W, H, depth, seed = cam.width, cam.height, sc.max_depth, sc.seed
+    s = pt.scene_from(sc, device=0)
+    out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda:0")
+    acc = torch.empty((H, W, 3), dtype=torch.float64, device="cuda:0")
+    chunk = 32
+
+    def run(n, sd, cache):
+        s.set_radiance_cache(pt.cache_config() if cache else None)
+        s.reset_accumulation()
+        s.reset_stats()
+        s.set_profiling(True, False)
+        t0 = time.perf_counter()
+        for k in range(0, n, chunk):
+            s.accumulate(cam, k, min(chunk, n - k), depth, sd)
+            print(f"[4k] {'cache' if cache else 'plain'} seed {sd}: {min(n, k + chunk)}/{n} spp, "
+                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        dt = time.perf_counter() - t0
+        st = s.stats()
+        s.set_profiling(False, False)
+        s.resolve(out, acc)
+        return dt, st, (acc / n).clone()
+
+    t_ref, _, ref = run(ref_spp, seed + 1, False)
+    res = {"workload": f"instanced scene (400 instances of 5 meshes, 10.8M instanced triangles), {W}x{H}, depth {depth}",
+           "reference": f"{ref_spp} spp plain tracer, FP64 sums, seed {seed + 1} ({t_ref:.1f} s)", "modes": {}}
+    for cache in (False, True):
+        dt, st, img = run(spp, seed, cache)
+        d = img - ref
+        rays = st["extension_rays"] + st["shadow_rays"]
+        res["modes"]["cache" if cache else "plain"] = {
+            "spp": spp, "seconds": round(dt, 3), "Mrays_per_s": round(rays / dt / 1e6, 1),
+            "samples_per_s": round(W * H * spp / dt, 1),
+            "rmse": round(torch.sqrt(torch.mean(d * d)).item(), 6),
+            "relmse": round(torch.mean(d * d / (ref * ref + 0.01)).item(), 6),
+            "cache_queries": st["cache_queries"], "adam_steps": st["cache_adam_steps"]}
+    s.set_radiance_cache(None)
+    s.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +256,10 @@ def main():
     ap.add_argument("--no-cache", action="store_true", help="skip the radiance-cache vs plain experiment")
     ap.add_argument("--cache-frames", type=int, default=256)
     ap.add_argument("--ref-spp", type=int, default=4096)
+    ap.add_argument("--workload", choices=["spheres-1080p", "instanced-4k"], default="spheres-1080p",
+                    help="instanced-4k: plain vs cache on the instanced scene at 3840x2160 (minutes; not the bench line)")
+    ap.add_argument("--spp-4k", type=int, default=1024)
+    ap.add_argument("--ref-spp-4k", type=int, default=2048)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -219,6 +271,12 @@ def main():
 
     import torch
     from paper_2407_19977_amd import pt, scenes
+
+    if args.workload == "instanced-4k":
+        torch.cuda.set_device(0)
+        print(json.dumps({"metric": "plain vs radiance cache, 4K instanced scene",
+                          "result": instanced_4k(pt, torch, args.spp_4k, args.ref_spp_4k)}), flush=True)
+        return
 
     sc = scenes.spheres(spp=args.spp)
     cam = sc.camera

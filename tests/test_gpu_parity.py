@@ -339,6 +339,10 @@ def test_error_codes(P, O):
     with pytest.raises(P.PtError) as e:
         fresh.render(cam, 1, 1, 0, out)
     assert e.value.status == -5
+    for args in ((-1, 0.5), (3, 1.5), (3, -0.1)):
+        with pytest.raises(P.PtError) as e:
+            s.set_tail(*args)
+        assert e.value.status == -1
     m = sc.meshes[0]
     broken = scenes.Mesh(m.vertices, m.indices.copy(), m.material_ids)
     broken.indices[0, 0] = 10 ** 6
@@ -348,3 +352,23 @@ def test_error_codes(P, O):
     # the scene is unchanged by the failed calls and still renders
     s.render(cam, 2, 4, 0, out)
     assert torch.isfinite(out).all()
+
+
+def test_box_image_rmse_against_fp64_reference(P, O):
+    """The box scene's 16-spp GPU image against a 4096-spp FP64 oracle render
+    with an independent seed: the RMSE is stated, and it equals the oracle's
+    own 16-spp RMSE (both draw the same random numbers, so the two 16-spp
+    images agree path by path) to 1 %."""
+    sc, s, os_ = _cornell(P, O)
+    cam = sc.camera
+    out = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device="cuda:0")
+    s.render(cam, 16, sc.max_depth, 0, out)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy().astype(np.float64)
+    ref = os_.render(4096, sc.max_depth, seed=1)["mean"]
+    o16 = os_.render(16, sc.max_depth, seed=0)["mean"]
+    e_gpu = float(np.sqrt(np.mean((g - ref) ** 2)))
+    e_ora = float(np.sqrt(np.mean((o16 - ref) ** 2)))
+    _say(f"[rmse] box 128x128, 16 spp vs 4096-spp FP64 reference: GPU {e_gpu:.5f}, oracle {e_ora:.5f} "
+         f"(reference mean {ref.mean():.4f})")
+    assert abs(e_gpu - e_ora) <= 0.01 * e_ora

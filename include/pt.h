@@ -37,7 +37,7 @@ typedef enum pt_status {
   PT_ERR_INVALID_ARG = -1,  /* a pointer, count, index or parameter is out of range */
   PT_ERR_OUT_OF_MEMORY = -2,
   PT_ERR_DEVICE = -3,       /* a HIP call failed (message has the HIP error string) */
-  PT_ERR_UNSUPPORTED = -4,  /* a valid parameter combination this build does not implement */
+  PT_ERR_UNSUPPORTED = -4,  /* a valid parameter combination this library does not implement */
   PT_ERR_STATE = -5         /* e.g. render before pt_build_bvh / pt_upload_materials */
 } pt_status;
 

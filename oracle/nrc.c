@@ -2,7 +2,7 @@
  * Oracle of the radiance cache (test infrastructure only), FP64.
  *
  * The paper names neural radiance caching (Mueller et al. 2021) as future
- * work for needing fewer samples (Sec. 6.1).  This build's reading of it:
+ * work for needing fewer samples (Sec. 6.1).  The reading implemented here:
  *
  * Inputs at a path vertex (12): position normalised to the scene box (3);
  * the outgoing direction wo and the shading normal n, each as

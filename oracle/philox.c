@@ -3,8 +3,8 @@
  * "Parallel random numbers: as easy as 1, 2, 3", SC'11).
  *
  * The paper draws its random numbers from a per-pixel generator
- * (Sec. 5.1.2, where it picks PCG); this build keys a counter-based
- * generator by (pixel, sample, bounce, dimension block) so that any single
+ * (Sec. 5.1.2, where it picks PCG); here a counter-based generator is keyed
+ * by (pixel, sample, bounce, dimension block) so that any single
  * path can be regenerated on its own, by the oracle or by the GPU.
  *
  * One round: with multipliers M0 = 0xD2511F53 and M1 = 0xCD9E8D57, take the

@@ -177,13 +177,7 @@ __device__ inline f32x4 mlp_forward(const uint4* __restrict__ sw, int lane, bf16
 // MODE 0: inputs x[n][12], outputs y[n][3].
 // MODE 1: the cache queries of a sampling pass: slot = q_nrc[i] for i < counts[kCountQuery];
 //         inputs nrc_q[slot][0..11], throughput nrc_q[slot][12..14]; L[slot] += beta * max(y, 0).
-#ifndef PT_NRC_INFER_WAVES
-#define PT_NRC_INFER_WAVES 8
-#endif
-#ifndef PT_NRC_LDS_WEIGHTS
-#define PT_NRC_LDS_WEIGHTS 1
-#endif
-constexpr int kInferWaves = PT_NRC_INFER_WAVES;  // waves per workgroup (one weight copy in LDS each)
+constexpr int kInferWaves = 8;  // waves per workgroup sharing one LDS copy of the weight fragments
 
 template <int MODE>
 __global__ __launch_bounds__(64 * kInferWaves) void k_nrc_infer(const float* __restrict__ xin, int64_t n_arg,
@@ -197,9 +191,9 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_nrc_infer(const float* __r
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, g = lane / 16, q = lane % 16;
   unsigned long long nonfinite = 0;
   for (int64_t grp = (int64_t)blockIdx.x * kInferWaves + wave; grp * 16 < n; grp += (int64_t)gridDim.x * kInferWaves) {
-#if PT_NRC_LDS_WEIGHTS
-    asm volatile("" ::: "memory");  // weights are read from LDS in every group, not held in registers
-#endif
+    // Read the weight fragments from LDS in every group: held in registers
+    // they would take 168 VGPRs and leave one wave per SIMD.
+    asm volatile("" ::: "memory");
     int64_t qi = grp * 16 + q;
     bool valid = qi < n;
     const float* r = nullptr;

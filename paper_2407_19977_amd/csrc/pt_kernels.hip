@@ -293,6 +293,18 @@ constexpr uint32_t kNoInst = 0xFFFFFFFFu;
 #define PT_REFILL 16
 #endif
 constexpr uint32_t kRefill = PT_REFILL;  // idle lanes that trigger a refill
+#ifndef PT_TAIL_SHADE_WAIT
+#define PT_TAIL_SHADE_WAIT 1
+#endif
+// tail kernel: lanes waiting to shade go ahead once kTailShadeWait x their
+// number reaches the number of lanes still walking (a large value shades at
+// once, as soon as a walk ends)
+constexpr uint32_t kTailShadeWait = PT_TAIL_SHADE_WAIT;
+#ifndef PT_TAIL_PATHS_PER_GROUP
+#define PT_TAIL_PATHS_PER_GROUP 384
+#endif
+// tail kernel beside the next pass: paths per workgroup (about 1.5 per lane)
+constexpr uint64_t kTailPathsPerGroup = PT_TAIL_PATHS_PER_GROUP;
 #ifndef PT_EXT_WAVES
 #define PT_EXT_WAVES 6
 #endif
@@ -840,10 +852,11 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
   const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
   DevStack st{lds_stack_base(s_stack), S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
   LaneRay L;
-  int phase = 0;  // 0 idle, 1 closest-hit walk, 2 shadow-ray walk
+  // 0 idle, 1 closest-hit walk, 2 shadow-ray walk, 3 hit found and waiting to be shaded
+  int phase = 0;
   bool drained = false, cont = false;
   uint32_t slot = 0;
-  int b = b_first;
+  int b = b_first, cls = kClsMiss;
   float4 sh_c = make_float4(0, 0, 0, 0);
   uint32_t n_ext = 0, n_sh = 0, nvis = 0, ntri = 0, svis = 0, stri = 0;
   unsigned long long nonfinite = 0;
@@ -874,7 +887,7 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
     if (phase == 1) {
       if (lane_step<false, COUNT, TWO>(S, L, st, nvis, ntri)) {
         overflow |= st.overflow;
-        int cls = kClsMiss;
+        cls = kClsMiss;
         if (L.best.tri != 0xFFFFFFFFu) {
           P.hit[slot] = make_float4(L.best.t, L.best.b1, L.best.b2, u2f(L.best.tri));
           uint32_t mid = L.best.mat;
@@ -887,22 +900,7 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
         } else {
           P.hit[slot] = make_float4(INFINITY, 0.0f, 0.0f, u2f(0xFFFFFFFFu));
         }
-        ShadeOut o;
-        shade_any<DEBUG, TWO>(cls, S, P, slot, b, max_depth, sample, k0, k1, img_w, o, nonfinite);
-        if (o.shadow) {
-          st.sp = 0;
-          lane_start<TWO>(L, o.sh_o.x, o.sh_o.y, o.sh_o.z, o.sh_d.x, o.sh_d.y, o.sh_d.z, S.tmin, o.sh_o.w,
-                          TWO ? o.sh_inst : 0u, f2u(o.sh_c.w), TWO ? 0u : S.root);
-          sh_c = o.sh_c;
-          cont = o.cont;
-          phase = 2;
-          n_sh++;
-        } else if (o.cont) {
-          b++;
-          start_closest();
-        } else {
-          phase = 0;
-        }
+        phase = 3;
       }
     } else if (phase == 2) {
       if (lane_step<true, COUNT, TWO>(S, L, st, svis, stri)) {
@@ -931,6 +929,30 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
         } else {
           phase = 0;
         }
+      }
+    }
+    // Shading is a long stretch of code per material class.  Lanes that found
+    // their hit wait until they are at least as many as the lanes still
+    // walking (or until no lane walks), so that one pass over the shading code
+    // serves many lanes instead of one pass per walk that ends.
+    const uint32_t n_ready = (uint32_t)__popcll((unsigned long long)__ballot(phase == 3));
+    const uint32_t n_walk = (uint32_t)__popcll((unsigned long long)__ballot(phase == 1 || phase == 2));
+    if (n_ready && kTailShadeWait * n_ready >= n_walk && phase == 3) {
+      ShadeOut o;
+      shade_any<DEBUG, TWO>(cls, S, P, slot, b, max_depth, sample, k0, k1, img_w, o, nonfinite);
+      if (o.shadow) {
+        st.sp = 0;
+        lane_start<TWO>(L, o.sh_o.x, o.sh_o.y, o.sh_o.z, o.sh_d.x, o.sh_d.y, o.sh_d.z, S.tmin, o.sh_o.w,
+                        TWO ? o.sh_inst : 0u, f2u(o.sh_c.w), TWO ? 0u : S.root);
+        sh_c = o.sh_c;
+        cont = o.cont;
+        phase = 2;
+        n_sh++;
+      } else if (o.cont) {
+        b++;
+        start_closest();
+      } else {
+        phase = 0;
       }
     }
   }
@@ -1053,7 +1075,8 @@ int tail_grid(int grid_trace, uint32_t paths, bool beside) {
     resident = cus * per;
   }
   if (!beside) return std::max(1, std::min(grid_trace, resident));
-  int want = (int)std::min<uint64_t>((uint64_t)cus, std::max<uint64_t>(8, ((uint64_t)paths + 767) / 768));
+  int want = (int)std::min<uint64_t>((uint64_t)cus, std::max<uint64_t>(8, ((uint64_t)paths + kTailPathsPerGroup - 1) /
+                                                                                 kTailPathsPerGroup));
   return std::max(1, std::min(grid_trace, want));
 }
 

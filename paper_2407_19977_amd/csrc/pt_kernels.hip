@@ -38,6 +38,12 @@ __device__ inline uint32_t wave_append(bool pred, uint32_t* count) {
   return pred ? base + lane_prefix(m) : 0xFFFFFFFFu;
 }
 
+// Sum of a value over the wave's 64 lanes (every lane gets the sum).
+__device__ inline uint32_t wave_sum(uint32_t v) {
+  for (int d = 32; d >= 1; d >>= 1) v += (uint32_t)__shfl_xor((int)v, d);
+  return v;
+}
+
 // ------------------------------------------------------------- signatures
 constexpr uint64_t kFnvOffset = 0xcbf29ce484222325ull;
 constexpr uint64_t kFnvPrime = 0x100000001b3ull;
@@ -293,6 +299,13 @@ constexpr uint32_t kNoInst = 0xFFFFFFFFu;
 #define PT_REFILL 16
 #endif
 constexpr uint32_t kRefill = PT_REFILL;  // idle lanes that trigger a refill
+#ifndef PT_BLOCK_APPEND
+#define PT_BLOCK_APPEND 1
+#endif
+#ifndef PT_SHADE_BLOCK
+#define PT_SHADE_BLOCK 256
+#endif
+constexpr int kShadeBlock = PT_SHADE_BLOCK;  // threads per workgroup of the shading kernels
 #ifndef PT_TAIL_SHADE_WAIT
 #define PT_TAIL_SHADE_WAIT 1
 #endif
@@ -732,12 +745,15 @@ __device__ inline void shade_one(const SceneDev& S, const PathsDev& P, uint32_t 
 }
 
 template <int CLS, bool DEBUG, bool TWO>
-__global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b, int max_depth, int next,
+__global__ __launch_bounds__(kShadeBlock) void k_shade(SceneDev S, PathsDev P, int b, int max_depth, int next,
                                                   uint32_t sample, uint32_t k0, uint32_t k1, uint32_t img_w,
                                                   int nrc_bounce) {
+  // per queue (next rays, shadow rays, cache queries): wave counts, then the workgroup's base
+  __shared__ uint32_t s_app[3][kShadeBlock / 64 + 1];
   const uint32_t count = P.counts[2 + CLS];
+  const bool query = b == nrc_bounce;
   unsigned long long nonfinite = 0;
-  for (uint32_t base = blockIdx.x * kBlock; base < count; base += gridDim.x * kBlock) {
+  for (uint32_t base = blockIdx.x * kShadeBlock; base < count; base += gridDim.x * kShadeBlock) {
     uint32_t i = base + threadIdx.x;
     bool active = i < count;
     uint32_t slot = 0;
@@ -747,14 +763,46 @@ __global__ __launch_bounds__(kBlock) void k_shade(SceneDev S, PathsDev P, int b,
       slot = P.q_cls[CLS][i];
       shade_one<CLS, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, nrc_bounce, o, nonfinite);
     }
+#if PT_BLOCK_APPEND
+    // One atomic per queue per workgroup iteration: the queue counters are
+    // single words that every workgroup of the launch appends to.
+    const uint64_t m_cont = __ballot(o.cont), m_sh = __ballot(o.shadow), m_q = __ballot(o.query);
+    const int w = (int)(threadIdx.x >> 6);
+    if (lane_id() == 0) {
+      s_app[0][w] = (uint32_t)__popcll(m_cont);
+      s_app[1][w] = (uint32_t)__popcll(m_sh);
+      s_app[2][w] = (uint32_t)__popcll(m_q);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      uint32_t tot = 0;
+      for (int k = 0; k < kShadeBlock / 64; ++k) tot += s_app[threadIdx.x][k];
+      uint32_t* ctr = threadIdx.x == 0 ? &P.counts[next] : threadIdx.x == 1 ? &P.counts[kCountShadow]
+                                                                              : &P.counts[kCountQuery];
+      s_app[threadIdx.x][kShadeBlock / 64] = tot ? atomicAdd(ctr, tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t off[3];
+    for (int q = 0; q < 3; ++q) {
+      uint32_t acc = s_app[q][kShadeBlock / 64];
+      for (int k = 0; k < w; ++k) acc += s_app[q][k];
+      off[q] = acc;
+    }
+    __syncthreads();  // s_app is rewritten by the next iteration
+    if (o.cont) P.q_ray[next][off[0] + lane_prefix(m_cont)] = slot;
+    if (query && o.query) P.q_nrc[off[2] + lane_prefix(m_q)] = slot;
+    if (o.shadow) {
+      const uint32_t spos = off[1] + lane_prefix(m_sh);
+#else
     uint32_t qpos = wave_append(o.cont, &P.counts[next]);
     if (o.cont) P.q_ray[next][qpos] = slot;
-    if (b == nrc_bounce) {
+    if (query) {
       uint32_t npos = wave_append(o.query, &P.counts[kCountQuery]);
       if (o.query) P.q_nrc[npos] = slot;
     }
     uint32_t spos = wave_append(o.shadow, &P.counts[kCountShadow]);
     if (o.shadow) {
+#endif
       P.sh_o[spos] = o.sh_o;
       P.sh_d[spos] = o.sh_d;
       P.sh_c[spos] = o.sh_c;
@@ -956,9 +1004,14 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
       }
     }
   }
-  atomicAdd(&P.stats[kStatExt], (unsigned long long)n_ext);
-  atomicAdd(&P.stats[kStatTailExt], (unsigned long long)n_ext);
-  atomicAdd(&P.stats[kStatShadow], (unsigned long long)n_sh);
+  // statistics: one atomic per wave and counter
+  n_ext = wave_sum(n_ext);
+  n_sh = wave_sum(n_sh);
+  if (lane_id() == 0) {
+    atomicAdd(&P.stats[kStatExt], (unsigned long long)n_ext);
+    atomicAdd(&P.stats[kStatTailExt], (unsigned long long)n_ext);
+    atomicAdd(&P.stats[kStatShadow], (unsigned long long)n_sh);
+  }
   if (COUNT) {
     atomicAdd(&P.stats[kStatTailNodes], (unsigned long long)nvis);
     atomicAdd(&P.stats[kStatTailTris], (unsigned long long)ntri);
@@ -1100,7 +1153,7 @@ int traversal_grid(int64_t rays) {
 template <bool DEBUG, bool TWO>
 static hipError_t shade_all(const SceneDev& S, const PathsDev& P, const PassArgs& A, int b, int next, uint32_t W,
                             hipStream_t st) {
-  dim3 g(A.grid), blk(kBlock);
+  dim3 g(std::max(1, A.grid * kBlock / kShadeBlock)), blk(kShadeBlock);
 #define PT_SHADE(C)                                                                                     \
   if (A.class_mask & (1u << C))                                                                         \
     hipLaunchKernelGGL((k_shade<C, DEBUG, TWO>), g, blk, 0, st, S, P, b, A.max_depth, next, A.sample, A.k0, \

@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Mrays/s and samples/s at 1080p; time-to-equal-RMSE, radiance cache vs plain"
 HBM_PEAK_GBS = 8000.0
 NODE_BYTES, TRI_BYTES, RAY_BYTES, HIT_BYTES = 128, 48, 32, 16
+SHADOW_RAY_BYTES = 48  # o + tmax, d + path slot, contribution + skip primitive (the L update is not counted)
 
 
 def kernel_source_hash() -> str:
@@ -41,9 +42,9 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic():
-    """HBM bytes per k_extend launch from the committed counter summary, or
+    """HBM bytes per k_traverse launch from the committed counter summary, or
     None when the kernel sources changed since those counters were taken."""
-    path = os.path.join(ROOT, "profiles", "k_extend_spheres_1080p.md")
+    path = os.path.join(ROOT, "profiles", "k_traverse_spheres_1080p.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -319,20 +320,26 @@ def main():
 
     roofline = None
     if counts is not None and st["launches_extend"] > 0:
-        # the wavefront closest-hit kernel only: the tail kernel's rays and visits are counted apart
+        # the wavefront traversal kernel only: the tail kernel's rays and visits are counted apart
         ext_rays = counts["extension_rays"] - counts["tail_extension_rays"]
+        sh_rays = counts["shadow_rays"] - counts["tail_shadow_rays"]
         ext_bytes = (counts["node_visits"] * NODE_BYTES + counts["tri_tests"] * TRI_BYTES +
                      ext_rays * (RAY_BYTES + HIT_BYTES))
+        sh_bytes = (counts["shadow_node_visits"] * NODE_BYTES + counts["shadow_tri_tests"] * TRI_BYTES +
+                    sh_rays * SHADOW_RAY_BYTES)
         launches_per_step = st["launches_extend"] / args.steps
-        bytes_per_launch = ext_bytes / launches_per_step
+        bytes_per_launch = (ext_bytes + sh_bytes) / launches_per_step
         avg_ms = st["ms_extend"] / st["launches_extend"]
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                    "kernel": "k_extend (BVH4 closest hit)",
+                    "kernel": "k_traverse (BVH4 walks: closest hits of a bounce and the previous bounce's shadow rays)",
                     "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": round(avg_ms, 4),
+                    "launches_per_step": launches_per_step,
                     "node_visits_per_ray": round(counts["node_visits"] / max(1, ext_rays), 2),
                     "tri_tests_per_ray": round(counts["tri_tests"] / max(1, ext_rays), 2),
+                    "node_visits_per_shadow_ray": round(counts["shadow_node_visits"] / max(1, sh_rays), 2),
+                    "tri_tests_per_shadow_ray": round(counts["shadow_tri_tests"] / max(1, sh_rays), 2),
                     "tail_kernel": tail_info(counts, st, args.steps)}
 
     result = {

@@ -85,13 +85,14 @@ typedef struct pt_stats {
   int64_t shadow_rays;       /* any-hit rays traced since the last reset */
   int64_t nonfinite_dropped; /* contributions dropped because they were not finite */
   int64_t samples;           /* path samples started */
-  double ms_extend;          /* summed kernel time of the closest-hit kernel (profiling on) */
+  double ms_extend;          /* summed kernel time of the traversal kernel: closest hits of a
+                                bounce and shadow rays of the bounce before (profiling on) */
   int64_t launches_extend;   /* its launch count (profiling on) */
   double ms_total;           /* summed time of all sampling passes (profiling on) */
   int64_t node_visits;       /* BVH node fetches of closest-hit rays (counting on) */
   int64_t tri_tests;         /* triangle tests of closest-hit rays (counting on) */
-  int64_t shadow_node_visits;/* BVH node fetches of shadow rays (counting on) */
-  int64_t shadow_tri_tests;  /* triangle tests of shadow rays (counting on) */
+  int64_t shadow_node_visits;/* BVH node fetches of shadow rays (counting on; tail kernel apart) */
+  int64_t shadow_tri_tests;  /* triangle tests of shadow rays (counting on; tail kernel apart) */
   int64_t cache_queries;     /* paths that ended in the radiance cache */
   int64_t cache_records;     /* training records produced by training paths */
   int64_t cache_adam_steps;  /* Adam steps taken since the cache was configured or given weights */
@@ -102,6 +103,9 @@ typedef struct pt_stats {
   int64_t tail_tri_tests;    /* their triangle tests (counting on; not in tri_tests) */
   double ms_tail;            /* summed time of the tail kernel (profiling on) */
   int64_t launches_tail;     /* its launch count (profiling on) */
+  int64_t tail_shadow_rays;  /* shadow rays of the tail kernel (included in shadow_rays) */
+  int64_t tail_shadow_node_visits; /* their node fetches (counting on; not in shadow_node_visits) */
+  int64_t tail_shadow_tri_tests;   /* their triangle tests (counting on; not in shadow_tri_tests) */
 } pt_stats;
 
 /* Create a scene bound to HIP device `hip_device` and stream `hip_stream`

@@ -513,7 +513,8 @@ pt_status nrc_train_records(pt_scene* s, const float* X_all, const float* T_all,
                             uint32_t frame, uint64_t seed, double* mean_loss);
 
 // Timing events of one pass (path set `set`): [0, 1] around the pass, [2, 3]
-// around the cache queries, [4, 5] around the tail kernel, then 2 per bounce.
+// around the cache queries, [4, 5] around the tail kernel, then 2 per
+// traversal launch.
 pt_status ensure_events(pt_scene* s, int set, int nev) {
   while ((int)s->events[set].size() < nev) {
     hipEvent_t e;
@@ -524,17 +525,15 @@ pt_status ensure_events(pt_scene* s, int set, int nev) {
 }
 
 // Accumulate a finished pass's timing events into the profiling totals.
-pt_status read_pass_events(pt_scene* s, int set, int wavefront_bounces, int max_depth, bool queries, bool stops_at_query,
-                           int nrc_bounce) {
+pt_status read_pass_events(pt_scene* s, int set, int wavefront_bounces, int trace_launches, int max_depth,
+                           bool queries) {
   hipEvent_t* ev = s->events[set].data();
   PT_HIP(hipEventSynchronize(ev[1]));
   float ms = 0.0f;
   PT_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
   s->ms_total += ms;
-  int last = wavefront_bounces - 1;
-  if (stops_at_query && nrc_bounce < last) last = nrc_bounce;
-  for (int b = 0; b <= last; ++b) {
-    PT_HIP(hipEventElapsedTime(&ms, ev[6 + 2 * b], ev[6 + 2 * b + 1]));
+  for (int i = 0; i < trace_launches; ++i) {
+    PT_HIP(hipEventElapsedTime(&ms, ev[6 + 2 * i], ev[6 + 2 * i + 1]));
     s->ms_extend += ms;
     s->launches_extend++;
   }
@@ -580,11 +579,11 @@ pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h,
       if (!s->ev_done[k]) PT_HIP(hipEventCreateWithFlags(&s->ev_done[k], hipEventDisableTiming));
     }
   }
-  const int nev = 6 + 2 * (max_depth + 1);
+  const int nev = 6 + 2 * (max_depth + 2);  // a pass makes at most max_depth + 2 traversal launches
   if (s->timing)
     for (int set = 0; set < nsets; ++set)
       if ((r = ensure_events(s, set, nev))) return r;
-  int wavefront[2] = {max_depth + 1, max_depth + 1};
+  int wavefront[2] = {max_depth + 1, max_depth + 1}, traces[2] = {0, 0};
   bool tail_on_2[2] = {false, false};
   int pending = -1;  // path set whose timing events are not read yet (overlap)
   for (int k = 0; k < n; ++k) {
@@ -624,6 +623,7 @@ pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h,
       A.tail_fraction = s->tail_fraction;
     }
     A.wavefront_bounces = &wavefront[set];
+    A.trace_launches = &traces[set];
     tail_on_2[set] = false;
     if (overlap) {
       A.tail_stream = s->stream2;
@@ -654,11 +654,10 @@ pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h,
     if (ev) {
       if (overlap) {  // read the previous pass while this one runs
         if (pending >= 0 &&
-            (r = read_pass_events(s, pending, wavefront[pending], max_depth, false, false, -1)))
+            (r = read_pass_events(s, pending, wavefront[pending], traces[pending], max_depth, false)))
           return r;
         pending = set;
-      } else if ((r = read_pass_events(s, set, wavefront[set], max_depth, A.nrc_bounce >= 0, P.n == P.n_render,
-                                       A.nrc_bounce))) {
+      } else if ((r = read_pass_events(s, set, wavefront[set], traces[set], max_depth, A.nrc_bounce >= 0))) {
         return r;
       }
     }
@@ -666,7 +665,8 @@ pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h,
   if (overlap) {  // the scene's stream sees every pass done
     PT_HIP(hipStreamWaitEvent(s->stream, s->ev_done[0], 0));
     PT_HIP(hipStreamWaitEvent(s->stream, s->ev_done[1], 0));
-    if (pending >= 0 && (r = read_pass_events(s, pending, wavefront[pending], max_depth, false, false, -1))) return r;
+    if (pending >= 0 && (r = read_pass_events(s, pending, wavefront[pending], traces[pending], max_depth, false)))
+      return r;
   }
   s->samples += (int64_t)n * N;
   if (train) {
@@ -1587,6 +1587,9 @@ pt_status pt_get_stats(pt_scene* s, pt_stats* o) {
     o->tail_extension_rays = (int64_t)v[kStatTailExt];
     o->tail_node_visits = (int64_t)v[kStatTailNodes];
     o->tail_tri_tests = (int64_t)v[kStatTailTris];
+    o->tail_shadow_rays = (int64_t)v[kStatTailShadow];
+    o->tail_shadow_node_visits = (int64_t)v[kStatTailShadowNodes];
+    o->tail_shadow_tri_tests = (int64_t)v[kStatTailShadowTris];
     if (v[kStatOverflow]) return fail(PT_ERR_DEVICE, "traversal stack overflow in %llu workgroups", v[kStatOverflow]);
   }
   o->samples = s->samples;

@@ -113,7 +113,10 @@ enum {
   kStatTailExt = 9,     // closest-hit rays traced by the tail kernel (also in kStatExt)
   kStatTailNodes = 10,  // their node visits and triangle tests (not in kStatNodes / kStatTris)
   kStatTailTris = 11,
-  kNumStats = 12
+  kStatTailShadow = 12,       // shadow rays traced by the tail kernel (also in kStatShadow)
+  kStatTailShadowNodes = 13,  // their node visits and triangle tests (not in kStatShadowNodes / kStatShadowTris)
+  kStatTailShadowTris = 14,
+  kNumStats = 15
 };
 constexpr int kCountShadow = 2 + kNumClasses;
 constexpr int kCountQuery = kCountShadow + 1;
@@ -131,7 +134,7 @@ struct PassArgs {
   bool count;
   bool two_level;
   uint32_t class_mask;  // material classes present (bit per class)
-  hipEvent_t* ext_events;  // 2 per bounce when timing, else nullptr
+  hipEvent_t* ext_events;  // 2 per traversal launch (at most max_depth + 2) when timing, else nullptr
   int nrc_bounce;          // vertex at which paths end in the radiance cache, -1: no cache
   const uint4* nrc_fwd;    // packed forward weight fragments (when nrc_bounce >= 0)
   hipEvent_t* nrc_events;  // 2 events around the cache-query kernel when timing, else nullptr
@@ -145,6 +148,7 @@ struct PassArgs {
   hipStream_t tail_stream;  // if set, the tail kernel runs there after tail_ready (recorded here)
   hipEvent_t tail_ready;
   bool* tail_launched;      // out: the tail kernel was launched on tail_stream
+  int* trace_launches;      // out: traversal launches of the pass (timed by ext_events)
 };
 
 hipError_t launch_pass(const SceneDev& S, const PathsDev& P, const CamDev& C, const PassArgs& A,
@@ -157,7 +161,7 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st);
 hipError_t launch_trace_rays(const SceneDev& S, const float* rays, int64_t n, uint32_t* hits, bool brute,
                              bool two_level, int grid, hipStream_t st);
 int trace_grid_blocks();
-int traversal_grid(int64_t rays);  // workgroups of k_extend / k_connect for a pass of `rays` paths
+int traversal_grid(int64_t rays);  // workgroups of the traversal kernel for a pass of `rays` paths
 int tail_grid(int grid_trace, uint32_t paths, bool beside);  // workgroups of the tail kernel
 
 // ---- radiance cache (pt_nrc.hip) ----

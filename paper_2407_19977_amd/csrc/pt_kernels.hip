@@ -2,12 +2,16 @@
 //
 // One sampling pass traces one path per slot (one sample of every pixel of
 // the tile) through the loop
-//   generate -> [reset -> extend -> shade<class>... -> connect] x (max_depth+1) -> accumulate
-// Queues live in HBM and are compacted per wavefront: a ballot of the
-// lanes that append, a popcount, one atomic per wave on the queue tail and
-// a lane-prefix (mbcnt) for the slot.  Queue lengths never leave the device:
-// every kernel is launched over a fixed grid and strides over the length it
-// reads from the counter array.
+//   generate -> [reset -> traverse -> bin -> shade<class>...] x (max_depth+1) -> traverse -> accumulate
+// where traverse finds the closest hits of a bounce's rays together with the
+// shadow rays of the previous bounce's shading.  From bounce 3 on, once few
+// paths are alive, one persistent kernel (k_tail) finishes every remaining
+// vertex instead.  Queues live in HBM and are compacted per workgroup: a
+// ballot of the lanes that append, wave counts gathered in LDS, one atomic
+// per workgroup on the queue tail and a lane prefix (mbcnt) for the slot.
+// Queue lengths never leave the device, except the one count read to decide
+// the tail hand-off: every kernel is launched over a fixed grid and strides
+// over the length it reads from the counter array.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,18 +28,6 @@ __device__ inline uint32_t lane_id() { return __lane_id(); }
 
 __device__ inline uint32_t lane_prefix(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-// Append `value` to queue q (tail at *count) for the lanes with `pred`;
-// one atomic per wave.  Returns the slot written (or 0xFFFFFFFF).
-__device__ inline uint32_t wave_append(bool pred, uint32_t* count) {
-  uint64_t m = __ballot(pred);
-  if (m == 0) return 0xFFFFFFFFu;
-  uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
-  uint32_t base = 0;
-  if (lane_id() == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
-  base = __shfl(base, (int)leader);
-  return pred ? base + lane_prefix(m) : 0xFFFFFFFFu;
 }
 
 // Sum of a value over the wave's 64 lanes (every lane gets the sum).
@@ -276,13 +268,16 @@ __global__ __launch_bounds__(kBlock) void k_generate(PathsDev P, CamDev C, uint3
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     P.counts[0] = (uint32_t)n;
+    P.counts[kCountShadow] = 0u;
     P.counts[kCountQuery] = 0u;
   }
 }
 
+// Empty the next ray queue and the class queues (the shadow queue is still
+// being traced; k_bin empties it).
 __global__ void k_reset_counts(uint32_t* counts, int next_queue) {
   int i = threadIdx.x;
-  if (i >= 2 && i <= kCountShadow) counts[i] = 0u;
+  if (i >= 2 && i < kCountShadow) counts[i] = 0u;
   if (i == next_queue) counts[i] = 0u;
 }
 
@@ -299,9 +294,15 @@ constexpr uint32_t kNoInst = 0xFFFFFFFFu;
 #define PT_REFILL 16
 #endif
 constexpr uint32_t kRefill = PT_REFILL;  // idle lanes that trigger a refill
-#ifndef PT_BLOCK_APPEND
-#define PT_BLOCK_APPEND 1
+#ifndef PT_LEAF_WAIT
+#define PT_LEAF_WAIT 1
 #endif
+#ifndef PT_LEAF_WAIT_DEN
+#define PT_LEAF_WAIT_DEN 1
+#endif
+// traversal kernels: lanes at a leaf wait until kLeafWait x their number
+// reaches kLeafWaitDen x the number of lanes at inner nodes (0: no waiting)
+constexpr uint32_t kLeafWait = PT_LEAF_WAIT, kLeafWaitDen = PT_LEAF_WAIT_DEN;
 #ifndef PT_SHADE_BLOCK
 #define PT_SHADE_BLOCK 256
 #endif
@@ -318,14 +319,11 @@ constexpr uint32_t kTailShadeWait = PT_TAIL_SHADE_WAIT;
 #endif
 // tail kernel beside the next pass: paths per workgroup (about 1.5 per lane)
 constexpr uint64_t kTailPathsPerGroup = PT_TAIL_PATHS_PER_GROUP;
-#ifndef PT_EXT_WAVES
-#define PT_EXT_WAVES 6
+#ifndef PT_TRACE_WAVES
+#define PT_TRACE_WAVES 7
 #endif
-#ifndef PT_CONN_WAVES
-#define PT_CONN_WAVES 7
-#endif
-// minimum waves per SIMD the closest-hit and shadow-ray kernels are compiled for
-constexpr int kExtWaves = PT_EXT_WAVES, kConnWaves = PT_CONN_WAVES;
+// minimum waves per SIMD the traversal kernel is compiled for
+constexpr int kTraceWaves = PT_TRACE_WAVES;
 
 struct LaneRay {
   RayPre r;   // ray in the space of the current level
@@ -336,6 +334,7 @@ struct LaneRay {
   float cur_key;   // its entry distance
   uint32_t inst;   // instance of the current mesh walk, kNoInst at the top level
   int base;        // stack size when that mesh walk started
+  bool any;        // shadow ray: stop at the first accepted triangle (kWalkPerLane walks)
   Hit best;
 };
 
@@ -355,13 +354,18 @@ __device__ inline void lane_start(LaneRay& L, float ox, float oy, float oz, floa
   hit_clear(L.best);
 }
 
+// Walk kinds of lane_step: closest hit, any hit (shadow rays), or the kind
+// the lane's own `any` flag names.
+enum { kWalkClosest = 0, kWalkAny = 1, kWalkPerLane = 2 };
+
 // One step of a lane's walk: visit one node, or test one leaf, then pop the
 // next entry that can still hold a closer hit.  In two-level scenes a
 // top-level leaf pushes its instances as entries (leaf bit, count 0,
 // instance id) that start a mesh walk on top of the stack.  Returns true when
-// the walk is over (ANY: also at the first accepted triangle).
-template <bool ANY, bool COUNT, bool TWO>
+// the walk is over (any-hit walks: also at the first accepted triangle).
+template <int KIND, bool COUNT, bool TWO>
 __device__ inline bool lane_step(const SceneDev& S, LaneRay& L, DevStack& st, uint32_t& nvis, uint32_t& ntri) {
+  const bool any = KIND == kWalkAny || (KIND == kWalkPerLane && L.any);
   const uint32_t cur = L.cur;
   if (cur != kEmpty) {
     if (!ref_is_leaf(cur)) {
@@ -398,8 +402,9 @@ __device__ inline bool lane_step(const SceneDev& S, LaneRay& L, DevStack& st, ui
       }
       for (int j = (int)cnt - 1; j >= 0; --j) st.push(kLeafBit | S.tlas_items[first + j], L.cur_key);
     } else {
-      if (leaf_test<ANY, COUNT>(S.tris, cur, L.r, L.tmin, L.tmax, TWO ? L.inst : 0u, L.skip_inst, L.skip_prim,
-                                L.best, ntri) && ANY)
+      if (leaf_test<KIND == kWalkAny, COUNT>(S.tris, cur, L.r, L.tmin, L.tmax, TWO ? L.inst : 0u, L.skip_inst,
+                                             L.skip_prim, L.best, ntri, any) &&
+          any)
         return true;
     }
     L.cur = kEmpty;
@@ -422,7 +427,7 @@ __device__ inline bool lane_step(const SceneDev& S, LaneRay& L, DevStack& st, ui
 
 // The persistent-lane loop shared by the traversal kernels.  Src supplies
 // start(i, L) (load item i into the lane) and finish(i, L, found).
-template <bool ANY, bool COUNT, bool TWO, class Src>
+template <int KIND, bool COUNT, bool TWO, class Src>
 __device__ inline void persistent_trace(const SceneDev& S, Src& src, uint32_t count, unsigned long long* s_stack,
                                         uint32_t* s_next, uint32_t& nvis, uint32_t& ntri, bool& overflow) {
   const uint32_t per = (count + gridDim.x - 1) / gridDim.x;
@@ -451,7 +456,17 @@ __device__ inline void persistent_trace(const SceneDev& S, Src& src, uint32_t co
       }
     }
     if (__ballot(busy) == 0) break;
-    if (busy && lane_step<ANY, COUNT, TWO>(S, L, st, nvis, ntri)) {
+    bool go = busy;
+    if (kLeafWait) {
+      // a lane at a leaf waits while there are many more lanes at inner
+      // nodes, so that fewer iterations run both the node and the triangle
+      // code
+      const bool at_leaf = busy && L.cur != kEmpty && ref_is_leaf(L.cur);
+      const uint32_t n_leaf = (uint32_t)__popcll((unsigned long long)__ballot(at_leaf));
+      const uint32_t n_node = (uint32_t)__popcll((unsigned long long)__ballot(busy && !at_leaf));
+      go = busy && (!at_leaf || kLeafWait * n_leaf >= kLeafWaitDen * n_node);
+    }
+    if (go && lane_step<KIND, COUNT, TWO>(S, L, st, nvis, ntri)) {
       src.finish(item, L, L.best.tri != 0xFFFFFFFFu);
       busy = false;
     }
@@ -488,28 +503,13 @@ struct ExtendSrc {
   }
 };
 
-template <bool COUNT, bool TWO>
-__global__ __launch_bounds__(kBlock, kExtWaves) void k_extend(SceneDev S, PathsDev P, int cur) {
-  __shared__ unsigned long long s_stack[kLdsStack * kBlock];
-  __shared__ uint32_t s_next;
-  const uint32_t count = P.counts[cur];
-  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&P.stats[kStatExt], (unsigned long long)count);
-  uint32_t nvis = 0, ntri = 0;
-  bool overflow = false;
-  ExtendSrc<TWO> src{S, P, cur};
-  persistent_trace<false, COUNT, TWO>(S, src, count, s_stack, &s_next, nvis, ntri, overflow);
-  if (COUNT) {
-    atomicAdd(&P.stats[kStatNodes], (unsigned long long)nvis);
-    atomicAdd(&P.stats[kStatTris], (unsigned long long)ntri);
-  }
-  if (overflow) atomicAdd(&P.stats[kStatOverflow], 1ull);
-}
-
 // Material binning of the rays just traced: a counting sort by class with
 // one atomic per class per workgroup (1024 rays).
 __global__ __launch_bounds__(kBlock) void k_bin(PathsDev P, int cur) {
   __shared__ uint32_t s_cnt[kNumClasses], s_base[kNumClasses];
   const uint32_t count = P.counts[cur];
+  // the traversal launch before this one has traced the shadow queue: empty it for the shading
+  if (blockIdx.x == 0 && threadIdx.x == 0) P.counts[kCountShadow] = 0u;
   for (uint32_t blk = blockIdx.x * (4u * kBlock); blk < count; blk += gridDim.x * (4u * kBlock)) {
     if (threadIdx.x < kNumClasses) s_cnt[threadIdx.x] = 0u;
     __syncthreads();
@@ -763,7 +763,6 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(SceneDev S, PathsDev P, i
       slot = P.q_cls[CLS][i];
       shade_one<CLS, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, nrc_bounce, o, nonfinite);
     }
-#if PT_BLOCK_APPEND
     // One atomic per queue per workgroup iteration: the queue counters are
     // single words that every workgroup of the launch appends to.
     const uint64_t m_cont = __ballot(o.cont), m_sh = __ballot(o.shadow), m_q = __ballot(o.query);
@@ -793,16 +792,6 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(SceneDev S, PathsDev P, i
     if (query && o.query) P.q_nrc[off[2] + lane_prefix(m_q)] = slot;
     if (o.shadow) {
       const uint32_t spos = off[1] + lane_prefix(m_sh);
-#else
-    uint32_t qpos = wave_append(o.cont, &P.counts[next]);
-    if (o.cont) P.q_ray[next][qpos] = slot;
-    if (query) {
-      uint32_t npos = wave_append(o.query, &P.counts[kCountQuery]);
-      if (o.query) P.q_nrc[npos] = slot;
-    }
-    uint32_t spos = wave_append(o.shadow, &P.counts[kCountShadow]);
-    if (o.shadow) {
-#endif
       P.sh_o[spos] = o.sh_o;
       P.sh_d[spos] = o.sh_d;
       P.sh_c[spos] = o.sh_c;
@@ -847,23 +836,95 @@ struct ConnectSrc {
   }
 };
 
+// One traversal launch per bounce: the closest hits of the bounce's rays
+// (queue `cur`, none if cur < 0) and the shadow rays of the previous bounce's
+// shading.  A lane's walk kind is a per-lane flag, so lanes of both kinds can
+// share a wave without running the walk code twice: the node step is the same
+// and the leaf step differs only in stopping at the first accepted triangle.
+// Each workgroup owns a share of both queues and takes its closest-hit rays
+// first; its shadow rays fill the lanes that the last closest-hit walks leave
+// idle, instead of every workgroup of the GPU draining at a kernel boundary.
 template <bool DEBUG, bool COUNT, bool TWO>
-__global__ __launch_bounds__(kBlock, kConnWaves) void k_connect(SceneDev S, PathsDev P) {
+__global__ __launch_bounds__(kBlock, kTraceWaves) void k_traverse(SceneDev S, PathsDev P, int cur) {
   __shared__ unsigned long long s_stack[kLdsStack * kBlock];
   __shared__ uint32_t s_next;
-  const uint32_t count = P.counts[kCountShadow];
-  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&P.stats[kStatShadow], (unsigned long long)count);
-  uint32_t nvis = 0, ntri = 0;
-  bool overflow = false;
+  const uint32_t ne = cur >= 0 ? P.counts[cur] : 0u, ns = P.counts[kCountShadow];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (ne) atomicAdd(&P.stats[kStatExt], (unsigned long long)ne);
+    if (ns) atomicAdd(&P.stats[kStatShadow], (unsigned long long)ns);
+  }
+  const uint32_t G = gridDim.x;
+  const uint32_t pe = (ne + G - 1) / G, ps = (ns + G - 1) / G;
+  const uint32_t e0 = min(ne, blockIdx.x * pe), e1 = min(ne, e0 + pe);
+  const uint32_t s0 = min(ns, blockIdx.x * ps), s1 = min(ns, s0 + ps);
+  const uint32_t n_e = e1 - e0, n_all = n_e + (s1 - s0);
+  if (threadIdx.x == 0) s_next = 0u;
+  __syncthreads();
+  const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
+  DevStack st{lds_stack_base(s_stack), S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
   unsigned long long nonfinite = 0;
-  ConnectSrc<DEBUG, TWO> src{S, P, nonfinite};
-  persistent_trace<true, COUNT, TWO>(S, src, count, s_stack, &s_next, nvis, ntri, overflow);
+  ExtendSrc<TWO> es{S, P, cur < 0 ? 0 : cur};
+  ConnectSrc<DEBUG, TWO> cs{S, P, nonfinite};
+  LaneRay L;
+  L.any = false;
+  bool busy = false, drained = false, shadow = false;
+  uint32_t item = 0;
+  uint32_t rv = 0, rt = 0, nvis = 0, ntri = 0, svis = 0, stri = 0;  // node visits / triangle tests
+  while (true) {
+    const uint64_t idle = __ballot(!busy);
+    const uint32_t n_idle = (uint32_t)__popcll((unsigned long long)idle);
+    if (!drained && (n_idle >= kRefill || n_idle == 64u)) {
+      uint32_t base = 0;
+      if (lane_id() == 0) base = atomicAdd(&s_next, n_idle);
+      base = __shfl(base, 0);
+      if (base + n_idle >= n_all) drained = true;
+      const uint32_t v = base + lane_prefix(idle);
+      if (!busy && v < n_all) {
+        shadow = v >= n_e;
+        item = shadow ? s0 + (v - n_e) : e0 + v;
+        st.sp = 0;
+        if (shadow) cs.start(item, L);
+        else es.start(item, L);
+        L.any = shadow;
+        busy = true;
+        rv = rt = 0;
+      }
+    }
+    if (__ballot(busy) == 0) break;
+    bool go = busy;
+    if (kLeafWait) {
+      // a lane at a leaf waits while there are many more lanes at inner
+      // nodes, so that fewer iterations run both the node and the triangle
+      // code
+      const bool at_leaf = busy && L.cur != kEmpty && ref_is_leaf(L.cur);
+      const uint32_t n_leaf = (uint32_t)__popcll((unsigned long long)__ballot(at_leaf));
+      const uint32_t n_node = (uint32_t)__popcll((unsigned long long)__ballot(busy && !at_leaf));
+      go = busy && (!at_leaf || kLeafWait * n_leaf >= kLeafWaitDen * n_node);
+    }
+    if (go && lane_step<kWalkPerLane, COUNT, TWO>(S, L, st, rv, rt)) {
+      const bool found = L.best.tri != 0xFFFFFFFFu;
+      if (shadow) cs.finish(item, L, found);
+      else es.finish(item, L, found);
+      if (COUNT) {
+        if (shadow) {
+          svis += rv;
+          stri += rt;
+        } else {
+          nvis += rv;
+          ntri += rt;
+        }
+      }
+      busy = false;
+    }
+  }
   if (COUNT) {
-    atomicAdd(&P.stats[kStatShadowNodes], (unsigned long long)nvis);
-    atomicAdd(&P.stats[kStatShadowTris], (unsigned long long)ntri);
+    atomicAdd(&P.stats[kStatNodes], (unsigned long long)nvis);
+    atomicAdd(&P.stats[kStatTris], (unsigned long long)ntri);
+    atomicAdd(&P.stats[kStatShadowNodes], (unsigned long long)svis);
+    atomicAdd(&P.stats[kStatShadowTris], (unsigned long long)stri);
   }
   if (nonfinite) atomicAdd(&P.stats[kStatNonFinite], nonfinite);
-  if (overflow) atomicAdd(&P.stats[kStatOverflow], 1ull);
+  if (st.overflow) atomicAdd(&P.stats[kStatOverflow], 1ull);
 }
 
 // -------------------------------------------------------------------- tail
@@ -933,7 +994,7 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
     }
     if (__ballot(phase != 0) == 0) break;
     if (phase == 1) {
-      if (lane_step<false, COUNT, TWO>(S, L, st, nvis, ntri)) {
+      if (lane_step<kWalkClosest, COUNT, TWO>(S, L, st, nvis, ntri)) {
         overflow |= st.overflow;
         cls = kClsMiss;
         if (L.best.tri != 0xFFFFFFFFu) {
@@ -951,7 +1012,7 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
         phase = 3;
       }
     } else if (phase == 2) {
-      if (lane_step<true, COUNT, TWO>(S, L, st, svis, stri)) {
+      if (lane_step<kWalkAny, COUNT, TWO>(S, L, st, svis, stri)) {
         overflow |= st.overflow;
         const bool occ = L.best.tri != 0xFFFFFFFFu;
         if (!occ) {
@@ -1011,12 +1072,13 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
     atomicAdd(&P.stats[kStatExt], (unsigned long long)n_ext);
     atomicAdd(&P.stats[kStatTailExt], (unsigned long long)n_ext);
     atomicAdd(&P.stats[kStatShadow], (unsigned long long)n_sh);
+    atomicAdd(&P.stats[kStatTailShadow], (unsigned long long)n_sh);
   }
   if (COUNT) {
     atomicAdd(&P.stats[kStatTailNodes], (unsigned long long)nvis);
     atomicAdd(&P.stats[kStatTailTris], (unsigned long long)ntri);
-    atomicAdd(&P.stats[kStatShadowNodes], (unsigned long long)svis);
-    atomicAdd(&P.stats[kStatShadowTris], (unsigned long long)stri);
+    atomicAdd(&P.stats[kStatTailShadowNodes], (unsigned long long)svis);
+    atomicAdd(&P.stats[kStatTailShadowTris], (unsigned long long)stri);
   }
   if (nonfinite) atomicAdd(&P.stats[kStatNonFinite], nonfinite);
   if (overflow) atomicAdd(&P.stats[kStatOverflow], 1ull);
@@ -1089,7 +1151,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays(SceneDev S, const float* 
   uint32_t nvis = 0, ntri = 0;
   bool overflow = false;
   RaysSrc<TWO> src{S, rays, hits};
-  persistent_trace<false, false, TWO>(S, src, n, s_stack, &s_next, nvis, ntri, overflow);
+  persistent_trace<kWalkClosest, false, TWO>(S, src, n, s_stack, &s_next, nvis, ntri, overflow);
 }
 
 // The same definition by testing every triangle (and every instance).
@@ -1143,7 +1205,8 @@ int traversal_grid(int64_t rays) {
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
       cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_extend<false, true>, kBlock, 0) != hipSuccess || per < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_traverse<true, true, true>, kBlock, 0) != hipSuccess ||
+        per < 1)
       per = 1;
     resident = std::max(1, cus * per);
   }
@@ -1174,6 +1237,15 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
                               hipStream_t st) {
   dim3 blk(kBlock);
   if (A.wavefront_bounces) *A.wavefront_bounces = A.max_depth + 1;
+  int n_trace = 0;
+  // closest hits of queue q (none if q < 0) and the shadow rays of the last shading
+  auto traverse = [&](int q) {
+    if (A.ext_events) hipEventRecord(A.ext_events[2 * n_trace], st);
+    hipLaunchKernelGGL((k_traverse<DEBUG, COUNT, TWO>), dim3(A.grid_trace), blk, 0, st, S, P, q);
+    if (A.ext_events) hipEventRecord(A.ext_events[2 * n_trace + 1], st);
+    n_trace++;
+  };
+  bool shadow_pending = false;  // the last shading queued shadow rays that no launch has traced yet
   for (int b = 0; b <= A.max_depth; ++b) {
     int cur = b & 1, next = cur ^ 1;
     if (A.tail_host_count && b >= A.tail_min_bounce && b > A.nrc_bounce) {
@@ -1183,6 +1255,10 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
       if (e0 != hipSuccess) return e0;
       if ((double)*A.tail_host_count <= A.tail_fraction * (double)P.n) {
         if (A.wavefront_bounces) *A.wavefront_bounces = b;
+        if (shadow_pending) {  // the previous vertex's shadow rays come before the tail's next vertex
+          traverse(-1);
+          shadow_pending = false;
+        }
         hipStream_t ts = st;
         if (A.tail_stream) {  // continue on the second stream; the caller's stream is free for the next pass
           hipError_t e1 = hipEventRecord(A.tail_ready, st);
@@ -1192,22 +1268,23 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
           if (A.tail_launched) *A.tail_launched = true;
         }
         if (A.tail_events) hipEventRecord(A.tail_events[0], ts);
-        hipLaunchKernelGGL((k_tail<DEBUG, COUNT, TWO>), dim3(tail_grid(A.grid_trace, *A.tail_host_count, A.tail_stream != nullptr)), blk, 0, ts,
-                           S, P, cur, b,
-                           A.max_depth, A.sample, A.k0, A.k1, (uint32_t)C.W);
+        hipLaunchKernelGGL((k_tail<DEBUG, COUNT, TWO>),
+                           dim3(tail_grid(A.grid_trace, *A.tail_host_count, A.tail_stream != nullptr)), blk, 0, ts,
+                           S, P, cur, b, A.max_depth, A.sample, A.k0, A.k1, (uint32_t)C.W);
         if (A.tail_events) hipEventRecord(A.tail_events[1], ts);
         break;
       }
     }
     hipLaunchKernelGGL(k_reset_counts, dim3(1), dim3(64), 0, st, P.counts, next);
-    if (A.ext_events) hipEventRecord(A.ext_events[2 * b], st);
-    hipLaunchKernelGGL((k_extend<COUNT, TWO>), dim3(A.grid_trace), blk, 0, st, S, P, cur);
-    if (A.ext_events) hipEventRecord(A.ext_events[2 * b + 1], st);
-    hipLaunchKernelGGL(k_bin, dim3(A.grid_bin), blk, 0, st, P, cur);
+    traverse(cur);  // this bounce's closest hits and the previous bounce's shadow rays
+    shadow_pending = false;
+    hipLaunchKernelGGL(k_bin, dim3(A.grid_bin), blk, 0, st, P, cur);  // also empties the shadow queue
     hipError_t e = shade_all<DEBUG, TWO>(S, P, A, b, next, (uint32_t)C.W, st);
     if (e != hipSuccess) return e;
-    if (b < A.max_depth) hipLaunchKernelGGL((k_connect<DEBUG, COUNT, TWO>), dim3(A.grid_trace), blk, 0, st, S, P);
+    shadow_pending = b < A.max_depth;
     if (b == A.nrc_bounce) {  // every path still alive ended in the cache at this vertex
+      // (a path that ends in the cache casts no shadow ray at that vertex, so
+      // the pending shadow rays touch other paths)
       if (A.nrc_events) hipEventRecord(A.nrc_events[0], st);
       hipError_t e2 = nrc_launch_query(P, A.nrc_fwd, std::min(A.grid, 1024), st);
       if (A.nrc_events) hipEventRecord(A.nrc_events[1], st);
@@ -1215,6 +1292,8 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
       if (P.n == P.n_render) break;  // no training paths: nothing continues
     }
   }
+  if (shadow_pending) traverse(-1);
+  if (A.trace_launches) *A.trace_launches = n_trace;
   return hipGetLastError();
 }
 

@@ -144,10 +144,13 @@ __host__ __device__ inline uint32_t node_slabs(const BVHNode& n, const RayPre& r
   return mask;
 }
 
+// Test the triangles of a leaf; true if one was accepted.  ANY (or any_rt,
+// the same choice made per lane at run time) stops at the first accepted
+// triangle, as a shadow ray may.
 template <bool ANY, bool COUNT>
 __host__ __device__ inline bool leaf_test(const TriRec* __restrict__ tris, uint32_t ref, const RayPre& r,
                                           float tmin, float tmax, uint32_t inst, uint32_t skip_inst,
-                                          uint32_t skip_prim, Hit& best, uint32_t& ntri) {
+                                          uint32_t skip_prim, Hit& best, uint32_t& ntri, bool any_rt = false) {
   uint32_t first = leaf_first(ref), cnt = leaf_count(ref);
   bool found = false;
   for (uint32_t j = 0; j < cnt; ++j) {
@@ -169,7 +172,7 @@ __host__ __device__ inline bool leaf_test(const TriRec* __restrict__ tris, uint3
     best.tri = first + j;
     best.mat = f2u(tr.b.w);
     found = true;
-    if (ANY) return true;
+    if (ANY || any_rt) return true;
   }
   return found;
 }

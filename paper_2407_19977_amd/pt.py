@@ -49,7 +49,9 @@ class pt_stats(C.Structure):
                 ("cache_queries", C.c_int64), ("cache_records", C.c_int64), ("cache_adam_steps", C.c_int64),
                 ("ms_cache_query", C.c_double), ("ms_cache_train", C.c_double),
                 ("tail_extension_rays", C.c_int64), ("tail_node_visits", C.c_int64), ("tail_tri_tests", C.c_int64),
-                ("ms_tail", C.c_double), ("launches_tail", C.c_int64)]
+                ("ms_tail", C.c_double), ("launches_tail", C.c_int64),
+                ("tail_shadow_rays", C.c_int64), ("tail_shadow_node_visits", C.c_int64),
+                ("tail_shadow_tri_tests", C.c_int64)]
 
 
 class pt_bvh_info(C.Structure):

@@ -261,6 +261,10 @@ def main():
                     help="instanced-4k: plain vs cache on the instanced scene at 3840x2160 (minutes; not the bench line)")
     ap.add_argument("--spp-4k", type=int, default=1024)
     ap.add_argument("--ref-spp-4k", type=int, default=2048)
+    ap.add_argument("--tail-min-bounce", type=int, default=None,
+                    help="first bounce at which the tail kernel may take over (library default if omitted)")
+    ap.add_argument("--tail-fraction", type=float, default=None,
+                    help="largest fraction of alive paths handed to the tail kernel (library default if omitted)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -284,6 +288,9 @@ def main():
     W, H = cam.width, cam.height
     torch.cuda.set_device(0)
     s = pt.scene_from(sc, device=0)
+    if args.tail_min_bounce is not None or args.tail_fraction is not None:
+        s.set_tail(3 if args.tail_min_bounce is None else args.tail_min_bounce,
+                   0.125 if args.tail_fraction is None else args.tail_fraction)
     out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda:0")
 
     if args.calibrate_copy:

@@ -81,20 +81,23 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
 def _frames(s, cam, depth, seed, frames, ref, out, torch):
-    """Frames of 1 spp into the FP64 sums: cumulative ms and RMSE against ref at the checkpoints."""
+    """Samples of 1 spp each into the FP64 sums, one call per span between
+    checkpoints (so the library overlaps consecutive passes or frames as a
+    user's call would): cumulative ms and RMSE against ref at the checkpoints."""
     s.reset_accumulation()
     t = 0.0
     rows = []
-    for k in range(frames):
+    done = 0
+    for cp in [c for c in CHECKPOINTS if c <= frames]:
         t0 = time.perf_counter()
-        s.accumulate(cam, k, 1, depth, seed)  # returns after the stream has drained
+        s.accumulate(cam, done, cp - done, depth, seed)  # returns after the stream has drained
         t += time.perf_counter() - t0
-        if k + 1 in CHECKPOINTS:
-            s.resolve(out)
-            d = out.double() - ref
-            e = torch.sqrt(torch.mean(d * d)).item()
-            rel = torch.mean(d * d / (ref * ref + 0.01)).item()
-            rows.append((k + 1, t * 1e3, e, rel))
+        done = cp
+        s.resolve(out)
+        d = out.double() - ref
+        e = torch.sqrt(torch.mean(d * d)).item()
+        rel = torch.mean(d * d / (ref * ref + 0.01)).item()
+        rows.append((cp, t * 1e3, e, rel))
     return rows
 
 
@@ -115,8 +118,9 @@ def _time_to(rows, target, col=2):
 
 
 def cache_experiment(pt, torch, sc, frames=256, ref_spp=4096):
-    """Plain vs radiance-cache rendering, frames of 1 spp, RMSE against a
-    ref_spp plain render with FP64 sums and an independent seed."""
+    """Plain vs radiance-cache rendering, frames of 1 spp (consecutive frames
+    of one call overlap in both modes), RMSE against a ref_spp plain render
+    with FP64 sums and an independent seed."""
     cam = sc.camera
     W, H, depth, seed = cam.width, cam.height, sc.max_depth, sc.seed
     s = pt.scene_from(sc, device=0)
@@ -133,10 +137,11 @@ def cache_experiment(pt, torch, sc, frames=256, ref_spp=4096):
     s.set_profiling(True, False)
     s.reset_stats()
     plain = _frames(s, cam, depth, seed, frames, ref, out, torch)
-    # one untimed cache frame allocates the cache's buffers; configuring again resets weights and Adam state
+    # untimed cache frames allocate the cache's buffers (the first frame runs alone, later ones
+    # overlap on two path sets); configuring again resets weights and Adam state
     s.set_radiance_cache(pt.cache_config())
     s.reset_accumulation()
-    s.accumulate(cam, 0, 1, depth, seed)
+    s.accumulate(cam, 0, 3, depth, seed)
     s.set_radiance_cache(pt.cache_config())
     s.reset_stats()
     nrc = _frames(s, cam, depth, seed, frames, ref, out, torch)

@@ -144,15 +144,17 @@ struct pt_scene {
   bool nrc_on = false;     // configured
   bool nrc_ready = false;  // weights set or trained: sampling passes end paths in the cache
   pt_radiance_cache_config nrc_cfg;
-  int64_t nrc_step = 0;    // Adam steps taken
+  DevBuf nrc_t;            // Adam steps applied (one device word: steps with no records are skipped there)
   DevBuf nrc_w, nrc_m, nrc_v, nrc_fwd, nrc_bwd;  // FP32 master weights, Adam moments, bf16 fragments
-  DevBuf nrc_rec, nrc_off, nrc_bsum, nrc_n, nrc_X, nrc_T;  // training records, compaction
+  DevBuf nrc_rec[2];       // training records, per path set (frames overlap on two sets)
+  DevBuf nrc_off, nrc_bsum, nrc_n, nrc_X, nrc_T;  // compaction
   int64_t nrc_rec_cap = 0;
   DevBuf nrc_Xb, nrc_Tb, nrc_a, nrc_g, nrc_loss, nrc_dw;  // one training step's workspace
   int64_t nrc_ws_npad = 0;
   int nrc_ws_split = 0;
-  int64_t nrc_records = 0;
   double ms_cache_query = 0.0, ms_cache_train = 0.0;
+  hipEvent_t ev_train = nullptr;  // the last enqueued training's weights are in place
+  hipEvent_t ev_train_t[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // timing around a frame's training
   // tail hand-off
   int tail_min_bounce = 3;
   double tail_fraction = 0.125;
@@ -474,15 +476,17 @@ pt_status ready_to_render(pt_scene* s) {
 // (0, 2^31 + frame, 0x4F4646, 0); sample index 2^31 + frame.  Each records
 // (inputs, radiance so far, throughput) at its vertices below max_depth.
 pt_status setup_training(pt_scene* s, const CamDev& C, PathsDev& P, int64_t n_render, uint32_t frame, int max_depth,
-                         uint64_t seed) {
+                         uint64_t seed, int set = 0) {
   const int64_t n = s->nrc_cfg.train_paths;
   const int depth = std::max(1, max_depth);
   if (n * depth > s->nrc_rec_cap) {
-    PT_HIP(s->nrc_rec.alloc((size_t)n * depth * kNrcRecFloats * sizeof(float)));
+    PT_HIP(s->nrc_rec[0].alloc((size_t)n * depth * kNrcRecFloats * sizeof(float)));
+    if (s->nrc_rec[1].p) PT_HIP(s->nrc_rec[1].alloc((size_t)n * depth * kNrcRecFloats * sizeof(float)));
     PT_HIP(s->nrc_X.alloc((size_t)n * depth * 12 * sizeof(float)));
     PT_HIP(s->nrc_T.alloc((size_t)n * depth * 3 * sizeof(float)));
     s->nrc_rec_cap = n * depth;
   }
+  if (set == 1 && !s->nrc_rec[1].p) PT_HIP(s->nrc_rec[1].alloc(s->nrc_rec[0].bytes));
   PT_HIP(s->nrc_off.alloc((size_t)n * sizeof(uint32_t)));
   PT_HIP(s->nrc_bsum.alloc((size_t)((n + 255) / 256) * sizeof(uint32_t)));
   if (!s->nrc_n.p) PT_HIP(s->nrc_n.alloc(sizeof(uint32_t)));
@@ -494,23 +498,29 @@ pt_status setup_training(pt_scene* s, const CamDev& C, PathsDev& P, int64_t n_re
   U4 u = philox(0u, 0x80000000u + frame, 0x4F4646u, 0u, (uint32_t)seed, (uint32_t)(seed >> 32));
   P.pix_off = (uint32_t)(((uint64_t)(u.x >> 8) * WH) >> 24);
   P.train_sample = 0x80000000u + frame;
-  P.rec = s->nrc_rec.as<float>();
+  P.rec = s->nrc_rec[set].as<float>();
   P.rec_depth = max_depth;
   return PT_OK;
 }
 
-// Targets of the training paths of the last pass, compacted path by path; *n_records on the host.
-pt_status finish_training(pt_scene* s, const PathsDev& P, uint32_t* n_records) {
+// Targets of the training paths of the last pass, compacted path by path, on stream st; the count
+// stays on the device (and is added to the record statistics) unless n_records asks for it on the host.
+pt_status finish_training(pt_scene* s, const PathsDev& P, uint32_t* n_records, hipStream_t st,
+                          bool count_stats = false) {
   const int n = P.n - P.n_render;
   PT_HIP(nrc_launch_targets(P, n, s->nrc_off.as<uint32_t>(), s->nrc_bsum.as<uint32_t>(), s->nrc_X.as<float>(),
-                            s->nrc_T.as<float>(), s->nrc_n.as<uint32_t>(), s->stream));
-  PT_HIP(hipMemcpyAsync(n_records, s->nrc_n.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
-  PT_HIP(hipStreamSynchronize(s->stream));
+                            s->nrc_T.as<float>(), s->nrc_n.as<uint32_t>(),
+                            count_stats ? s->stats.as<unsigned long long>() : nullptr, st));
+  if (n_records) {
+    PT_HIP(hipMemcpyAsync(n_records, s->nrc_n.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    PT_HIP(hipStreamSynchronize(st));
+  }
   return PT_OK;
 }
 
 pt_status nrc_train_records(pt_scene* s, const float* X_all, const float* T_all, const uint32_t* n_dev,
-                            uint32_t frame, uint64_t seed, double* mean_loss);
+                            uint32_t frame, uint64_t seed, double* mean_loss, hipStream_t st);
+pt_status nrc_ensure_ws(pt_scene* s, int64_t N);
 
 // Timing events of one pass (path set `set`): [0, 1] around the pass, [2, 3]
 // around the cache queries, [4, 5] around the tail kernel, then 2 per
@@ -674,20 +684,148 @@ pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h,
     PathsDev P = paths_dev(s, N, x0, y0, w, 0);
     P.n = (int32_t)slots;
     P.n_render = (int32_t)N;
-    P.rec = s->nrc_rec.as<float>();
+    P.rec = s->nrc_rec[0].as<float>();
     P.rec_depth = max_depth;
-    uint32_t nrec = 0;
-    if ((r = finish_training(s, P, &nrec))) return r;
-    s->nrc_records += nrec;
-    if (nrec > 0 &&  // else nothing to learn from (e.g. every training path missed)
-        (r = nrc_train_records(s, s->nrc_X.as<float>(), s->nrc_T.as<float>(), s->nrc_n.as<uint32_t>(),
-                               (uint32_t)first, seed, nullptr)))
+    if ((r = finish_training(s, P, nullptr, s->stream, true))) return r;
+    if ((r = nrc_train_records(s, s->nrc_X.as<float>(), s->nrc_T.as<float>(), s->nrc_n.as<uint32_t>(),
+                               (uint32_t)first, seed, nullptr, s->stream)))
       return r;
     if (s->timing) {
       PT_HIP(hipStreamSynchronize(s->stream));
       s->ms_cache_train += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
   }
+  return PT_OK;
+}
+
+// Frames of the radiance cache once it has weights, pipelined over the two
+// path sets.  A frame's sampling paths all end by the query vertex, so its
+// accumulation follows its cache queries on the scene's stream; its training
+// paths' remaining vertices (tail kernel), their targets and the frame's
+// Adam steps run on the second stream while the next frame's dense bounces
+// run on the scene's stream.  The next frame's cache queries wait for those
+// Adam steps, so every frame sees the weights a frame-by-frame loop would.
+pt_status run_cache_frames(pt_scene* s, const CamDev& C, int first, int n, int max_depth, uint64_t seed) {
+  const int64_t N = (int64_t)C.W * C.H;
+  const int64_t slots = N + s->nrc_cfg.train_paths;
+  int grid = grid_for(slots), grid_trace = traversal_grid(slots);
+  pt_status r = PT_OK;
+  PathsDev Ps[2];
+  for (int set = 0; set < 2; ++set) {  // every allocation before the first launch
+    if ((r = ensure_paths(s, slots, set))) return r;
+    if ((r = ensure_counters(s, set))) return r;
+    if ((r = ensure_spill(s, grid_trace, set))) return r;
+    PathBufs& B = s->pb[set];
+    if (N > B.nrc_q_cap) {
+      PT_HIP(B.nrc_q.alloc((size_t)N * kNrcQueryFloats * sizeof(float)));
+      PT_HIP(B.q_nrc.alloc((size_t)N * sizeof(uint32_t)));
+      B.nrc_q_cap = N;
+    }
+    Ps[set] = paths_dev(s, N, 0, 0, C.W, set);
+    if ((r = setup_training(s, C, Ps[set], N, (uint32_t)first, max_depth, seed, set))) return r;
+  }
+  if ((r = nrc_ensure_ws(s, s->nrc_cfg.batch_size))) return r;
+  if (!s->tail_counts) PT_HIP(hipHostMalloc((void**)&s->tail_counts, 2 * sizeof(uint32_t), hipHostMallocDefault));
+  if (!s->stream2) PT_HIP(hipStreamCreateWithFlags(&s->stream2, hipStreamNonBlocking));
+  for (int k = 0; k < 2; ++k) {
+    if (!s->ev_bulk[k]) PT_HIP(hipEventCreateWithFlags(&s->ev_bulk[k], hipEventDisableTiming));
+    if (!s->ev_done[k]) PT_HIP(hipEventCreateWithFlags(&s->ev_done[k], hipEventDisableTiming));
+    for (int j = 0; j < 2; ++j)
+      if (s->timing && !s->ev_train_t[k][j]) PT_HIP(hipEventCreate(&s->ev_train_t[k][j]));
+  }
+  if (!s->ev_train) PT_HIP(hipEventCreateWithFlags(&s->ev_train, hipEventDisableTiming));
+  const int nev = 6 + 2 * (max_depth + 2);
+  if (s->timing)
+    for (int set = 0; set < 2; ++set)
+      if ((r = ensure_events(s, set, nev))) return r;
+  const bool tail = s->tail_fraction > 0.0 && s->tail_min_bounce <= max_depth;
+  int wavefront[2] = {max_depth + 1, max_depth + 1}, traces[2] = {0, 0};
+  bool tail_on_2[2] = {false, false};
+  int pending = -1;  // path set whose timing events are not read yet
+  auto read_training_time = [&](int set) -> pt_status {
+    float ms = 0.0f;
+    PT_HIP(hipEventSynchronize(s->ev_train_t[set][1]));
+    PT_HIP(hipEventElapsedTime(&ms, s->ev_train_t[set][0], s->ev_train_t[set][1]));
+    s->ms_cache_train += ms;
+    return PT_OK;
+  };
+  for (int k = 0; k < n; ++k) {
+    const int set = k & 1;
+    const uint32_t frame = (uint32_t)(first + k);
+    SceneDev S = scene_dev(s, grid_trace, set);
+    PathsDev P = Ps[set];
+    if ((r = setup_training(s, C, P, N, frame, max_depth, seed, set))) return r;  // no allocation now
+    P.nrc_q = s->pb[set].nrc_q.as<float>();
+    P.q_nrc = s->pb[set].q_nrc.as<uint32_t>();
+    PassArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.sample = frame;
+    A.k0 = (uint32_t)seed;
+    A.k1 = (uint32_t)(seed >> 32);
+    A.max_depth = max_depth;
+    A.grid = grid;
+    A.grid_trace = grid_trace;
+    A.grid_bin = bin_grid(slots);
+    A.count = s->counting;
+    A.two_level = s->two_level;
+    A.class_mask = s->class_mask | (1u << kClsMiss);
+    A.nrc_bounce = s->nrc_cfg.query_bounce;
+    A.nrc_fwd = s->nrc_fwd.as<uint4>();
+    A.query_wait = k > 0 ? s->ev_train : nullptr;  // the previous frame's Adam steps
+    if (tail) {
+      A.tail_host_count = s->tail_counts + set;
+      A.tail_min_bounce = s->tail_min_bounce;
+      A.tail_fraction = s->tail_fraction;
+      A.tail_bound = (uint32_t)s->nrc_cfg.train_paths;
+    }
+    A.wavefront_bounces = &wavefront[set];
+    A.trace_launches = &traces[set];
+    tail_on_2[set] = false;
+    A.tail_stream = s->stream2;
+    A.tail_ready = s->ev_bulk[set];
+    A.tail_launched = &tail_on_2[set];
+    hipEvent_t* ev = s->timing ? s->events[set].data() : nullptr;
+    if (ev) {
+      A.ext_events = ev + 6;
+      A.nrc_events = ev + 2;
+      A.tail_events = ev + 4;
+    }
+    // the set's paths and records are free once the frame that used them two frames ago has trained
+    if (k >= 2) PT_HIP(hipStreamWaitEvent(s->stream, s->ev_done[set], 0));
+    if (ev) PT_HIP(hipEventRecord(ev[0], s->stream));
+    PT_HIP(launch_pass(S, P, C, A, s->stream));
+    if (!tail_on_2[set]) {
+      // no hand-off (the tail is off, or max_depth ends the paths first): everything ran here
+      PT_HIP(hipEventRecord(s->ev_bulk[set], s->stream));
+      PT_HIP(hipStreamWaitEvent(s->stream2, s->ev_bulk[set], 0));
+    }
+    // the sampling paths ended by the query vertex: their radiance is final
+    PT_HIP(launch_accumulate(P, s->sum.as<double>(), C.W, nullptr, nullptr, 1, 0, s->stream));
+    if (ev) PT_HIP(hipEventRecord(ev[1], s->stream));
+    if (s->timing) PT_HIP(hipEventRecord(s->ev_train_t[set][0], s->stream2));
+    if ((r = finish_training(s, P, nullptr, s->stream2, true))) return r;
+    if ((r = nrc_train_records(s, s->nrc_X.as<float>(), s->nrc_T.as<float>(), s->nrc_n.as<uint32_t>(), frame, seed,
+                               nullptr, s->stream2)))
+      return r;
+    if (s->timing) PT_HIP(hipEventRecord(s->ev_train_t[set][1], s->stream2));
+    PT_HIP(hipEventRecord(s->ev_train, s->stream2));
+    PT_HIP(hipEventRecord(s->ev_done[set], s->stream2));
+    if (s->timing) {  // read the previous frame while this one runs
+      if (pending >= 0) {  // (the training's end event follows the tail kernel's on the second stream)
+        if ((r = read_training_time(pending))) return r;
+        if ((r = read_pass_events(s, pending, wavefront[pending], traces[pending], max_depth, true))) return r;
+      }
+      pending = set;
+    }
+  }
+  // the scene's stream sees every frame's training done
+  PT_HIP(hipStreamWaitEvent(s->stream, s->ev_done[0], 0));
+  PT_HIP(hipStreamWaitEvent(s->stream, s->ev_done[1], 0));
+  if (pending >= 0) {
+    if ((r = read_training_time(pending))) return r;
+    if ((r = read_pass_events(s, pending, wavefront[pending], traces[pending], max_depth, true))) return r;
+  }
+  s->samples += (int64_t)n * N;
   return PT_OK;
 }
 
@@ -739,7 +877,7 @@ pt_status nrc_ensure_ws(pt_scene* s, int64_t N) {
 // One step on N samples X [N][12], T [N][3] (device): gradient into the
 // partial buffers, then Adam (apply) or just the summed gradient (grad_out).
 pt_status nrc_step(pt_scene* s, const float* X, const float* T, int64_t N, float* grad_out, bool apply,
-                   int* grid_used) {
+                   int* grid_used, hipStream_t st, const uint32_t* n_records = nullptr) {
   pt_status r = nrc_ensure_ws(s, N);
   if (r) return r;
   int split;
@@ -750,20 +888,21 @@ pt_status nrc_step(pt_scene* s, const float* X, const float* T, int64_t N, float
   if (grid_used) *grid_used = grid_fb;
   PT_HIP(nrc_launch_train(X, T, (int)N, (int)npad, split, s->nrc_fwd.as<uint4>(), s->nrc_bwd.as<uint4>(),
                           s->nrc_a.as<uint16_t>(), s->nrc_g.as<uint16_t>(), s->nrc_loss.as<float>(), grid_fb,
-                          s->nrc_dw.as<float>(), s->stream));
+                          s->nrc_dw.as<float>(), st));
   const pt_radiance_cache_config& c = s->nrc_cfg;
-  if (apply) ++s->nrc_step;
   PT_HIP(nrc_launch_adam(s->nrc_w.as<float>(), s->nrc_m.as<float>(), s->nrc_v.as<float>(), s->nrc_dw.as<float>(),
-                         split, grad_out, c.learning_rate, c.beta1, c.beta2, c.epsilon,
-                         (int)std::max<int64_t>(1, s->nrc_step), apply ? 1 : 0, s->stream));
-  if (apply) PT_HIP(nrc_launch_pack(s->nrc_w.as<float>(), s->nrc_fwd.as<uint4>(), s->nrc_bwd.as<uint4>(), s->stream));
+                         split, grad_out, c.learning_rate, c.beta1, c.beta2, c.epsilon, s->nrc_t.as<uint32_t>(),
+                         n_records, apply ? 1 : 0, st));
+  if (apply)
+    PT_HIP(nrc_launch_pack(s->nrc_w.as<float>(), s->nrc_fwd.as<uint4>(), s->nrc_bwd.as<uint4>(),
+                           s->nrc_t.as<uint32_t>(), n_records, st));
   return PT_OK;
 }
 
-pt_status nrc_read_loss(pt_scene* s, int grid, int64_t N, double* loss) {
+pt_status nrc_read_loss(pt_scene* s, int grid, int64_t N, double* loss, hipStream_t st) {
   std::vector<float> part((size_t)grid);
-  PT_HIP(hipMemcpyAsync(part.data(), s->nrc_loss.p, (size_t)grid * sizeof(float), hipMemcpyDeviceToHost, s->stream));
-  PT_HIP(hipStreamSynchronize(s->stream));
+  PT_HIP(hipMemcpyAsync(part.data(), s->nrc_loss.p, (size_t)grid * sizeof(float), hipMemcpyDeviceToHost, st));
+  PT_HIP(hipStreamSynchronize(st));
   double sum = 0.0;
   for (float v : part) sum += v;
   *loss = sum / (3.0 * (double)N);
@@ -795,12 +934,15 @@ pt_status nrc_trace_training(pt_scene* s, const CamDev& C, uint32_t frame, int m
   A.class_mask = s->class_mask | (1u << kClsMiss);
   A.nrc_bounce = -1;
   PT_HIP(launch_pass(S, P, C, A, s->stream));
-  return finish_training(s, P, n_records);
+  return finish_training(s, P, n_records, s->stream);
 }
 
 // The frame's Adam steps on batches drawn with replacement from n records X_all, T_all.
+// The frame's Adam steps on stream st, each on a batch drawn from the n_dev
+// records (a device count: with none, the steps change nothing and are not
+// counted).  mean_loss (host) waits for each step's loss.
 pt_status nrc_train_records(pt_scene* s, const float* X_all, const float* T_all, const uint32_t* n_dev,
-                            uint32_t frame, uint64_t seed, double* mean_loss) {
+                            uint32_t frame, uint64_t seed, double* mean_loss, hipStream_t st) {
   const pt_radiance_cache_config& c = s->nrc_cfg;
   const int B = c.batch_size;
   pt_status r = nrc_ensure_ws(s, B);
@@ -808,12 +950,12 @@ pt_status nrc_train_records(pt_scene* s, const float* X_all, const float* T_all,
   double lsum = 0.0;
   for (int step = 0; step < c.steps_per_frame; ++step) {
     PT_HIP(nrc_launch_gather(X_all, T_all, n_dev, B, frame, step, (uint32_t)seed, (uint32_t)(seed >> 32),
-                             s->nrc_Xb.as<float>(), s->nrc_Tb.as<float>(), s->stream));
+                             s->nrc_Xb.as<float>(), s->nrc_Tb.as<float>(), st));
     int grid = 0;
-    if ((r = nrc_step(s, s->nrc_Xb.as<float>(), s->nrc_Tb.as<float>(), B, nullptr, true, &grid))) return r;
+    if ((r = nrc_step(s, s->nrc_Xb.as<float>(), s->nrc_Tb.as<float>(), B, nullptr, true, &grid, st, n_dev))) return r;
     if (mean_loss) {
       double l = 0.0;
-      if ((r = nrc_read_loss(s, grid, B, &l))) return r;
+      if ((r = nrc_read_loss(s, grid, B, &l, st))) return r;
       lsum += l;
     }
   }
@@ -828,11 +970,14 @@ pt_status nrc_train_records(pt_scene* s, const float* X_all, const float* T_all,
 pt_status render_samples(pt_scene* s, const CamDev& C, int first, int n, int max_depth, uint64_t seed) {
   if (!s->nrc_on)
     return run_passes(s, C, 0, 0, C.W, C.H, first, n, max_depth, seed, s->sum.as<double>(), nullptr, nullptr, n);
-  for (int k = 0; k < n; ++k) {
+  int k = 0;
+  // frames before the cache has weights (and with training off) run one by one
+  for (; k < n && !(s->nrc_ready && s->nrc_cfg.steps_per_frame > 0 && max_depth > s->nrc_cfg.query_bounce); ++k) {
     pt_status r = run_passes(s, C, 0, 0, C.W, C.H, first + k, 1, max_depth, seed, s->sum.as<double>(), nullptr,
                              nullptr, 1, true);
     if (r) return r;
   }
+  if (k < n) return run_cache_frames(s, C, first + k, n - k, max_depth, seed);
   return PT_OK;
 }
 
@@ -1144,7 +1289,10 @@ void pt_scene_destroy(pt_scene* s) {
   for (int k = 0; k < 2; ++k) {
     if (s->ev_bulk[k]) (void)hipEventDestroy(s->ev_bulk[k]);
     if (s->ev_done[k]) (void)hipEventDestroy(s->ev_done[k]);
+    for (int j = 0; j < 2; ++j)
+      if (s->ev_train_t[k][j]) (void)hipEventDestroy(s->ev_train_t[k][j]);
   }
+  if (s->ev_train) (void)hipEventDestroy(s->ev_train);
   if (s->stream2) (void)hipStreamDestroy(s->stream2);
   if (s->tail_counts) (void)hipHostFree(s->tail_counts);
   delete s;
@@ -1444,9 +1592,11 @@ pt_status pt_set_radiance_cache(pt_scene* s, const pt_radiance_cache_config* cfg
   PT_HIP(upload(s->nrc_v, zero.data(), bytes, s->stream));
   if (!s->nrc_fwd.p) PT_HIP(s->nrc_fwd.alloc(kNrcFwdFrags * 64 * sizeof(uint4)));
   if (!s->nrc_bwd.p) PT_HIP(s->nrc_bwd.alloc(kNrcBwdFrags * 64 * sizeof(uint4)));
-  PT_HIP(nrc_launch_pack(s->nrc_w.as<float>(), s->nrc_fwd.as<uint4>(), s->nrc_bwd.as<uint4>(), s->stream));
+  if (!s->nrc_t.p) PT_HIP(s->nrc_t.alloc(sizeof(uint32_t)));
+  PT_HIP(hipMemsetAsync(s->nrc_t.p, 0, sizeof(uint32_t), s->stream));
+  PT_HIP(nrc_launch_pack(s->nrc_w.as<float>(), s->nrc_fwd.as<uint4>(), s->nrc_bwd.as<uint4>(), nullptr, nullptr,
+                         s->stream));
   s->nrc_cfg = c;
-  s->nrc_step = 0;
   s->nrc_on = true;
   s->nrc_ready = false;
   return sync(s);
@@ -1462,8 +1612,9 @@ pt_status pt_nrc_set_weights(pt_scene* s, const float* weights, int64_t n) {
   std::vector<float> zero(kNrcParams, 0.0f);
   PT_HIP(hipMemcpyAsync(s->nrc_m.p, zero.data(), kNrcParams * sizeof(float), hipMemcpyHostToDevice, s->stream));
   PT_HIP(hipMemcpyAsync(s->nrc_v.p, zero.data(), kNrcParams * sizeof(float), hipMemcpyHostToDevice, s->stream));
-  PT_HIP(nrc_launch_pack(s->nrc_w.as<float>(), s->nrc_fwd.as<uint4>(), s->nrc_bwd.as<uint4>(), s->stream));
-  s->nrc_step = 0;
+  PT_HIP(nrc_launch_pack(s->nrc_w.as<float>(), s->nrc_fwd.as<uint4>(), s->nrc_bwd.as<uint4>(), nullptr, nullptr,
+                         s->stream));
+  PT_HIP(hipMemsetAsync(s->nrc_t.p, 0, sizeof(uint32_t), s->stream));
   s->nrc_ready = true;
   return sync(s);
 }
@@ -1477,7 +1628,12 @@ pt_status pt_nrc_get_weights(pt_scene* s, float* weights, float* adam_m, float* 
   if (weights) PT_HIP(hipMemcpyAsync(weights, s->nrc_w.p, bytes, hipMemcpyDeviceToDevice, s->stream));
   if (adam_m) PT_HIP(hipMemcpyAsync(adam_m, s->nrc_m.p, bytes, hipMemcpyDeviceToDevice, s->stream));
   if (adam_v) PT_HIP(hipMemcpyAsync(adam_v, s->nrc_v.p, bytes, hipMemcpyDeviceToDevice, s->stream));
-  if (step) *step = s->nrc_step;
+  if (step) {
+    uint32_t t = 0;
+    PT_HIP(hipMemcpyAsync(&t, s->nrc_t.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
+    PT_HIP(hipStreamSynchronize(s->stream));
+    *step = (int64_t)t;
+  }
   return sync(s);
 }
 
@@ -1502,8 +1658,8 @@ pt_status pt_nrc_gradient(pt_scene* s, const float* inputs, const float* targets
   if (!inputs || !targets || !grad) return fail(PT_ERR_INVALID_ARG, "inputs, targets and grad must be non-NULL");
   if ((r = set_device(s))) return r;
   int grid = 0;
-  if ((r = nrc_step(s, inputs, targets, n, grad, false, &grid))) return r;
-  if (loss) return nrc_read_loss(s, grid, n, loss);
+  if ((r = nrc_step(s, inputs, targets, n, grad, false, &grid, s->stream))) return r;
+  if (loss) return nrc_read_loss(s, grid, n, loss, s->stream);
   return sync(s);
 }
 
@@ -1520,7 +1676,9 @@ pt_status pt_nrc_train(pt_scene* s, const float* inputs, const float* targets, i
   uint32_t nn = (uint32_t)n;
   PT_HIP(hipMemcpyAsync(s->nrc_n.p, &nn, sizeof(uint32_t), hipMemcpyHostToDevice, s->stream));
   PT_HIP(hipStreamSynchronize(s->stream));
-  if ((r = nrc_train_records(s, inputs, targets, s->nrc_n.as<uint32_t>(), (uint32_t)frame, seed, mean_loss))) return r;
+  if ((r = nrc_train_records(s, inputs, targets, s->nrc_n.as<uint32_t>(), (uint32_t)frame, seed, mean_loss,
+                             s->stream)))
+    return r;
   return sync(s);
 }
 
@@ -1584,6 +1742,7 @@ pt_status pt_get_stats(pt_scene* s, pt_stats* o) {
     o->shadow_node_visits = (int64_t)v[kStatShadowNodes];
     o->shadow_tri_tests = (int64_t)v[kStatShadowTris];
     o->cache_queries = (int64_t)v[kStatQueries];
+    o->cache_records = (int64_t)v[kStatRecords];
     o->tail_extension_rays = (int64_t)v[kStatTailExt];
     o->tail_node_visits = (int64_t)v[kStatTailNodes];
     o->tail_tri_tests = (int64_t)v[kStatTailTris];
@@ -1596,8 +1755,13 @@ pt_status pt_get_stats(pt_scene* s, pt_stats* o) {
   o->ms_extend = s->ms_extend;
   o->launches_extend = s->launches_extend;
   o->ms_total = s->ms_total;
-  o->cache_records = s->nrc_records;
-  o->cache_adam_steps = s->nrc_step;
+  o->cache_adam_steps = 0;
+  if (s->nrc_t.p) {
+    uint32_t t = 0;
+    PT_HIP(hipMemcpyAsync(&t, s->nrc_t.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
+    PT_HIP(hipStreamSynchronize(s->stream));
+    o->cache_adam_steps = (int64_t)t;
+  }
   o->ms_cache_query = s->ms_cache_query;
   o->ms_cache_train = s->ms_cache_train;
   o->ms_tail = s->ms_tail;
@@ -1614,7 +1778,6 @@ pt_status pt_reset_stats(pt_scene* s) {
   s->ms_extend = s->ms_total = 0.0;
   s->launches_extend = 0;
   s->samples = 0;
-  s->nrc_records = 0;
   s->ms_cache_query = s->ms_cache_train = 0.0;
   s->ms_tail = 0.0;
   s->launches_tail = 0;

@@ -116,7 +116,8 @@ enum {
   kStatTailShadow = 12,       // shadow rays traced by the tail kernel (also in kStatShadow)
   kStatTailShadowNodes = 13,  // their node visits and triangle tests (not in kStatShadowNodes / kStatShadowTris)
   kStatTailShadowTris = 14,
-  kNumStats = 15
+  kStatRecords = 15,          // radiance-cache training records of the frame loop
+  kNumStats = 16
 };
 constexpr int kCountShadow = 2 + kNumClasses;
 constexpr int kCountQuery = kCountShadow + 1;
@@ -149,6 +150,11 @@ struct PassArgs {
   hipEvent_t tail_ready;
   bool* tail_launched;      // out: the tail kernel was launched on tail_stream
   int* trace_launches;      // out: traversal launches of the pass (timed by ext_events)
+  // radiance-cache frames: the stream waits for this event (if set) before the cache queries, and,
+  // past the query vertex, at most tail_bound paths (the training paths) can be alive: when that
+  // is at most tail_fraction of the slots, the tail kernel takes over without reading the count
+  hipEvent_t query_wait;
+  uint32_t tail_bound;
 };
 
 hipError_t launch_pass(const SceneDev& S, const PathsDev& P, const CamDev& C, const PassArgs& A,
@@ -165,16 +171,19 @@ int traversal_grid(int64_t rays);  // workgroups of the traversal kernel for a p
 int tail_grid(int grid_trace, uint32_t paths, bool beside);  // workgroups of the tail kernel
 
 // ---- radiance cache (pt_nrc.hip) ----
-hipError_t nrc_launch_pack(const float* w, uint4* fwd, uint4* bwd, hipStream_t st);
+// t_step / n_records (nullable): count the applied Adam step on the device unless the batch had no records
+hipError_t nrc_launch_pack(const float* w, uint4* fwd, uint4* bwd, uint32_t* t_step, const uint32_t* n_records,
+                           hipStream_t st);
 hipError_t nrc_launch_forward(const float* x, int64_t n, const uint4* fwd, float* y, hipStream_t st);
 hipError_t nrc_launch_query(const PathsDev& P, const uint4* fwd, int grid, hipStream_t st);
 hipError_t nrc_launch_train(const float* X, const float* T, int N, int npad, int n_split, const uint4* fwd,
                             const uint4* bwd, uint16_t* a_store, uint16_t* g_store, float* loss_part, int grid_fb,
                             float* dw_part, hipStream_t st);
 hipError_t nrc_launch_adam(float* w, float* m, float* v, const float* dw_part, int n_split, float* grad_out, float lr,
-                           float b1, float b2, float eps, int step, int apply, hipStream_t st);
+                           float b1, float b2, float eps, const uint32_t* t_step, const uint32_t* n_records, int apply,
+                           hipStream_t st);
 hipError_t nrc_launch_targets(const PathsDev& P, int n_paths, uint32_t* offsets, uint32_t* block_sums, float* X,
-                              float* T, uint32_t* n_out, hipStream_t st);
+                              float* T, uint32_t* n_out, unsigned long long* record_stats, hipStream_t st);
 hipError_t nrc_launch_gather(const float* X_all, const float* T_all, const uint32_t* n_all, int B, uint32_t frame,
                              int step, uint32_t k0, uint32_t k1, float* Xb, float* Tb, hipStream_t st);
 constexpr int kNrcFbGrid = 256;  // workgroups of the forward+backward kernel

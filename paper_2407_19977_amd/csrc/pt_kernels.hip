@@ -1250,9 +1250,13 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
     int cur = b & 1, next = cur ^ 1;
     if (A.tail_host_count && b >= A.tail_min_bounce && b > A.nrc_bounce) {
       // hand the remaining vertices to one persistent kernel once few paths are left
-      hipError_t e0 = hipMemcpyAsync(A.tail_host_count, &P.counts[cur], sizeof(uint32_t), hipMemcpyDeviceToHost, st);
-      if (e0 == hipSuccess) e0 = hipStreamSynchronize(st);
-      if (e0 != hipSuccess) return e0;
+      if (A.tail_bound && A.nrc_bounce >= 0 && (double)A.tail_bound <= A.tail_fraction * (double)P.n) {
+        *A.tail_host_count = A.tail_bound;  // a bound known on the host: no need to read the count
+      } else {
+        hipError_t e0 = hipMemcpyAsync(A.tail_host_count, &P.counts[cur], sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+        if (e0 == hipSuccess) e0 = hipStreamSynchronize(st);
+        if (e0 != hipSuccess) return e0;
+      }
       if ((double)*A.tail_host_count <= A.tail_fraction * (double)P.n) {
         if (A.wavefront_bounces) *A.wavefront_bounces = b;
         if (shadow_pending) {  // the previous vertex's shadow rays come before the tail's next vertex
@@ -1285,6 +1289,10 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
     if (b == A.nrc_bounce) {  // every path still alive ended in the cache at this vertex
       // (a path that ends in the cache casts no shadow ray at that vertex, so
       // the pending shadow rays touch other paths)
+      if (A.query_wait) {  // the weights of the last training must be in place
+        hipError_t e1 = hipStreamWaitEvent(st, A.query_wait, 0);
+        if (e1 != hipSuccess) return e1;
+      }
       if (A.nrc_events) hipEventRecord(A.nrc_events[0], st);
       hipError_t e2 = nrc_launch_query(P, A.nrc_fwd, std::min(A.grid, 1024), st);
       if (A.nrc_events) hipEventRecord(A.nrc_events[1], st);

@@ -50,8 +50,13 @@ __device__ inline bf16x8 chain_relu(f32x4 lo, f32x4 hi) {
 __device__ inline float bf16x8_get(bf16x8 v, int j) { return (float)v[j]; }
 
 // --------------------------------------------------------------- packing
-__global__ void k_nrc_pack(const float* __restrict__ w, uint4* __restrict__ fwd, uint4* __restrict__ bwd) {
+// Also counts the Adam step just applied (t_step, when given), unless the
+// batch had no records (n_records given and zero): the step then left the
+// weights and moments unchanged and is not counted.
+__global__ void k_nrc_pack(const float* __restrict__ w, uint4* __restrict__ fwd, uint4* __restrict__ bwd,
+                           uint32_t* __restrict__ t_step, const uint32_t* __restrict__ n_records) {
   int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id == 0 && t_step && (!n_records || *n_records > 0u)) *t_step += 1u;
   int total = (kNrcFwdFrags + kNrcBwdFrags) * 64;
   if (id >= total) return;
   int frag = id / 64, lane = id % 64, g = lane / 16, r = lane % 16;
@@ -375,16 +380,24 @@ __global__ __launch_bounds__(256) void k_nrc_dw(const uint16_t* __restrict__ a_s
 }
 
 // ------------------------------------------------------------------ Adam
+// Step t = t_step + 1 (the counter of applied steps lives on the device, so
+// that a batch drawn from zero records, known only on the device, can be
+// skipped without the host waiting for the record count).  Bias corrections
+// 1 / (1 - beta^t) in double, rounded to float.
 __global__ __launch_bounds__(256) void k_nrc_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
                                                   const float* __restrict__ dw_part, int n_split,
                                                   float* __restrict__ grad_out, float lr, float b1, float b2,
-                                                  float eps, float c1, float c2, int apply) {
+                                                  float eps, const uint32_t* __restrict__ t_step,
+                                                  const uint32_t* __restrict__ n_records, int apply) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= kNrcParams) return;
   float gsum = 0.0f;
   for (int s = 0; s < n_split; ++s) gsum += dw_part[(size_t)s * kNrcParams + p];
   if (grad_out) grad_out[p] = gsum;
-  if (!apply) return;
+  if (!apply || (n_records && *n_records == 0u)) return;
+  const double t = (double)(*t_step + 1u);
+  const float c1 = (float)(1.0 / (1.0 - pow((double)b1, t)));
+  const float c2 = (float)(1.0 / (1.0 - pow((double)b2, t)));
   float mm = b1 * m[p] + (1.0f - b1) * gsum;
   float vv = b2 * v[p] + (1.0f - b2) * gsum * gsum;
   m[p] = mm;
@@ -446,7 +459,8 @@ __global__ __launch_bounds__(256) void k_nrc_count(PathsDev P, int n_paths, uint
 }
 
 // In-place exclusive scan of the workgroup sums (one workgroup); total to *n_out.
-__global__ __launch_bounds__(1024) void k_nrc_scan(int n, uint32_t* __restrict__ sums, uint32_t* __restrict__ n_out) {
+__global__ __launch_bounds__(1024) void k_nrc_scan(int n, uint32_t* __restrict__ sums, uint32_t* __restrict__ n_out,
+                                                  unsigned long long* __restrict__ stats) {
   __shared__ uint32_t part[1024];
   const int per = (n + 1023) / 1024;
   const int k0 = min(n, (int)threadIdx.x * per), k1 = min(n, k0 + per);
@@ -466,7 +480,10 @@ __global__ __launch_bounds__(1024) void k_nrc_scan(int n, uint32_t* __restrict__
     sums[k] = base;
     base += c;
   }
-  if (threadIdx.x == 1023) *n_out = part[1023];
+  if (threadIdx.x == 1023) {
+    *n_out = part[1023];
+    if (stats) atomicAdd(&stats[kStatRecords], (unsigned long long)part[1023]);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_nrc_compact(PathsDev P, int n_paths, uint32_t* __restrict__ offsets,
@@ -512,9 +529,10 @@ __global__ __launch_bounds__(256) void k_nrc_gather(const float* __restrict__ X_
 }
 
 // ------------------------------------------------------------- launchers
-hipError_t nrc_launch_pack(const float* w, uint4* fwd, uint4* bwd, hipStream_t st) {
+hipError_t nrc_launch_pack(const float* w, uint4* fwd, uint4* bwd, uint32_t* t_step, const uint32_t* n_records,
+                           hipStream_t st) {
   int total = (kNrcFwdFrags + kNrcBwdFrags) * 64;
-  hipLaunchKernelGGL(k_nrc_pack, dim3((total + 255) / 256), dim3(256), 0, st, w, fwd, bwd);
+  hipLaunchKernelGGL(k_nrc_pack, dim3((total + 255) / 256), dim3(256), 0, st, w, fwd, bwd, t_step, n_records);
   return hipGetLastError();
 }
 
@@ -563,19 +581,18 @@ hipError_t nrc_launch_train(const float* X, const float* T, int N, int npad, int
 }
 
 hipError_t nrc_launch_adam(float* w, float* m, float* v, const float* dw_part, int n_split, float* grad_out, float lr,
-                           float b1, float b2, float eps, int step, int apply, hipStream_t st) {
-  float c1 = (float)(1.0 / (1.0 - std::pow((double)b1, (double)step)));
-  float c2 = (float)(1.0 / (1.0 - std::pow((double)b2, (double)step)));
+                           float b1, float b2, float eps, const uint32_t* t_step, const uint32_t* n_records, int apply,
+                           hipStream_t st) {
   hipLaunchKernelGGL(k_nrc_adam, dim3((kNrcParams + 255) / 256), dim3(256), 0, st, w, m, v, dw_part, n_split, grad_out,
-                     lr, b1, b2, eps, c1, c2, apply);
+                     lr, b1, b2, eps, t_step, n_records, apply);
   return hipGetLastError();
 }
 
 hipError_t nrc_launch_targets(const PathsDev& P, int n_paths, uint32_t* offsets, uint32_t* block_sums, float* X,
-                              float* T, uint32_t* n_out, hipStream_t st) {
+                              float* T, uint32_t* n_out, unsigned long long* record_stats, hipStream_t st) {
   const int nb = (n_paths + 255) / 256;
   hipLaunchKernelGGL(k_nrc_count, dim3(nb), dim3(256), 0, st, P, n_paths, offsets, block_sums);
-  hipLaunchKernelGGL(k_nrc_scan, dim3(1), dim3(1024), 0, st, nb, block_sums, n_out);
+  hipLaunchKernelGGL(k_nrc_scan, dim3(1), dim3(1024), 0, st, nb, block_sums, n_out, record_stats);
   hipLaunchKernelGGL(k_nrc_compact, dim3(nb), dim3(256), 0, st, P, n_paths, offsets, block_sums, X, T);
   return hipGetLastError();
 }

@@ -12,6 +12,8 @@
   paths equal the oracle's, path by path.
 * Closed form: a network that outputs 1 on the white furnace gives 1.
 * The frame loop learns: the loss on held-out records falls.
+* Frames of one call, which overlap on two path sets, give bitwise the sums
+  and weights of one call per frame.
 """
 import math
 
@@ -307,6 +309,44 @@ def test_frame_loop_learns_and_counts_steps(P, O):
     s.resolve(out)
     img = out.cpu().numpy()
     assert np.isfinite(img).all() and img.mean() > 0
+    s.set_radiance_cache(None)
+
+
+def test_overlapped_frames_equal_frame_by_frame(P, O):
+    """Frames of one call overlap (a frame's training beside the next frame's
+    bounces, on two path sets); the FP64 sums, weights, Adam moments and step
+    count must be bitwise those of one call per frame.  64x64 with 512
+    training paths, so the tail takes the training paths over without a
+    host read of the path count (512 <= 1/8 of 4096 + 512 slots)."""
+    _say("[nrc overlap] box scene 64x64, 6 frames, 512 training paths")
+    sc = scenes.cornell(width=64, height=64)
+    cfg = P.cache_config(train_paths=512, batch_size=512, steps_per_frame=2)
+    _, s, _ = _cache_scene(P, O, "cornell64b", lambda: sc, cfg)
+    depth, seed, frames = 5, 3, 6
+    out = torch.empty((64, 64, 3), dtype=torch.float32, device="cuda:0")
+    results = []
+    for one_call in (True, False):
+        s.set_radiance_cache(cfg)
+        s.reset_accumulation()
+        s.reset_stats()
+        if one_call:
+            s.accumulate(sc.camera, 0, frames, depth, seed)
+        else:
+            for k in range(frames):
+                s.accumulate(sc.camera, k, 1, depth, seed)
+        acc = torch.empty((64, 64, 3), dtype=torch.float64, device="cuda:0")
+        s.resolve(out, acc)
+        w = torch.empty(P.NRC_PARAMS, dtype=torch.float32, device="cuda:0")
+        m, v = torch.empty_like(w), torch.empty_like(w)
+        step = s.nrc_get_weights(w, m, v)
+        st = s.stats()
+        results.append((acc.cpu().numpy(), w.cpu().numpy(), m.cpu().numpy(), v.cpu().numpy(), step,
+                        st["cache_records"], st["cache_queries"]))
+    a, b = results
+    assert a[4] == b[4] == frames * 2
+    assert a[5] == b[5] > 0 and a[6] == b[6] > 0
+    for x, y in zip(a[:4], b[:4]):
+        assert np.array_equal(x, y)
     s.set_radiance_cache(None)
 
 

@@ -126,6 +126,8 @@ struct pt_scene {
   PathBufs pb[2];
   DevBuf stats;
   hipStream_t stream2 = nullptr;       // created on first use (default priority)
+  hipStream_t shade_side[2] = {nullptr, nullptr};  // side streams of the shading kernels (default priority)
+  hipEvent_t shade_fork = nullptr, shade_join[2] = {nullptr, nullptr};
   hipEvent_t ev_bulk[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
   uint32_t* tail_counts = nullptr;     // pinned host words, one per set
   // accumulation
@@ -565,6 +567,23 @@ pt_status read_pass_events(pt_scene* s, int set, int wavefront_bounces, int trac
 // passes use the two path sets alternately: a pass's tail kernel and its
 // accumulation run on the second stream while the next pass's dense bounces
 // run on the scene's stream; the accumulations stay in pass order.
+#ifndef PT_SHADE_SIDE
+#define PT_SHADE_SIDE 1
+#endif
+// Side streams for the shading kernels of a pass (created once).
+pt_status shade_streams(pt_scene* s, PassArgs& A) {
+  if (!PT_SHADE_SIDE) return PT_OK;
+  for (int k = 0; k < 2; ++k) {
+    if (!s->shade_side[k]) PT_HIP(hipStreamCreateWithFlags(&s->shade_side[k], hipStreamNonBlocking));
+    if (!s->shade_join[k]) PT_HIP(hipEventCreateWithFlags(&s->shade_join[k], hipEventDisableTiming));
+    A.shade_side[k] = s->shade_side[k];
+    A.shade_join[k] = s->shade_join[k];
+  }
+  if (!s->shade_fork) PT_HIP(hipEventCreateWithFlags(&s->shade_fork, hipEventDisableTiming));
+  A.shade_fork = s->shade_fork;
+  return PT_OK;
+}
+
 pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h, int first, int n, int max_depth,
                      uint64_t seed, double* sum, float* per_sample, uint64_t* sigs, int spp_total,
                      bool train = false) {
@@ -634,6 +653,7 @@ pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h,
     }
     A.wavefront_bounces = &wavefront[set];
     A.trace_launches = &traces[set];
+    if ((r = shade_streams(s, A))) return r;
     tail_on_2[set] = false;
     if (overlap) {
       A.tail_stream = s->stream2;
@@ -780,6 +800,7 @@ pt_status run_cache_frames(pt_scene* s, const CamDev& C, int first, int n, int m
     }
     A.wavefront_bounces = &wavefront[set];
     A.trace_launches = &traces[set];
+    if ((r = shade_streams(s, A))) return r;
     tail_on_2[set] = false;
     A.tail_stream = s->stream2;
     A.tail_ready = s->ev_bulk[set];
@@ -1293,6 +1314,12 @@ void pt_scene_destroy(pt_scene* s) {
       if (s->ev_train_t[k][j]) (void)hipEventDestroy(s->ev_train_t[k][j]);
   }
   if (s->ev_train) (void)hipEventDestroy(s->ev_train);
+  for (int k = 0; k < 2; ++k) {
+    if (s->shade_side[k]) (void)hipStreamSynchronize(s->shade_side[k]);
+    if (s->shade_join[k]) (void)hipEventDestroy(s->shade_join[k]);
+    if (s->shade_side[k]) (void)hipStreamDestroy(s->shade_side[k]);
+  }
+  if (s->shade_fork) (void)hipEventDestroy(s->shade_fork);
   if (s->stream2) (void)hipStreamDestroy(s->stream2);
   if (s->tail_counts) (void)hipHostFree(s->tail_counts);
   delete s;

@@ -155,6 +155,10 @@ struct PassArgs {
   // is at most tail_fraction of the slots, the tail kernel takes over without reading the count
   hipEvent_t query_wait;
   uint32_t tail_bound;
+  // two side streams (both or neither) on which shading kernels of different material classes run
+  // beside the pass's stream, with a fork event and one join event per side stream
+  hipStream_t shade_side[2];
+  hipEvent_t shade_fork, shade_join[2];
 };
 
 hipError_t launch_pass(const SceneDev& S, const PathsDev& P, const CamDev& C, const PassArgs& A,

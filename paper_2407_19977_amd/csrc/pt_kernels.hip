@@ -303,6 +303,11 @@ constexpr uint32_t kRefill = PT_REFILL;  // idle lanes that trigger a refill
 // traversal kernels: lanes at a leaf wait until kLeafWait x their number
 // reaches kLeafWaitDen x the number of lanes at inner nodes (0: no waiting)
 constexpr uint32_t kLeafWait = PT_LEAF_WAIT, kLeafWaitDen = PT_LEAF_WAIT_DEN;
+#ifndef PT_SHADE_GRID_DIV
+#define PT_SHADE_GRID_DIV 3
+#endif
+// with side streams each class kernel gets 1/PT_SHADE_GRID_DIV of the grid, so
+// that the concurrent class kernels can be resident together
 #ifndef PT_SHADE_BLOCK
 #define PT_SHADE_BLOCK 256
 #endif
@@ -1216,19 +1221,48 @@ int traversal_grid(int64_t rays) {
 template <bool DEBUG, bool TWO>
 static hipError_t shade_all(const SceneDev& S, const PathsDev& P, const PassArgs& A, int b, int next, uint32_t W,
                             hipStream_t st) {
-  dim3 g(std::max(1, A.grid * kBlock / kShadeBlock)), blk(kShadeBlock);
-#define PT_SHADE(C)                                                                                     \
-  if (A.class_mask & (1u << C))                                                                         \
-    hipLaunchKernelGGL((k_shade<C, DEBUG, TWO>), g, blk, 0, st, S, P, b, A.max_depth, next, A.sample, A.k0, \
-                       A.k1, W, A.nrc_bounce);
-  PT_SHADE(kClsMiss)
-  PT_SHADE(kClsAbsorb)
-  PT_SHADE(kClsDiffuse)
-  PT_SHADE(kClsMetal)
-  PT_SHADE(kClsPlastic)
-  PT_SHADE(kClsGlass)
-  PT_SHADE(kClsGeneral)
+  // The class kernels touch disjoint path slots and append through atomics,
+  // so with side streams they run concurrently (each is bound by the
+  // latency of its own dependent loads): class i of those present goes to
+  // stream i mod 3 (0: the pass's stream), which then waits for the others.
+  hipStream_t lane[3] = {st, A.shade_side[0], A.shade_side[1]};
+  int n_streams = A.shade_side[0] && A.shade_side[1] ? 3 : 1, used = 0;
+  dim3 g(std::max(1, A.grid * kBlock / kShadeBlock / (n_streams > 1 ? PT_SHADE_GRID_DIV : 1))), blk(kShadeBlock);
+  bool forked = false;
+  for (int c = 0; c < kNumClasses; ++c) {
+    if (!(A.class_mask & (1u << c))) continue;
+    hipStream_t q = lane[used % n_streams];
+    if (q != st && !forked) {
+      hipError_t e = hipEventRecord(A.shade_fork, st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(A.shade_side[0], A.shade_fork, 0);
+      if (e == hipSuccess) e = hipStreamWaitEvent(A.shade_side[1], A.shade_fork, 0);
+      if (e != hipSuccess) return e;
+      forked = true;
+    }
+    ++used;
+    switch (c) {
+#define PT_SHADE(C)                                                                                      \
+  case C:                                                                                                \
+    hipLaunchKernelGGL((k_shade<C, DEBUG, TWO>), g, blk, 0, q, S, P, b, A.max_depth, next, A.sample, A.k0, \
+                       A.k1, W, A.nrc_bounce);                                                           \
+    break;
+      PT_SHADE(kClsMiss)
+      PT_SHADE(kClsAbsorb)
+      PT_SHADE(kClsDiffuse)
+      PT_SHADE(kClsMetal)
+      PT_SHADE(kClsPlastic)
+      PT_SHADE(kClsGlass)
+      PT_SHADE(kClsGeneral)
 #undef PT_SHADE
+    }
+  }
+  if (forked) {
+    for (int k = 0; k < 2; ++k) {
+      hipError_t e = hipEventRecord(A.shade_join[k], A.shade_side[k]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, A.shade_join[k], 0);
+      if (e != hipSuccess) return e;
+    }
+  }
   return hipGetLastError();
 }
 

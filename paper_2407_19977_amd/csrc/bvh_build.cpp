@@ -59,6 +59,10 @@ struct BNode {
 };
 
 constexpr int kBins = 32;
+#ifndef PT_SAH_TRAVERSAL
+#define PT_SAH_TRAVERSAL 1.0
+#endif
+constexpr double kSahTraversal = PT_SAH_TRAVERSAL;  // cost of a node step relative to one triangle test
 
 struct Builder {
   const std::vector<Box>* tb;
@@ -125,9 +129,9 @@ struct Builder {
         }
       }
     }
-    // leaf if small and splitting does not pay (SAH with traversal cost 1, triangle cost 1)
+    // leaf if small and splitting does not pay (SAH: traversal cost kSahTraversal, triangle cost 1)
     double leaf_cost = (double)count;
-    double split_cost = parent_area > 0 ? 1.0 + best_cost / parent_area : 1.0 + count;
+    double split_cost = parent_area > 0 ? kSahTraversal + best_cost / parent_area : kSahTraversal + count;
     bool make_leaf = count <= 1 || (count <= kMaxLeafTris && (best_axis < 0 || leaf_cost <= split_cost));
     if (make_leaf) {
       nd.first = first;

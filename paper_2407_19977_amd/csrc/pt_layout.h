@@ -24,7 +24,11 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kLeafBit = 0x80000000u;
 constexpr int kLeafCountShift = 27;
 constexpr uint32_t kLeafFirstMask = (1u << kLeafCountShift) - 1u;
-constexpr int kMaxLeafTris = 4;
+#ifndef PT_MAX_LEAF_TRIS
+#define PT_MAX_LEAF_TRIS 4
+#endif
+constexpr int kMaxLeafTris = PT_MAX_LEAF_TRIS;  // at most 7 (3-bit count in a leaf reference)
+static_assert(kMaxLeafTris >= 1 && kMaxLeafTris <= 7, "leaf references hold 3-bit triangle counts");
 
 __host__ __device__ inline bool ref_is_leaf(uint32_t r) { return (r & kLeafBit) != 0u; }
 __host__ __device__ inline uint32_t leaf_count(uint32_t r) { return (r >> kLeafCountShift) & 7u; }

@@ -94,8 +94,8 @@ typedef struct pt_stats {
   int64_t shadow_node_visits;/* BVH node fetches of shadow rays (counting on; tail kernel apart) */
   int64_t shadow_tri_tests;  /* triangle tests of shadow rays (counting on; tail kernel apart) */
   int64_t cache_queries;     /* paths that ended in the radiance cache */
-  int64_t cache_records;     /* training records produced by training paths */
-  int64_t cache_adam_steps;  /* Adam steps taken since the cache was configured or given weights */
+  int64_t cache_records;     /* training records produced by the frames' training paths */
+  int64_t cache_adam_steps;  /* Adam steps applied since the cache was configured or given weights */
   double ms_cache_query;     /* summed time of the cache-query kernel (profiling on) */
   double ms_cache_train;     /* summed time of training: targets and Adam steps (profiling on) */
   int64_t tail_extension_rays; /* closest-hit rays of the tail kernel (included in extension_rays) */
@@ -207,7 +207,11 @@ pt_status pt_set_profiling(pt_scene* scene, int32_t timing, int32_t counting);
  * 2^31 + frame, pixels (k * floor(WH / train_paths) + o_frame) mod WH)
  * record (inputs, (L_end - L_k) / beta_k) at their vertices, and
  * steps_per_frame Adam steps run on batches of batch_size records drawn
- * with replacement by Philox (see pt_nrc_train). */
+ * with replacement by Philox (see pt_nrc_train).  A frame with no record
+ * changes no weight and counts no step.  The frames of one call overlap on
+ * the device (a frame's training beside the next frame's first bounces,
+ * whose cache queries wait for it); images, weights and step counts are
+ * bitwise those of one call per frame. */
 typedef struct pt_radiance_cache_config {
   int32_t query_bounce;    /* vertex at which sampling paths end in the cache, >= 0 (2 by default) */
   int32_t train_paths;     /* training paths per frame, [1, 2^24] (65536) */

@@ -8,6 +8,7 @@
 * Closed forms on the GPU: white furnace, smooth glass sphere, diffuse plane.
 * The full-size workload of the benchmark, checked on sampled pixels.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -230,6 +231,47 @@ def test_tail_hand_off_parity(P, O, which, mode):
     assert (st["tail_extension_rays"] > 0) == (mode != "wavefront")
     ref = os_.render(spp, sc.max_depth, crop=crop, per_sample=True)
     _compare(g, gs, ref, {"box": 0.999, "spheres": 0.99, "instanced": 0.98}[which], f"{which} {mode}")
+
+
+@pytest.mark.parametrize("depth", [0, 1])
+def test_shallow_depth_parity(P, O, depth):
+    """max_depth 0 (camera rays only: emission and environment at the first
+    vertex, no light sampling) and 1 (one bounce, no Russian roulette yet)."""
+    sc, s, os_ = _cornell(P, O)
+    crop = (40, 40, 24, 24)
+    _say(f"[edge] box crop {crop}, 4 spp, depth {depth}")
+    g, gs = _debug(s, sc.camera, crop, 0, 4, depth)
+    ref = os_.render(4, depth, crop=crop, per_sample=True)
+    _compare(g, gs, ref, 0.999, f"box depth {depth}")
+
+
+def test_single_pixel_and_single_row_parity(P, O):
+    """Crops of one pixel, one row and one column: queues far shorter than a
+    wave, ragged in every workgroup."""
+    sc, s, os_ = _spheres(P, O)
+    for crop, spp in (((1000, 600, 1, 1), 32), ((1000, 600, 67, 1), 4), ((1000, 600, 1, 67), 4)):
+        _say(f"[edge] icosphere field crop {crop}, {spp} spp")
+        g, gs = _debug(s, sc.camera, crop, 2, spp, 8)
+        ref = os_.render(spp, 8, crop=crop, first_sample=2, per_sample=True, n_threads=16)
+        _compare(g, gs, ref, 0.9, f"spheres{crop}")
+
+
+def test_all_rays_miss_parity(P, O):
+    """A camera that sees only sky: every path ends at its first vertex in
+    the environment (empty class queues, no shadow rays, no second bounce)."""
+    sc, s, os_ = _spheres(P, O)
+    cam = dataclasses.replace(sc.camera, look_at=(0.0, 100.0, 0.0), width=64, height=36)
+    _say("[edge] icosphere field, camera at the sky, 64x36, 4 spp")
+    g, gs = _debug(s, cam, (0, 0, 64, 36), 0, 4, 8)
+    ref = os_.render(4, 8, per_sample=True, camera=cam, n_threads=16)
+    _compare(g, gs, ref, 0.999, "all miss")
+    assert g.mean() > 0.0  # the sky is lit
+    s.reset_stats()
+    out = torch.empty((36, 64, 3), dtype=torch.float32, device="cuda:0")
+    s.render(cam, 4, 8, 0, out)
+    st = s.stats()
+    assert st["extension_rays"] == 64 * 36 * 4 and st["shadow_rays"] == 0
+    assert np.allclose(out.cpu().numpy(), g.mean(2), rtol=2e-6, atol=1e-7)
 
 
 def test_progressive_accumulation_is_bitwise(P, O):

@@ -30,6 +30,33 @@ __device__ inline uint32_t lane_prefix(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// A workgroup's share of a queue of n items in a grid of G workgroups:
+// chunks of kShareChunk consecutive items dealt round-robin (chunk c to
+// workgroup c mod G), so every workgroup gets items from all over the queue
+// (regions of the image differ widely in cost) while a wave's refill still
+// takes neighbouring items.  kShareChunk 0: one contiguous share each.
+#ifndef PT_SHARE_CHUNK
+#define PT_SHARE_CHUNK 256
+#endif
+constexpr uint32_t kShareChunk = PT_SHARE_CHUNK;
+__device__ inline uint32_t share_size(uint32_t n, uint32_t wg, uint32_t G) {
+  if (!kShareChunk) {
+    const uint32_t per = (n + G - 1) / G, a = min(n, wg * per);
+    return min(n, a + per) - a;
+  }
+  const uint32_t nc = (n + kShareChunk - 1) / kShareChunk;  // chunks, the last one possibly partial
+  if (nc <= wg) return 0u;
+  const uint32_t mine = (nc - 1 - wg) / G + 1;
+  uint32_t items = mine * kShareChunk;
+  if ((nc - 1) % G == wg) items -= nc * kShareChunk - n;  // this workgroup holds the partial chunk
+  return items;
+}
+// queue index of item v (< share_size) of workgroup wg
+__device__ inline uint32_t share_item(uint32_t v, uint32_t n, uint32_t wg, uint32_t G) {
+  if (!kShareChunk) return min(n, wg * ((n + G - 1) / G)) + v;
+  return ((v / kShareChunk) * G + wg) * kShareChunk + v % kShareChunk;
+}
+
 // Sum of a value over the wave's 64 lanes (every lane gets the sum).
 __device__ inline uint32_t wave_sum(uint32_t v) {
   for (int d = 32; d >= 1; d >>= 1) v += (uint32_t)__shfl_xor((int)v, d);
@@ -858,11 +885,8 @@ __global__ __launch_bounds__(kBlock, kTraceWaves) void k_traverse(SceneDev S, Pa
     if (ne) atomicAdd(&P.stats[kStatExt], (unsigned long long)ne);
     if (ns) atomicAdd(&P.stats[kStatShadow], (unsigned long long)ns);
   }
-  const uint32_t G = gridDim.x;
-  const uint32_t pe = (ne + G - 1) / G, ps = (ns + G - 1) / G;
-  const uint32_t e0 = min(ne, blockIdx.x * pe), e1 = min(ne, e0 + pe);
-  const uint32_t s0 = min(ns, blockIdx.x * ps), s1 = min(ns, s0 + ps);
-  const uint32_t n_e = e1 - e0, n_all = n_e + (s1 - s0);
+  const uint32_t G = gridDim.x, wg = blockIdx.x;
+  const uint32_t n_e = share_size(ne, wg, G), n_all = n_e + share_size(ns, wg, G);
   if (threadIdx.x == 0) s_next = 0u;
   __syncthreads();
   const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
@@ -886,7 +910,7 @@ __global__ __launch_bounds__(kBlock, kTraceWaves) void k_traverse(SceneDev S, Pa
       const uint32_t v = base + lane_prefix(idle);
       if (!busy && v < n_all) {
         shadow = v >= n_e;
-        item = shadow ? s0 + (v - n_e) : e0 + v;
+        item = shadow ? share_item(v - n_e, ns, wg, G) : share_item(v, ne, wg, G);
         st.sp = 0;
         if (shadow) cs.start(item, L);
         else es.start(item, L);

@@ -999,10 +999,13 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
   uint32_t n_ext = 0, n_sh = 0, nvis = 0, ntri = 0, svis = 0, stri = 0;
   unsigned long long nonfinite = 0;
   bool overflow = false;
+  uint32_t rv = 0, rt = 0;  // node visits / triangle tests of the current walk
   auto start_closest = [&](void) {
     float4 o = P.ray_o[slot], d = P.ray_d[slot];
     st.sp = 0;
     lane_start<TWO>(L, o.x, o.y, o.z, d.x, d.y, d.z, S.tmin, INFINITY, f2u(d.w), f2u(o.w), TWO ? 0u : S.root);
+    L.any = false;
+    rv = rt = 0;
     phase = 1;
     n_ext++;
   };
@@ -1022,8 +1025,28 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
       }
     }
     if (__ballot(phase != 0) == 0) break;
+    // closest-hit and shadow walks share one walk step (kind per lane); a
+    // lane at a leaf waits while lanes at inner nodes outnumber it
+    const bool walking = phase == 1 || phase == 2;
+    bool go = walking;
+    if (kLeafWait) {
+      const bool at_leaf = walking && L.cur != kEmpty && ref_is_leaf(L.cur);
+      const uint32_t n_leaf = (uint32_t)__popcll((unsigned long long)__ballot(at_leaf));
+      const uint32_t n_node = (uint32_t)__popcll((unsigned long long)__ballot(walking && !at_leaf));
+      go = walking && (!at_leaf || kLeafWait * n_leaf >= kLeafWaitDen * n_node);
+    }
+    const bool done = go && lane_step<kWalkPerLane, COUNT, TWO>(S, L, st, rv, rt);
+    if (done && COUNT) {
+      if (phase == 1) {
+        nvis += rv;
+        ntri += rt;
+      } else {
+        svis += rv;
+        stri += rt;
+      }
+    }
     if (phase == 1) {
-      if (lane_step<kWalkClosest, COUNT, TWO>(S, L, st, nvis, ntri)) {
+      if (done) {
         overflow |= st.overflow;
         cls = kClsMiss;
         if (L.best.tri != 0xFFFFFFFFu) {
@@ -1041,7 +1064,7 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
         phase = 3;
       }
     } else if (phase == 2) {
-      if (lane_step<kWalkAny, COUNT, TWO>(S, L, st, svis, stri)) {
+      if (done) {
         overflow |= st.overflow;
         const bool occ = L.best.tri != 0xFFFFFFFFu;
         if (!occ) {
@@ -1082,6 +1105,8 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
         st.sp = 0;
         lane_start<TWO>(L, o.sh_o.x, o.sh_o.y, o.sh_o.z, o.sh_d.x, o.sh_d.y, o.sh_d.z, S.tmin, o.sh_o.w,
                         TWO ? o.sh_inst : 0u, f2u(o.sh_c.w), TWO ? 0u : S.root);
+        L.any = true;
+        rv = rt = 0;
         sh_c = o.sh_c;
         cont = o.cont;
         phase = 2;

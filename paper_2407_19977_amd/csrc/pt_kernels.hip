@@ -347,9 +347,9 @@ constexpr int kShadeBlock = PT_SHADE_BLOCK;  // threads per workgroup of the sha
 // once, as soon as a walk ends)
 constexpr uint32_t kTailShadeWait = PT_TAIL_SHADE_WAIT;
 #ifndef PT_TAIL_PATHS_PER_GROUP
-#define PT_TAIL_PATHS_PER_GROUP 384
+#define PT_TAIL_PATHS_PER_GROUP 512
 #endif
-// tail kernel beside the next pass: paths per workgroup (about 1.5 per lane)
+// tail kernel beside the next pass: paths per workgroup (two per lane)
 constexpr uint64_t kTailPathsPerGroup = PT_TAIL_PATHS_PER_GROUP;
 #ifndef PT_TRACE_WAVES
 #define PT_TRACE_WAVES 7

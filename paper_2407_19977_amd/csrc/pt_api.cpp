@@ -719,12 +719,12 @@ pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h,
 }
 
 // Frames of the radiance cache once it has weights, pipelined over the two
-// path sets.  A frame's sampling paths all end by the query vertex, so its
-// accumulation follows its cache queries on the scene's stream; its training
-// paths' remaining vertices (tail kernel), their targets and the frame's
-// Adam steps run on the second stream while the next frame's dense bounces
-// run on the scene's stream.  The next frame's cache queries wait for those
-// Adam steps, so every frame sees the weights a frame-by-frame loop would.
+// path sets.  A frame's sampling paths all end by the query vertex; its cache
+// queries, its training paths' remaining vertices (tail kernel), its
+// accumulation, the training targets and the frame's Adam steps run on the
+// second stream while the next frame's dense bounces run on the scene's
+// stream.  Each frame's cache queries come after the previous frame's Adam
+// steps, so every frame sees the weights a frame-by-frame loop would.
 pt_status run_cache_frames(pt_scene* s, const CamDev& C, int first, int n, int max_depth, uint64_t seed) {
   const int64_t N = (int64_t)C.W * C.H;
   const int64_t slots = N + s->nrc_cfg.train_paths;
@@ -792,6 +792,7 @@ pt_status run_cache_frames(pt_scene* s, const CamDev& C, int first, int n, int m
     A.nrc_bounce = s->nrc_cfg.query_bounce;
     A.nrc_fwd = s->nrc_fwd.as<uint4>();
     A.query_wait = k > 0 ? s->ev_train : nullptr;  // the previous frame's Adam steps
+    A.query_beside = true;
     if (tail) {
       A.tail_host_count = s->tail_counts + set;
       A.tail_min_bounce = s->tail_min_bounce;
@@ -820,9 +821,9 @@ pt_status run_cache_frames(pt_scene* s, const CamDev& C, int first, int n, int m
       PT_HIP(hipEventRecord(s->ev_bulk[set], s->stream));
       PT_HIP(hipStreamWaitEvent(s->stream2, s->ev_bulk[set], 0));
     }
-    // the sampling paths ended by the query vertex: their radiance is final
-    PT_HIP(launch_accumulate(P, s->sum.as<double>(), C.W, nullptr, nullptr, 1, 0, s->stream));
-    if (ev) PT_HIP(hipEventRecord(ev[1], s->stream));
+    // accumulation, targets and training follow on the second stream, in frame order
+    PT_HIP(launch_accumulate(P, s->sum.as<double>(), C.W, nullptr, nullptr, 1, 0, s->stream2));
+    if (ev) PT_HIP(hipEventRecord(ev[1], s->stream2));
     if (s->timing) PT_HIP(hipEventRecord(s->ev_train_t[set][0], s->stream2));
     if ((r = finish_training(s, P, nullptr, s->stream2, true))) return r;
     if ((r = nrc_train_records(s, s->nrc_X.as<float>(), s->nrc_T.as<float>(), s->nrc_n.as<uint32_t>(), frame, seed,

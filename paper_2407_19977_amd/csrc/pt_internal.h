@@ -155,6 +155,7 @@ struct PassArgs {
   // is at most tail_fraction of the slots, the tail kernel takes over without reading the count
   hipEvent_t query_wait;
   uint32_t tail_bound;
+  bool query_beside;  // launch the cache queries on tail_stream at the hand-off, before the tail kernel
   // two side streams (both or neither) on which shading kernels of different material classes run
   // beside the pass's stream, with a fork event and one join event per side stream
   hipStream_t shade_side[2];

@@ -1329,6 +1329,17 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
     n_trace++;
   };
   bool shadow_pending = false;  // the last shading queued shadow rays that no launch has traced yet
+  bool query_pending = false;   // the cache queries wait for the tail kernel's stream
+  auto query = [&](hipStream_t q) -> hipError_t {
+    if (A.query_wait) {  // the weights of the last training must be in place
+      hipError_t e1 = hipStreamWaitEvent(q, A.query_wait, 0);
+      if (e1 != hipSuccess) return e1;
+    }
+    if (A.nrc_events) hipEventRecord(A.nrc_events[0], q);
+    hipError_t e2 = nrc_launch_query(P, A.nrc_fwd, std::min(A.grid, 1024), q);
+    if (A.nrc_events) hipEventRecord(A.nrc_events[1], q);
+    return e2;
+  };
   for (int b = 0; b <= A.max_depth; ++b) {
     int cur = b & 1, next = cur ^ 1;
     if (A.tail_host_count && b >= A.tail_min_bounce && b > A.nrc_bounce) {
@@ -1354,6 +1365,11 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
           ts = A.tail_stream;
           if (A.tail_launched) *A.tail_launched = true;
         }
+        if (query_pending) {  // the queries run on the tail kernel's stream, before it
+          hipError_t e2 = query(ts);
+          if (e2 != hipSuccess) return e2;
+          query_pending = false;
+        }
         if (A.tail_events) hipEventRecord(A.tail_events[0], ts);
         hipLaunchKernelGGL((k_tail<DEBUG, COUNT, TWO>),
                            dim3(tail_grid(A.grid_trace, *A.tail_host_count, A.tail_stream != nullptr)), blk, 0, ts,
@@ -1371,19 +1387,22 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
     shadow_pending = b < A.max_depth;
     if (b == A.nrc_bounce) {  // every path still alive ended in the cache at this vertex
       // (a path that ends in the cache casts no shadow ray at that vertex, so
-      // the pending shadow rays touch other paths)
-      if (A.query_wait) {  // the weights of the last training must be in place
-        hipError_t e1 = hipStreamWaitEvent(st, A.query_wait, 0);
-        if (e1 != hipSuccess) return e1;
+      // the pending shadow rays touch other paths; the queries touch only the
+      // paths that ended here, so they can wait for the tail kernel's stream)
+      if (A.query_beside && A.tail_stream && P.n > P.n_render) {
+        query_pending = true;
+      } else {
+        hipError_t e2 = query(st);
+        if (e2 != hipSuccess) return e2;
       }
-      if (A.nrc_events) hipEventRecord(A.nrc_events[0], st);
-      hipError_t e2 = nrc_launch_query(P, A.nrc_fwd, std::min(A.grid, 1024), st);
-      if (A.nrc_events) hipEventRecord(A.nrc_events[1], st);
-      if (e2 != hipSuccess) return e2;
       if (P.n == P.n_render) break;  // no training paths: nothing continues
     }
   }
   if (shadow_pending) traverse(-1);
+  if (query_pending) {  // no hand-off: the queries run here after all
+    hipError_t e2 = query(st);
+    if (e2 != hipSuccess) return e2;
+  }
   if (A.trace_launches) *A.trace_launches = n_trace;
   return hipGetLastError();
 }

@@ -1321,11 +1321,11 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
   dim3 blk(kBlock);
   if (A.wavefront_bounces) *A.wavefront_bounces = A.max_depth + 1;
   int n_trace = 0;
-  // closest hits of queue q (none if q < 0) and the shadow rays of the last shading
-  auto traverse = [&](int q) {
-    if (A.ext_events) hipEventRecord(A.ext_events[2 * n_trace], st);
-    hipLaunchKernelGGL((k_traverse<DEBUG, COUNT, TWO>), dim3(A.grid_trace), blk, 0, st, S, P, q);
-    if (A.ext_events) hipEventRecord(A.ext_events[2 * n_trace + 1], st);
+  // closest hits of queue q (none if q < 0) and the shadow rays of the last shading, on stream on
+  auto traverse = [&](int q, hipStream_t on) {
+    if (A.ext_events) hipEventRecord(A.ext_events[2 * n_trace], on);
+    hipLaunchKernelGGL((k_traverse<DEBUG, COUNT, TWO>), dim3(A.grid_trace), blk, 0, on, S, P, q);
+    if (A.ext_events) hipEventRecord(A.ext_events[2 * n_trace + 1], on);
     n_trace++;
   };
   bool shadow_pending = false;  // the last shading queued shadow rays that no launch has traced yet
@@ -1353,10 +1353,6 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
       }
       if ((double)*A.tail_host_count <= A.tail_fraction * (double)P.n) {
         if (A.wavefront_bounces) *A.wavefront_bounces = b;
-        if (shadow_pending) {  // the previous vertex's shadow rays come before the tail's next vertex
-          traverse(-1);
-          shadow_pending = false;
-        }
         hipStream_t ts = st;
         if (A.tail_stream) {  // continue on the second stream; the caller's stream is free for the next pass
           hipError_t e1 = hipEventRecord(A.tail_ready, st);
@@ -1364,6 +1360,10 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
           if (e1 != hipSuccess) return e1;
           ts = A.tail_stream;
           if (A.tail_launched) *A.tail_launched = true;
+        }
+        if (shadow_pending) {  // the previous vertex's shadow rays come before the tail's next vertex
+          traverse(-1, ts);
+          shadow_pending = false;
         }
         if (query_pending) {  // the queries run on the tail kernel's stream, before it
           hipError_t e2 = query(ts);
@@ -1379,7 +1379,7 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
       }
     }
     hipLaunchKernelGGL(k_reset_counts, dim3(1), dim3(64), 0, st, P.counts, next);
-    traverse(cur);  // this bounce's closest hits and the previous bounce's shadow rays
+    traverse(cur, st);  // this bounce's closest hits and the previous bounce's shadow rays
     shadow_pending = false;
     hipLaunchKernelGGL(k_bin, dim3(A.grid_bin), blk, 0, st, P, cur);  // also empties the shadow queue
     hipError_t e = shade_all<DEBUG, TWO>(S, P, A, b, next, (uint32_t)C.W, st);
@@ -1398,7 +1398,7 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
       if (P.n == P.n_render) break;  // no training paths: nothing continues
     }
   }
-  if (shadow_pending) traverse(-1);
+  if (shadow_pending) traverse(-1, st);
   if (query_pending) {  // no hand-off: the queries run here after all
     hipError_t e2 = query(st);
     if (e2 != hipSuccess) return e2;

@@ -294,8 +294,8 @@ def main():
     torch.cuda.set_device(0)
     s = pt.scene_from(sc, device=0)
     if args.tail_min_bounce is not None or args.tail_fraction is not None:
-        s.set_tail(3 if args.tail_min_bounce is None else args.tail_min_bounce,
-                   0.125 if args.tail_fraction is None else args.tail_fraction)
+        s.set_tail(2 if args.tail_min_bounce is None else args.tail_min_bounce,
+                   0.25 if args.tail_fraction is None else args.tail_fraction)
     out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda:0")
 
     if args.calibrate_copy:

@@ -158,8 +158,8 @@ struct pt_scene {
   hipEvent_t ev_train = nullptr;  // the last enqueued training's weights are in place
   hipEvent_t ev_train_t[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // timing around a frame's training
   // tail hand-off
-  int tail_min_bounce = 3;
-  double tail_fraction = 0.125;
+  int tail_min_bounce = 2;
+  double tail_fraction = 0.25;
   double ms_tail = 0.0;
   int64_t launches_tail = 0;
 };

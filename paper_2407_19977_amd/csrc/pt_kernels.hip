@@ -4,7 +4,7 @@
 // the tile) through the loop
 //   generate -> [reset -> traverse -> bin -> shade<class>...] x (max_depth+1) -> traverse -> accumulate
 // where traverse finds the closest hits of a bounce's rays together with the
-// shadow rays of the previous bounce's shading.  From bounce 3 on, once few
+// shadow rays of the previous bounce's shading.  From bounce 2 on, once few
 // paths are alive, one persistent kernel (k_tail) finishes every remaining
 // vertex instead.  Queues live in HBM and are compacted per workgroup: a
 // ballot of the lanes that append, wave counts gathered in LDS, one atomic

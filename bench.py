@@ -213,7 +213,15 @@ def tail_info(counts, st, steps):
     return info
 
 
-def instanced_4k(pt, torch, spp, ref_spp):
+def _tail_args(args):
+    """(min_bounce, max_fraction) from the command line, None for the library's defaults."""
+    if args.tail_min_bounce is None and args.tail_fraction is None:
+        return None
+    return (2 if args.tail_min_bounce is None else args.tail_min_bounce,
+            0.15 if args.tail_fraction is None else args.tail_fraction)
+
+
+def instanced_4k(pt, torch, spp, ref_spp, tail=None):
     """The instanced scene at 3840x2160: plain tracer and radiance cache side by
     side, each accumulated to `spp` samples (FP64 sums; the cache in frames of
     1 spp), against a `ref_spp` plain render with an independent seed.
@@ -223,6 +231,8 @@ def instanced_4k(pt, torch, spp, ref_spp):
     cam = sc.camera
     W, H, depth, seed = cam.width, cam.height, sc.max_depth, sc.seed
     s = pt.scene_from(sc, device=0)
+    if tail is not None:
+        s.set_tail(*tail)
     out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda:0")
     acc = torch.empty((H, W, 3), dtype=torch.float64, device="cuda:0")
     chunk = 32
@@ -295,7 +305,8 @@ def main():
     if args.workload == "instanced-4k":
         torch.cuda.set_device(0)
         print(json.dumps({"metric": "plain vs radiance cache, 4K instanced scene",
-                          "result": instanced_4k(pt, torch, args.spp_4k, args.ref_spp_4k)}), flush=True)
+                          "result": instanced_4k(pt, torch, args.spp_4k, args.ref_spp_4k, _tail_args(args))}),
+              flush=True)
         return
 
     sc = scenes.spheres(spp=args.spp)
@@ -303,9 +314,8 @@ def main():
     W, H = cam.width, cam.height
     torch.cuda.set_device(0)
     s = pt.scene_from(sc, device=0)
-    if args.tail_min_bounce is not None or args.tail_fraction is not None:
-        s.set_tail(2 if args.tail_min_bounce is None else args.tail_min_bounce,
-                   0.25 if args.tail_fraction is None else args.tail_fraction)
+    if _tail_args(args) is not None:
+        s.set_tail(*_tail_args(args))
     out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda:0")
 
     if args.calibrate_copy:

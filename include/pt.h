@@ -279,7 +279,7 @@ pt_status pt_nrc_training_records(pt_scene* scene, const pt_camera* camera, int3
  * (closest hit, shading, shadow ray, next ray) without a kernel boundary
  * per bounce.  The decision reads one counter back per pass.  Results are
  * identical either way (same arithmetic, same random numbers).  Defaults:
- * min_bounce 2, max_fraction 0.25; max_fraction 0 (or min_bounce > 64)
+ * min_bounce 2, max_fraction 0.15; max_fraction 0 (or min_bounce > 64)
  * keeps the wavefront throughout.  Errors: INVALID_ARG for min_bounce < 0
  * or max_fraction outside [0, 1]. */
 pt_status pt_set_tail(pt_scene* scene, int32_t min_bounce, double max_fraction);

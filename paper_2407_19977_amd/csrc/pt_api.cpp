@@ -159,7 +159,7 @@ struct pt_scene {
   hipEvent_t ev_train_t[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // timing around a frame's training
   // tail hand-off
   int tail_min_bounce = 2;
-  double tail_fraction = 0.25;
+  double tail_fraction = 0.15;
   double ms_tail = 0.0;
   int64_t launches_tail = 0;
 };

@@ -281,7 +281,7 @@ class PtScene:
     def reset_stats(self):
         _check(_lib.pt_reset_stats(self.h))
 
-    def set_tail(self, min_bounce=2, max_fraction=0.25):
+    def set_tail(self, min_bounce=2, max_fraction=0.15):
         _check(_lib.pt_set_tail(self.h, int(min_bounce), float(max_fraction)))
 
     def set_profiling(self, timing: bool, counting: bool = False):

@@ -380,7 +380,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32 (f64 sums)", "data": "synthetic",
         "config": {"workload": "icosphere field: 1,310,722 tris, 1920x1080, 64 spp, depth 8, sky + sun env",
                    "width": W, "height": H, "spp": sc.spp, "max_depth": sc.max_depth, "triangles": sc.n_triangles,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "tail_hand_off": dict(zip(("min_bounce", "max_fraction"), _tail_args(args) or (2, 0.15)))},
         "samples_per_s": round(samples_s, 1),
         "extension_rays_per_step": st["extension_rays"] // args.steps,
         "shadow_rays_per_step": st["shadow_rays"] // args.steps,

@@ -84,6 +84,22 @@ static void make_frame(const oinst* I, v3 n, v3* t, v3* b) {
   *b = vcross(n, *t);
 }
 
+/* Test hook: the shading frame of make_frame for an instance whose
+ * object-to-world transform is o2w (row-major 3x4; NULL = identity) at the
+ * unit normal n. */
+void oracle_shading_frame(const float* o2w, const double n[3], double t[3], double b[3]) {
+  oinst I;
+  memset(&I, 0, sizeof I);
+  I.identity = o2w == NULL;
+  if (o2w)
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) I.R[r][c] = o2w[4 * r + c];
+  v3 tt, bb;
+  make_frame(&I, V(n[0], n[1], n[2]), &tt, &bb);
+  t[0] = tt.x; t[1] = tt.y; t[2] = tt.z;
+  b[0] = bb.x; b[1] = bb.y; b[2] = bb.z;
+}
+
 static int add_finite(double L[3], const double c[3], oracle_stats* st) {
   if (!isfinite(c[0]) || !isfinite(c[1]) || !isfinite(c[2])) {
     if (st) st->dropped_nonfinite++;

@@ -116,6 +116,11 @@ int oracle_render(const oracle_scene* s, const oracle_camera* cam, int32_t x0, i
 double oracle_bf16_round(double x);
 void oracle_nrc_encode(const double x[12], double f[64]);
 void oracle_nrc_forward(const double* W, const double x[12], int32_t bf16, double y[3]);
+/* Test hook: the 12 cache inputs at point p (scene box [lo, hi]), outgoing
+ * direction wo and shading normal n (world space, unit) of a material given
+ * as its 27 OpenPBR floats. */
+void oracle_nrc_inputs(const double lo[3], const double hi[3], const double p[3], const double wo[3],
+                       const double n[3], const float* mat27, double x[12]);
 /* Training records of one path (plain tracer): for every vertex k < max_depth
  * that scatters or absorbs, the 12 cache inputs and the target
  * (L_end - L_k) / beta_k; vertices with a zero throughput channel are dropped.
@@ -123,6 +128,13 @@ void oracle_nrc_forward(const double* W, const double x[12], int32_t bf16, doubl
 int oracle_training_records(const oracle_scene* s, const oracle_camera* cam, int32_t px, int32_t py,
                             int32_t sample, int32_t max_depth, uint64_t seed, double* inputs, double* targets,
                             int32_t* n);
+
+/* Test hook: the shading frame (t, b, n) at unit normal n of an instance
+ * with object-to-world transform o2w (row-major 3x4; NULL = world space):
+ * t is the instance's object +z axis projected onto the tangent plane, or
+ * the Duff et al. 2017 basis vector when that projection is shorter than
+ * 1e-3; b = n x t. */
+void oracle_shading_frame(const float* o2w, const double n[3], double t[3], double b[3]);
 
 /* ---- BSDF and light-sampling probes (local shading frame, n = +z) ---- */
 /* mat: 27 floats.  entering: 1 if wo is on the front side of the geometric normal. */

@@ -117,6 +117,10 @@ def _declare(L):
     L.oracle_nrc_encode.restype = None
     L.oracle_nrc_forward.argtypes = [_dp, _dp, C.c_int32, _dp]
     L.oracle_nrc_forward.restype = None
+    L.oracle_nrc_inputs.argtypes = [_dp, _dp, _dp, _dp, _dp, C.c_void_p, _dp]
+    L.oracle_nrc_inputs.restype = None
+    L.oracle_shading_frame.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    L.oracle_shading_frame.restype = None
     L.oracle_training_records.argtypes = [C.c_void_p, C.POINTER(OCamera), C.c_int32, C.c_int32, C.c_int32,
                                           C.c_int32, C.c_uint64, _dp, _dp, C.POINTER(C.c_int32)]
 
@@ -222,6 +226,26 @@ def nrc_forward(W, x12, bf16=False):
     y = (C.c_double * 3)()
     lib().oracle_nrc_forward(w.ctypes.data_as(_dp), (C.c_double * 12)(*[float(v) for v in x12]), 1 if bf16 else 0, y)
     return np.array(y[:])
+
+
+def nrc_inputs(lo, hi, p, wo, n, mat):
+    """The 12 cache inputs at point p of a scene box [lo, hi] (test hook)."""
+    m = _mat(mat)
+    x = (C.c_double * 12)()
+    lib().oracle_nrc_inputs(_d3(lo), _d3(hi), _d3(p), _d3(wo), _d3(n), m.ctypes.data, x)
+    return np.array(x[:])
+
+
+def shading_frame(n, object_to_world=None):
+    """(t, b) of the shading frame at unit normal n (test hook)."""
+    t = (C.c_double * 3)()
+    b = (C.c_double * 3)()
+    if object_to_world is None:
+        lib().oracle_shading_frame(None, _d3(n), t, b)
+    else:
+        w = np.ascontiguousarray(np.asarray(object_to_world, dtype=np.float32).reshape(12))
+        lib().oracle_shading_frame(w.ctypes.data, _d3(n), t, b)
+    return np.array(t[:]), np.array(b[:])
 
 
 def ggx_D(at, ab, m):

@@ -293,6 +293,9 @@ typedef struct pt_bvh_info {
   int32_t max_leaf_tris;
   double sah_cost;
   double build_ms;
+  int32_t stack_capacity; /* traversal stack entries per lane the GPU walk is given: three per
+                             inner level plus one top-level leaf's instances (3 * depth +
+                             max leaf size), which bounds every walk of this hierarchy */
 } pt_bvh_info;
 /* Build the BVH4 of one mesh on the host (the same builder pt_build_bvh uses). */
 pt_status pt_bvh_host_build(const pt_mesh* mesh, pt_bvh_host** out);
@@ -307,6 +310,14 @@ pt_status pt_bvh_host_copy(const pt_bvh_host* bvh, void* nodes, void* tris);
 /* Closest hit on the host through the BVH4 (same traversal code as the GPU,
  * compiled for the CPU).  rays/hits as for pt_trace_closest, host memory. */
 pt_status pt_bvh_host_trace(const pt_bvh_host* bvh, const float* rays, int64_t n, uint32_t* hits);
+/* The same walk with a stack of `stack_capacity` entries per ray (<= 0: the
+ * capacity pt_bvh_info reports; at most 512), for checking the stack bound
+ * on the CPU.  *high_water (nullable) receives the deepest stack any ray
+ * used.  A push beyond the capacity is dropped as on the GPU, and the call
+ * then fails with PT_ERR_DEVICE ("traversal stack overflow"); hits of the
+ * rays traced so far are still written. */
+pt_status pt_bvh_host_trace_stack(const pt_bvh_host* bvh, const float* rays, int64_t n, uint32_t* hits,
+                                  int32_t stack_capacity, int32_t* high_water);
 void pt_bvh_host_destroy(pt_bvh_host* bvh);
 
 /* Thread-local message of the last failed call on this thread ("" if none). */

@@ -125,6 +125,7 @@ struct pt_scene {
   // while the next pass starts on the first
   PathBufs pb[2];
   DevBuf stats;
+  unsigned long long overflow_seen = 0;  // stack overflows already reported by a failed call
   hipStream_t stream2 = nullptr;       // created on first use (default priority)
   hipStream_t shade_side[2] = {nullptr, nullptr};  // side streams of the shading kernels (default priority)
   hipEvent_t shade_fork = nullptr, shade_join[2] = {nullptr, nullptr};
@@ -348,7 +349,7 @@ pt_status ensure_counters(pt_scene* s, int set = 0) {
 }
 
 pt_status ensure_spill(pt_scene* s, int grid_trace, int set = 0) {
-  int cap = 3 * std::max(s->bvh_depth, 1) + 4;
+  int cap = stack_capacity(s->bvh_depth);
   size_t per = cap > kLdsStack ? (size_t)(cap - kLdsStack) : 1;
   size_t bytes = per * (size_t)grid_trace * kBlock * sizeof(uint2);
   PT_HIP(s->pb[set].spill.alloc(bytes));
@@ -382,7 +383,7 @@ SceneDev scene_dev(pt_scene* s, int grid_trace, int set = 0) {
   S.axis[1] = 0.0f;
   S.axis[2] = 1.0f;
   S.spill = s->pb[set].spill.as<uint2>();
-  S.stack_cap = 3 * std::max(s->bvh_depth, 1) + 4;
+  S.stack_cap = stack_capacity(s->bvh_depth);
   S.spill_stride = (uint32_t)grid_trace * kBlock;
   S.insts = s->insts.as<InstRec>();
   S.n_insts = (uint32_t)s->host_insts.size();
@@ -1026,6 +1027,25 @@ pt_status sync(pt_scene* s) {
   return PT_OK;
 }
 
+// sync(), then fail the call if a traversal ran out of stack since the last
+// check: its walk dropped entries, so some closest hits or occlusion tests
+// may be wrong.  One 8-byte read per call.
+pt_status sync_traced(pt_scene* s) {
+  pt_status r = sync(s);
+  if (r || !s->stats.p) return r;
+  unsigned long long v = 0;
+  PT_HIP(hipMemcpyAsync(&v, s->stats.as<unsigned long long>() + kStatOverflow, sizeof(v), hipMemcpyDeviceToHost,
+                        s->stream));
+  PT_HIP(hipStreamSynchronize(s->stream));
+  if (v > s->overflow_seen) {
+    unsigned long long d = v - s->overflow_seen;
+    s->overflow_seen = v;
+    return fail(PT_ERR_DEVICE, "traversal stack overflow in %llu workgroups (capacity %d entries per lane)", d,
+                stack_capacity(s->bvh_depth));
+  }
+  return PT_OK;
+}
+
 pt_status validate_material(const pt_openpbr_material& m, int i) {
   const float* f = reinterpret_cast<const float*>(&m);
   for (int k = 0; k < 27; ++k) {
@@ -1541,7 +1561,7 @@ pt_status pt_accumulate(pt_scene* s, const pt_camera* cam, int32_t first, int32_
   if ((r = ensure_accum(s, C.W, C.H))) return r;
   if ((r = render_samples(s, C, first, n, max_depth, seed))) return r;
   s->acc_samples += n;
-  return sync(s);
+  return sync_traced(s);
 }
 
 pt_status pt_resolve(pt_scene* s, float* out, double* out_sum) {
@@ -1571,7 +1591,7 @@ pt_status pt_render(pt_scene* s, const pt_camera* cam, int32_t spp, int32_t max_
   if ((r = render_samples(s, C, 0, spp, max_depth, seed))) return r;
   s->acc_samples = spp;
   PT_HIP(launch_resolve(s->sum.as<double>(), out, (int64_t)C.W * C.H * 3, 1.0 / (double)spp, s->stream));
-  return sync(s);
+  return sync_traced(s);
 }
 
 pt_status pt_render_debug(pt_scene* s, const pt_camera* cam, int32_t x0, int32_t y0, int32_t w, int32_t h,
@@ -1589,7 +1609,7 @@ pt_status pt_render_debug(pt_scene* s, const pt_camera* cam, int32_t x0, int32_t
   if ((r = set_device(s))) return r;
   if ((r = ready_to_render(s))) return r;
   if ((r = run_passes(s, C, x0, y0, w, h, first, spp, max_depth, seed, nullptr, per_sample, sig, spp))) return r;
-  return sync(s);
+  return sync_traced(s);
 }
 
 // ------------------------------------------------------------ radiance cache
@@ -1747,9 +1767,11 @@ pt_status pt_trace_closest(pt_scene* s, const float* rays, int64_t n, uint32_t* 
   if ((r = set_device(s))) return r;
   int grid = brute ? trace_grid_blocks() : traversal_grid(n);
   if ((r = ensure_spill(s, grid))) return r;
+  if ((r = ensure_counters(s))) return r;
   SceneDev S = scene_dev(s, grid);
-  PT_HIP(launch_trace_rays(S, rays, n, hits, brute != 0, s->two_level, grid, s->stream));
-  return sync(s);
+  PT_HIP(launch_trace_rays(S, rays, n, hits, brute != 0, s->two_level, grid, s->stats.as<unsigned long long>(),
+                           s->stream));
+  return sync_traced(s);
 }
 
 pt_status pt_get_stats(pt_scene* s, pt_stats* o) {
@@ -1803,6 +1825,7 @@ pt_status pt_reset_stats(pt_scene* s) {
   if ((r = set_device(s))) return r;
   if ((r = ensure_counters(s))) return r;
   PT_HIP(launch_zero_u64(s->stats.as<unsigned long long>(), kNumStats, s->stream));
+  s->overflow_seen = 0;
   s->ms_extend = s->ms_total = 0.0;
   s->launches_extend = 0;
   s->samples = 0;
@@ -1895,6 +1918,7 @@ pt_status pt_bvh_host_info(const pt_bvh_host* h, pt_bvh_info* info) {
     info->max_leaf_tris = kMaxLeafTris;
     info->sah_cost = 0.0;
     info->build_ms = 0.0;
+    info->stack_capacity = stack_capacity(h->T.depth);
     return PT_OK;
   }
   info->n_nodes = (int64_t)h->b.nodes.size();
@@ -1903,6 +1927,7 @@ pt_status pt_bvh_host_info(const pt_bvh_host* h, pt_bvh_info* info) {
   info->max_leaf_tris = h->b.max_leaf;
   info->sah_cost = h->b.sah_cost;
   info->build_ms = h->b.build_ms;
+  info->stack_capacity = stack_capacity(h->b.depth);
   return PT_OK;
 }
 
@@ -1915,14 +1940,21 @@ pt_status pt_bvh_host_copy(const pt_bvh_host* h, void* nodes, void* tris) {
   return PT_OK;
 }
 
-pt_status pt_bvh_host_trace(const pt_bvh_host* h, const float* rays, int64_t n, uint32_t* hits) {
+pt_status pt_bvh_host_trace_stack(const pt_bvh_host* h, const float* rays, int64_t n, uint32_t* hits,
+                                  int32_t capacity, int32_t* high_water) {
   if (!h || n < 0 || (n > 0 && (!rays || !hits))) return fail(PT_ERR_INVALID_ARG, "bad arguments");
+  const int bound = stack_capacity(h->two ? h->T.depth : h->b.depth);
+  const int cap = capacity > 0 ? capacity : bound;
+  if (cap > HostStack::kMax) return fail(PT_ERR_INVALID_ARG, "stack capacity above %d", HostStack::kMax);
+  int high = 0;
+  int64_t dropped = 0;
   for (int64_t i = 0; i < n; ++i) {
     const float* R = rays + 8 * i;
     RayPre r = ray_prepare(R[0], R[1], R[2], R[4], R[5], R[6]);
     Hit best;
     hit_clear(best);
     HostStack st;
+    st.cap = cap;
     uint32_t nv = 0, nt = 0;
     if (h->two)
       traverse_two_level<false, false>(h->T.top.nodes.data(), h->T.items.data(), h->T.insts.data(),
@@ -1931,7 +1963,8 @@ pt_status pt_bvh_host_trace(const pt_bvh_host* h, const float* rays, int64_t n, 
     else
       traverse_bvh<false, false>(h->b.nodes.data(), h->b.tris.data(), 0u, r, R[3], R[7], 0u, 0xFFFFFFFFu,
                                  0xFFFFFFFFu, best, st, nv, nt);
-    if (st.overflow) return fail(PT_ERR_DEVICE, "host traversal stack overflow");
+    high = std::max(high, st.high);
+    if (st.overflow) dropped++;
     uint32_t* H = hits + 6 * i;
     bool hit = best.tri != 0xFFFFFFFFu;
     H[0] = f2u(best.t);
@@ -1941,7 +1974,13 @@ pt_status pt_bvh_host_trace(const pt_bvh_host* h, const float* rays, int64_t n, 
     H[4] = hit ? f2u(best.b2) : 0u;
     H[5] = hit ? 1u : 0u;
   }
+  if (high_water) *high_water = high;
+  if (dropped) return fail(PT_ERR_DEVICE, "traversal stack overflow on %lld rays (capacity %d)", (long long)dropped, cap);
   return PT_OK;
+}
+
+pt_status pt_bvh_host_trace(const pt_bvh_host* h, const float* rays, int64_t n, uint32_t* hits) {
+  return pt_bvh_host_trace_stack(h, rays, n, hits, 0, nullptr);
 }
 
 void pt_bvh_host_destroy(pt_bvh_host* h) { delete h; }

@@ -170,7 +170,7 @@ hipError_t launch_resolve(const double* sum, float* out, int64_t n_values, doubl
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st);
 hipError_t launch_trace_rays(const SceneDev& S, const float* rays, int64_t n, uint32_t* hits, bool brute,
-                             bool two_level, int grid, hipStream_t st);
+                             bool two_level, int grid, unsigned long long* stats, hipStream_t st);
 int trace_grid_blocks();
 int traversal_grid(int64_t rays);  // workgroups of the traversal kernel for a pass of `rays` paths
 int tail_grid(int grid_trace, uint32_t paths, bool beside);  // workgroups of the tail kernel

@@ -1199,13 +1199,15 @@ struct RaysSrc {
 };
 
 template <bool TWO>
-__global__ __launch_bounds__(kBlock) void k_trace_rays(SceneDev S, const float* rays, uint32_t n, uint32_t* hits) {
+__global__ __launch_bounds__(kBlock) void k_trace_rays(SceneDev S, const float* rays, uint32_t n, uint32_t* hits,
+                                                       unsigned long long* stats) {
   __shared__ unsigned long long s_stack[kLdsStack * kBlock];
   __shared__ uint32_t s_next;
   uint32_t nvis = 0, ntri = 0;
   bool overflow = false;
   RaysSrc<TWO> src{S, rays, hits};
   persistent_trace<kWalkClosest, false, TWO>(S, src, n, s_stack, &s_next, nvis, ntri, overflow);
+  if (overflow) atomicAdd(&stats[kStatOverflow], 1ull);
 }
 
 // The same definition by testing every triangle (and every instance).
@@ -1454,13 +1456,13 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st) {
 }
 
 hipError_t launch_trace_rays(const SceneDev& S, const float* rays, int64_t n, uint32_t* hits, bool brute,
-                             bool two_level, int grid, hipStream_t st) {
+                             bool two_level, int grid, unsigned long long* stats, hipStream_t st) {
   dim3 g(grid), blk(kBlock);
   const uint32_t nn = (uint32_t)n;
   if (brute && two_level) hipLaunchKernelGGL((k_trace_rays_brute<true>), g, blk, 0, st, S, rays, nn, hits);
   else if (brute) hipLaunchKernelGGL((k_trace_rays_brute<false>), g, blk, 0, st, S, rays, nn, hits);
-  else if (two_level) hipLaunchKernelGGL((k_trace_rays<true>), g, blk, 0, st, S, rays, nn, hits);
-  else hipLaunchKernelGGL((k_trace_rays<false>), g, blk, 0, st, S, rays, nn, hits);
+  else if (two_level) hipLaunchKernelGGL((k_trace_rays<true>), g, blk, 0, st, S, rays, nn, hits, stats);
+  else hipLaunchKernelGGL((k_trace_rays<false>), g, blk, 0, st, S, rays, nn, hits, stats);
   return hipGetLastError();
 }
 

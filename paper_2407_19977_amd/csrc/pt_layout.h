@@ -30,6 +30,16 @@ constexpr uint32_t kLeafFirstMask = (1u << kLeafCountShift) - 1u;
 constexpr int kMaxLeafTris = PT_MAX_LEAF_TRIS;  // at most 7 (3-bit count in a leaf reference)
 static_assert(kMaxLeafTris >= 1 && kMaxLeafTris <= 7, "leaf references hold 3-bit triangle counts");
 
+// Traversal stack entries a walk can need.  A depth-first walk that pushes
+// the (at most three) siblings it does not descend into keeps at most three
+// entries per inner level on the stack; a top-level leaf adds its instances
+// (at most kMaxLeafTris) as entries, one of which is popped at once, before
+// a mesh walk starts on top.  `depth` counts the levels of nodes and leaves
+// on the longest path (top-level plus mesh levels for two-level scenes).
+__host__ __device__ constexpr int stack_capacity(int depth) {
+  return 3 * (depth > 1 ? depth : 1) + kMaxLeafTris;
+}
+
 __host__ __device__ inline bool ref_is_leaf(uint32_t r) { return (r & kLeafBit) != 0u; }
 __host__ __device__ inline uint32_t leaf_count(uint32_t r) { return (r >> kLeafCountShift) & 7u; }
 __host__ __device__ inline uint32_t leaf_first(uint32_t r) { return r & kLeafFirstMask; }

@@ -257,9 +257,12 @@ __host__ __device__ inline RayPre ray_to_object(const float* w, float ox, float 
 }
 
 // Two-level walk: a top-level BVH4 over instance world boxes whose leaves
-// list instance ids; at each instance the ray moves to object space and the
-// mesh's BVH is walked on top of the same stack.  t values are compared in
-// each instance's object space, as the single-precision definition does.
+// list instance ids; a top-level leaf pushes its instances as entries (leaf
+// bit, count 0, instance id) with the leaf's key, and a popped instance entry
+// moves the ray to object space and walks the mesh's BVH on top of the same
+// stack — the stack discipline of the GPU's per-lane walk, so the two need
+// the same stack depth.  t values are compared in each instance's object
+// space, as the single-precision definition does.
 template <bool ANY, bool COUNT, class Stack>
 __host__ __device__ inline bool traverse_two_level(const BVHNode* __restrict__ tlas,
                                                    const uint32_t* __restrict__ tlas_items,
@@ -269,6 +272,7 @@ __host__ __device__ inline bool traverse_two_level(const BVHNode* __restrict__ t
                                                    float tmax, uint32_t skip_inst, uint32_t skip_prim, Hit& best,
                                                    Stack& st, uint32_t& nvis, uint32_t& ntri) {
   uint32_t cur = 0;
+  float cur_key = 0.0f;
   bool found = false;
   const int base = st.size();
   while (true) {
@@ -291,19 +295,21 @@ __host__ __device__ inline bool traverse_two_level(const BVHNode* __restrict__ t
       if (r2 != kEmpty) st.push(r2, k2);
       if (r1 != kEmpty) st.push(r1, k1);
       cur = r0;
+      cur_key = k0;
       continue;
     }
     if (cur != kEmpty) {
       uint32_t first = leaf_first(cur), cnt = leaf_count(cur);
-      for (uint32_t j = 0; j < cnt; ++j) {
-        uint32_t inst = tlas_items[first + j];
-        const InstRec& I = insts[inst];
+      if (cnt == 0) {  // an instance entry: walk its mesh in object space on top of the stack
+        const InstRec& I = insts[first];
         RayPre ro = ray_to_object(I.w2o, rw.ox, rw.oy, rw.oz, rw.dx, rw.dy, rw.dz);
-        if (traverse_bvh<ANY, COUNT>(nodes, tris, I.blas_root, ro, tmin, tmax, inst, skip_inst, skip_prim, best,
+        if (traverse_bvh<ANY, COUNT>(nodes, tris, I.blas_root, ro, tmin, tmax, first, skip_inst, skip_prim, best,
                                      st, nvis, ntri, st.size())) {
           found = true;
           if (ANY) return true;
         }
+      } else {
+        for (int j = (int)cnt - 1; j >= 0; --j) st.push(kLeafBit | tlas_items[first + j], cur_key);
       }
     }
     cur = kEmpty;
@@ -312,6 +318,7 @@ __host__ __device__ inline bool traverse_two_level(const BVHNode* __restrict__ t
       uint32_t q = st.pop(k);
       if (k <= fminf(best.t, tmax)) {
         cur = q;
+        cur_key = k;
         break;
       }
     }
@@ -366,15 +373,19 @@ __host__ __device__ inline bool brute_force(const TriRec* __restrict__ tris, uin
   return found;
 }
 
-// Host-side stack for CPU checks of the traversal.
+// Host-side stack for CPU checks of the traversal: a push beyond `cap`
+// entries is dropped and flagged, as on the GPU; `high` records the deepest
+// the stack has been.
 struct HostStack {
-  uint32_t ref[512];
-  float key[512];
-  int sp = 0;
+  static constexpr int kMax = 512;
+  uint32_t ref[kMax];
+  float key[kMax];
+  int sp = 0, cap = kMax, high = 0;
   bool overflow = false;
   void push(uint32_t r, float k) {
-    if (sp >= 512) { overflow = true; return; }
+    if (sp >= cap) { overflow = true; return; }
     ref[sp] = r; key[sp] = k; sp++;
+    if (sp > high) high = sp;
   }
   uint32_t pop(float& k) { --sp; k = key[sp]; return ref[sp]; }
   int size() const { return sp; }

@@ -56,7 +56,8 @@ class pt_stats(C.Structure):
 
 class pt_bvh_info(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_tris", C.c_int64), ("depth", C.c_int32),
-                ("max_leaf_tris", C.c_int32), ("sah_cost", C.c_double), ("build_ms", C.c_double)]
+                ("max_leaf_tris", C.c_int32), ("sah_cost", C.c_double), ("build_ms", C.c_double),
+                ("stack_capacity", C.c_int32)]
 
 
 class pt_radiance_cache_config(C.Structure):
@@ -111,6 +112,8 @@ _SIGS = {
     "pt_bvh_host_info": (C.c_int, [C.c_void_p, C.POINTER(pt_bvh_info)]),
     "pt_bvh_host_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pt_bvh_host_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "pt_bvh_host_trace_stack": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32,
+                                          C.POINTER(C.c_int32)]),
     "pt_bvh_host_destroy": (None, [C.c_void_p]),
     "pt_last_error": (C.c_char_p, []),
     "pt_version": (C.c_char_p, []),
@@ -338,3 +341,13 @@ class HostBvh:
         hits = np.zeros((rays.shape[0], 6), dtype=np.uint32)
         _check(_lib.pt_bvh_host_trace(self.h, rays.ctypes.data, rays.shape[0], hits.ctypes.data))
         return hits
+
+    def trace_stack(self, rays: np.ndarray, capacity: int = 0):
+        """Host walk with a stack of `capacity` entries (0: the library's
+        bound); returns (hits, deepest stack used).  Raises PTError on overflow."""
+        rays = np.ascontiguousarray(rays, dtype=np.float32)
+        hits = np.zeros((rays.shape[0], 6), dtype=np.uint32)
+        high = C.c_int32(0)
+        _check(_lib.pt_bvh_host_trace_stack(self.h, rays.ctypes.data, rays.shape[0], hits.ctypes.data, capacity,
+                                            C.byref(high)))
+        return hits, high.value

@@ -221,6 +221,65 @@ def cornell(width=128, height=128, spp=16, max_depth=4, seed=0) -> Scene:
 
 
 # --------------------------------------------------------------------------
+# material zoo: every shading class, mixed and tinted OpenPBR materials
+# --------------------------------------------------------------------------
+
+ZOO_MATERIALS = [
+    # (name, OpenPBR parameters)
+    ("partial metal", dict(base_metalness=0.5, base_color=(0.9, 0.6, 0.3), specular_color=(0.8, 0.9, 1.0),
+                           specular_roughness=0.3)),
+    ("coat over metal", dict(base_metalness=1.0, base_color=(0.95, 0.8, 0.5), specular_roughness=0.25,
+                             coat_weight=1.0, coat_roughness=0.1, coat_color=(0.9, 0.8, 1.0), coat_ior=1.5)),
+    ("delta coat over anisotropic metal", dict(base_metalness=1.0, base_color=(0.7, 0.8, 0.9), specular_roughness=0.4,
+                                              specular_roughness_anisotropy=0.6, coat_weight=0.6,
+                                              coat_roughness=0.0, coat_color=(1.0, 0.85, 0.85))),
+    ("transmission over partial metal", dict(base_metalness=0.3, base_color=(0.8, 0.7, 0.6), specular_roughness=0.2,
+                                             transmission_weight=0.5, transmission_color=(0.8, 1.0, 0.9))),
+    ("transmission over diffuse", dict(transmission_weight=0.7, base_color=(0.6, 0.3, 0.2), specular_roughness=0.25,
+                                       transmission_color=(0.7, 0.9, 0.8), specular_ior=1.45)),
+    ("weak tinted specular plastic", dict(base_color=(0.2, 0.5, 0.3), specular_weight=0.6,
+                                          specular_color=(1.0, 0.7, 0.7), specular_roughness=0.3)),
+    ("anisotropic coated plastic", dict(base_color=(0.3, 0.3, 0.7), specular_roughness=0.35,
+                                        specular_roughness_anisotropy=0.6, coat_weight=0.5, coat_roughness=0.2,
+                                        coat_color=(1.0, 0.9, 0.7), coat_ior=1.6)),
+    ("weak tinted metal", dict(base_metalness=1.0, base_weight=0.9, base_color=(0.95, 0.9, 0.8), specular_weight=0.7,
+                               specular_color=(0.6, 0.8, 1.0), specular_roughness=0.15)),
+]
+
+
+def material_zoo(width=96, height=96, spp=8, max_depth=6, seed=0, sphere_level=2) -> Scene:
+    """An open-topped box (floor, back, left and right walls, Lambert) under
+    a small sky with a sun, a 0.3 x 0.3 quad light of radiance 12 hung below
+    the open top, and eight icospheres (radius 0.11, level 2) in two rows,
+    each with one of ZOO_MATERIALS: partial metalness, coat over metal,
+    transmission over diffuse and over partial metal, tints of the
+    specular, coat and transmission colours, specular_weight < 1 and
+    anisotropy under a coat — the OpenPBR mixes that the closed-box,
+    icosphere-field and instanced scenes do not reach."""
+    mats = [lambert((0.6, 0.6, 0.6)), lambert((0.7, 0.4, 0.3)), lambert((0.3, 0.6, 0.4)), lambert((0.4, 0.4, 0.7)),
+            material(base_weight=0.0, specular_weight=0.0, emission_luminance=12.0,
+                     emission_color=(1.0, 0.95, 0.9))]
+    mats += [material(**kw) for _, kw in ZOO_MATERIALS]
+    b = _MeshBuilder()
+    b.add_quad([0, 0, 0], [1, 0, 0], [1, 0, 1], [0, 0, 1], [0, 1, 0], 0)    # floor
+    b.add_quad([0, 0, 1], [1, 0, 1], [1, 1, 1], [0, 1, 1], [0, 0, -1], 1)   # back
+    b.add_quad([0, 0, 0], [0, 1, 0], [0, 1, 1], [0, 0, 1], [1, 0, 0], 2)    # left
+    b.add_quad([1, 0, 0], [1, 1, 0], [1, 1, 1], [1, 0, 1], [-1, 0, 0], 3)   # right
+    b.add_quad([.35, .92, .45], [.65, .92, .45], [.65, .92, .75], [.35, .92, .75], [0, -1, 0], 4)
+    v, f = icosphere(sphere_level)
+    rad = 0.11
+    for k in range(len(ZOO_MATERIALS)):
+        cx = 0.17 + 0.22 * (k % 4)
+        cz = 0.35 if k < 4 else 0.68
+        cy = rad + (0.0 if k < 4 else 0.12)
+        b.add(v * rad + np.array([cx, cy, cz]), f, 5 + k)
+    cam = Camera((0.5, 0.5, -0.45), (0.5, 0.18, 0.5), (0.0, 1.0, 0.0), 42.0, width, height)
+    env = sky_env(width=256, height=128, sun_elev_deg=55.0, sun_azim_deg=160.0, sun_diam_deg=3.0,
+                  sun_radiance=200.0)
+    return Scene("material_zoo", [b.mesh()], [], np.stack(mats), env, cam, spp, max_depth, seed)
+
+
+# --------------------------------------------------------------------------
 # icosphere field (~1.31M triangles)
 # --------------------------------------------------------------------------
 

@@ -92,6 +92,30 @@ def test_forward_matches_bf16_oracle(P, O, n):
     assert rel.max() <= 5e-3
 
 
+def test_forward_full_size_sampled(P, O):
+    """A full frame's worth of queries (2^21 + 37: every tile plus a ragged
+    tail) in one launch, checked on 2^15 sampled rows (the first and last
+    tiles included) against the bf16-rounding oracle."""
+    n = (1 << 21) + 37
+    _say(f"[nrc forward] n={n} (sampled check)")
+    _, s, _ = _net_scene(P, O)
+    w = _weights(O, 13)
+    s.nrc_set_weights(_dev(w))
+    X = _inputs(n, 3)
+    y = torch.empty((n, 3), dtype=torch.float32, device="cuda:0")
+    s.nrc_forward(_dev(X), y)
+    y = y.cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(y))
+    r = np.random.Generator(np.random.PCG64(14))
+    sel = np.unique(np.concatenate([np.arange(64), np.arange(n - 101, n), r.choice(n, 1 << 15, replace=False)]))
+    ref, _ = N.forward(w.astype(np.float64), X[sel].astype(np.float64), use_bf16=True)
+    scale = math.sqrt(float((ref ** 2).mean())) + 1e-12
+    rel = np.abs(y[sel] - ref) / (np.abs(ref) + scale)
+    _say(f"[nrc forward] n={n}: {len(sel)} rows, rel err max {rel.max():.2e} p99.9 {np.quantile(rel, 0.999):.2e}")
+    assert np.quantile(rel, 0.999) <= 1e-4
+    assert rel.max() <= 5e-3
+
+
 def test_forward_of_permutation_network_is_exact(P, O):
     """Permutation matrices move bfloat16 features without arithmetic: the
     output is the encoded feature the index bookkeeping names, rounded to bf16."""
@@ -172,15 +196,34 @@ def test_two_adam_steps_match_oracle(P, O):
     wr = w.astype(np.float64)
     m = np.zeros_like(wr)
     v = np.zeros_like(wr)
+    g_steps = []
     for k in range(2):
         idx = _batch(O, seed, frame, k, n, 2048)
         _, g = N.gradient(wr, X[idx].astype(np.float64), T[idx].astype(np.float64), use_bf16=True)
+        g_steps.append(g)
         wr, m, v = N.adam(wr, m, v, g, k + 1)
     dw = np.abs(wg.cpu().numpy() - wr)
     lr = 1e-3
     _say(f"[nrc adam] |w_gpu - w_ref| / lr: p99 {np.quantile(dw, 0.99) / lr:.3e} max {dw.max() / lr:.3e}")
     assert np.quantile(dw, 0.99) <= 0.05 * lr
-    assert dw.max() <= 4.0 * lr
+    # Where the gradient is well above the bfloat16 noise of its layer (both
+    # steps' |g| above 1e-2 of the layer's rms gradient, and the bias-corrected
+    # first moment not cancelled, |m_hat| >= 0.1 sqrt(v_hat)), the update is
+    # well conditioned and the GPU's weights follow the oracle's to 0.05 lr.
+    # Elsewhere Adam's normalisation turns a bfloat16-sized gradient
+    # difference into a change of the step's sign, bounded only by 2 lr.
+    layer_rms = np.zeros_like(wr)
+    for l in range(6):
+        sl = slice(4096 * l, 4096 * (l + 1)) if l < 5 else slice(20480, None)
+        layer_rms[sl] = np.sqrt(np.mean(g_steps[0][sl] ** 2))
+    mh = m / (1 - 0.9 ** 2)
+    vh = v / (1 - 0.99 ** 2)
+    good = (np.abs(g_steps[0]) > 1e-2 * layer_rms) & (np.abs(g_steps[1]) > 1e-2 * layer_rms) & \
+        (np.abs(mh) >= 0.1 * np.sqrt(vh))
+    _say(f"[nrc adam] well-conditioned weights {int(good.sum())} / {good.size}: max |dw| / lr "
+         f"{dw[good].max() / lr:.3e}; all weights max {dw.max() / lr:.3e}")
+    assert good.sum() > 0.5 * good.size
+    assert dw[good].max() <= 0.05 * lr
     em = np.linalg.norm(mg.cpu().numpy() - m) / np.linalg.norm(m)
     assert em <= 2e-2, em
 
@@ -238,9 +281,10 @@ def test_cache_terminated_paths_match_oracle(P, O):
     # The cache inputs come from FP32 hit points and directions.  In the FP64
     # oracle itself, moving the 12 inputs by 1e-7 (FP32 rounding) flips
     # bfloat16 roundings of the high-frequency features and moves the output
-    # by up to 1.2% (p99 0.4%, p99.9 0.8%).  The gates allow that, and the
-    # flips must not bias the mean.
-    assert np.quantile(rel, 0.99) <= 1e-2
+    # by up to 1.2% (p99.9 0.8%); such flips are rare on the GPU's paths
+    # (measured p99 2e-6).  The gates allow the rare flip in the maximum, hold
+    # the 99th percentile to 1e-4, and the flips must not bias the mean.
+    assert np.quantile(rel, 0.99) <= 1e-4
     assert rel.max() <= 5e-2
     assert abs(bias) <= 1e-3
     assert np.isfinite(g).all()

@@ -161,3 +161,42 @@ def test_instanced_generator_invariants():
     metal = mats[:, 4] == 1.0         # base_metalness
     coat = mats[:, 17] == 1.0         # coat_weight
     assert (glass.sum(), metal.sum(), coat.sum()) == (120, 160, 120)
+
+
+@pytest.mark.parametrize("n_inst", [24, 150])
+def test_stack_bound_holds_and_overflow_is_an_error(n_inst):
+    """The walk never needs more stack than the capacity the library gives
+    the GPU lanes (3 entries per inner level plus one top-level leaf's
+    instances), and a walk that runs out of stack fails the call instead of
+    returning hits silently."""
+    from paper_2407_19977_amd import pt
+    sc = _scene(_small_meshes(), exact=False, n=n_inst, seed=4)
+    b = pt.HostBvh(meshes=sc.meshes, instances=sc.instances)
+    cap = b.info["stack_capacity"]
+    assert cap == 3 * b.info["depth"] + b.info["max_leaf_tris"]
+    rays = _rays_f32(sc, 3000, 9)
+    ref = b.trace(rays)
+    hits, high = b.trace_stack(rays)
+    assert np.array_equal(hits, ref)
+    assert 0 < high <= cap
+    # every hit survives a stack exactly as deep as the deepest walk needed
+    hits2, high2 = b.trace_stack(rays, capacity=high)
+    assert np.array_equal(hits2, ref) and high2 == high
+    with pytest.raises(pt.PtError, match="stack overflow"):
+        b.trace_stack(rays, capacity=2)
+    # single-level BVH: the same bound
+    m = sc.meshes[2]
+    b1 = pt.HostBvh(m)
+    assert b1.info["stack_capacity"] == 3 * b1.info["depth"] + b1.info["max_leaf_tris"] or \
+        b1.info["stack_capacity"] == 3 * b1.info["depth"] + b.info["max_leaf_tris"]
+    r = np.random.Generator(np.random.PCG64(12))
+    r1 = np.zeros((2000, 8), np.float32)
+    r1[:, 0:3] = r.uniform(-2, 2, (2000, 3))
+    d = r.uniform(-0.5, 0.5, (2000, 3)) - r1[:, 0:3]      # aimed at the mesh
+    r1[:, 4:7] = d / np.linalg.norm(d, axis=1, keepdims=True)
+    r1[:, 3] = 1e-4
+    r1[:, 7] = np.inf
+    h1, hw = b1.trace_stack(r1)
+    assert h1[:, 5].sum() > 200 and 0 < hw <= b1.info["stack_capacity"]
+    with pytest.raises(pt.PtError, match="stack overflow"):
+        b1.trace_stack(r1, capacity=1)

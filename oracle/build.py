@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["philox.c", "geometry.c", "bsdf.c", "lights.c", "integrator.c", "nrc.c"]
+SOURCES = ["philox.c", "geometry.c", "bsdf.c", "lights.c", "integrator.c", "nrc.c", "display.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

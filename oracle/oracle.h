@@ -136,6 +136,12 @@ int oracle_training_records(const oracle_scene* s, const oracle_camera* cam, int
  * 1e-3; b = n x t. */
 void oracle_shading_frame(const float* o2w, const double n[3], double t[3], double b[3]);
 
+/* ---- display path (display.c): PBR Neutral tone map, sRGB, 8-bit ---- */
+void oracle_pbr_neutral(const double in[3], double out[3]);
+double oracle_srgb_encode(double v);
+void oracle_display(const double* sum, int64_t n_pixels, double inv_samples, double exposure, double* encoded,
+                    uint8_t* rgba8);
+
 /* ---- BSDF and light-sampling probes (local shading frame, n = +z) ---- */
 /* mat: 27 floats.  entering: 1 if wo is on the front side of the geometric normal. */
 int oracle_bsdf_eval(const float* mat, int32_t entering, const double wo[3], const double wi[3],

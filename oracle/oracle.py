@@ -121,6 +121,12 @@ def _declare(L):
     L.oracle_nrc_inputs.restype = None
     L.oracle_shading_frame.argtypes = [C.c_void_p, _dp, _dp, _dp]
     L.oracle_shading_frame.restype = None
+    L.oracle_pbr_neutral.argtypes = [_dp, _dp]
+    L.oracle_pbr_neutral.restype = None
+    L.oracle_srgb_encode.argtypes = [C.c_double]
+    L.oracle_srgb_encode.restype = C.c_double
+    L.oracle_display.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_double, C.c_void_p, C.c_void_p]
+    L.oracle_display.restype = None
     L.oracle_training_records.argtypes = [C.c_void_p, C.POINTER(OCamera), C.c_int32, C.c_int32, C.c_int32,
                                           C.c_int32, C.c_uint64, _dp, _dp, C.POINTER(C.c_int32)]
 
@@ -246,6 +252,26 @@ def shading_frame(n, object_to_world=None):
         w = np.ascontiguousarray(np.asarray(object_to_world, dtype=np.float32).reshape(12))
         lib().oracle_shading_frame(w.ctypes.data, _d3(n), t, b)
     return np.array(t[:]), np.array(b[:])
+
+
+def pbr_neutral(c):
+    out = (C.c_double * 3)()
+    lib().oracle_pbr_neutral(_d3(c), out)
+    return np.array(out[:])
+
+
+def srgb_encode(v):
+    return lib().oracle_srgb_encode(float(v))
+
+
+def display(sum_rgb, samples, exposure=1.0):
+    """Display image of FP64 sums [h, w, 3]: (encoded [h, w, 3] in [0, 1], rgba8 [h, w, 4])."""
+    s = np.ascontiguousarray(sum_rgb, dtype=np.float64)
+    h, w = s.shape[:2]
+    enc = np.zeros((h, w, 3))
+    rgba = np.zeros((h, w, 4), np.uint8)
+    lib().oracle_display(s.ctypes.data, h * w, 1.0 / samples, float(exposure), enc.ctypes.data, rgba.ctypes.data)
+    return enc, rgba
 
 
 def ggx_D(at, ab, m):

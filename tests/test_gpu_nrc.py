@@ -3,8 +3,10 @@
 * Network: the matrix-core forward and gradient against the FP64 numpy
   oracle that rounds the same operands to bfloat16.  Emulating the GPU's
   FP32 sums in numpy puts 99.9% of outputs within 1e-5 of |y| + rms(y) and
-  the worst at 2e-3 (a bfloat16 rounding flip of a hidden activation
-  carried to the output); the gates are 1e-4 for 99.9% and 5e-3 for all.
+  the worst at 2e-3 on 4099 rows, 1.5e-2 on the 32,933 rows of the
+  full-size check (a bfloat16 rounding flip of a hidden activation carried
+  to the output); the gates are 1e-4 for 99.9% and 5e-3 (3e-2 on the
+  full-size rows) for all.
 * Adam: two steps on batches drawn by the documented Philox rule, against
   the oracle's Adam on the oracle's own gradients.
 * Paths: render paths that end in the cache carry the same event signature
@@ -113,7 +115,10 @@ def test_forward_full_size_sampled(P, O):
     rel = np.abs(y[sel] - ref) / (np.abs(ref) + scale)
     _say(f"[nrc forward] n={n}: {len(sel)} rows, rel err max {rel.max():.2e} p99.9 {np.quantile(rel, 0.999):.2e}")
     assert np.quantile(rel, 0.999) <= 1e-4
-    assert rel.max() <= 5e-3
+    # FP32 sums emulated in numpy on these same rows flip a bfloat16 rounding in 7 of
+    # 32,933 rows; the worst of them reaches 1.5e-2 at the output (one flipped hidden
+    # activation carried through the remaining layers), hence 3e-2 for the maximum here
+    assert rel.max() <= 3e-2
 
 
 def test_forward_of_permutation_network_is_exact(P, O):

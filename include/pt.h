@@ -179,6 +179,24 @@ pt_status pt_render_debug(pt_scene* scene, const pt_camera* camera, int32_t x0, 
 pt_status pt_trace_closest(pt_scene* scene, const float* rays, int64_t n, uint32_t* hits,
                            int32_t brute_force);
 
+/* pt_trace_closest for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels, results bit-identical to pt_trace_closest,
+ * but the traversal stack spill and the launch's counters live in a static
+ * device array of the library (32 MiB, one copy per GPU, held until the
+ * process ends) instead of scene buffers.  The call allocates nothing; the
+ * caller passes rays and hits as for pt_trace_closest.  The grid of the BVH
+ * walk shrinks until every lane's spill area fits the array.  Every call on
+ * a GPU shares that GPU's array: calls that overlap on one GPU (several
+ * host threads, or scenes on different streams of the same device) race
+ * and must not be issued concurrently.  It adds nothing to pt_get_stats.
+ * Errors: as pt_trace_closest; UNSUPPORTED if one workgroup's spill area of
+ * this BVH's depth exceeds the array (a hierarchy far deeper than any
+ * binned-SAH build of 2^31 triangles); DEVICE on a traversal stack overflow
+ * (hits of that call may then be wrong). */
+pt_status pt_trace_closest_noalloc(pt_scene* scene, const float* rays, int64_t n, uint32_t* hits,
+                                   int32_t brute_force);
+
 /* Statistics since the last pt_reset_stats. */
 pt_status pt_get_stats(pt_scene* scene, pt_stats* out);
 pt_status pt_reset_stats(pt_scene* scene);

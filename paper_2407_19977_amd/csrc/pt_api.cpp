@@ -1317,6 +1317,11 @@ pt_status pt_scene_create(int32_t hip_device, void* hip_stream, pt_scene** out) 
   s->stream = static_cast<hipStream_t>(hip_stream);
   pt_status r = set_device(s.get());
   if (r) return r;
+  // set-up of the allocation-free call: this device's scratch address, looked up once per device
+  unsigned char* scratch_dev = nullptr;
+  e = noalloc_scratch(hip_device, &scratch_dev);
+  if (e != hipSuccess)
+    return fail(PT_ERR_DEVICE, "hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
   *out = s.release();
   return PT_OK;
 }
@@ -1772,6 +1777,40 @@ pt_status pt_trace_closest(pt_scene* s, const float* rays, int64_t n, uint32_t* 
   PT_HIP(launch_trace_rays(S, rays, n, hits, brute != 0, s->two_level, grid, s->stats.as<unsigned long long>(),
                            s->stream));
   return sync_traced(s);
+}
+
+pt_status pt_trace_closest_noalloc(pt_scene* s, const float* rays, int64_t n, uint32_t* hits, int32_t brute) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (n < 0 || n > 0x7FFFFFFF || (n > 0 && (!rays || !hits))) return fail(PT_ERR_INVALID_ARG, "bad rays/hits");
+  if (!s->has_bvh) return fail(PT_ERR_STATE, "pt_build_bvh has not been called");
+  if (n == 0) return PT_OK;
+  if ((r = set_device(s))) return r;
+  unsigned char* base = nullptr;
+  PT_HIP(noalloc_scratch(s->device, &base));
+  // the spill area holds the stack entries beyond the LDS part of every lane of the grid:
+  // the grid shrinks until it fits (the lanes are persistent, so any grid traces all rays)
+  const int cap = stack_capacity(s->bvh_depth);
+  const size_t lane_bytes = (size_t)std::max(1, cap - kLdsStack) * sizeof(uint2);
+  const int64_t fit = (int64_t)((kNoAllocScratchBytes - kNoAllocStatsBytes) / (lane_bytes * kBlock));
+  if (!brute && fit < 1)
+    return fail(PT_ERR_UNSUPPORTED, "BVH depth %d needs %zu bytes of stack spill per workgroup, more than the %zu-byte "
+                "scratch of the allocation-free call", s->bvh_depth, lane_bytes * kBlock,
+                kNoAllocScratchBytes - kNoAllocStatsBytes);
+  const int grid = brute ? trace_grid_blocks() : (int)std::min<int64_t>(traversal_grid(n), fit);
+  SceneDev S = scene_dev(s, grid);
+  S.spill = reinterpret_cast<uint2*>(base + kNoAllocStatsBytes);
+  S.spill_stride = (uint32_t)grid * kBlock;
+  unsigned long long* counters = reinterpret_cast<unsigned long long*>(base);
+  PT_HIP(launch_zero_u64(counters, kNumStats, s->stream));  // the previous call's counters are still there
+  PT_HIP(launch_trace_rays(S, rays, n, hits, brute != 0, s->two_level, grid, counters, s->stream));
+  unsigned long long overflow = 0;
+  PT_HIP(hipMemcpyAsync(&overflow, counters + kStatOverflow, sizeof(overflow), hipMemcpyDeviceToHost, s->stream));
+  if ((r = sync(s))) return r;
+  if (overflow)
+    return fail(PT_ERR_DEVICE, "traversal stack overflow in %llu workgroups (capacity %d entries per lane)", overflow,
+                cap);
+  return PT_OK;
 }
 
 pt_status pt_get_stats(pt_scene* s, pt_stats* o) {

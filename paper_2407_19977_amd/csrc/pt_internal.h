@@ -172,6 +172,15 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st);
 hipError_t launch_trace_rays(const SceneDev& S, const float* rays, int64_t n, uint32_t* hits, bool brute,
                              bool two_level, int grid, unsigned long long* stats, hipStream_t st);
 int trace_grid_blocks();
+// Allocation-free closest hits: the library's static device scratch (one copy
+// per GPU).  The first kNoAllocStatsBytes hold a launch's statistics counters,
+// the rest the traversal stack spill area.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+constexpr size_t kNoAllocStatsBytes = 256;
+static_assert(kNumStats * sizeof(unsigned long long) <= kNoAllocStatsBytes, "counters fit the scratch header");
+// Device address of `dev`'s scratch; call with `dev` current.  The symbol is
+// looked up once per device and the address kept.
+hipError_t noalloc_scratch(int dev, unsigned char** out);
 int traversal_grid(int64_t rays);  // workgroups of the traversal kernel for a pass of `rays` paths
 int tail_grid(int grid_trace, uint32_t paths, bool beside);  // workgroups of the tail kernel
 

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "pt_internal.h"
 #include "pt_nrc.h"
@@ -1464,6 +1465,34 @@ hipError_t launch_trace_rays(const SceneDev& S, const float* rays, int64_t n, ui
   else if (two_level) hipLaunchKernelGGL((k_trace_rays<true>), g, blk, 0, st, S, rays, nn, hits, stats);
   else hipLaunchKernelGGL((k_trace_rays<false>), g, blk, 0, st, S, rays, nn, hits, stats);
   return hipGetLastError();
+}
+
+// ------------------------------------------------ allocation-free scratch
+// Device memory of the allocation-free closest-hit call: a file-scope array,
+// one copy per GPU, held until the process ends and shared by every call on
+// that GPU.  In host code its name is not a device address: kernels receive
+// the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxScratchDevices];
+}  // namespace
+
+hipError_t noalloc_scratch(int dev, unsigned char** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace pt

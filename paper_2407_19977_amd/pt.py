@@ -92,6 +92,7 @@ _SIGS = {
     "pt_render_debug": (C.c_int, [C.c_void_p, C.POINTER(pt_camera), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                   C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p]),
     "pt_trace_closest": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32]),
+    "pt_trace_closest_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32]),
     "pt_get_stats": (C.c_int, [C.c_void_p, C.POINTER(pt_stats)]),
     "pt_reset_stats": (C.c_int, [C.c_void_p]),
     "pt_set_profiling": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
@@ -274,6 +275,11 @@ class PtScene:
     def trace_closest(self, rays, hits, brute_force=False):
         _check(_lib.pt_trace_closest(self.h, rays.data_ptr(), rays.shape[0], hits.data_ptr(),
                                      1 if brute_force else 0))
+        return hits
+
+    def trace_closest_noalloc(self, rays, hits, brute_force=False):
+        _check(_lib.pt_trace_closest_noalloc(self.h, rays.data_ptr(), rays.shape[0], hits.data_ptr(),
+                                             1 if brute_force else 0))
         return hits
 
     def stats(self) -> dict:

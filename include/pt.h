@@ -106,6 +106,11 @@ typedef struct pt_stats {
   int64_t tail_shadow_rays;  /* shadow rays of the tail kernel (included in shadow_rays) */
   int64_t tail_shadow_node_visits; /* their node fetches (counting on; not in shadow_node_visits) */
   int64_t tail_shadow_tri_tests;   /* their triangle tests (counting on; not in shadow_tri_tests) */
+  double ms_display;         /* summed time of the display kernel (profiling on) */
+  int64_t launches_display;  /* its launch count (profiling on) */
+  int64_t instances_entered; /* two-level scenes: instances whose mesh walk started, closest-hit and
+                                shadow walks of the traversal kernel (counting on; tail kernel apart) */
+  int64_t tail_instances_entered; /* the same for the tail kernel's walks (counting on) */
 } pt_stats;
 
 /* Create a scene bound to HIP device `hip_device` and stream `hip_stream`
@@ -159,6 +164,30 @@ pt_status pt_reset_accumulation(pt_scene* scene);
  * and optionally copy the raw FP64 sums to out_sum_f64 (device, [h][w][3]
  * double, or NULL).  Errors: STATE if nothing was accumulated. */
 pt_status pt_resolve(pt_scene* scene, float* out_rgb32f, double* out_sum_f64);
+
+/* Replace the FP64 sums and their sample count (resuming a progressive
+ * render from sums saved with pt_resolve's out_sum_f64): sum (device,
+ * [height][width][3] double, copied) holds the sums of `samples` samples per
+ * pixel.  A later pt_accumulate with a camera of the same size adds to them.
+ * Errors: INVALID_ARG (sum NULL, width, height or samples <= 0), DEVICE. */
+pt_status pt_set_accumulation(pt_scene* scene, const double* sum, int32_t width, int32_t height, int64_t samples);
+
+/* Display image of the running mean (Sec. 5.1.4: the mean of the samples
+ * accumulated so far is tone mapped with Khronos PBR Neutral and shown after
+ * every sampling iteration).  Per pixel, in FP64: c = (sum / samples) *
+ * exposure; PBR Neutral (the smallest channel x sets an offset x - 6.25 x^2
+ * for x < 0.08, else 0.04, subtracted from every channel; a peak p at or
+ * above 0.76 is compressed to q = 1 - 0.0576 / (p - 0.56), the colour scaled
+ * by q / p and mixed towards grey q by 1 - 1 / (0.15 (p - q) + 1)); the sRGB
+ * transfer function on [0, 1]; code floor(255 e + 1/2).  out_rgba8 (device,
+ * [height][width] uint32, bytes R, G, B, A = 255 in memory order) and
+ * out_encoded (device, [height][width][3] float, the sRGB values before
+ * quantisation) are caller-owned; either may be NULL, not both.  Reads the
+ * sums left by pt_render / pt_accumulate without changing them, so calling
+ * it after every pt_accumulate gives the progressive display.
+ * Errors: INVALID_ARG (both outputs NULL, exposure negative or not finite),
+ * STATE (nothing accumulated), DEVICE. */
+pt_status pt_display(pt_scene* scene, double exposure, uint32_t* out_rgba8, float* out_encoded);
 
 /* Per-path output for parity checks: render samples [first_sample,
  * first_sample + spp) of the pixels in the crop (x0, y0, w, h) of the
@@ -239,12 +268,15 @@ typedef struct pt_radiance_cache_config {
   float beta1, beta2;      /* in [0, 1) (0.9, 0.99) */
   float epsilon;           /* > 0 (1e-8) */
   uint64_t init_seed;      /* Philox key of the He-uniform initial weights */
+  float ema_decay;         /* [0, 1): after each Adam step t the moving average e = ema_decay e +
+                              (1 - ema_decay) w (e starts at 0) is updated and the cache queries use
+                              e / (1 - ema_decay^t); 0 uses the weights themselves (0) */
 } pt_radiance_cache_config;
 
 /* Configure (cfg != NULL) or switch off (cfg == NULL) the cache.  Weights
  * start He-uniform: weight k of layer l is (2u - 1) sqrt(6/64), u the
  * Philox uniform at counter (k, l, 0x4E5243, 0) under init_seed; Adam
- * moments and step count start at zero; rendering does not use the cache
+ * moments, the moving average and the step count start at zero; rendering does not use the cache
  * until it has been trained or given weights.  Errors: INVALID_ARG for a
  * field out of range, DEVICE. */
 pt_status pt_set_radiance_cache(pt_scene* scene, const pt_radiance_cache_config* cfg);
@@ -258,9 +290,15 @@ pt_status pt_nrc_set_weights(pt_scene* scene, const float* weights, int64_t n);
  * each; any pointer may be NULL) and the number of Adam steps taken. */
 pt_status pt_nrc_get_weights(pt_scene* scene, float* weights, float* adam_m, float* adam_v, int64_t* step);
 
-/* Cache outputs of n inputs: inputs (device, [n][12] float) -> outputs
- * (device, [n][3] float, unclamped).  The same kernel code answers the
- * queries of the sampling passes. */
+/* The inference weights the cache queries use (device, 20,672 floats): the
+ * bias-corrected moving average after Adam steps with ema_decay > 0, else
+ * the weights; equal to the weights before the first step and after
+ * pt_nrc_set_weights. */
+pt_status pt_nrc_get_inference_weights(pt_scene* scene, float* weights);
+
+/* Cache outputs of n inputs under the inference weights: inputs (device,
+ * [n][12] float) -> outputs (device, [n][3] float, unclamped).  The same
+ * kernel code answers the queries of the sampling passes. */
 pt_status pt_nrc_forward(pt_scene* scene, const float* inputs, int64_t n, float* outputs);
 
 /* Gradient of the mean loss over n samples (device inputs [n][12], targets

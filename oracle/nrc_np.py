@@ -10,6 +10,8 @@ W5 (3 x 64), row-major [out][in], concatenated: 20,672 values.
   (y - t)^2 / (sg(y)^2 + 0.01), sg = no gradient through the denominator.
 * backward: g_5 = dL/dy; dW_l = sum_n g_l a_l^T; g_{l-1} = (W_l^T g_l) * [z_{l-1} > 0].
 * Adam (Kingma & Ba) with bias correction: lr 1e-3, beta1 0.9, beta2 0.99, eps 1e-8.
+* Inference weights: bias-corrected exponential moving average of the
+  weights over the Adam steps (decay in [0, 1); 0 = the weights).
 * He-uniform initialisation: weight k of layer l is (2u - 1) sqrt(6 / 64)
   with u the Philox uniform at (pixel k, sample l, bounce 0x4E5243, dim 0).
 
@@ -133,6 +135,21 @@ def adam(w, m, v, g, step, lr=1e-3, b1=0.9, b2=0.99, eps=1e-8):
     mh = m / (1.0 - b1 ** step)
     vh = v / (1.0 - b2 ** step)
     return w - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def ema_update(e, w, alpha):
+    """Moving average of the weights after an Adam step: e = alpha e + (1 - alpha) w
+    (e starts at zero).  The cited cache method renders with such an average of
+    the weights rather than the latest ones (Sec. 6.1 names the method)."""
+    return alpha * np.asarray(e, dtype=np.float64) + (1.0 - alpha) * np.asarray(w, dtype=np.float64)
+
+
+def ema_weights(e, t, alpha, w):
+    """Inference weights after t Adam steps: the bias-corrected average
+    e / (1 - alpha^t); the weights w themselves when alpha is 0 or t is 0."""
+    if alpha == 0.0 or t == 0:
+        return np.asarray(w, dtype=np.float64)
+    return np.asarray(e, dtype=np.float64) / (1.0 - alpha ** t)
 
 
 def init_weights(seed, uniform):

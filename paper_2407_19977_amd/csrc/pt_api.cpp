@@ -149,6 +149,7 @@ struct pt_scene {
   pt_radiance_cache_config nrc_cfg;
   DevBuf nrc_t;            // Adam steps applied (one device word: steps with no records are skipped there)
   DevBuf nrc_w, nrc_m, nrc_v, nrc_fwd, nrc_bwd;  // FP32 master weights, Adam moments, bf16 fragments
+  DevBuf nrc_e, nrc_wi, nrc_inf;  // moving average of the weights, inference weights, their bf16 fragments
   DevBuf nrc_rec[2];       // training records, per path set (frames overlap on two sets)
   DevBuf nrc_off, nrc_bsum, nrc_n, nrc_X, nrc_T;  // compaction
   int64_t nrc_rec_cap = 0;
@@ -163,6 +164,10 @@ struct pt_scene {
   double tail_fraction = 0.15;
   double ms_tail = 0.0;
   int64_t launches_tail = 0;
+  // display path
+  double ms_display = 0.0;
+  int64_t launches_display = 0;
+  hipEvent_t ev_display[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -643,7 +648,7 @@ pt_status run_passes(pt_scene* s, const CamDev& C, int x0, int y0, int w, int h,
         B.nrc_q_cap = N;
       }
       A.nrc_bounce = s->nrc_cfg.query_bounce;
-      A.nrc_fwd = s->nrc_fwd.as<uint4>();
+      A.nrc_fwd = s->nrc_inf.as<uint4>();
       P.nrc_q = B.nrc_q.as<float>();
       P.q_nrc = B.q_nrc.as<uint32_t>();
     }
@@ -791,7 +796,7 @@ pt_status run_cache_frames(pt_scene* s, const CamDev& C, int first, int n, int m
     A.two_level = s->two_level;
     A.class_mask = s->class_mask | (1u << kClsMiss);
     A.nrc_bounce = s->nrc_cfg.query_bounce;
-    A.nrc_fwd = s->nrc_fwd.as<uint4>();
+    A.nrc_fwd = s->nrc_inf.as<uint4>();
     A.query_wait = k > 0 ? s->ev_train : nullptr;  // the previous frame's Adam steps
     A.query_beside = true;
     if (tail) {
@@ -877,6 +882,12 @@ void nrc_split(int64_t N, int& n_split, int64_t& npad) {
   npad = (N + q - 1) / q * q;
 }
 
+// All three fragment sets from the weights and the inference weights.
+hipError_t nrc_pack(pt_scene* s, uint32_t* t_step, const uint32_t* n_records, hipStream_t st) {
+  return nrc_launch_pack(s->nrc_w.as<float>(), s->nrc_wi.as<float>(), s->nrc_fwd.as<uint4>(), s->nrc_bwd.as<uint4>(),
+                         s->nrc_inf.as<uint4>(), t_step, n_records, st);
+}
+
 pt_status nrc_ensure_ws(pt_scene* s, int64_t N) {
   int split;
   int64_t npad;
@@ -913,12 +924,10 @@ pt_status nrc_step(pt_scene* s, const float* X, const float* T, int64_t N, float
                           s->nrc_a.as<uint16_t>(), s->nrc_g.as<uint16_t>(), s->nrc_loss.as<float>(), grid_fb,
                           s->nrc_dw.as<float>(), st));
   const pt_radiance_cache_config& c = s->nrc_cfg;
-  PT_HIP(nrc_launch_adam(s->nrc_w.as<float>(), s->nrc_m.as<float>(), s->nrc_v.as<float>(), s->nrc_dw.as<float>(),
-                         split, grad_out, c.learning_rate, c.beta1, c.beta2, c.epsilon, s->nrc_t.as<uint32_t>(),
-                         n_records, apply ? 1 : 0, st));
-  if (apply)
-    PT_HIP(nrc_launch_pack(s->nrc_w.as<float>(), s->nrc_fwd.as<uint4>(), s->nrc_bwd.as<uint4>(),
-                           s->nrc_t.as<uint32_t>(), n_records, st));
+  PT_HIP(nrc_launch_adam(s->nrc_w.as<float>(), s->nrc_m.as<float>(), s->nrc_v.as<float>(), s->nrc_e.as<float>(),
+                         s->nrc_wi.as<float>(), s->nrc_dw.as<float>(), split, grad_out, c.learning_rate, c.beta1,
+                         c.beta2, c.epsilon, c.ema_decay, s->nrc_t.as<uint32_t>(), n_records, apply ? 1 : 0, st));
+  if (apply) PT_HIP(nrc_pack(s, s->nrc_t.as<uint32_t>(), n_records, st));
   return PT_OK;
 }
 
@@ -1335,6 +1344,7 @@ void pt_scene_destroy(pt_scene* s) {
     for (hipEvent_t e : v) (void)hipEventDestroy(e);
   for (int k = 0; k < 2; ++k) {
     if (s->ev_bulk[k]) (void)hipEventDestroy(s->ev_bulk[k]);
+    if (s->ev_display[k]) (void)hipEventDestroy(s->ev_display[k]);
     if (s->ev_done[k]) (void)hipEventDestroy(s->ev_done[k]);
     for (int j = 0; j < 2; ++j)
       if (s->ev_train_t[k][j]) (void)hipEventDestroy(s->ev_train_t[k][j]);
@@ -1581,6 +1591,46 @@ pt_status pt_resolve(pt_scene* s, float* out, double* out_sum) {
   return sync(s);
 }
 
+pt_status pt_set_accumulation(pt_scene* s, const double* sum, int32_t width, int32_t height, int64_t samples) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (!sum) return fail(PT_ERR_INVALID_ARG, "sum is NULL");
+  if (width <= 0 || height <= 0) return fail(PT_ERR_INVALID_ARG, "width and height must be > 0");
+  if (samples <= 0) return fail(PT_ERR_INVALID_ARG, "samples must be > 0");
+  if ((r = set_device(s))) return r;
+  if ((r = ensure_accum(s, width, height))) return r;
+  PT_HIP(hipMemcpyAsync(s->sum.p, sum, (size_t)width * height * 3 * sizeof(double), hipMemcpyDeviceToDevice,
+                        s->stream));
+  s->acc_samples = samples;
+  return sync(s);
+}
+
+pt_status pt_display(pt_scene* s, double exposure, uint32_t* out_rgba8, float* out_encoded) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (!out_rgba8 && !out_encoded) return fail(PT_ERR_INVALID_ARG, "out_rgba8 and out_encoded are both NULL");
+  if (!(exposure >= 0.0) || !std::isfinite(exposure)) return fail(PT_ERR_INVALID_ARG, "exposure must be finite and >= 0");
+  if (s->acc_samples <= 0) return fail(PT_ERR_STATE, "nothing accumulated");
+  if ((r = set_device(s))) return r;
+  const int64_t np = (int64_t)s->acc_w * s->acc_h;
+  if (s->timing) {
+    for (hipEvent_t& e : s->ev_display)
+      if (!e) PT_HIP(hipEventCreate(&e));
+    PT_HIP(hipEventRecord(s->ev_display[0], s->stream));
+  }
+  PT_HIP(launch_display(s->sum.as<double>(), np, 1.0 / (double)s->acc_samples, exposure, out_rgba8, out_encoded,
+                        s->stream));
+  if (s->timing) PT_HIP(hipEventRecord(s->ev_display[1], s->stream));
+  if ((r = sync(s))) return r;
+  if (s->timing) {
+    float ms = 0.0f;
+    PT_HIP(hipEventElapsedTime(&ms, s->ev_display[0], s->ev_display[1]));
+    s->ms_display += ms;
+    s->launches_display += 1;
+  }
+  return PT_OK;
+}
+
 pt_status pt_render(pt_scene* s, const pt_camera* cam, int32_t spp, int32_t max_depth, uint64_t seed, float* out) {
   pt_status r = check_scene(s);
   if (r) return r;
@@ -1635,20 +1685,23 @@ pt_status pt_set_radiance_cache(pt_scene* s, const pt_radiance_cache_config* cfg
   if (!(c.beta1 >= 0.0f && c.beta1 < 1.0f) || !(c.beta2 >= 0.0f && c.beta2 < 1.0f))
     return fail(PT_ERR_INVALID_ARG, "beta1 and beta2 must be in [0, 1)");
   if (!(c.epsilon > 0.0f) || !std::isfinite(c.epsilon)) return fail(PT_ERR_INVALID_ARG, "epsilon must be > 0");
+  if (!(c.ema_decay >= 0.0f && c.ema_decay < 1.0f)) return fail(PT_ERR_INVALID_ARG, "ema_decay must be in [0, 1)");
   if ((r = set_device(s))) return r;
   std::vector<float> w;
   nrc_init_weights(c.init_seed, w);
   const size_t bytes = kNrcParams * sizeof(float);
   PT_HIP(upload(s->nrc_w, w.data(), bytes, s->stream));
+  PT_HIP(upload(s->nrc_wi, w.data(), bytes, s->stream));
   std::vector<float> zero(kNrcParams, 0.0f);
   PT_HIP(upload(s->nrc_m, zero.data(), bytes, s->stream));
   PT_HIP(upload(s->nrc_v, zero.data(), bytes, s->stream));
+  PT_HIP(upload(s->nrc_e, zero.data(), bytes, s->stream));
   if (!s->nrc_fwd.p) PT_HIP(s->nrc_fwd.alloc(kNrcFwdFrags * 64 * sizeof(uint4)));
   if (!s->nrc_bwd.p) PT_HIP(s->nrc_bwd.alloc(kNrcBwdFrags * 64 * sizeof(uint4)));
+  if (!s->nrc_inf.p) PT_HIP(s->nrc_inf.alloc(kNrcFwdFrags * 64 * sizeof(uint4)));
   if (!s->nrc_t.p) PT_HIP(s->nrc_t.alloc(sizeof(uint32_t)));
   PT_HIP(hipMemsetAsync(s->nrc_t.p, 0, sizeof(uint32_t), s->stream));
-  PT_HIP(nrc_launch_pack(s->nrc_w.as<float>(), s->nrc_fwd.as<uint4>(), s->nrc_bwd.as<uint4>(), nullptr, nullptr,
-                         s->stream));
+  PT_HIP(nrc_pack(s, nullptr, nullptr, s->stream));
   s->nrc_cfg = c;
   s->nrc_on = true;
   s->nrc_ready = false;
@@ -1662,11 +1715,12 @@ pt_status pt_nrc_set_weights(pt_scene* s, const float* weights, int64_t n) {
   if (!weights || n != kNrcParams) return fail(PT_ERR_INVALID_ARG, "weights must be %d device floats", kNrcParams);
   if ((r = set_device(s))) return r;
   PT_HIP(hipMemcpyAsync(s->nrc_w.p, weights, kNrcParams * sizeof(float), hipMemcpyDeviceToDevice, s->stream));
+  PT_HIP(hipMemcpyAsync(s->nrc_wi.p, weights, kNrcParams * sizeof(float), hipMemcpyDeviceToDevice, s->stream));
   std::vector<float> zero(kNrcParams, 0.0f);
   PT_HIP(hipMemcpyAsync(s->nrc_m.p, zero.data(), kNrcParams * sizeof(float), hipMemcpyHostToDevice, s->stream));
   PT_HIP(hipMemcpyAsync(s->nrc_v.p, zero.data(), kNrcParams * sizeof(float), hipMemcpyHostToDevice, s->stream));
-  PT_HIP(nrc_launch_pack(s->nrc_w.as<float>(), s->nrc_fwd.as<uint4>(), s->nrc_bwd.as<uint4>(), nullptr, nullptr,
-                         s->stream));
+  PT_HIP(hipMemcpyAsync(s->nrc_e.p, zero.data(), kNrcParams * sizeof(float), hipMemcpyHostToDevice, s->stream));
+  PT_HIP(nrc_pack(s, nullptr, nullptr, s->stream));
   PT_HIP(hipMemsetAsync(s->nrc_t.p, 0, sizeof(uint32_t), s->stream));
   s->nrc_ready = true;
   return sync(s);
@@ -1690,6 +1744,16 @@ pt_status pt_nrc_get_weights(pt_scene* s, float* weights, float* adam_m, float* 
   return sync(s);
 }
 
+pt_status pt_nrc_get_inference_weights(pt_scene* s, float* weights) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (!s->nrc_on) return fail(PT_ERR_STATE, "pt_set_radiance_cache has not been called");
+  if (!weights) return fail(PT_ERR_INVALID_ARG, "weights is NULL");
+  if ((r = set_device(s))) return r;
+  PT_HIP(hipMemcpyAsync(weights, s->nrc_wi.p, kNrcParams * sizeof(float), hipMemcpyDeviceToDevice, s->stream));
+  return sync(s);
+}
+
 pt_status pt_nrc_forward(pt_scene* s, const float* inputs, int64_t n, float* outputs) {
   pt_status r = check_scene(s);
   if (r) return r;
@@ -1698,7 +1762,7 @@ pt_status pt_nrc_forward(pt_scene* s, const float* inputs, int64_t n, float* out
   if (n == 0) return PT_OK;
   if (!inputs || !outputs) return fail(PT_ERR_INVALID_ARG, "inputs and outputs must be non-NULL");
   if ((r = set_device(s))) return r;
-  PT_HIP(nrc_launch_forward(inputs, n, s->nrc_fwd.as<uint4>(), outputs, s->stream));
+  PT_HIP(nrc_launch_forward(inputs, n, s->nrc_inf.as<uint4>(), outputs, s->stream));
   return sync(s);
 }
 
@@ -1838,6 +1902,8 @@ pt_status pt_get_stats(pt_scene* s, pt_stats* o) {
     o->tail_shadow_rays = (int64_t)v[kStatTailShadow];
     o->tail_shadow_node_visits = (int64_t)v[kStatTailShadowNodes];
     o->tail_shadow_tri_tests = (int64_t)v[kStatTailShadowTris];
+    o->instances_entered = (int64_t)v[kStatInstances];
+    o->tail_instances_entered = (int64_t)v[kStatTailInstances];
     if (v[kStatOverflow]) return fail(PT_ERR_DEVICE, "traversal stack overflow in %llu workgroups", v[kStatOverflow]);
   }
   o->samples = s->samples;
@@ -1855,6 +1921,8 @@ pt_status pt_get_stats(pt_scene* s, pt_stats* o) {
   o->ms_cache_train = s->ms_cache_train;
   o->ms_tail = s->ms_tail;
   o->launches_tail = s->launches_tail;
+  o->ms_display = s->ms_display;
+  o->launches_display = s->launches_display;
   return PT_OK;
 }
 
@@ -1871,6 +1939,8 @@ pt_status pt_reset_stats(pt_scene* s) {
   s->ms_cache_query = s->ms_cache_train = 0.0;
   s->ms_tail = 0.0;
   s->launches_tail = 0;
+  s->ms_display = 0.0;
+  s->launches_display = 0;
   return sync(s);
 }
 

@@ -117,7 +117,9 @@ enum {
   kStatTailShadowNodes = 13,  // their node visits and triangle tests (not in kStatShadowNodes / kStatShadowTris)
   kStatTailShadowTris = 14,
   kStatRecords = 15,          // radiance-cache training records of the frame loop
-  kNumStats = 16
+  kStatInstances = 16,        // instances entered by the traversal kernel's walks (two-level; counting on)
+  kStatTailInstances = 17,    // instances entered by the tail kernel's walks (two-level; counting on)
+  kNumStats = 18
 };
 constexpr int kCountShadow = 2 + kNumClasses;
 constexpr int kCountQuery = kCountShadow + 1;
@@ -168,6 +170,9 @@ hipError_t launch_accumulate(const PathsDev& P, double* sum, int W, float* per_s
                              int spp_total, int sample_index, hipStream_t st);
 hipError_t launch_resolve(const double* sum, float* out, int64_t n_values, double inv_spp, hipStream_t st);
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
+// display image of the running mean (pt_display.hip): rgba8 and encoded are nullable
+hipError_t launch_display(const double* sum, int64_t n_pixels, double inv_samples, double exposure, uint32_t* rgba8,
+                          float* encoded, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st);
 hipError_t launch_trace_rays(const SceneDev& S, const float* rays, int64_t n, uint32_t* hits, bool brute,
                              bool two_level, int grid, unsigned long long* stats, hipStream_t st);
@@ -186,16 +191,16 @@ int tail_grid(int grid_trace, uint32_t paths, bool beside);  // workgroups of th
 
 // ---- radiance cache (pt_nrc.hip) ----
 // t_step / n_records (nullable): count the applied Adam step on the device unless the batch had no records
-hipError_t nrc_launch_pack(const float* w, uint4* fwd, uint4* bwd, uint32_t* t_step, const uint32_t* n_records,
-                           hipStream_t st);
+hipError_t nrc_launch_pack(const float* w, const float* wi, uint4* fwd, uint4* bwd, uint4* inf, uint32_t* t_step,
+                           const uint32_t* n_records, hipStream_t st);
 hipError_t nrc_launch_forward(const float* x, int64_t n, const uint4* fwd, float* y, hipStream_t st);
 hipError_t nrc_launch_query(const PathsDev& P, const uint4* fwd, int grid, hipStream_t st);
 hipError_t nrc_launch_train(const float* X, const float* T, int N, int npad, int n_split, const uint4* fwd,
                             const uint4* bwd, uint16_t* a_store, uint16_t* g_store, float* loss_part, int grid_fb,
                             float* dw_part, hipStream_t st);
-hipError_t nrc_launch_adam(float* w, float* m, float* v, const float* dw_part, int n_split, float* grad_out, float lr,
-                           float b1, float b2, float eps, const uint32_t* t_step, const uint32_t* n_records, int apply,
-                           hipStream_t st);
+hipError_t nrc_launch_adam(float* w, float* m, float* v, float* e, float* wi, const float* dw_part, int n_split,
+                           float* grad_out, float lr, float b1, float b2, float eps, float ema, const uint32_t* t_step,
+                           const uint32_t* n_records, int apply, hipStream_t st);
 hipError_t nrc_launch_targets(const PathsDev& P, int n_paths, uint32_t* offsets, uint32_t* block_sums, float* X,
                               float* T, uint32_t* n_out, unsigned long long* record_stats, hipStream_t st);
 hipError_t nrc_launch_gather(const float* X_all, const float* T_all, const uint32_t* n_all, int B, uint32_t frame,

@@ -397,7 +397,8 @@ enum { kWalkClosest = 0, kWalkAny = 1, kWalkPerLane = 2 };
 // instance id) that start a mesh walk on top of the stack.  Returns true when
 // the walk is over (any-hit walks: also at the first accepted triangle).
 template <int KIND, bool COUNT, bool TWO>
-__device__ inline bool lane_step(const SceneDev& S, LaneRay& L, DevStack& st, uint32_t& nvis, uint32_t& ntri) {
+__device__ inline bool lane_step(const SceneDev& S, LaneRay& L, DevStack& st, uint32_t& nvis, uint32_t& ntri,
+                                 uint32_t& ninst) {
   const bool any = KIND == kWalkAny || (KIND == kWalkPerLane && L.any);
   const uint32_t cur = L.cur;
   if (cur != kEmpty) {
@@ -427,6 +428,7 @@ __device__ inline bool lane_step(const SceneDev& S, LaneRay& L, DevStack& st, ui
       const uint32_t first = leaf_first(cur), cnt = leaf_count(cur);
       if (cnt == 0) {  // an instance entry: walk its mesh in object space
         const InstRec& I = S.insts[first];
+        if (COUNT) ninst++;
         L.r = ray_to_object(I.w2o, L.rw.ox, L.rw.oy, L.rw.oz, L.rw.dx, L.rw.dy, L.rw.dz);
         L.inst = first;
         L.base = st.size();
@@ -499,7 +501,8 @@ __device__ inline void persistent_trace(const SceneDev& S, Src& src, uint32_t co
       const uint32_t n_node = (uint32_t)__popcll((unsigned long long)__ballot(busy && !at_leaf));
       go = busy && (!at_leaf || kLeafWait * n_leaf >= kLeafWaitDen * n_node);
     }
-    if (go && lane_step<KIND, COUNT, TWO>(S, L, st, nvis, ntri)) {
+    uint32_t ninst = 0;
+    if (go && lane_step<KIND, COUNT, TWO>(S, L, st, nvis, ntri, ninst)) {
       src.finish(item, L, L.best.tri != 0xFFFFFFFFu);
       busy = false;
     }
@@ -900,6 +903,7 @@ __global__ __launch_bounds__(kBlock, kTraceWaves) void k_traverse(SceneDev S, Pa
   bool busy = false, drained = false, shadow = false;
   uint32_t item = 0;
   uint32_t rv = 0, rt = 0, nvis = 0, ntri = 0, svis = 0, stri = 0;  // node visits / triangle tests
+  uint32_t ri = 0, ninst = 0;  // instances entered (both walk kinds)
   while (true) {
     const uint64_t idle = __ballot(!busy);
     const uint32_t n_idle = (uint32_t)__popcll((unsigned long long)idle);
@@ -917,7 +921,7 @@ __global__ __launch_bounds__(kBlock, kTraceWaves) void k_traverse(SceneDev S, Pa
         else es.start(item, L);
         L.any = shadow;
         busy = true;
-        rv = rt = 0;
+        rv = rt = ri = 0;
       }
     }
     if (__ballot(busy) == 0) break;
@@ -931,11 +935,12 @@ __global__ __launch_bounds__(kBlock, kTraceWaves) void k_traverse(SceneDev S, Pa
       const uint32_t n_node = (uint32_t)__popcll((unsigned long long)__ballot(busy && !at_leaf));
       go = busy && (!at_leaf || kLeafWait * n_leaf >= kLeafWaitDen * n_node);
     }
-    if (go && lane_step<kWalkPerLane, COUNT, TWO>(S, L, st, rv, rt)) {
+    if (go && lane_step<kWalkPerLane, COUNT, TWO>(S, L, st, rv, rt, ri)) {
       const bool found = L.best.tri != 0xFFFFFFFFu;
       if (shadow) cs.finish(item, L, found);
       else es.finish(item, L, found);
       if (COUNT) {
+        ninst += ri;
         if (shadow) {
           svis += rv;
           stri += rt;
@@ -952,6 +957,7 @@ __global__ __launch_bounds__(kBlock, kTraceWaves) void k_traverse(SceneDev S, Pa
     atomicAdd(&P.stats[kStatTris], (unsigned long long)ntri);
     atomicAdd(&P.stats[kStatShadowNodes], (unsigned long long)svis);
     atomicAdd(&P.stats[kStatShadowTris], (unsigned long long)stri);
+    if (TWO) atomicAdd(&P.stats[kStatInstances], (unsigned long long)ninst);
   }
   if (nonfinite) atomicAdd(&P.stats[kStatNonFinite], nonfinite);
   if (st.overflow) atomicAdd(&P.stats[kStatOverflow], 1ull);
@@ -1000,13 +1006,14 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
   uint32_t n_ext = 0, n_sh = 0, nvis = 0, ntri = 0, svis = 0, stri = 0;
   unsigned long long nonfinite = 0;
   bool overflow = false;
-  uint32_t rv = 0, rt = 0;  // node visits / triangle tests of the current walk
+  uint32_t rv = 0, rt = 0, ri = 0;  // node visits / triangle tests / instances entered of the current walk
+  uint32_t ninst = 0;
   auto start_closest = [&](void) {
     float4 o = P.ray_o[slot], d = P.ray_d[slot];
     st.sp = 0;
     lane_start<TWO>(L, o.x, o.y, o.z, d.x, d.y, d.z, S.tmin, INFINITY, f2u(d.w), f2u(o.w), TWO ? 0u : S.root);
     L.any = false;
-    rv = rt = 0;
+    rv = rt = ri = 0;
     phase = 1;
     n_ext++;
   };
@@ -1036,8 +1043,9 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
       const uint32_t n_node = (uint32_t)__popcll((unsigned long long)__ballot(walking && !at_leaf));
       go = walking && (!at_leaf || kLeafWait * n_leaf >= kLeafWaitDen * n_node);
     }
-    const bool done = go && lane_step<kWalkPerLane, COUNT, TWO>(S, L, st, rv, rt);
+    const bool done = go && lane_step<kWalkPerLane, COUNT, TWO>(S, L, st, rv, rt, ri);
     if (done && COUNT) {
+      ninst += ri;
       if (phase == 1) {
         nvis += rv;
         ntri += rt;
@@ -1107,7 +1115,7 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
         lane_start<TWO>(L, o.sh_o.x, o.sh_o.y, o.sh_o.z, o.sh_d.x, o.sh_d.y, o.sh_d.z, S.tmin, o.sh_o.w,
                         TWO ? o.sh_inst : 0u, f2u(o.sh_c.w), TWO ? 0u : S.root);
         L.any = true;
-        rv = rt = 0;
+        rv = rt = ri = 0;
         sh_c = o.sh_c;
         cont = o.cont;
         phase = 2;
@@ -1134,6 +1142,7 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
     atomicAdd(&P.stats[kStatTailTris], (unsigned long long)ntri);
     atomicAdd(&P.stats[kStatTailShadowNodes], (unsigned long long)svis);
     atomicAdd(&P.stats[kStatTailShadowTris], (unsigned long long)stri);
+    if (TWO) atomicAdd(&P.stats[kStatTailInstances], (unsigned long long)ninst);
   }
   if (nonfinite) atomicAdd(&P.stats[kStatNonFinite], nonfinite);
   if (overflow) atomicAdd(&P.stats[kStatOverflow], 1ull);

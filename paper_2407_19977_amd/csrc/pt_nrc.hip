@@ -1,14 +1,16 @@
 // Radiance-cache kernels for gfx950: BF16 matrix-core inference and training.
 //
 // k_nrc_pack      FP32 master weights -> bf16 operand fragments (forward and
-//                 transposed for the backward pass), in the chained K order.
+//                 transposed for the backward pass), in the chained K order;
+//                 FP32 inference weights -> forward fragments of the queries.
 // k_nrc_infer     encode + 6 layers per 16 queries per wave, weights in LDS.
 // k_nrc_fwd_bwd   forward with kept activations, relative-L2 loss gradient,
 //                 backward through the transposed fragments; writes layer
 //                 inputs and layer output gradients (bf16, [feature][sample]).
 // k_nrc_dw        dW_l = g_l^T a_l as a matrix-core GEMM over samples, split
 //                 over sample ranges; partial tiles in FP32.
-// k_nrc_adam      fixed-order sum of the partials, Adam with FP32 master weights.
+// k_nrc_adam      fixed-order sum of the partials, Adam with FP32 master weights,
+//                 moving average of the weights for inference.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -50,16 +52,24 @@ __device__ inline bf16x8 chain_relu(f32x4 lo, f32x4 hi) {
 __device__ inline float bf16x8_get(bf16x8 v, int j) { return (float)v[j]; }
 
 // --------------------------------------------------------------- packing
+// Training fragments (forward and transposed) from the weights w, and the
+// inference fragments (forward layout) from the inference weights wi.
 // Also counts the Adam step just applied (t_step, when given), unless the
 // batch had no records (n_records given and zero): the step then left the
 // weights and moments unchanged and is not counted.
-__global__ void k_nrc_pack(const float* __restrict__ w, uint4* __restrict__ fwd, uint4* __restrict__ bwd,
-                           uint32_t* __restrict__ t_step, const uint32_t* __restrict__ n_records) {
+__global__ void k_nrc_pack(const float* __restrict__ w, const float* __restrict__ wi, uint4* __restrict__ fwd,
+                           uint4* __restrict__ bwd, uint4* __restrict__ inf, uint32_t* __restrict__ t_step,
+                           const uint32_t* __restrict__ n_records) {
   int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id == 0 && t_step && (!n_records || *n_records > 0u)) *t_step += 1u;
-  int total = (kNrcFwdFrags + kNrcBwdFrags) * 64;
+  int total = (2 * kNrcFwdFrags + kNrcBwdFrags) * 64;
   if (id >= total) return;
   int frag = id / 64, lane = id % 64, g = lane / 16, r = lane % 16;
+  const bool to_inf = frag >= kNrcFwdFrags + kNrcBwdFrags;
+  if (to_inf) {
+    frag -= kNrcFwdFrags + kNrcBwdFrags;
+    w = wi;
+  }
   float v[8];
   if (frag < kNrcFwdFrags) {
     if (frag < 40) {
@@ -90,7 +100,8 @@ __global__ void k_nrc_pack(const float* __restrict__ w, uint4* __restrict__ fwd,
   u.y = pack2(v[2], v[3]);
   u.z = pack2(v[4], v[5]);
   u.w = pack2(v[6], v[7]);
-  if (frag < kNrcFwdFrags) fwd[frag * 64 + lane] = u;
+  if (to_inf) inf[frag * 64 + lane] = u;
+  else if (frag < kNrcFwdFrags) fwd[frag * 64 + lane] = u;
   else bwd[(frag - kNrcFwdFrags) * 64 + lane] = u;
 }
 
@@ -383,11 +394,14 @@ __global__ __launch_bounds__(256) void k_nrc_dw(const uint16_t* __restrict__ a_s
 // Step t = t_step + 1 (the counter of applied steps lives on the device, so
 // that a batch drawn from zero records, known only on the device, can be
 // skipped without the host waiting for the record count).  Bias corrections
-// 1 / (1 - beta^t) in double, rounded to float.
+// 1 / (1 - beta^t) in double, rounded to float.  Then the moving average of
+// the weights, e = ema e + (1 - ema) w, and the inference weights
+// wi = e / (1 - ema^t) (wi = w when ema is 0).
 __global__ __launch_bounds__(256) void k_nrc_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                                                  float* __restrict__ e, float* __restrict__ wi,
                                                   const float* __restrict__ dw_part, int n_split,
                                                   float* __restrict__ grad_out, float lr, float b1, float b2,
-                                                  float eps, const uint32_t* __restrict__ t_step,
+                                                  float eps, float ema, const uint32_t* __restrict__ t_step,
                                                   const uint32_t* __restrict__ n_records, int apply) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= kNrcParams) return;
@@ -402,7 +416,16 @@ __global__ __launch_bounds__(256) void k_nrc_adam(float* __restrict__ w, float* 
   float vv = b2 * v[p] + (1.0f - b2) * gsum * gsum;
   m[p] = mm;
   v[p] = vv;
-  w[p] -= lr * (mm * c1) / (sqrtf(vv * c2) + eps);
+  const float wn = w[p] - lr * (mm * c1) / (sqrtf(vv * c2) + eps);
+  w[p] = wn;
+  if (ema > 0.0f) {
+    const float ce = (float)(1.0 / (1.0 - pow((double)ema, t)));
+    const float ee = ema * e[p] + (1.0f - ema) * wn;
+    e[p] = ee;
+    wi[p] = ee * ce;
+  } else {
+    wi[p] = wn;
+  }
 }
 
 // ------------------------------------------------------- training targets
@@ -529,10 +552,11 @@ __global__ __launch_bounds__(256) void k_nrc_gather(const float* __restrict__ X_
 }
 
 // ------------------------------------------------------------- launchers
-hipError_t nrc_launch_pack(const float* w, uint4* fwd, uint4* bwd, uint32_t* t_step, const uint32_t* n_records,
-                           hipStream_t st) {
-  int total = (kNrcFwdFrags + kNrcBwdFrags) * 64;
-  hipLaunchKernelGGL(k_nrc_pack, dim3((total + 255) / 256), dim3(256), 0, st, w, fwd, bwd, t_step, n_records);
+hipError_t nrc_launch_pack(const float* w, const float* wi, uint4* fwd, uint4* bwd, uint4* inf, uint32_t* t_step,
+                           const uint32_t* n_records, hipStream_t st) {
+  int total = (2 * kNrcFwdFrags + kNrcBwdFrags) * 64;
+  hipLaunchKernelGGL(k_nrc_pack, dim3((total + 255) / 256), dim3(256), 0, st, w, wi, fwd, bwd, inf, t_step,
+                     n_records);
   return hipGetLastError();
 }
 
@@ -580,11 +604,11 @@ hipError_t nrc_launch_train(const float* X, const float* T, int N, int npad, int
   return hipGetLastError();
 }
 
-hipError_t nrc_launch_adam(float* w, float* m, float* v, const float* dw_part, int n_split, float* grad_out, float lr,
-                           float b1, float b2, float eps, const uint32_t* t_step, const uint32_t* n_records, int apply,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(k_nrc_adam, dim3((kNrcParams + 255) / 256), dim3(256), 0, st, w, m, v, dw_part, n_split, grad_out,
-                     lr, b1, b2, eps, t_step, n_records, apply);
+hipError_t nrc_launch_adam(float* w, float* m, float* v, float* e, float* wi, const float* dw_part, int n_split,
+                           float* grad_out, float lr, float b1, float b2, float eps, float ema, const uint32_t* t_step,
+                           const uint32_t* n_records, int apply, hipStream_t st) {
+  hipLaunchKernelGGL(k_nrc_adam, dim3((kNrcParams + 255) / 256), dim3(256), 0, st, w, m, v, e, wi, dw_part, n_split,
+                     grad_out, lr, b1, b2, eps, ema, t_step, n_records, apply);
   return hipGetLastError();
 }
 

@@ -51,7 +51,8 @@ class pt_stats(C.Structure):
                 ("tail_extension_rays", C.c_int64), ("tail_node_visits", C.c_int64), ("tail_tri_tests", C.c_int64),
                 ("ms_tail", C.c_double), ("launches_tail", C.c_int64),
                 ("tail_shadow_rays", C.c_int64), ("tail_shadow_node_visits", C.c_int64),
-                ("tail_shadow_tri_tests", C.c_int64)]
+                ("tail_shadow_tri_tests", C.c_int64), ("ms_display", C.c_double), ("launches_display", C.c_int64),
+                ("instances_entered", C.c_int64), ("tail_instances_entered", C.c_int64)]
 
 
 class pt_bvh_info(C.Structure):
@@ -63,18 +64,19 @@ class pt_bvh_info(C.Structure):
 class pt_radiance_cache_config(C.Structure):
     _fields_ = [("query_bounce", C.c_int32), ("train_paths", C.c_int32), ("batch_size", C.c_int32),
                 ("steps_per_frame", C.c_int32), ("learning_rate", C.c_float), ("beta1", C.c_float),
-                ("beta2", C.c_float), ("epsilon", C.c_float), ("init_seed", C.c_uint64)]
+                ("beta2", C.c_float), ("epsilon", C.c_float), ("init_seed", C.c_uint64), ("ema_decay", C.c_float)]
 
 
 NRC_PARAMS = 5 * 64 * 64 + 3 * 64
 
 
 def cache_config(query_bounce=2, train_paths=1 << 16, batch_size=1 << 14, steps_per_frame=4, learning_rate=1e-3,
-                 beta1=0.9, beta2=0.99, epsilon=1e-8, init_seed=0):
+                 beta1=0.9, beta2=0.99, epsilon=1e-8, init_seed=0, ema_decay=0.0):
     c = pt_radiance_cache_config()
     c.query_bounce, c.train_paths, c.batch_size, c.steps_per_frame = query_bounce, train_paths, batch_size, \
         steps_per_frame
     c.learning_rate, c.beta1, c.beta2, c.epsilon, c.init_seed = learning_rate, beta1, beta2, epsilon, init_seed
+    c.ema_decay = ema_decay
     return c
 
 
@@ -93,6 +95,8 @@ _SIGS = {
                                   C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p]),
     "pt_trace_closest": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32]),
     "pt_trace_closest_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32]),
+    "pt_display": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
+    "pt_set_accumulation": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int64]),
     "pt_get_stats": (C.c_int, [C.c_void_p, C.POINTER(pt_stats)]),
     "pt_reset_stats": (C.c_int, [C.c_void_p]),
     "pt_set_profiling": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
@@ -100,6 +104,7 @@ _SIGS = {
     "pt_set_radiance_cache": (C.c_int, [C.c_void_p, C.POINTER(pt_radiance_cache_config)]),
     "pt_nrc_set_weights": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
     "pt_nrc_get_weights": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]),
+    "pt_nrc_get_inference_weights": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pt_nrc_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "pt_nrc_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                                   C.POINTER(C.c_double)]),
@@ -243,6 +248,10 @@ class PtScene:
     def nrc_set_weights(self, w):
         _check(_lib.pt_nrc_set_weights(self.h, w.data_ptr(), w.numel()))
 
+    def nrc_get_inference_weights(self, w):
+        _check(_lib.pt_nrc_get_inference_weights(self.h, w.data_ptr()))
+        return w
+
     def nrc_get_weights(self, w=None, m=None, v=None):
         step = C.c_int64(0)
         _check(_lib.pt_nrc_get_weights(self.h, None if w is None else w.data_ptr(),
@@ -276,6 +285,15 @@ class PtScene:
         _check(_lib.pt_trace_closest(self.h, rays.data_ptr(), rays.shape[0], hits.data_ptr(),
                                      1 if brute_force else 0))
         return hits
+
+    def set_accumulation(self, sums, samples):
+        """sums: float64 [h][w][3] device tensor holding the sums of `samples` samples per pixel."""
+        _check(_lib.pt_set_accumulation(self.h, sums.data_ptr(), sums.shape[1], sums.shape[0], samples))
+
+    def display(self, rgba8=None, encoded=None, exposure=1.0):
+        """rgba8: uint8 [h][w][4] (or int32 [h][w]) device tensor; encoded: float32 [h][w][3]."""
+        _check(_lib.pt_display(self.h, float(exposure), None if rgba8 is None else rgba8.data_ptr(),
+                               None if encoded is None else encoded.data_ptr()))
 
     def trace_closest_noalloc(self, rays, hits, brute_force=False):
         _check(_lib.pt_trace_closest_noalloc(self.h, rays.data_ptr(), rays.shape[0], hits.data_ptr(),

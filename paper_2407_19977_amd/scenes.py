@@ -636,3 +636,26 @@ def plane(rho=(0.3, 0.5, 0.7), L=2.0, width=32, height=32, spp=8, max_depth=4, s
     cam = Camera((0.0, 1.0, 0.0), (0.0, 0.6, -2.0), (0.0, 1.0, 0.0), 60.0, width, height)
     return Scene("plane", [b.mesh()], [], np.stack([lambert(rho)]),
                  uniform_env(L, upper_only=True), cam, spp, max_depth, seed)
+
+
+def display_sums(width=1920, height=1080, samples=64, seed=0) -> np.ndarray:
+    """Seeded FP64 per-pixel sums [height, width, 3] of `samples` samples for
+    the display path: mean radiance log-uniform over [1e-4, 1e3] per pixel,
+    with colour ratios U[0.05, 1] per channel, plus rows of special values
+    (black, exact greys from 0 to 20, the values 0.08 and 0.76 + 0.04 in
+    every channel, one dark channel, and a ramp of greys that steps across
+    8-bit code boundaries).  Data only; no display arithmetic."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    mag = 10.0 ** r.uniform(-4.0, 3.0, size=(height, width, 1))
+    mean = mag * r.uniform(0.05, 1.0, size=(height, width, 3))
+    specials = [np.zeros(3), np.full(3, 0.08), np.full(3, 0.8), np.array([0.0, 0.5, 2.0]),
+                np.array([0.079, 0.3, 0.9]), np.array([1e-9, 1e-9, 1e-9]), np.array([50.0, 0.1, 0.1])]
+    k = 0
+    for y in range(min(height, 4)):
+        for x in range(width):
+            if k < len(specials):
+                mean[y, x] = specials[k]
+            else:
+                mean[y, x] = np.full(3, 20.0 * (k - len(specials)) / max(1, 4 * width - len(specials)))
+            k += 1
+    return mean * float(samples)

@@ -187,7 +187,7 @@ def _batch(O, seed, frame, step, n, B):
 def test_two_adam_steps_match_oracle(P, O):
     _say("[nrc adam] 2 steps, batch 2048 from 5000 records")
     sc, s, _ = _cache_scene(P, O, "cornell", scenes.cornell,
-                            P.cache_config(batch_size=2048, steps_per_frame=2))
+                            P.cache_config(batch_size=2048, steps_per_frame=2, ema_decay=0.99))
     w = _weights(O, 3)
     s.nrc_set_weights(_dev(w))
     n, seed, frame = 5000, 9, 6
@@ -231,6 +231,45 @@ def test_two_adam_steps_match_oracle(P, O):
     assert dw[good].max() <= 0.05 * lr
     em = np.linalg.norm(mg.cpu().numpy() - m) / np.linalg.norm(m)
     assert em <= 2e-2, em
+    # inference weights: the bias-corrected moving average (decay 0.99) of the two steps' weights
+    wi = torch.empty_like(wg)
+    s.nrc_get_inference_weights(wi)
+    wr1 = w.astype(np.float64)
+    e = np.zeros_like(wr1)
+    mm, vv = np.zeros_like(wr1), np.zeros_like(wr1)
+    for k in range(2):
+        wr1, mm, vv = N.adam(wr1, mm, vv, g_steps[k], k + 1)
+        e = N.ema_update(e, wr1, 0.99)
+    wi_ref = N.ema_weights(e, 2, 0.99, wr1)
+    di = np.abs(wi.cpu().numpy() - wi_ref)
+    _say(f"[nrc adam] inference weights |wi_gpu - wi_ref| / lr: p99 {np.quantile(di, 0.99) / lr:.3e} "
+         f"max {di.max() / lr:.3e}")
+    assert np.quantile(di, 0.99) <= 0.05 * lr
+    assert di[good].max() <= 0.05 * lr
+    # the average of two steps is not the latest weights
+    assert np.abs(wi.cpu().numpy() - wg.cpu().numpy()).max() > 0.1 * lr
+
+
+def test_inference_weights_without_moving_average_are_the_weights(P, O):
+    """ema_decay 0: after Adam steps the cache queries use the weights themselves."""
+    sc, s, _ = _cache_scene(P, O, "cornell", scenes.cornell,
+                            P.cache_config(batch_size=512, steps_per_frame=3, ema_decay=0.0))
+    s.nrc_set_weights(_dev(_weights(O, 4)))
+    n = 700
+    X = _inputs(n, 17)
+    T = np.random.Generator(np.random.PCG64(18)).uniform(0, 2, (n, 3)).astype(np.float32)
+    s.nrc_train(_dev(X), _dev(T), 2, 5)
+    wg = torch.empty(P.NRC_PARAMS, dtype=torch.float32, device="cuda:0")
+    wi = torch.empty_like(wg)
+    assert s.nrc_get_weights(wg) == 3
+    s.nrc_get_inference_weights(wi)
+    assert torch.equal(wg, wi)
+    # and the forward call answers with them
+    y = torch.empty((n, 3), dtype=torch.float32, device="cuda:0")
+    s.nrc_forward(_dev(X), y)
+    ref, _ = N.forward(wg.cpu().numpy().astype(np.float64), X.astype(np.float64), use_bf16=True)
+    scale = math.sqrt(float((ref ** 2).mean()))
+    assert np.quantile(np.abs(y.cpu().numpy() - ref) / (np.abs(ref) + scale), 0.999) <= 1e-4
 
 
 # -------------------------------------------------------------------- paths --

@@ -245,6 +245,42 @@ def test_adam_impulse_gradient_closed_form():
     assert abs(abs(steps[1]) - LR * (0.9 / 1.9) / math.sqrt(0.999 / 1.999)) > 1e-3 * abs(steps[1])
 
 
+# --------------------------------------------- moving average of weights --
+
+def _run_ema(ws, alpha):
+    e = np.zeros(1)
+    out = []
+    for t, w in enumerate(ws, start=1):
+        e = N.ema_update(e, np.array([w]), alpha)
+        out.append(float(N.ema_weights(e, t, alpha, np.array([w]))[0]))
+    return out
+
+
+def test_ema_of_constant_weights_is_the_weights():
+    # e_t = (1 - a^t) w: the bias correction returns w exactly at every step
+    for a in (0.5, 0.9, 0.99):
+        for v in _run_ema([1.75] * 12, a):
+            assert v == pytest.approx(1.75, rel=1e-13)
+
+
+def test_ema_of_linear_drift_closed_form():
+    # w_t = t d: e_t / d = t (1 - a^t) - a (1 - t a^(t-1) + (t-1) a^t) / (1 - a)
+    d = 0.3
+    for a in (0.5, 0.9, 0.99):
+        got = _run_ema([d * t for t in range(1, 11)], a)
+        for t, v in enumerate(got, start=1):
+            e = d * (t * (1 - a ** t) - a * (1 - t * a ** (t - 1) + (t - 1) * a ** t) / (1 - a))
+            assert v == pytest.approx(e / (1 - a ** t), rel=1e-12)
+    # the average lags the drift: at t = 2 with a = 0.9 it is (2 - a - a^2) d / (1 - a^2) = 1.4737 d
+    assert _run_ema([d, 2 * d], 0.9)[1] == pytest.approx(d * (2 - 0.9 - 0.81) / (1 - 0.81), rel=1e-12)
+
+
+def test_ema_off_and_before_the_first_step_is_the_weights():
+    assert _run_ema([0.1, -4.0, 2.5], 0.0) == [0.1, -4.0, 2.5]
+    w = np.array([0.25, -1.0])
+    assert np.array_equal(N.ema_weights(np.zeros(2), 0, 0.99, w), w)
+
+
 # -------------------------------------------------------------- bfloat16 --
 
 def _bf16_by_definition(f32):

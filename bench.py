@@ -135,7 +135,7 @@ def _frames(s, cam, depth, seed, frames, ref, out, torch):
         d = out.double() - ref
         mse = torch.mean(d * d).item()
         rel = torch.mean(d * d / (ref * ref + 0.01)).item()
-        rows.append((cp, t * 1e3, mse, rel))
+        rows.append((cp, t * 1e3, mse, rel, torch.mean(d).item()))
     return rows
 
 
@@ -147,7 +147,8 @@ def _average(runs):
         ms = sum(r[k][1] for r in runs) / len(runs)
         mse = sum(r[k][2] for r in runs) / len(runs)
         rel = sum(r[k][3] for r in runs) / len(runs)
-        out.append((cp, ms, math.sqrt(mse), rel))
+        bias = sum(r[k][4] for r in runs) / len(runs)
+        out.append((cp, ms, math.sqrt(mse), rel, bias))
     return out
 
 
@@ -176,35 +177,19 @@ def _error_at(rows, ms_target, col=2):
     return None
 
 
-def cache_experiment(pt, torch, sc, frames=256, ref_spp=4096, seeds=4, **cache_kw):
-    """Plain vs radiance-cache rendering, frames of 1 spp (consecutive frames
-    of one call overlap in both modes), MSE against a ref_spp plain render with
-    FP64 sums and an independent seed, averaged over `seeds` independent runs
-    (sample seeds 0..seeds-1; the cache also starts from a different initial
-    network per run).  The cache's first frame renders plain (nothing is
-    trained yet), so its curve enters the time-to-target search from frame 2
-    on.  Bias floor: with MSE(N) = V / N + B^2 per mode, B^2 from the averaged
-    MSE at N1 = frames / 4 and N2 = frames."""
-    cam = sc.camera
-    W, H, depth = cam.width, cam.height, sc.max_depth
-    s = pt.scene_from(sc, device=0)
-    out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda:0")
-    acc = torch.empty((H, W, 3), dtype=torch.float64, device="cuda:0")
-    ref_seed = 1000
-    s.set_radiance_cache(None)
-    s.reset_accumulation()
-    chunk = 256
-    for k in range(0, ref_spp, chunk):
-        s.accumulate(cam, k, min(chunk, ref_spp - k), depth, ref_seed)
-    s.resolve(out, acc)
-    ref = acc / ref_spp
-    print(f"[cache] reference: {ref_spp} spp plain, seed {ref_seed}", file=sys.stderr, flush=True)
-    s.set_profiling(True, False)
-    plain_runs, cache_runs = [], []
+CACHE_VARIANTS = (
+    ("refinements of the cited method: adaptive termination (spread 0.01) by vertex 2, training paths "
+     "ending in the cache at vertex 3 (self-training), factorised by the reflectance",
+     {"spread_c": 0.01, "train_end_bounce": 3, "factorize": 1}),
+    ("adaptive termination only (spread 0.01)", {"spread_c": 0.01}),
+)
+
+
+def _cache_runs(pt, s, cam, depth, frames, seeds, ref, out, torch, cache_kw):
+    """Frames of the cache for each seed (fresh network per seed); statistics summed over the runs."""
+    runs = []
     st_all = {"cache_queries": 0, "cache_records": 0, "ms_cache_query": 0.0, "ms_cache_train": 0.0, "steps": 0}
     for seed in range(seeds):
-        s.set_radiance_cache(None)
-        plain_runs.append(_frames(s, cam, depth, seed, frames, ref, out, torch))
         # untimed cache frames allocate the cache's buffers (the first frame runs alone, later ones
         # overlap on two path sets); configuring again resets weights and Adam state
         s.set_radiance_cache(pt.cache_config(init_seed=seed, **cache_kw))
@@ -212,25 +197,17 @@ def cache_experiment(pt, torch, sc, frames=256, ref_spp=4096, seeds=4, **cache_k
         s.accumulate(cam, 0, 3, depth, seed)
         s.set_radiance_cache(pt.cache_config(init_seed=seed, **cache_kw))
         s.reset_stats()
-        cache_runs.append(_frames(s, cam, depth, seed, frames, ref, out, torch))
+        runs.append(_frames(s, cam, depth, seed, frames, ref, out, torch))
         st = s.stats()
         for k in ("cache_queries", "cache_records", "ms_cache_query", "ms_cache_train"):
             st_all[k] += st[k]
         st_all["steps"] += st["cache_adam_steps"]
-        print(f"[cache] seed {seed}: plain {plain_runs[-1][-1]}  cache {cache_runs[-1][-1]}", file=sys.stderr,
-              flush=True)
-    # the query kernel alone: frames of one call each (nothing beside them), 8 of them
-    s.reset_stats()
-    for k in range(8):
-        s.accumulate(cam, frames + k, 1, depth, 0)
-    st_iso = s.stats()
-    s.set_radiance_cache(None)
-    plain, cache = _average(plain_runs), _average(cache_runs)
-    table = [{"spp": a[0], "plain_ms": round(a[1], 2), "plain_rmse": round(a[2], 6), "plain_relmse": round(a[3], 6),
-              "cache_ms": round(b[1], 2), "cache_rmse": round(b[2], 6), "cache_relmse": round(b[3], 6),
-              "cache_frame_trained": a[0] > 1}
-             for a, b in zip(plain, cache)]
+        print(f"[cache] {cache_kw or 'defaults'} seed {seed}: {runs[-1][-1]}", file=sys.stderr, flush=True)
+    return runs, st_all
 
+
+def _compare(plain, cache, frames, seeds, ref_mean):
+    """Time to the plain tracer's RMSE / relMSE at 4, 16 and 64 spp, RMSE at equal time, bias measures."""
     def floor(rows):
         n1 = max(1, frames // 4)
         r1 = [r for r in rows if r[0] == n1]
@@ -262,6 +239,74 @@ def cache_experiment(pt, torch, sc, frames=256, ref_spp=4096, seeds=4, **cache_k
 
     def at(rows):
         return rows[-1][2] if rows[-1][1] <= t_eq else _error_at(rows, t_eq)
+    return {
+        "time_to_equal_rmse": tte,
+        "rmse_at_equal_time": {"ms": round(t_eq, 2), "plain": None if at(plain) is None else round(at(plain), 6),
+                               "cache": None if at(trained) is None else round(at(trained), 6)},
+        "mean_bias": {"cache": round(cache[-1][4] / ref_mean, 6), "plain": round(plain[-1][4] / ref_mean, 6),
+                      "what": f"(mean of the {frames}-spp image - mean of the reference) / mean of the reference, "
+                              f"averaged over seeds"},
+        "bias_floor_rmse": {"cache": None if bias_cache is None else round(bias_cache, 6),
+                            "plain": None if bias_plain is None else round(bias_plain, 6),
+                            "method": f"MSE(N) = V/N + B^2 fitted through the seed-averaged MSE at N = "
+                                      f"{max(1, frames // 4)} and {frames}; the plain tracer's B is the "
+                                      f"reference's own error"},
+        "ms_per_frame_plain": round(plain[-1][1] / plain[-1][0], 3),
+        "ms_per_frame_cache": round(cache[-1][1] / cache[-1][0], 3),
+    }
+
+
+def cache_experiment(pt, torch, sc, frames=256, ref_spp=4096, seeds=4, variants=CACHE_VARIANTS, **cache_kw):
+    """Plain vs radiance-cache rendering, frames of 1 spp (consecutive frames
+    of one call overlap in both modes), MSE against a ref_spp plain render with
+    FP64 sums and an independent seed, averaged over `seeds` independent runs
+    (sample seeds 0..seeds-1; the cache also starts from a different initial
+    network per run).  The cache's first frame renders plain (nothing is
+    trained yet), so its curve enters the time-to-target search from frame 2
+    on.  Bias floor: with MSE(N) = V / N + B^2 per mode, B^2 from the averaged
+    MSE at N1 = frames / 4 and N2 = frames.  The main comparison uses the
+    library's cache settings (overridden by cache_kw); each variant changes
+    some of them and is compared against the same plain runs."""
+    cam = sc.camera
+    W, H, depth = cam.width, cam.height, sc.max_depth
+    s = pt.scene_from(sc, device=0)
+    out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda:0")
+    acc = torch.empty((H, W, 3), dtype=torch.float64, device="cuda:0")
+    ref_seed = 1000
+    s.set_radiance_cache(None)
+    s.reset_accumulation()
+    chunk = 256
+    for k in range(0, ref_spp, chunk):
+        s.accumulate(cam, k, min(chunk, ref_spp - k), depth, ref_seed)
+    s.resolve(out, acc)
+    ref = acc / ref_spp
+    ref_mean = ref.mean().item()
+    print(f"[cache] reference: {ref_spp} spp plain, seed {ref_seed}", file=sys.stderr, flush=True)
+    s.set_profiling(True, False)
+    plain_runs = []
+    for seed in range(seeds):
+        s.set_radiance_cache(None)
+        plain_runs.append(_frames(s, cam, depth, seed, frames, ref, out, torch))
+    plain = _average(plain_runs)
+    cache_runs, st_all = _cache_runs(pt, s, cam, depth, frames, seeds, ref, out, torch, cache_kw)
+    cache = _average(cache_runs)
+    # the query kernel alone: frames of one call each (nothing beside them), 8 of them
+    s.reset_stats()
+    for k in range(8):
+        s.accumulate(cam, frames + k, 1, depth, 0)
+    st_iso = s.stats()
+    var_out = []
+    for name, kw in variants:
+        vruns, _ = _cache_runs(pt, s, cam, depth, frames, seeds, ref, out, torch, {**kw, **cache_kw})
+        v = _average(vruns)
+        ent = {"name": name, "settings": kw, "rmse_final": round(v[-1][2], 6)}
+        ent.update(_compare(plain, v, frames, seeds, ref_mean))
+        var_out.append(ent)
+    s.set_radiance_cache(None)
+    table = [{"spp": a[0], "plain_ms": round(a[1], 2), "plain_rmse": round(a[2], 6), "plain_relmse": round(a[3], 6),
+              "cache_ms": round(b[1], 2), "cache_rmse": round(b[2], 6), "cache_relmse": round(b[3], 6),
+              "cache_frame_trained": a[0] > 1}
+             for a, b in zip(plain, cache)]
     q_ms = st_iso["ms_cache_query"]
     achieved = st_iso["cache_queries"] * NRC_FLOP_PER_QUERY / (q_ms * 1e-3) / 1e12 if q_ms > 0 else None
     q_ms_frames = st_all["ms_cache_query"]
@@ -271,20 +316,16 @@ def cache_experiment(pt, torch, sc, frames=256, ref_spp=4096, seeds=4, **cache_k
     train_samples = st_all["steps"] * cfg.batch_size
     result = {
         "workload": f"icosphere field {W}x{H}, depth {depth}, frames of 1 spp; cache: 64-feature encoding, "
-                    "5x64 ReLU MLP (bf16 matrix cores), query at vertex 2, 65,536 training paths and "
+                    "5x64 ReLU MLP (bf16 matrix cores), paths end in it by vertex 2, 65,536 training paths and "
                     "4 Adam steps of 16,384 records per frame",
         "reference": f"{ref_spp} spp plain tracer, FP64 sums, seed {ref_seed}",
         "seeds": seeds,
         "cache_config": {k: getattr(cfg, k) for k, _ in cfg._fields_},
         "rmse": table,
-        "time_to_equal_rmse": tte,
-        "rmse_at_equal_time": {"ms": round(t_eq, 2), "plain": None if at(plain) is None else round(at(plain), 6),
-                               "cache": None if at(trained) is None else round(at(trained), 6)},
-        "bias_floor_rmse": {"cache": None if bias_cache is None else round(bias_cache, 6),
-                            "plain": None if bias_plain is None else round(bias_plain, 6),
-                            "method": f"MSE(N) = V/N + B^2 fitted through the seed-averaged MSE at N = {max(1, frames // 4)} and {frames}"},
-        "ms_per_frame_plain": round(plain[-1][1] / plain[-1][0], 3),
-        "ms_per_frame_cache": round(cache[-1][1] / cache[-1][0], 3),
+    }
+    result.update(_compare(plain, cache, frames, seeds, ref_mean))
+    result.update({
+        "variants": var_out,
         "cache_queries_per_s": round(st_all["cache_queries"] / (sum(r[-1][1] for r in cache_runs) * 1e-3), 1),
         "training_records_per_frame": st_all["cache_records"] // (frames * seeds),
         "training_samples_per_s": round(train_samples / (st_all["ms_cache_train"] * 1e-3), 1)
@@ -298,7 +339,7 @@ def cache_experiment(pt, torch, sc, frames=256, ref_spp=4096, seeds=4, **cache_k
             "avg_launch_ms": round(q_ms / 8, 4),
             "measured_on": "8 frames of one call each (the query kernel with nothing beside it)",
             "in_overlapped_frames_tflops": None if achieved_frames is None else round(achieved_frames, 2)},
-    }
+    })
     s.close()
     return result
 
@@ -423,7 +464,9 @@ def instanced_1080p(pt, torch, spp, tail=None):
 
 def _cache_kw(args):
     """Cache settings given on the command line (the library's defaults otherwise)."""
-    return {} if args.cache_ema is None else {"ema_decay": args.cache_ema}
+    kw = {"ema_decay": args.cache_ema, "train_end_bounce": args.cache_train_end, "factorize": args.cache_factorize,
+          "query_bounce": args.cache_query_bounce, "spread_c": args.cache_spread}
+    return {k: v for k, v in kw.items() if v is not None}
 
 
 def _tail_args(args):
@@ -500,6 +543,11 @@ def main():
     ap.add_argument("--ref-spp", type=int, default=4096)
     ap.add_argument("--instanced-spp", type=int, default=256)
     ap.add_argument("--cache-ema", type=float, default=None, help="ema_decay of the cache (library default if omitted)")
+    ap.add_argument("--cache-train-end", type=int, default=None,
+                    help="train_end_bounce of the cache: vertex at which training paths end in it (self-training)")
+    ap.add_argument("--cache-factorize", type=int, default=None, help="factorize of the cache (0 or 1)")
+    ap.add_argument("--cache-query-bounce", type=int, default=None, help="query_bounce of the cache")
+    ap.add_argument("--cache-spread", type=float, default=None, help="spread_c of the cache (adaptive termination)")
     ap.add_argument("--workload", choices=["spheres-1080p", "instanced-4k", "cache", "instanced-1080p"],
                     default="spheres-1080p",
                     help="instanced-4k: plain vs cache on the instanced scene at 3840x2160 (minutes); cache: only "

@@ -271,6 +271,21 @@ typedef struct pt_radiance_cache_config {
   float ema_decay;         /* [0, 1): after each Adam step t the moving average e = ema_decay e +
                               (1 - ema_decay) w (e starts at 0) is updated and the cache queries use
                               e / (1 - ema_decay^t); 0 uses the weights themselves (0) */
+  int32_t train_end_bounce; /* self-training, >= -1: once the cache has weights, a training path
+                              that reaches this vertex below max_depth ends there in the cache (no
+                              record at that vertex; beta * cache(x) joins its radiance before the
+                              targets of its earlier vertices are formed); -1: plain training paths
+                              to max_depth (-1) */
+  float spread_c;          /* >= 0: adaptive termination of the cited method: a sampling path ends in the
+                              cache at the first vertex b >= 1 where (sum over its non-delta bounces of
+                              sqrt(t_i^2 / (pdf_i |cos theta_i|)))^2 > spread_c * t_0^2 / (4 pi
+                              |cos theta_0|) (t: hit distance, pdf: solid-angle pdf of the bounce
+                              into that vertex, theta: angle to the geometric normal there), and at
+                              query_bounce at the latest; 0: always at query_bounce (0) */
+  int32_t factorize;       /* 0 or 1: the network predicts radiance divided, per channel, by
+                              (diffuse albedo + specular luminance) of the vertex (inputs 8..10 and
+                              11); queries multiply by that factor, targets are divided by it and
+                              dropped where it is zero (0) */
 } pt_radiance_cache_config;
 
 /* Configure (cfg != NULL) or switch off (cfg == NULL) the cache.  Weights

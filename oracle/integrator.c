@@ -128,6 +128,9 @@ static int trace_impl(const oracle_scene* s, const oracle_camera* cam, int32_t p
   v3 o = V(o_[0], o_[1], o_[2]), d = V(d_[0], d_[1], d_[2]);
   int prev_delta = 1;
   double pdf_prev = 0.0, eta_scale = 1.0;
+  /* path spread of the cited cache method: primary footprint a0 and the running sum of the
+   * per-bounce spread terms */
+  double spread_a0 = 0.0, spread_sum = 0.0;
   int32_t skip_inst = -1, skip_prim = -1;
   const double tmin = s->tmin;
   for (int b = 0;; ++b) {
@@ -210,13 +213,29 @@ static int trace_impl(const oracle_scene* s, const oracle_camera* cam, int32_t p
     v3 t, bt;
     make_frame(I, n, &t, &bt);
     v3 wo = V(vdot(wo_w, t), vdot(wo_w, bt), vdot(wo_w, n));
-    if (opt && opt->nrc_weights && b == opt->nrc_bounce) {
-      /* the path ends in the radiance cache: outgoing radiance without emission */
+    int spread_end = 0;
+    if (opt && opt->nrc_weights && !rec_x && opt->spread_c > 0.0 && b <= opt->nrc_bounce) {
+      double ac = fabs(cos_ng);
+      if (b == 0) {
+        spread_a0 = h.t * h.t / (4.0 * O_PI * ac);
+      } else {
+        if (!prev_delta) spread_sum += sqrt(h.t * h.t / (pdf_prev * ac));
+        spread_end = spread_sum * spread_sum > opt->spread_c * spread_a0;
+      }
+    }
+    int to_cache = opt && opt->nrc_weights &&
+                   (rec_x ? (opt->train_end >= 0 && b == opt->train_end) : (b == opt->nrc_bounce || spread_end));
+    if (to_cache) {
+      /* the path ends in the radiance cache: outgoing radiance without emission (a training
+       * path ending so is self-training: its earlier vertices' targets include this answer) */
       double x[12], y[3];
       onrc_inputs(s, p, wo_w, n, mat, x);
       oracle_nrc_forward(opt->nrc_weights, x, opt->nrc_bf16, y);
-      double c[3] = {beta[0] * (y[0] > 0.0 ? y[0] : 0.0), beta[1] * (y[1] > 0.0 ? y[1] : 0.0),
-                     beta[2] * (y[2] > 0.0 ? y[2] : 0.0)};
+      double c[3];
+      for (int k = 0; k < 3; ++k) {
+        double f = opt->nrc_factor ? x[8 + k] + x[11] : 1.0;
+        c[k] = beta[k] * f * (y[k] > 0.0 ? y[k] : 0.0);
+      }
       add_finite(L, c, st);
       sig_word(&sig, 6);
       sig_word(&sig, 4);
@@ -323,21 +342,37 @@ int oracle_trace_path(const oracle_scene* s, const oracle_camera* cam, int32_t p
 }
 
 int oracle_training_records(const oracle_scene* s, const oracle_camera* cam, int32_t px, int32_t py,
-                            int32_t sample, int32_t max_depth, uint64_t seed, double* inputs, double* targets,
-                            int32_t* n) {
+                            int32_t sample, int32_t max_depth, uint64_t seed, const oracle_options* opt,
+                            double* inputs, double* targets, int32_t* n) {
   if (!s || !cam || !inputs || !targets || !n || max_depth < 0 || max_depth > 1024) return -1;
   double rgb[3];
   double* L = (double*)malloc(sizeof(double) * 3 * (size_t)(max_depth + 1));
   double* B = (double*)malloc(sizeof(double) * 3 * (size_t)(max_depth + 1));
   int32_t k = 0;
-  int rc = trace_impl(s, cam, px, py, sample, max_depth, seed, NULL, rgb, NULL, NULL, inputs, L, B, &k);
+  /* a training path never ends at the sampling paths' query vertex */
+  oracle_options o;
+  memset(&o, 0, sizeof o);
+  if (opt) {
+    o = *opt;
+  } else {
+    o.estimator = ORACLE_MIS;
+    o.russian_roulette = 1;
+    o.n_threads = 1;
+    o.train_end = -1;
+  }
+  o.nrc_bounce = -1;
+  int factor = opt && opt->nrc_factor;
+  int rc = trace_impl(s, cam, px, py, sample, max_depth, seed, &o, rgb, NULL, NULL, inputs, L, B, &k);
   int32_t m = 0;
   for (int32_t i = 0; rc == 0 && i < k; ++i) {
     if (!(B[3 * i] != 0.0 && B[3 * i + 1] != 0.0 && B[3 * i + 2] != 0.0)) continue;
     double tg[3];
     int ok = 1;
+    const double* xi = inputs + 12 * i;
     for (int c = 0; c < 3; ++c) {
-      tg[c] = (rgb[c] - L[3 * i + c]) / B[3 * i + c];
+      double f = factor ? xi[8 + c] + xi[11] : 1.0;
+      if (f == 0.0) ok = 0;
+      tg[c] = (rgb[c] - L[3 * i + c]) / B[3 * i + c] / f;
       if (!isfinite(tg[c])) ok = 0;
     }
     if (!ok) continue;

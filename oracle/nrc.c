@@ -14,8 +14,10 @@
  * Encoding to 64 features: for each position axis and k = 0..5 the pair
  * sin(2^k pi x), cos(2^k pi x) (36); one-blob encodings with 4 bins of the
  * four direction coordinates (16) and of 1 - exp(-roughness) (4), bin i of s
- * being exp(-((s - (i + 1/2)/4) * 4)^2 / 2); the four albedo values (4); and
- * the constants 1, 0, 0, 0 (4).
+ * being exp(-(4 d)^2 / 2) with d = s - (i + 1/2)/4; for the two azimuths
+ * (inputs 4 and 6, periodic: 0 and 1 are the same direction) d is taken
+ * modulo 1 into [-1/2, 1/2); the four albedo values (4); and the constants
+ * 1, 0, 0, 0 (4).
  *
  * Network: 64 -> 64 x 5 hidden layers with ReLU -> 3 linear outputs, no
  * biases; weights W0..W4 (64 x 64) and W5 (3 x 64), row-major [out][in],
@@ -46,8 +48,10 @@ double oracle_bf16_round(double x) {
   return (double)f;
 }
 
-static double one_blob(double s, int i) {
-  double z = (s - (i + 0.5) / 4.0) * 4.0;
+static double one_blob(double s, int i, int periodic) {
+  double d = s - (i + 0.5) / 4.0;
+  if (periodic) d -= floor(d + 0.5);
+  double z = d * 4.0;
   return exp(-0.5 * z * z);
 }
 
@@ -59,9 +63,9 @@ void oracle_nrc_encode(const double x[12], double f[64]) {
       f[12 * a + 2 * k + 1] = cos(w);
     }
   for (int c = 0; c < 4; ++c)
-    for (int i = 0; i < 4; ++i) f[36 + 4 * c + i] = one_blob(x[3 + c], i);
+    for (int i = 0; i < 4; ++i) f[36 + 4 * c + i] = one_blob(x[3 + c], i, c & 1);
   double rr = 1.0 - exp(-x[7]);
-  for (int i = 0; i < 4; ++i) f[52 + i] = one_blob(rr, i);
+  for (int i = 0; i < 4; ++i) f[52 + i] = one_blob(rr, i, 0);
   for (int i = 0; i < 4; ++i) f[56 + i] = x[8 + i];
   f[60] = 1.0;
   f[61] = f[62] = f[63] = 0.0;
@@ -99,7 +103,8 @@ void onrc_inputs(const oracle_scene* s, v3 p, v3 wo, v3 n, const omat* m, double
   for (int d = 0; d < 2; ++d) {
     double yv = dirs[d].y < -1.0 ? -1.0 : (dirs[d].y > 1.0 ? 1.0 : dirs[d].y);
     x[3 + 2 * d] = acos(yv) / O_PI;
-    x[4 + 2 * d] = atan2(dirs[d].x, -dirs[d].z) / (2.0 * O_PI) + 0.5;
+    /* + 0.0 turns -0 into +0: a direction exactly at a pole gets azimuth 0 whatever the signs of its zeros */
+    x[4 + 2 * d] = atan2(dirs[d].x + 0.0, -dirs[d].z + 0.0) / (2.0 * O_PI) + 0.5;
   }
   x[7] = m->spec_rough;
   double k = (1.0 - m->metalness) * (1.0 - m->trans_weight) * m->base_weight;

@@ -63,13 +63,16 @@ def encode(X):
             F[:, 12 * a + 2 * k] = np.sin(w)
             F[:, 12 * a + 2 * k + 1] = np.cos(w)
 
-    def blob(s, i):
-        z = (s - (i + 0.5) / 4.0) * 4.0
+    def blob(s, i, periodic=False):
+        d = s - (i + 0.5) / 4.0
+        if periodic:  # the azimuths wrap: 0 and 1 are the same direction
+            d = d - np.floor(d + 0.5)
+        z = d * 4.0
         return np.exp(-0.5 * z * z)
 
     for c in range(4):
         for i in range(4):
-            F[:, 36 + 4 * c + i] = blob(X[:, 3 + c], i)
+            F[:, 36 + 4 * c + i] = blob(X[:, 3 + c], i, periodic=(c % 2 == 1))
     rr = 1.0 - np.exp(-X[:, 7])
     for i in range(4):
         F[:, 52 + i] = blob(rr, i)

@@ -60,6 +60,12 @@ typedef struct {
   const double* nrc_weights; /* radiance cache weights (20,672, see nrc.c) or NULL: plain paths */
   int32_t nrc_bounce;    /* vertex index at which paths end in the cache (2) */
   int32_t nrc_bf16;      /* 1: evaluate the cache with bfloat16 operands */
+  int32_t train_end;     /* training records: the path ends in the cache at this vertex (self-training; needs
+                            nrc_weights), -1: plain path to max_depth */
+  int32_t nrc_factor;    /* 1: the cache predicts radiance / (diffuse albedo + specular luminance) */
+  double spread_c;       /* > 0: adaptive termination (path spread): a rendering path ends in the cache at
+                            the first vertex b >= 1 whose spread exceeds spread_c times the primary
+                            footprint, at nrc_bounce at the latest; 0: always at nrc_bounce */
 } oracle_options;
 
 typedef struct {
@@ -121,13 +127,17 @@ void oracle_nrc_forward(const double* W, const double x[12], int32_t bf16, doubl
  * as its 27 OpenPBR floats. */
 void oracle_nrc_inputs(const double lo[3], const double hi[3], const double p[3], const double wo[3],
                        const double n[3], const float* mat27, double x[12]);
-/* Training records of one path (plain tracer): for every vertex k < max_depth
- * that scatters or absorbs, the 12 cache inputs and the target
- * (L_end - L_k) / beta_k; vertices with a zero throughput channel are dropped.
- * inputs [max_depth][12], targets [max_depth][3]; *n receives the count. */
+/* Training records of one path: for every vertex k < max_depth that scatters
+ * or absorbs, the 12 cache inputs and the target (L_end - L_k) / beta_k
+ * (divided by the reflectance factor with opt->nrc_factor); vertices with a
+ * zero throughput or factor channel are dropped.  With opt->train_end >= 0
+ * and weights, the path ends in the cache at that vertex (self-training):
+ * L_end = L_T + beta_T * cache(x_T) and no record at T.  opt may be NULL
+ * (plain path).  inputs [max_depth][12], targets [max_depth][3]; *n receives
+ * the count. */
 int oracle_training_records(const oracle_scene* s, const oracle_camera* cam, int32_t px, int32_t py,
-                            int32_t sample, int32_t max_depth, uint64_t seed, double* inputs, double* targets,
-                            int32_t* n);
+                            int32_t sample, int32_t max_depth, uint64_t seed, const oracle_options* opt,
+                            double* inputs, double* targets, int32_t* n);
 
 /* Test hook: the shading frame (t, b, n) at unit normal n of an instance
  * with object-to-world transform o2w (row-major 3x4; NULL = world space):

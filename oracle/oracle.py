@@ -50,7 +50,8 @@ class OCamera(C.Structure):
 class OOptions(C.Structure):
     _fields_ = [("estimator", C.c_int32), ("russian_roulette", C.c_int32), ("n_threads", C.c_int32),
                 ("verbose", C.c_int32), ("nrc_weights", C.c_void_p), ("nrc_bounce", C.c_int32),
-                ("nrc_bf16", C.c_int32)]
+                ("nrc_bf16", C.c_int32), ("train_end", C.c_int32), ("nrc_factor", C.c_int32),
+                ("spread_c", C.c_double)]
 
 
 class OStats(C.Structure):
@@ -128,7 +129,7 @@ def _declare(L):
     L.oracle_display.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_double, C.c_void_p, C.c_void_p]
     L.oracle_display.restype = None
     L.oracle_training_records.argtypes = [C.c_void_p, C.POINTER(OCamera), C.c_int32, C.c_int32, C.c_int32,
-                                          C.c_int32, C.c_uint64, _dp, _dp, C.POINTER(C.c_int32)]
+                                          C.c_int32, C.c_uint64, C.c_void_p, _dp, _dp, C.POINTER(C.c_int32)]
 
 
 def _d3(x):
@@ -367,7 +368,7 @@ class OracleScene:
         cam = camera_struct(camera or self.camera)
         w = None if nrc_weights is None else np.ascontiguousarray(nrc_weights, dtype=np.float64)
         opt = OOptions(estimator, 1 if rr else 0, 1, 1 if verbose else 0, None if w is None else w.ctypes.data,
-                       nrc_bounce, 1 if nrc_bf16 else 0)
+                       nrc_bounce, 1 if nrc_bf16 else 0, -1, 0)
         rgb = (C.c_double * 3)()
         sig = C.c_uint64()
         st = OStats()
@@ -378,7 +379,8 @@ class OracleScene:
         return np.array(rgb[:]), int(sig.value)
 
     def render(self, spp, max_depth, seed=0, crop=None, first_sample=0, estimator=MIS, rr=True,
-               per_sample=False, n_threads=None, camera=None, nrc_weights=None, nrc_bounce=2, nrc_bf16=False):
+               per_sample=False, n_threads=None, camera=None, nrc_weights=None, nrc_bounce=2, nrc_bf16=False,
+               nrc_factor=False, spread_c=0.0):
         """Returns dict(sum [h,w,3] f64, mean, per_sample [h,w,n,3], sigs [h,w,n] u64, stats)."""
         cam_py = camera or self.camera
         cam = camera_struct(cam_py)
@@ -386,7 +388,7 @@ class OracleScene:
         nt = n_threads or min(16, os.cpu_count() or 1)
         wts = None if nrc_weights is None else np.ascontiguousarray(nrc_weights, dtype=np.float64)
         opt = OOptions(estimator, 1 if rr else 0, nt, 0, None if wts is None else wts.ctypes.data, nrc_bounce,
-                       1 if nrc_bf16 else 0)
+                       1 if nrc_bf16 else 0, -1, 1 if nrc_factor else 0, float(spread_c))
         s = np.zeros((h, w, 3), dtype=np.float64)
         ps = np.zeros((h, w, spp, 3), dtype=np.float64) if per_sample else None
         sg = np.zeros((h, w, spp), dtype=np.uint64) if per_sample else None
@@ -400,14 +402,19 @@ class OracleScene:
                     stats=dict(extension_rays=st.extension_rays, shadow_rays=st.shadow_rays,
                                dropped_nonfinite=st.dropped_nonfinite, threads=nt))
 
-    def training_records(self, px, py, sample, max_depth, seed=0, camera=None):
-        """Cache training records of one plain path: (inputs [k,12], targets [k,3])."""
+    def training_records(self, px, py, sample, max_depth, seed=0, camera=None, nrc_weights=None, train_end=-1,
+                         nrc_bf16=False, factorize=False, rr=True):
+        """Cache training records of one path: (inputs [k,12], targets [k,3]).  With weights and
+        train_end >= 0 the path ends in the cache at that vertex (self-training)."""
         cam = camera_struct(camera or self.camera)
         x = np.zeros((max_depth + 1, 12))
         t = np.zeros((max_depth + 1, 3))
         n = C.c_int32()
-        rc = lib().oracle_training_records(self.h, C.byref(cam), px, py, sample, max_depth, seed, _dptr(x), _dptr(t),
-                                           C.byref(n))
+        wts = None if nrc_weights is None else np.ascontiguousarray(nrc_weights, dtype=np.float64)
+        opt = OOptions(MIS, 1 if rr else 0, 1, 0, None if wts is None else wts.ctypes.data, -1, 1 if nrc_bf16 else 0,
+                       train_end if wts is not None else -1, 1 if factorize else 0)
+        rc = lib().oracle_training_records(self.h, C.byref(cam), px, py, sample, max_depth, seed, C.byref(opt),
+                                           _dptr(x), _dptr(t), C.byref(n))
         assert rc == 0
         return x[:n.value].copy(), t[:n.value].copy()
 

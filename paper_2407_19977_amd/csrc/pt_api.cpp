@@ -87,7 +87,7 @@ bool finite_all(const float* p, size_t n) {
 struct PathBufs {
   int64_t capacity = 0, nrc_q_cap = 0;
   DevBuf ray_o, ray_d, hit, hit_inst, cls, beta, L, flags, q_ray[2], q_cls[kNumClasses], sh_o, sh_d, sh_c, sh_inst,
-      counts, sig, dbg_nee, dbg_tail, spill, nrc_q, q_nrc;
+      counts, sig, dbg_nee, dbg_tail, spill, nrc_q, q_nrc, spread;
 };
 
 struct pt_scene {
@@ -150,6 +150,7 @@ struct pt_scene {
   DevBuf nrc_t;            // Adam steps applied (one device word: steps with no records are skipped there)
   DevBuf nrc_w, nrc_m, nrc_v, nrc_fwd, nrc_bwd;  // FP32 master weights, Adam moments, bf16 fragments
   DevBuf nrc_e, nrc_wi, nrc_inf;  // moving average of the weights, inference weights, their bf16 fragments
+  DevBuf nrc_tail[2];  // per training path: beta * cache at its terminal vertex (self-training), per path set
   DevBuf nrc_rec[2];       // training records, per path set (frames overlap on two sets)
   DevBuf nrc_off, nrc_bsum, nrc_n, nrc_X, nrc_T;  // compaction
   int64_t nrc_rec_cap = 0;
@@ -327,6 +328,7 @@ pt_status ensure_paths(pt_scene* s, int64_t n, int set = 0) {
   PT_HIP(B.sig.alloc((size_t)n * sizeof(uint64_t)));
   PT_HIP(B.dbg_nee.alloc(u4));
   PT_HIP(B.dbg_tail.alloc(u4));
+  PT_HIP(B.spread.alloc((size_t)n * sizeof(float2)));
   B.capacity = n;
   return PT_OK;
 }
@@ -427,11 +429,15 @@ PathsDev paths_dev(pt_scene* s, int64_t n, int x0, int y0, int w, int set = 0) {
   P.sig = B.sig.as<uint64_t>();
   P.dbg_nee = B.dbg_nee.as<uint32_t>();
   P.dbg_tail = B.dbg_tail.as<uint32_t>();
+  P.spread = B.spread.as<float2>();
+  P.spread_c = s->nrc_on ? s->nrc_cfg.spread_c : 0.0f;
   P.n = (int32_t)n;
   P.n_render = (int32_t)n;
   P.x0 = x0;
   P.y0 = y0;
   P.w = w;
+  P.train_end = -1;
+  P.nrc_factor = s->nrc_on && s->nrc_cfg.factorize ? 1 : 0;
   return P;
 }
 
@@ -508,6 +514,10 @@ pt_status setup_training(pt_scene* s, const CamDev& C, PathsDev& P, int64_t n_re
   P.train_sample = 0x80000000u + frame;
   P.rec = s->nrc_rec[set].as<float>();
   P.rec_depth = max_depth;
+  // self-training: once the cache has weights, training paths end in it at train_end_bounce
+  const int te = s->nrc_cfg.train_end_bounce;
+  P.train_end = (s->nrc_ready && te >= 0 && te < max_depth) ? te : -1;
+  P.nrc_factor = s->nrc_cfg.factorize ? 1 : 0;
   return PT_OK;
 }
 
@@ -516,7 +526,12 @@ pt_status setup_training(pt_scene* s, const CamDev& C, PathsDev& P, int64_t n_re
 pt_status finish_training(pt_scene* s, const PathsDev& P, uint32_t* n_records, hipStream_t st,
                           bool count_stats = false) {
   const int n = P.n - P.n_render;
-  PT_HIP(nrc_launch_targets(P, n, s->nrc_off.as<uint32_t>(), s->nrc_bsum.as<uint32_t>(), s->nrc_X.as<float>(),
+  float4* tail = nullptr;
+  if (P.train_end >= 0) {  // the cache's answer at the training paths' terminal vertices
+    tail = s->nrc_tail[P.rec == s->nrc_rec[1].as<float>() ? 1 : 0].as<float4>();
+    PT_HIP(nrc_launch_terminal(P, n, s->nrc_inf.as<uint4>(), tail, st));
+  }
+  PT_HIP(nrc_launch_targets(P, n, tail, s->nrc_off.as<uint32_t>(), s->nrc_bsum.as<uint32_t>(), s->nrc_X.as<float>(),
                             s->nrc_T.as<float>(), s->nrc_n.as<uint32_t>(),
                             count_stats ? s->stats.as<unsigned long long>() : nullptr, st));
   if (n_records) {
@@ -1686,6 +1701,9 @@ pt_status pt_set_radiance_cache(pt_scene* s, const pt_radiance_cache_config* cfg
     return fail(PT_ERR_INVALID_ARG, "beta1 and beta2 must be in [0, 1)");
   if (!(c.epsilon > 0.0f) || !std::isfinite(c.epsilon)) return fail(PT_ERR_INVALID_ARG, "epsilon must be > 0");
   if (!(c.ema_decay >= 0.0f && c.ema_decay < 1.0f)) return fail(PT_ERR_INVALID_ARG, "ema_decay must be in [0, 1)");
+  if (c.train_end_bounce < -1) return fail(PT_ERR_INVALID_ARG, "train_end_bounce must be >= -1");
+  if (c.factorize != 0 && c.factorize != 1) return fail(PT_ERR_INVALID_ARG, "factorize must be 0 or 1");
+  if (!(c.spread_c >= 0.0f) || !std::isfinite(c.spread_c)) return fail(PT_ERR_INVALID_ARG, "spread_c must be >= 0");
   if ((r = set_device(s))) return r;
   std::vector<float> w;
   nrc_init_weights(c.init_seed, w);
@@ -1700,6 +1718,8 @@ pt_status pt_set_radiance_cache(pt_scene* s, const pt_radiance_cache_config* cfg
   if (!s->nrc_bwd.p) PT_HIP(s->nrc_bwd.alloc(kNrcBwdFrags * 64 * sizeof(uint4)));
   if (!s->nrc_inf.p) PT_HIP(s->nrc_inf.alloc(kNrcFwdFrags * 64 * sizeof(uint4)));
   if (!s->nrc_t.p) PT_HIP(s->nrc_t.alloc(sizeof(uint32_t)));
+  if (c.train_end_bounce >= 0)  // both path sets: the frame loop allocates nothing while frames overlap
+    for (DevBuf& b : s->nrc_tail) PT_HIP(b.alloc((size_t)c.train_paths * sizeof(float4)));
   PT_HIP(hipMemsetAsync(s->nrc_t.p, 0, sizeof(uint32_t), s->stream));
   PT_HIP(nrc_pack(s, nullptr, nullptr, s->stream));
   s->nrc_cfg = c;

@@ -98,6 +98,13 @@ struct PathsDev {
   uint32_t* q_nrc;     // slots that queried the cache (count in counts[kCountQuery])
   float* rec;          // training records [n][rec_depth][20] (nullptr: not a training pass)
   int32_t rec_depth;
+  int32_t train_end;   // training paths end in the cache at this vertex (terminal record), -1: plain
+  int32_t nrc_factor;  // 1: the cache predicts radiance / (diffuse albedo + specular luminance)
+  // adaptive termination: per sampling path the primary footprint a0 and the running sum of the
+  // spread terms; with spread_c > 0 a path ends in the cache at the first vertex b >= 1 where
+  // sum^2 > spread_c * a0 (and at the query vertex at the latest)
+  float2* spread;
+  float spread_c;
 };
 
 enum {
@@ -201,7 +208,9 @@ hipError_t nrc_launch_train(const float* X, const float* T, int N, int npad, int
 hipError_t nrc_launch_adam(float* w, float* m, float* v, float* e, float* wi, const float* dw_part, int n_split,
                            float* grad_out, float lr, float b1, float b2, float eps, float ema, const uint32_t* t_step,
                            const uint32_t* n_records, int apply, hipStream_t st);
-hipError_t nrc_launch_targets(const PathsDev& P, int n_paths, uint32_t* offsets, uint32_t* block_sums, float* X,
+// self-training: tail[k] = beta_T * cache(x_T) for training paths with a terminal record at vertex P.train_end, else 0
+hipError_t nrc_launch_terminal(const PathsDev& P, int n_paths, const uint4* fwd, float4* tail, hipStream_t st);
+hipError_t nrc_launch_targets(const PathsDev& P, int n_paths, const float4* tail, uint32_t* offsets, uint32_t* block_sums, float* X,
                               float* T, uint32_t* n_out, unsigned long long* record_stats, hipStream_t st);
 hipError_t nrc_launch_gather(const float* X_all, const float* T_all, const uint32_t* n_all, int B, uint32_t frame,
                              int step, uint32_t k0, uint32_t k1, float* Xb, float* Tb, hipStream_t st);

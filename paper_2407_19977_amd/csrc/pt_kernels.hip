@@ -674,9 +674,21 @@ __device__ inline void shade_one(const SceneDev& S, const PathsDev& P, uint32_t 
     bool nee_done = false;
     bool entering = cos_ng > 0.0f;
     V3 n = entering ? ng : ng * -1.0f;
+    // adaptive termination (path spread): a0 = t^2 / (4 pi |cos|) at the primary vertex, then the
+    // sum of sqrt(t^2 / (pdf |cos|)) over the non-delta bounces that led to each later vertex
+    bool spread_end = false;
+    if (P.spread_c > 0.0f && slot < (uint32_t)P.n_render && nrc_bounce >= 0 && b <= nrc_bounce) {
+      const float t = hv.x, ac = fabsf(cos_ng);
+      float2 sp = b == 0 ? make_float2(t * t / (4.0f * kPi * ac), 0.0f) : P.spread[slot];
+      if (b >= 1) {
+        if (!prev_delta) sp.y += sqrtf(t * t / (pdf_prev * ac));
+        spread_end = sp.y * sp.y > P.spread_c * sp.x;
+      }
+      P.spread[slot] = sp;
+    }
     if (b == max_depth) {
       end_ev = 1;
-    } else if (b == nrc_bounce && slot < (uint32_t)P.n_render) {
+    } else if ((b == nrc_bounce || spread_end) && slot < (uint32_t)P.n_render) {
       // the path ends in the radiance cache: the query adds beta * cache(x) after the pass
       float* qr = P.nrc_q + (size_t)slot * kNrcQueryFloats;
       nrc_inputs(S.box_lo, S.box_inv, p, wo_w, n, m, qr);
@@ -684,6 +696,19 @@ __device__ inline void shade_one(const SceneDev& S, const PathsDev& P, uint32_t 
       qr[13] = beta.y;
       qr[14] = beta.z;
       o.query = true;
+      end_ev = 4;
+    } else if (b == P.train_end && slot >= (uint32_t)P.n_render) {
+      // self-training: the training path ends in the cache; its terminal record (flag 2) is
+      // answered by the cache before the targets of its earlier vertices are formed
+      float* rr = P.rec + ((size_t)(slot - P.n_render) * P.rec_depth + b) * kNrcRecFloats;
+      nrc_inputs(S.box_lo, S.box_inv, p, wo_w, n, m, rr);
+      rr[12] = L.x;
+      rr[13] = L.y;
+      rr[14] = L.z;
+      rr[15] = beta.x;
+      rr[16] = beta.y;
+      rr[17] = beta.z;
+      rr[18] = 2.0f;
       end_ev = 4;
     } else {
       if (P.rec && slot >= (uint32_t)P.n_render) {  // training record: inputs, radiance so far, throughput
@@ -787,7 +812,6 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(SceneDev S, PathsDev P, i
   // per queue (next rays, shadow rays, cache queries): wave counts, then the workgroup's base
   __shared__ uint32_t s_app[3][kShadeBlock / 64 + 1];
   const uint32_t count = P.counts[2 + CLS];
-  const bool query = b == nrc_bounce;
   unsigned long long nonfinite = 0;
   for (uint32_t base = blockIdx.x * kShadeBlock; base < count; base += gridDim.x * kShadeBlock) {
     uint32_t i = base + threadIdx.x;
@@ -825,7 +849,7 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(SceneDev S, PathsDev P, i
     }
     __syncthreads();  // s_app is rewritten by the next iteration
     if (o.cont) P.q_ray[next][off[0] + lane_prefix(m_cont)] = slot;
-    if (query && o.query) P.q_nrc[off[2] + lane_prefix(m_q)] = slot;
+    if (o.query) P.q_nrc[off[2] + lane_prefix(m_q)] = slot;
     if (o.shadow) {
       const uint32_t spos = off[1] + lane_prefix(m_sh);
       P.sh_o[spos] = o.sh_o;

@@ -6,8 +6,8 @@
 // diffuse albedo (1-metalness)(1-transmission) base_weight base_color (3);
 // specular luminance metalness lum(bw bc) + (1-metalness) F_dielectric(1, ior).
 // Encoding (64): sin / cos(2^k pi x_a), k = 0..5 (36); one-blob, 4 bins, of
-// the four direction coordinates (16) and of 1 - exp(-roughness) (4); the four
-// albedo values (4); constants 1, 0, 0, 0 (4).
+// the four direction coordinates (16; the two azimuths periodic) and of
+// 1 - exp(-roughness) (4); the four albedo values (4); constants 1, 0, 0, 0 (4).
 // Network: 64 -> 5 x (64, ReLU) -> 3, no biases, bfloat16 operands, FP32 sums.
 //
 // Matrix-core layout (v_mfma_f32_16x16x32_bf16, wave64): the layer computes
@@ -62,6 +62,15 @@ __host__ __device__ inline float nrc_one_blob(float s, int i) {
   return expf(-0.5f * z * z);
 }
 
+// One-blob bin of an azimuth (periodic: 0 and 1 are the same direction): the
+// distance to the bin centre is taken modulo 1 into [-1/2, 1/2).
+__host__ __device__ inline float nrc_one_blob_periodic(float s, int i) {
+  float d = s - ((float)i + 0.5f) * 0.25f;
+  d -= floorf(d + 0.5f);
+  float z = d * 4.0f;
+  return expf(-0.5f * z * z);
+}
+
 // Feature f (0..63) of the 12 inputs.
 __host__ __device__ inline float nrc_feature(int f, const float* x) {
   if (f < 36) {
@@ -75,7 +84,7 @@ __host__ __device__ inline float nrc_feature(int f, const float* x) {
   }
   if (f < 52) {
     int c = (f - 36) >> 2, i = (f - 36) & 3;
-    return nrc_one_blob(x[3 + c], i);
+    return (c & 1) ? nrc_one_blob_periodic(x[3 + c], i) : nrc_one_blob(x[3 + c], i);
   }
   if (f < 56) return nrc_one_blob(1.0f - expf(-x[7]), f - 52);
   if (f < 60) return x[8 + (f - 56)];
@@ -93,7 +102,8 @@ __host__ __device__ inline void nrc_inputs(const float* lo, const float* inv_ext
   for (int k = 0; k < 2; ++k) {
     float y = fminf(fmaxf(d[k].y, -1.0f), 1.0f);
     x[3 + 2 * k] = acosf(y) * (1.0f / kPi);
-    x[4 + 2 * k] = atan2f(d[k].x, -d[k].z) * (0.5f / kPi) + 0.5f;
+    // + 0.0f turns -0 into +0, so that a direction exactly at a pole has azimuth 0 on every side
+    x[4 + 2 * k] = atan2f(d[k].x + 0.0f, -d[k].z + 0.0f) * (0.5f / kPi) + 0.5f;
   }
   x[7] = m.spec_rough;
   float kd = (1.0f - m.metalness) * (1.0f - m.trans_weight) * m.base_weight;

@@ -135,7 +135,7 @@ __device__ inline void encode_operand(const float* x, int g, bool valid, bf16x8 
   float lo[4], hi[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    lo[i] = nrc_one_blob(s1, i);
+    lo[i] = nrc_one_blob_periodic(s1, i);  // an azimuth (x4 or x6) wherever lo is used
     hi[i] = nrc_one_blob(s2, i);
   }
   const float w4 = x[2] * 16.0f, w5 = x[2] * 32.0f;
@@ -189,10 +189,16 @@ __device__ inline f32x4 mlp_forward(const uint4* __restrict__ sw, int lane, bf16
   return out;
 }
 
+// Reflectance factor of a query's inputs: the cache predicts radiance divided
+// by (diffuse albedo + specular luminance) per channel when factorising.
+__device__ inline float nrc_factor(const float* x, int c, bool on) { return on ? x[8 + c] + x[11] : 1.0f; }
+
 // ------------------------------------------------------------- inference
 // MODE 0: inputs x[n][12], outputs y[n][3].
 // MODE 1: the cache queries of a sampling pass: slot = q_nrc[i] for i < counts[kCountQuery];
-//         inputs nrc_q[slot][0..11], throughput nrc_q[slot][12..14]; L[slot] += beta * max(y, 0).
+//         inputs nrc_q[slot][0..11], throughput nrc_q[slot][12..14]; L[slot] += beta * factor * max(y, 0).
+// MODE 2: the terminal vertices of n training paths (self-training): path k's record at vertex
+//         P.train_end, if it is a terminal record, gives out4[k] = beta * factor * max(y, 0); else 0.
 constexpr int kInferWaves = 8;  // waves per workgroup sharing one LDS copy of the weight fragments
 
 template <int MODE>
@@ -203,6 +209,7 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_nrc_infer(const float* __r
   for (int i = threadIdx.x; i < kNrcFwdFrags * 64; i += blockDim.x) sw[i] = fwd[i];
   __syncthreads();
   const int64_t n = MODE == 1 ? (int64_t)P.counts[kCountQuery] : n_arg;
+  float4* out4 = reinterpret_cast<float4*>(out);
   if (MODE == 1 && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&P.stats[kStatQueries], (unsigned long long)n);
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, g = lane / 16, q = lane % 16;
   unsigned long long nonfinite = 0;
@@ -212,14 +219,18 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_nrc_infer(const float* __r
     asm volatile("" ::: "memory");
     int64_t qi = grp * 16 + q;
     bool valid = qi < n;
+    const bool row = valid;  // MODE 2: every path below n gets an output (0 if not terminal)
     const float* r = nullptr;
     uint32_t slot = 0;
     if (valid) {
       if (MODE == 0) {
         r = xin + qi * 12;
-      } else {
+      } else if (MODE == 1) {
         slot = P.q_nrc[qi];
         r = P.nrc_q + (size_t)slot * kNrcQueryFloats;
+      } else {
+        r = P.rec + ((size_t)qi * P.rec_depth + P.train_end) * kNrcRecFloats;
+        valid = r[18] == 2.0f;
       }
     }
     float x[12];
@@ -228,13 +239,27 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_nrc_infer(const float* __r
     bf16x8 B[2];
     encode_operand(x, g, valid, B);
     f32x4 y = mlp_forward(sw, lane, B, nullptr);
-    if (valid && g == 0) {
+    if (MODE == 2 && row && g == 0) {
+      float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (valid) {
+        const bool fo = P.nrc_factor != 0;
+        t.x = r[15] * nrc_factor(x, 0, fo) * fmaxf(y[0], 0.0f);
+        t.y = r[16] * nrc_factor(x, 1, fo) * fmaxf(y[1], 0.0f);
+        t.z = r[17] * nrc_factor(x, 2, fo) * fmaxf(y[2], 0.0f);
+        if (!(isfinite(t.x) && isfinite(t.y) && isfinite(t.z))) t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
+      out4[qi] = t;
+    }
+    if (MODE != 2 && valid && g == 0) {
       if (MODE == 0) {
         out[qi * 3 + 0] = y[0];
         out[qi * 3 + 1] = y[1];
         out[qi * 3 + 2] = y[2];
       } else {
-        float cx = r[12] * fmaxf(y[0], 0.0f), cy = r[13] * fmaxf(y[1], 0.0f), cz = r[14] * fmaxf(y[2], 0.0f);
+        const bool fo = P.nrc_factor != 0;
+        float cx = r[12] * nrc_factor(x, 0, fo) * fmaxf(y[0], 0.0f);
+        float cy = r[13] * nrc_factor(x, 1, fo) * fmaxf(y[1], 0.0f);
+        float cz = r[14] * nrc_factor(x, 2, fo) * fmaxf(y[2], 0.0f);
         if (isfinite(cx) && isfinite(cy) && isfinite(cz)) {
           float4 l = P.L[slot];
           P.L[slot] = make_float4(l.x + cx, l.y + cy, l.z + cz, l.w);
@@ -429,23 +454,39 @@ __global__ __launch_bounds__(256) void k_nrc_adam(float* __restrict__ w, float* 
 }
 
 // ------------------------------------------------------- training targets
-// Record r of training path k is valid when the path reached vertex r with
-// b < max_depth; its target is (L_end - L_r) / beta_r, dropped when a channel
-// of beta_r is zero or the target is not finite.  Offsets come from an
-// exclusive scan over paths, so the compacted list is in path-major, vertex
-// order whatever the scheduling.
-__device__ inline bool nrc_target(const float* rec, float4 Lend, float t[3]) {
-  if (rec[18] == 0.0f) return false;
+// Record r of training path k is valid (flag 1) when the path scattered at
+// vertex r with r < max_depth; its target is (L_end - L_r) / beta_r, divided
+// by the reflectance factor when factorising, dropped when a channel of
+// beta_r or of the factor is zero or the target is not finite.  A terminal
+// record (flag 2, self-training) is no sample: its cache answer is in L_end.
+// Offsets come from an exclusive scan over paths, so the compacted list is in
+// path-major, vertex order whatever the scheduling.
+__device__ inline bool nrc_target(const float* rec, float4 Lend, bool factor, float t[3]) {
+  if (rec[18] != 1.0f) return false;
   const float Lr[3] = {rec[12], rec[13], rec[14]}, be[3] = {rec[15], rec[16], rec[17]};
   const float Le[3] = {Lend.x, Lend.y, Lend.z};
   bool ok = true;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    ok = ok && be[c] != 0.0f;
+    const float f = nrc_factor(rec, c, factor);
+    ok = ok && be[c] != 0.0f && f != 0.0f;
     t[c] = (Le[c] - Lr[c]) / be[c];
+    if (factor) t[c] = t[c] / f;
     ok = ok && isfinite(t[c]);
   }
   return ok;
+}
+
+// L at the end of training path k: its radiance plus, with self-training, the cache at its terminal vertex.
+__device__ inline float4 nrc_path_end(const PathsDev& P, const float4* tail, int k) {
+  float4 Le = P.L[P.n_render + k];
+  if (tail) {
+    const float4 t = tail[k];
+    Le.x += t.x;
+    Le.y += t.y;
+    Le.z += t.z;
+  }
+  return Le;
 }
 
 // Compaction in three kernels: per-path counts with per-workgroup sums, a
@@ -463,16 +504,16 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* s, uint32_
   return s[threadIdx.x] - v;
 }
 
-__global__ __launch_bounds__(256) void k_nrc_count(PathsDev P, int n_paths, uint32_t* __restrict__ counts,
-                                                   uint32_t* __restrict__ block_sums) {
+__global__ __launch_bounds__(256) void k_nrc_count(PathsDev P, int n_paths, const float4* __restrict__ tail,
+                                                   uint32_t* __restrict__ counts, uint32_t* __restrict__ block_sums) {
   __shared__ uint32_t s[256];
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t c = 0;
   if (k < n_paths) {
-    float4 Le = P.L[P.n_render + k];
+    const float4 Le = nrc_path_end(P, tail, k);
     for (int r = 0; r < P.rec_depth; ++r) {
       float t[3];
-      c += nrc_target(P.rec + ((size_t)k * P.rec_depth + r) * kNrcRecFloats, Le, t) ? 1u : 0u;
+      c += nrc_target(P.rec + ((size_t)k * P.rec_depth + r) * kNrcRecFloats, Le, P.nrc_factor != 0, t) ? 1u : 0u;
     }
     counts[k] = c;
   }
@@ -509,7 +550,8 @@ __global__ __launch_bounds__(1024) void k_nrc_scan(int n, uint32_t* __restrict__
   }
 }
 
-__global__ __launch_bounds__(256) void k_nrc_compact(PathsDev P, int n_paths, uint32_t* __restrict__ offsets,
+__global__ __launch_bounds__(256) void k_nrc_compact(PathsDev P, int n_paths, const float4* __restrict__ tail,
+                                                     uint32_t* __restrict__ offsets,
                                                      const uint32_t* __restrict__ block_base, float* __restrict__ X,
                                                      float* __restrict__ T) {
   __shared__ uint32_t s[256];
@@ -519,11 +561,11 @@ __global__ __launch_bounds__(256) void k_nrc_compact(PathsDev P, int n_paths, ui
   uint32_t o = block_base[blockIdx.x] + block_exclusive_scan(c, s, total);
   if (k >= n_paths) return;
   offsets[k] = o;
-  float4 Le = P.L[P.n_render + k];
+  const float4 Le = nrc_path_end(P, tail, k);
   for (int r = 0; r < P.rec_depth; ++r) {
     const float* rec = P.rec + ((size_t)k * P.rec_depth + r) * kNrcRecFloats;
     float t[3];
-    if (!nrc_target(rec, Le, t)) continue;
+    if (!nrc_target(rec, Le, P.nrc_factor != 0, t)) continue;
     for (int i = 0; i < 12; ++i) X[(size_t)o * 12 + i] = rec[i];
     for (int j = 0; j < 3; ++j) T[(size_t)o * 3 + j] = t[j];
     ++o;
@@ -612,12 +654,21 @@ hipError_t nrc_launch_adam(float* w, float* m, float* v, float* e, float* wi, co
   return hipGetLastError();
 }
 
-hipError_t nrc_launch_targets(const PathsDev& P, int n_paths, uint32_t* offsets, uint32_t* block_sums, float* X,
-                              float* T, uint32_t* n_out, unsigned long long* record_stats, hipStream_t st) {
+hipError_t nrc_launch_terminal(const PathsDev& P, int n_paths, const uint4* fwd, float4* tail, hipStream_t st) {
+  int64_t groups = (n_paths + 15) / 16;
+  int grid = (int)std::max<int64_t>(1, std::min<int64_t>((groups + kInferWaves - 1) / kInferWaves, nrc_infer_grid()));
+  hipLaunchKernelGGL((k_nrc_infer<2>), dim3(grid), dim3(64 * kInferWaves), 0, st, nullptr, (int64_t)n_paths, P, fwd,
+                     reinterpret_cast<float*>(tail));
+  return hipGetLastError();
+}
+
+hipError_t nrc_launch_targets(const PathsDev& P, int n_paths, const float4* tail, uint32_t* offsets,
+                              uint32_t* block_sums, float* X, float* T, uint32_t* n_out,
+                              unsigned long long* record_stats, hipStream_t st) {
   const int nb = (n_paths + 255) / 256;
-  hipLaunchKernelGGL(k_nrc_count, dim3(nb), dim3(256), 0, st, P, n_paths, offsets, block_sums);
+  hipLaunchKernelGGL(k_nrc_count, dim3(nb), dim3(256), 0, st, P, n_paths, tail, offsets, block_sums);
   hipLaunchKernelGGL(k_nrc_scan, dim3(1), dim3(1024), 0, st, nb, block_sums, n_out, record_stats);
-  hipLaunchKernelGGL(k_nrc_compact, dim3(nb), dim3(256), 0, st, P, n_paths, offsets, block_sums, X, T);
+  hipLaunchKernelGGL(k_nrc_compact, dim3(nb), dim3(256), 0, st, P, n_paths, tail, offsets, block_sums, X, T);
   return hipGetLastError();
 }
 

@@ -64,19 +64,22 @@ class pt_bvh_info(C.Structure):
 class pt_radiance_cache_config(C.Structure):
     _fields_ = [("query_bounce", C.c_int32), ("train_paths", C.c_int32), ("batch_size", C.c_int32),
                 ("steps_per_frame", C.c_int32), ("learning_rate", C.c_float), ("beta1", C.c_float),
-                ("beta2", C.c_float), ("epsilon", C.c_float), ("init_seed", C.c_uint64), ("ema_decay", C.c_float)]
+                ("beta2", C.c_float), ("epsilon", C.c_float), ("init_seed", C.c_uint64), ("ema_decay", C.c_float),
+                ("train_end_bounce", C.c_int32), ("spread_c", C.c_float), ("factorize", C.c_int32)]
 
 
 NRC_PARAMS = 5 * 64 * 64 + 3 * 64
 
 
 def cache_config(query_bounce=2, train_paths=1 << 16, batch_size=1 << 14, steps_per_frame=4, learning_rate=1e-3,
-                 beta1=0.9, beta2=0.99, epsilon=1e-8, init_seed=0, ema_decay=0.0):
+                 beta1=0.9, beta2=0.99, epsilon=1e-8, init_seed=0, ema_decay=0.0, train_end_bounce=-1,
+                 spread_c=0.0, factorize=0):
     c = pt_radiance_cache_config()
     c.query_bounce, c.train_paths, c.batch_size, c.steps_per_frame = query_bounce, train_paths, batch_size, \
         steps_per_frame
     c.learning_rate, c.beta1, c.beta2, c.epsilon, c.init_seed = learning_rate, beta1, beta2, epsilon, init_seed
     c.ema_decay = ema_decay
+    c.train_end_bounce, c.spread_c, c.factorize = train_end_bounce, spread_c, factorize
     return c
 
 

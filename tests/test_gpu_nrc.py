@@ -256,7 +256,7 @@ def test_inference_weights_without_moving_average_are_the_weights(P, O):
                             P.cache_config(batch_size=512, steps_per_frame=3, ema_decay=0.0))
     s.nrc_set_weights(_dev(_weights(O, 4)))
     n = 700
-    X = _inputs(n, 17)
+    X = _inputs(20000, 17)[:n]
     T = np.random.Generator(np.random.PCG64(18)).uniform(0, 2, (n, 3)).astype(np.float32)
     s.nrc_train(_dev(X), _dev(T), 2, 5)
     wg = torch.empty(P.NRC_PARAMS, dtype=torch.float32, device="cuda:0")
@@ -264,12 +264,15 @@ def test_inference_weights_without_moving_average_are_the_weights(P, O):
     assert s.nrc_get_weights(wg) == 3
     s.nrc_get_inference_weights(wi)
     assert torch.equal(wg, wi)
-    # and the forward call answers with them
-    y = torch.empty((n, 3), dtype=torch.float32, device="cuda:0")
-    s.nrc_forward(_dev(X), y)
-    ref, _ = N.forward(wg.cpu().numpy().astype(np.float64), X.astype(np.float64), use_bf16=True)
+    # and the forward call answers with them (20,000 queries: the bfloat16 flip rate of FP32 sums,
+    # about 2 rows in 10^4, is then resolved by the 99.9th percentile)
+    Xq = _inputs(20000, 19)
+    y = torch.empty((20000, 3), dtype=torch.float32, device="cuda:0")
+    s.nrc_forward(_dev(Xq), y)
+    ref, _ = N.forward(wg.cpu().numpy().astype(np.float64), Xq.astype(np.float64), use_bf16=True)
     scale = math.sqrt(float((ref ** 2).mean()))
-    assert np.quantile(np.abs(y.cpu().numpy() - ref) / (np.abs(ref) + scale), 0.999) <= 1e-4
+    rel = np.abs(y.cpu().numpy() - ref) / (np.abs(ref) + scale)
+    assert np.quantile(rel, 0.999) <= 1e-4 and rel.max() <= 3e-2
 
 
 # -------------------------------------------------------------------- paths --
@@ -289,7 +292,7 @@ def test_unit_cache_on_white_furnace_gives_one(P, O):
     _say("[nrc furnace] unit cache at vertex 0")
     sc = scenes.furnace("sphere", width=16, height=16)
     s = P.scene_from(sc, device=0)
-    s.set_radiance_cache(P.cache_config(query_bounce=0))
+    s.set_radiance_cache(P.cache_config(query_bounce=0, factorize=0))
     s.nrc_set_weights(_dev(_constant_cache(1.0)))
     per = torch.empty((16, 16, 4, 3), dtype=torch.float32, device="cuda:0")
     sig = torch.empty((16, 16, 4), dtype=torch.int64, device="cuda:0")
@@ -301,7 +304,8 @@ def test_unit_cache_on_white_furnace_gives_one(P, O):
 
 def test_cache_terminated_paths_match_oracle(P, O):
     _say("[nrc paths] box scene 48x48 crop, 4 spp, depth 6, cache at vertex 2")
-    sc, s, os_ = _cache_scene(P, O, "cornell", scenes.cornell, P.cache_config(query_bounce=2))
+    sc, s, os_ = _cache_scene(P, O, "cornell", scenes.cornell,
+                              P.cache_config(query_bounce=2, spread_c=0.0, factorize=0))
     w = _weights(O, 21)
     s.nrc_set_weights(_dev(w))
     crop, spp, depth = (40, 40, 48, 48), 4, 6
@@ -337,7 +341,8 @@ def test_cache_terminated_paths_match_oracle(P, O):
 def test_training_records_match_oracle(P, O):
     _say("[nrc records] box scene 32x32, 1024 training paths, depth 5, frame 3")
     sc0 = scenes.cornell(width=32, height=32)
-    sc, s, os_ = _cache_scene(P, O, "cornell32", lambda: sc0, P.cache_config(train_paths=1024))
+    sc, s, os_ = _cache_scene(P, O, "cornell32", lambda: sc0,
+                              P.cache_config(train_paths=1024, train_end_bounce=-1, factorize=0))
     depth, frame, seed = 5, 3, 0
     cap = 1024 * depth
     X = torch.empty((cap, 12), dtype=torch.float32, device="cuda:0")
@@ -368,6 +373,126 @@ def test_training_records_match_oracle(P, O):
     _say(f"[nrc records] {n} records (oracle {total_ref}), paths identical {good}/1024")
     assert good >= 0.99 * 1024
     assert abs(n - total_ref) <= 0.02 * total_ref
+
+
+@pytest.mark.parametrize("train_end,factorize", [(2, 0), (2, 1), (-1, 1)])
+def test_self_trained_and_factorised_records_match_oracle(P, O, train_end, factorize):
+    """Training records with the refinements of the cited cache method: training
+    paths that end in the cache at vertex 2 (self-training: the cache's answer
+    there, under given weights, joins the radiance of the path's earlier
+    vertices) and targets divided by the reflectance factor."""
+    _say(f"[nrc records] box 32x32, 1024 training paths, depth 5, train_end {train_end}, factorize {factorize}")
+    sc0 = scenes.cornell(width=32, height=32)
+    cfg = P.cache_config(train_paths=1024, train_end_bounce=train_end, factorize=factorize)
+    sc, s, os_ = _cache_scene(P, O, "cornell32", lambda: sc0, cfg)
+    w = _weights(O, 31)
+    s.nrc_set_weights(_dev(w))  # weights given: the cache is in use, self-training on
+    depth, frame, seed = 5, 4, 0
+    cap = 1024 * depth
+    X = torch.empty((cap, 12), dtype=torch.float32, device="cuda:0")
+    T = torch.empty((cap, 3), dtype=torch.float32, device="cuda:0")
+    off = torch.empty(1024, dtype=torch.int32, device="cuda:0")
+    n = s.nrc_training_records(sc.camera, frame, depth, seed, X, T, off)
+    X, T, off = X.cpu().numpy()[:n].astype(np.float64), T.cpu().numpy()[:n].astype(np.float64), off.cpu().numpy()
+    WH = 32 * 32
+    stride = max(1, WH // 1024)
+    m = round(O.uniform(seed, 0, 0x80000000 + frame, 0x4F4646, 0) * 16777216.0)
+    o_f = (m * WH) >> 24
+    good = total_ref = 0
+    for k in range(1024):
+        pix = (k * stride + o_f) % WH
+        xr, tr = os_.training_records(pix % 32, pix // 32, 0x80000000 + frame, depth, seed,
+                                      nrc_weights=w.astype(np.float64), train_end=train_end, nrc_bf16=True,
+                                      factorize=bool(factorize))
+        total_ref += len(xr)
+        a, b = int(off[k]), int(off[k + 1]) if k + 1 < 1024 else n
+        if b - a != len(xr):
+            continue
+        if len(xr) == 0:
+            good += 1
+            continue
+        if train_end >= 0:
+            assert len(xr) <= train_end
+        dx = np.abs(X[a:b] - xr)
+        dt = np.abs(T[a:b] - tr)
+        if np.all(dx <= 1e-4) and np.all(dt <= 1e-3 * np.abs(tr) + 1e-5 * max(1.0, float(np.abs(tr).max()))):
+            good += 1
+    _say(f"[nrc records] {n} records (oracle {total_ref}), paths identical {good}/1024")
+    assert good >= 0.98 * 1024
+    assert abs(n - total_ref) <= 0.02 * total_ref
+
+
+def test_factorised_cache_paths_match_oracle(P, O):
+    _say("[nrc paths] box 48x48 crop, 4 spp, depth 6, factorised cache at vertex 1")
+    sc, s, os_ = _cache_scene(P, O, "cornell", scenes.cornell,
+                              P.cache_config(query_bounce=1, spread_c=0.0, factorize=1))
+    w = _weights(O, 22)
+    s.nrc_set_weights(_dev(w))
+    crop, spp, depth = (40, 40, 48, 48), 4, 6
+    x0, y0, cw, ch = crop
+    per = torch.empty((ch, cw, spp, 3), dtype=torch.float32, device="cuda:0")
+    sig = torch.empty((ch, cw, spp), dtype=torch.int64, device="cuda:0")
+    s.render_debug(sc.camera, x0, y0, cw, ch, 0, spp, depth, 0, per, sig)
+    g = per.cpu().numpy().astype(np.float64)
+    gs = sig.cpu().numpy().view(np.uint64)
+    ref = os_.render(spp, depth, crop=crop, per_sample=True, nrc_weights=w.astype(np.float64), nrc_bounce=1,
+                     nrc_bf16=True, nrc_factor=True)
+    match = gs == ref["sigs"]
+    o = ref["per_sample"]
+    floor = 1e-6 * max(1.0, float(o.mean()))
+    rel = (np.abs(g - o).max(-1) / (np.abs(o).max(-1) + floor))[match]
+    bias = float((g - o)[match].mean() / o[match].mean())
+    _say(f"[nrc paths] factorised: identical {match.mean() * 100:.3f}%  rel err p99 {np.quantile(rel, 0.99):.2e} "
+         f"max {rel.max():.2e}  mean bias {bias:.2e}")
+    assert match.mean() >= 0.999
+    assert np.quantile(rel, 0.99) <= 1e-4   # the same gates as the unfactorised paths
+    assert rel.max() <= 5e-2
+    assert abs(bias) <= 1e-3
+
+
+@pytest.mark.parametrize("which", ["cornell", "zoo"])
+def test_adaptive_termination_paths_match_oracle(P, O, which):
+    """Paths end in the cache where their spread first exceeds 0.01 of the
+    primary footprint (delta bounces add none), at vertex 3 at the latest."""
+    _say(f"[nrc paths] {which}: adaptive termination, spread threshold 0.01, query vertex 3 at the latest")
+    make = scenes.cornell if which == "cornell" else scenes.material_zoo
+    sc, s, os_ = _cache_scene(P, O, which, make, P.cache_config(query_bounce=3, spread_c=0.01, factorize=0))
+    # A random network is chaotic in the high-frequency position features: the
+    # GPU's FP32 hit points flip their bfloat16 roundings now and then and move
+    # the answer by up to a few per cent, which dominates paths that end at
+    # vertex 1.  With the inputs of frequencies 4 pi and up switched off, the
+    # cache answer is smooth and the per-path gates are those of the plain tracer.
+    w = _weights(O, 23)
+    W0 = w[:4096].reshape(64, 64)
+    for f in range(36):
+        if ((f % 12) >> 1) >= 2:
+            W0[:, f] = 0.0
+    s.nrc_set_weights(_dev(w))
+    crop, spp, depth = ((40, 40, 48, 48) if which == "cornell" else (24, 24, 48, 48)), 4, 6
+    x0, y0, cw, ch = crop
+    per = torch.empty((ch, cw, spp, 3), dtype=torch.float32, device="cuda:0")
+    sig = torch.empty((ch, cw, spp), dtype=torch.int64, device="cuda:0")
+    s.render_debug(sc.camera, x0, y0, cw, ch, 0, spp, depth, 0, per, sig)
+    g = per.cpu().numpy().astype(np.float64)
+    gs = sig.cpu().numpy().view(np.uint64)
+    ref = os_.render(spp, depth, crop=crop, per_sample=True, nrc_weights=w.astype(np.float64), nrc_bounce=3,
+                     nrc_bf16=True, spread_c=0.01)
+    fixed = os_.render(spp, depth, crop=crop, per_sample=True, nrc_weights=w.astype(np.float64), nrc_bounce=3,
+                       nrc_bf16=True)
+    match = gs == ref["sigs"]
+    o = ref["per_sample"]
+    floor = 1e-6 * max(1.0, float(o.mean()))
+    rel = (np.abs(g - o).max(-1) / (np.abs(o).max(-1) + floor))[match]
+    early = float((ref["sigs"] != fixed["sigs"]).mean())
+    _say(f"[nrc paths] {which}: identical {match.mean() * 100:.3f}%, ended before vertex 3 {early * 100:.1f}%, "
+         f"rel err p99 {np.quantile(rel, 0.99):.2e} max {rel.max():.2e}")
+    assert early > 0.2  # the heuristic ends a good share of the paths early
+    assert match.mean() >= 0.99
+    assert np.quantile(rel, 0.99) <= 1e-4
+    # Directions within FP32 rounding of the poles of the spherical inputs (the floor's normal,
+    # vertical bounces) have an azimuth decided by rounding noise; such a query may answer
+    # differently on the two sides.  At most 2 paths in 10^4 (and 2 in any case) may exceed 5e-2.
+    assert (rel > 5e-2).sum() <= max(2, int(2e-4 * rel.size)), np.sort(rel)[-5:]
 
 
 # --------------------------------------------------------------- frame loop --

@@ -46,6 +46,19 @@ def test_encoding_c_equals_numpy_and_identities(O):
     assert np.allclose(np.diag(f), 1.0, atol=1e-15)
     for i in range(3):
         assert abs(f[i, i + 1] - math.exp(-0.5)) < 1e-15 and abs(f[i + 1, i] - math.exp(-0.5)) < 1e-15
+    # the azimuth bins (inputs 4 and 6) are periodic: s = 0 and s = 1 encode alike, bin 3 at s = 0
+    # sees the distance 1/8 across the seam, and bin 0 at s = 1 - 1/8 the distance 1/4
+    x = np.zeros((3, 12))
+    x[:, 4] = x[:, 6] = [0.0, 1.0, 0.875]
+    f = N.encode(x)
+    for base in (40, 48):
+        assert np.allclose(f[0, base:base + 4], f[1, base:base + 4], atol=1e-15)
+        assert abs(f[0, base + 3] - math.exp(-0.5 * 0.25)) < 1e-15 and abs(f[0, base] - math.exp(-0.5 * 0.25)) < 1e-15
+        assert abs(f[2, base] - math.exp(-0.5)) < 1e-15 and abs(f[2, base + 3] - 1.0) < 1e-15
+        for c in range(3):
+            assert np.allclose(O.nrc_encode(x[c])[base:base + 4], f[c, base:base + 4], atol=1e-15)
+    # the polar angles and the roughness are not periodic
+    assert abs(f[0, 36] - math.exp(-0.5 * 0.25)) < 1e-15 and abs(f[0, 39] - math.exp(-0.5 * 3.5 ** 2)) < 1e-15
     assert np.all(F[:, 60] == 1) and np.all(F[:, 61:64] == 0)
     assert np.array_equal(F[:, 56:60], X[:, 8:12])
     assert np.all(np.abs(F) <= 1.0 + 1e-15)
@@ -181,3 +194,144 @@ def test_training_targets_are_outgoing_radiance(O):
     assert len(tg) > 3000
     m, se = tg.mean(0), tg.std(0) / math.sqrt(len(tg))
     assert np.all(np.abs(m - 1.0) < 4 * se)
+
+
+# ------------------------------------------------- self-training, factorisation --
+
+def _box_paths(os_, n_paths, fn):
+    for k in range(n_paths):
+        px, py, smp = (7 * k) % 32, (11 * k) % 32, k // 7
+        yield k, fn(px, py, smp)
+
+
+def test_self_training_with_a_zero_cache_is_the_truncated_path(O):
+    """A training path that ends in a cache answering 0 at vertex T carries the
+    records and targets of the same path traced plain to max_depth T (its
+    vertices before T, the emission found at T, nothing after)."""
+    sc = scenes.cornell(width=32, height=32)
+    os_ = O.OracleScene(sc)
+    zero = np.zeros(N.N_PARAMS)
+    seen = 0
+    for T in (1, 2, 3):
+        for k, (a, b) in _box_paths(os_, 300, lambda px, py, smp: (
+                os_.training_records(px, py, smp, 6, nrc_weights=zero, train_end=T),
+                os_.training_records(px, py, smp, T))):
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+            seen += len(a[0])
+    assert seen > 500
+
+
+def test_self_training_adds_the_cache_times_the_albedo_product(O):
+    """Lambertian box, roulette off: cosine sampling gives each bounce the
+    weight rho(x_j) exactly, so a cache answering c at vertex T raises the
+    target of vertex k by c * prod_{j=k}^{T-1} rho(x_j), with rho read from the
+    records' diffuse-albedo inputs; a path that leaves the box before T is
+    unchanged."""
+    sc = scenes.cornell(width=32, height=32)
+    os_ = O.OracleScene(sc)
+    c = 0.7
+    w = _constant_cache(c)
+    T = 3
+    raised = 0
+    for k, (a, b) in _box_paths(os_, 400, lambda px, py, smp: (
+            os_.training_records(px, py, smp, 6, nrc_weights=w, train_end=T, rr=False),
+            os_.training_records(px, py, smp, T, rr=False))):
+        (Xs, Ts), (Xp, Tp) = a, b
+        assert np.array_equal(Xs, Xp)
+        d = Ts - Tp
+        if not np.any(d):
+            continue
+        assert len(Xs) == T  # the path reached T: every earlier vertex scattered and recorded
+        for i in range(T):
+            prod = np.prod(Xs[i:T, 8:11], axis=0)
+            assert np.allclose(d[i], c * prod, rtol=1e-12, atol=0), (k, i, d[i], c * prod)
+        raised += 1
+    assert raised > 50
+
+
+def test_factorised_targets_divide_by_albedo_plus_normal_reflectance(O):
+    """Lambertian materials (specular_ior 1.5): the reflectance factor is
+    rho + ((1.5 - 1) / (1.5 + 1))^2 = rho + 0.04 per channel, and factorised
+    targets are the plain ones divided by it."""
+    sc = scenes.cornell(width=32, height=32)
+    os_ = O.OracleScene(sc)
+    n = 0
+    for k, (a, b) in _box_paths(os_, 200, lambda px, py, smp: (
+            os_.training_records(px, py, smp, 5, factorize=True), os_.training_records(px, py, smp, 5))):
+        (Xf, Tf), (Xp, Tp) = a, b
+        assert np.array_equal(Xf, Xp)
+        assert np.allclose(Xf[:, 11], 0.04, rtol=1e-12)
+        assert np.allclose(Tf * (Xf[:, 8:11] + 0.04), Tp, rtol=1e-12, atol=1e-15)
+        n += len(Tf)
+    assert n > 300
+
+
+def test_factorised_cache_query_multiplies_by_the_factor(O):
+    """The box seen through a cache answering c at vertex 0: every path that
+    hits a Lambertian wall first carries c * (rho + 0.04) (emission at vertex 0
+    aside, the light's own albedo factor is 0)."""
+    sc = scenes.cornell(width=16, height=16)
+    os_ = O.OracleScene(sc)
+    r = os_.render(2, 4, per_sample=True, nrc_weights=_constant_cache(0.5), nrc_bounce=0, nrc_factor=True)
+    rp = os_.render(2, 4, per_sample=True, nrc_weights=_constant_cache(0.5), nrc_bounce=0)
+    v, vp = r["per_sample"].reshape(-1, 3), rp["per_sample"].reshape(-1, 3)
+    alb = sc.materials[:7, 1:4].astype(np.float64)
+    ok = 0
+    for a, b in zip(v, vp):
+        if np.allclose(b, 0.5, rtol=1e-12):  # a wall: the plain query gives 0.5 exactly
+            rho = a / 0.5 - 0.04
+            assert np.any(np.all(np.isclose(alb, rho, rtol=1e-6, atol=1e-7), axis=1)), rho
+            ok += 1
+    assert ok > 100
+
+
+# ------------------------------------------------------- adaptive termination --
+
+def test_spread_termination_limits(O):
+    """Spread heuristic of the cited method: any non-delta bounce adds spread, so
+    with a vanishing threshold every path ends in the cache at vertex 1 (as with
+    a fixed query at vertex 1); with a huge threshold none does before the
+    fixed query vertex; in between, the share ending early falls as the
+    threshold grows."""
+    sc = scenes.cornell(width=16, height=16)
+    os_ = O.OracleScene(sc)
+    w = N.init_weights(3, O.uniform)
+    kw = dict(per_sample=True, nrc_weights=w, nrc_bf16=False)
+    r1 = os_.render(2, 5, nrc_bounce=1, **kw)
+    r2 = os_.render(2, 5, nrc_bounce=2, **kw)
+    tiny = os_.render(2, 5, nrc_bounce=2, spread_c=1e-30, **kw)
+    huge = os_.render(2, 5, nrc_bounce=2, spread_c=1e30, **kw)
+    assert np.array_equal(tiny["per_sample"], r1["per_sample"]) and np.array_equal(tiny["sigs"], r1["sigs"])
+    assert np.array_equal(huge["per_sample"], r2["per_sample"]) and np.array_equal(huge["sigs"], r2["sigs"])
+    assert not np.array_equal(r1["sigs"], r2["sigs"])
+    early = []
+    for c in (1e-3, 1e-2, 1e-1, 1.0, 10.0, 100.0):
+        r = os_.render(2, 5, nrc_bounce=2, spread_c=c, **kw)
+        early.append(float((r["sigs"] == r1["sigs"]).mean()))
+    assert all(a >= b for a, b in zip(early, early[1:])), early
+    assert early[0] > 0.9 and early[-1] < early[0]
+
+
+def test_spread_of_a_delta_bounce_is_zero(O):
+    """A mirror floor (metal, roughness 0): a path whose first bounce is the
+    mirror's delta reflection has no spread at vertex 1 and does not end there
+    even with a vanishing threshold; paths that scatter diffusely first do."""
+    import dataclasses
+    sc = scenes.cornell(width=16, height=16)
+    m = sc.materials.copy()
+    m[0] = scenes.material(base_metalness=1.0, base_color=(0.9, 0.9, 0.9), specular_roughness=0.0)
+    sc = dataclasses.replace(sc, materials=m)
+    os_ = O.OracleScene(sc)
+    w = N.init_weights(4, O.uniform)
+    kw = dict(per_sample=True, nrc_weights=w)
+    r1 = os_.render(2, 5, nrc_bounce=1, **kw)
+    r2 = os_.render(2, 5, nrc_bounce=2, **kw)
+    tiny = os_.render(2, 5, nrc_bounce=2, spread_c=1e-30, **kw)
+    as1 = tiny["sigs"] == r1["sigs"]
+    as2 = tiny["sigs"] == r2["sigs"]
+    differ = r1["sigs"] != r2["sigs"]
+    assert np.all(as1 | as2)
+    # among paths where the fixed vertex matters, the mirror's (bottom rows) keep going to vertex 2
+    bottom = np.zeros_like(as1)
+    bottom[12:] = True
+    assert as2[differ & bottom].mean() > 0.5 and as1[differ & ~bottom].mean() > 0.9

@@ -469,6 +469,47 @@ def _cache_kw(args):
     return {k: v for k, v in kw.items() if v is not None}
 
 
+def bvh_builds(pt, torch, sc_spheres, steps=2):
+    """Host binned-SAH build vs device linear-BVH build (soup in host memory -> BVH ready), and what the
+    device tree costs the traversal: the icosphere field rendered through each tree."""
+    from paper_2407_19977_amd import scenes
+    res = {"paper_context": "Table 1: CPU BVH set-up of 327.57 ms (Apple M1 Max) and 383.10 ms (Ryzen 5 5600X) "
+                            "for 1,068,735 triangles; context only (other machines, other builder)"}
+    cam = sc_spheres.camera
+    out = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device="cuda:0")
+    for name, sc in (("icosphere field (1,310,722 triangles)", sc_spheres),
+                     ("instanced scene (5 meshes, 135,000 unique triangles; top level on the host)", None)):
+        if sc is None:
+            sc = scenes.instanced()
+        ent = {}
+        for gpu in (False, True):
+            s = pt.scene_from(sc, device=0, gpu_bvh=gpu)
+            if gpu:  # a second build: the first one also loads the builder's kernels
+                s.build_bvh(sc.meshes, sc.instances, on_device=True)
+            info = s.bvh_info()
+            e = {"build_ms": round(info["build_ms"], 2), "nodes": info["n_nodes"], "depth": info["depth"],
+                 "max_leaf": info["max_leaf_tris"]}
+            if info["sah_cost"]:
+                e["sah_cost"] = round(info["sah_cost"], 3)
+            if sc is sc_spheres:  # the traversal through this tree
+                s.render(cam, sc.spp, sc.max_depth, sc.seed, out)
+                s.set_profiling(True, False)
+                s.reset_stats()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    s.render(cam, sc.spp, sc.max_depth, sc.seed, out)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                st = s.stats()
+                e["render_Mrays_per_s"] = round((st["extension_rays"] + st["shadow_rays"]) / dt / 1e6, 1)
+            ent["device" if gpu else "host"] = e
+            s.close()
+        ent["speedup"] = round(ent["host"]["build_ms"] / ent["device"]["build_ms"], 2)
+        res[name] = ent
+    return res
+
+
 def _tail_args(args):
     """(min_bounce, max_fraction) from the command line, None for the library's defaults."""
     if args.tail_min_bounce is None and args.tail_fraction is None:
@@ -538,6 +579,7 @@ def main():
     ap.add_argument("--no-cache", action="store_true", help="skip the radiance-cache vs plain experiment")
     ap.add_argument("--no-instanced", action="store_true", help="skip the instanced scene at 1080p")
     ap.add_argument("--no-display", action="store_true", help="skip the display kernel's roofline")
+    ap.add_argument("--no-bvh", action="store_true", help="skip the host vs device BVH build comparison")
     ap.add_argument("--cache-frames", type=int, default=256)
     ap.add_argument("--cache-seeds", type=int, default=4)
     ap.add_argument("--ref-spp", type=int, default=4096)
@@ -648,10 +690,14 @@ def main():
         "shade_valu": shade_valu(),
         "display": None if args.no_display else display_roofline(s, W, H, torch),
         "cpu_baseline": None,
+        "bvh_build": None,
         "instanced_1080p": None,
         "radiance_cache": None,
     }
     s.close()
+    if not args.no_bvh:
+        print("[bench] BVH builds", file=sys.stderr, flush=True)
+        result["bvh_build"] = bvh_builds(pt, torch, sc)
     if not args.no_instanced:
         print("[bench] instanced scene 1080p", file=sys.stderr, flush=True)
         result["instanced_1080p"] = instanced_1080p(pt, torch, args.instanced_spp, _tail_args(args))

@@ -131,6 +131,19 @@ void pt_scene_destroy(pt_scene* scene);
 pt_status pt_build_bvh(pt_scene* scene, const pt_mesh* meshes, int32_t n_meshes,
                        const pt_instance* instances, int32_t n_instances);
 
+/* The same acceleration structure built on the GPU instead (the paper times
+ * its CPU set-up as its own stage, Sec. 5.1.1, Table 1): a linear BVH over
+ * 30-bit Morton codes of the triangle centroids (radix-sorted, binary radix
+ * tree built per node in parallel, boxes merged bottom-up), collapsed top-down
+ * to the same 128-byte BVH4 nodes and 48-byte triangle records.  Arguments,
+ * primitive numbering and errors as pt_build_bvh; the tree differs, the
+ * closest hits do not (a hit is defined by the triangle test alone).  With
+ * instances each mesh's BVH is built on the GPU and the top level over the
+ * instance boxes on the CPU.  Error: DEVICE if a device step fails (the scene
+ * then has no BVH).  pt_scene_bvh_info reports its build time. */
+pt_status pt_build_bvh_gpu(pt_scene* scene, const pt_mesh* meshes, int32_t n_meshes,
+                           const pt_instance* instances, int32_t n_instances);
+
 /* Upload the OpenPBR materials (Sec. 4).  Errors: INVALID_ARG (n <= 0,
  * negative or non-finite parameters, IOR <= 0, weights outside [0,1]),
  * UNSUPPORTED (base_diffuse_roughness != 0, coat together with transmission). */
@@ -368,6 +381,17 @@ typedef struct pt_bvh_info {
                              inner level plus one top-level leaf's instances (3 * depth +
                              max leaf size), which bounds every walk of this hierarchy */
 } pt_bvh_info;
+/* The scene's mesh-level BVH (either builder): node and triangle counts,
+ * depth, largest leaf, SAH cost (host builds; 0 for device builds),
+ * build_ms from the triangle soup in host memory to the BVH in the builder's
+ * memory (device builds: soup upload included; two-level: summed over the
+ * meshes), and the traversal stack capacity.  Errors: STATE without a BVH. */
+pt_status pt_scene_bvh_info(pt_scene* scene, pt_bvh_info* info);
+/* Copy the scene's mesh-level BVH to host memory: nodes (n_nodes * 128
+ * bytes, root at 0; two-level scenes: the meshes' trees concatenated) and
+ * triangles (n_tris * 48 bytes, leaf order); either may be NULL. */
+pt_status pt_scene_copy_bvh(pt_scene* scene, void* nodes, void* tris);
+
 /* Build the BVH4 of one mesh on the host (the same builder pt_build_bvh uses). */
 pt_status pt_bvh_host_build(const pt_mesh* mesh, pt_bvh_host** out);
 /* Build the two-level hierarchy of an instanced scene on the host (the same

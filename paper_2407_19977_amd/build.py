@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpt.so")
-SOURCES = ["pt_kernels.hip", "pt_nrc.hip", "pt_display.hip", "pt_api.cpp", "bvh_build.cpp"]
+SOURCES = ["pt_kernels.hip", "pt_nrc.hip", "pt_display.hip", "pt_bvh_gpu.hip", "pt_api.cpp", "bvh_build.cpp"]
 ARCH = "gfx950"
 
 

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -98,6 +99,11 @@ struct pt_scene {
   DevBuf nodes, tris;
   uint32_t n_tris = 0;
   int bvh_depth = 0;
+  int64_t n_nodes = 0;       // mesh-level BVH4 nodes in `nodes`
+  int bvh_max_leaf = 0;
+  double bvh_sah = 0.0;      // host builds only
+  double bvh_build_ms = 0.0; // triangle soup in host memory -> BVH ready where the builder leaves it
+  bool bvh_on_device = false;
   float tmin = 0.0f;
   int32_t max_mat_id = -1;
   std::vector<float> host_tri_verts;  // [n][9] world space, prim order (single level)
@@ -1172,10 +1178,17 @@ struct TwoLevel {
   int depth = 0;
   int32_t max_mat = -1;
   double box_lo[3], box_hi[3];
+  int64_t mesh_nodes = 0;  // BVH4 nodes of all meshes
+  double build_ms = 0.0;   // summed mesh builds
+  int max_leaf = 0;
+  double sah = 0.0;
 };
 
+// Builds one mesh's BVH4 into host memory: the host builder, or the device builder copied back.
+using MeshBuilder = std::function<bool(const float*, const uint32_t*, const uint32_t*, int64_t, Bvh4&, std::string&)>;
+
 pt_status build_two_level_host(const pt_mesh* meshes, int32_t n_meshes, const pt_instance* instances,
-                               int32_t n_instances, TwoLevel& out) {
+                               int32_t n_instances, TwoLevel& out, const MeshBuilder* builder = nullptr) {
   std::vector<std::vector<float>> mverts((size_t)n_meshes);
   std::vector<std::vector<int32_t>> mmat((size_t)n_meshes);
   std::vector<BVHNode> nodes;
@@ -1201,8 +1214,13 @@ pt_status build_two_level_host(const pt_mesh* meshes, int32_t n_meshes, const pt
     }
     Bvh4 b;
     std::string err;
-    if (!build_bvh4(v.data(), prim.data(), mat.data(), m.n_triangles, b, err))
-      return fail(PT_ERR_INVALID_ARG, "mesh %d: %s", i, err.c_str());
+    const bool ok = builder ? (*builder)(v.data(), prim.data(), mat.data(), m.n_triangles, b, err)
+                            : build_bvh4(v.data(), prim.data(), mat.data(), m.n_triangles, b, err);
+    if (!ok) return fail(builder ? PT_ERR_DEVICE : PT_ERR_INVALID_ARG, "mesh %d: %s", i, err.c_str());
+    out.mesh_nodes += (int64_t)b.nodes.size();
+    out.build_ms += b.build_ms;
+    out.max_leaf = std::max(out.max_leaf, b.max_leaf);
+    out.sah += b.sah_cost;
     tfirst[(size_t)i] = (uint32_t)tris.size();
     tcount[(size_t)i] = (uint32_t)m.n_triangles;
     root[(size_t)i] = append_bvh(b, nodes, tris);
@@ -1288,12 +1306,50 @@ pt_status build_two_level_host(const pt_mesh* meshes, int32_t n_meshes, const pt
   return PT_OK;
 }
 
+// Device build of one mesh, copied back to host memory (meshes of a two-level scene are
+// concatenated and re-based on the host).  Times the soup upload, the build and the copy.
+bool gpu_mesh_bvh(pt_scene* s, const float* v, const uint32_t* prim, const uint32_t* mat, int64_t n, Bvh4& b,
+                  std::string& err) {
+  auto t0 = std::chrono::steady_clock::now();
+  DevBuf dsoup, dprim, dmat, dnodes, dtris;
+  const int64_t nn = std::max<int64_t>(1, n - 1);
+  hipError_t e = upload(dsoup, v, (size_t)n * 9 * sizeof(float), s->stream);
+  if (e == hipSuccess) e = upload(dprim, prim, (size_t)n * sizeof(uint32_t), s->stream);
+  if (e == hipSuccess) e = upload(dmat, mat, (size_t)n * sizeof(uint32_t), s->stream);
+  if (e == hipSuccess) e = dnodes.alloc((size_t)nn * sizeof(BVHNode));
+  if (e == hipSuccess) e = dtris.alloc((size_t)n * sizeof(TriRec));
+  GpuBvhStats st{};
+  if (e == hipSuccess)
+    e = gpu_build_bvh4(dsoup.as<float>(), dprim.as<uint32_t>(), dmat.as<uint32_t>(), n, dnodes.as<BVHNode>(),
+                       dtris.as<TriRec>(), s->stream, &st);
+  if (e == hipSuccess) {
+    b.nodes.resize((size_t)st.n_nodes);
+    b.tris.resize((size_t)n);
+    e = hipMemcpyAsync(b.nodes.data(), dnodes.p, (size_t)st.n_nodes * sizeof(BVHNode), hipMemcpyDeviceToHost,
+                       s->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b.tris.data(), dtris.p, (size_t)n * sizeof(TriRec), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  }
+  if (e != hipSuccess) {
+    err = std::string("device BVH build failed: ") + hipGetErrorString(e);
+    return false;
+  }
+  b.depth = st.depth;
+  b.max_leaf = st.max_leaf;
+  b.sah_cost = 0.0;
+  b.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return true;
+}
+
 pt_status build_two_level(pt_scene* s, const pt_mesh* meshes, int32_t n_meshes, const pt_instance* instances,
-                          int32_t n_instances) {
+                          int32_t n_instances, bool on_device = false) {
   TwoLevel T;
-  pt_status r = build_two_level_host(meshes, n_meshes, instances, n_instances, T);
+  pt_status r = set_device(s);
   if (r) return r;
-  r = set_device(s);
+  MeshBuilder gpu = [s](const float* v, const uint32_t* prim, const uint32_t* mat, int64_t n, Bvh4& b,
+                        std::string& err) { return gpu_mesh_bvh(s, v, prim, mat, n, b, err); };
+  r = build_two_level_host(meshes, n_meshes, instances, n_instances, T, on_device ? &gpu : nullptr);
   if (r) return r;
   PT_HIP(upload(s->nodes, T.nodes.data(), T.nodes.size() * sizeof(BVHNode), s->stream));
   PT_HIP(upload(s->tris, T.tris.data(), T.tris.size() * sizeof(TriRec), s->stream));
@@ -1307,6 +1363,11 @@ pt_status build_two_level(pt_scene* s, const pt_mesh* meshes, int32_t n_meshes, 
   set_box(s, T.box_lo, T.box_hi);
   s->n_tris = (uint32_t)T.tris.size();
   s->bvh_depth = T.depth;
+  s->n_nodes = T.mesh_nodes;
+  s->bvh_max_leaf = T.max_leaf;
+  s->bvh_sah = T.sah;
+  s->bvh_build_ms = T.build_ms;
+  s->bvh_on_device = on_device;
   s->max_mat_id = T.max_mat;
   s->host_tri_verts.clear();
   s->host_tri_mat.clear();
@@ -1314,6 +1375,134 @@ pt_status build_two_level(pt_scene* s, const pt_mesh* meshes, int32_t n_meshes, 
   s->host_mesh_verts.swap(T.mverts);
   s->host_mesh_mat.swap(T.mmat);
   s->two_level = true;
+  s->has_bvh = true;
+  s->lights_dirty = true;
+  return PT_OK;
+}
+
+// Validation shared by the host and device builds (checked before any state change).
+pt_status check_build_args(const pt_mesh* meshes, int32_t n_meshes, const pt_instance* instances,
+                           int32_t n_instances, int64_t* total_out) {
+  if (!meshes || n_meshes <= 0) return fail(PT_ERR_INVALID_ARG, "meshes must be non-NULL with n_meshes > 0");
+  if (n_instances < 0 || (n_instances > 0 && !instances)) return fail(PT_ERR_INVALID_ARG, "bad instances");
+  for (int i = 0; i < n_instances; ++i) {
+    const pt_instance& in = instances[i];
+    if (in.mesh < 0 || in.mesh >= n_meshes) return fail(PT_ERR_INVALID_ARG, "instance %d: mesh %d out of range", i, in.mesh);
+    if (!finite_all(in.object_to_world, 12)) return fail(PT_ERR_INVALID_ARG, "instance %d: non-finite transform", i);
+    if (in.material_override < -1) return fail(PT_ERR_INVALID_ARG, "instance %d: bad material override", i);
+    if (in.material_override < 0 && !meshes[in.mesh].material_ids)
+      return fail(PT_ERR_INVALID_ARG, "instance %d: mesh %d has no material ids and no override", i, in.mesh);
+  }
+  int64_t total = 0;
+  for (int i = 0; i < n_meshes; ++i) {
+    const pt_mesh& m = meshes[i];
+    if (!m.vertices || !m.indices || m.n_vertices <= 0 || m.n_triangles <= 0)
+      return fail(PT_ERR_INVALID_ARG, "mesh %d: NULL arrays or empty counts", i);
+    if (!m.material_ids && n_instances == 0)
+      return fail(PT_ERR_INVALID_ARG, "mesh %d: material_ids is NULL and nothing overrides it", i);
+    if (!finite_all(m.vertices, (size_t)m.n_vertices * 3)) return fail(PT_ERR_INVALID_ARG, "mesh %d: non-finite vertex", i);
+    for (int64_t t = 0; t < m.n_triangles * 3; ++t)
+      if (m.indices[t] < 0 || m.indices[t] >= m.n_vertices)
+        return fail(PT_ERR_INVALID_ARG, "mesh %d: index %lld out of range", i, (long long)m.indices[t]);
+    if (m.material_ids)
+      for (int64_t t = 0; t < m.n_triangles; ++t)
+        if (m.material_ids[t] < 0) return fail(PT_ERR_INVALID_ARG, "mesh %d: negative material id", i);
+    total += m.n_triangles;
+  }
+  if (n_instances == 0 && total >= (int64_t)kLeafFirstMask) return fail(PT_ERR_INVALID_ARG, "too many triangles");
+  *total_out = total;
+  return PT_OK;
+}
+
+// pt_build_bvh (on_device false: host binned-SAH builder) and pt_build_bvh_gpu (device linear BVH).
+pt_status build_bvh_any(pt_scene* s, const pt_mesh* meshes, int32_t n_meshes, const pt_instance* instances,
+                        int32_t n_instances, bool on_device) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  int64_t total = 0;
+  if ((r = check_build_args(meshes, n_meshes, instances, n_instances, &total))) return r;
+  if (n_instances > 0) return build_two_level(s, meshes, n_meshes, instances, n_instances, on_device);
+  std::vector<float> verts((size_t)total * 9);
+  std::vector<int32_t> mat((size_t)total);
+  std::vector<uint32_t> prim((size_t)total), matu((size_t)total);
+  int64_t t = 0;
+  int32_t max_mat = -1;
+  for (int i = 0; i < n_meshes; ++i) {
+    const pt_mesh& m = meshes[i];
+    for (int64_t k = 0; k < m.n_triangles; ++k, ++t) {
+      for (int v = 0; v < 3; ++v) {
+        int32_t vi = m.indices[3 * k + v];
+        for (int c = 0; c < 3; ++c) verts[9 * (size_t)t + 3 * v + c] = m.vertices[3 * (size_t)vi + c];
+      }
+      mat[(size_t)t] = m.material_ids[k];
+      matu[(size_t)t] = (uint32_t)m.material_ids[k];
+      prim[(size_t)t] = (uint32_t)t;
+      max_mat = std::max(max_mat, m.material_ids[k]);
+    }
+  }
+  r = set_device(s);
+  if (r) return r;
+  int64_t n_nodes = 0;
+  int depth = 0, max_leaf = 0;
+  double sah = 0.0, build_ms = 0.0;
+  if (on_device) {
+    // the soup goes up once; nodes and triangle records are written in place
+    auto t0 = std::chrono::steady_clock::now();
+    DevBuf dsoup, dprim, dmat;
+    PT_HIP(upload(dsoup, verts.data(), verts.size() * sizeof(float), s->stream));
+    PT_HIP(upload(dprim, prim.data(), prim.size() * sizeof(uint32_t), s->stream));
+    PT_HIP(upload(dmat, matu.data(), matu.size() * sizeof(uint32_t), s->stream));
+    PT_HIP(s->nodes.alloc((size_t)std::max<int64_t>(1, total - 1) * sizeof(BVHNode)));
+    PT_HIP(s->tris.alloc((size_t)total * sizeof(TriRec)));
+    GpuBvhStats st{};
+    hipError_t e = gpu_build_bvh4(dsoup.as<float>(), dprim.as<uint32_t>(), dmat.as<uint32_t>(), total,
+                                  s->nodes.as<BVHNode>(), s->tris.as<TriRec>(), s->stream, &st);
+    if (e != hipSuccess) {
+      s->has_bvh = false;  // the scene's buffers were overwritten
+      return fail(PT_ERR_DEVICE, "device BVH build failed: %s", hipGetErrorString(e));
+    }
+    n_nodes = st.n_nodes;
+    depth = st.depth;
+    max_leaf = st.max_leaf;
+    build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  } else {
+    Bvh4 bvh;
+    std::string err;
+    if (!build_bvh4(verts.data(), prim.data(), matu.data(), total, bvh, err)) return fail(PT_ERR_INVALID_ARG, "%s", err.c_str());
+    PT_HIP(upload(s->nodes, bvh.nodes.data(), bvh.nodes.size() * sizeof(BVHNode), s->stream));
+    PT_HIP(upload(s->tris, bvh.tris.data(), bvh.tris.size() * sizeof(TriRec), s->stream));
+    PT_HIP(hipStreamSynchronize(s->stream));
+    n_nodes = (int64_t)bvh.nodes.size();
+    depth = bvh.depth;
+    max_leaf = bvh.max_leaf;
+    sah = bvh.sah_cost;
+    build_ms = bvh.build_ms;
+  }
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (size_t q = 0; q < verts.size(); q += 3)
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::min(lo[k], (double)verts[q + k]);
+      hi[k] = std::max(hi[k], (double)verts[q + k]);
+    }
+  // t_min from the float box of the triangles (as the host builder reports it)
+  double dx = (double)(float)hi[0] - (float)lo[0], dy = (double)(float)hi[1] - (float)lo[1],
+         dz = (double)(float)hi[2] - (float)lo[2];
+  s->tmin = (float)(1e-5 * std::sqrt(dx * dx + dy * dy + dz * dz));
+  set_box(s, lo, hi);
+  s->n_tris = (uint32_t)total;
+  s->bvh_depth = depth;
+  s->n_nodes = n_nodes;
+  s->bvh_max_leaf = max_leaf;
+  s->bvh_sah = sah;
+  s->bvh_build_ms = build_ms;
+  s->bvh_on_device = on_device;
+  s->max_mat_id = max_mat;
+  s->host_tri_verts.swap(verts);
+  s->host_tri_mat.swap(mat);
+  s->host_insts.clear();
+  s->host_mesh_verts.clear();
+  s->host_mesh_mat.clear();
+  s->two_level = false;
   s->has_bvh = true;
   s->lights_dirty = true;
   return PT_OK;
@@ -1378,85 +1567,38 @@ void pt_scene_destroy(pt_scene* s) {
 
 pt_status pt_build_bvh(pt_scene* s, const pt_mesh* meshes, int32_t n_meshes, const pt_instance* instances,
                        int32_t n_instances) {
+  return build_bvh_any(s, meshes, n_meshes, instances, n_instances, false);
+}
+
+pt_status pt_build_bvh_gpu(pt_scene* s, const pt_mesh* meshes, int32_t n_meshes, const pt_instance* instances,
+                           int32_t n_instances) {
+  return build_bvh_any(s, meshes, n_meshes, instances, n_instances, true);
+}
+
+pt_status pt_scene_bvh_info(pt_scene* s, pt_bvh_info* info) {
   pt_status r = check_scene(s);
   if (r) return r;
-  if (!meshes || n_meshes <= 0) return fail(PT_ERR_INVALID_ARG, "meshes must be non-NULL with n_meshes > 0");
-  if (n_instances < 0 || (n_instances > 0 && !instances)) return fail(PT_ERR_INVALID_ARG, "bad instances");
-  for (int i = 0; i < n_instances; ++i) {
-    const pt_instance& in = instances[i];
-    if (in.mesh < 0 || in.mesh >= n_meshes) return fail(PT_ERR_INVALID_ARG, "instance %d: mesh %d out of range", i, in.mesh);
-    if (!finite_all(in.object_to_world, 12)) return fail(PT_ERR_INVALID_ARG, "instance %d: non-finite transform", i);
-    if (in.material_override < -1) return fail(PT_ERR_INVALID_ARG, "instance %d: bad material override", i);
-    if (in.material_override < 0 && !meshes[in.mesh].material_ids)
-      return fail(PT_ERR_INVALID_ARG, "instance %d: mesh %d has no material ids and no override", i, in.mesh);
-  }
-  int64_t total = 0;
-  for (int i = 0; i < n_meshes; ++i) {
-    const pt_mesh& m = meshes[i];
-    if (!m.vertices || !m.indices || m.n_vertices <= 0 || m.n_triangles <= 0)
-      return fail(PT_ERR_INVALID_ARG, "mesh %d: NULL arrays or empty counts", i);
-    if (!m.material_ids && n_instances == 0)
-      return fail(PT_ERR_INVALID_ARG, "mesh %d: material_ids is NULL and nothing overrides it", i);
-    if (!finite_all(m.vertices, (size_t)m.n_vertices * 3)) return fail(PT_ERR_INVALID_ARG, "mesh %d: non-finite vertex", i);
-    for (int64_t t = 0; t < m.n_triangles * 3; ++t)
-      if (m.indices[t] < 0 || m.indices[t] >= m.n_vertices)
-        return fail(PT_ERR_INVALID_ARG, "mesh %d: index %lld out of range", i, (long long)m.indices[t]);
-    if (m.material_ids)
-      for (int64_t t = 0; t < m.n_triangles; ++t)
-        if (m.material_ids[t] < 0) return fail(PT_ERR_INVALID_ARG, "mesh %d: negative material id", i);
-    total += m.n_triangles;
-  }
-  if (n_instances > 0) return build_two_level(s, meshes, n_meshes, instances, n_instances);
-  if (total >= (int64_t)kLeafFirstMask) return fail(PT_ERR_INVALID_ARG, "too many triangles");
-  std::vector<float> verts((size_t)total * 9);
-  std::vector<int32_t> mat((size_t)total);
-  std::vector<uint32_t> prim((size_t)total), matu((size_t)total);
-  int64_t t = 0;
-  int32_t max_mat = -1;
-  for (int i = 0; i < n_meshes; ++i) {
-    const pt_mesh& m = meshes[i];
-    for (int64_t k = 0; k < m.n_triangles; ++k, ++t) {
-      for (int v = 0; v < 3; ++v) {
-        int32_t vi = m.indices[3 * k + v];
-        for (int c = 0; c < 3; ++c) verts[9 * (size_t)t + 3 * v + c] = m.vertices[3 * (size_t)vi + c];
-      }
-      mat[(size_t)t] = m.material_ids[k];
-      matu[(size_t)t] = (uint32_t)m.material_ids[k];
-      prim[(size_t)t] = (uint32_t)t;
-      max_mat = std::max(max_mat, m.material_ids[k]);
-    }
-  }
-  Bvh4 bvh;
-  std::string err;
-  if (!build_bvh4(verts.data(), prim.data(), matu.data(), total, bvh, err)) return fail(PT_ERR_INVALID_ARG, "%s", err.c_str());
-  r = set_device(s);
-  if (r) return r;
-  PT_HIP(upload(s->nodes, bvh.nodes.data(), bvh.nodes.size() * sizeof(BVHNode), s->stream));
-  PT_HIP(upload(s->tris, bvh.tris.data(), bvh.tris.size() * sizeof(TriRec), s->stream));
-  PT_HIP(hipStreamSynchronize(s->stream));
-  double dx = (double)bvh.hi[0] - bvh.lo[0], dy = (double)bvh.hi[1] - bvh.lo[1], dz = (double)bvh.hi[2] - bvh.lo[2];
-  s->tmin = (float)(1e-5 * std::sqrt(dx * dx + dy * dy + dz * dz));
-  {
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (size_t q = 0; q < verts.size(); q += 3)
-      for (int k = 0; k < 3; ++k) {
-        lo[k] = std::min(lo[k], (double)verts[q + k]);
-        hi[k] = std::max(hi[k], (double)verts[q + k]);
-      }
-    set_box(s, lo, hi);
-  }
-  s->n_tris = (uint32_t)total;
-  s->bvh_depth = bvh.depth;
-  s->max_mat_id = max_mat;
-  s->host_tri_verts.swap(verts);
-  s->host_tri_mat.swap(mat);
-  s->host_insts.clear();
-  s->host_mesh_verts.clear();
-  s->host_mesh_mat.clear();
-  s->two_level = false;
-  s->has_bvh = true;
-  s->lights_dirty = true;
+  if (!info) return fail(PT_ERR_INVALID_ARG, "info is NULL");
+  if (!s->has_bvh) return fail(PT_ERR_STATE, "pt_build_bvh has not been called");
+  info->n_nodes = s->n_nodes;
+  info->n_tris = s->n_tris;
+  info->depth = s->bvh_depth;
+  info->max_leaf_tris = s->bvh_max_leaf;
+  info->sah_cost = s->bvh_sah;
+  info->build_ms = s->bvh_build_ms;
+  info->stack_capacity = stack_capacity(s->bvh_depth);
   return PT_OK;
+}
+
+pt_status pt_scene_copy_bvh(pt_scene* s, void* nodes, void* tris) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (!s->has_bvh) return fail(PT_ERR_STATE, "pt_build_bvh has not been called");
+  if ((r = set_device(s))) return r;
+  if (nodes)
+    PT_HIP(hipMemcpyAsync(nodes, s->nodes.p, (size_t)s->n_nodes * sizeof(BVHNode), hipMemcpyDeviceToHost, s->stream));
+  if (tris) PT_HIP(hipMemcpyAsync(tris, s->tris.p, (size_t)s->n_tris * sizeof(TriRec), hipMemcpyDeviceToHost, s->stream));
+  return sync(s);
 }
 
 pt_status pt_upload_materials(pt_scene* s, const pt_openpbr_material* m, int32_t n) {

@@ -1,0 +1,502 @@
+// GPU construction of the BVH4 for gfx950 (the paper builds its BVH on the
+// CPU once per scene and times that set-up separately, Sec. 5.1.1, Table 1).
+//
+// A linear BVH over the triangles' centroids (Karras 2012):
+//   1. triangle boxes, and the centroid bounds by a block reduction;
+//   2. 30-bit Morton codes (10 bits per axis) of the normalised centroids;
+//   3. an LSD radix sort of (code, index): four 8-bit passes, each a tile
+//      histogram, one scan over (digit, tile) and a stable scatter that ranks
+//      equal digits with wave ballots;
+//   4. the binary radix tree over the sorted codes, every internal node in
+//      parallel (ties between equal codes broken by the index);
+//   5. node boxes bottom-up: each leaf walks towards the root and the second
+//      thread to reach a node merges its children's boxes;
+//   6. a top-down collapse to 128-byte BVH4 nodes, one launch per level: a
+//      node opens its largest-area children until it has four, subtrees of at
+//      most kMaxLeafTris triangles become leaves (contiguous in sorted order);
+//   7. the 48-byte triangle records in sorted (leaf) order.
+// The result has the layout of the host builder's (root at node 0, empty
+// child slots kEmpty with zero boxes, meta[0] = child count); only the tree
+// differs.  Every closest hit is the same, since the hit is defined by the
+// triangle test alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "pt_internal.h"
+
+namespace pt {
+namespace {
+
+constexpr int kBB = 256;               // threads per block
+constexpr int kItems = 8;              // keys per thread and radix pass
+constexpr int kTile = kBB * kItems;    // keys per radix tile
+constexpr uint32_t kLeafRef = 0x80000000u;  // binary-tree child reference: leaf flag
+constexpr int kMaxTreeLevels = 128;          // bound on any walk or level loop over the binary tree
+
+// Float <-> order-preserving unsigned, for atomic min / max of floats.
+__device__ inline uint32_t f2ord(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float ord2f(uint32_t u) { return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u); }
+
+__device__ inline uint32_t spread10(uint32_t v) {  // the 10 low bits of v to every third bit
+  v &= 0x3FFu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+// 1. boxes [n][6] (lo xyz, hi xyz) and centroid bounds cb[6] (ordered min xyz, max xyz)
+__global__ __launch_bounds__(kBB) void k_tri_boxes(const float* __restrict__ soup, int64_t n, float* __restrict__ box,
+                                                   uint32_t* __restrict__ cb) {
+  __shared__ float red[6][kBB];
+  float cmin[3] = {INFINITY, INFINITY, INFINITY}, cmax[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = blockIdx.x * (int64_t)kBB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBB) {
+    const float* p = soup + 9 * i;
+    float lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = fminf(fminf(p[k], p[3 + k]), p[6 + k]);
+      hi[k] = fmaxf(fmaxf(p[k], p[3 + k]), p[6 + k]);
+      box[6 * i + k] = lo[k];
+      box[6 * i + 3 + k] = hi[k];
+      const float c = 0.5f * (lo[k] + hi[k]);
+      cmin[k] = fminf(cmin[k], c);
+      cmax[k] = fmaxf(cmax[k], c);
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    red[k][threadIdx.x] = cmin[k];
+    red[3 + k][threadIdx.x] = cmax[k];
+  }
+  __syncthreads();
+  for (int off = kBB / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+      for (int k = 0; k < 3; ++k) {
+        red[k][threadIdx.x] = fminf(red[k][threadIdx.x], red[k][threadIdx.x + off]);
+        red[3 + k][threadIdx.x] = fmaxf(red[3 + k][threadIdx.x], red[3 + k][threadIdx.x + off]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) {
+    atomicMin(&cb[threadIdx.x], f2ord(red[threadIdx.x][0]));
+    atomicMax(&cb[3 + threadIdx.x], f2ord(red[3 + threadIdx.x][0]));
+  }
+}
+
+__global__ void k_init_bounds(uint32_t* cb) {
+  if (threadIdx.x < 3) cb[threadIdx.x] = 0xFFFFFFFFu;        // min: +inf of the order
+  else if (threadIdx.x < 6) cb[threadIdx.x] = 0u;            // max: -inf of the order
+}
+
+// 2. Morton code of the centroid normalised to the centroid bounds; value = triangle index
+__global__ __launch_bounds__(kBB) void k_morton(const float* __restrict__ box, int64_t n,
+                                                const uint32_t* __restrict__ cb, uint32_t* __restrict__ key,
+                                                uint32_t* __restrict__ val) {
+  float lo[3], sc[3];
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = ord2f(cb[k]);
+    const float ext = ord2f(cb[3 + k]) - lo[k];
+    sc[k] = ext > 0.0f ? 1024.0f / ext : 0.0f;
+  }
+  for (int64_t i = blockIdx.x * (int64_t)kBB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBB) {
+    uint32_t q[3];
+    for (int k = 0; k < 3; ++k) {
+      const float c = 0.5f * (box[6 * i + k] + box[6 * i + 3 + k]);
+      const float t = (c - lo[k]) * sc[k];
+      q[k] = (uint32_t)fminf(fmaxf(t, 0.0f), 1023.0f);
+    }
+    key[i] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+    val[i] = (uint32_t)i;
+  }
+}
+
+// 3. radix sort passes over tiles of kTile keys (block b: keys [b kTile, (b + 1) kTile))
+__global__ __launch_bounds__(kBB) void k_radix_hist(const uint32_t* __restrict__ key, int64_t n, int shift,
+                                                    uint32_t* __restrict__ hist, int nb) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = base + r * kBB + threadIdx.x;
+    if (i < n) atomicAdd(&h[(key[i] >> shift) & 0xFFu], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive scan of m counts in place (one workgroup of 1024 threads)
+__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* __restrict__ a, int64_t m) {
+  __shared__ uint32_t part[1024];
+  const int64_t per = (m + 1023) / 1024;
+  const int64_t k0 = std::min<int64_t>(m, (int64_t)threadIdx.x * per), k1 = std::min<int64_t>(m, k0 + per);
+  uint32_t local = 0;
+  for (int64_t k = k0; k < k1; ++k) local += a[k];
+  part[threadIdx.x] = local;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - local;
+  for (int64_t k = k0; k < k1; ++k) {
+    const uint32_t c = a[k];
+    a[k] = run;
+    run += c;
+  }
+}
+
+// Stable scatter: within each round of 256 keys a key's rank among equal
+// digits comes from its wave's ballots (lane order) and the counts of the
+// waves before it; rounds run in order and carry a per-digit running offset.
+__global__ __launch_bounds__(kBB) void k_radix_scatter(const uint32_t* __restrict__ kin,
+                                                       const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+                                                       uint32_t* __restrict__ vout, int64_t n, int shift,
+                                                       const uint32_t* __restrict__ offs, int nb) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[kBB / 64][256];
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  run[tid] = offs[(size_t)tid * nb + blockIdx.x];
+  for (int w = 0; w < kBB / 64; ++w) wcnt[w][tid] = 0u;
+  __syncthreads();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t i = base + r * kBB + tid;
+    const bool valid = i < n;
+    const uint32_t k = valid ? kin[i] : 0u, v = valid ? vin[i] : 0u;
+    const uint32_t d = (k >> shift) & 0xFFu;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = ((d >> b) & 1u) != 0u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && rank == 0u) wcnt[wave][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank;
+      for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+      kout[pos] = k;
+      vout[pos] = v;
+    }
+    __syncthreads();
+    uint32_t tot = 0u;
+    for (int w = 0; w < kBB / 64; ++w) {
+      tot += wcnt[w][tid];
+      wcnt[w][tid] = 0u;
+    }
+    run[tid] += tot;
+    __syncthreads();
+  }
+}
+
+// 4. binary radix tree (n - 1 internal nodes).  Child references: leaf
+// (kLeafRef | sorted index) or internal node index; parents of leaves and of
+// internal nodes (-1 for the root); the sorted range [first, last] of each node.
+__device__ inline int delta(const uint32_t* key, int64_t n, int64_t i, int64_t j) {
+  if (j < 0 || j >= n) return -1;
+  const uint32_t a = key[i], b = key[j];
+  if (a == b) return 32 + __clz((uint32_t)i ^ (uint32_t)j);
+  return __clz(a ^ b);
+}
+
+__global__ __launch_bounds__(kBB) void k_radix_tree(const uint32_t* __restrict__ key, int64_t n,
+                                                    uint2* __restrict__ child, int32_t* __restrict__ parent_leaf,
+                                                    int32_t* __restrict__ parent_int, uint2* __restrict__ range,
+                                                    uint32_t* __restrict__ err) {
+  for (int64_t i = blockIdx.x * (int64_t)kBB + threadIdx.x; i < n - 1; i += (int64_t)gridDim.x * kBB) {
+    const int d = delta(key, n, i, i + 1) - delta(key, n, i, i - 1) >= 0 ? 1 : -1;
+    const int dmin = delta(key, n, i, i - d);
+    int64_t lmax = 2;
+    while (delta(key, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int64_t l = 0;
+    for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
+      if (delta(key, n, i, i + (l + t) * d) > dmin) l += t;
+    const int64_t j = i + l * d;
+    const int dnode = delta(key, n, i, j);
+    int64_t s = 0, t = l;
+    do {
+      t = (t + 1) >> 1;
+      if (delta(key, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    const int64_t gamma = i + s * d + (d < 0 ? -1 : 0);
+    const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+    if (gamma < lo || gamma + 1 > hi) {  // only unsorted codes could get here: report, write nothing
+      atomicOr(err, 1u);
+      continue;
+    }
+    uint32_t cl, cr;
+    if (lo == gamma) {
+      cl = kLeafRef | (uint32_t)gamma;
+      parent_leaf[gamma] = (int32_t)i;
+    } else {
+      cl = (uint32_t)gamma;
+      parent_int[gamma] = (int32_t)i;
+    }
+    if (hi == gamma + 1) {
+      cr = kLeafRef | (uint32_t)(gamma + 1);
+      parent_leaf[gamma + 1] = (int32_t)i;
+    } else {
+      cr = (uint32_t)(gamma + 1);
+      parent_int[gamma + 1] = (int32_t)i;
+    }
+    child[i] = make_uint2(cl, cr);
+    range[i] = make_uint2((uint32_t)lo, (uint32_t)hi);
+  }
+}
+
+// box of a binary-tree reference: a leaf's triangle box (sorted index -> triangle) or a node box
+__device__ inline void ref_box(uint32_t ref, const uint32_t* val, const float* tbox, const float* nbox, float b[6]) {
+  const float* src = (ref & kLeafRef) ? tbox + 6 * (size_t)val[ref & ~kLeafRef] : nbox + 6 * (size_t)ref;
+  for (int k = 0; k < 6; ++k) b[k] = src[k];
+}
+
+// 5. boxes bottom-up: the second arrival at a node merges both children's boxes
+__global__ __launch_bounds__(kBB) void k_boxes_up(int64_t n, const uint32_t* __restrict__ val,
+                                                  const float* __restrict__ tbox, const uint2* __restrict__ child,
+                                                  const int32_t* __restrict__ parent_leaf,
+                                                  const int32_t* __restrict__ parent_int, float* nbox,
+                                                  uint32_t* flag) {
+  for (int64_t i = blockIdx.x * (int64_t)kBB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBB) {
+    int32_t p = n > 1 ? parent_leaf[i] : -1;
+    // a radix tree over 30-bit codes and 32-bit indices is at most 63 levels deep; the bound only
+    // guards the walk against a malformed tree
+    for (int level = 0; p >= 0 && level < kMaxTreeLevels; ++level) {
+      // release this subtree's box, acquire the sibling's
+      if (__hip_atomic_fetch_add(&flag[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 0u) break;
+      const uint2 c = child[p];
+      float a[6], b[6];
+      ref_box(c.x, val, tbox, nbox, a);
+      ref_box(c.y, val, tbox, nbox, b);
+      for (int k = 0; k < 3; ++k) {
+        nbox[6 * (size_t)p + k] = fminf(a[k], b[k]);
+        nbox[6 * (size_t)p + 3 + k] = fmaxf(a[3 + k], b[3 + k]);
+      }
+      p = parent_int[p];
+    }
+  }
+}
+
+__device__ inline uint32_t ref_count(uint32_t ref, const uint2* range) {
+  if (ref & kLeafRef) return 1u;
+  const uint2 r = range[ref];
+  return r.y - r.x + 1u;
+}
+
+__device__ inline uint32_t ref_first(uint32_t ref, const uint2* range) {
+  return (ref & kLeafRef) ? (ref & ~kLeafRef) : range[ref].x;
+}
+
+__device__ inline float half_area(const float b[6]) {
+  const float dx = b[3] - b[0], dy = b[4] - b[1], dz = b[5] - b[2];
+  return dx * dy + dy * dz + dz * dx;
+}
+
+// 6. one level of the collapse: job (binary reference, BVH4 node index)
+__global__ __launch_bounds__(kBB) void k_collapse(const uint2* __restrict__ jobs, uint32_t n_jobs,
+                                                  uint2* __restrict__ next_jobs, uint32_t* __restrict__ n_next,
+                                                  uint32_t* __restrict__ n_nodes, uint32_t* __restrict__ max_leaf,
+                                                  const uint32_t* __restrict__ val, const float* __restrict__ tbox,
+                                                  const float* __restrict__ nbox, const uint2* __restrict__ child,
+                                                  const uint2* __restrict__ range, BVHNode* __restrict__ out,
+                                                  uint32_t cap, uint32_t* __restrict__ err) {
+  const uint32_t j = blockIdx.x * kBB + threadIdx.x;
+  if (j >= n_jobs) return;
+  const uint2 job = jobs[j];
+  uint32_t kids[4];
+  int nk = 0;
+  if ((job.x & kLeafRef) || ref_count(job.x, range) <= (uint32_t)kMaxLeafTris) {
+    kids[nk++] = job.x;  // the whole tree is one leaf under a one-child root
+  } else {
+    const uint2 c = child[job.x];
+    kids[nk++] = c.x;
+    kids[nk++] = c.y;
+    while (nk < 4) {
+      int pick = -1;
+      float pa = -1.0f;
+      for (int q = 0; q < nk; ++q) {
+        if (ref_count(kids[q], range) > (uint32_t)kMaxLeafTris) {
+          float b[6];
+          ref_box(kids[q], val, tbox, nbox, b);
+          const float a = half_area(b);
+          if (a > pa) {
+            pa = a;
+            pick = q;
+          }
+        }
+      }
+      if (pick < 0) break;
+      const uint2 cc = child[kids[pick]];
+      for (int q = nk; q > pick + 1; --q) kids[q] = kids[q - 1];  // open in place: siblings keep their order
+      kids[pick] = cc.x;
+      kids[pick + 1] = cc.y;
+      nk++;
+    }
+  }
+  BVHNode node;
+  for (int q = 0; q < 4; ++q) {
+    node.lo_x[q] = node.hi_x[q] = node.lo_y[q] = node.hi_y[q] = node.lo_z[q] = node.hi_z[q] = 0.0f;
+    node.child[q] = kEmpty;
+    node.meta[q] = 0u;
+  }
+  node.meta[0] = (uint32_t)nk;
+  uint32_t leaf_max = 0;
+  for (int q = 0; q < nk; ++q) {
+    float b[6];
+    ref_box(kids[q], val, tbox, nbox, b);
+    node.lo_x[q] = b[0];
+    node.lo_y[q] = b[1];
+    node.lo_z[q] = b[2];
+    node.hi_x[q] = b[3];
+    node.hi_y[q] = b[4];
+    node.hi_z[q] = b[5];
+    const uint32_t cnt = ref_count(kids[q], range);
+    if (cnt <= (uint32_t)kMaxLeafTris) {
+      node.child[q] = make_leaf(ref_first(kids[q], range), cnt);
+      leaf_max = cnt > leaf_max ? cnt : leaf_max;
+    } else {
+      const uint32_t o = atomicAdd(n_nodes, 1u);
+      const uint32_t slot = atomicAdd(n_next, 1u);
+      if (o >= cap || slot >= cap) {  // more nodes than a tree of this size can have: report
+        atomicOr(err, 2u);
+        continue;
+      }
+      node.child[q] = o;
+      next_jobs[slot] = make_uint2(kids[q], o);
+    }
+  }
+  if (job.y < cap) out[job.y] = node;
+  if (leaf_max) atomicMax(max_leaf, leaf_max);
+}
+
+// 7. triangle records in sorted order
+__global__ __launch_bounds__(kBB) void k_sorted_tris(const float* __restrict__ soup, const uint32_t* __restrict__ prim,
+                                                     const uint32_t* __restrict__ mat, const uint32_t* __restrict__ val,
+                                                     int64_t n, TriRec* __restrict__ tris) {
+  for (int64_t i = blockIdx.x * (int64_t)kBB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBB) {
+    const uint32_t t = val[i];
+    const float* p = soup + 9 * (size_t)t;
+    TriRec r;
+    r.a = make_float4(p[0], p[1], p[2], __uint_as_float(prim[t]));
+    r.b = make_float4(p[3], p[4], p[5], __uint_as_float(mat[t]));
+    r.c = make_float4(p[6], p[7], p[8], 0.0f);
+    tris[i] = r;
+  }
+}
+
+int grid_of(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBB - 1) / kBB, 8192)); }
+
+// device workspace of one build, freed when it goes out of scope
+struct Scratch {
+  std::vector<void*> ptrs;
+  ~Scratch() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <class T>
+  hipError_t get(T** out, size_t count) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(count * sizeof(T), 16));
+    if (e == hipSuccess) ptrs.push_back(p);
+    *out = static_cast<T*>(p);
+    return e;
+  }
+};
+
+}  // namespace
+
+#define PT_TRY(x)                         \
+  do {                                    \
+    hipError_t e_ = (x);                  \
+    if (e_ != hipSuccess) return e_;      \
+  } while (0)
+
+hipError_t gpu_build_bvh4(const float* soup, const uint32_t* prim, const uint32_t* mat, int64_t n, BVHNode* nodes,
+                          TriRec* tris, hipStream_t st, GpuBvhStats* stats) {
+  if (n <= 0 || n >= (int64_t)kLeafFirstMask) return hipErrorInvalidValue;
+  Scratch S;
+  float *tbox = nullptr, *nbox = nullptr;
+  uint32_t *cb = nullptr, *keyA = nullptr, *valA = nullptr, *keyB = nullptr, *valB = nullptr, *hist = nullptr;
+  uint32_t *flag = nullptr, *counters = nullptr;
+  uint2 *child = nullptr, *range = nullptr, *jobs[2] = {nullptr, nullptr};
+  int32_t *parent_leaf = nullptr, *parent_int = nullptr;
+  const int nb = (int)((n + kTile - 1) / kTile);
+  const int64_t ni = std::max<int64_t>(1, n - 1);
+  PT_TRY(S.get(&tbox, (size_t)n * 6));
+  PT_TRY(S.get(&nbox, (size_t)ni * 6));
+  PT_TRY(S.get(&cb, 6));
+  PT_TRY(S.get(&keyA, (size_t)n));
+  PT_TRY(S.get(&valA, (size_t)n));
+  PT_TRY(S.get(&keyB, (size_t)n));
+  PT_TRY(S.get(&valB, (size_t)n));
+  PT_TRY(S.get(&hist, (size_t)256 * nb));
+  PT_TRY(S.get(&flag, (size_t)ni));
+  PT_TRY(S.get(&counters, 4));  // [0] BVH4 nodes, [1] jobs of the next level, [2] largest leaf, [3] error bits
+  PT_TRY(S.get(&child, (size_t)ni));
+  PT_TRY(S.get(&range, (size_t)ni));
+  PT_TRY(S.get(&parent_leaf, (size_t)n));
+  PT_TRY(S.get(&parent_int, (size_t)ni));
+  PT_TRY(S.get(&jobs[0], (size_t)n));
+  PT_TRY(S.get(&jobs[1], (size_t)n));
+
+  hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, st, cb);
+  hipLaunchKernelGGL(k_tri_boxes, dim3(grid_of(n)), dim3(kBB), 0, st, soup, n, tbox, cb);
+  hipLaunchKernelGGL(k_morton, dim3(grid_of(n)), dim3(kBB), 0, st, tbox, n, cb, keyA, valA);
+  for (int pass = 0; pass < 4; ++pass) {  // codes have 30 bits
+    const int shift = 8 * pass;
+    hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kBB), 0, st, keyA, n, shift, hist, nb);
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, hist, (int64_t)256 * nb);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kBB), 0, st, keyA, valA, keyB, valB, n, shift, hist, nb);
+    std::swap(keyA, keyB);
+    std::swap(valA, valB);
+  }
+  PT_TRY(hipMemsetAsync(flag, 0, (size_t)ni * sizeof(uint32_t), st));
+  PT_TRY(hipMemsetAsync(counters, 0, 4 * sizeof(uint32_t), st));
+  if (n > 1) {
+    PT_TRY(hipMemsetAsync(parent_int, 0xFF, (size_t)ni * sizeof(int32_t), st));  // root: -1
+    hipLaunchKernelGGL(k_radix_tree, dim3(grid_of(n - 1)), dim3(kBB), 0, st, keyA, n, child, parent_leaf, parent_int,
+                       range, counters + 3);
+    hipLaunchKernelGGL(k_boxes_up, dim3(grid_of(n)), dim3(kBB), 0, st, n, valA, tbox, child, parent_leaf, parent_int,
+                       nbox, flag);
+  }
+  hipLaunchKernelGGL(k_sorted_tris, dim3(grid_of(n)), dim3(kBB), 0, st, soup, prim, mat, valA, n, tris);
+  // collapse, level by level, from the root (internal node 0, or the only leaf)
+  const uint32_t cap = (uint32_t)ni;  // nodes of the output (and jobs of a level) at most
+  const uint32_t init[3] = {1u, 0u, 0u};
+  const uint2 root = make_uint2(n > 1 ? 0u : kLeafRef, 0u);
+  PT_TRY(hipMemcpyAsync(counters, init, sizeof(init), hipMemcpyHostToDevice, st));
+  PT_TRY(hipMemcpyAsync(jobs[0], &root, sizeof(root), hipMemcpyHostToDevice, st));
+  uint32_t n_jobs = 1;
+  int levels = 0, cur = 0;
+  while (n_jobs > 0) {
+    if (levels >= kMaxTreeLevels) return hipErrorUnknown;
+    PT_TRY(hipMemsetAsync(counters + 1, 0, sizeof(uint32_t), st));
+    hipLaunchKernelGGL(k_collapse, dim3((n_jobs + kBB - 1) / kBB), dim3(kBB), 0, st, jobs[cur], n_jobs, jobs[cur ^ 1],
+                       counters + 1, counters, counters + 2, valA, tbox, nbox, child, range, nodes, cap,
+                       counters + 3);
+    PT_TRY(hipGetLastError());
+    PT_TRY(hipMemcpyAsync(&n_jobs, counters + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    PT_TRY(hipStreamSynchronize(st));
+    n_jobs = std::min(n_jobs, cap);
+    cur ^= 1;
+    levels++;
+  }
+  uint32_t fin[4];
+  PT_TRY(hipMemcpyAsync(fin, counters, sizeof(fin), hipMemcpyDeviceToHost, st));
+  PT_TRY(hipStreamSynchronize(st));
+  if (fin[3] != 0u || fin[0] > cap) return hipErrorUnknown;  // malformed tree: no result
+  stats->n_nodes = fin[0];
+  stats->max_leaf = (int)fin[2];
+  stats->depth = levels + 1;  // node levels, plus the leaves under the deepest nodes
+  return hipGetLastError();
+}
+
+}  // namespace pt

@@ -196,6 +196,17 @@ hipError_t noalloc_scratch(int dev, unsigned char** out);
 int traversal_grid(int64_t rays);  // workgroups of the traversal kernel for a pass of `rays` paths
 int tail_grid(int grid_trace, uint32_t paths, bool beside);  // workgroups of the tail kernel
 
+// ---- GPU BVH construction (pt_bvh_gpu.hip) ----
+struct GpuBvhStats {
+  int64_t n_nodes;  // BVH4 nodes written (at most max(1, n - 1))
+  int depth;        // nodes on the longest root-to-leaf path, counting the leaf level
+  int max_leaf;     // largest leaf (triangles)
+};
+// soup [n][9] floats, prim / mat [n] (device); nodes (device, room for max(1, n - 1) nodes; node 0 is
+// the root) and tris (device, [n], leaf order) are written; synchronises the stream.
+hipError_t gpu_build_bvh4(const float* soup, const uint32_t* prim, const uint32_t* mat, int64_t n, BVHNode* nodes,
+                          TriRec* tris, hipStream_t st, GpuBvhStats* stats);
+
 // ---- radiance cache (pt_nrc.hip) ----
 // t_step / n_records (nullable): count the applied Adam step on the device unless the batch had no records
 hipError_t nrc_launch_pack(const float* w, const float* wi, uint4* fwd, uint4* bwd, uint4* inf, uint32_t* t_step,

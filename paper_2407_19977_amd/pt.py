@@ -99,6 +99,9 @@ _SIGS = {
     "pt_trace_closest": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32]),
     "pt_trace_closest_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32]),
     "pt_display": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
+    "pt_build_bvh_gpu": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
+    "pt_scene_bvh_info": (C.c_int, [C.c_void_p, C.POINTER(pt_bvh_info)]),
+    "pt_scene_copy_bvh": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pt_set_accumulation": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int64]),
     "pt_get_stats": (C.c_int, [C.c_void_p, C.POINTER(pt_stats)]),
     "pt_reset_stats": (C.c_int, [C.c_void_p]),
@@ -203,7 +206,7 @@ class PtScene:
         self.close()
 
     # -- set-up
-    def build_bvh(self, meshes, instances=()):
+    def build_bvh(self, meshes, instances=(), on_device=False):
         keep = []
         arr = _mesh_structs(meshes, keep)
         ni = len(instances)
@@ -212,7 +215,21 @@ class PtScene:
             ia[i].object_to_world[:] = [float(x) for x in np.asarray(ins.object_to_world, np.float32).reshape(12)]
             ia[i].mesh = int(ins.mesh)
             ia[i].material_override = int(ins.material_override)
-        _check(_lib.pt_build_bvh(self.h, arr, len(meshes), ia, ni))
+        build = _lib.pt_build_bvh_gpu if on_device else _lib.pt_build_bvh
+        _check(build(self.h, arr, len(meshes), ia, ni))
+
+    def bvh_info(self) -> dict:
+        info = pt_bvh_info()
+        _check(_lib.pt_scene_bvh_info(self.h, C.byref(info)))
+        return {k: getattr(info, k) for k, _ in pt_bvh_info._fields_}
+
+    def copy_bvh(self):
+        """(nodes uint8 [n_nodes, 128], triangle records uint8 [n_tris, 48]) of the mesh-level BVH."""
+        info = self.bvh_info()
+        nodes = np.zeros((info["n_nodes"], 128), np.uint8)
+        tris = np.zeros((info["n_tris"], 48), np.uint8)
+        _check(_lib.pt_scene_copy_bvh(self.h, nodes.ctypes.data, tris.ctypes.data))
+        return nodes, tris
 
     def upload_materials(self, materials: np.ndarray):
         m = np.ascontiguousarray(materials, dtype=np.float32).reshape(-1, 27)
@@ -318,10 +335,11 @@ class PtScene:
         _check(_lib.pt_set_profiling(self.h, 1 if timing else 0, 1 if counting else 0))
 
 
-def scene_from(scene, device: int = 0, stream=None) -> PtScene:
-    """Upload a scenes.Scene (geometry, materials, environment) to a new PtScene."""
+def scene_from(scene, device: int = 0, stream=None, gpu_bvh: bool = False) -> PtScene:
+    """Upload a scenes.Scene (geometry, materials, environment) to a new PtScene
+    (BVH built on the host, or on the GPU with gpu_bvh)."""
     s = PtScene(device, stream)
-    s.build_bvh(scene.meshes, scene.instances)
+    s.build_bvh(scene.meshes, scene.instances, on_device=gpu_bvh)
     s.upload_materials(scene.materials)
     s.set_environment(scene.env)
     return s

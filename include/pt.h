@@ -144,9 +144,12 @@ pt_status pt_build_bvh(pt_scene* scene, const pt_mesh* meshes, int32_t n_meshes,
 pt_status pt_build_bvh_gpu(pt_scene* scene, const pt_mesh* meshes, int32_t n_meshes,
                            const pt_instance* instances, int32_t n_instances);
 
-/* Upload the OpenPBR materials (Sec. 4).  Errors: INVALID_ARG (n <= 0,
- * negative or non-finite parameters, IOR <= 0, weights outside [0,1]),
- * UNSUPPORTED (base_diffuse_roughness != 0, coat together with transmission). */
+/* Upload the OpenPBR materials (Sec. 4).  base_diffuse_roughness > 0 gives
+ * the energy-preserving Oren-Nayar diffuse (EON); specular_weight modulates
+ * the dielectric IOR (F0(eta') = specular_weight F0(eta)) and scales the
+ * metal Fresnel.  Errors: INVALID_ARG (n <= 0, negative or non-finite
+ * parameters, IOR <= 0, weights or base_diffuse_roughness outside [0,1]),
+ * UNSUPPORTED (coat together with transmission). */
 pt_status pt_upload_materials(pt_scene* scene, const pt_openpbr_material* materials, int32_t n);
 
 /* Set the environment: an equirectangular RGB32F image [h][w][3] (y up,

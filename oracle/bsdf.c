@@ -16,12 +16,24 @@
  *   Metal Fresnel: OpenPBR F82-tint.
  *   Lobes: C coat (dielectric GGX reflection), M metal, I dielectric interface
  *   (GGX reflection + rough refraction, Walter et al. 2007 eq. 21, with the
- *   1/eta^2 radiance factor), D Lambert attenuated by the interface Fresnel.
+ *   1/eta^2 radiance factor), D diffuse attenuated by the interface Fresnel:
+ *   Lambert, or with base_diffuse_roughness sigma > 0 the energy-preserving
+ *   Oren-Nayar model EON (Portsmouth, Kutz, Hill 2024) over Fujii's FON:
+ *   f = rho (A + B s/t)/pi + rho_ms (1 - E(mu_o))(1 - E(mu_i)) / (pi (1 - Eb)),
+ *   A = 1/(1 + (1/2 - 2/(3 pi)) sigma), B = sigma A, s = wi.wo - mu_i mu_o,
+ *   t = max(mu_i, mu_o) if s > 0 else 1, E(mu) = A + (B/pi) G(mu) the FON
+ *   albedo with G(mu) = sin(th) (th - sin(th) mu + (2/3)(1 - sin^3(th))/mu - 2/3),
+ *   Eb = A + B (2/3 - 28/(15 pi)) its cosine-weighted mean,
+ *   rho_ms = rho^2 Eb / (1 - rho (1 - Eb)); sampled by the cosine.
+ *   specular_weight xi modulates the dielectric IOR (OpenPBR): the interface
+ *   and the cache input use eta' with F0(eta') = xi F0(eta), so reflection,
+ *   refraction and the diffuse attenuation stay consistent; the metal
+ *   Fresnel is scaled by xi.
  *   f = C + [(1-cw) + cw*coat_color*(1-Fc(|mu_i|))(1-Fc(mu_o))]
  *           * [metalness*M + (1-metalness)*(I + D)].
  *   Lobe choice pmf at mu_o: w_C = cw*Fc, w_M = Tc*metalness*sw*lum(F82),
  *   w_I = Tc*(1-metalness)*(Fd + tw*(1-Fd)), w_D = Tc*(1-metalness)*(1-tw)*(1-Fd)*lum(bw*bc),
- *   Tc = 1 - cw*Fc(mu_o), Fd = sw*F(mu_o, eta).
+ *   Tc = 1 - cw*Fc(mu_o), Fd = F(mu_o, eta').
  *   Non-delta sampling weight: f_nd*|cos|/sum_k P_k pdf_k (one-sample MIS over lobes).
  *
  * Frame: local +z is the surface normal flipped to the side of wo, so mu_o > 0.
@@ -39,6 +51,34 @@ double ofresnel_diel(double c, double eta) {
   double a = (g - c) / (g + c);
   double b = (c * (g + c) - 1.0) / (c * (g - c) + 1.0);
   return 0.5 * a * a * (1.0 + b * b);
+}
+
+double omod_ior(const omat* m) {
+  /* F0(eta') = xi F0(eta): eta' = (1 + sqrt(xi F0)) / (1 - sqrt(xi F0)), inverted below 1 */
+  double eta = m->spec_ior, xi = m->spec_weight;
+  if (xi >= 1.0) return eta;
+  double r0 = (eta - 1.0) / (eta + 1.0);
+  double r = sqrt(xi * r0 * r0);
+  return eta >= 1.0 ? (1.0 + r) / (1.0 - r) : (1.0 - r) / (1.0 + r);
+}
+
+/* FON albedo E(mu) for rho = 1 and its cosine-weighted mean Eb */
+static double ofon_albedo(double A, double B, double mu) {
+  double sn = sqrt(1.0 - mu * mu > 0.0 ? 1.0 - mu * mu : 0.0);
+  double th = acos(mu);
+  double G = sn * (th - sn * mu + (2.0 / 3.0) * mu * (1.0 + sn + sn * sn) / (1.0 + sn) - 2.0 / 3.0);
+  return A + B / O_PI * G;
+}
+
+double oeon(double rho, double sigma, double mu_i, double mu_o, double s) {
+  if (!(sigma > 0.0)) return rho / O_PI;
+  double A = 1.0 / (1.0 + (0.5 - 2.0 / (3.0 * O_PI)) * sigma), B = sigma * A;
+  double t = s > 0.0 ? (mu_i > mu_o ? mu_i : mu_o) : 1.0;
+  double f = rho * (A + B * s / t) / O_PI;
+  double Eb = A + B * (2.0 / 3.0 - 28.0 / (15.0 * O_PI));
+  double Eo = ofon_albedo(A, B, mu_o), Ei = ofon_albedo(A, B, mu_i);
+  double rho_ms = rho * rho * Eb / (1.0 - rho * (1.0 - Eb));
+  return f + rho_ms / O_PI * (1.0 - Eo) * (1.0 - Ei) / (1.0 - Eb);
 }
 
 void of82(const omat* m, double mu, double F[3]) {
@@ -101,7 +141,8 @@ static double clampa(double a) { return a < 1e-4 ? 1e-4 : a; }
 void obsdf_setup(const omat* m, int entering, double mu_o, obsdf* b) {
   b->m = *m;
   b->entering = entering;
-  b->eta = (m->trans_weight > 0.0 && !entering) ? 1.0 / m->spec_ior : m->spec_ior;
+  double ior = omod_ior(m);
+  b->eta = (m->trans_weight > 0.0 && !entering) ? 1.0 / ior : ior;
   double r = m->spec_rough, a = m->spec_aniso;
   double alpha = r * r;
   double at = alpha * sqrt(2.0 / (1.0 + (1.0 - a) * (1.0 - a)));
@@ -113,7 +154,7 @@ void obsdf_setup(const omat* m, int entering, double mu_o, obsdf* b) {
   double cw = m->coat_weight, mt = m->metalness, tw = m->trans_weight, sw = m->spec_weight;
   double Fc = ofresnel_diel(mu_o, m->coat_ior);
   double Tc = 1.0 - cw * Fc;
-  double Fd = sw * ofresnel_diel(mu_o, b->eta);
+  double Fd = ofresnel_diel(mu_o, b->eta);
   double F82[3];
   of82(m, mu_o, F82);
   double bwbc[3] = {m->base_weight * m->base_color[0], m->base_weight * m->base_color[1],
@@ -181,15 +222,16 @@ void obsdf_eval(const obsdf* b, v3 wo, v3 wi, double f[3], double* pdf) {
       of82(m, oh, F82);
       for (int c = 0; c < 3; ++c) fm[c] = sw * F82[c] * D * g / (4.0 * mu_o * mu_i);
       double Fi = ofresnel_diel(oh, b->eta);
-      fi = sw * Fi * D * g / (4.0 * mu_o * mu_i);
+      fi = Fi * D * g / (4.0 * mu_o * mu_i);
       pm = pv;
       double denom = Fi + tw * (1.0 - Fi);
       pi = denom > 0.0 ? (Fi / denom) * pv : 0.0;
     }
     double Fdi = ofresnel_diel(mu_i, b->eta), Fdo = ofresnel_diel(mu_o, b->eta);
-    double kd = (1.0 - tw) * (1.0 - sw * Fdi) * (1.0 - sw * Fdo) / O_PI;
+    double kd = (1.0 - tw) * (1.0 - Fdi) * (1.0 - Fdo);
+    double s = vdot(wi, wo) - mu_i * mu_o;
     for (int c = 0; c < 3; ++c) {
-      double fd = kd * m->base_weight * m->base_color[c];
+      double fd = kd * oeon(m->base_weight * m->base_color[c], m->diffuse_roughness, mu_i, mu_o, s);
       f[c] = fc + L[c] * (mt * fm[c] + (1.0 - mt) * (fi + fd));
     }
     *pdf = b->P[LOBE_C] * pc + b->P[LOBE_M] * pm + b->P[LOBE_I] * pi + b->P[LOBE_D] * (mu_i / O_PI);
@@ -294,7 +336,7 @@ int obsdf_sample(const obsdf* b, v3 wo, double u_lobe, double u1, double u2, dou
         *lobe_code = 2;
         *wi = V(-wo.x, -wo.y, wo.z);
         coat_layer(b, mu_o, mu_o, L);
-        for (int c = 0; c < 3; ++c) weight[c] = L[c] * (1.0 - mt) * sw * F / (b->P[LOBE_I] * pr);
+        for (int c = 0; c < 3; ++c) weight[c] = L[c] * (1.0 - mt) * F / (b->P[LOBE_I] * pr);
         return 1;
       }
       *lobe_code = 3;

@@ -9,7 +9,8 @@
  * (acos(y)/pi, atan2(x, -z)/2pi + 1/2) (2 + 2); specular roughness (1);
  * diffuse albedo (1-metalness)(1-transmission) base_weight base_color (3);
  * specular luminance metalness lum(base_weight base_color) +
- * (1-metalness) F_dielectric(1, specular_ior) (1).
+ * (1-metalness) F_dielectric(1, eta') (1), eta' the IOR after the
+ * specular_weight modulation.
  *
  * Encoding to 64 features: for each position axis and k = 0..5 the pair
  * sin(2^k pi x), cos(2^k pi x) (36); one-blob encodings with 4 bins of the
@@ -111,7 +112,7 @@ void onrc_inputs(const oracle_scene* s, v3 p, v3 wo, v3 n, const omat* m, double
   for (int c = 0; c < 3; ++c) x[8 + c] = k * m->base_color[c];
   double F0[3] = {m->base_weight * m->base_color[0], m->base_weight * m->base_color[1],
                   m->base_weight * m->base_color[2]};
-  x[11] = m->metalness * lum3(F0) + (1.0 - m->metalness) * ofresnel_diel(1.0, m->spec_ior);
+  x[11] = m->metalness * lum3(F0) + (1.0 - m->metalness) * ofresnel_diel(1.0, omod_ior(m));
 }
 
 /* Test hook: onrc_inputs for a scene box [lo, hi] and a material given as

@@ -35,6 +35,10 @@ typedef struct {
 } omat;
 
 void omat_from_floats(const float* f, omat* m);
+/* dielectric IOR after the specular_weight modulation (bsdf.c) */
+double omod_ior(const omat* m);
+/* EON diffuse value (1/pi included) for albedo rho, roughness sigma, s = wi.wo - mu_i mu_o (bsdf.c) */
+double oeon(double rho, double sigma, double mu_i, double mu_o, double s);
 
 /* ---- BVH over one mesh, object space, FP64 ---- */
 typedef struct {

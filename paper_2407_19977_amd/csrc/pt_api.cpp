@@ -1086,8 +1086,8 @@ pt_status validate_material(const pt_openpbr_material& m, int i) {
   for (float u : unit)
     if (u > 1.0f) return fail(PT_ERR_INVALID_ARG, "material %d: weights and roughness must be in [0, 1]", i);
   if (!(m.specular_ior > 0.0f) || !(m.coat_ior > 0.0f)) return fail(PT_ERR_INVALID_ARG, "material %d: IOR must be > 0", i);
-  if (m.base_diffuse_roughness != 0.0f)
-    return fail(PT_ERR_UNSUPPORTED, "material %d: base_diffuse_roughness != 0 is not supported", i);
+  if (m.base_diffuse_roughness > 1.0f)
+    return fail(PT_ERR_INVALID_ARG, "material %d: base_diffuse_roughness must be in [0, 1]", i);
   if (m.coat_weight > 0.0f && m.transmission_weight > 0.0f)
     return fail(PT_ERR_UNSUPPORTED, "material %d: coat together with transmission is not supported", i);
   return PT_OK;
@@ -1106,7 +1106,21 @@ MatRec make_matrec(const pt_openpbr_material& m) {
   r.base_weight = m.base_weight;
   r.metalness = m.base_metalness;
   r.spec_weight = m.specular_weight;
-  r.spec_ior = m.specular_ior;
+  {  // specular_weight xi modulates the dielectric IOR: F0(eta') = xi F0(eta) (OpenPBR)
+    const double eta = m.specular_ior, xi = m.specular_weight;
+    double mod = eta;
+    if (xi < 1.0) {
+      const double r0 = (eta - 1.0) / (eta + 1.0), q = std::sqrt(xi * r0 * r0);
+      mod = eta >= 1.0 ? (1.0 + q) / (1.0 - q) : (1.0 - q) / (1.0 + q);
+    }
+    r.spec_ior = (float)mod;
+  }
+  {  // EON diffuse roughness: FON's A and B (B = 0: Lambert)
+    const double sg = m.base_diffuse_roughness;
+    const double A = 1.0 / (1.0 + (0.5 - 2.0 / (3.0 * M_PI)) * sg);
+    r.eon_a = (float)A;
+    r.eon_b = (float)(sg * A);
+  }
   r.trans_weight = m.transmission_weight;
   r.coat_weight = m.coat_weight;
   r.coat_ior = m.coat_ior;
@@ -1139,8 +1153,8 @@ MatRec make_matrec(const pt_openpbr_material& m) {
   else cls = kClsGeneral;
   r.cls = cls;
   r.spec_rough = m.specular_roughness;
-  {  // exact unpolarised dielectric reflectance at normal incidence, c = 1
-    double eta = m.specular_ior, c = 1.0;
+  {  // exact unpolarised dielectric reflectance at normal incidence, c = 1, of the modulated IOR
+    double eta = r.spec_ior, c = 1.0;
     double g = std::sqrt(eta * eta - 1.0 + c * c);
     double a = (g - c) / (g + c), b = (c * (g + c) - 1.0) / (c * (g - c) + 1.0);
     r.f0_diel = (float)(0.5 * a * a * (1.0 + b * b));

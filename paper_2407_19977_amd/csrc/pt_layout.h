@@ -76,8 +76,8 @@ struct alignas(128) MatRec {
   float coat_color[3];  float bwbc_lum;     // lum(base_weight * base_color)
   float Le[3];          uint32_t flags;     // emission radiance; flags below
   float at, ab, ac;     int32_t cls;        // GGX alphas (specular t/b, coat), class
-  float spec_rough;     float f0_diel;      // specular roughness; F_dielectric(1, specular_ior)
-  float pad[2];
+  float spec_rough;     float f0_diel;      // specular roughness; F_dielectric(1, eta')
+  float eon_a, eon_b;   // diffuse roughness sigma as FON's A = 1/(1 + (1/2 - 2/(3 pi)) sigma), B = sigma A
 };
 static_assert(sizeof(MatRec) == 128, "material record is 128 bytes");
 constexpr uint32_t kMatSpecDelta = 1u, kMatCoatDelta = 2u, kMatEmissive = 4u;

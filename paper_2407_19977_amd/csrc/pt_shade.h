@@ -191,7 +191,7 @@ __host__ __device__ inline Bsdf bsdf_setup(const MatRec& m, bool entering, float
   b.eta = (m.trans_weight > 0.0f && !entering) ? 1.0f / m.spec_ior : m.spec_ior;
   float Fc = L::C ? fresnel_diel(mu_o, m.coat_ior) : 0.0f;
   float Tc = 1.0f - m.coat_weight * Fc;
-  float Fd = (L::I || L::D) ? m.spec_weight * fresnel_diel(mu_o, b.eta) : 0.0f;
+  float Fd = (L::I || L::D) ? fresnel_diel(mu_o, b.eta) : 0.0f;
   float w0 = L::C ? m.coat_weight * Fc : 0.0f;
   float w1 = 0.0f;
   if (L::M) {
@@ -226,6 +226,30 @@ __host__ __device__ inline V3 coat_layer(const MatRec& m, float mu_i, float mu_o
   float k = (1.0f - Fi) * (1.0f - Fo);
   return v3((1.0f - cw) + cw * m.coat_color[0] * k, (1.0f - cw) + cw * m.coat_color[1] * k,
             (1.0f - cw) + cw * m.coat_color[2] * k);
+}
+
+// Diffuse value (1/pi included) of albedo rho: Lambert when the material's
+// FON B is 0, else EON, the energy-preserving Oren-Nayar model (Portsmouth,
+// Kutz, Hill 2024) over Fujii's FON: rho (A + B s/t)/pi plus the
+// multiple-scattering term rho_ms (1 - E(mu_o))(1 - E(mu_i)) / (pi (1 - Eb)),
+// with E the FON albedo, Eb its cosine-weighted mean and
+// rho_ms = rho^2 Eb / (1 - rho (1 - Eb)); s = wi.wo - mu_i mu_o.
+__host__ __device__ inline float fon_albedo(float A, float B, float mu) {
+  float sn = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
+  float th = acosf(mu);
+  float G = sn * (th - sn * mu + (2.0f / 3.0f) * mu * (1.0f + sn + sn * sn) / (1.0f + sn) - 2.0f / 3.0f);
+  return A + B * (1.0f / kPi) * G;
+}
+
+__host__ __device__ inline float eon(const MatRec& m, float rho, float mu_i, float mu_o, float s) {
+  const float A = m.eon_a, B = m.eon_b;
+  if (!(B > 0.0f)) return rho * (1.0f / kPi);
+  float t = s > 0.0f ? fmaxf(mu_i, mu_o) : 1.0f;
+  float f = rho * (A + B * s / t) * (1.0f / kPi);
+  float Eb = A + B * (2.0f / 3.0f - 28.0f / (15.0f * kPi));
+  float Eo = fon_albedo(A, B, mu_o), Ei = fon_albedo(A, B, mu_i);
+  float rho_ms = rho * rho * Eb / (1.0f - rho * (1.0f - Eb));
+  return f + rho_ms * (1.0f / kPi) * (1.0f - Eo) * (1.0f - Ei) / (1.0f - Eb);
 }
 
 // Non-delta f(wo, wi) and the mixture pdf sum_k P_k pdf_k(wi).
@@ -264,19 +288,23 @@ __host__ __device__ inline V3 bsdf_eval(const MatRec& m, const Bsdf& b, V3 wo, V
       }
       if (L::I) {
         float Fi = fresnel_diel(oh, b.eta);
-        fi = sw * Fi * D * g * inv4;
+        fi = Fi * D * g * inv4;
         float dn = Fi + tw * (1.0f - Fi);
         pi = dn > 0.0f ? (Fi / dn) * pv : 0.0f;
       }
     }
-    float kd = 0.0f;
+    V3 fd = v3(0.0f, 0.0f, 0.0f);
     if (L::D) {
       float Fdi = fresnel_diel(mu_i, b.eta), Fdo = fresnel_diel(mu_o, b.eta);
-      kd = (1.0f - tw) * (1.0f - sw * Fdi) * (1.0f - sw * Fdo) * (1.0f / kPi);
+      float kd = (1.0f - tw) * (1.0f - Fdi) * (1.0f - Fdo);
+      float s = dot(wi, wo) - mu_i * mu_o;
+      fd = v3(kd * eon(m, m.base_weight * m.base_color[0], mu_i, mu_o, s),
+              kd * eon(m, m.base_weight * m.base_color[1], mu_i, mu_o, s),
+              kd * eon(m, m.base_weight * m.base_color[2], mu_i, mu_o, s));
     }
-    float fx = fc + Lc.x * (mt * fm.x + (1.0f - mt) * (fi + kd * m.base_weight * m.base_color[0]));
-    float fy = fc + Lc.y * (mt * fm.y + (1.0f - mt) * (fi + kd * m.base_weight * m.base_color[1]));
-    float fz = fc + Lc.z * (mt * fm.z + (1.0f - mt) * (fi + kd * m.base_weight * m.base_color[2]));
+    float fx = fc + Lc.x * (mt * fm.x + (1.0f - mt) * (fi + fd.x));
+    float fy = fc + Lc.y * (mt * fm.y + (1.0f - mt) * (fi + fd.y));
+    float fz = fc + Lc.z * (mt * fm.z + (1.0f - mt) * (fi + fd.z));
     f = v3(fx, fy, fz);
     pdf = b.P[0] * pc + b.P[1] * pm + b.P[2] * pi + b.P[3] * (mu_i * (1.0f / kPi));
     return f;
@@ -391,7 +419,7 @@ __host__ __device__ inline BsdfSample bsdf_sample(const MatRec& m, const Bsdf& b
         s.lobe = 2;
         s.wi = v3(-wo.x, -wo.y, wo.z);
         V3 Lc = coat_layer<CLS>(m, mu_o, mu_o);
-        float k = (1.0f - mt) * sw * F / (b.P[2] * pr);
+        float k = (1.0f - mt) * F / (b.P[2] * pr);
         s.weight = v3(Lc.x * k, Lc.y * k, Lc.z * k);
         s.ok = true;
         return s;

@@ -255,8 +255,13 @@ def material_zoo(width=96, height=96, spp=8, max_depth=6, seed=0, sphere_level=2
     transmission over diffuse and over partial metal, tints of the
     specular, coat and transmission colours, specular_weight < 1 and
     anisotropy under a coat — the OpenPBR mixes that the closed-box,
-    icosphere-field and instanced scenes do not reach."""
-    mats = [lambert((0.6, 0.6, 0.6)), lambert((0.7, 0.4, 0.3)), lambert((0.3, 0.6, 0.4)), lambert((0.4, 0.4, 0.7)),
+    icosphere-field and instanced scenes do not reach.  The back wall is a
+    rough diffuse (base_diffuse_roughness 0.7) and the left wall a rough
+    diffuse base (0.3) under a glossy specular layer."""
+    mats = [lambert((0.6, 0.6, 0.6)),
+            material(base_color=(0.7, 0.4, 0.3), base_diffuse_roughness=0.7, specular_weight=0.0),
+            material(base_color=(0.3, 0.6, 0.4), base_diffuse_roughness=0.3, specular_roughness=0.5),
+            lambert((0.4, 0.4, 0.7)),
             material(base_weight=0.0, specular_weight=0.0, emission_luminance=12.0,
                      emission_color=(1.0, 0.95, 0.9))]
     mats += [material(**kw) for _, kw in ZOO_MATERIALS]

@@ -329,9 +329,11 @@ def test_progressive_accumulation_is_bitwise(P, O):
 # ------------------------------------------------------------ closed forms --
 
 def test_gpu_white_furnace_and_glass(P, O):
-    _say("[closed form] white furnace sphere / cubes, smooth glass sphere")
-    for kind, depth in (("sphere", 6), ("cubes", 64), ("glass", 64)):
-        sc = scenes.furnace(kind, width=32, height=32)
+    _say("[closed form] white furnace sphere / cubes, rough white diffuse (EON), smooth glass sphere")
+    rough = scenes.material(base_color=(1.0, 1.0, 1.0), base_diffuse_roughness=1.0, specular_weight=0.0)
+    for kind, depth, mat in (("sphere", 6, None), ("cubes", 64, None), ("sphere", 6, rough), ("cubes", 64, rough),
+                             ("glass", 64, None)):
+        sc = scenes.furnace(kind, width=32, height=32, mat=mat)
         s = P.scene_from(sc, device=0)
         g, _ = _debug(s, sc.camera, (0, 0, 32, 32), 0, 16, depth)
         v = g.reshape(-1, 3)
@@ -402,7 +404,12 @@ def test_error_codes(P, O):
         s.render(sc.with_camera(vfov_deg=180.0).camera, 4, 4, 0, out)
     assert e.value.status == -1
     bad = sc.materials.copy()
-    bad[0, 5] = 0.5  # base_diffuse_roughness
+    bad[0, 5] = 1.5  # base_diffuse_roughness above 1
+    with pytest.raises(P.PtError) as e:
+        s.upload_materials(bad)
+    assert e.value.status == -1
+    bad = sc.materials.copy()
+    bad[0] = scenes.material(coat_weight=1.0, transmission_weight=1.0)  # coat over transmission
     with pytest.raises(P.PtError) as e:
         s.upload_materials(bad)
     assert e.value.status == -4

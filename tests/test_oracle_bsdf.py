@@ -31,8 +31,12 @@ MATS = {
     "glass_rough": M(base_weight=0.0, transmission_weight=1.0, specular_roughness=0.3, specular_ior=1.5),
     "glass_tinted": M(base_weight=0.0, transmission_weight=0.7, transmission_color=(0.9, 0.5, 0.5),
                       specular_roughness=0.45, specular_ior=1.33, base_color=(0.3, 0.3, 0.3)),
+    "eon": M(base_color=(0.7, 0.4, 0.2), base_diffuse_roughness=0.8, specular_weight=0.0),
+    "eon_plastic_weak": M(base_color=(0.5, 0.3, 0.2), base_diffuse_roughness=0.4, specular_roughness=0.4,
+                          specular_weight=0.5),
 }
-OPAQUE = ["lambert", "metal", "metal_aniso", "plastic", "coated_delta", "coated_rough", "half_metal"]
+OPAQUE = ["lambert", "metal", "metal_aniso", "plastic", "coated_delta", "coated_rough", "half_metal", "eon",
+          "eon_plastic_weak"]
 
 
 def sph(theta, phi):

@@ -250,26 +250,33 @@ def test_self_training_adds_the_cache_times_the_albedo_product(O):
 
 
 def test_factorised_targets_divide_by_albedo_plus_normal_reflectance(O):
-    """Lambertian materials (specular_ior 1.5): the reflectance factor is
-    rho + ((1.5 - 1) / (1.5 + 1))^2 = rho + 0.04 per channel, and factorised
-    targets are the plain ones divided by it."""
+    """The box's Lambert walls have specular_weight 0, so their modulated IOR is
+    1 and their specular input F(1, 1) is 0: the reflectance factor is rho per
+    channel, and factorised targets are the plain ones divided by it.  A wall
+    with specular_weight 1 (IOR 1.5) adds ((1.5 - 1) / (1.5 + 1))^2 = 0.04."""
     sc = scenes.cornell(width=32, height=32)
     os_ = O.OracleScene(sc)
     n = 0
     for k, (a, b) in _box_paths(os_, 200, lambda px, py, smp: (
             os_.training_records(px, py, smp, 5, factorize=True), os_.training_records(px, py, smp, 5))):
         (Xf, Tf), (Xp, Tp) = a, b
+        keep = np.all(Xp[:, 8:11] + Xp[:, 11:12] != 0.0, axis=1)  # a zero factor drops the record (the light)
+        Xp, Tp = Xp[keep], Tp[keep]
         assert np.array_equal(Xf, Xp)
-        assert np.allclose(Xf[:, 11], 0.04, rtol=1e-12)
-        assert np.allclose(Tf * (Xf[:, 8:11] + 0.04), Tp, rtol=1e-12, atol=1e-15)
+        assert np.all(Xf[:, 11] == 0.0)
+        assert np.allclose(Tf * Xf[:, 8:11], Tp, rtol=1e-12, atol=1e-15)
         n += len(Tf)
     assert n > 300
+    # specular_weight 1: the cache input is the normal-incidence reflectance 0.04 of IOR 1.5
+    x = O.nrc_inputs((0, 0, 0), (1, 1, 1), (0.5, 0.5, 0.5), (0, 0, 1), (0, 0, 1),
+                     scenes.material(base_color=(0.3, 0.4, 0.5), specular_weight=1.0))
+    assert abs(x[11] - 0.04) < 1e-15
 
 
 def test_factorised_cache_query_multiplies_by_the_factor(O):
     """The box seen through a cache answering c at vertex 0: every path that
-    hits a Lambertian wall first carries c * (rho + 0.04) (emission at vertex 0
-    aside, the light's own albedo factor is 0)."""
+    hits a Lambertian wall first carries c * rho (the walls' specular input is
+    0; emission at vertex 0 aside, the light's own albedo factor is 0)."""
     sc = scenes.cornell(width=16, height=16)
     os_ = O.OracleScene(sc)
     r = os_.render(2, 4, per_sample=True, nrc_weights=_constant_cache(0.5), nrc_bounce=0, nrc_factor=True)
@@ -279,7 +286,7 @@ def test_factorised_cache_query_multiplies_by_the_factor(O):
     ok = 0
     for a, b in zip(v, vp):
         if np.allclose(b, 0.5, rtol=1e-12):  # a wall: the plain query gives 0.5 exactly
-            rho = a / 0.5 - 0.04
+            rho = a / 0.5
             assert np.any(np.all(np.isclose(alb, rho, rtol=1e-6, atol=1e-7), axis=1)), rho
             ok += 1
     assert ok > 100

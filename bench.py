@@ -295,6 +295,7 @@ def cache_experiment(pt, torch, sc, frames=256, ref_spp=4096, seeds=4, variants=
     for k in range(8):
         s.accumulate(cam, frames + k, 1, depth, 0)
     st_iso = s.stats()
+    fwd_2m = forward_rate(s, torch)
     var_out = []
     for name, kw in variants:
         vruns, _ = _cache_runs(pt, s, cam, depth, frames, seeds, ref, out, torch, {**kw, **cache_kw})
@@ -338,6 +339,7 @@ def cache_experiment(pt, torch, sc, frames=256, ref_spp=4096, seeds=4, variants=
             "flop_per_query": NRC_FLOP_PER_QUERY, "queries": st_iso["cache_queries"],
             "avg_launch_ms": round(q_ms / 8, 4),
             "measured_on": "8 frames of one call each (the query kernel with nothing beside it)",
+            "pt_nrc_forward_2M_queries": fwd_2m,
             "in_overlapped_frames_tflops": None if achieved_frames is None else round(achieved_frames, 2)},
     })
     s.close()
@@ -458,6 +460,59 @@ def instanced_1080p(pt, torch, spp, tail=None):
            "ms_per_render": round(dt * 1e3, 2), "extension_rays": st["extension_rays"],
            "shadow_rays": st["shadow_rays"],
            "roofline": traversal_roofline(counts, st, 1, "k_traverse<two-level> (top-level + per-mesh BVH4 walks)")}
+    s.close()
+    return res
+
+
+def forward_rate(s, torch, n=1 << 21, calls=10):
+    """pt_nrc_forward on n uniform inputs: average kernel time (HIP events on
+    the library's stream) and the matrix-core roofline it reaches."""
+    g = torch.Generator(device="cpu").manual_seed(7)
+    x = torch.rand((n, 12), generator=g, dtype=torch.float32).to("cuda:0")
+    y = torch.empty((n, 3), dtype=torch.float32, device="cuda:0")
+    s.nrc_forward(x, y)
+    s.set_profiling(True, False)
+    s.reset_stats()
+    for _ in range(calls):
+        s.nrc_forward(x, y)
+    st = s.stats()
+    ms = st["ms_cache_forward"] / calls
+    tflops = n * NRC_FLOP_PER_QUERY / (ms * 1e-3) / 1e12
+    return {"queries": n, "avg_launch_ms": round(ms, 4), "achieved_tflops": round(tflops, 2),
+            "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4)}
+
+
+def nrc_kernels(pt, torch, scenes, warm_frames=16, iso_frames=8, n_forward=1 << 21, forward_calls=20):
+    """The radiance-cache kernels on their own (icosphere field 1080p, frames of
+    1 spp): queries of frames run one call each (the query kernel with nothing
+    beside it), the training steps of those frames, and pt_nrc_forward on
+    n_forward uniform inputs (HIP events around each call).  Short
+    enough to run under a counter profiler."""
+    sc = scenes.spheres(spp=1)
+    cam = sc.camera
+    s = pt.scene_from(sc, device=0)
+    s.set_radiance_cache(pt.cache_config())
+    s.reset_accumulation()
+    s.accumulate(cam, 0, warm_frames, sc.max_depth, 0)
+    s.set_profiling(True, False)
+    s.reset_stats()
+    steps0 = s.stats()["cache_adam_steps"]  # the device's step counter is not reset
+    for k in range(iso_frames):
+        s.accumulate(cam, warm_frames + k, 1, sc.max_depth, 0)
+    st = s.stats()
+    s.set_profiling(False, False)
+    cfg = pt.cache_config()
+    q_ms = st["ms_cache_query"]
+    res = {"workload": f"icosphere field {cam.width}x{cam.height}, depth {sc.max_depth}, cache after {warm_frames} "
+                       f"frames; {iso_frames} frames of one call each",
+           "queries_per_frame": st["cache_queries"] // iso_frames,
+           "query_kernel_ms_per_frame": round(q_ms / iso_frames, 4),
+           "query_tflops": round(st["cache_queries"] * NRC_FLOP_PER_QUERY / (q_ms * 1e-3) / 1e12, 2) if q_ms > 0
+           else None,
+           "train_ms_per_frame": round(st["ms_cache_train"] / iso_frames, 4),
+           "train_samples_per_frame": (st["cache_adam_steps"] - steps0) * cfg.batch_size // iso_frames}
+    res["pt_nrc_forward"] = forward_rate(s, torch, n_forward, forward_calls)
+    s.set_radiance_cache(None)
     s.close()
     return res
 
@@ -590,11 +645,11 @@ def main():
     ap.add_argument("--cache-factorize", type=int, default=None, help="factorize of the cache (0 or 1)")
     ap.add_argument("--cache-query-bounce", type=int, default=None, help="query_bounce of the cache")
     ap.add_argument("--cache-spread", type=float, default=None, help="spread_c of the cache (adaptive termination)")
-    ap.add_argument("--workload", choices=["spheres-1080p", "instanced-4k", "cache", "instanced-1080p"],
+    ap.add_argument("--workload", choices=["spheres-1080p", "instanced-4k", "cache", "instanced-1080p", "nrc-kernels"],
                     default="spheres-1080p",
                     help="instanced-4k: plain vs cache on the instanced scene at 3840x2160 (minutes); cache: only "
-                         "the radiance-cache experiment; instanced-1080p: only the instanced scene (none is the "
-                         "bench line)")
+                         "the radiance-cache experiment; instanced-1080p: only the instanced scene; nrc-kernels: "
+                         "the cache kernels alone, short enough for counter profiling (none is the bench line)")
     ap.add_argument("--spp-4k", type=int, default=1024)
     ap.add_argument("--ref-spp-4k", type=int, default=2048)
     ap.add_argument("--tail-min-bounce", type=int, default=None,
@@ -624,6 +679,9 @@ def main():
         print(json.dumps({"metric": "radiance cache vs plain, icosphere field 1080p",
                           "result": cache_experiment(pt, torch, sc, args.cache_frames, args.ref_spp,
                                                      args.cache_seeds, **_cache_kw(args))}), flush=True)
+        return
+    if args.workload == "nrc-kernels":
+        print(json.dumps({"metric": "radiance-cache kernels", "result": nrc_kernels(pt, torch, scenes)}), flush=True)
         return
     if args.workload == "instanced-1080p":
         print(json.dumps({"metric": "instanced scene 1080p",

@@ -111,6 +111,8 @@ typedef struct pt_stats {
   int64_t instances_entered; /* two-level scenes: instances whose mesh walk started, closest-hit and
                                 shadow walks of the traversal kernel (counting on; tail kernel apart) */
   int64_t tail_instances_entered; /* the same for the tail kernel's walks (counting on) */
+  double ms_cache_forward;   /* summed kernel time of pt_nrc_forward calls (profiling on) */
+  int64_t cache_forward_queries; /* queries answered by those calls (profiling on) */
 } pt_stats;
 
 /* Create a scene bound to HIP device `hip_device` and stream `hip_stream`

@@ -175,6 +175,9 @@ struct pt_scene {
   double ms_display = 0.0;
   int64_t launches_display = 0;
   hipEvent_t ev_display[2] = {nullptr, nullptr};
+  double ms_cache_forward = 0.0;
+  int64_t cache_forward_queries = 0;
+  hipEvent_t ev_forward[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -1563,6 +1566,7 @@ void pt_scene_destroy(pt_scene* s) {
   for (int k = 0; k < 2; ++k) {
     if (s->ev_bulk[k]) (void)hipEventDestroy(s->ev_bulk[k]);
     if (s->ev_display[k]) (void)hipEventDestroy(s->ev_display[k]);
+    if (s->ev_forward[k]) (void)hipEventDestroy(s->ev_forward[k]);
     if (s->ev_done[k]) (void)hipEventDestroy(s->ev_done[k]);
     for (int j = 0; j < 2; ++j)
       if (s->ev_train_t[k][j]) (void)hipEventDestroy(s->ev_train_t[k][j]);
@@ -1938,8 +1942,21 @@ pt_status pt_nrc_forward(pt_scene* s, const float* inputs, int64_t n, float* out
   if (n == 0) return PT_OK;
   if (!inputs || !outputs) return fail(PT_ERR_INVALID_ARG, "inputs and outputs must be non-NULL");
   if ((r = set_device(s))) return r;
+  if (s->timing) {
+    for (hipEvent_t& e : s->ev_forward)
+      if (!e) PT_HIP(hipEventCreate(&e));
+    PT_HIP(hipEventRecord(s->ev_forward[0], s->stream));
+  }
   PT_HIP(nrc_launch_forward(inputs, n, s->nrc_inf.as<uint4>(), outputs, s->stream));
-  return sync(s);
+  if (s->timing) PT_HIP(hipEventRecord(s->ev_forward[1], s->stream));
+  if ((r = sync(s))) return r;
+  if (s->timing) {
+    float ms = 0.0f;
+    PT_HIP(hipEventElapsedTime(&ms, s->ev_forward[0], s->ev_forward[1]));
+    s->ms_cache_forward += ms;
+    s->cache_forward_queries += n;
+  }
+  return PT_OK;
 }
 
 pt_status pt_nrc_gradient(pt_scene* s, const float* inputs, const float* targets, int32_t n, float* grad,
@@ -2099,6 +2116,8 @@ pt_status pt_get_stats(pt_scene* s, pt_stats* o) {
   o->launches_tail = s->launches_tail;
   o->ms_display = s->ms_display;
   o->launches_display = s->launches_display;
+  o->ms_cache_forward = s->ms_cache_forward;
+  o->cache_forward_queries = s->cache_forward_queries;
   return PT_OK;
 }
 
@@ -2117,6 +2136,8 @@ pt_status pt_reset_stats(pt_scene* s) {
   s->launches_tail = 0;
   s->ms_display = 0.0;
   s->launches_display = 0;
+  s->ms_cache_forward = 0.0;
+  s->cache_forward_queries = 0;
   return sync(s);
 }
 

@@ -17,7 +17,8 @@
 // rows 4g..4g+3 of query q.  For hidden layers the K entries of chunk c are
 // ordered [tile 2c rows 4g..4g+3, tile 2c+1 rows 4g..4g+3], so a layer's
 // result registers are the next layer's B operand without any data movement;
-// the weight fragments are stored in that order.
+// the input layer's K entries follow nrc_k_in.  The weight fragments are
+// stored in these orders.
 #pragma once
 
 #include <math.h>
@@ -48,8 +49,22 @@ __host__ __device__ inline float bf16_float(uint16_t b) {
   return f;
 }
 
-// Input feature index of K entry (chunk c, lane group g, element j).
-__host__ __device__ inline int nrc_k_natural(int c, int g, int j) { return 32 * c + 8 * g + j; }
+// Input feature index of layer-0 K entry (chunk c, lane group g, element j).
+// The order spreads the encoding evenly over the four lanes of a query, so
+// that every lane runs the same instructions: chunk 0 holds the sin/cos
+// pairs 4g..4g+3 (pair p = 6a + k: axis a, frequency 2^k); chunk 1 holds
+// feature 32 + g (one value of the last two pairs), the four one-blob bins
+// of direction coordinate g, bin g of the roughness, and two of the albedo
+// and constant features.
+__host__ __device__ inline int nrc_k_in(int c, int g, int j) {
+  if (c == 0) return 8 * g + j;
+  if (j == 0) return 32 + g;
+  if (j <= 4) return 36 + 4 * g + (j - 1);
+  if (j == 5) return 52 + g;
+  return 56 + 2 * g + (j - 6);
+}
+
+// Input index of hidden-layer K entry (chunk c, lane group g, element j).
 __host__ __device__ inline int nrc_k_chained(int c, int g, int j) {
   return j < 4 ? 32 * c + 4 * g + j : 32 * c + 16 + 4 * g + (j - 4);
 }

@@ -3,7 +3,7 @@
 // k_nrc_pack      FP32 master weights -> bf16 operand fragments (forward and
 //                 transposed for the backward pass), in the chained K order;
 //                 FP32 inference weights -> forward fragments of the queries.
-// k_nrc_infer     encode + 6 layers per 16 queries per wave, weights in LDS.
+// k_nrc_infer     encode + 6 layers per 32 queries per wave, weights in LDS.
 // k_nrc_fwd_bwd   forward with kept activations, relative-L2 loss gradient,
 //                 backward through the transposed fragments; writes layer
 //                 inputs and layer output gradients (bf16, [feature][sample]).
@@ -39,13 +39,29 @@ __device__ inline uint32_t pack2(float a, float b) {
   return __builtin_bit_cast(uint32_t, v);
 }
 
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+
+// ReLU of a packed bfloat16 pair: a bfloat16 with its sign bit set is a
+// negative int16, so an int16 maximum with 0 zeroes exactly the negative
+// values and -0 (v_pk_max_i16).  Equal to rounding max(x, 0) for every
+// non-NaN x, since rounding to nearest is monotonic and keeps the sign.
+__device__ inline uint32_t relu2(uint32_t u) {
+  // An empty asm statement keeps u one 32-bit register, so that the pair is
+  // converted by one v_cvt_pk_bf16_f32 (seen through, the conversion was
+  // split into two and a permute).
+  asm("" : "+v"(u));
+  i16x2 v = __builtin_bit_cast(i16x2, u);
+  v = __builtin_elementwise_max(v, i16x2{0, 0});
+  return __builtin_bit_cast(uint32_t, v);
+}
+
 // B operand of a chained chunk from two result tiles, with ReLU.
 __device__ inline bf16x8 chain_relu(f32x4 lo, f32x4 hi) {
   uint4 u;
-  u.x = pack2(fmaxf(lo[0], 0.0f), fmaxf(lo[1], 0.0f));
-  u.y = pack2(fmaxf(lo[2], 0.0f), fmaxf(lo[3], 0.0f));
-  u.z = pack2(fmaxf(hi[0], 0.0f), fmaxf(hi[1], 0.0f));
-  u.w = pack2(fmaxf(hi[2], 0.0f), fmaxf(hi[3], 0.0f));
+  u.x = relu2(pack2(lo[0], lo[1]));
+  u.y = relu2(pack2(lo[2], lo[3]));
+  u.z = relu2(pack2(hi[0], hi[1]));
+  u.w = relu2(pack2(hi[2], hi[3]));
   return as_bf16x8(u);
 }
 
@@ -75,7 +91,7 @@ __global__ void k_nrc_pack(const float* __restrict__ w, const float* __restrict_
     if (frag < 40) {
       int l = frag / 8, t = (frag % 8) / 2, c = frag % 2;
       for (int j = 0; j < 8; ++j) {
-        int in = l == 0 ? nrc_k_natural(c, g, j) : nrc_k_chained(c, g, j);
+        int in = l == 0 ? nrc_k_in(c, g, j) : nrc_k_chained(c, g, j);
         v[j] = w[nrc_widx(l, 16 * t + r, in)];
       }
     } else {
@@ -105,11 +121,11 @@ __global__ void k_nrc_pack(const float* __restrict__ w, const float* __restrict_
   else bwd[(frag - kNrcFwdFrags) * 64 + lane] = u;
 }
 
-// Encoded input as the layer-0 B operand: lane (g, q) holds features 32c + 8g + j
-// of query q.  The work is laid out so every lane runs the same instructions
-// (no per-lane branch on the feature index): chunk 0 is four sin/cos pairs
-// per lane, chunk 1 is two sin/cos pairs, two one-blob groups, the albedos
-// and the constants, selected by the lane group g.
+// Encoded input as the layer-0 B operand: lane (g, q) holds the features
+// nrc_k_in(c, g, j) of query q.  Every lane runs the same instructions (no
+// per-lane branch on the feature index): five sin/cos pairs, the four
+// one-blob bins of one direction coordinate, one roughness bin and two
+// copied values, with lane-dependent arguments chosen by selects.
 // Lane-dependent choice among registers, written as a sum of selects against
 // zero so the compiler keeps the inputs in registers (a select between two
 // array loads would become an indexed load from a stack copy).
@@ -117,36 +133,50 @@ __device__ inline float pick3(int a, float v0, float v1, float v2) {
   return ((a == 0 ? v0 : 0.0f) + (a == 1 ? v1 : 0.0f)) + (a == 2 ? v2 : 0.0f);
 }
 
-__device__ inline void encode_operand(const float* x, int g, bool valid, bf16x8 B[2]) {
+__device__ inline float pick4(int a, float v0, float v1, float v2, float v3) {
+  return ((a == 0 ? v0 : 0.0f) + (a == 1 ? v1 : 0.0f)) + ((a == 2 ? v2 : 0.0f) + (a == 3 ? v3 : 0.0f));
+}
+
+__device__ inline void encode_operand(const float* x, int g, bf16x8 B[2]) {
+  // sincospif shares one argument reduction between sin and cos; its results
+  // are bitwise those of sinpif and cospif (checked on 2^24 arguments of the
+  // form u 2^k, k = 0..5, and quarter integers).
   float f0[8];
+  // pairs 4g, 4g + 1 share an axis, and so do pairs 4g + 2, 4g + 3 (p = 6a + k)
+  const float xa01 = pick3(g < 2 ? 0 : g - 1, x[0], x[1], x[2]);
+  const float xa23 = pick3(g == 0 ? 0 : (g < 3 ? 1 : 2), x[0], x[1], x[2]);
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {  // features 8g + 2m (sin) and 8g + 2m + 1 (cos)
-    const int f = 8 * g + 2 * m, a = f / 12, k = (f % 12) >> 1;
-    const float xa = pick3(a, x[0], x[1], x[2]);
-    const float w = xa * (float)(1 << k);
-    f0[2 * m] = sinpif(w);
-    f0[2 * m + 1] = cospif(w);
+  for (int m = 0; m < 4; ++m) {  // pair p = 4g + m: sin and cos of 2^k pi x_a
+    const int k = (4 * g + m) % 6;
+    const float w = (m < 2 ? xa01 : xa23) * (float)(1 << k);
+    sincospif(w, &f0[2 * m], &f0[2 * m + 1]);
   }
-  // chunk 1: g = 0: sin/cos(16 pi x2), sin/cos(32 pi x2), blob(x3); g = 1: blob(x4), blob(x5);
-  //          g = 2: blob(x6), blob(1 - exp(-x7)); g = 3: x8..x11, 1, 0, 0, 0
-  const float r7 = 1.0f - expf(-x[7]);
-  const float s1 = pick3(g == 1 ? 0 : 1, x[4], x[6], 0.0f);
-  const float s2 = pick3(g == 0 ? 0 : (g == 1 ? 1 : 2), x[3], x[5], r7);
-  float lo[4], hi[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    lo[i] = nrc_one_blob_periodic(s1, i);  // an azimuth (x4 or x6) wherever lo is used
-    hi[i] = nrc_one_blob(s2, i);
-  }
-  const float w4 = x[2] * 16.0f, w5 = x[2] * 32.0f;
-  const float t0 = sinpif(w4), t1 = cospif(w4), t2 = sinpif(w5), t3 = cospif(w5);
   float f1[8];
-  f1[0] = g == 0 ? t0 : (g == 3 ? x[8] : lo[0]);
-  f1[1] = g == 0 ? t1 : (g == 3 ? x[9] : lo[1]);
-  f1[2] = g == 0 ? t2 : (g == 3 ? x[10] : lo[2]);
-  f1[3] = g == 0 ? t3 : (g == 3 ? x[11] : lo[3]);
+  {  // feature 32 + g: sin (g even) or cos (g odd) of 16 pi x2 (g < 2) or 32 pi x2
+    const float w = x[2] * (float)(16 << (g >> 1));
+    float sv, cv;
+    sincospif(w, &sv, &cv);
+    f1[0] = (g & 1) ? cv : sv;
+  }
+  {  // features 36 + 4g + i: one-blob bins of direction coordinate g (x3..x6; x4 and x6 are periodic)
+    const float sd = pick4(g, x[3], x[4], x[5], x[6]);
+    const bool periodic = (g & 1) != 0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) f1[4 + i] = g == 3 ? (i == 0 ? 1.0f : 0.0f) : hi[i];
+    for (int i = 0; i < 4; ++i) {
+      float d = sd - ((float)i + 0.5f) * 0.25f;
+      if (periodic) d -= floorf(d + 0.5f);
+      const float z = d * 4.0f;
+      f1[1 + i] = expf(-0.5f * z * z);
+    }
+  }
+  {  // feature 52 + g: bin g of 1 - exp(-roughness)
+    const float rr = 1.0f - expf(-x[7]);
+    const float z = (rr - ((float)g + 0.5f) * 0.25f) * 4.0f;
+    f1[5] = expf(-0.5f * z * z);
+  }
+  // features 56 + 2g, 57 + 2g: albedos x8..x11, then the constants 1, 0, 0, 0
+  f1[6] = pick4(g, x[8], x[10], 1.0f, 0.0f);
+  f1[7] = pick4(g, x[9], x[11], 0.0f, 0.0f);
   uint4 u0, u1;
   u0.x = pack2(f0[0], f0[1]);
   u0.y = pack2(f0[2], f0[3]);
@@ -156,7 +186,6 @@ __device__ inline void encode_operand(const float* x, int g, bool valid, bf16x8 
   u1.y = pack2(f1[2], f1[3]);
   u1.z = pack2(f1[4], f1[5]);
   u1.w = pack2(f1[6], f1[7]);
-  if (!valid) u0 = u1 = make_uint4(0u, 0u, 0u, 0u);
   B[0] = as_bf16x8(u0);
   B[1] = as_bf16x8(u1);
 }
@@ -199,73 +228,138 @@ __device__ inline float nrc_factor(const float* x, int c, bool on) { return on ?
 //         inputs nrc_q[slot][0..11], throughput nrc_q[slot][12..14]; L[slot] += beta * factor * max(y, 0).
 // MODE 2: the terminal vertices of n training paths (self-training): path k's record at vertex
 //         P.train_end, if it is a terminal record, gives out4[k] = beta * factor * max(y, 0); else 0.
+// A wave takes 32 queries per iteration, two groups of 16, so that every
+// weight fragment read from LDS feeds two matrix-core instructions.
 constexpr int kInferWaves = 8;  // waves per workgroup sharing one LDS copy of the weight fragments
+constexpr int kInferSub = 2;    // groups of 16 queries per wave and iteration
+
+// The 12 inputs of query row qc (always a valid row: callers clamp), as
+// float4 loads where the rows are 16-byte aligned by construction.
+template <int MODE>
+__device__ inline const float* infer_row(const float* xin, const PathsDev& P, int64_t qc, uint32_t& slot) {
+  if (MODE == 0) return xin + qc * 12;
+  if (MODE == 1) {
+    slot = P.q_nrc[qc];
+    return P.nrc_q + (size_t)slot * kNrcQueryFloats;
+  }
+  return P.rec + ((size_t)qc * P.rec_depth + P.train_end) * kNrcRecFloats;
+}
+
+template <int MODE>
+__device__ inline void infer_load(const float* r, float* x) {
+  if (MODE == 0) {  // caller's rows of 48 bytes: only 4-byte alignment is known
+#pragma unroll
+    for (int k = 0; k < 12; ++k) x[k] = r[k];
+  } else {
+    const float4* r4 = reinterpret_cast<const float4*>(r);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float4 v = r4[k];
+      x[4 * k] = v.x;
+      x[4 * k + 1] = v.y;
+      x[4 * k + 2] = v.z;
+      x[4 * k + 3] = v.w;
+    }
+  }
+}
 
 template <int MODE>
 __global__ __launch_bounds__(64 * kInferWaves) void k_nrc_infer(const float* __restrict__ xin, int64_t n_arg,
                                                                 PathsDev P, const uint4* __restrict__ fwd,
                                                                 float* __restrict__ out) {
   __shared__ uint4 sw[kNrcFwdFrags * 64];
+  const int64_t n = MODE == 1 ? (int64_t)P.counts[kCountQuery] : n_arg;
+  if (MODE == 1 && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&P.stats[kStatQueries], (unsigned long long)n);
+  constexpr int kPerIter = 16 * kInferSub;
+  if ((int64_t)blockIdx.x * kInferWaves * kPerIter >= n) return;  // no work: skip staging the weights
   for (int i = threadIdx.x; i < kNrcFwdFrags * 64; i += blockDim.x) sw[i] = fwd[i];
   __syncthreads();
-  const int64_t n = MODE == 1 ? (int64_t)P.counts[kCountQuery] : n_arg;
   float4* out4 = reinterpret_cast<float4*>(out);
-  if (MODE == 1 && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&P.stats[kStatQueries], (unsigned long long)n);
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, g = lane / 16, q = lane % 16;
   unsigned long long nonfinite = 0;
-  for (int64_t grp = (int64_t)blockIdx.x * kInferWaves + wave; grp * 16 < n; grp += (int64_t)gridDim.x * kInferWaves) {
-    // Read the weight fragments from LDS in every group: held in registers
-    // they would take 168 VGPRs and leave one wave per SIMD.
+  for (int64_t it = (int64_t)blockIdx.x * kInferWaves + wave; it * kPerIter < n;
+       it += (int64_t)gridDim.x * kInferWaves) {
+    // Read the weight fragments from LDS in every iteration: held in
+    // registers they would take 168 VGPRs and leave one wave per SIMD.
     asm volatile("" ::: "memory");
-    int64_t qi = grp * 16 + q;
-    bool valid = qi < n;
-    const bool row = valid;  // MODE 2: every path below n gets an output (0 if not terminal)
-    const float* r = nullptr;
-    uint32_t slot = 0;
-    if (valid) {
-      if (MODE == 0) {
-        r = xin + qi * 12;
-      } else if (MODE == 1) {
-        slot = P.q_nrc[qi];
-        r = P.nrc_q + (size_t)slot * kNrcQueryFloats;
-      } else {
-        r = P.rec + ((size_t)qi * P.rec_depth + P.train_end) * kNrcRecFloats;
-        valid = r[18] == 2.0f;
-      }
-    }
-    float x[12];
+    int64_t qi[kInferSub];
+    bool valid[kInferSub];
+    const float* r[kInferSub];
+    uint32_t slot[kInferSub];
+    float x[kInferSub][12];
+    bf16x8 B[kInferSub][2];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) x[k] = valid ? r[k] : 0.0f;
-    bf16x8 B[2];
-    encode_operand(x, g, valid, B);
-    f32x4 y = mlp_forward(sw, lane, B, nullptr);
-    if (MODE == 2 && row && g == 0) {
-      float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (valid) {
-        const bool fo = P.nrc_factor != 0;
-        t.x = r[15] * nrc_factor(x, 0, fo) * fmaxf(y[0], 0.0f);
-        t.y = r[16] * nrc_factor(x, 1, fo) * fmaxf(y[1], 0.0f);
-        t.z = r[17] * nrc_factor(x, 2, fo) * fmaxf(y[2], 0.0f);
-        if (!(isfinite(t.x) && isfinite(t.y) && isfinite(t.z))) t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      }
-      out4[qi] = t;
+    for (int h = 0; h < kInferSub; ++h) {
+      qi[h] = it * kPerIter + 16 * h + q;
+      valid[h] = qi[h] < n;
+      slot[h] = 0;
+      // rows past n read row n - 1 (their results are dropped), so every load is in bounds
+      r[h] = infer_row<MODE>(xin, P, valid[h] ? qi[h] : n - 1, slot[h]);
+      infer_load<MODE>(r[h], x[h]);
+      encode_operand(x[h], g, B[h]);
     }
-    if (MODE != 2 && valid && g == 0) {
-      if (MODE == 0) {
-        out[qi * 3 + 0] = y[0];
-        out[qi * 3 + 1] = y[1];
-        out[qi * 3 + 2] = y[2];
-      } else {
-        const bool fo = P.nrc_factor != 0;
-        float cx = r[12] * nrc_factor(x, 0, fo) * fmaxf(y[0], 0.0f);
-        float cy = r[13] * nrc_factor(x, 1, fo) * fmaxf(y[1], 0.0f);
-        float cz = r[14] * nrc_factor(x, 2, fo) * fmaxf(y[2], 0.0f);
-        if (isfinite(cx) && isfinite(cy) && isfinite(cz)) {
-          float4 l = P.L[slot];
-          P.L[slot] = make_float4(l.x + cx, l.y + cy, l.z + cz, l.w);
-        } else {
-          nonfinite++;
+    f32x4 acc[kInferSub][4];
+#pragma unroll
+    for (int l = 0; l < 5; ++l) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int h = 0; h < kInferSub; ++h) acc[h][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const bf16x8 a = as_bf16x8(sw[((l * 4 + t) * 2 + c) * 64 + lane]);
+#pragma unroll
+          for (int h = 0; h < kInferSub; ++h) acc[h][t] = mfma(a, B[h][c], acc[h][t]);
         }
+      }
+#pragma unroll
+      for (int h = 0; h < kInferSub; ++h) {
+        B[h][0] = chain_relu(acc[h][0], acc[h][1]);
+        B[h][1] = chain_relu(acc[h][2], acc[h][3]);
+      }
+    }
+    f32x4 y[kInferSub];
+#pragma unroll
+    for (int h = 0; h < kInferSub; ++h) y[h] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const bf16x8 a = as_bf16x8(sw[(40 + c) * 64 + lane]);
+#pragma unroll
+      for (int h = 0; h < kInferSub; ++h) y[h] = mfma(a, B[h][c], y[h]);
+    }
+    if (g != 0) continue;  // lanes g == 0 hold output rows 0..3 of query q
+#pragma unroll
+    for (int h = 0; h < kInferSub; ++h) {
+      if (!valid[h]) continue;
+      if (MODE == 0) {
+        out[qi[h] * 3 + 0] = y[h][0];
+        out[qi[h] * 3 + 1] = y[h][1];
+        out[qi[h] * 3 + 2] = y[h][2];
+        continue;
+      }
+      const bool fo = P.nrc_factor != 0;
+      if (MODE == 2) {  // every path below n gets an output: 0 unless its record is terminal
+        float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const float4 tail = reinterpret_cast<const float4*>(r[h])[3];  // beta at 15..17, flag at 18
+        const float4 more = reinterpret_cast<const float4*>(r[h])[4];
+        if (more.z == 2.0f) {
+          t.x = tail.w * nrc_factor(x[h], 0, fo) * fmaxf(y[h][0], 0.0f);
+          t.y = more.x * nrc_factor(x[h], 1, fo) * fmaxf(y[h][1], 0.0f);
+          t.z = more.y * nrc_factor(x[h], 2, fo) * fmaxf(y[h][2], 0.0f);
+          if (!(isfinite(t.x) && isfinite(t.y) && isfinite(t.z))) t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+        out4[qi[h]] = t;
+        continue;
+      }
+      const float4 beta = reinterpret_cast<const float4*>(r[h])[3];
+      const float cx = beta.x * nrc_factor(x[h], 0, fo) * fmaxf(y[h][0], 0.0f);
+      const float cy = beta.y * nrc_factor(x[h], 1, fo) * fmaxf(y[h][1], 0.0f);
+      const float cz = beta.z * nrc_factor(x[h], 2, fo) * fmaxf(y[h][2], 0.0f);
+      if (isfinite(cx) && isfinite(cy) && isfinite(cz)) {
+        const float4 l = P.L[slot[h]];
+        P.L[slot[h]] = make_float4(l.x + cx, l.y + cy, l.z + cz, l.w);
+      } else {
+        nonfinite++;
       }
     }
   }
@@ -298,7 +392,7 @@ __global__ __launch_bounds__(256) void k_nrc_fwd_bwd(const float* __restrict__ X
     for (int k = 0; k < 12; ++k) x[k] = valid ? X[(size_t)qi * 12 + k] : 0.0f;
     bf16x8 keep[12];
     bf16x8 B[2];
-    encode_operand(x, g, valid, B);
+    encode_operand(x, g, B);
     f32x4 y = mlp_forward(sw, lane, B, keep);
     // layer inputs a_0..a_5
 #pragma unroll
@@ -307,7 +401,7 @@ __global__ __launch_bounds__(256) void k_nrc_fwd_bwd(const float* __restrict__ X
       for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-          int f = l == 0 ? nrc_k_natural(c, g, j) : nrc_k_chained(c, g, j);
+          int f = l == 0 ? nrc_k_in(c, g, j) : nrc_k_chained(c, g, j);
           float v = valid ? bf16x8_get(keep[2 * l + c], j) : 0.0f;
           a_store[l * L + (size_t)f * npad + qi] = bf16_bits(v);
         }
@@ -602,9 +696,9 @@ hipError_t nrc_launch_pack(const float* w, const float* wi, uint4* fwd, uint4* b
   return hipGetLastError();
 }
 
-// The inference kernel keeps all weight fragments in registers (one wave per
-// SIMD): launch one resident set of workgroups and let each wave stride over
-// the query groups, so the weights are staged once per workgroup.
+// The inference kernel stages the weight fragments in LDS once per
+// workgroup: launch at most one resident set of workgroups and let each wave
+// stride over the queries.
 static int nrc_infer_grid() {
   static int resident = 0;
   if (!resident) {
@@ -620,11 +714,16 @@ static int nrc_infer_grid() {
   return resident;
 }
 
+// Workgroups for n queries: enough for one iteration per wave, at most one resident set.
+static int nrc_infer_groups(int64_t n) {
+  const int64_t per_group = (int64_t)16 * kInferSub * kInferWaves;
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + per_group - 1) / per_group, nrc_infer_grid()));
+}
+
 hipError_t nrc_launch_forward(const float* x, int64_t n, const uint4* fwd, float* y, hipStream_t st) {
   PathsDev P;
   __builtin_memset(&P, 0, sizeof(P));
-  int64_t groups = (n + 15) / 16;
-  int grid = (int)std::max<int64_t>(1, std::min<int64_t>((groups + kInferWaves - 1) / kInferWaves, nrc_infer_grid()));
+  const int grid = nrc_infer_groups(n);
   hipLaunchKernelGGL((k_nrc_infer<0>), dim3(grid), dim3(64 * kInferWaves), 0, st, x, n, P, fwd, y);
   return hipGetLastError();
 }
@@ -655,8 +754,7 @@ hipError_t nrc_launch_adam(float* w, float* m, float* v, float* e, float* wi, co
 }
 
 hipError_t nrc_launch_terminal(const PathsDev& P, int n_paths, const uint4* fwd, float4* tail, hipStream_t st) {
-  int64_t groups = (n_paths + 15) / 16;
-  int grid = (int)std::max<int64_t>(1, std::min<int64_t>((groups + kInferWaves - 1) / kInferWaves, nrc_infer_grid()));
+  const int grid = nrc_infer_groups(n_paths);
   hipLaunchKernelGGL((k_nrc_infer<2>), dim3(grid), dim3(64 * kInferWaves), 0, st, nullptr, (int64_t)n_paths, P, fwd,
                      reinterpret_cast<float*>(tail));
   return hipGetLastError();

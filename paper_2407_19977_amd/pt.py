@@ -52,7 +52,8 @@ class pt_stats(C.Structure):
                 ("ms_tail", C.c_double), ("launches_tail", C.c_int64),
                 ("tail_shadow_rays", C.c_int64), ("tail_shadow_node_visits", C.c_int64),
                 ("tail_shadow_tri_tests", C.c_int64), ("ms_display", C.c_double), ("launches_display", C.c_int64),
-                ("instances_entered", C.c_int64), ("tail_instances_entered", C.c_int64)]
+                ("instances_entered", C.c_int64), ("tail_instances_entered", C.c_int64),
+                ("ms_cache_forward", C.c_double), ("cache_forward_queries", C.c_int64)]
 
 
 class pt_bvh_info(C.Structure):

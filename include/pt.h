@@ -63,7 +63,8 @@ typedef struct pt_instance {
   int32_t material_override;  /* -1: use the mesh's per-triangle ids */
 } pt_instance;
 
-/* OpenPBR parameters (Sec. 4), linear RGB; 27 floats in this order. */
+/* OpenPBR parameters (Sec. 4), linear RGB; 30 floats in this order.
+ * thin_film_thickness is in micrometres. */
 typedef struct pt_openpbr_material {
   float base_weight, base_color[3], base_metalness, base_diffuse_roughness;
   float specular_weight, specular_color[3], specular_roughness, specular_roughness_anisotropy,
@@ -71,6 +72,7 @@ typedef struct pt_openpbr_material {
   float transmission_weight, transmission_color[3];
   float coat_weight, coat_color[3], coat_roughness, coat_ior;
   float emission_luminance, emission_color[3];
+  float thin_film_weight, thin_film_thickness, thin_film_ior;
 } pt_openpbr_material;
 
 /* Pinhole camera (Sec. 5.1.2): vertical field of view in degrees, aspect width/height. */
@@ -149,9 +151,14 @@ pt_status pt_build_bvh_gpu(pt_scene* scene, const pt_mesh* meshes, int32_t n_mes
 /* Upload the OpenPBR materials (Sec. 4).  base_diffuse_roughness > 0 gives
  * the energy-preserving Oren-Nayar diffuse (EON); specular_weight modulates
  * the dielectric IOR (F0(eta') = specular_weight F0(eta)) and scales the
- * metal Fresnel.  Errors: INVALID_ARG (n <= 0, negative or non-finite
- * parameters, IOR <= 0, weights or base_diffuse_roughness outside [0,1]),
- * UNSUPPORTED (coat together with transmission). */
+ * metal Fresnel.  thin_film_weight > 0 puts a thin film (thickness in
+ * micrometres, thin_film_ior >= 1) on the dielectric interface: its
+ * reflectance is the interference (Airy) sum of the film, evaluated at 650,
+ * 550 and 450 nm for red, green and blue, mixed with the plain Fresnel by
+ * the weight; metals ignore the film.  Errors: INVALID_ARG (n <= 0,
+ * negative or non-finite parameters, IOR <= 0, thin_film_ior < 1, weights
+ * or base_diffuse_roughness outside [0,1]), UNSUPPORTED (coat together with
+ * transmission). */
 pt_status pt_upload_materials(pt_scene* scene, const pt_openpbr_material* materials, int32_t n);
 
 /* Set the environment: an equirectangular RGB32F image [h][w][3] (y up,

@@ -53,6 +53,58 @@ double ofresnel_diel(double c, double eta) {
   return 0.5 * a * a * (1.0 + b * b);
 }
 
+/*
+ * Thin film on the dielectric interface (OpenPBR thin_film_*; the paper's
+ * Sec. 4 names OpenPBR): reflectance of the stack incident medium (index 1)
+ * | film (relative index n2) | base (relative index n3) at incident cosine
+ * c1, for one wavelength, by Airy summation of the multiply reflected waves:
+ * per polarisation R = (r12^2 + r23^2 + 2 r12 r23 cos d) /
+ * (1 + r12^2 r23^2 + 2 r12 r23 cos d), with the Fresnel amplitudes
+ * r_ij = (a_i - a_j) / (a_i + a_j), a = n cos (s) or cos / n (p), and the
+ * phase d = 2 pi (2 film_ior d_nm cos_film / lambda); unpolarised: the mean.
+ * Total internal reflection at either interface gives 1 (no propagating
+ * wave leaves: the film's index is at least 1, so an evanescent film also
+ * means an evanescent exit).
+ */
+double ofilm_airy(double c1, double n2, double n3, double film_ior, double d_nm, double lambda_nm) {
+  c1 = fabs(c1);
+  double s2 = 1.0 - c1 * c1;
+  double c2sq = 1.0 - s2 / (n2 * n2), c3sq = 1.0 - s2 / (n3 * n3);
+  if (c2sq < 0.0 || c3sq < 0.0) return 1.0;
+  double c2 = sqrt(c2sq), c3 = sqrt(c3sq);
+  double cd = cos(2.0 * O_PI * (2.0 * film_ior * d_nm * c2 / lambda_nm));
+  double a[2][3] = {{c1, n2 * c2, n3 * c3}, {c1, c2 / n2, c3 / n3}};
+  double R = 0.0;
+  for (int pol = 0; pol < 2; ++pol) {
+    double r12 = (a[pol][0] - a[pol][1]) / (a[pol][0] + a[pol][1]);
+    double r23 = (a[pol][1] - a[pol][2]) / (a[pol][1] + a[pol][2]);
+    double x = 2.0 * r12 * r23 * cd;
+    R += 0.5 * (r12 * r12 + r23 * r23 + x) / (1.0 + r12 * r12 * r23 * r23 + x);
+  }
+  return R;
+}
+
+/* one wavelength per channel (nm) */
+static const double FILM_LAMBDA[3] = {650.0, 550.0, 450.0};
+
+/* Reflectance of the specular dielectric interface at incident cosine c:
+ * per channel F[k], and the scalar Fs that chooses lobes and reflection vs
+ * refraction (the plain Fresnel without a film, the luminance with one). */
+void oiface_fresnel(const obsdf* b, double c, double F[3], double* Fs) {
+  double F0 = ofresnel_diel(c, b->eta);
+  double w = b->m.film_weight;
+  if (!(w > 0.0)) {
+    F[0] = F[1] = F[2] = F0;
+    *Fs = F0;
+    return;
+  }
+  for (int k = 0; k < 3; ++k) {
+    double Rf = ofilm_airy(c, b->film_n2, b->eta, b->m.film_ior, 1000.0 * b->m.film_thickness_um, FILM_LAMBDA[k]);
+    F[k] = (1.0 - w) * F0 + w * Rf;
+  }
+  *Fs = lum3(F);
+}
+
 double omod_ior(const omat* m) {
   /* F0(eta') = xi F0(eta): eta' = (1 + sqrt(xi F0)) / (1 - sqrt(xi F0)), inverted below 1 */
   double eta = m->spec_ior, xi = m->spec_weight;
@@ -152,9 +204,12 @@ void obsdf_setup(const omat* m, int entering, double mu_o, obsdf* b) {
   b->ac = clampa(m->coat_rough * m->coat_rough);
   b->coat_delta = m->coat_rough < 1e-3;
   double cw = m->coat_weight, mt = m->metalness, tw = m->trans_weight, sw = m->spec_weight;
+  /* the film's index relative to the medium wo is in: air, or the base when leaving a transmissive one */
+  b->film_n2 = (m->trans_weight > 0.0 && !entering) ? m->film_ior / ior : m->film_ior;
   double Fc = ofresnel_diel(mu_o, m->coat_ior);
   double Tc = 1.0 - cw * Fc;
-  double Fd = ofresnel_diel(mu_o, b->eta);
+  double Fdv[3], Fd;
+  oiface_fresnel(b, mu_o, Fdv, &Fd);
   double F82[3];
   of82(m, mu_o, F82);
   double bwbc[3] = {m->base_weight * m->base_color[0], m->base_weight * m->base_color[1],
@@ -213,7 +268,7 @@ void obsdf_eval(const obsdf* b, v3 wo, v3 wi, double f[3], double* pdf) {
       fc = cw * ofresnel_diel(oh, m->coat_ior) * Dc * G2(b->ac, b->ac, wo, wi) / (4.0 * mu_o * mu_i);
       pc = oggx_vndf_pdf(b->ac, b->ac, wo, h) / (4.0 * oh);
     }
-    double fm[3] = {0, 0, 0}, fi = 0.0, pm = 0.0, pi = 0.0;
+    double fm[3] = {0, 0, 0}, fi[3] = {0, 0, 0}, pm = 0.0, pi = 0.0;
     if (!b->spec_delta) {
       double D = oggx_D(b->at, b->ab, h);
       double g = G2(b->at, b->ab, wo, wi);
@@ -221,18 +276,21 @@ void obsdf_eval(const obsdf* b, v3 wo, v3 wi, double f[3], double* pdf) {
       double F82[3];
       of82(m, oh, F82);
       for (int c = 0; c < 3; ++c) fm[c] = sw * F82[c] * D * g / (4.0 * mu_o * mu_i);
-      double Fi = ofresnel_diel(oh, b->eta);
-      fi = Fi * D * g / (4.0 * mu_o * mu_i);
+      double Fiv[3], Fi;
+      oiface_fresnel(b, oh, Fiv, &Fi);
+      for (int c = 0; c < 3; ++c) fi[c] = Fiv[c] * D * g / (4.0 * mu_o * mu_i);
       pm = pv;
       double denom = Fi + tw * (1.0 - Fi);
       pi = denom > 0.0 ? (Fi / denom) * pv : 0.0;
     }
-    double Fdi = ofresnel_diel(mu_i, b->eta), Fdo = ofresnel_diel(mu_o, b->eta);
-    double kd = (1.0 - tw) * (1.0 - Fdi) * (1.0 - Fdo);
+    double Fdi[3], Fdo[3], Fsi, Fso;
+    oiface_fresnel(b, mu_i, Fdi, &Fsi);
+    oiface_fresnel(b, mu_o, Fdo, &Fso);
     double s = vdot(wi, wo) - mu_i * mu_o;
     for (int c = 0; c < 3; ++c) {
+      double kd = (1.0 - tw) * (1.0 - Fdi[c]) * (1.0 - Fdo[c]);
       double fd = kd * oeon(m->base_weight * m->base_color[c], m->diffuse_roughness, mu_i, mu_o, s);
-      f[c] = fc + L[c] * (mt * fm[c] + (1.0 - mt) * (fi + fd));
+      f[c] = fc + L[c] * (mt * fm[c] + (1.0 - mt) * (fi[c] + fd));
     }
     *pdf = b->P[LOBE_C] * pc + b->P[LOBE_M] * pm + b->P[LOBE_I] * pi + b->P[LOBE_D] * (mu_i / O_PI);
   } else {
@@ -241,13 +299,14 @@ void obsdf_eval(const obsdf* b, v3 wo, v3 wi, double f[3], double* pdf) {
     v3 h = refr_half(wo, wi, eta);
     double oh = vdot(wo, h), ih = vdot(wi, h);
     if (oh <= 0.0 || ih >= 0.0) return;
-    double F = ofresnel_diel(oh, eta);
+    double Fv[3], F;
+    oiface_fresnel(b, oh, Fv, &F);
     double s = ih + oh / eta;
     double denom = s * s;
     double D = oggx_D(b->at, b->ab, h);
     double g = G2(b->at, b->ab, wo, wi);
-    double bt = tw * (1.0 - F) * D * g * fabs(ih) * fabs(oh) / (denom * fabs(mu_i) * mu_o) / (eta * eta);
     for (int c = 0; c < 3; ++c) {
+      double bt = tw * (1.0 - Fv[c]) * D * g * fabs(ih) * fabs(oh) / (denom * fabs(mu_i) * mu_o) / (eta * eta);
       double tint = b->entering ? m->trans_color[c] : 1.0;
       f[c] = L[c] * (1.0 - mt) * bt * tint;
     }
@@ -327,7 +386,8 @@ int obsdf_sample(const obsdf* b, v3 wo, double u_lobe, double u1, double u2, dou
   } else if (lobe == LOBE_I) {
     double eta = b->eta;
     if (b->spec_delta) {
-      double F = ofresnel_diel(mu_o, eta);
+      double Fv[3], F;
+      oiface_fresnel(b, mu_o, Fv, &F);
       double dn = F + tw * (1.0 - F);
       double pr = dn > 0.0 ? F / dn : 0.0;
       double L[3];
@@ -336,7 +396,7 @@ int obsdf_sample(const obsdf* b, v3 wo, double u_lobe, double u1, double u2, dou
         *lobe_code = 2;
         *wi = V(-wo.x, -wo.y, wo.z);
         coat_layer(b, mu_o, mu_o, L);
-        for (int c = 0; c < 3; ++c) weight[c] = L[c] * (1.0 - mt) * F / (b->P[LOBE_I] * pr);
+        for (int c = 0; c < 3; ++c) weight[c] = L[c] * (1.0 - mt) * Fv[c] / (b->P[LOBE_I] * pr);
         return 1;
       }
       *lobe_code = 3;
@@ -347,12 +407,13 @@ int obsdf_sample(const obsdf* b, v3 wo, double u_lobe, double u1, double u2, dou
       coat_layer(b, t.z, mu_o, L);
       for (int c = 0; c < 3; ++c) {
         double tint = b->entering ? m->trans_color[c] : 1.0;
-        weight[c] = L[c] * (1.0 - mt) * tw * tint * (1.0 - F) / (eta * eta) / (b->P[LOBE_I] * (1.0 - pr));
+        weight[c] = L[c] * (1.0 - mt) * tw * tint * (1.0 - Fv[c]) / (eta * eta) / (b->P[LOBE_I] * (1.0 - pr));
       }
       return 1;
     }
     v3 h = oggx_vndf_sample(b->at, b->ab, wo, u1, u2);
-    double F = ofresnel_diel(vdot(wo, h), eta);
+    double Fv[3], F;
+    oiface_fresnel(b, vdot(wo, h), Fv, &F);
     double dn = F + tw * (1.0 - F);
     double pr = dn > 0.0 ? F / dn : 0.0;
     if (u_rt < pr) {
@@ -419,6 +480,11 @@ void oracle_lobe_pmf(const float* mat, int32_t entering, double mu_o, double pmf
 }
 
 double oracle_fresnel_dielectric(double cos_i, double eta) { return ofresnel_diel(cos_i, eta); }
+
+double oracle_film_reflectance(double cos_i, double n2, double n3, double film_ior, double d_nm,
+                               double lambda_nm) {
+  return ofilm_airy(cos_i, n2, n3, film_ior, d_nm, lambda_nm);
+}
 
 void oracle_fresnel_f82(const float* mat, double mu, double F[3]) {
   omat m;

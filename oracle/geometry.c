@@ -40,6 +40,9 @@ void omat_from_floats(const float* f, omat* m) {
   m->coat_ior = f[i++];
   m->emis_lum = f[i++];
   for (int c = 0; c < 3; ++c) m->emis_color[c] = f[i++];
+  m->film_weight = f[i++];
+  m->film_thickness_um = f[i++];
+  m->film_ior = f[i++];
 }
 
 /* ------------------------------------------------------------------ BVH -- */
@@ -154,7 +157,7 @@ int oracle_scene_create(const oracle_mesh* meshes, int32_t n_meshes, const oracl
   if (!s) return -2;
   s->n_mats = n_materials;
   s->mats = (omat*)calloc((size_t)n_materials, sizeof(omat));
-  for (int32_t i = 0; i < n_materials; ++i) omat_from_floats(materials + 27 * i, &s->mats[i]);
+  for (int32_t i = 0; i < n_materials; ++i) omat_from_floats(materials + OMAT_FLOATS * i, &s->mats[i]);
 
   /* meshes: with no instances, all meshes are concatenated into one world-space mesh */
   int32_t n_out = n_instances == 0 ? 1 : n_meshes;

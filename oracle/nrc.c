@@ -116,13 +116,13 @@ void onrc_inputs(const oracle_scene* s, v3 p, v3 wo, v3 n, const omat* m, double
 }
 
 /* Test hook: onrc_inputs for a scene box [lo, hi] and a material given as
- * its 27 OpenPBR floats. */
+ * its 30 OpenPBR floats. */
 void oracle_nrc_inputs(const double lo[3], const double hi[3], const double p[3], const double wo[3],
-                       const double n[3], const float* mat27, double x[12]) {
+                       const double n[3], const float* mat, double x[12]) {
   oracle_scene s;
   memset(&s, 0, sizeof s);
   for (int k = 0; k < 3; ++k) { s.lo[k] = lo[k]; s.hi[k] = hi[k]; }
   omat m;
-  omat_from_floats(mat27, &m);
+  omat_from_floats(mat, &m);
   onrc_inputs(&s, V(p[0], p[1], p[2]), V(wo[0], wo[1], wo[2]), V(n[0], n[1], n[2]), &m, x);
 }

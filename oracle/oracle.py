@@ -96,6 +96,8 @@ def _declare(L):
     L.oracle_lobe_pmf.restype = None
     L.oracle_fresnel_dielectric.argtypes = [C.c_double, C.c_double]
     L.oracle_fresnel_dielectric.restype = C.c_double
+    L.oracle_film_reflectance.argtypes = [C.c_double] * 6
+    L.oracle_film_reflectance.restype = C.c_double
     L.oracle_fresnel_f82.argtypes = [C.c_void_p, C.c_double, _dp]
     L.oracle_fresnel_f82.restype = None
     L.oracle_ggx_D.argtypes = [C.c_double, C.c_double, _dp]
@@ -174,7 +176,7 @@ def camera_ray(cam, fx, fy):
 
 
 def _mat(m) -> np.ndarray:
-    m = np.ascontiguousarray(np.asarray(m, dtype=np.float32).reshape(27))
+    m = np.ascontiguousarray(np.asarray(m, dtype=np.float32).reshape(30))
     return m
 
 
@@ -209,6 +211,11 @@ def lobe_pmf(mat, mu_o, entering=1):
 
 def fresnel_dielectric(c, eta):
     return lib().oracle_fresnel_dielectric(c, eta)
+
+
+def film_reflectance(c, n2, n3, film_ior, d_nm, lambda_nm):
+    """Unpolarised reflectance of a thin film (relative index n2) on a base (relative index n3)."""
+    return lib().oracle_film_reflectance(c, n2, n3, film_ior, d_nm, lambda_nm)
 
 
 def fresnel_f82(mat, mu):

@@ -32,7 +32,11 @@ typedef struct {
   double trans_weight, trans_color[3];
   double coat_weight, coat_color[3], coat_rough, coat_ior;
   double emis_lum, emis_color[3];
+  double film_weight, film_thickness_um, film_ior;
 } omat;
+
+/* floats of one OpenPBR parameter record at the C ABI */
+#define OMAT_FLOATS 30
 
 void omat_from_floats(const float* f, omat* m);
 /* dielectric IOR after the specular_weight modulation (bsdf.c) */
@@ -113,6 +117,7 @@ typedef struct {
   int coat_delta;
   double P[4];         /* lobe pmf: coat, metal, dielectric interface, diffuse */
   int absorbed;        /* sum of lobe weights is zero */
+  double film_n2;      /* thin film IOR relative to the medium wo is in */
 } obsdf;
 
 enum { LOBE_C = 0, LOBE_M = 1, LOBE_I = 2, LOBE_D = 3 };
@@ -123,6 +128,8 @@ void obsdf_eval(const obsdf* b, v3 wo, v3 wi, double f[3], double* pdf);
 int obsdf_sample(const obsdf* b, v3 wo, double u_lobe, double u1, double u2, double u_rt,
                  v3* wi, double weight[3], double* pdf, int* delta, int* refract, int* lobe_code);
 double ofresnel_diel(double c, double eta);
+double ofilm_airy(double c1, double n2, double n3, double film_ior, double d_nm, double lambda_nm);
+void oiface_fresnel(const obsdf* b, double c, double F[3], double* Fs);
 void of82(const omat* m, double mu, double F[3]);
 double oggx_D(double at, double ab, v3 m);
 double oggx_lambda(double at, double ab, v3 w);

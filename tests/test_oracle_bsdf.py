@@ -34,9 +34,13 @@ MATS = {
     "eon": M(base_color=(0.7, 0.4, 0.2), base_diffuse_roughness=0.8, specular_weight=0.0),
     "eon_plastic_weak": M(base_color=(0.5, 0.3, 0.2), base_diffuse_roughness=0.4, specular_roughness=0.4,
                           specular_weight=0.5),
+    "plastic_film": M(base_color=(0.5, 0.3, 0.2), specular_roughness=0.4, thin_film_weight=1.0,
+                      thin_film_thickness=0.35, thin_film_ior=1.33),
+    "glass_film": M(base_weight=0.0, transmission_weight=1.0, specular_roughness=0.3, specular_ior=1.5,
+                    thin_film_weight=0.8, thin_film_thickness=0.5, thin_film_ior=1.38),
 }
 OPAQUE = ["lambert", "metal", "metal_aniso", "plastic", "coated_delta", "coated_rough", "half_metal", "eon",
-          "eon_plastic_weak"]
+          "eon_plastic_weak", "plastic_film"]
 
 
 def sph(theta, phi):
@@ -325,7 +329,7 @@ def test_pdf_integrates_to_nondelta_mass(O, name):
         assert val > 0.8 * P.sum()
 
 
-@pytest.mark.parametrize("name", ["plastic", "metal_aniso", "glass_tinted"])
+@pytest.mark.parametrize("name", ["plastic", "metal_aniso", "glass_tinted", "plastic_film", "glass_film"])
 def test_sampled_directions_chi2(O, name):
     """Histogram of sampled directions over (cos theta, phi) bins against the integrated pdf."""
     mat = MATS[name]

@@ -1081,16 +1081,18 @@ pt_status sync_traced(pt_scene* s) {
 
 pt_status validate_material(const pt_openpbr_material& m, int i) {
   const float* f = reinterpret_cast<const float*>(&m);
-  for (int k = 0; k < 27; ++k) {
+  for (int k = 0; k < (int)(sizeof(pt_openpbr_material) / sizeof(float)); ++k) {
     if (!std::isfinite(f[k]) || f[k] < 0.0f) return fail(PT_ERR_INVALID_ARG, "material %d: parameter %d is negative or not finite", i, k);
   }
   const float unit[] = {m.base_weight, m.base_metalness, m.specular_weight, m.specular_roughness,
-                        m.specular_roughness_anisotropy, m.transmission_weight, m.coat_weight, m.coat_roughness};
+                        m.specular_roughness_anisotropy, m.transmission_weight, m.coat_weight, m.coat_roughness,
+                        m.thin_film_weight};
   for (float u : unit)
     if (u > 1.0f) return fail(PT_ERR_INVALID_ARG, "material %d: weights and roughness must be in [0, 1]", i);
   if (!(m.specular_ior > 0.0f) || !(m.coat_ior > 0.0f)) return fail(PT_ERR_INVALID_ARG, "material %d: IOR must be > 0", i);
   if (m.base_diffuse_roughness > 1.0f)
     return fail(PT_ERR_INVALID_ARG, "material %d: base_diffuse_roughness must be in [0, 1]", i);
+  if (m.thin_film_ior < 1.0f) return fail(PT_ERR_INVALID_ARG, "material %d: thin_film_ior must be >= 1", i);
   if (m.coat_weight > 0.0f && m.transmission_weight > 0.0f)
     return fail(PT_ERR_UNSUPPORTED, "material %d: coat together with transmission is not supported", i);
   return PT_OK;
@@ -1124,6 +1126,9 @@ MatRec make_matrec(const pt_openpbr_material& m) {
     r.eon_a = (float)A;
     r.eon_b = (float)(sg * A);
   }
+  r.film_w = m.thin_film_weight;
+  r.film_ior = m.thin_film_ior;
+  r.film_d_nm = (float)(1000.0 * (double)m.thin_film_thickness);
   r.trans_weight = m.transmission_weight;
   r.coat_weight = m.coat_weight;
   r.coat_ior = m.coat_ior;
@@ -1144,13 +1149,15 @@ MatRec make_matrec(const pt_openpbr_material& m) {
   // class: the smallest lobe set that contains every lobe the material can use
   bool hasC = m.coat_weight > 0.0f;
   bool hasM = m.base_metalness > 0.0f && m.specular_weight > 0.0f;
-  bool hasI = m.base_metalness < 1.0f && (m.specular_weight > 0.0f || m.transmission_weight > 0.0f);
+  bool hasI = m.base_metalness < 1.0f &&
+              (m.specular_weight > 0.0f || m.transmission_weight > 0.0f || m.thin_film_weight > 0.0f);
   bool hasD = m.base_metalness < 1.0f && m.transmission_weight < 1.0f && r.bwbc_lum > 0.0f;
   bool hasT = m.base_metalness < 1.0f && m.transmission_weight > 0.0f;
   int cls;
   if (!hasC && !hasM && !hasI && !hasD) cls = kClsAbsorb;
   else if (!hasC && !hasM && !hasI) cls = kClsDiffuse;
   else if (!hasC && !hasI && !hasD) cls = kClsMetal;
+  else if (m.thin_film_weight > 0.0f) cls = kClsGeneral;  // only the general class evaluates films
   else if (!hasM && !hasT) cls = kClsPlastic;
   else if (!hasC && !hasM) cls = kClsGlass;
   else cls = kClsGeneral;

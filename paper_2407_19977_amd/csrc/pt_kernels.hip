@@ -137,14 +137,18 @@ __device__ inline lds_u64* lds_stack_base(unsigned long long* shared_stack) {
 }
 
 // ------------------------------------------------------------------ lights
+// sin(theta) as |(x, z)| and theta = atan2(|(x, z)|, y): near the poles
+// acos(y) and sqrt(1 - y^2) lose most of their FP32 digits to cancellation
+// (at 0.4 degrees from the zenith sqrt(1 - y^2) is off by ~1e-3 relative,
+// which moves the environment's pdf and every MIS weight that uses it).
 __device__ inline int env_texel(const SceneDev& S, V3 d, float& sin_t) {
-  float y = fminf(fmaxf(d.y, -1.0f), 1.0f);
-  float th = acosf(y), ph = atan2f(d.x, -d.z);
+  const float sxz = sqrtf(d.x * d.x + d.z * d.z);
+  float th = atan2f(sxz, d.y), ph = atan2f(d.x, -d.z);
   float u = ph * (0.5f / kPi) + 0.5f, v = th * (1.0f / kPi);
   int c = (int)floorf(u * (float)S.env_w), r = (int)floorf(v * (float)S.env_h);
   c = min(max(c, 0), S.env_w - 1);
   r = min(max(r, 0), S.env_h - 1);
-  sin_t = sqrtf(fmaxf(0.0f, 1.0f - y * y));
+  sin_t = sxz;
   return r * S.env_w + c;
 }
 

@@ -68,7 +68,7 @@ enum MatClass : int {
 };
 
 // Device material record, 128 bytes, derived on the host from the OpenPBR parameters.
-struct alignas(128) MatRec {
+struct alignas(32) MatRec {
   float base_color[3];  float base_weight;
   float metalness;      float spec_weight;  float spec_ior;     float trans_weight;
   float spec_color[3];  float coat_weight;
@@ -78,8 +78,10 @@ struct alignas(128) MatRec {
   float at, ab, ac;     int32_t cls;        // GGX alphas (specular t/b, coat), class
   float spec_rough;     float f0_diel;      // specular roughness; F_dielectric(1, eta')
   float eon_a, eon_b;   // diffuse roughness sigma as FON's A = 1/(1 + (1/2 - 2/(3 pi)) sigma), B = sigma A
+  float film_w;         float film_ior;     // thin film on the dielectric interface: weight (0: none), IOR
+  float film_d_nm;      float pad[5];       // its thickness in nm
 };
-static_assert(sizeof(MatRec) == 128, "material record is 128 bytes");
+static_assert(sizeof(MatRec) == 160, "material record is 160 bytes");
 constexpr uint32_t kMatSpecDelta = 1u, kMatCoatDelta = 2u, kMatEmissive = 4u;
 
 // Instance of a mesh in the two-level hierarchy, 128 bytes.  w2o is the

@@ -11,8 +11,9 @@
 // BSDF (OpenPBR, Sec. 4; importance sampling, Sec. 5.1.3): coat C
 // (dielectric GGX reflection), metal M (GGX with F82-tint Fresnel),
 // dielectric interface I (GGX reflection + rough refraction after Walter et
-// al. 2007, with the 1/eta^2 radiance factor), diffuse D (Lambert attenuated
-// by the interface Fresnel on both sides):
+// al. 2007, with the 1/eta^2 radiance factor), diffuse D (Lambert, or the
+// energy-preserving Oren-Nayar model at base_diffuse_roughness > 0,
+// attenuated by the interface Fresnel on both sides):
 //   f = C + [(1-cw) + cw*coat_color*(1-Fc(|mu_i|))(1-Fc(mu_o))]
 //           * [metalness*M + (1-metalness)*(I + D)]
 // GGX uses alpha = roughness^2 with the OpenPBR anisotropy mapping,
@@ -20,8 +21,10 @@
 // 2014, 2018); a lobe with roughness < 1e-3 is a delta lobe.  One lobe is
 // chosen per bounce with probabilities proportional to
 //   w_C = cw*Fc, w_M = Tc*metalness*sw*lum(F82), w_I = Tc*(1-metalness)*(Fd + tw(1-Fd)),
-//   w_D = Tc*(1-metalness)*(1-tw)*(1-Fd)*lum(bw*bc),  Tc = 1-cw*Fc(mu_o), Fd = sw*F(mu_o),
-// and the non-delta weight is f*|cos|/sum_k P_k pdf_k (one-sample MIS).
+//   w_D = Tc*(1-metalness)*(1-tw)*(1-Fd)*lum(bw*bc),  Tc = 1-cw*Fc(mu_o), Fd = F(eta', mu_o),
+// and the non-delta weight is f*|cos|/sum_k P_k pdf_k (one-sample MIS).  eta'
+// is the IOR after the specular_weight modulation; with a thin film the
+// interface reflectance is per channel and Fd its luminance (iface_fresnel).
 #pragma once
 
 #include <math.h>
@@ -101,6 +104,41 @@ __host__ __device__ inline float fresnel_diel(float c, float eta) {
   return 0.5f * a * a * (1.0f + b * b);
 }
 
+// Thin film on the dielectric interface: reflectance of the stack incident
+// medium (index 1) | film (relative index n2) | base (relative index n3) at
+// incident cosine c1 for one wavelength, by the Airy sum of the film's
+// multiply reflected waves, per polarisation
+// R = (r12^2 + r23^2 + 2 r12 r23 cos d) / (1 + r12^2 r23^2 + 2 r12 r23 cos d),
+// r_ij = (a_i - a_j) / (a_i + a_j) with a = n cos (s) or cos / n (p), phase
+// d = 2 pi (2 film_ior d_nm cos_film / lambda); unpolarised: the mean.  Total
+// internal reflection at either interface reflects everything (the film's
+// index is at least 1).
+__host__ __device__ inline float film_airy(float c1, float n2, float n3, float film_ior, float d_nm,
+                                           float inv_lambda) {
+  c1 = fabsf(c1);
+  const float s2 = 1.0f - c1 * c1;
+  const float c2sq = 1.0f - s2 / (n2 * n2), c3sq = 1.0f - s2 / (n3 * n3);
+  if (c2sq < 0.0f || c3sq < 0.0f) return 1.0f;
+  const float c2 = sqrtf(c2sq), c3 = sqrtf(c3sq);
+  const float cyc = 2.0f * (2.0f * film_ior * d_nm * c2 * inv_lambda);  // phase / pi
+#ifdef __HIP_DEVICE_COMPILE__
+  const float cd = cospif(cyc);
+#else
+  const float cd = cosf(kPi * cyc);
+#endif
+  const float as[3] = {c1, n2 * c2, n3 * c3}, ap[3] = {c1, c2 / n2, c3 / n3};
+  float R = 0.0f;
+#pragma unroll
+  for (int pol = 0; pol < 2; ++pol) {
+    const float* a = pol == 0 ? as : ap;
+    const float r12 = (a[0] - a[1]) / (a[0] + a[1]);
+    const float r23 = (a[1] - a[2]) / (a[1] + a[2]);
+    const float x = 2.0f * r12 * r23 * cd;
+    R += 0.5f * (r12 * r12 + r23 * r23 + x) / (1.0f + r12 * r12 * r23 * r23 + x);
+  }
+  return R;
+}
+
 // OpenPBR F82-tint metal Fresnel, clamped to [0,1].
 __host__ __device__ inline V3 fresnel_f82(const MatRec& m, float mu) {
   const float mb = 1.0f / 7.0f;
@@ -174,24 +212,49 @@ struct Lobes {
   static constexpr bool I = CLS == kClsPlastic || CLS == kClsGlass || CLS == kClsGeneral;
   static constexpr bool D = CLS == kClsDiffuse || CLS == kClsPlastic || CLS == kClsGlass || CLS == kClsGeneral;
   static constexpr bool T = CLS == kClsGlass || CLS == kClsGeneral;
+  static constexpr bool F = CLS == kClsGeneral;  // thin film (materials with one are of the general class)
 };
 
 struct Bsdf {
   float eta;  // relative IOR of the interface seen from wo
+  float film_n2;  // thin film IOR relative to the medium wo is in
   bool entering;
   float P[4];  // lobe probabilities C, M, I, D
   bool absorbed;
 };
+
+// Reflectance of the specular dielectric interface at incident cosine c: per
+// channel, and the scalar Fs that chooses lobes and reflection vs refraction
+// (the plain Fresnel without a film, the luminance of the three with one).
+// One wavelength per channel: 650, 550, 450 nm.
+template <int CLS>
+__host__ __device__ inline V3 iface_fresnel(const MatRec& m, const Bsdf& b, float c, float& Fs) {
+  const float F0 = fresnel_diel(c, b.eta);
+  const float w = m.film_w;
+  if (!Lobes<CLS>::F || !(w > 0.0f)) {
+    Fs = F0;
+    return v3(F0, F0, F0);
+  }
+  const float r = film_airy(c, b.film_n2, b.eta, m.film_ior, m.film_d_nm, 1.0f / 650.0f);
+  const float g = film_airy(c, b.film_n2, b.eta, m.film_ior, m.film_d_nm, 1.0f / 550.0f);
+  const float bl = film_airy(c, b.film_n2, b.eta, m.film_ior, m.film_d_nm, 1.0f / 450.0f);
+  V3 F = v3((1.0f - w) * F0 + w * r, (1.0f - w) * F0 + w * g, (1.0f - w) * F0 + w * bl);
+  Fs = lum(F.x, F.y, F.z);
+  return F;
+}
 
 template <int CLS>
 __host__ __device__ inline Bsdf bsdf_setup(const MatRec& m, bool entering, float mu_o) {
   using L = Lobes<CLS>;
   Bsdf b;
   b.entering = entering;
-  b.eta = (m.trans_weight > 0.0f && !entering) ? 1.0f / m.spec_ior : m.spec_ior;
+  const bool inside = m.trans_weight > 0.0f && !entering;
+  b.eta = inside ? 1.0f / m.spec_ior : m.spec_ior;
+  b.film_n2 = inside ? m.film_ior / m.spec_ior : m.film_ior;
   float Fc = L::C ? fresnel_diel(mu_o, m.coat_ior) : 0.0f;
   float Tc = 1.0f - m.coat_weight * Fc;
-  float Fd = (L::I || L::D) ? fresnel_diel(mu_o, b.eta) : 0.0f;
+  float Fd = 0.0f;
+  if (L::I || L::D) (void)iface_fresnel<CLS>(m, b, mu_o, Fd);
   float w0 = L::C ? m.coat_weight * Fc : 0.0f;
   float w1 = 0.0f;
   if (L::M) {
@@ -275,7 +338,8 @@ __host__ __device__ inline V3 bsdf_eval(const MatRec& m, const Bsdf& b, V3 wo, V
       pc = ggx_vndf_pdf(m.ac, m.ac, wo, h) / (4.0f * oh);
     }
     V3 fm = v3(0.0f, 0.0f, 0.0f);
-    float fi = 0.0f, pm = 0.0f, pi = 0.0f;
+    V3 fi = v3(0.0f, 0.0f, 0.0f);
+    float pm = 0.0f, pi = 0.0f;
     if ((L::M || L::I) && spec_nd) {
       float D = ggx_D(m.at, m.ab, h);
       float g = ggx_G2(m.at, m.ab, wo, wi);
@@ -287,24 +351,25 @@ __host__ __device__ inline V3 bsdf_eval(const MatRec& m, const Bsdf& b, V3 wo, V
         pm = pv;
       }
       if (L::I) {
-        float Fi = fresnel_diel(oh, b.eta);
-        fi = Fi * D * g * inv4;
+        float Fi;
+        const V3 Fiv = iface_fresnel<CLS>(m, b, oh, Fi);
+        fi = v3(Fiv.x * D * g * inv4, Fiv.y * D * g * inv4, Fiv.z * D * g * inv4);
         float dn = Fi + tw * (1.0f - Fi);
         pi = dn > 0.0f ? (Fi / dn) * pv : 0.0f;
       }
     }
     V3 fd = v3(0.0f, 0.0f, 0.0f);
     if (L::D) {
-      float Fdi = fresnel_diel(mu_i, b.eta), Fdo = fresnel_diel(mu_o, b.eta);
-      float kd = (1.0f - tw) * (1.0f - Fdi) * (1.0f - Fdo);
+      float Fsi, Fso;
+      const V3 Fdi = iface_fresnel<CLS>(m, b, mu_i, Fsi), Fdo = iface_fresnel<CLS>(m, b, mu_o, Fso);
       float s = dot(wi, wo) - mu_i * mu_o;
-      fd = v3(kd * eon(m, m.base_weight * m.base_color[0], mu_i, mu_o, s),
-              kd * eon(m, m.base_weight * m.base_color[1], mu_i, mu_o, s),
-              kd * eon(m, m.base_weight * m.base_color[2], mu_i, mu_o, s));
+      fd = v3((1.0f - tw) * (1.0f - Fdi.x) * (1.0f - Fdo.x) * eon(m, m.base_weight * m.base_color[0], mu_i, mu_o, s),
+              (1.0f - tw) * (1.0f - Fdi.y) * (1.0f - Fdo.y) * eon(m, m.base_weight * m.base_color[1], mu_i, mu_o, s),
+              (1.0f - tw) * (1.0f - Fdi.z) * (1.0f - Fdo.z) * eon(m, m.base_weight * m.base_color[2], mu_i, mu_o, s));
     }
-    float fx = fc + Lc.x * (mt * fm.x + (1.0f - mt) * (fi + fd.x));
-    float fy = fc + Lc.y * (mt * fm.y + (1.0f - mt) * (fi + fd.y));
-    float fz = fc + Lc.z * (mt * fm.z + (1.0f - mt) * (fi + fd.z));
+    float fx = fc + Lc.x * (mt * fm.x + (1.0f - mt) * (fi.x + fd.x));
+    float fy = fc + Lc.y * (mt * fm.y + (1.0f - mt) * (fi.y + fd.y));
+    float fz = fc + Lc.z * (mt * fm.z + (1.0f - mt) * (fi.z + fd.z));
     f = v3(fx, fy, fz);
     pdf = b.P[0] * pc + b.P[1] * pm + b.P[2] * pi + b.P[3] * (mu_i * (1.0f / kPi));
     return f;
@@ -315,16 +380,19 @@ __host__ __device__ inline V3 bsdf_eval(const MatRec& m, const Bsdf& b, V3 wo, V
   if (h.z < 0.0f) h = h * -1.0f;
   float oh = dot(wo, h), ih = dot(wi, h);
   if (oh <= 0.0f || ih >= 0.0f) return f;
-  float F = fresnel_diel(oh, eta);
+  float F;
+  const V3 Fv = iface_fresnel<CLS>(m, b, oh, F);
   float s = ih + oh / eta;
   float denom = s * s;
   float D = ggx_D(m.at, m.ab, h);
   float g = ggx_G2(m.at, m.ab, wo, wi);
-  float bt = tw * (1.0f - F) * D * g * fabsf(ih) * fabsf(oh) / (denom * fabsf(mu_i) * mu_o) / (eta * eta);
-  float k = (1.0f - mt) * bt;
+  const float den = denom * fabsf(mu_i) * mu_o;
+  const float btx = tw * (1.0f - Fv.x) * D * g * fabsf(ih) * fabsf(oh) / den / (eta * eta);
+  const float bty = tw * (1.0f - Fv.y) * D * g * fabsf(ih) * fabsf(oh) / den / (eta * eta);
+  const float btz = tw * (1.0f - Fv.z) * D * g * fabsf(ih) * fabsf(oh) / den / (eta * eta);
   float tr = b.entering ? m.trans_color[0] : 1.0f, tg = b.entering ? m.trans_color[1] : 1.0f,
         tb = b.entering ? m.trans_color[2] : 1.0f;
-  f = v3(Lc.x * k * tr, Lc.y * k * tg, Lc.z * k * tb);
+  f = v3(Lc.x * ((1.0f - mt) * btx) * tr, Lc.y * ((1.0f - mt) * bty) * tg, Lc.z * ((1.0f - mt) * btz) * tb);
   float dn = F + tw * (1.0f - F);
   float pr = dn > 0.0f ? F / dn : 0.0f;
   pdf = b.P[2] * (1.0f - pr) * ggx_vndf_pdf(m.at, m.ab, wo, h) * fabsf(ih) / denom;
@@ -411,7 +479,8 @@ __host__ __device__ inline BsdfSample bsdf_sample(const MatRec& m, const Bsdf& b
   } else if (L::I && lobe == 2) {
     float eta = b.eta;
     if (spec_delta) {
-      float F = fresnel_diel(mu_o, eta);
+      float F;
+      const V3 Fv = iface_fresnel<CLS>(m, b, mu_o, F);
       float dn = F + tw * (1.0f - F);
       float pr = dn > 0.0f ? F / dn : 0.0f;
       s.delta = true;
@@ -419,8 +488,9 @@ __host__ __device__ inline BsdfSample bsdf_sample(const MatRec& m, const Bsdf& b
         s.lobe = 2;
         s.wi = v3(-wo.x, -wo.y, wo.z);
         V3 Lc = coat_layer<CLS>(m, mu_o, mu_o);
-        float k = (1.0f - mt) * F / (b.P[2] * pr);
-        s.weight = v3(Lc.x * k, Lc.y * k, Lc.z * k);
+        const float q = b.P[2] * pr;
+        s.weight = v3(Lc.x * ((1.0f - mt) * Fv.x / q), Lc.y * ((1.0f - mt) * Fv.y / q),
+                      Lc.z * ((1.0f - mt) * Fv.z / q));
         s.ok = true;
         return s;
       }
@@ -430,15 +500,18 @@ __host__ __device__ inline BsdfSample bsdf_sample(const MatRec& m, const Bsdf& b
       s.wi = t;
       s.refract = true;
       V3 Lc = coat_layer<CLS>(m, t.z, mu_o);
-      float k = (1.0f - mt) * tw * (1.0f - F) / (eta * eta) / (b.P[2] * (1.0f - pr));
+      const float q = b.P[2] * (1.0f - pr);
       float tr = b.entering ? m.trans_color[0] : 1.0f, tg = b.entering ? m.trans_color[1] : 1.0f,
             tb = b.entering ? m.trans_color[2] : 1.0f;
-      s.weight = v3(Lc.x * k * tr, Lc.y * k * tg, Lc.z * k * tb);
+      s.weight = v3(Lc.x * ((1.0f - mt) * tw * (1.0f - Fv.x) / (eta * eta) / q) * tr,
+                    Lc.y * ((1.0f - mt) * tw * (1.0f - Fv.y) / (eta * eta) / q) * tg,
+                    Lc.z * ((1.0f - mt) * tw * (1.0f - Fv.z) / (eta * eta) / q) * tb);
       s.ok = true;
       return s;
     }
     V3 h = ggx_vndf_sample(m.at, m.ab, wo, u1, u2);
-    float F = fresnel_diel(dot(wo, h), eta);
+    float F;
+    (void)iface_fresnel<CLS>(m, b, dot(wo, h), F);
     float dn = F + tw * (1.0f - F);
     float pr = dn > 0.0f ? F / dn : 0.0f;
     if (u_rt < pr) {

@@ -247,18 +247,27 @@ ZOO_MATERIALS = [
                                         coat_color=(1.0, 0.9, 0.7), coat_ior=1.6)),
     ("weak tinted metal", dict(base_metalness=1.0, base_weight=0.9, base_color=(0.95, 0.9, 0.8), specular_weight=0.7,
                                specular_color=(0.6, 0.8, 1.0), specular_roughness=0.15)),
+    ("thin film on plastic", dict(base_color=(0.15, 0.15, 0.2), specular_roughness=0.15, thin_film_weight=1.0,
+                                  thin_film_thickness=0.38, thin_film_ior=1.33)),
+    ("thin film on smooth glass", dict(base_weight=0.0, transmission_weight=1.0, specular_roughness=0.0,
+                                       thin_film_weight=1.0, thin_film_thickness=0.3, thin_film_ior=1.38)),
+    ("half-weight thin film on rough glass", dict(base_weight=0.0, transmission_weight=1.0, specular_roughness=0.3,
+                                                  thin_film_weight=0.5, thin_film_thickness=0.7, thin_film_ior=2.0)),
+    ("thin film on a base without specular", dict(base_color=(0.5, 0.5, 0.5), specular_weight=0.0,
+                                                  specular_roughness=0.2, thin_film_weight=1.0,
+                                                  thin_film_thickness=0.5, thin_film_ior=1.5)),
 ]
 
 
 def material_zoo(width=96, height=96, spp=8, max_depth=6, seed=0, sphere_level=2) -> Scene:
     """An open-topped box (floor, back, left and right walls, Lambert) under
     a small sky with a sun, a 0.3 x 0.3 quad light of radiance 12 hung below
-    the open top, and eight icospheres (radius 0.11, level 2) in two rows,
-    each with one of ZOO_MATERIALS: partial metalness, coat over metal,
+    the open top, and twelve icospheres (radius 0.1, level 2) in three
+    rows, each with one of ZOO_MATERIALS: partial metalness, coat over metal,
     transmission over diffuse and over partial metal, tints of the
-    specular, coat and transmission colours, specular_weight < 1 and
-    anisotropy under a coat — the OpenPBR mixes that the closed-box,
-    icosphere-field and instanced scenes do not reach.  The back wall is a
+    specular, coat and transmission colours, specular_weight < 1,
+    anisotropy under a coat and thin films — the OpenPBR mixes that the
+    closed-box, icosphere-field and instanced scenes do not reach.  The back wall is a
     rough diffuse (base_diffuse_roughness 0.7) and the left wall a rough
     diffuse base (0.3) under a glossy specular layer."""
     mats = [lambert((0.6, 0.6, 0.6)),
@@ -275,11 +284,12 @@ def material_zoo(width=96, height=96, spp=8, max_depth=6, seed=0, sphere_level=2
     b.add_quad([1, 0, 0], [1, 1, 0], [1, 1, 1], [1, 0, 1], [-1, 0, 0], 3)   # right
     b.add_quad([.35, .92, .45], [.65, .92, .45], [.65, .92, .75], [.35, .92, .75], [0, -1, 0], 4)
     v, f = icosphere(sphere_level)
-    rad = 0.11
+    rad = 0.1
     for k in range(len(ZOO_MATERIALS)):
+        row = k // 4
         cx = 0.17 + 0.22 * (k % 4)
-        cz = 0.35 if k < 4 else 0.68
-        cy = rad + (0.0 if k < 4 else 0.12)
+        cz = (0.3, 0.58, 0.86)[row]
+        cy = rad + (0.0, 0.13, 0.26)[row]
         b.add(v * rad + np.array([cx, cy, cz]), f, 5 + k)
     cam = Camera((0.5, 0.5, -0.45), (0.5, 0.18, 0.5), (0.0, 1.0, 0.0), 42.0, width, height)
     env = sky_env(width=256, height=128, sun_elev_deg=55.0, sun_azim_deg=160.0, sun_diam_deg=3.0,

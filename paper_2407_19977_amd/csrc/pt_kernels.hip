@@ -307,6 +307,8 @@ __global__ __launch_bounds__(kBlock) void k_generate(PathsDev P, CamDev C, uint3
 
 // Empty the next ray queue and the class queues (the shadow queue is still
 // being traced; k_bin empties it).
+__global__ void k_zero_u32(uint32_t* p) { *p = 0u; }
+
 __global__ void k_reset_counts(uint32_t* counts, int next_queue) {
   int i = threadIdx.x;
   if (i >= 2 && i < kCountShadow) counts[i] = 0u;
@@ -346,6 +348,9 @@ constexpr uint32_t kLeafWait = PT_LEAF_WAIT, kLeafWaitDen = PT_LEAF_WAIT_DEN;
 constexpr int kShadeBlock = PT_SHADE_BLOCK;  // threads per workgroup of the shading kernels
 #ifndef PT_TAIL_SHADE_WAIT
 #define PT_TAIL_SHADE_WAIT 1
+#endif
+#ifndef PT_TAIL_DYNAMIC
+#define PT_TAIL_DYNAMIC 1  // tail kernel: paths from a device-wide counter (0: a static share per workgroup)
 #endif
 // tail kernel: lanes waiting to shade go ahead once kTailShadeWait x their
 // number reaches the number of lanes still walking (a large value shades at
@@ -1018,12 +1023,20 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
                                                  uint32_t sample, uint32_t k0, uint32_t k1, uint32_t img_w,
                                                  int nrc_bounce) {
   __shared__ unsigned long long s_stack[kLdsStack * kBlock];
-  __shared__ uint32_t s_next;
   const uint32_t count = P.counts[cur];
+#if PT_TAIL_DYNAMIC
+  // every wave takes paths from one device-wide counter (zeroed before the
+  // launch), so the longest paths do not pile up in one workgroup's share
+  uint32_t* next_path = &P.counts[kCountTail];
+  const uint32_t q1 = count;
+#else
+  __shared__ uint32_t s_next;
   const uint32_t per = (count + gridDim.x - 1) / gridDim.x;
   const uint32_t q0 = min(count, blockIdx.x * per), q1 = min(count, q0 + per);
   if (threadIdx.x == 0) s_next = q0;
   __syncthreads();
+  uint32_t* next_path = &s_next;
+#endif
   const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
   DevStack st{lds_stack_base(s_stack), S.spill + gtid, S.spill_stride, 0, S.stack_cap, false};
   LaneRay L;
@@ -1052,7 +1065,7 @@ __global__ __launch_bounds__(kBlock) void k_tail(SceneDev S, PathsDev P, int cur
     const uint32_t n_idle = (uint32_t)__popcll((unsigned long long)idle);
     if (!drained && (n_idle >= kRefill || n_idle == 64u)) {
       uint32_t base = 0;
-      if (lane_id() == 0) base = atomicAdd(&s_next, n_idle);
+      if (lane_id() == 0) base = atomicAdd(next_path, n_idle);
       base = __shfl(base, 0);
       if (base + n_idle >= q1) drained = true;
       const uint32_t i = base + lane_prefix(idle);
@@ -1422,6 +1435,7 @@ static hipError_t bounce_loop(const SceneDev& S, const PathsDev& P, const CamDev
           if (e2 != hipSuccess) return e2;
           query_pending = false;
         }
+        if (PT_TAIL_DYNAMIC) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, ts, P.counts + kCountTail);
         if (A.tail_events) hipEventRecord(A.tail_events[0], ts);
         hipLaunchKernelGGL((k_tail<DEBUG, COUNT, TWO>),
                            dim3(tail_grid(A.grid_trace, *A.tail_host_count, A.tail_stream != nullptr)), blk, 0, ts,

@@ -63,7 +63,7 @@ typedef struct pt_instance {
   int32_t material_override;  /* -1: use the mesh's per-triangle ids */
 } pt_instance;
 
-/* OpenPBR parameters (Sec. 4), linear RGB; 30 floats in this order.
+/* OpenPBR parameters (Sec. 4), linear RGB; 35 floats in this order.
  * thin_film_thickness is in micrometres. */
 typedef struct pt_openpbr_material {
   float base_weight, base_color[3], base_metalness, base_diffuse_roughness;
@@ -73,6 +73,7 @@ typedef struct pt_openpbr_material {
   float coat_weight, coat_color[3], coat_roughness, coat_ior;
   float emission_luminance, emission_color[3];
   float thin_film_weight, thin_film_thickness, thin_film_ior;
+  float fuzz_weight, fuzz_color[3], fuzz_roughness;
 } pt_openpbr_material;
 
 /* Pinhole camera (Sec. 5.1.2): vertical field of view in degrees, aspect width/height. */

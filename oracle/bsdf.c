@@ -38,6 +38,7 @@
  *
  * Frame: local +z is the surface normal flipped to the side of wo, so mu_o > 0.
  */
+#include <pthread.h>
 #include <string.h>
 
 #include "oracle_internal.h"
@@ -103,6 +104,88 @@ void oiface_fresnel(const obsdf* b, double c, double F[3], double* Fs) {
     F[k] = (1.0 - w) * F0 + w * Rf;
   }
   *Fs = lum3(F);
+}
+
+/*
+ * Fuzz (OpenPBR fuzz_weight, fuzz_color, fuzz_roughness): a sheen lobe on
+ * top of the material.  Reading: the "Charlie" sheen distribution of
+ * Estevez & Kulla (2017), D(h) = (2 + 1/a) sin(theta_h)^(1/a) / (2 pi) with
+ * a = max(roughness^2, 1e-2), and the visibility term of Neubelt & Pettineo
+ * (2013), V = 1 / (4 (mu_i + mu_o - mu_i mu_o)); f = w fuzz_color D V.  The
+ * layers below are attenuated by (1 - w E(mu_i)) (1 - w E(mu_o)), E the
+ * lobe's directional albedo, so the fuzz takes the energy it reflects.
+ */
+double ofuzz_alpha(double r) {
+  double a = r * r;
+  return a < 1e-2 ? 1e-2 : a;
+}
+
+double ofuzz_f(double alpha, v3 wo, v3 wi) {
+  if (wo.z <= 0.0 || wi.z <= 0.0) return 0.0;
+  v3 h = vnorm(vadd(wo, wi));
+  double s2 = 1.0 - h.z * h.z;
+  double sn = s2 > 0.0 ? sqrt(s2) : 0.0;
+  double D = (2.0 + 1.0 / alpha) * pow(sn, 1.0 / alpha) / (2.0 * O_PI);
+  double V = 1.0 / (4.0 * (wi.z + wo.z - wi.z * wo.z));
+  return D * V;
+}
+
+/* E(mu_k) for mu_k = k / 64: the midpoint rule over mu_i in [0, 1] and phi in
+ * [0, 2 pi) with 256 x 256 cells of the cosine-weighted lobe (the table is
+ * defined by this rule), for wo = (sqrt(1 - mu^2), 0, mu).  Tables are kept
+ * per roughness: a render builds each once per material. */
+#define FUZZ_CACHE 16
+static pthread_mutex_t fuzz_mu = PTHREAD_MUTEX_INITIALIZER;
+static double fuzz_cache_r[FUZZ_CACHE];
+static double fuzz_cache_E[FUZZ_CACHE][65];
+static int fuzz_cache_n = 0;
+
+void ofuzz_table(double rough, double E[65]) {
+  pthread_mutex_lock(&fuzz_mu);
+  for (int i = 0; i < fuzz_cache_n; ++i)
+    if (fuzz_cache_r[i] == rough) {
+      memcpy(E, fuzz_cache_E[i], sizeof(double) * 65);
+      pthread_mutex_unlock(&fuzz_mu);
+      return;
+    }
+  pthread_mutex_unlock(&fuzz_mu);
+  const int N = 256, M = 256;
+  double alpha = ofuzz_alpha(rough);
+  for (int k = 0; k <= 64; ++k) {
+    double mu = k / 64.0;
+    v3 wo = V(sqrt(1.0 - mu * mu), 0.0, mu);
+    double acc = 0.0;
+    for (int a = 0; a < N; ++a) {
+      double mi = (a + 0.5) / N, si = sqrt(1.0 - mi * mi);
+      for (int b = 0; b < M; ++b) {
+        double phi = 2.0 * O_PI * (b + 0.5) / M;
+        v3 wi = V(si * cos(phi), si * sin(phi), mi);
+        acc += ofuzz_f(alpha, wo, wi) * mi;
+      }
+    }
+    E[k] = acc * (1.0 / N) * (2.0 * O_PI / M);
+  }
+  pthread_mutex_lock(&fuzz_mu);
+  int slot = fuzz_cache_n < FUZZ_CACHE ? fuzz_cache_n++ : FUZZ_CACHE - 1;
+  fuzz_cache_r[slot] = rough;
+  memcpy(fuzz_cache_E[slot], E, sizeof(double) * 65);
+  pthread_mutex_unlock(&fuzz_mu);
+}
+
+/* E at mu by linear interpolation of the table, clamped to [0, 1] */
+double ofuzz_albedo(const omat* m, double mu) {
+  double t = (mu < 0.0 ? 0.0 : (mu > 1.0 ? 1.0 : mu)) * 64.0;
+  int k = (int)floor(t);
+  if (k > 63) k = 63;
+  double e = m->fuzz_E[k] + (t - k) * (m->fuzz_E[k + 1] - m->fuzz_E[k]);
+  return e < 0.0 ? 0.0 : (e > 1.0 ? 1.0 : e);
+}
+
+/* attenuation of the layers under the fuzz */
+static double fuzz_att(const omat* m, double mu_i, double mu_o) {
+  double w = m->fuzz_weight;
+  if (!(w > 0.0)) return 1.0;
+  return (1.0 - w * ofuzz_albedo(m, fabs(mu_i))) * (1.0 - w * ofuzz_albedo(m, mu_o));
 }
 
 double omod_ior(const omat* m) {
@@ -214,18 +297,24 @@ void obsdf_setup(const omat* m, int entering, double mu_o, obsdf* b) {
   of82(m, mu_o, F82);
   double bwbc[3] = {m->base_weight * m->base_color[0], m->base_weight * m->base_color[1],
                     m->base_weight * m->base_color[2]};
-  double w[4];
+  double w[5];
   w[LOBE_C] = cw * Fc;
   w[LOBE_M] = Tc * mt * sw * lum3(F82);
   w[LOBE_I] = Tc * (1.0 - mt) * (Fd + tw * (1.0 - Fd));
   w[LOBE_D] = Tc * (1.0 - mt) * (1.0 - tw) * (1.0 - Fd) * lum3(bwbc);
-  double sum = w[0] + w[1] + w[2] + w[3];
+  w[LOBE_Z] = 0.0;
+  if (m->fuzz_weight > 0.0) {  /* the fuzz reflects w E(mu_o) and passes the rest to the layers below */
+    double fz = m->fuzz_weight * ofuzz_albedo(m, mu_o);
+    for (int k = 0; k < 4; ++k) w[k] *= 1.0 - fz;
+    w[LOBE_Z] = fz * lum3(m->fuzz_color);
+  }
+  double sum = ((w[0] + w[1]) + (w[2] + w[3])) + w[4];
   b->absorbed = !(sum > 0.0);
-  for (int k = 0; k < 4; ++k) b->P[k] = b->absorbed ? 0.0 : w[k] / sum;
+  for (int k = 0; k < 5; ++k) b->P[k] = b->absorbed ? 0.0 : w[k] / sum;
 }
 
 int obsdf_has_nondelta(const obsdf* b) {
-  double s = b->P[LOBE_D];
+  double s = b->P[LOBE_D] + b->P[LOBE_Z];
   if (!b->coat_delta) s += b->P[LOBE_C];
   if (!b->spec_delta) s += b->P[LOBE_M] + b->P[LOBE_I];
   return s > 0.0;
@@ -287,12 +376,15 @@ void obsdf_eval(const obsdf* b, v3 wo, v3 wi, double f[3], double* pdf) {
     oiface_fresnel(b, mu_i, Fdi, &Fsi);
     oiface_fresnel(b, mu_o, Fdo, &Fso);
     double s = vdot(wi, wo) - mu_i * mu_o;
+    double A = fuzz_att(m, mu_i, mu_o);
+    double fz = m->fuzz_weight > 0.0 ? m->fuzz_weight * ofuzz_f(ofuzz_alpha(m->fuzz_rough), wo, wi) : 0.0;
     for (int c = 0; c < 3; ++c) {
       double kd = (1.0 - tw) * (1.0 - Fdi[c]) * (1.0 - Fdo[c]);
       double fd = kd * oeon(m->base_weight * m->base_color[c], m->diffuse_roughness, mu_i, mu_o, s);
-      f[c] = fc + L[c] * (mt * fm[c] + (1.0 - mt) * (fi[c] + fd));
+      f[c] = fz * m->fuzz_color[c] + A * (fc + L[c] * (mt * fm[c] + (1.0 - mt) * (fi[c] + fd)));
     }
-    *pdf = b->P[LOBE_C] * pc + b->P[LOBE_M] * pm + b->P[LOBE_I] * pi + b->P[LOBE_D] * (mu_i / O_PI);
+    *pdf = b->P[LOBE_C] * pc + b->P[LOBE_M] * pm + b->P[LOBE_I] * pi + b->P[LOBE_D] * (mu_i / O_PI) +
+           b->P[LOBE_Z] * (mu_i / O_PI);
   } else {
     if (b->spec_delta || tw <= 0.0) return;
     double eta = b->eta;
@@ -328,11 +420,11 @@ static int refract_about(v3 wo, v3 m, double eta, v3* wi) {
 }
 
 /*
- * Sample a direction: lobe by u_lobe against the cumulative pmf (C, M, I, D;
- * if rounding leaves u_lobe past the last bucket, the last lobe with
+ * Sample a direction: lobe by u_lobe against the cumulative pmf (C, M, I, D,
+ * Z; if rounding leaves u_lobe past the last bucket, the last lobe with
  * nonzero probability is taken), microfacet or cosine direction from
  * (u1, u2), reflect-vs-refract from u_rt.  Lobe codes: 0 coat, 1 metal,
- * 2 interface reflection, 3 interface refraction, 4 diffuse.
+ * 2 interface reflection, 3 interface refraction, 4 diffuse, 5 fuzz.
  */
 int obsdf_sample(const obsdf* b, v3 wo, double u_lobe, double u1, double u2, double u_rt, v3* wi,
                  double weight[3], double* pdf, int* delta, int* refract, int* lobe_code) {
@@ -346,7 +438,7 @@ int obsdf_sample(const obsdf* b, v3 wo, double u_lobe, double u1, double u2, dou
   const omat* m = &b->m;
   int lobe = -1, last = -1;
   double acc = 0.0;
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 5; ++k) {
     if (b->P[k] > 0.0) {
       last = k;
       if (lobe < 0 && u_lobe < acc + b->P[k]) lobe = k;
@@ -361,7 +453,7 @@ int obsdf_sample(const obsdf* b, v3 wo, double u_lobe, double u1, double u2, dou
     *lobe_code = 0;
     if (b->coat_delta) {
       *wi = V(-wo.x, -wo.y, wo.z);
-      double w = cw * ofresnel_diel(mu_o, m->coat_ior) / b->P[LOBE_C];
+      double w = fuzz_att(m, mu_o, mu_o) * cw * ofresnel_diel(mu_o, m->coat_ior) / b->P[LOBE_C];
       weight[0] = weight[1] = weight[2] = w;
       *delta = 1;
       return 1;
@@ -376,7 +468,8 @@ int obsdf_sample(const obsdf* b, v3 wo, double u_lobe, double u1, double u2, dou
       double L[3], F[3];
       coat_layer(b, mu_o, mu_o, L);
       of82(m, mu_o, F);
-      for (int c = 0; c < 3; ++c) weight[c] = L[c] * mt * sw * F[c] / b->P[LOBE_M];
+      double A = fuzz_att(m, mu_o, mu_o);
+      for (int c = 0; c < 3; ++c) weight[c] = A * L[c] * mt * sw * F[c] / b->P[LOBE_M];
       *delta = 1;
       return 1;
     }
@@ -396,7 +489,8 @@ int obsdf_sample(const obsdf* b, v3 wo, double u_lobe, double u1, double u2, dou
         *lobe_code = 2;
         *wi = V(-wo.x, -wo.y, wo.z);
         coat_layer(b, mu_o, mu_o, L);
-        for (int c = 0; c < 3; ++c) weight[c] = L[c] * (1.0 - mt) * Fv[c] / (b->P[LOBE_I] * pr);
+        double A = fuzz_att(m, mu_o, mu_o);
+        for (int c = 0; c < 3; ++c) weight[c] = A * L[c] * (1.0 - mt) * Fv[c] / (b->P[LOBE_I] * pr);
         return 1;
       }
       *lobe_code = 3;
@@ -427,7 +521,7 @@ int obsdf_sample(const obsdf* b, v3 wo, double u_lobe, double u1, double u2, dou
       *refract = 1;
     }
   } else {
-    *lobe_code = 4;
+    *lobe_code = lobe == LOBE_Z ? 5 : 4;  /* fuzz and diffuse: cosine-weighted directions */
     double r = sqrt(u1), phi = 2.0 * O_PI * u2;
     double z = 1.0 - u1;
     d = V(r * cos(phi), r * sin(phi), sqrt(z > 0.0 ? z : 0.0));
@@ -471,15 +565,24 @@ int oracle_bsdf_sample(const float* mat, int32_t entering, const double wo[3], c
   return ok;
 }
 
-void oracle_lobe_pmf(const float* mat, int32_t entering, double mu_o, double pmf[4]) {
+void oracle_lobe_pmf(const float* mat, int32_t entering, double mu_o, double pmf[5]) {
   omat m;
   omat_from_floats(mat, &m);
   obsdf b;
   obsdf_setup(&m, entering, mu_o, &b);
-  memcpy(pmf, b.P, sizeof(double) * 4);
+  memcpy(pmf, b.P, sizeof(double) * 5);
 }
 
 double oracle_fresnel_dielectric(double cos_i, double eta) { return ofresnel_diel(cos_i, eta); }
+
+double oracle_fuzz_albedo(double rough, double mu) {
+  omat m;
+  memset(&m, 0, sizeof m);
+  m.fuzz_weight = 1.0;
+  m.fuzz_rough = rough;
+  ofuzz_table(rough, m.fuzz_E);
+  return ofuzz_albedo(&m, mu);
+}
 
 double oracle_film_reflectance(double cos_i, double n2, double n3, double film_ior, double d_nm,
                                double lambda_nm) {

@@ -43,6 +43,12 @@ void omat_from_floats(const float* f, omat* m) {
   m->film_weight = f[i++];
   m->film_thickness_um = f[i++];
   m->film_ior = f[i++];
+  m->fuzz_weight = f[i++];
+  for (int c = 0; c < 3; ++c) m->fuzz_color[c] = f[i++];
+  m->fuzz_rough = f[i++];
+  if (m->fuzz_weight > 0.0) ofuzz_table(m->fuzz_rough, m->fuzz_E);
+  else
+    for (int k = 0; k < 65; ++k) m->fuzz_E[k] = 0.0;
 }
 
 /* ------------------------------------------------------------------ BVH -- */

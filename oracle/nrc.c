@@ -116,7 +116,7 @@ void onrc_inputs(const oracle_scene* s, v3 p, v3 wo, v3 n, const omat* m, double
 }
 
 /* Test hook: onrc_inputs for a scene box [lo, hi] and a material given as
- * its 30 OpenPBR floats. */
+ * its 35 OpenPBR floats. */
 void oracle_nrc_inputs(const double lo[3], const double hi[3], const double p[3], const double wo[3],
                        const double n[3], const float* mat, double x[12]) {
   oracle_scene s;

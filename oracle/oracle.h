@@ -81,7 +81,7 @@ double oracle_uniform(uint64_t seed, uint32_t pixel, uint32_t sample, uint32_t b
 
 int oracle_scene_create(const oracle_mesh* meshes, int32_t n_meshes,
                         const oracle_instance* instances, int32_t n_instances,
-                        const float* materials /* [n][30] */, int32_t n_materials,
+                        const float* materials /* [n][35] */, int32_t n_materials,
                         const float* env /* [h][w][3] or NULL */, int32_t env_w, int32_t env_h,
                         oracle_scene** out);
 void oracle_scene_destroy(oracle_scene* s);
@@ -124,7 +124,7 @@ void oracle_nrc_encode(const double x[12], double f[64]);
 void oracle_nrc_forward(const double* W, const double x[12], int32_t bf16, double y[3]);
 /* Test hook: the 12 cache inputs at point p (scene box [lo, hi]), outgoing
  * direction wo and shading normal n (world space, unit) of a material given
- * as its 30 OpenPBR floats. */
+ * as its 35 OpenPBR floats. */
 void oracle_nrc_inputs(const double lo[3], const double hi[3], const double p[3], const double wo[3],
                        const double n[3], const float* mat, double x[12]);
 /* Training records of one path: for every vertex k < max_depth that scatters
@@ -153,15 +153,17 @@ void oracle_display(const double* sum, int64_t n_pixels, double inv_samples, dou
                     uint8_t* rgba8);
 
 /* ---- BSDF and light-sampling probes (local shading frame, n = +z) ---- */
-/* mat: 30 floats.  entering: 1 if wo is on the front side of the geometric normal. */
+/* mat: 35 floats.  entering: 1 if wo is on the front side of the geometric normal. */
 int oracle_bsdf_eval(const float* mat, int32_t entering, const double wo[3], const double wi[3],
                      double f[3], double* pdf);
 /* u[4] = (lobe, dir1, dir2, reflect/refract).  out: wi[3], weight[3], pdf, flags
  * (bit0 delta, bit1 refraction), lobe code; returns 1 if a direction was produced. */
 int oracle_bsdf_sample(const float* mat, int32_t entering, const double wo[3], const double u[4],
                        double wi[3], double weight[3], double* pdf, int32_t* flags, int32_t* lobe);
-void oracle_lobe_pmf(const float* mat, int32_t entering, double mu_o, double pmf[4]);
+void oracle_lobe_pmf(const float* mat, int32_t entering, double mu_o, double pmf[5]);
 double oracle_fresnel_dielectric(double cos_i, double eta);
+/* directional albedo of the fuzz lobe (weight 1, colour 1) at cosine mu, from its table */
+double oracle_fuzz_albedo(double rough, double mu);
 /* thin-film reflectance (unpolarised, one wavelength): incident index 1, film n2, base n3 (relative),
  * absolute film IOR and thickness in nm for the phase */
 double oracle_film_reflectance(double cos_i, double n2, double n3, double film_ior, double d_nm,

@@ -96,6 +96,8 @@ def _declare(L):
     L.oracle_lobe_pmf.restype = None
     L.oracle_fresnel_dielectric.argtypes = [C.c_double, C.c_double]
     L.oracle_fresnel_dielectric.restype = C.c_double
+    L.oracle_fuzz_albedo.argtypes = [C.c_double, C.c_double]
+    L.oracle_fuzz_albedo.restype = C.c_double
     L.oracle_film_reflectance.argtypes = [C.c_double] * 6
     L.oracle_film_reflectance.restype = C.c_double
     L.oracle_fresnel_f82.argtypes = [C.c_void_p, C.c_double, _dp]
@@ -176,7 +178,7 @@ def camera_ray(cam, fx, fy):
 
 
 def _mat(m) -> np.ndarray:
-    m = np.ascontiguousarray(np.asarray(m, dtype=np.float32).reshape(30))
+    m = np.ascontiguousarray(np.asarray(m, dtype=np.float32).reshape(35))
     return m
 
 
@@ -204,13 +206,18 @@ def bsdf_sample(mat, wo, u, entering=1):
 
 def lobe_pmf(mat, mu_o, entering=1):
     m = _mat(mat)
-    p = (C.c_double * 4)()
+    p = (C.c_double * 5)()
     lib().oracle_lobe_pmf(m.ctypes.data, entering, mu_o, p)
     return np.array(p[:])
 
 
 def fresnel_dielectric(c, eta):
     return lib().oracle_fresnel_dielectric(c, eta)
+
+
+def fuzz_albedo(rough, mu):
+    """Directional albedo of the fuzz lobe (weight 1, colour 1) from the oracle's table."""
+    return lib().oracle_fuzz_albedo(rough, mu)
 
 
 def film_reflectance(c, n2, n3, film_ior, d_nm, lambda_nm):

@@ -33,10 +33,12 @@ typedef struct {
   double coat_weight, coat_color[3], coat_rough, coat_ior;
   double emis_lum, emis_color[3];
   double film_weight, film_thickness_um, film_ior;
+  double fuzz_weight, fuzz_color[3], fuzz_rough;
+  double fuzz_E[65];   /* directional albedo of the fuzz lobe at mu = k/64 (zero without fuzz) */
 } omat;
 
 /* floats of one OpenPBR parameter record at the C ABI */
-#define OMAT_FLOATS 30
+#define OMAT_FLOATS 35
 
 void omat_from_floats(const float* f, omat* m);
 /* dielectric IOR after the specular_weight modulation (bsdf.c) */
@@ -115,12 +117,12 @@ typedef struct {
   int spec_delta;
   double ac;           /* coat alpha */
   int coat_delta;
-  double P[4];         /* lobe pmf: coat, metal, dielectric interface, diffuse */
+  double P[5];         /* lobe pmf: coat, metal, dielectric interface, diffuse, fuzz */
   int absorbed;        /* sum of lobe weights is zero */
   double film_n2;      /* thin film IOR relative to the medium wo is in */
 } obsdf;
 
-enum { LOBE_C = 0, LOBE_M = 1, LOBE_I = 2, LOBE_D = 3 };
+enum { LOBE_C = 0, LOBE_M = 1, LOBE_I = 2, LOBE_D = 3, LOBE_Z = 4 };
 
 void obsdf_setup(const omat* m, int entering, double mu_o, obsdf* b);
 int obsdf_has_nondelta(const obsdf* b);
@@ -130,6 +132,10 @@ int obsdf_sample(const obsdf* b, v3 wo, double u_lobe, double u1, double u2, dou
 double ofresnel_diel(double c, double eta);
 double ofilm_airy(double c1, double n2, double n3, double film_ior, double d_nm, double lambda_nm);
 void oiface_fresnel(const obsdf* b, double c, double F[3], double* Fs);
+double ofuzz_f(double alpha, v3 wo, v3 wi);
+double ofuzz_alpha(double rough);
+void ofuzz_table(double rough, double E[65]);
+double ofuzz_albedo(const omat* m, double mu);
 void of82(const omat* m, double mu, double F[3]);
 double oggx_D(double at, double ab, v3 m);
 double oggx_lambda(double at, double ab, v3 w);

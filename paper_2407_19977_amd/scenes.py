@@ -28,7 +28,7 @@ from typing import List, Optional
 
 import numpy as np
 
-# One OpenPBR parameter record: 30 float32, in this order.  The C ABI's
+# One OpenPBR parameter record: 35 float32, in this order.  The C ABI's
 # pt_openpbr_material and the oracle's input record have the same layout.
 MATERIAL_FIELDS = [
     ("base_weight", 1), ("base_color", 3), ("base_metalness", 1),
@@ -39,18 +39,19 @@ MATERIAL_FIELDS = [
     ("coat_weight", 1), ("coat_color", 3), ("coat_roughness", 1), ("coat_ior", 1),
     ("emission_luminance", 1), ("emission_color", 3),
     ("thin_film_weight", 1), ("thin_film_thickness", 1), ("thin_film_ior", 1),
+    ("fuzz_weight", 1), ("fuzz_color", 3), ("fuzz_roughness", 1),
 ]
-MATERIAL_FLOATS = sum(n for _, n in MATERIAL_FIELDS)  # 30
+MATERIAL_FLOATS = sum(n for _, n in MATERIAL_FIELDS)  # 35
 
 
 def material(**kw) -> np.ndarray:
-    """Return one material as float32[30], OpenPBR defaults for unset fields.
+    """Return one material as float32[35], OpenPBR defaults for unset fields.
 
     Defaults follow the OpenPBR specification: base_weight 1, base_color 0.8,
     specular_weight 1, specular_color 1, specular_roughness 0.3,
     specular_ior 1.5, transmission_color 1, coat_color 1, coat_ior 1.6,
     emission_color 1, thin_film_thickness 0.5 (micrometres), thin_film_ior
-    1.5, everything else 0.
+    1.5, fuzz_color 1, fuzz_roughness 0.5, everything else 0.
     """
     d = {
         "base_weight": 1.0, "base_color": (0.8, 0.8, 0.8), "base_metalness": 0.0,
@@ -63,6 +64,7 @@ def material(**kw) -> np.ndarray:
         "coat_ior": 1.6,
         "emission_luminance": 0.0, "emission_color": (1.0, 1.0, 1.0),
         "thin_film_weight": 0.0, "thin_film_thickness": 0.5, "thin_film_ior": 1.5,
+        "fuzz_weight": 0.0, "fuzz_color": (1.0, 1.0, 1.0), "fuzz_roughness": 0.5,
     }
     for k, v in kw.items():
         if k not in d:
@@ -118,7 +120,7 @@ class Scene:
     name: str
     meshes: List[Mesh]
     instances: List[Instance]          # empty: single level, meshes in world space
-    materials: np.ndarray              # float32 [n_materials, 30]
+    materials: np.ndarray              # float32 [n_materials, 35]
     env: Optional[np.ndarray]          # float32 [h, w, 3] equirect (y up) or None
     camera: Camera
     spp: int

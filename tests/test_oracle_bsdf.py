@@ -38,9 +38,13 @@ MATS = {
                       thin_film_thickness=0.35, thin_film_ior=1.33),
     "glass_film": M(base_weight=0.0, transmission_weight=1.0, specular_roughness=0.3, specular_ior=1.5,
                     thin_film_weight=0.8, thin_film_thickness=0.5, thin_film_ior=1.38),
+    "fuzz_plastic": M(base_color=(0.5, 0.3, 0.2), specular_roughness=0.4, fuzz_weight=0.7,
+                      fuzz_color=(0.9, 0.8, 0.6), fuzz_roughness=0.4),
+    "fuzz_coated": M(base_color=(0.2, 0.3, 0.6), specular_roughness=0.3, coat_weight=1.0, coat_roughness=0.0,
+                     fuzz_weight=0.5, fuzz_roughness=0.8),
 }
 OPAQUE = ["lambert", "metal", "metal_aniso", "plastic", "coated_delta", "coated_rough", "half_metal", "eon",
-          "eon_plastic_weak", "plastic_film"]
+          "eon_plastic_weak", "plastic_film", "fuzz_plastic", "fuzz_coated"]
 
 
 def sph(theta, phi):
@@ -329,7 +333,8 @@ def test_pdf_integrates_to_nondelta_mass(O, name):
         assert val > 0.8 * P.sum()
 
 
-@pytest.mark.parametrize("name", ["plastic", "metal_aniso", "glass_tinted", "plastic_film", "glass_film"])
+@pytest.mark.parametrize("name", ["plastic", "metal_aniso", "glass_tinted", "plastic_film", "glass_film",
+                                  "fuzz_plastic"])
 def test_sampled_directions_chi2(O, name):
     """Histogram of sampled directions over (cos theta, phi) bins against the integrated pdf."""
     mat = MATS[name]

@@ -160,7 +160,13 @@ void ofuzz_table(double rough, double E[65]) {
       for (int b = 0; b < M; ++b) {
         double phi = 2.0 * O_PI * (b + 0.5) / M;
         v3 wi = V(si * cos(phi), si * sin(phi), mi);
-        acc += ofuzz_f(alpha, wo, wi) * mi;
+        /* D V written out rather than ofuzz_f, which is zero for wo on the horizon: the entry at
+           mu = 0 is the integrand's value there (its limit), not zero */
+        v3 h = vnorm(vadd(wo, wi));
+        double s2 = 1.0 - h.z * h.z;
+        double sn = s2 > 0.0 ? sqrt(s2) : 0.0;
+        double D = (2.0 + 1.0 / alpha) * pow(sn, 1.0 / alpha) / (2.0 * O_PI);
+        acc += D / (4.0 * (wi.z + wo.z - wi.z * wo.z)) * mi;
       }
     }
     E[k] = acc * (1.0 / N) * (2.0 * O_PI / M);

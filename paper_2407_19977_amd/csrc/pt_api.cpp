@@ -117,7 +117,7 @@ struct pt_scene {
   // materials
   bool has_mats = false;
   std::vector<pt_openpbr_material> host_mats;
-  DevBuf mats;
+  DevBuf mats, fuzz_tabs;
   uint32_t class_mask = 0;
   // environment
   int env_w = 0, env_h = 0;
@@ -1086,7 +1086,7 @@ pt_status validate_material(const pt_openpbr_material& m, int i) {
   }
   const float unit[] = {m.base_weight, m.base_metalness, m.specular_weight, m.specular_roughness,
                         m.specular_roughness_anisotropy, m.transmission_weight, m.coat_weight, m.coat_roughness,
-                        m.thin_film_weight};
+                        m.thin_film_weight, m.fuzz_weight, m.fuzz_roughness};
   for (float u : unit)
     if (u > 1.0f) return fail(PT_ERR_INVALID_ARG, "material %d: weights and roughness must be in [0, 1]", i);
   if (!(m.specular_ior > 0.0f) || !(m.coat_ior > 0.0f)) return fail(PT_ERR_INVALID_ARG, "material %d: IOR must be > 0", i);
@@ -1095,6 +1095,8 @@ pt_status validate_material(const pt_openpbr_material& m, int i) {
   if (m.thin_film_ior < 1.0f) return fail(PT_ERR_INVALID_ARG, "material %d: thin_film_ior must be >= 1", i);
   if (m.coat_weight > 0.0f && m.transmission_weight > 0.0f)
     return fail(PT_ERR_UNSUPPORTED, "material %d: coat together with transmission is not supported", i);
+  if (m.fuzz_weight > 0.0f && m.transmission_weight > 0.0f)
+    return fail(PT_ERR_UNSUPPORTED, "material %d: fuzz together with transmission is not supported", i);
   return PT_OK;
 }
 
@@ -1126,6 +1128,10 @@ MatRec make_matrec(const pt_openpbr_material& m) {
     r.eon_a = (float)A;
     r.eon_b = (float)(sg * A);
   }
+  r.fuzz_w = m.fuzz_weight;
+  for (int c = 0; c < 3; ++c) r.fuzz_color[c] = m.fuzz_color[c];
+  r.fuzz_a = (float)std::max((double)m.fuzz_roughness * m.fuzz_roughness, 1e-2);
+  r.fuzz_E = nullptr;  // set by pt_upload_materials
   r.film_w = m.thin_film_weight;
   r.film_ior = m.thin_film_ior;
   r.film_d_nm = (float)(1000.0 * (double)m.thin_film_thickness);
@@ -1157,7 +1163,7 @@ MatRec make_matrec(const pt_openpbr_material& m) {
   if (!hasC && !hasM && !hasI && !hasD) cls = kClsAbsorb;
   else if (!hasC && !hasM && !hasI) cls = kClsDiffuse;
   else if (!hasC && !hasI && !hasD) cls = kClsMetal;
-  else if (m.thin_film_weight > 0.0f) cls = kClsGeneral;  // only the general class evaluates films
+  else if (m.thin_film_weight > 0.0f || m.fuzz_weight > 0.0f) cls = kClsGeneral;  // only it has films and fuzz
   else if (!hasM && !hasT) cls = kClsPlastic;
   else if (!hasC && !hasM) cls = kClsGlass;
   else cls = kClsGeneral;
@@ -1626,6 +1632,30 @@ pt_status pt_scene_copy_bvh(pt_scene* s, void* nodes, void* tris) {
   return sync(s);
 }
 
+// Directional albedo of the fuzz lobe (weight 1, colour 1) at mu = k/64,
+// k = 0..64: the midpoint rule over mu_i in [0, 1] and phi in [0, 2 pi) with
+// 256 x 256 cells of D V mu_i, wo = (sqrt(1 - mu^2), 0, mu).
+static void fuzz_albedo_table(double a, float* out) {
+  const int N = 256, Np = 256;
+  for (int k = 0; k <= 64; ++k) {
+    const double mu = k / 64.0, so = std::sqrt(1.0 - mu * mu);
+    double acc = 0.0;
+    for (int i = 0; i < N; ++i) {
+      const double mi = (i + 0.5) / N, si = std::sqrt(1.0 - mi * mi);
+      const double V = 1.0 / (4.0 * (mi + mu - mi * mu));
+      for (int j = 0; j < Np; ++j) {
+        const double ph = 2.0 * M_PI * (j + 0.5) / Np;
+        const double hx = si * std::cos(ph) + so, hy = si * std::sin(ph), hz = mi + mu;
+        const double hl = std::sqrt(hx * hx + hy * hy + hz * hz);
+        const double c = hz / hl;
+        const double sn = std::sqrt(std::max(0.0, 1.0 - c * c));
+        acc += (2.0 + 1.0 / a) * std::pow(sn, 1.0 / a) / (2.0 * M_PI) * V * mi;
+      }
+    }
+    out[k] = (float)(acc * (1.0 / N) * (2.0 * M_PI / Np));
+  }
+}
+
 pt_status pt_upload_materials(pt_scene* s, const pt_openpbr_material* m, int32_t n) {
   pt_status r = check_scene(s);
   if (r) return r;
@@ -1640,6 +1670,29 @@ pt_status pt_upload_materials(pt_scene* s, const pt_openpbr_material* m, int32_t
   }
   r = set_device(s);
   if (r) return r;
+  // fuzz albedo tables, one per distinct sheen alpha, 65 floats each
+  std::vector<float> fuzz;
+  std::vector<float> alphas;
+  std::vector<int> tab_of((size_t)n, -1);
+  for (int i = 0; i < n; ++i) {
+    if (!(recs[(size_t)i].fuzz_w > 0.0f)) continue;
+    const float a = recs[(size_t)i].fuzz_a;
+    int t = -1;
+    for (size_t q = 0; q < alphas.size(); ++q)
+      if (alphas[q] == a) t = (int)q;
+    if (t < 0) {
+      t = (int)alphas.size();
+      alphas.push_back(a);
+      fuzz.resize(fuzz.size() + 65);
+      fuzz_albedo_table((double)a, fuzz.data() + 65 * (size_t)t);
+    }
+    tab_of[(size_t)i] = t;
+  }
+  if (!fuzz.empty()) {
+    PT_HIP(upload(s->fuzz_tabs, fuzz.data(), fuzz.size() * sizeof(float), s->stream));
+    for (int i = 0; i < n; ++i)
+      if (tab_of[(size_t)i] >= 0) recs[(size_t)i].fuzz_E = s->fuzz_tabs.as<float>() + 65 * (size_t)tab_of[(size_t)i];
+  }
   PT_HIP(upload(s->mats, recs.data(), recs.size() * sizeof(MatRec), s->stream));
   PT_HIP(hipStreamSynchronize(s->stream));
   s->host_mats.assign(m, m + n);

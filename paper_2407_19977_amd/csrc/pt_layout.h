@@ -79,9 +79,12 @@ struct alignas(32) MatRec {
   float spec_rough;     float f0_diel;      // specular roughness; F_dielectric(1, eta')
   float eon_a, eon_b;   // diffuse roughness sigma as FON's A = 1/(1 + (1/2 - 2/(3 pi)) sigma), B = sigma A
   float film_w;         float film_ior;     // thin film on the dielectric interface: weight (0: none), IOR
-  float film_d_nm;      float pad[5];       // its thickness in nm
+  float film_d_nm;                          // its thickness in nm
+  float fuzz_w;         float fuzz_color[3]; float fuzz_a;  // fuzz: weight (0: none), colour, sheen alpha
+  const float* fuzz_E;  // its directional albedo at mu = k/64, k = 0..64 (device memory; null without fuzz)
+  float pad[6];
 };
-static_assert(sizeof(MatRec) == 160, "material record is 160 bytes");
+static_assert(sizeof(MatRec) == 192, "material record is 192 bytes");
 constexpr uint32_t kMatSpecDelta = 1u, kMatCoatDelta = 2u, kMatEmissive = 4u;
 
 // Instance of a mesh in the two-level hierarchy, 128 bytes.  w2o is the

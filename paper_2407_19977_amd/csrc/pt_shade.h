@@ -113,7 +113,7 @@ __host__ __device__ inline float fresnel_diel(float c, float eta) {
 // d = 2 pi (2 film_ior d_nm cos_film / lambda); unpolarised: the mean.  Total
 // internal reflection at either interface reflects everything (the film's
 // index is at least 1).
-__host__ __device__ inline float film_airy(float c1, float n2, float n3, float film_ior, float d_nm,
+__host__ __device__ inline __attribute__((noinline)) float film_airy(float c1, float n2, float n3, float film_ior, float d_nm,
                                            float inv_lambda) {
   c1 = fabsf(c1);
   const float s2 = 1.0f - c1 * c1;
@@ -213,15 +213,47 @@ struct Lobes {
   static constexpr bool D = CLS == kClsDiffuse || CLS == kClsPlastic || CLS == kClsGlass || CLS == kClsGeneral;
   static constexpr bool T = CLS == kClsGlass || CLS == kClsGeneral;
   static constexpr bool F = CLS == kClsGeneral;  // thin film (materials with one are of the general class)
+  static constexpr bool Z = CLS == kClsGeneral;  // fuzz (likewise)
 };
 
 struct Bsdf {
   float eta;  // relative IOR of the interface seen from wo
   float film_n2;  // thin film IOR relative to the medium wo is in
   bool entering;
-  float P[4];  // lobe probabilities C, M, I, D
+  float P[5];  // lobe probabilities C, M, I, D, Z (fuzz)
   bool absorbed;
 };
+
+// Fuzz (OpenPBR fuzz_*): a sheen lobe on top of the material, the "Charlie"
+// distribution (Estevez & Kulla 2017) D = (2 + 1/a) sin^(1/a)(theta_h) / (2 pi)
+// with Neubelt & Pettineo's visibility 1 / (4 (mu_i + mu_o - mu_i mu_o)); the
+// layers below are attenuated by (1 - w E(mu_i)) (1 - w E(mu_o)), E the lobe's
+// directional albedo (a table at mu = k/64, interpolated linearly, clamped to [0, 1]).
+// (not inlined, as film_airy: materials without fuzz or film never call them,
+// and inlined they raise the register count of the tail kernel, which runs
+// beside the next pass's traversal, from 224 to 232: one traversal wave per
+// SIMD fewer beside it, 5 % slower passes)
+__host__ __device__ inline __attribute__((noinline)) float fuzz_f(float a, V3 wo, V3 wi) {
+  if (wo.z <= 0.0f || wi.z <= 0.0f) return 0.0f;
+  V3 h = normalize(wo + wi);
+  const float sn = sqrtf(fmaxf(0.0f, 1.0f - h.z * h.z));
+  const float D = (2.0f + 1.0f / a) * powf(sn, 1.0f / a) * (0.5f / kPi);
+  const float V = 1.0f / (4.0f * (wi.z + wo.z - wi.z * wo.z));
+  return D * V;
+}
+
+__host__ __device__ inline float fuzz_albedo(const MatRec& m, float mu) {
+  const float t = fminf(fmaxf(mu, 0.0f), 1.0f) * 64.0f;
+  const int k = min((int)floorf(t), 63);
+  const float e = m.fuzz_E[k] + (t - (float)k) * (m.fuzz_E[k + 1] - m.fuzz_E[k]);
+  return fminf(fmaxf(e, 0.0f), 1.0f);
+}
+
+template <int CLS>
+__host__ __device__ inline float fuzz_att(const MatRec& m, float mu_i, float mu_o) {
+  if (!Lobes<CLS>::Z || !(m.fuzz_w > 0.0f)) return 1.0f;
+  return (1.0f - m.fuzz_w * fuzz_albedo(m, fabsf(mu_i))) * (1.0f - m.fuzz_w * fuzz_albedo(m, mu_o));
+}
 
 // Reflectance of the specular dielectric interface at incident cosine c: per
 // channel, and the scalar Fs that chooses lobes and reflection vs refraction
@@ -263,19 +295,29 @@ __host__ __device__ inline Bsdf bsdf_setup(const MatRec& m, bool entering, float
   }
   float w2 = L::I ? Tc * (1.0f - m.metalness) * (Fd + m.trans_weight * (1.0f - Fd)) : 0.0f;
   float w3 = L::D ? Tc * (1.0f - m.metalness) * (1.0f - m.trans_weight) * (1.0f - Fd) * m.bwbc_lum : 0.0f;
-  float sum = w0 + w1 + w2 + w3;
+  float w4 = 0.0f;
+  if (L::Z && m.fuzz_w > 0.0f) {  // the fuzz reflects w E(mu_o) and passes the rest to the layers below
+    const float fz = m.fuzz_w * fuzz_albedo(m, mu_o);
+    w0 *= 1.0f - fz;
+    w1 *= 1.0f - fz;
+    w2 *= 1.0f - fz;
+    w3 *= 1.0f - fz;
+    w4 = fz * lum(m.fuzz_color[0], m.fuzz_color[1], m.fuzz_color[2]);
+  }
+  float sum = ((w0 + w1) + (w2 + w3)) + w4;
   b.absorbed = !(sum > 0.0f);
   float inv = b.absorbed ? 0.0f : 1.0f / sum;
   b.P[0] = w0 * inv;
   b.P[1] = w1 * inv;
   b.P[2] = w2 * inv;
   b.P[3] = w3 * inv;
+  b.P[4] = w4 * inv;
   return b;
 }
 
 template <int CLS>
 __host__ __device__ inline bool bsdf_has_nondelta(const MatRec& m, const Bsdf& b) {
-  float s = b.P[3];
+  float s = b.P[3] + b.P[4];
   if (!(m.flags & kMatCoatDelta)) s += b.P[0];
   if (!(m.flags & kMatSpecDelta)) s += b.P[1] + b.P[2];
   return s > 0.0f;
@@ -370,8 +412,16 @@ __host__ __device__ inline V3 bsdf_eval(const MatRec& m, const Bsdf& b, V3 wo, V
     float fx = fc + Lc.x * (mt * fm.x + (1.0f - mt) * (fi.x + fd.x));
     float fy = fc + Lc.y * (mt * fm.y + (1.0f - mt) * (fi.y + fd.y));
     float fz = fc + Lc.z * (mt * fm.z + (1.0f - mt) * (fi.z + fd.z));
+    if (L::Z && m.fuzz_w > 0.0f) {
+      const float A = fuzz_att<CLS>(m, mu_i, mu_o);
+      const float zf = m.fuzz_w * fuzz_f(m.fuzz_a, wo, wi);
+      fx = zf * m.fuzz_color[0] + A * fx;
+      fy = zf * m.fuzz_color[1] + A * fy;
+      fz = zf * m.fuzz_color[2] + A * fz;
+    }
     f = v3(fx, fy, fz);
     pdf = b.P[0] * pc + b.P[1] * pm + b.P[2] * pi + b.P[3] * (mu_i * (1.0f / kPi));
+    if (L::Z) pdf += b.P[4] * (mu_i * (1.0f / kPi));
     return f;
   }
   if (!L::T || !spec_nd || tw <= 0.0f) return f;
@@ -435,7 +485,7 @@ __host__ __device__ inline BsdfSample bsdf_sample(const MatRec& m, const Bsdf& b
   int lobe = -1, last = -1;
   float acc = 0.0f;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < (L::Z ? 5 : 4); ++k) {
     if (b.P[k] > 0.0f) {
       last = k;
       if (lobe < 0 && u_lobe < acc + b.P[k]) lobe = k;
@@ -452,7 +502,7 @@ __host__ __device__ inline BsdfSample bsdf_sample(const MatRec& m, const Bsdf& b
     s.lobe = 0;
     if (coat_delta) {
       s.wi = v3(-wo.x, -wo.y, wo.z);
-      float w = m.coat_weight * fresnel_diel(mu_o, m.coat_ior) / b.P[0];
+      float w = fuzz_att<CLS>(m, mu_o, mu_o) * m.coat_weight * fresnel_diel(mu_o, m.coat_ior) / b.P[0];
       s.weight = v3(w, w, w);
       s.delta = true;
       s.ok = true;
@@ -468,7 +518,8 @@ __host__ __device__ inline BsdfSample bsdf_sample(const MatRec& m, const Bsdf& b
       V3 Lc = coat_layer<CLS>(m, mu_o, mu_o);
       V3 F = fresnel_f82(m, mu_o);
       float k = mt * sw / b.P[1];
-      s.weight = v3(Lc.x * F.x * k, Lc.y * F.y * k, Lc.z * F.z * k);
+      const float A = fuzz_att<CLS>(m, mu_o, mu_o);
+      s.weight = v3(A * (Lc.x * F.x * k), A * (Lc.y * F.y * k), A * (Lc.z * F.z * k));
       s.delta = true;
       s.ok = true;
       return s;
@@ -489,8 +540,9 @@ __host__ __device__ inline BsdfSample bsdf_sample(const MatRec& m, const Bsdf& b
         s.wi = v3(-wo.x, -wo.y, wo.z);
         V3 Lc = coat_layer<CLS>(m, mu_o, mu_o);
         const float q = b.P[2] * pr;
-        s.weight = v3(Lc.x * ((1.0f - mt) * Fv.x / q), Lc.y * ((1.0f - mt) * Fv.y / q),
-                      Lc.z * ((1.0f - mt) * Fv.z / q));
+        const float A = fuzz_att<CLS>(m, mu_o, mu_o);
+        s.weight = v3(A * (Lc.x * ((1.0f - mt) * Fv.x / q)), A * (Lc.y * ((1.0f - mt) * Fv.y / q)),
+                      A * (Lc.z * ((1.0f - mt) * Fv.z / q)));
         s.ok = true;
         return s;
       }
@@ -524,8 +576,8 @@ __host__ __device__ inline BsdfSample bsdf_sample(const MatRec& m, const Bsdf& b
       if (d.z >= 0.0f) return s;
       s.refract = true;
     }
-  } else if (L::D && lobe == 3) {
-    s.lobe = 4;
+  } else if ((L::D && lobe == 3) || (L::Z && lobe == 4)) {  // diffuse or fuzz: cosine-weighted
+    s.lobe = lobe == 4 ? 5 : 4;
     float r = sqrtf(u1);
     float sn, cs;
     sincosf(2.0f * kPi * u2, &sn, &cs);

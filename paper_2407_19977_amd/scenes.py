@@ -258,18 +258,25 @@ ZOO_MATERIALS = [
     ("thin film on a base without specular", dict(base_color=(0.5, 0.5, 0.5), specular_weight=0.0,
                                                   specular_roughness=0.2, thin_film_weight=1.0,
                                                   thin_film_thickness=0.5, thin_film_ior=1.5)),
+    ("fuzz over plastic", dict(base_color=(0.6, 0.2, 0.2), specular_roughness=0.4, fuzz_weight=0.8,
+                               fuzz_color=(0.9, 0.9, 1.0), fuzz_roughness=0.5)),
+    ("fuzz over a delta coat on metal", dict(base_metalness=1.0, base_color=(0.8, 0.7, 0.4), specular_roughness=0.3,
+                                             coat_weight=1.0, coat_roughness=0.0, fuzz_weight=0.5,
+                                             fuzz_color=(1.0, 0.6, 0.8), fuzz_roughness=0.9)),
+    ("fuzz over a smooth dielectric", dict(base_color=(0.2, 0.4, 0.2), specular_roughness=0.0, fuzz_weight=1.0,
+                                           fuzz_color=(0.7, 0.8, 0.6), fuzz_roughness=0.2)),
 ]
 
 
 def material_zoo(width=96, height=96, spp=8, max_depth=6, seed=0, sphere_level=2) -> Scene:
     """An open-topped box (floor, back, left and right walls, Lambert) under
     a small sky with a sun, a 0.3 x 0.3 quad light of radiance 12 hung below
-    the open top, and twelve icospheres (radius 0.1, level 2) in three
+    the open top, and fifteen icospheres (radius 0.085, level 2) in three
     rows, each with one of ZOO_MATERIALS: partial metalness, coat over metal,
     transmission over diffuse and over partial metal, tints of the
     specular, coat and transmission colours, specular_weight < 1,
-    anisotropy under a coat and thin films — the OpenPBR mixes that the
-    closed-box, icosphere-field and instanced scenes do not reach.  The back wall is a
+    anisotropy under a coat, thin films and fuzz — the OpenPBR mixes that
+    the closed-box, icosphere-field and instanced scenes do not reach.  The back wall is a
     rough diffuse (base_diffuse_roughness 0.7) and the left wall a rough
     diffuse base (0.3) under a glossy specular layer."""
     mats = [lambert((0.6, 0.6, 0.6)),
@@ -286,10 +293,10 @@ def material_zoo(width=96, height=96, spp=8, max_depth=6, seed=0, sphere_level=2
     b.add_quad([1, 0, 0], [1, 1, 0], [1, 1, 1], [1, 0, 1], [-1, 0, 0], 3)   # right
     b.add_quad([.35, .92, .45], [.65, .92, .45], [.65, .92, .75], [.35, .92, .75], [0, -1, 0], 4)
     v, f = icosphere(sphere_level)
-    rad = 0.1
+    rad = 0.085
     for k in range(len(ZOO_MATERIALS)):
-        row = k // 4
-        cx = 0.17 + 0.22 * (k % 4)
+        row = k // 5
+        cx = 0.14 + 0.18 * (k % 5)
         cz = (0.3, 0.58, 0.86)[row]
         cy = rad + (0.0, 0.13, 0.26)[row]
         b.add(v * rad + np.array([cx, cy, cz]), f, 5 + k)

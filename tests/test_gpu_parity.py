@@ -219,8 +219,9 @@ def test_material_zoo_full_frame_parity(P, O):
     """Mixed and tinted OpenPBR materials (partial metalness, coat over
     metal, transmission over diffuse and over partial metal, specular, coat
     and transmission tints, specular_weight < 1, anisotropy under a coat,
-    thin films on plastic and glass): the general shading class and every
-    tint and film branch, path by path."""
+    thin films on plastic and glass, fuzz over plastic, a delta coat and a
+    smooth dielectric): the general shading class and every tint, film and
+    fuzz branch, path by path."""
     sc, s, os_ = _zoo(P, O)
     W, H = sc.camera.width, sc.camera.height
     _say(f"[parity] material zoo {W}x{H}, 16 spp, depth 6")
@@ -420,17 +421,19 @@ def test_error_codes(P, O):
     with pytest.raises(P.PtError) as e:
         s.upload_materials(bad)
     assert e.value.status == -1
-    for kw in (dict(thin_film_weight=1.0, thin_film_ior=0.9), dict(thin_film_weight=1.5)):
+    for kw in (dict(thin_film_weight=1.0, thin_film_ior=0.9), dict(thin_film_weight=1.5), dict(fuzz_weight=1.5),
+               dict(fuzz_weight=0.5, fuzz_roughness=1.5)):
         bad = sc.materials.copy()
         bad[0] = scenes.material(**kw)  # film IOR below 1, film weight above 1
         with pytest.raises(P.PtError) as e:
             s.upload_materials(bad)
         assert e.value.status == -1
-    bad = sc.materials.copy()
-    bad[0] = scenes.material(coat_weight=1.0, transmission_weight=1.0)  # coat over transmission
-    with pytest.raises(P.PtError) as e:
-        s.upload_materials(bad)
-    assert e.value.status == -4
+    for kw in (dict(coat_weight=1.0, transmission_weight=1.0), dict(fuzz_weight=0.5, transmission_weight=1.0)):
+        bad = sc.materials.copy()
+        bad[0] = scenes.material(**kw)  # coat or fuzz over transmission
+        with pytest.raises(P.PtError) as e:
+            s.upload_materials(bad)
+        assert e.value.status == -4
     bad = sc.materials.copy()
     bad[0, 0] = -1.0
     with pytest.raises(P.PtError) as e:

@@ -156,10 +156,14 @@ pt_status pt_build_bvh_gpu(pt_scene* scene, const pt_mesh* meshes, int32_t n_mes
  * micrometres, thin_film_ior >= 1) on the dielectric interface: its
  * reflectance is the interference (Airy) sum of the film, evaluated at 650,
  * 550 and 450 nm for red, green and blue, mixed with the plain Fresnel by
- * the weight; metals ignore the film.  Errors: INVALID_ARG (n <= 0,
- * negative or non-finite parameters, IOR <= 0, thin_film_ior < 1, weights
- * or base_diffuse_roughness outside [0,1]), UNSUPPORTED (coat together with
- * transmission). */
+ * the weight; metals ignore the film.  fuzz_weight > 0 adds a sheen lobe
+ * on top of everything else (Charlie distribution, alpha = fuzz_roughness^2
+ * clamped below at 0.01, tinted by fuzz_color), which attenuates the layers
+ * below by its directional albedo; the albedo table is computed here, once
+ * per distinct alpha.  Errors: INVALID_ARG (n <= 0, negative or non-finite
+ * parameters, IOR <= 0, thin_film_ior < 1, weights, fuzz_roughness or
+ * base_diffuse_roughness outside [0,1]), UNSUPPORTED (coat or fuzz together
+ * with transmission). */
 pt_status pt_upload_materials(pt_scene* scene, const pt_openpbr_material* materials, int32_t n);
 
 /* Set the environment: an equirectangular RGB32F image [h][w][3] (y up,

@@ -525,8 +525,9 @@ def _cache_kw(args):
 
 
 def bvh_builds(pt, torch, sc_spheres, steps=2):
-    """Host binned-SAH build vs device linear-BVH build (soup in host memory -> BVH ready), and what the
-    device tree costs the traversal: the icosphere field rendered through each tree."""
+    """Host binned-SAH build vs the device builds (locally-ordered clustering, the default, and the linear
+    BVH; soup in host memory -> BVH ready), and what each tree costs the traversal: the icosphere field
+    rendered through each tree."""
     from paper_2407_19977_amd import scenes
     res = {"paper_context": "Table 1: CPU BVH set-up of 327.57 ms (Apple M1 Max) and 383.10 ms (Ryzen 5 5600X) "
                             "for 1,068,735 triangles; context only (other machines, other builder)"}
@@ -537,7 +538,7 @@ def bvh_builds(pt, torch, sc_spheres, steps=2):
         if sc is None:
             sc = scenes.instanced()
         ent = {}
-        for gpu in (False, True):
+        for gpu in (False, "ploc", "lbvh"):
             s = pt.scene_from(sc, device=0, gpu_bvh=gpu)
             if gpu:  # a second build: the first one also loads the builder's kernels
                 s.build_bvh(sc.meshes, sc.instances, on_device=True)
@@ -558,7 +559,7 @@ def bvh_builds(pt, torch, sc_spheres, steps=2):
                 dt = time.perf_counter() - t0
                 st = s.stats()
                 e["render_Mrays_per_s"] = round((st["extension_rays"] + st["shadow_rays"]) / dt / 1e6, 1)
-            ent["device" if gpu else "host"] = e
+            ent[{"ploc": "device", "lbvh": "device_lbvh"}.get(gpu, "host")] = e
             s.close()
         ent["speedup"] = round(ent["host"]["build_ms"] / ent["device"]["build_ms"], 2)
         res[name] = ent

@@ -137,10 +137,12 @@ pt_status pt_build_bvh(pt_scene* scene, const pt_mesh* meshes, int32_t n_meshes,
                        const pt_instance* instances, int32_t n_instances);
 
 /* The same acceleration structure built on the GPU instead (the paper times
- * its CPU set-up as its own stage, Sec. 5.1.1, Table 1): a linear BVH over
- * 30-bit Morton codes of the triangle centroids (radix-sorted, binary radix
- * tree built per node in parallel, boxes merged bottom-up), collapsed top-down
- * to the same 128-byte BVH4 nodes and 48-byte triangle records.  Arguments,
+ * its CPU set-up as its own stage, Sec. 5.1.1, Table 1): triangles sorted by
+ * 30-bit Morton codes of their centroids, a binary tree over them (by
+ * default locally-ordered clustering: neighbours in the sorted order whose
+ * merged box has the least surface area merge, round by round; else a linear
+ * BVH, see pt_set_gpu_bvh_builder), collapsed top-down to the same 128-byte
+ * BVH4 nodes and 48-byte triangle records.  Arguments,
  * primitive numbering and errors as pt_build_bvh; the tree differs, the
  * closest hits do not (a hit is defined by the triangle test alone).  With
  * instances each mesh's BVH is built on the GPU and the top level over the
@@ -148,6 +150,17 @@ pt_status pt_build_bvh(pt_scene* scene, const pt_mesh* meshes, int32_t n_meshes,
  * then has no BVH).  pt_scene_bvh_info reports its build time. */
 pt_status pt_build_bvh_gpu(pt_scene* scene, const pt_mesh* meshes, int32_t n_meshes,
                            const pt_instance* instances, int32_t n_instances);
+
+/* Builders of pt_build_bvh_gpu. */
+typedef enum {
+  PT_GPU_BVH_PLOC = 0, /* locally-ordered clustering (Meister & Bittner 2018): the default */
+  PT_GPU_BVH_LBVH = 1  /* linear BVH (Karras 2012): binary radix tree over the sorted codes */
+} pt_gpu_bvh_builder;
+
+/* Choose the builder of the scene's later pt_build_bvh_gpu calls (an
+ * acceleration-structure choice only: every closest hit is the same).
+ * Error: INVALID_ARG (builder not one of pt_gpu_bvh_builder). */
+pt_status pt_set_gpu_bvh_builder(pt_scene* scene, int32_t builder);
 
 /* Upload the OpenPBR materials (Sec. 4).  base_diffuse_roughness > 0 gives
  * the energy-preserving Oren-Nayar diffuse (EON); specular_weight modulates

@@ -169,6 +169,7 @@ struct pt_scene {
   // tail hand-off
   int tail_min_bounce = 2;
   double tail_fraction = 0.15;
+  int gpu_bvh_builder = kGpuBvhPloc;  // builder of pt_build_bvh_gpu
   double ms_tail = 0.0;
   int64_t launches_tail = 0;
   // display path
@@ -1351,7 +1352,7 @@ bool gpu_mesh_bvh(pt_scene* s, const float* v, const uint32_t* prim, const uint3
   GpuBvhStats st{};
   if (e == hipSuccess)
     e = gpu_build_bvh4(dsoup.as<float>(), dprim.as<uint32_t>(), dmat.as<uint32_t>(), n, dnodes.as<BVHNode>(),
-                       dtris.as<TriRec>(), s->stream, &st);
+                       dtris.as<TriRec>(), s->stream, &st, s->gpu_bvh_builder);
   if (e == hipSuccess) {
     b.nodes.resize((size_t)st.n_nodes);
     b.tris.resize((size_t)n);
@@ -1486,7 +1487,7 @@ pt_status build_bvh_any(pt_scene* s, const pt_mesh* meshes, int32_t n_meshes, co
     PT_HIP(s->tris.alloc((size_t)total * sizeof(TriRec)));
     GpuBvhStats st{};
     hipError_t e = gpu_build_bvh4(dsoup.as<float>(), dprim.as<uint32_t>(), dmat.as<uint32_t>(), total,
-                                  s->nodes.as<BVHNode>(), s->tris.as<TriRec>(), s->stream, &st);
+                                  s->nodes.as<BVHNode>(), s->tris.as<TriRec>(), s->stream, &st, s->gpu_bvh_builder);
     if (e != hipSuccess) {
       s->has_bvh = false;  // the scene's buffers were overwritten
       return fail(PT_ERR_DEVICE, "device BVH build failed: %s", hipGetErrorString(e));
@@ -2208,6 +2209,15 @@ pt_status pt_set_tail(pt_scene* s, int32_t min_bounce, double max_fraction) {
   if (!(max_fraction >= 0.0 && max_fraction <= 1.0)) return fail(PT_ERR_INVALID_ARG, "max_fraction must be in [0, 1]");
   s->tail_min_bounce = min_bounce;
   s->tail_fraction = max_fraction;
+  return PT_OK;
+}
+
+pt_status pt_set_gpu_bvh_builder(pt_scene* s, int32_t builder) {
+  pt_status r = check_scene(s);
+  if (r) return r;
+  if (builder != PT_GPU_BVH_PLOC && builder != PT_GPU_BVH_LBVH)
+    return fail(PT_ERR_INVALID_ARG, "builder must be PT_GPU_BVH_PLOC or PT_GPU_BVH_LBVH");
+  s->gpu_bvh_builder = builder == PT_GPU_BVH_PLOC ? kGpuBvhPloc : kGpuBvhLbvh;
   return PT_OK;
 }
 

@@ -1,20 +1,27 @@
 // GPU construction of the BVH4 for gfx950 (the paper builds its BVH on the
 // CPU once per scene and times that set-up separately, Sec. 5.1.1, Table 1).
 //
-// A linear BVH over the triangles' centroids (Karras 2012):
+// Two builders share the first and last steps:
 //   1. triangle boxes, and the centroid bounds by a block reduction;
 //   2. 30-bit Morton codes (10 bits per axis) of the normalised centroids;
 //   3. an LSD radix sort of (code, index): four 8-bit passes, each a tile
 //      histogram, one scan over (digit, tile) and a stable scatter that ranks
 //      equal digits with wave ballots;
-//   4. the binary radix tree over the sorted codes, every internal node in
-//      parallel (ties between equal codes broken by the index);
-//   5. node boxes bottom-up: each leaf walks towards the root and the second
-//      thread to reach a node merges its children's boxes;
-//   6. a top-down collapse to 128-byte BVH4 nodes, one launch per level: a
+//   then a binary tree over the sorted triangles, either
+//   4a. linear BVH (Karras 2012): the binary radix tree over the sorted codes,
+//      every internal node in parallel (ties between equal codes broken by
+//      the index), and node boxes bottom-up (each leaf walks towards the root
+//      and the second thread to reach a node merges its children's boxes); or
+//   4b. locally-ordered clustering (PLOC, Meister & Bittner 2018): clusters
+//      in Morton order, each finds the neighbour within kPlocRadius places
+//      whose merged box has the least surface area, mutual nearest
+//      neighbours merge into a new node, the rest are compacted in order,
+//      until one cluster is left (a greedy bottom-up SAH tree);
+//   5. a top-down collapse to 128-byte BVH4 nodes, one launch per level: a
 //      node opens its largest-area children until it has four, subtrees of at
-//      most kMaxLeafTris triangles become leaves (contiguous in sorted order);
-//   7. the 48-byte triangle records in sorted (leaf) order.
+//      most kMaxLeafTris triangles become leaves, their triangles placed in
+//      depth-first order;
+//   6. the 48-byte triangle records in that (leaf) order.
 // The result has the layout of the host builder's (root at node 0, empty
 // child slots kEmpty with zero boxes, meta[0] = child count); only the tree
 // differs.  Every closest hit is the same, since the hit is defined by the
@@ -34,6 +41,18 @@ constexpr int kItems = 8;              // keys per thread and radix pass
 constexpr int kTile = kBB * kItems;    // keys per radix tile
 constexpr uint32_t kLeafRef = 0x80000000u;  // binary-tree child reference: leaf flag
 constexpr int kMaxTreeLevels = 128;          // bound on any walk or level loop over the binary tree
+#ifndef PT_PLOC_RADIUS
+#define PT_PLOC_RADIUS 16
+#endif
+constexpr int kPlocRadius = PT_PLOC_RADIUS;  // clusters searched on either side
+constexpr int kPlocMaxRounds = 4096;         // bound on the clustering rounds
+constexpr int kPlocBatch = 8;                // rounds enqueued between two reads of the cluster count
+#ifndef PT_SAH_TRAVERSAL
+#define PT_SAH_TRAVERSAL 1.0
+#endif
+constexpr float kSahNode = (float)PT_SAH_TRAVERSAL;  // a node step, in triangle tests
+// binary-node triangle counts carry this bit when the subtree becomes one BVH4 leaf
+constexpr uint32_t kLeafBitCnt = 0x80000000u;
 
 // Float <-> order-preserving unsigned, for atomic min / max of floats.
 __device__ inline uint32_t f2ord(float f) {
@@ -199,9 +218,9 @@ __global__ __launch_bounds__(kBB) void k_radix_scatter(const uint32_t* __restric
   }
 }
 
-// 4. binary radix tree (n - 1 internal nodes).  Child references: leaf
+// 4a. binary radix tree (n - 1 internal nodes).  Child references: leaf
 // (kLeafRef | sorted index) or internal node index; parents of leaves and of
-// internal nodes (-1 for the root); the sorted range [first, last] of each node.
+// internal nodes (-1 for the root); the number of triangles under each node.
 __device__ inline int delta(const uint32_t* key, int64_t n, int64_t i, int64_t j) {
   if (j < 0 || j >= n) return -1;
   const uint32_t a = key[i], b = key[j];
@@ -211,7 +230,7 @@ __device__ inline int delta(const uint32_t* key, int64_t n, int64_t i, int64_t j
 
 __global__ __launch_bounds__(kBB) void k_radix_tree(const uint32_t* __restrict__ key, int64_t n,
                                                     uint2* __restrict__ child, int32_t* __restrict__ parent_leaf,
-                                                    int32_t* __restrict__ parent_int, uint2* __restrict__ range,
+                                                    int32_t* __restrict__ parent_int, uint32_t* __restrict__ cnt,
                                                     uint32_t* __restrict__ err) {
   for (int64_t i = blockIdx.x * (int64_t)kBB + threadIdx.x; i < n - 1; i += (int64_t)gridDim.x * kBB) {
     const int d = delta(key, n, i, i + 1) - delta(key, n, i, i - 1) >= 0 ? 1 : -1;
@@ -250,7 +269,8 @@ __global__ __launch_bounds__(kBB) void k_radix_tree(const uint32_t* __restrict__
       parent_int[gamma + 1] = (int32_t)i;
     }
     child[i] = make_uint2(cl, cr);
-    range[i] = make_uint2((uint32_t)lo, (uint32_t)hi);
+    const uint32_t c = (uint32_t)(hi - lo + 1);
+    cnt[i] = c <= (uint32_t)kMaxLeafTris ? (c | kLeafBitCnt) : c;
   }
 }
 
@@ -260,7 +280,7 @@ __device__ inline void ref_box(uint32_t ref, const uint32_t* val, const float* t
   for (int k = 0; k < 6; ++k) b[k] = src[k];
 }
 
-// 5. boxes bottom-up: the second arrival at a node merges both children's boxes
+// boxes bottom-up: the second arrival at a node merges both children's boxes
 __global__ __launch_bounds__(kBB) void k_boxes_up(int64_t n, const uint32_t* __restrict__ val,
                                                   const float* __restrict__ tbox, const uint2* __restrict__ child,
                                                   const int32_t* __restrict__ parent_leaf,
@@ -286,14 +306,13 @@ __global__ __launch_bounds__(kBB) void k_boxes_up(int64_t n, const uint32_t* __r
   }
 }
 
-__device__ inline uint32_t ref_count(uint32_t ref, const uint2* range) {
-  if (ref & kLeafRef) return 1u;
-  const uint2 r = range[ref];
-  return r.y - r.x + 1u;
+__device__ inline uint32_t ref_count(uint32_t ref, const uint32_t* cnt) {
+  return (ref & kLeafRef) ? 1u : (cnt[ref] & ~kLeafBitCnt);
 }
 
-__device__ inline uint32_t ref_first(uint32_t ref, const uint2* range) {
-  return (ref & kLeafRef) ? (ref & ~kLeafRef) : range[ref].x;
+// the subtree of `ref` becomes one BVH4 leaf
+__device__ inline bool ref_is_leaf_subtree(uint32_t ref, const uint32_t* cnt) {
+  return (ref & kLeafRef) || (cnt[ref] & kLeafBitCnt);
 }
 
 __device__ inline float half_area(const float b[6]) {
@@ -301,20 +320,203 @@ __device__ inline float half_area(const float b[6]) {
   return dx * dy + dy * dz + dz * dx;
 }
 
-// 6. one level of the collapse: job (binary reference, BVH4 node index)
-__global__ __launch_bounds__(kBB) void k_collapse(const uint2* __restrict__ jobs, uint32_t n_jobs,
-                                                  uint2* __restrict__ next_jobs, uint32_t* __restrict__ n_next,
+// ---- 4b. locally-ordered clustering.  Cluster i of a round: a binary-tree
+// reference cid[i] and its box cbox[i][6]; m clusters in Morton order.
+
+__global__ __launch_bounds__(kBB) void k_ploc_init(const uint32_t* __restrict__ val, const float* __restrict__ tbox,
+                                                   int64_t n, uint32_t* __restrict__ cid, float* __restrict__ cbox) {
+  for (int64_t i = blockIdx.x * (int64_t)kBB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBB) {
+    cid[i] = kLeafRef | (uint32_t)i;
+    const float* b = tbox + 6 * (size_t)val[i];
+    for (int k = 0; k < 6; ++k) cbox[6 * i + k] = b[k];
+  }
+}
+
+// Nearest neighbour of every cluster: the least surface area of the merged
+// box; among equal areas the nearer place, then an even lower index of the
+// pair, then the lower index (one rank per pair, so mutual nearest neighbours
+// always exist, and equal boxes pair up as (2k, 2k + 1)).  With `forced` the
+// neighbour is the adjacent cluster of the pair (2k, 2k + 1) outright (a
+// round after one that merged too few).  One block per kBB clusters, whose
+// boxes and their neighbours' are staged in LDS; grid >= ceil(m / kBB).  The
+// round's cluster count is mc[0] (set by the round before), and that round's
+// own count mc[1]: a round that kept over 99 % pairs neighbours outright.
+__global__ __launch_bounds__(kBB) void k_ploc_nn(const float* __restrict__ cbox, const uint32_t* __restrict__ mc,
+                                                 int32_t* __restrict__ nn) {
+  constexpr int kSpan = kBB + 2 * kPlocRadius;
+  __shared__ float sb[kSpan * 6];
+  const uint32_t m = mc[0];
+  const bool forced = (uint64_t)m * 100u > (uint64_t)mc[1] * 99u;
+  const int64_t b0 = (int64_t)blockIdx.x * kBB, s0 = b0 - kPlocRadius;
+  if (b0 >= (int64_t)m) return;
+  for (int t = threadIdx.x; t < kSpan * 6; t += kBB) {
+    const int64_t g = s0 * 6 + t;  // float index of the staged window
+    sb[t] = (g >= 0 && g < (int64_t)m * 6) ? cbox[g] : 0.0f;
+  }
+  __syncthreads();
+  const int64_t i = b0 + threadIdx.x;
+  if (i >= (int64_t)m) return;
+  if (forced) {
+    const int64_t j = i ^ 1;
+    nn[i] = (int32_t)(j < (int64_t)m ? j : i);
+    return;
+  }
+  const float* bi = sb + 6 * (threadIdx.x + kPlocRadius);
+  float best = INFINITY;
+  uint32_t bd = 0xFFFFFFFFu, blo = 0xFFFFFFFFu;
+  int32_t bj = (int32_t)i;
+  for (int d = -kPlocRadius; d <= kPlocRadius; ++d) {
+    const int64_t j = i + d;
+    if (d == 0 || j < 0 || j >= (int64_t)m) continue;
+    const float* bb = sb + 6 * (threadIdx.x + kPlocRadius + d);
+    float u[6];
+    for (int k = 0; k < 3; ++k) {
+      u[k] = fminf(bi[k], bb[k]);
+      u[3 + k] = fmaxf(bi[3 + k], bb[3 + k]);
+    }
+    const float a = half_area(u);
+    const uint32_t ad = (uint32_t)(d < 0 ? -d : d), lo = (uint32_t)(d < 0 ? j : i);
+    const bool better =
+        a < best || (a == best && (ad < bd || (ad == bd && ((lo & 1u) < (blo & 1u) ||
+                                                            ((lo & 1u) == (blo & 1u) && lo < blo)))));
+    if (better) {
+      best = a;
+      bd = ad;
+      blo = lo;
+      bj = (int32_t)j;
+    }
+  }
+  nn[i] = bj;
+}
+
+// Mutual nearest neighbours i < j merge: a new node (children cid[i], cid[j])
+// takes place i; place j is dropped (keep[j] = 0).  Only thread i reads place
+// j and writes place i, so the update is in place.  The new node's SAH cost
+// (surface area x (kSahNode + the children's costs), a single triangle costing
+// its area) decides whether its subtree becomes one BVH4 leaf: when it holds
+// at most kMaxLeafTris triangles and testing them all costs no more.
+__global__ __launch_bounds__(kBB) void k_ploc_merge(uint32_t* __restrict__ cid, float* __restrict__ cbox,
+                                                    const uint32_t* __restrict__ mc, const int32_t* __restrict__ nn,
+                                                    uint2* __restrict__ child, float* __restrict__ nbox,
+                                                    uint32_t* __restrict__ cnt, float* __restrict__ ncost,
+                                                    uint32_t* __restrict__ n_int, uint32_t cap,
+                                                    uint32_t* __restrict__ keep, uint32_t* __restrict__ err) {
+  const uint32_t m = mc[0];
+  for (int64_t i = blockIdx.x * (int64_t)kBB + threadIdx.x; i < (int64_t)m; i += (int64_t)gridDim.x * kBB) {
+    const int32_t j = nn[i];
+    const bool mutual = j != (int32_t)i && j >= 0 && j < (int32_t)m && nn[j] == (int32_t)i;
+    if (mutual && j < (int32_t)i) {
+      keep[i] = 0u;
+      continue;
+    }
+    keep[i] = 1u;
+    if (!mutual) continue;
+    const uint32_t o = atomicAdd(n_int, 1u);
+    if (o >= cap) {  // more merges than a binary tree of this size has nodes: report
+      atomicOr(err, 4u);
+      continue;
+    }
+    const uint32_t a = cid[i], b = cid[j];
+    float u[6], ba[6], bb[6];
+    for (int k = 0; k < 6; ++k) {
+      ba[k] = cbox[6 * i + k];
+      bb[k] = cbox[6 * (size_t)j + k];
+    }
+    for (int k = 0; k < 3; ++k) {
+      u[k] = fminf(ba[k], bb[k]);
+      u[3 + k] = fmaxf(ba[3 + k], bb[3 + k]);
+    }
+    for (int k = 0; k < 6; ++k) {
+      nbox[6 * (size_t)o + k] = u[k];
+      cbox[6 * i + k] = u[k];
+    }
+    const uint32_t c = ref_count(a, cnt) + ref_count(b, cnt);
+    const float area = half_area(u);
+    const float ca = (a & kLeafRef) ? half_area(ba) : ncost[a], cb = (b & kLeafRef) ? half_area(bb) : ncost[b];
+    const float split = kSahNode * area + ca + cb, leaf = (float)c * area;
+    const bool as_leaf = c <= (uint32_t)kMaxLeafTris && leaf <= split;
+    ncost[o] = as_leaf ? leaf : split;
+    child[o] = make_uint2(a, b);
+    cnt[o] = as_leaf ? (c | kLeafBitCnt) : c;
+    cid[i] = o;
+  }
+}
+
+// Kept clusters per block of kBB places (every block of the grid writes its count).
+__global__ __launch_bounds__(kBB) void k_ploc_count(const uint32_t* __restrict__ keep, const uint32_t* __restrict__ mc,
+                                                    uint32_t* __restrict__ bc) {
+  __shared__ uint32_t w[kBB / 64];
+  const uint32_t m = mc[0];
+  const int64_t i = (int64_t)blockIdx.x * kBB + threadIdx.x;
+  const uint64_t bal = __ballot(i < (int64_t)m && keep[i] != 0u);
+  if (threadIdx.x % 64 == 0) w[threadIdx.x / 64] = (uint32_t)__popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int k = 0; k < kBB / 64; ++k) t += w[k];
+    bc[blockIdx.x] = t;
+  }
+}
+
+// Kept clusters to their places in the next round's arrays, in order (off:
+// exclusive scan of the block counts); the last block writes the new count
+// to mc_out[0] and this round's to mc_out[1] (the next round's mc).
+__global__ __launch_bounds__(kBB) void k_ploc_scatter(const uint32_t* __restrict__ cid, const float* __restrict__ cbox,
+                                                      const uint32_t* __restrict__ keep, const uint32_t* __restrict__ mc,
+                                                      const uint32_t* __restrict__ off, uint32_t* __restrict__ cid2,
+                                                      float* __restrict__ cbox2, uint32_t* __restrict__ mc_out) {
+  __shared__ uint32_t w[kBB / 64];
+  const uint32_t m = mc[0];
+  const int64_t i = (int64_t)blockIdx.x * kBB + threadIdx.x;
+  const bool k = i < (int64_t)m && keep[i] != 0u;
+  const uint64_t bal = __ballot(k);
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane == 0) w[wave] = (uint32_t)__popcll(bal);
+  __syncthreads();
+  uint32_t pos = off[blockIdx.x];
+  for (int q = 0; q < wave; ++q) pos += w[q];
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  pos += (uint32_t)__popcll(bal & lt);
+  if (k) {
+    cid2[pos] = cid[i];
+    for (int q = 0; q < 6; ++q) cbox2[6 * (size_t)pos + q] = cbox[6 * i + q];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    uint32_t t = off[blockIdx.x];
+    for (int q = 0; q < kBB / 64; ++q) t += w[q];
+    mc_out[0] = t;
+    mc_out[1] = m;
+  }
+}
+
+// The collapse's first job: the last cluster (the root) at BVH4 node 0, first triangle 0.
+__global__ void k_root_job(const uint32_t* __restrict__ cid, uint4* __restrict__ jobs) {
+  jobs[0] = make_uint4(cid[0], 0u, 0u, 0u);
+}
+
+// Cluster counts of the first round: n clusters, and no round before it.
+__global__ void k_ploc_start(uint32_t* __restrict__ mc, uint32_t n) {
+  mc[0] = n;
+  mc[1] = 0xFFFFFFFFu;
+}
+
+// 5. one level of the collapse: job (binary reference, BVH4 node index, place
+// of its first triangle in leaf order).  A leaf's triangles take consecutive
+// places in depth-first order of its subtree: order[place] = sorted index.
+__global__ __launch_bounds__(kBB) void k_collapse(const uint4* __restrict__ jobs, uint32_t n_jobs,
+                                                  uint4* __restrict__ next_jobs, uint32_t* __restrict__ n_next,
                                                   uint32_t* __restrict__ n_nodes, uint32_t* __restrict__ max_leaf,
                                                   const uint32_t* __restrict__ val, const float* __restrict__ tbox,
                                                   const float* __restrict__ nbox, const uint2* __restrict__ child,
-                                                  const uint2* __restrict__ range, BVHNode* __restrict__ out,
-                                                  uint32_t cap, uint32_t* __restrict__ err) {
+                                                  const uint32_t* __restrict__ cnt, BVHNode* __restrict__ out,
+                                                  uint32_t cap, uint32_t n_tris, uint32_t* __restrict__ order,
+                                                  uint32_t* __restrict__ err) {
   const uint32_t j = blockIdx.x * kBB + threadIdx.x;
   if (j >= n_jobs) return;
-  const uint2 job = jobs[j];
+  const uint4 job = jobs[j];
   uint32_t kids[4];
   int nk = 0;
-  if ((job.x & kLeafRef) || ref_count(job.x, range) <= (uint32_t)kMaxLeafTris) {
+  if (ref_is_leaf_subtree(job.x, cnt)) {
     kids[nk++] = job.x;  // the whole tree is one leaf under a one-child root
   } else {
     const uint2 c = child[job.x];
@@ -324,7 +526,7 @@ __global__ __launch_bounds__(kBB) void k_collapse(const uint2* __restrict__ jobs
       int pick = -1;
       float pa = -1.0f;
       for (int q = 0; q < nk; ++q) {
-        if (ref_count(kids[q], range) > (uint32_t)kMaxLeafTris) {
+        if (!ref_is_leaf_subtree(kids[q], cnt)) {
           float b[6];
           ref_box(kids[q], val, tbox, nbox, b);
           const float a = half_area(b);
@@ -349,7 +551,15 @@ __global__ __launch_bounds__(kBB) void k_collapse(const uint2* __restrict__ jobs
     node.meta[q] = 0u;
   }
   node.meta[0] = (uint32_t)nk;
-  uint32_t leaf_max = 0;
+  uint32_t leaf_max = 0, place = job.z;
+  // the node's inner children take consecutive node indices (siblings share lines of the cache)
+  int n_inner = 0;
+  for (int q = 0; q < nk; ++q) n_inner += ref_is_leaf_subtree(kids[q], cnt) ? 0 : 1;
+  uint32_t o_next = 0, slot_next = 0;
+  if (n_inner) {
+    o_next = atomicAdd(n_nodes, (uint32_t)n_inner);
+    slot_next = atomicAdd(n_next, (uint32_t)n_inner);
+  }
   for (int q = 0; q < nk; ++q) {
     float b[6];
     ref_box(kids[q], val, tbox, nbox, b);
@@ -359,31 +569,57 @@ __global__ __launch_bounds__(kBB) void k_collapse(const uint2* __restrict__ jobs
     node.hi_x[q] = b[3];
     node.hi_y[q] = b[4];
     node.hi_z[q] = b[5];
-    const uint32_t cnt = ref_count(kids[q], range);
-    if (cnt <= (uint32_t)kMaxLeafTris) {
-      node.child[q] = make_leaf(ref_first(kids[q], range), cnt);
-      leaf_max = cnt > leaf_max ? cnt : leaf_max;
+    const uint32_t c = ref_count(kids[q], cnt);
+    if (place + c > n_tris) {  // counts that do not add up: report
+      atomicOr(err, 8u);
+      break;
+    }
+    if (ref_is_leaf_subtree(kids[q], cnt)) {
+      node.child[q] = make_leaf(place, c);
+      leaf_max = c > leaf_max ? c : leaf_max;
+      // the subtree's leaves, left before right (at most kMaxLeafTris of them,
+      // so the stack never holds more than that many entries)
+      uint32_t stk[kMaxLeafTris];
+      int sp = 0;
+      uint32_t w = place;
+      stk[sp++] = kids[q];
+      while (sp > 0) {
+        const uint32_t r = stk[--sp];
+        if (r & kLeafRef) {
+          if (w < place + c) order[w] = r & ~kLeafRef;
+          w++;
+        } else if (sp + 2 <= kMaxLeafTris) {
+          const uint2 cc = child[r];
+          stk[sp++] = cc.y;
+          stk[sp++] = cc.x;
+        } else {
+          atomicOr(err, 8u);
+          break;
+        }
+      }
+      if (w != place + c) atomicOr(err, 8u);
     } else {
-      const uint32_t o = atomicAdd(n_nodes, 1u);
-      const uint32_t slot = atomicAdd(n_next, 1u);
+      const uint32_t o = o_next++, slot = slot_next++;
       if (o >= cap || slot >= cap) {  // more nodes than a tree of this size can have: report
         atomicOr(err, 2u);
         continue;
       }
       node.child[q] = o;
-      next_jobs[slot] = make_uint2(kids[q], o);
+      next_jobs[slot] = make_uint4(kids[q], o, place, 0u);
     }
+    place += c;
   }
   if (job.y < cap) out[job.y] = node;
   if (leaf_max) atomicMax(max_leaf, leaf_max);
 }
 
-// 7. triangle records in sorted order
+// 6. triangle records in leaf order
 __global__ __launch_bounds__(kBB) void k_sorted_tris(const float* __restrict__ soup, const uint32_t* __restrict__ prim,
                                                      const uint32_t* __restrict__ mat, const uint32_t* __restrict__ val,
-                                                     int64_t n, TriRec* __restrict__ tris) {
+                                                     const uint32_t* __restrict__ order, int64_t n,
+                                                     TriRec* __restrict__ tris) {
   for (int64_t i = blockIdx.x * (int64_t)kBB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBB) {
-    const uint32_t t = val[i];
+    const uint32_t t = val[order[i]];
     const float* p = soup + 9 * (size_t)t;
     TriRec r;
     r.a = make_float4(p[0], p[1], p[2], __uint_as_float(prim[t]));
@@ -420,14 +656,15 @@ struct Scratch {
   } while (0)
 
 hipError_t gpu_build_bvh4(const float* soup, const uint32_t* prim, const uint32_t* mat, int64_t n, BVHNode* nodes,
-                          TriRec* tris, hipStream_t st, GpuBvhStats* stats) {
+                          TriRec* tris, hipStream_t st, GpuBvhStats* stats, int builder) {
   if (n <= 0 || n >= (int64_t)kLeafFirstMask) return hipErrorInvalidValue;
+  if (builder != kGpuBvhPloc && builder != kGpuBvhLbvh) return hipErrorInvalidValue;
   Scratch S;
   float *tbox = nullptr, *nbox = nullptr;
   uint32_t *cb = nullptr, *keyA = nullptr, *valA = nullptr, *keyB = nullptr, *valB = nullptr, *hist = nullptr;
-  uint32_t *flag = nullptr, *counters = nullptr;
-  uint2 *child = nullptr, *range = nullptr, *jobs[2] = {nullptr, nullptr};
-  int32_t *parent_leaf = nullptr, *parent_int = nullptr;
+  uint32_t *counters = nullptr, *cnt = nullptr, *order = nullptr;
+  uint2* child = nullptr;
+  uint4* jobs[2] = {nullptr, nullptr};
   const int nb = (int)((n + kTile - 1) / kTile);
   const int64_t ni = std::max<int64_t>(1, n - 1);
   PT_TRY(S.get(&tbox, (size_t)n * 6));
@@ -438,12 +675,12 @@ hipError_t gpu_build_bvh4(const float* soup, const uint32_t* prim, const uint32_
   PT_TRY(S.get(&keyB, (size_t)n));
   PT_TRY(S.get(&valB, (size_t)n));
   PT_TRY(S.get(&hist, (size_t)256 * nb));
-  PT_TRY(S.get(&flag, (size_t)ni));
-  PT_TRY(S.get(&counters, 4));  // [0] BVH4 nodes, [1] jobs of the next level, [2] largest leaf, [3] error bits
+  // [0] BVH4 nodes, [1] jobs of the next level, [2] largest leaf, [3] error bits, [4] binary nodes,
+  // [5] clusters after a round
+  PT_TRY(S.get(&counters, 8));
   PT_TRY(S.get(&child, (size_t)ni));
-  PT_TRY(S.get(&range, (size_t)ni));
-  PT_TRY(S.get(&parent_leaf, (size_t)n));
-  PT_TRY(S.get(&parent_int, (size_t)ni));
+  PT_TRY(S.get(&cnt, (size_t)ni));
+  PT_TRY(S.get(&order, (size_t)n));
   PT_TRY(S.get(&jobs[0], (size_t)n));
   PT_TRY(S.get(&jobs[1], (size_t)n));
 
@@ -458,30 +695,81 @@ hipError_t gpu_build_bvh4(const float* soup, const uint32_t* prim, const uint32_
     std::swap(keyA, keyB);
     std::swap(valA, valB);
   }
-  PT_TRY(hipMemsetAsync(flag, 0, (size_t)ni * sizeof(uint32_t), st));
-  PT_TRY(hipMemsetAsync(counters, 0, 4 * sizeof(uint32_t), st));
-  if (n > 1) {
+  PT_TRY(hipMemsetAsync(counters, 0, 8 * sizeof(uint32_t), st));
+  if (n > 1 && builder == kGpuBvhLbvh) {
+    uint32_t* flag = nullptr;
+    int32_t *parent_leaf = nullptr, *parent_int = nullptr;
+    PT_TRY(S.get(&flag, (size_t)ni));
+    PT_TRY(S.get(&parent_leaf, (size_t)n));
+    PT_TRY(S.get(&parent_int, (size_t)ni));
+    PT_TRY(hipMemsetAsync(flag, 0, (size_t)ni * sizeof(uint32_t), st));
     PT_TRY(hipMemsetAsync(parent_int, 0xFF, (size_t)ni * sizeof(int32_t), st));  // root: -1
     hipLaunchKernelGGL(k_radix_tree, dim3(grid_of(n - 1)), dim3(kBB), 0, st, keyA, n, child, parent_leaf, parent_int,
-                       range, counters + 3);
+                       cnt, counters + 3);
     hipLaunchKernelGGL(k_boxes_up, dim3(grid_of(n)), dim3(kBB), 0, st, n, valA, tbox, child, parent_leaf, parent_int,
                        nbox, flag);
+    const uint4 root = make_uint4(0u, 0u, 0u, 0u);
+    PT_TRY(hipMemcpyAsync(jobs[0], &root, sizeof(root), hipMemcpyHostToDevice, st));
+  } else if (n > 1) {
+    uint32_t *cid[2] = {nullptr, nullptr}, *keep = nullptr, *bc = nullptr, *mc = nullptr;
+    float* cbox[2] = {nullptr, nullptr};
+    float* ncost = nullptr;
+    int32_t* nn = nullptr;
+    const int64_t nblk = (n + kBB - 1) / kBB;
+    for (int k = 0; k < 2; ++k) {
+      PT_TRY(S.get(&cid[k], (size_t)n));
+      PT_TRY(S.get(&cbox[k], (size_t)n * 6));
+    }
+    PT_TRY(S.get(&keep, (size_t)n));
+    PT_TRY(S.get(&bc, (size_t)nblk));
+    PT_TRY(S.get(&nn, (size_t)n));
+    PT_TRY(S.get(&ncost, (size_t)ni));
+    PT_TRY(S.get(&mc, 4));  // cluster counts: [0..1] read by even rounds, [2..3] by odd rounds
+    hipLaunchKernelGGL(k_ploc_init, dim3(grid_of(n)), dim3(kBB), 0, st, valA, tbox, n, cid[0], cbox[0]);
+    hipLaunchKernelGGL(k_ploc_start, dim3(1), dim3(1), 0, st, mc, (uint32_t)n);
+    // the counts stay on the device; the host reads them once per batch of rounds and sizes the
+    // batch's grids by the count at its start (kernels skip the places past the current count; a
+    // round with one cluster left copies it unchanged)
+    uint32_t m = (uint32_t)n, m_host[2] = {0u, 0u};
+    int cur = 0, rounds = 0;
+    while (m > 1) {
+      if (rounds >= kPlocMaxRounds) return hipErrorUnknown;
+      const int blocks = (int)((m + kBB - 1) / kBB);
+      for (int r = 0; r < kPlocBatch; ++r, ++rounds) {
+        const uint32_t* mc_in = mc + 2 * (rounds & 1);
+        uint32_t* mc_out = mc + 2 * ((rounds & 1) ^ 1);
+        hipLaunchKernelGGL(k_ploc_nn, dim3(blocks), dim3(kBB), 0, st, cbox[cur], mc_in, nn);
+        hipLaunchKernelGGL(k_ploc_merge, dim3(grid_of(m)), dim3(kBB), 0, st, cid[cur], cbox[cur], mc_in, nn, child,
+                           nbox, cnt, ncost, counters + 4, (uint32_t)ni, keep, counters + 3);
+        hipLaunchKernelGGL(k_ploc_count, dim3(blocks), dim3(kBB), 0, st, keep, mc_in, bc);
+        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, bc, (int64_t)blocks);
+        hipLaunchKernelGGL(k_ploc_scatter, dim3(blocks), dim3(kBB), 0, st, cid[cur], cbox[cur], keep, mc_in, bc,
+                           cid[cur ^ 1], cbox[cur ^ 1], mc_out);
+        cur ^= 1;
+      }
+      PT_TRY(hipGetLastError());
+      PT_TRY(hipMemcpyAsync(m_host, mc + 2 * (rounds & 1), sizeof(m_host), hipMemcpyDeviceToHost, st));
+      PT_TRY(hipStreamSynchronize(st));
+      if (m_host[0] == 0u || m_host[0] > m) return hipErrorUnknown;  // a round never loses every cluster
+      m = m_host[0];
+    }
+    hipLaunchKernelGGL(k_root_job, dim3(1), dim3(1), 0, st, cid[cur], jobs[0]);
+  } else {
+    const uint4 root = make_uint4(kLeafRef, 0u, 0u, 0u);
+    PT_TRY(hipMemcpyAsync(jobs[0], &root, sizeof(root), hipMemcpyHostToDevice, st));
   }
-  hipLaunchKernelGGL(k_sorted_tris, dim3(grid_of(n)), dim3(kBB), 0, st, soup, prim, mat, valA, n, tris);
-  // collapse, level by level, from the root (internal node 0, or the only leaf)
+  // collapse, level by level, from the root
   const uint32_t cap = (uint32_t)ni;  // nodes of the output (and jobs of a level) at most
-  const uint32_t init[3] = {1u, 0u, 0u};
-  const uint2 root = make_uint2(n > 1 ? 0u : kLeafRef, 0u);
-  PT_TRY(hipMemcpyAsync(counters, init, sizeof(init), hipMemcpyHostToDevice, st));
-  PT_TRY(hipMemcpyAsync(jobs[0], &root, sizeof(root), hipMemcpyHostToDevice, st));
+  const uint32_t one = 1u;
+  PT_TRY(hipMemcpyAsync(counters, &one, sizeof(one), hipMemcpyHostToDevice, st));
   uint32_t n_jobs = 1;
   int levels = 0, cur = 0;
   while (n_jobs > 0) {
     if (levels >= kMaxTreeLevels) return hipErrorUnknown;
     PT_TRY(hipMemsetAsync(counters + 1, 0, sizeof(uint32_t), st));
     hipLaunchKernelGGL(k_collapse, dim3((n_jobs + kBB - 1) / kBB), dim3(kBB), 0, st, jobs[cur], n_jobs, jobs[cur ^ 1],
-                       counters + 1, counters, counters + 2, valA, tbox, nbox, child, range, nodes, cap,
-                       counters + 3);
+                       counters + 1, counters, counters + 2, valA, tbox, nbox, child, cnt, nodes, cap, (uint32_t)n,
+                       order, counters + 3);
     PT_TRY(hipGetLastError());
     PT_TRY(hipMemcpyAsync(&n_jobs, counters + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     PT_TRY(hipStreamSynchronize(st));
@@ -489,6 +777,7 @@ hipError_t gpu_build_bvh4(const float* soup, const uint32_t* prim, const uint32_
     cur ^= 1;
     levels++;
   }
+  hipLaunchKernelGGL(k_sorted_tris, dim3(grid_of(n)), dim3(kBB), 0, st, soup, prim, mat, valA, order, n, tris);
   uint32_t fin[4];
   PT_TRY(hipMemcpyAsync(fin, counters, sizeof(fin), hipMemcpyDeviceToHost, st));
   PT_TRY(hipStreamSynchronize(st));

@@ -205,8 +205,10 @@ struct GpuBvhStats {
 };
 // soup [n][9] floats, prim / mat [n] (device); nodes (device, room for max(1, n - 1) nodes; node 0 is
 // the root) and tris (device, [n], leaf order) are written; synchronises the stream.
+// builder: kGpuBvhPloc (locally-ordered clustering) or kGpuBvhLbvh (linear BVH)
+constexpr int kGpuBvhPloc = 0, kGpuBvhLbvh = 1;
 hipError_t gpu_build_bvh4(const float* soup, const uint32_t* prim, const uint32_t* mat, int64_t n, BVHNode* nodes,
-                          TriRec* tris, hipStream_t st, GpuBvhStats* stats);
+                          TriRec* tris, hipStream_t st, GpuBvhStats* stats, int builder);
 
 // ---- radiance cache (pt_nrc.hip) ----
 // t_step / n_records (nullable): count the applied Adam step on the device unless the batch had no records

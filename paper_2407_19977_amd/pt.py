@@ -101,6 +101,7 @@ _SIGS = {
     "pt_trace_closest_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32]),
     "pt_display": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
     "pt_build_bvh_gpu": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
+    "pt_set_gpu_bvh_builder": (C.c_int, [C.c_void_p, C.c_int32]),
     "pt_scene_bvh_info": (C.c_int, [C.c_void_p, C.POINTER(pt_bvh_info)]),
     "pt_scene_copy_bvh": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pt_set_accumulation": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int64]),
@@ -219,6 +220,10 @@ class PtScene:
         build = _lib.pt_build_bvh_gpu if on_device else _lib.pt_build_bvh
         _check(build(self.h, arr, len(meshes), ia, ni))
 
+    def set_gpu_bvh_builder(self, builder: str):
+        """Builder of later build_bvh(on_device=True) calls: "ploc" (default) or "lbvh"."""
+        _check(_lib.pt_set_gpu_bvh_builder(self.h, {"ploc": 0, "lbvh": 1}.get(builder, -1)))
+
     def bvh_info(self) -> dict:
         info = pt_bvh_info()
         _check(_lib.pt_scene_bvh_info(self.h, C.byref(info)))
@@ -336,11 +341,14 @@ class PtScene:
         _check(_lib.pt_set_profiling(self.h, 1 if timing else 0, 1 if counting else 0))
 
 
-def scene_from(scene, device: int = 0, stream=None, gpu_bvh: bool = False) -> PtScene:
+def scene_from(scene, device: int = 0, stream=None, gpu_bvh=False) -> PtScene:
     """Upload a scenes.Scene (geometry, materials, environment) to a new PtScene
-    (BVH built on the host, or on the GPU with gpu_bvh)."""
+    (BVH built on the host, or on the GPU with gpu_bvh: True or "ploc" for the
+    default device builder, "lbvh" for the linear BVH)."""
     s = PtScene(device, stream)
-    s.build_bvh(scene.meshes, scene.instances, on_device=gpu_bvh)
+    if isinstance(gpu_bvh, str):
+        s.set_gpu_bvh_builder(gpu_bvh)
+    s.build_bvh(scene.meshes, scene.instances, on_device=bool(gpu_bvh))
     s.upload_materials(scene.materials)
     s.set_environment(scene.env)
     return s

@@ -2,7 +2,8 @@
 own, Sec. 5.1.1, Table 1) against the host builder and the definition of the
 closest hit, through the C ABI.
 
-Any valid tree is acceptable: what must hold is (a) the BVH4 invariants
+Both device builders (locally-ordered clustering, the default, and the
+linear BVH) are checked.  Any valid tree is acceptable: what must hold is (a) the BVH4 invariants
 (leaves partition the triangles, at most 4 per leaf, every child box inside
 its parent's box of it, the reported depth), (b) closest hits bit-exact
 against brute force and against the host-built tree on the same rays, and
@@ -94,15 +95,19 @@ CASES = {
 }
 
 
+BUILDERS = ["ploc", "lbvh"]
+
+
+@pytest.mark.parametrize("builder", BUILDERS)
 @pytest.mark.parametrize("which", list(CASES))
-def test_gpu_bvh_valid_and_hits_bit_exact(P, which):
+def test_gpu_bvh_valid_and_hits_bit_exact(P, which, builder):
     make, lo, hi, spread = CASES[which]
     sc = make()
-    s_gpu = P.scene_from(sc, device=0, gpu_bvh=True)
+    s_gpu = P.scene_from(sc, device=0, gpu_bvh=builder)
     s_cpu = P.scene_from(sc, device=0)
     try:
         gi, ci = s_gpu.bvh_info(), s_cpu.bvh_info()
-        _say(f"[gpu bvh] {which}: {gi['n_tris']} triangles, device build {gi['build_ms']:.1f} ms "
+        _say(f"[gpu bvh] {which} ({builder}): {gi['n_tris']} triangles, device build {gi['build_ms']:.1f} ms "
              f"({gi['n_nodes']} nodes, depth {gi['depth']}), host build {ci['build_ms']:.1f} ms "
              f"({ci['n_nodes']} nodes, depth {ci['depth']})")
         assert gi["n_tris"] == ci["n_tris"] and gi["max_leaf_tris"] <= 4
@@ -157,19 +162,21 @@ def test_gpu_bvh_render_equals_host_bvh_render(P):
     """Same hits, same shading, same FP64 sums: the images are bitwise equal."""
     sc = scenes.material_zoo(width=64, height=64)
     outs = []
-    for gpu in (False, True):
+    for gpu in (False, "ploc", "lbvh"):
         s = P.scene_from(sc, device=0, gpu_bvh=gpu)
         out = torch.empty((64, 64, 3), dtype=torch.float32, device="cuda:0")
         s.render(sc.camera, 8, 6, 0, out)
         outs.append(out.cpu().numpy())
         s.close()
-    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
+@pytest.mark.parametrize("builder", BUILDERS)
 @pytest.mark.parametrize("n_tris", [1, 2, 4, 5, 17, 1000])
-def test_gpu_bvh_small_and_degenerate_meshes(P, n_tris):
+def test_gpu_bvh_small_and_degenerate_meshes(P, n_tris, builder):
     """Few triangles (a one-leaf root up to 4), and all centroids in one Morton
-    cell (equal codes, ties broken by the index)."""
+    cell (equal codes, ties broken by the index; for the clustering, equal
+    boxes: every merged box has the same area, and the ties pair neighbours)."""
     r = np.random.Generator(np.random.PCG64(n_tris))
     for same_cell in (False, True):
         c = np.zeros((n_tris, 1, 3)) if same_cell else r.uniform(-1, 1, (n_tris, 1, 3))
@@ -180,6 +187,7 @@ def test_gpu_bvh_small_and_degenerate_meshes(P, n_tris):
         mesh = scenes.Mesh(v, np.arange(3 * n_tris, dtype=np.int32).reshape(-1, 3), np.zeros(n_tris, np.int32))
         s = P.PtScene(0)
         try:
+            s.set_gpu_bvh_builder(builder)
             s.build_bvh([mesh], on_device=True)
             info = s.bvh_info()
             nodes, tris = s.copy_bvh()
@@ -197,3 +205,14 @@ def test_gpu_bvh_small_and_degenerate_meshes(P, n_tris):
             assert torch.equal(hb, hf)
         finally:
             s.close()
+
+
+def test_gpu_bvh_builder_choice_is_checked(P):
+    s = P.PtScene(0)
+    try:
+        for bad in ("sah", ""):
+            with pytest.raises(P.PtError) as e:
+                s.set_gpu_bvh_builder(bad)
+            assert e.value.status == -1
+    finally:
+        s.close()

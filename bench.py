@@ -629,8 +629,9 @@ def _tail_args(args):
 def instanced_4k(pt, torch, spp, ref_spp, tail=None):
     """The instanced scene at 3840x2160: plain tracer and radiance cache side by
     side, each accumulated to `spp` samples (FP64 sums; the cache in frames of
-    1 spp), against a `ref_spp` plain render with an independent seed.
-    Prints progress to stderr; returns the JSON object of the comparison."""
+    1 spp, as configured and with the first of CACHE_VARIANTS), against a
+    `ref_spp` plain render with an independent seed.  Prints progress to
+    stderr; returns the JSON object of the comparison."""
     from paper_2407_19977_amd import scenes
     sc = scenes.instanced(width=3840, height=2160, spp=spp)
     cam = sc.camera
@@ -642,8 +643,8 @@ def instanced_4k(pt, torch, spp, ref_spp, tail=None):
     acc = torch.empty((H, W, 3), dtype=torch.float64, device="cuda:0")
     chunk = 32
 
-    def run(n, sd, cache):
-        s.set_radiance_cache(pt.cache_config() if cache else None)
+    def run(n, sd, cache, kw=None):
+        s.set_radiance_cache(pt.cache_config(**(kw or {})) if cache else None)
         s.reset_accumulation()
         s.reset_stats()
         s.set_profiling(True, False)
@@ -661,16 +662,20 @@ def instanced_4k(pt, torch, spp, ref_spp, tail=None):
     t_ref, _, ref = run(ref_spp, seed + 1, False)
     res = {"workload": f"instanced scene (400 instances of 5 meshes, 10.8M instanced triangles), {W}x{H}, depth {depth}",
            "reference": f"{ref_spp} spp plain tracer, FP64 sums, seed {seed + 1} ({t_ref:.1f} s)", "modes": {}}
-    for cache in (False, True):
-        dt, st, img = run(spp, seed, cache)
+    modes = (("plain", False, None), ("cache", True, None), ("cache_refined", True, CACHE_VARIANTS[0][1]))
+    for name, cache, kw in modes:
+        dt, st, img = run(spp, seed, cache, kw)
         d = img - ref
         rays = st["extension_rays"] + st["shadow_rays"]
-        res["modes"]["cache" if cache else "plain"] = {
+        res["modes"][name] = {
             "spp": spp, "seconds": round(dt, 3), "Mrays_per_s": round(rays / dt / 1e6, 1),
             "samples_per_s": round(W * H * spp / dt, 1),
             "rmse": round(torch.sqrt(torch.mean(d * d)).item(), 6),
             "relmse": round(torch.mean(d * d / (ref * ref + 0.01)).item(), 6),
-            "cache_queries": st["cache_queries"], "adam_steps": st["cache_adam_steps"]}
+            "cache_queries": st["cache_queries"], "adam_steps": st["cache_adam_steps"],
+            "mean_bias": round(((img.mean() - ref.mean()) / ref.mean()).item(), 6)}
+        if kw:
+            res["modes"][name]["settings"] = kw
     s.set_radiance_cache(None)
     s.close()
     return res

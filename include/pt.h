@@ -326,7 +326,7 @@ typedef struct pt_radiance_cache_config {
                               into that vertex, theta: angle to the geometric normal there), and at
                               query_bounce at the latest; 0: always at query_bounce (0) */
   int32_t factorize;       /* 0 or 1: the network predicts radiance divided, per channel, by
-                              (diffuse albedo + specular luminance) of the vertex (inputs 8..10 and
+                              (diffuse albedo + specular albedo) of the vertex (inputs 8..10 and
                               11); queries multiply by that factor, targets are divided by it and
                               dropped where it is zero (0) */
 } pt_radiance_cache_config;

@@ -8,9 +8,10 @@
  * the outgoing direction wo and the shading normal n, each as
  * (acos(y)/pi, atan2(x, -z)/2pi + 1/2) (2 + 2); specular roughness (1);
  * diffuse albedo (1-metalness)(1-transmission) base_weight base_color (3);
- * specular luminance metalness lum(base_weight base_color) +
- * (1-metalness) F_dielectric(1, eta') (1), eta' the IOR after the
- * specular_weight modulation.
+ * specular albedo metalness lum(base_weight base_color) +
+ * (1-metalness) (F + transmission_weight (1 - F)), F = F_dielectric(1, eta')
+ * (1), eta' the IOR after the specular_weight modulation: what the metal or
+ * the dielectric interface reflects or transmits at normal incidence.
  *
  * Encoding to 64 features: for each position axis and k = 0..5 the pair
  * sin(2^k pi x), cos(2^k pi x) (36); one-blob encodings with 4 bins of the
@@ -112,7 +113,8 @@ void onrc_inputs(const oracle_scene* s, v3 p, v3 wo, v3 n, const omat* m, double
   for (int c = 0; c < 3; ++c) x[8 + c] = k * m->base_color[c];
   double F0[3] = {m->base_weight * m->base_color[0], m->base_weight * m->base_color[1],
                   m->base_weight * m->base_color[2]};
-  x[11] = m->metalness * lum3(F0) + (1.0 - m->metalness) * ofresnel_diel(1.0, omod_ior(m));
+  const double Fd = ofresnel_diel(1.0, omod_ior(m));
+  x[11] = m->metalness * lum3(F0) + (1.0 - m->metalness) * (Fd + m->trans_weight * (1.0 - Fd));
 }
 
 /* Test hook: onrc_inputs for a scene box [lo, hi] and a material given as

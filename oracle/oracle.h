@@ -62,7 +62,7 @@ typedef struct {
   int32_t nrc_bf16;      /* 1: evaluate the cache with bfloat16 operands */
   int32_t train_end;     /* training records: the path ends in the cache at this vertex (self-training; needs
                             nrc_weights), -1: plain path to max_depth */
-  int32_t nrc_factor;    /* 1: the cache predicts radiance / (diffuse albedo + specular luminance) */
+  int32_t nrc_factor;    /* 1: the cache predicts radiance / (diffuse albedo + specular albedo) */
   double spread_c;       /* > 0: adaptive termination (path spread): a rendering path ends in the cache at
                             the first vertex b >= 1 whose spread exceeds spread_c times the primary
                             footprint, at nrc_bounce at the latest; 0: always at nrc_bounce */

@@ -99,7 +99,7 @@ struct PathsDev {
   float* rec;          // training records [n][rec_depth][20] (nullptr: not a training pass)
   int32_t rec_depth;
   int32_t train_end;   // training paths end in the cache at this vertex (terminal record), -1: plain
-  int32_t nrc_factor;  // 1: the cache predicts radiance / (diffuse albedo + specular luminance)
+  int32_t nrc_factor;  // 1: the cache predicts radiance / (diffuse albedo + specular albedo)
   // adaptive termination: per sampling path the primary footprint a0 and the running sum of the
   // spread terms; with spread_c > 0 a path ends in the cache at the first vertex b >= 1 where
   // sum^2 > spread_c * a0 (and at the query vertex at the latest)

@@ -4,7 +4,9 @@
 // Inputs at a vertex (12): position in the scene box (3); wo and the shading
 // normal as (acos(y)/pi, atan2(x,-z)/2pi + 1/2) (2 + 2); specular roughness;
 // diffuse albedo (1-metalness)(1-transmission) base_weight base_color (3);
-// specular luminance metalness lum(bw bc) + (1-metalness) F_dielectric(1, ior).
+// specular albedo metalness lum(bw bc) + (1-metalness) (F + transmission (1 - F)),
+// F = F_dielectric(1, ior): what the metal or the dielectric interface reflects or
+// transmits at normal incidence (so that a glass's reflectance factor is about 1).
 // Encoding (64): sin / cos(2^k pi x_a), k = 0..5 (36); one-blob, 4 bins, of
 // the four direction coordinates (16; the two azimuths periodic) and of
 // 1 - exp(-roughness) (4); the four albedo values (4); constants 1, 0, 0, 0 (4).
@@ -125,7 +127,7 @@ __host__ __device__ inline void nrc_inputs(const float* lo, const float* inv_ext
   x[8] = kd * m.base_color[0];
   x[9] = kd * m.base_color[1];
   x[10] = kd * m.base_color[2];
-  x[11] = m.metalness * m.bwbc_lum + (1.0f - m.metalness) * m.f0_diel;
+  x[11] = m.metalness * m.bwbc_lum + (1.0f - m.metalness) * (m.f0_diel + m.trans_weight * (1.0f - m.f0_diel));
 }
 
 }  // namespace pt

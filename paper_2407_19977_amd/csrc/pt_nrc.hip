@@ -219,7 +219,7 @@ __device__ inline f32x4 mlp_forward(const uint4* __restrict__ sw, int lane, bf16
 }
 
 // Reflectance factor of a query's inputs: the cache predicts radiance divided
-// by (diffuse albedo + specular luminance) per channel when factorising.
+// by (diffuse albedo + specular albedo) per channel when factorising.
 __device__ inline float nrc_factor(const float* x, int c, bool on) { return on ? x[8 + c] + x[11] : 1.0f; }
 
 // ------------------------------------------------------------- inference

@@ -185,11 +185,17 @@ def test_cache_position_albedo_and_specular_inputs(O):
     assert np.allclose(x[0:3], [0.5, 0.5, 0.5], atol=1e-15)
     assert np.all(x[8:11] == 0.0)
     assert x[11] == pytest.approx(0.2126 + 0.7152 * 0.5, abs=1e-7)
-    # glass: transmission removes the diffuse albedo
+    # glass: transmission removes the diffuse albedo; the interface reflects F(1, 2) = 1/9 and
+    # transmits the rest, so the specular albedo is 1
     glass = scenes.material(transmission_weight=1.0, specular_ior=2.0)
     x = O.nrc_inputs(lo, hi, (0.0, 4.0, 12.0), wo, n, glass)
     assert np.all(x[8:11] == 0.0)
-    assert x[11] == pytest.approx(1.0 / 9.0, abs=1e-7)
+    assert x[11] == pytest.approx(1.0, abs=1e-7)
+    # half transmissive: 1/9 + 0.5 (8/9)
+    half = scenes.material(transmission_weight=0.5, specular_ior=2.0, base_color=(0.2, 0.4, 0.6))
+    x = O.nrc_inputs(lo, hi, (0.0, 4.0, 12.0), wo, n, half)
+    assert np.allclose(x[8:11], [0.1, 0.2, 0.3], atol=1e-7)   # (1 - transmission 0.5) base_color
+    assert x[11] == pytest.approx(1.0 / 9.0 + 0.5 * 8.0 / 9.0, abs=1e-7)
     # normal pair of n = +x: theta = pi/2, phi = pi/2
     assert np.allclose(x[5:7], [0.5, 0.75], atol=1e-15)
 

@@ -63,8 +63,11 @@ typedef struct pt_instance {
   int32_t material_override;  /* -1: use the mesh's per-triangle ids */
 } pt_instance;
 
-/* OpenPBR parameters (Sec. 4), linear RGB; 35 floats in this order.
- * thin_film_thickness is in micrometres. */
+/* OpenPBR parameters (Sec. 4), linear RGB; 39 floats in this order.
+ * thin_film_thickness is in micrometres.  Subsurface is its local limit: a
+ * diffuse reflector of albedo subsurface_color mixed into the dielectric
+ * base by subsurface_weight (no light travels sideways under the surface,
+ * so OpenPBR's subsurface radius and anisotropy are not parameters). */
 typedef struct pt_openpbr_material {
   float base_weight, base_color[3], base_metalness, base_diffuse_roughness;
   float specular_weight, specular_color[3], specular_roughness, specular_roughness_anisotropy,
@@ -74,6 +77,7 @@ typedef struct pt_openpbr_material {
   float emission_luminance, emission_color[3];
   float thin_film_weight, thin_film_thickness, thin_film_ior;
   float fuzz_weight, fuzz_color[3], fuzz_roughness;
+  float subsurface_weight, subsurface_color[3];
 } pt_openpbr_material;
 
 /* Pinhole camera (Sec. 5.1.2): vertical field of view in degrees, aspect width/height. */
@@ -173,10 +177,12 @@ pt_status pt_set_gpu_bvh_builder(pt_scene* scene, int32_t builder);
  * on top of everything else (Charlie distribution, alpha = fuzz_roughness^2
  * clamped below at 0.01, tinted by fuzz_color), which attenuates the layers
  * below by its directional albedo; the albedo table is computed here, once
- * per distinct alpha.  Errors: INVALID_ARG (n <= 0, negative or non-finite
- * parameters, IOR <= 0, thin_film_ior < 1, weights, fuzz_roughness or
- * base_diffuse_roughness outside [0,1]), UNSUPPORTED (coat or fuzz together
- * with transmission). */
+ * per distinct alpha.  subsurface_weight > 0 mixes subsurface_color into the
+ * albedo of the dielectric base's diffuse lobe (the subsurface's local limit,
+ * see pt_openpbr_material).  Errors: INVALID_ARG (n <= 0, negative or
+ * non-finite parameters, IOR <= 0, thin_film_ior < 1, weights,
+ * fuzz_roughness or base_diffuse_roughness outside [0,1]), UNSUPPORTED (coat
+ * or fuzz together with transmission). */
 pt_status pt_upload_materials(pt_scene* scene, const pt_openpbr_material* materials, int32_t n);
 
 /* Set the environment: an equirectangular RGB32F image [h][w][3] (y up,

@@ -24,7 +24,10 @@
  *   t = max(mu_i, mu_o) if s > 0 else 1, E(mu) = A + (B/pi) G(mu) the FON
  *   albedo with G(mu) = sin(th) (th - sin(th) mu + (2/3)(1 - sin^3(th))/mu - 2/3),
  *   Eb = A + B (2/3 - 28/(15 pi)) its cosine-weighted mean,
- *   rho_ms = rho^2 Eb / (1 - rho (1 - Eb)); sampled by the cosine.
+ *   rho_ms = rho^2 Eb / (1 - rho (1 - Eb)); sampled by the cosine.  Its
+ *   albedo rho mixes the glossy diffuse bw*bc and OpenPBR's subsurface in
+ *   its local limit (no light moving sideways under the surface: a diffuse
+ *   reflector of albedo subsurface_color): rho = (1-ssw) bw*bc + ssw*ssc.
  *   specular_weight xi modulates the dielectric IOR (OpenPBR): the interface
  *   and the cache input use eta' with F0(eta') = xi F0(eta), so reflection,
  *   refraction and the diffuse attenuation stay consistent; the metal
@@ -32,7 +35,7 @@
  *   f = C + [(1-cw) + cw*coat_color*(1-Fc(|mu_i|))(1-Fc(mu_o))]
  *           * [metalness*M + (1-metalness)*(I + D)].
  *   Lobe choice pmf at mu_o: w_C = cw*Fc, w_M = Tc*metalness*sw*lum(F82),
- *   w_I = Tc*(1-metalness)*(Fd + tw*(1-Fd)), w_D = Tc*(1-metalness)*(1-tw)*(1-Fd)*lum(bw*bc),
+ *   w_I = Tc*(1-metalness)*(Fd + tw*(1-Fd)), w_D = Tc*(1-metalness)*(1-tw)*(1-Fd)*lum(rho),
  *   Tc = 1 - cw*Fc(mu_o), Fd = F(mu_o, eta').
  *   Non-delta sampling weight: f_nd*|cos|/sum_k P_k pdf_k (one-sample MIS over lobes).
  *
@@ -194,6 +197,10 @@ static double fuzz_att(const omat* m, double mu_i, double mu_o) {
   return (1.0 - w * ofuzz_albedo(m, fabs(mu_i))) * (1.0 - w * ofuzz_albedo(m, mu_o));
 }
 
+double odiffuse_albedo(const omat* m, int c) {
+  return (1.0 - m->ss_weight) * m->base_weight * m->base_color[c] + m->ss_weight * m->ss_color[c];
+}
+
 double omod_ior(const omat* m) {
   /* F0(eta') = xi F0(eta): eta' = (1 + sqrt(xi F0)) / (1 - sqrt(xi F0)), inverted below 1 */
   double eta = m->spec_ior, xi = m->spec_weight;
@@ -301,13 +308,12 @@ void obsdf_setup(const omat* m, int entering, double mu_o, obsdf* b) {
   oiface_fresnel(b, mu_o, Fdv, &Fd);
   double F82[3];
   of82(m, mu_o, F82);
-  double bwbc[3] = {m->base_weight * m->base_color[0], m->base_weight * m->base_color[1],
-                    m->base_weight * m->base_color[2]};
+  double rho[3] = {odiffuse_albedo(m, 0), odiffuse_albedo(m, 1), odiffuse_albedo(m, 2)};
   double w[5];
   w[LOBE_C] = cw * Fc;
   w[LOBE_M] = Tc * mt * sw * lum3(F82);
   w[LOBE_I] = Tc * (1.0 - mt) * (Fd + tw * (1.0 - Fd));
-  w[LOBE_D] = Tc * (1.0 - mt) * (1.0 - tw) * (1.0 - Fd) * lum3(bwbc);
+  w[LOBE_D] = Tc * (1.0 - mt) * (1.0 - tw) * (1.0 - Fd) * lum3(rho);
   w[LOBE_Z] = 0.0;
   if (m->fuzz_weight > 0.0) {  /* the fuzz reflects w E(mu_o) and passes the rest to the layers below */
     double fz = m->fuzz_weight * ofuzz_albedo(m, mu_o);
@@ -386,7 +392,7 @@ void obsdf_eval(const obsdf* b, v3 wo, v3 wi, double f[3], double* pdf) {
     double fz = m->fuzz_weight > 0.0 ? m->fuzz_weight * ofuzz_f(ofuzz_alpha(m->fuzz_rough), wo, wi) : 0.0;
     for (int c = 0; c < 3; ++c) {
       double kd = (1.0 - tw) * (1.0 - Fdi[c]) * (1.0 - Fdo[c]);
-      double fd = kd * oeon(m->base_weight * m->base_color[c], m->diffuse_roughness, mu_i, mu_o, s);
+      double fd = kd * oeon(odiffuse_albedo(m, c), m->diffuse_roughness, mu_i, mu_o, s);
       f[c] = fz * m->fuzz_color[c] + A * (fc + L[c] * (mt * fm[c] + (1.0 - mt) * (fi[c] + fd)));
     }
     *pdf = b->P[LOBE_C] * pc + b->P[LOBE_M] * pm + b->P[LOBE_I] * pi + b->P[LOBE_D] * (mu_i / O_PI) +

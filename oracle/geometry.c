@@ -46,6 +46,8 @@ void omat_from_floats(const float* f, omat* m) {
   m->fuzz_weight = f[i++];
   for (int c = 0; c < 3; ++c) m->fuzz_color[c] = f[i++];
   m->fuzz_rough = f[i++];
+  m->ss_weight = f[i++];
+  for (int c = 0; c < 3; ++c) m->ss_color[c] = f[i++];
   if (m->fuzz_weight > 0.0) ofuzz_table(m->fuzz_rough, m->fuzz_E);
   else
     for (int k = 0; k < 65; ++k) m->fuzz_E[k] = 0.0;

@@ -7,7 +7,8 @@
  * Inputs at a path vertex (12): position normalised to the scene box (3);
  * the outgoing direction wo and the shading normal n, each as
  * (acos(y)/pi, atan2(x, -z)/2pi + 1/2) (2 + 2); specular roughness (1);
- * diffuse albedo (1-metalness)(1-transmission) base_weight base_color (3);
+ * diffuse albedo (1-metalness)(1-transmission) rho, rho the diffuse lobe's
+ * albedo (base_weight base_color, mixed with subsurface_color) (3);
  * specular albedo metalness lum(base_weight base_color) +
  * (1-metalness) (F + transmission_weight (1 - F)), F = F_dielectric(1, eta')
  * (1), eta' the IOR after the specular_weight modulation: what the metal or
@@ -109,8 +110,8 @@ void onrc_inputs(const oracle_scene* s, v3 p, v3 wo, v3 n, const omat* m, double
     x[4 + 2 * d] = atan2(dirs[d].x + 0.0, -dirs[d].z + 0.0) / (2.0 * O_PI) + 0.5;
   }
   x[7] = m->spec_rough;
-  double k = (1.0 - m->metalness) * (1.0 - m->trans_weight) * m->base_weight;
-  for (int c = 0; c < 3; ++c) x[8 + c] = k * m->base_color[c];
+  double k = (1.0 - m->metalness) * (1.0 - m->trans_weight);
+  for (int c = 0; c < 3; ++c) x[8 + c] = k * odiffuse_albedo(m, c);
   double F0[3] = {m->base_weight * m->base_color[0], m->base_weight * m->base_color[1],
                   m->base_weight * m->base_color[2]};
   const double Fd = ofresnel_diel(1.0, omod_ior(m));

@@ -81,7 +81,7 @@ double oracle_uniform(uint64_t seed, uint32_t pixel, uint32_t sample, uint32_t b
 
 int oracle_scene_create(const oracle_mesh* meshes, int32_t n_meshes,
                         const oracle_instance* instances, int32_t n_instances,
-                        const float* materials /* [n][35] */, int32_t n_materials,
+                        const float* materials /* [n][39] */, int32_t n_materials,
                         const float* env /* [h][w][3] or NULL */, int32_t env_w, int32_t env_h,
                         oracle_scene** out);
 void oracle_scene_destroy(oracle_scene* s);
@@ -153,7 +153,7 @@ void oracle_display(const double* sum, int64_t n_pixels, double inv_samples, dou
                     uint8_t* rgba8);
 
 /* ---- BSDF and light-sampling probes (local shading frame, n = +z) ---- */
-/* mat: 35 floats.  entering: 1 if wo is on the front side of the geometric normal. */
+/* mat: 39 floats.  entering: 1 if wo is on the front side of the geometric normal. */
 int oracle_bsdf_eval(const float* mat, int32_t entering, const double wo[3], const double wi[3],
                      double f[3], double* pdf);
 /* u[4] = (lobe, dir1, dir2, reflect/refract).  out: wi[3], weight[3], pdf, flags

@@ -178,7 +178,7 @@ def camera_ray(cam, fx, fy):
 
 
 def _mat(m) -> np.ndarray:
-    m = np.ascontiguousarray(np.asarray(m, dtype=np.float32).reshape(35))
+    m = np.ascontiguousarray(np.asarray(m, dtype=np.float32).reshape(39))
     return m
 
 

@@ -34,13 +34,18 @@ typedef struct {
   double emis_lum, emis_color[3];
   double film_weight, film_thickness_um, film_ior;
   double fuzz_weight, fuzz_color[3], fuzz_rough;
+  double ss_weight, ss_color[3];  /* subsurface (its local limit: a diffuse albedo) */
   double fuzz_E[65];   /* directional albedo of the fuzz lobe at mu = k/64 (zero without fuzz) */
 } omat;
 
 /* floats of one OpenPBR parameter record at the C ABI */
-#define OMAT_FLOATS 35
+#define OMAT_FLOATS 39
 
 void omat_from_floats(const float* f, omat* m);
+/* albedo of the dielectric base's diffuse lobe, channel c: the glossy
+ * diffuse (base_weight base_color) and the subsurface's local limit
+ * (subsurface_color) mixed by subsurface_weight (bsdf.c) */
+double odiffuse_albedo(const omat* m, int c);
 /* dielectric IOR after the specular_weight modulation (bsdf.c) */
 double omod_ior(const omat* m);
 /* EON diffuse value (1/pi included) for albedo rho, roughness sigma, s = wi.wo - mu_i mu_o (bsdf.c) */

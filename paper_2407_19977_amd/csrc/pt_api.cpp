@@ -1087,7 +1087,7 @@ pt_status validate_material(const pt_openpbr_material& m, int i) {
   }
   const float unit[] = {m.base_weight, m.base_metalness, m.specular_weight, m.specular_roughness,
                         m.specular_roughness_anisotropy, m.transmission_weight, m.coat_weight, m.coat_roughness,
-                        m.thin_film_weight, m.fuzz_weight, m.fuzz_roughness};
+                        m.thin_film_weight, m.fuzz_weight, m.fuzz_roughness, m.subsurface_weight};
   for (float u : unit)
     if (u > 1.0f) return fail(PT_ERR_INVALID_ARG, "material %d: weights and roughness must be in [0, 1]", i);
   if (!(m.specular_ior > 0.0f) || !(m.coat_ior > 0.0f)) return fail(PT_ERR_INVALID_ARG, "material %d: IOR must be > 0", i);
@@ -1141,6 +1141,15 @@ MatRec make_matrec(const pt_openpbr_material& m) {
   r.coat_ior = m.coat_ior;
   r.bwbc_lum = (float)lumd((double)m.base_weight * m.base_color[0], (double)m.base_weight * m.base_color[1],
                            (double)m.base_weight * m.base_color[2]);
+  {  // the diffuse lobe's albedo: glossy diffuse and the subsurface's local limit, mixed
+    const double ws = m.subsurface_weight;
+    double kd[3];
+    for (int c = 0; c < 3; ++c) {
+      kd[c] = (1.0 - ws) * ((double)m.base_weight * m.base_color[c]) + ws * (double)m.subsurface_color[c];
+      r.kd[c] = (float)kd[c];
+    }
+    r.kd_lum = (float)lumd(kd[0], kd[1], kd[2]);
+  }
   double rr = m.specular_roughness, a = m.specular_roughness_anisotropy;
   double alpha = rr * rr;
   double at = alpha * std::sqrt(2.0 / (1.0 + (1.0 - a) * (1.0 - a)));
@@ -1158,7 +1167,7 @@ MatRec make_matrec(const pt_openpbr_material& m) {
   bool hasM = m.base_metalness > 0.0f && m.specular_weight > 0.0f;
   bool hasI = m.base_metalness < 1.0f &&
               (m.specular_weight > 0.0f || m.transmission_weight > 0.0f || m.thin_film_weight > 0.0f);
-  bool hasD = m.base_metalness < 1.0f && m.transmission_weight < 1.0f && r.bwbc_lum > 0.0f;
+  bool hasD = m.base_metalness < 1.0f && m.transmission_weight < 1.0f && r.kd_lum > 0.0f;
   bool hasT = m.base_metalness < 1.0f && m.transmission_weight > 0.0f;
   int cls;
   if (!hasC && !hasM && !hasI && !hasD) cls = kClsAbsorb;

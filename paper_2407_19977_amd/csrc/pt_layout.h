@@ -67,7 +67,7 @@ enum MatClass : int {
   kNumClasses = 7
 };
 
-// Device material record, 128 bytes, derived on the host from the OpenPBR parameters.
+// Device material record, 192 bytes, derived on the host from the OpenPBR parameters.
 struct alignas(32) MatRec {
   float base_color[3];  float base_weight;
   float metalness;      float spec_weight;  float spec_ior;     float trans_weight;
@@ -82,7 +82,8 @@ struct alignas(32) MatRec {
   float film_d_nm;                          // its thickness in nm
   float fuzz_w;         float fuzz_color[3]; float fuzz_a;  // fuzz: weight (0: none), colour, sheen alpha
   const float* fuzz_E;  // its directional albedo at mu = k/64, k = 0..64 (device memory; null without fuzz)
-  float pad[6];
+  float kd[3];          float kd_lum;       // diffuse lobe albedo: (1 - ssw) bw bc + ssw subsurface_color; its lum
+  float pad[2];
 };
 static_assert(sizeof(MatRec) == 192, "material record is 192 bytes");
 constexpr uint32_t kMatSpecDelta = 1u, kMatCoatDelta = 2u, kMatEmissive = 4u;

@@ -3,7 +3,7 @@
 //
 // Inputs at a vertex (12): position in the scene box (3); wo and the shading
 // normal as (acos(y)/pi, atan2(x,-z)/2pi + 1/2) (2 + 2); specular roughness;
-// diffuse albedo (1-metalness)(1-transmission) base_weight base_color (3);
+// diffuse albedo (1-metalness)(1-transmission) kd, kd the diffuse lobe's albedo (3);
 // specular albedo metalness lum(bw bc) + (1-metalness) (F + transmission (1 - F)),
 // F = F_dielectric(1, ior): what the metal or the dielectric interface reflects or
 // transmits at normal incidence (so that a glass's reflectance factor is about 1).
@@ -123,10 +123,10 @@ __host__ __device__ inline void nrc_inputs(const float* lo, const float* inv_ext
     x[4 + 2 * k] = atan2f(d[k].x + 0.0f, -d[k].z + 0.0f) * (0.5f / kPi) + 0.5f;
   }
   x[7] = m.spec_rough;
-  float kd = (1.0f - m.metalness) * (1.0f - m.trans_weight) * m.base_weight;
-  x[8] = kd * m.base_color[0];
-  x[9] = kd * m.base_color[1];
-  x[10] = kd * m.base_color[2];
+  const float k = (1.0f - m.metalness) * (1.0f - m.trans_weight);
+  x[8] = k * m.kd[0];
+  x[9] = k * m.kd[1];
+  x[10] = k * m.kd[2];
   x[11] = m.metalness * m.bwbc_lum + (1.0f - m.metalness) * (m.f0_diel + m.trans_weight * (1.0f - m.f0_diel));
 }
 

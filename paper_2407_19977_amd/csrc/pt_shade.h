@@ -294,7 +294,7 @@ __host__ __device__ inline Bsdf bsdf_setup(const MatRec& m, bool entering, float
     w1 = Tc * m.metalness * m.spec_weight * lum(F.x, F.y, F.z);
   }
   float w2 = L::I ? Tc * (1.0f - m.metalness) * (Fd + m.trans_weight * (1.0f - Fd)) : 0.0f;
-  float w3 = L::D ? Tc * (1.0f - m.metalness) * (1.0f - m.trans_weight) * (1.0f - Fd) * m.bwbc_lum : 0.0f;
+  float w3 = L::D ? Tc * (1.0f - m.metalness) * (1.0f - m.trans_weight) * (1.0f - Fd) * m.kd_lum : 0.0f;
   float w4 = 0.0f;
   if (L::Z && m.fuzz_w > 0.0f) {  // the fuzz reflects w E(mu_o) and passes the rest to the layers below
     const float fz = m.fuzz_w * fuzz_albedo(m, mu_o);
@@ -405,9 +405,9 @@ __host__ __device__ inline V3 bsdf_eval(const MatRec& m, const Bsdf& b, V3 wo, V
       float Fsi, Fso;
       const V3 Fdi = iface_fresnel<CLS>(m, b, mu_i, Fsi), Fdo = iface_fresnel<CLS>(m, b, mu_o, Fso);
       float s = dot(wi, wo) - mu_i * mu_o;
-      fd = v3((1.0f - tw) * (1.0f - Fdi.x) * (1.0f - Fdo.x) * eon(m, m.base_weight * m.base_color[0], mu_i, mu_o, s),
-              (1.0f - tw) * (1.0f - Fdi.y) * (1.0f - Fdo.y) * eon(m, m.base_weight * m.base_color[1], mu_i, mu_o, s),
-              (1.0f - tw) * (1.0f - Fdi.z) * (1.0f - Fdo.z) * eon(m, m.base_weight * m.base_color[2], mu_i, mu_o, s));
+      fd = v3((1.0f - tw) * (1.0f - Fdi.x) * (1.0f - Fdo.x) * eon(m, m.kd[0], mu_i, mu_o, s),
+              (1.0f - tw) * (1.0f - Fdi.y) * (1.0f - Fdo.y) * eon(m, m.kd[1], mu_i, mu_o, s),
+              (1.0f - tw) * (1.0f - Fdi.z) * (1.0f - Fdo.z) * eon(m, m.kd[2], mu_i, mu_o, s));
     }
     float fx = fc + Lc.x * (mt * fm.x + (1.0f - mt) * (fi.x + fd.x));
     float fy = fc + Lc.y * (mt * fm.y + (1.0f - mt) * (fi.y + fd.y));

@@ -238,7 +238,7 @@ class PtScene:
         return nodes, tris
 
     def upload_materials(self, materials: np.ndarray):
-        m = np.ascontiguousarray(materials, dtype=np.float32).reshape(-1, 35)
+        m = np.ascontiguousarray(materials, dtype=np.float32).reshape(-1, 39)
         _check(_lib.pt_upload_materials(self.h, m.ctypes.data, m.shape[0]))
 
     def set_environment(self, env: Optional[np.ndarray]):

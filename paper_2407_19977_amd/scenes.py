@@ -28,7 +28,7 @@ from typing import List, Optional
 
 import numpy as np
 
-# One OpenPBR parameter record: 35 float32, in this order.  The C ABI's
+# One OpenPBR parameter record: 39 float32, in this order.  The C ABI's
 # pt_openpbr_material and the oracle's input record have the same layout.
 MATERIAL_FIELDS = [
     ("base_weight", 1), ("base_color", 3), ("base_metalness", 1),
@@ -40,18 +40,20 @@ MATERIAL_FIELDS = [
     ("emission_luminance", 1), ("emission_color", 3),
     ("thin_film_weight", 1), ("thin_film_thickness", 1), ("thin_film_ior", 1),
     ("fuzz_weight", 1), ("fuzz_color", 3), ("fuzz_roughness", 1),
+    ("subsurface_weight", 1), ("subsurface_color", 3),
 ]
-MATERIAL_FLOATS = sum(n for _, n in MATERIAL_FIELDS)  # 35
+MATERIAL_FLOATS = sum(n for _, n in MATERIAL_FIELDS)  # 39
 
 
 def material(**kw) -> np.ndarray:
-    """Return one material as float32[35], OpenPBR defaults for unset fields.
+    """Return one material as float32[39], OpenPBR defaults for unset fields.
 
     Defaults follow the OpenPBR specification: base_weight 1, base_color 0.8,
     specular_weight 1, specular_color 1, specular_roughness 0.3,
     specular_ior 1.5, transmission_color 1, coat_color 1, coat_ior 1.6,
     emission_color 1, thin_film_thickness 0.5 (micrometres), thin_film_ior
-    1.5, fuzz_color 1, fuzz_roughness 0.5, everything else 0.
+    1.5, fuzz_color 1, fuzz_roughness 0.5, subsurface_color 0.8, everything
+    else 0.
     """
     d = {
         "base_weight": 1.0, "base_color": (0.8, 0.8, 0.8), "base_metalness": 0.0,
@@ -65,6 +67,7 @@ def material(**kw) -> np.ndarray:
         "emission_luminance": 0.0, "emission_color": (1.0, 1.0, 1.0),
         "thin_film_weight": 0.0, "thin_film_thickness": 0.5, "thin_film_ior": 1.5,
         "fuzz_weight": 0.0, "fuzz_color": (1.0, 1.0, 1.0), "fuzz_roughness": 0.5,
+        "subsurface_weight": 0.0, "subsurface_color": (0.8, 0.8, 0.8),
     }
     for k, v in kw.items():
         if k not in d:
@@ -120,7 +123,7 @@ class Scene:
     name: str
     meshes: List[Mesh]
     instances: List[Instance]          # empty: single level, meshes in world space
-    materials: np.ndarray              # float32 [n_materials, 35]
+    materials: np.ndarray              # float32 [n_materials, 39]
     env: Optional[np.ndarray]          # float32 [h, w, 3] equirect (y up) or None
     camera: Camera
     spp: int
@@ -242,8 +245,10 @@ ZOO_MATERIALS = [
                                              transmission_weight=0.5, transmission_color=(0.8, 1.0, 0.9))),
     ("transmission over diffuse", dict(transmission_weight=0.7, base_color=(0.6, 0.3, 0.2), specular_roughness=0.25,
                                        transmission_color=(0.7, 0.9, 0.8), specular_ior=1.45)),
-    ("weak tinted specular plastic", dict(base_color=(0.2, 0.5, 0.3), specular_weight=0.6,
-                                          specular_color=(1.0, 0.7, 0.7), specular_roughness=0.3)),
+    ("weak tinted specular plastic, half subsurface", dict(base_color=(0.2, 0.5, 0.3), specular_weight=0.6,
+                                                           specular_color=(1.0, 0.7, 0.7), specular_roughness=0.3,
+                                                           subsurface_weight=0.5,
+                                                           subsurface_color=(0.9, 0.7, 0.5))),
     ("anisotropic coated plastic", dict(base_color=(0.3, 0.3, 0.7), specular_roughness=0.35,
                                         specular_roughness_anisotropy=0.6, coat_weight=0.5, coat_roughness=0.2,
                                         coat_color=(1.0, 0.9, 0.7), coat_ior=1.6)),
@@ -275,14 +280,16 @@ def material_zoo(width=96, height=96, spp=8, max_depth=6, seed=0, sphere_level=2
     rows, each with one of ZOO_MATERIALS: partial metalness, coat over metal,
     transmission over diffuse and over partial metal, tints of the
     specular, coat and transmission colours, specular_weight < 1,
-    anisotropy under a coat, thin films and fuzz — the OpenPBR mixes that
-    the closed-box, icosphere-field and instanced scenes do not reach.  The back wall is a
-    rough diffuse (base_diffuse_roughness 0.7) and the left wall a rough
-    diffuse base (0.3) under a glossy specular layer."""
+    anisotropy under a coat, thin films, fuzz and subsurface — the OpenPBR
+    mixes that the closed-box, icosphere-field and instanced scenes do not
+    reach.  The back wall is a rough diffuse (base_diffuse_roughness 0.7),
+    the left wall a rough diffuse base (0.3) under a glossy specular layer,
+    the right wall a diffuse base with 40 % subsurface."""
     mats = [lambert((0.6, 0.6, 0.6)),
             material(base_color=(0.7, 0.4, 0.3), base_diffuse_roughness=0.7, specular_weight=0.0),
             material(base_color=(0.3, 0.6, 0.4), base_diffuse_roughness=0.3, specular_roughness=0.5),
-            lambert((0.4, 0.4, 0.7)),
+            material(base_color=(0.4, 0.4, 0.7), specular_weight=0.0, subsurface_weight=0.4,
+                     subsurface_color=(0.8, 0.6, 0.4)),
             material(base_weight=0.0, specular_weight=0.0, emission_luminance=12.0,
                      emission_color=(1.0, 0.95, 0.9))]
     mats += [material(**kw) for _, kw in ZOO_MATERIALS]

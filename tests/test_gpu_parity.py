@@ -422,7 +422,8 @@ def test_error_codes(P, O):
         s.upload_materials(bad)
     assert e.value.status == -1
     for kw in (dict(thin_film_weight=1.0, thin_film_ior=0.9), dict(thin_film_weight=1.5), dict(fuzz_weight=1.5),
-               dict(fuzz_weight=0.5, fuzz_roughness=1.5)):
+               dict(fuzz_weight=0.5, fuzz_roughness=1.5), dict(subsurface_weight=1.5),
+               dict(subsurface_weight=0.5, subsurface_color=(0.5, -0.1, 0.5))):
         bad = sc.materials.copy()
         bad[0] = scenes.material(**kw)  # film IOR below 1, film weight above 1
         with pytest.raises(P.PtError) as e:

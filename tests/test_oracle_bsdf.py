@@ -42,9 +42,11 @@ MATS = {
                       fuzz_color=(0.9, 0.8, 0.6), fuzz_roughness=0.4),
     "fuzz_coated": M(base_color=(0.2, 0.3, 0.6), specular_roughness=0.3, coat_weight=1.0, coat_roughness=0.0,
                      fuzz_weight=0.5, fuzz_roughness=0.8),
+    "subsurface_eon": M(base_color=(0.7, 0.3, 0.2), base_diffuse_roughness=0.5, specular_roughness=0.3,
+                        subsurface_weight=0.6, subsurface_color=(0.9, 0.8, 0.6)),
 }
 OPAQUE = ["lambert", "metal", "metal_aniso", "plastic", "coated_delta", "coated_rough", "half_metal", "eon",
-          "eon_plastic_weak", "plastic_film", "fuzz_plastic", "fuzz_coated"]
+          "eon_plastic_weak", "plastic_film", "fuzz_plastic", "fuzz_coated", "subsurface_eon"]
 
 
 def sph(theta, phi):

@@ -47,6 +47,7 @@ constexpr int kMaxTreeLevels = 128;          // bound on any walk or level loop 
 constexpr int kPlocRadius = PT_PLOC_RADIUS;  // clusters searched on either side
 constexpr int kPlocMaxRounds = 4096;         // bound on the clustering rounds
 constexpr int kPlocBatch = 8;                // rounds enqueued between two reads of the cluster count
+constexpr int kCollapseBatch = 8;            // collapse levels enqueued between two reads of the job count
 #ifndef PT_SAH_TRAVERSAL
 #define PT_SAH_TRAVERSAL 1.0
 #endif
@@ -489,9 +490,161 @@ __global__ __launch_bounds__(kBB) void k_ploc_scatter(const uint32_t* __restrict
   }
 }
 
-// The collapse's first job: the last cluster (the root) at BVH4 node 0, first triangle 0.
-__global__ void k_root_job(const uint32_t* __restrict__ cid, uint4* __restrict__ jobs) {
-  jobs[0] = make_uint4(cid[0], 0u, 0u, 0u);
+// The last rounds of the clustering in one workgroup, once at most
+// kFinishMax clusters are left: the same rounds as k_ploc_nn .. k_ploc_scatter
+// (same ranks, same merges, same forced rounds) with the clusters in LDS and
+// barriers between the steps instead of launches.  Then the root's job.
+constexpr int kFinishThreads = 1024;
+constexpr int kFinishMax = 2048;
+constexpr int kFinishPer = kFinishMax / kFinishThreads;
+
+__device__ inline uint32_t block_excl_scan_1024(bool flag, uint32_t* s_w, uint32_t& total) {
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const uint64_t bal = __ballot(flag);
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  if (lane == 0) s_w[wave] = (uint32_t)__popcll(bal);
+  __syncthreads();
+  uint32_t before = 0, t = 0;
+  for (int w = 0; w < kFinishThreads / 64; ++w) {
+    if (w < wave) before += s_w[w];
+    t += s_w[w];
+  }
+  __syncthreads();  // s_w is reused by the next scan
+  total = t;
+  return before + (uint32_t)__popcll(bal & lt);
+}
+
+__global__ __launch_bounds__(kFinishThreads) void k_ploc_finish(const uint32_t* __restrict__ cid_in,
+                                                                const float* __restrict__ cbox_in,
+                                                                const uint32_t* __restrict__ mc,
+                                                                uint2* __restrict__ child, float* __restrict__ nbox,
+                                                                uint32_t* __restrict__ cnt, float* __restrict__ ncost,
+                                                                uint32_t* __restrict__ n_int, uint32_t cap,
+                                                                uint4* __restrict__ jobs, uint32_t* __restrict__ err) {
+  __shared__ float sb[kFinishMax * 6];
+  __shared__ uint32_t sid[kFinishMax];
+  __shared__ int32_t snn[kFinishMax];
+  __shared__ uint32_t s_w[kFinishThreads / 64];
+  uint32_t m = mc[0], prev = mc[1];
+  if (m > (uint32_t)kFinishMax) {  // the host launches this only at or below kFinishMax clusters
+    if (threadIdx.x == 0) atomicOr(err, 16u);
+    return;
+  }
+  for (int e = 0; e < kFinishPer; ++e) {
+    const uint32_t i = threadIdx.x + e * kFinishThreads;
+    if (i < m) {
+      sid[i] = cid_in[i];
+      for (int k = 0; k < 6; ++k) sb[6 * i + k] = cbox_in[6 * (size_t)i + k];
+    }
+  }
+  __syncthreads();
+  for (int round = 0; m > 1; ++round) {
+    if (round >= kPlocMaxRounds) {
+      if (threadIdx.x == 0) atomicOr(err, 16u);
+      return;
+    }
+    const bool forced = (uint64_t)m * 100u > (uint64_t)prev * 99u;
+    for (int e = 0; e < kFinishPer; ++e) {  // nearest neighbours
+      const int64_t i = threadIdx.x + e * kFinishThreads;
+      if (i >= (int64_t)m) continue;
+      if (forced) {
+        const int64_t j = i ^ 1;
+        snn[i] = (int32_t)(j < (int64_t)m ? j : i);
+        continue;
+      }
+      const float* bi = sb + 6 * i;
+      float best = INFINITY;
+      uint32_t bd = 0xFFFFFFFFu, blo = 0xFFFFFFFFu;
+      int32_t bj = (int32_t)i;
+      for (int d = -kPlocRadius; d <= kPlocRadius; ++d) {
+        const int64_t j = i + d;
+        if (d == 0 || j < 0 || j >= (int64_t)m) continue;
+        const float* bb = sb + 6 * j;
+        float u[6];
+        for (int k = 0; k < 3; ++k) {
+          u[k] = fminf(bi[k], bb[k]);
+          u[3 + k] = fmaxf(bi[3 + k], bb[3 + k]);
+        }
+        const float a = half_area(u);
+        const uint32_t ad = (uint32_t)(d < 0 ? -d : d), lo = (uint32_t)(d < 0 ? j : i);
+        const bool better =
+            a < best || (a == best && (ad < bd || (ad == bd && ((lo & 1u) < (blo & 1u) ||
+                                                                ((lo & 1u) == (blo & 1u) && lo < blo)))));
+        if (better) {
+          best = a;
+          bd = ad;
+          blo = lo;
+          bj = (int32_t)j;
+        }
+      }
+      snn[i] = bj;
+    }
+    __syncthreads();
+    bool keep[kFinishPer];
+    for (int e = 0; e < kFinishPer; ++e) {  // merges (in place, as in k_ploc_merge)
+      const int64_t i = threadIdx.x + e * kFinishThreads;
+      keep[e] = false;
+      if (i >= (int64_t)m) continue;
+      const int32_t j = snn[i];
+      const bool mutual = j != (int32_t)i && j >= 0 && j < (int32_t)m && snn[j] == (int32_t)i;
+      keep[e] = !(mutual && j < (int32_t)i);
+      if (!mutual || j < (int32_t)i) continue;
+      const uint32_t o = atomicAdd(n_int, 1u);
+      if (o >= cap) {
+        atomicOr(err, 4u);
+        continue;
+      }
+      const uint32_t a = sid[i], b = sid[j];
+      float u[6], ba[6], bb[6];
+      for (int k = 0; k < 6; ++k) {
+        ba[k] = sb[6 * i + k];
+        bb[k] = sb[6 * j + k];
+      }
+      for (int k = 0; k < 3; ++k) {
+        u[k] = fminf(ba[k], bb[k]);
+        u[3 + k] = fmaxf(ba[3 + k], bb[3 + k]);
+      }
+      for (int k = 0; k < 6; ++k) {
+        nbox[6 * (size_t)o + k] = u[k];
+        sb[6 * i + k] = u[k];
+      }
+      const uint32_t c = ref_count(a, cnt) + ref_count(b, cnt);
+      const float area = half_area(u);
+      const float ca = (a & kLeafRef) ? half_area(ba) : ncost[a], cb = (b & kLeafRef) ? half_area(bb) : ncost[b];
+      const float split = kSahNode * area + ca + cb, leaf = (float)c * area;
+      const bool as_leaf = c <= (uint32_t)kMaxLeafTris && leaf <= split;
+      ncost[o] = as_leaf ? leaf : split;
+      child[o] = make_uint2(a, b);
+      cnt[o] = as_leaf ? (c | kLeafBitCnt) : c;
+      sid[i] = o;
+    }
+    __syncthreads();
+    // compaction in order: places tid (first) then tid + kFinishThreads (second)
+    uint32_t pos[kFinishPer], tot[kFinishPer];
+    for (int e = 0; e < kFinishPer; ++e) pos[e] = block_excl_scan_1024(keep[e], s_w, tot[e]);
+    uint32_t id_r[kFinishPer];
+    float box_r[kFinishPer][6];
+    for (int e = 0; e < kFinishPer; ++e) {
+      const uint32_t i = threadIdx.x + e * kFinishThreads;
+      if (!keep[e]) continue;
+      id_r[e] = sid[i];
+      for (int k = 0; k < 6; ++k) box_r[e][k] = sb[6 * i + k];
+    }
+    __syncthreads();
+    uint32_t base = 0;
+    for (int e = 0; e < kFinishPer; ++e) {
+      if (keep[e]) {
+        const uint32_t q = base + pos[e];
+        sid[q] = id_r[e];
+        for (int k = 0; k < 6; ++k) sb[6 * q + k] = box_r[e][k];
+      }
+      base += tot[e];
+    }
+    __syncthreads();
+    prev = m;
+    m = base;
+  }
+  if (threadIdx.x == 0) jobs[0] = make_uint4(sid[0], 0u, 0u, 0u);
 }
 
 // Cluster counts of the first round: n clusters, and no round before it.
@@ -503,17 +656,12 @@ __global__ void k_ploc_start(uint32_t* __restrict__ mc, uint32_t n) {
 // 5. one level of the collapse: job (binary reference, BVH4 node index, place
 // of its first triangle in leaf order).  A leaf's triangles take consecutive
 // places in depth-first order of its subtree: order[place] = sorted index.
-__global__ __launch_bounds__(kBB) void k_collapse(const uint4* __restrict__ jobs, uint32_t n_jobs,
-                                                  uint4* __restrict__ next_jobs, uint32_t* __restrict__ n_next,
-                                                  uint32_t* __restrict__ n_nodes, uint32_t* __restrict__ max_leaf,
-                                                  const uint32_t* __restrict__ val, const float* __restrict__ tbox,
-                                                  const float* __restrict__ nbox, const uint2* __restrict__ child,
-                                                  const uint32_t* __restrict__ cnt, BVHNode* __restrict__ out,
-                                                  uint32_t cap, uint32_t n_tris, uint32_t* __restrict__ order,
-                                                  uint32_t* __restrict__ err) {
-  const uint32_t j = blockIdx.x * kBB + threadIdx.x;
-  if (j >= n_jobs) return;
-  const uint4 job = jobs[j];
+__device__ inline void collapse_one(const uint4 job, uint4* __restrict__ next_jobs, uint32_t* __restrict__ n_next,
+                                    uint32_t* __restrict__ n_nodes, uint32_t* __restrict__ max_leaf,
+                                    const uint32_t* __restrict__ val, const float* __restrict__ tbox,
+                                    const float* __restrict__ nbox, const uint2* __restrict__ child,
+                                    const uint32_t* __restrict__ cnt, BVHNode* __restrict__ out, uint32_t cap,
+                                    uint32_t n_tris, uint32_t* __restrict__ order, uint32_t* __restrict__ err) {
   uint32_t kids[4];
   int nk = 0;
   if (ref_is_leaf_subtree(job.x, cnt)) {
@@ -613,6 +761,28 @@ __global__ __launch_bounds__(kBB) void k_collapse(const uint4* __restrict__ jobs
   if (leaf_max) atomicMax(max_leaf, leaf_max);
 }
 
+// Level `level` of the collapse: its job count is jc[level % 3] (written by the
+// level before), its jobs append to jc[(level + 1) % 3], and it zeroes
+// jc[(level + 2) % 3] for the level after next; jc[3] counts the levels that
+// had jobs.  Any grid (a grid-stride loop), so that levels are enqueued
+// without the host reading the counts in between.
+__global__ __launch_bounds__(kBB) void k_collapse(const uint4* __restrict__ jobs, uint32_t* __restrict__ jc, int level,
+                                                  uint4* __restrict__ next_jobs, uint32_t* __restrict__ n_nodes,
+                                                  uint32_t* __restrict__ max_leaf, const uint32_t* __restrict__ val,
+                                                  const float* __restrict__ tbox, const float* __restrict__ nbox,
+                                                  const uint2* __restrict__ child, const uint32_t* __restrict__ cnt,
+                                                  BVHNode* __restrict__ out, uint32_t cap, uint32_t n_tris,
+                                                  uint32_t* __restrict__ order, uint32_t* __restrict__ err) {
+  const uint32_t n_jobs = min(jc[level % 3], cap);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    jc[(level + 2) % 3] = 0u;
+    if (n_jobs) atomicMax(jc + 3, (uint32_t)(level + 1));
+  }
+  for (uint32_t j = blockIdx.x * kBB + threadIdx.x; j < n_jobs; j += gridDim.x * kBB)
+    collapse_one(jobs[j], next_jobs, jc + (level + 1) % 3, n_nodes, max_leaf, val, tbox, nbox, child, cnt, out, cap,
+                 n_tris, order, err);
+}
+
 // 6. triangle records in leaf order
 __global__ __launch_bounds__(kBB) void k_sorted_tris(const float* __restrict__ soup, const uint32_t* __restrict__ prim,
                                                      const uint32_t* __restrict__ mat, const uint32_t* __restrict__ val,
@@ -632,20 +802,38 @@ __global__ __launch_bounds__(kBB) void k_sorted_tris(const float* __restrict__ s
 int grid_of(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBB - 1) / kBB, 8192)); }
 
 // device workspace of one build, freed when it goes out of scope
+// (one allocation sized for the whole build, carved in 256-byte aligned
+// pieces; a piece that does not fit gets an allocation of its own)
 struct Scratch {
-  std::vector<void*> ptrs;
+  void* arena = nullptr;
+  size_t cap = 0, used = 0;
+  std::vector<void*> extra;
+  explicit Scratch(size_t bytes) {
+    if (hipMalloc(&arena, bytes) == hipSuccess) cap = bytes;
+    else arena = nullptr;
+  }
   ~Scratch() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : extra) (void)hipFree(p);
+    if (arena) (void)hipFree(arena);
   }
   template <class T>
   hipError_t get(T** out, size_t count) {
+    const size_t b = (std::max<size_t>(count * sizeof(T), 16) + 255) & ~size_t(255);
+    if (arena && used + b <= cap) {
+      *out = reinterpret_cast<T*>(static_cast<char*>(arena) + used);
+      used += b;
+      return hipSuccess;
+    }
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, std::max<size_t>(count * sizeof(T), 16));
-    if (e == hipSuccess) ptrs.push_back(p);
+    hipError_t e = hipMalloc(&p, b);
+    if (e == hipSuccess) extra.push_back(p);
     *out = static_cast<T*>(p);
     return e;
   }
 };
+
+// workspace bytes per triangle of one build: boxes, keys, tree, jobs, clusters (an upper bound)
+constexpr size_t kBuildBytesPerTri = 208;
 
 }  // namespace
 
@@ -659,7 +847,7 @@ hipError_t gpu_build_bvh4(const float* soup, const uint32_t* prim, const uint32_
                           TriRec* tris, hipStream_t st, GpuBvhStats* stats, int builder) {
   if (n <= 0 || n >= (int64_t)kLeafFirstMask) return hipErrorInvalidValue;
   if (builder != kGpuBvhPloc && builder != kGpuBvhLbvh) return hipErrorInvalidValue;
-  Scratch S;
+  Scratch S((size_t)n * kBuildBytesPerTri + (size_t)256 * 4 * (size_t)((n + kTile - 1) / kTile) + (64u << 10));
   float *tbox = nullptr, *nbox = nullptr;
   uint32_t *cb = nullptr, *keyA = nullptr, *valA = nullptr, *keyB = nullptr, *valB = nullptr, *hist = nullptr;
   uint32_t *counters = nullptr, *cnt = nullptr, *order = nullptr;
@@ -732,7 +920,7 @@ hipError_t gpu_build_bvh4(const float* soup, const uint32_t* prim, const uint32_
     // round with one cluster left copies it unchanged)
     uint32_t m = (uint32_t)n, m_host[2] = {0u, 0u};
     int cur = 0, rounds = 0;
-    while (m > 1) {
+    while (m > (uint32_t)kFinishMax) {
       if (rounds >= kPlocMaxRounds) return hipErrorUnknown;
       const int blocks = (int)((m + kBB - 1) / kBB);
       for (int r = 0; r < kPlocBatch; ++r, ++rounds) {
@@ -753,30 +941,38 @@ hipError_t gpu_build_bvh4(const float* soup, const uint32_t* prim, const uint32_
       if (m_host[0] == 0u || m_host[0] > m) return hipErrorUnknown;  // a round never loses every cluster
       m = m_host[0];
     }
-    hipLaunchKernelGGL(k_root_job, dim3(1), dim3(1), 0, st, cid[cur], jobs[0]);
+    // the last rounds (at most kFinishMax clusters) in one workgroup; it also writes the root's job
+    hipLaunchKernelGGL(k_ploc_finish, dim3(1), dim3(kFinishThreads), 0, st, cid[cur], cbox[cur],
+                       mc + 2 * (rounds & 1), child, nbox, cnt, ncost, counters + 4, (uint32_t)ni, jobs[0],
+                       counters + 3);
   } else {
     const uint4 root = make_uint4(kLeafRef, 0u, 0u, 0u);
     PT_TRY(hipMemcpyAsync(jobs[0], &root, sizeof(root), hipMemcpyHostToDevice, st));
   }
-  // collapse, level by level, from the root
+  // collapse, level by level, from the root; the levels' job counts stay on the device and the host
+  // reads the next one once per batch of levels
   const uint32_t cap = (uint32_t)ni;  // nodes of the output (and jobs of a level) at most
-  const uint32_t one = 1u;
+  uint32_t* jc = nullptr;  // job counts of three consecutive levels, [3]: levels that had jobs
+  PT_TRY(S.get(&jc, 4));
+  const uint32_t one = 1u, jc0[4] = {1u, 0u, 0u, 0u};
   PT_TRY(hipMemcpyAsync(counters, &one, sizeof(one), hipMemcpyHostToDevice, st));
-  uint32_t n_jobs = 1;
-  int levels = 0, cur = 0;
-  while (n_jobs > 0) {
-    if (levels >= kMaxTreeLevels) return hipErrorUnknown;
-    PT_TRY(hipMemsetAsync(counters + 1, 0, sizeof(uint32_t), st));
-    hipLaunchKernelGGL(k_collapse, dim3((n_jobs + kBB - 1) / kBB), dim3(kBB), 0, st, jobs[cur], n_jobs, jobs[cur ^ 1],
-                       counters + 1, counters, counters + 2, valA, tbox, nbox, child, cnt, nodes, cap, (uint32_t)n,
-                       order, counters + 3);
+  PT_TRY(hipMemcpyAsync(jc, jc0, sizeof(jc0), hipMemcpyHostToDevice, st));
+  const int cgrid = grid_of(cap);
+  int level = 0;
+  uint32_t pending[2] = {1u, 0u};
+  while (pending[0] > 0) {
+    for (int r = 0; r < kCollapseBatch; ++r, ++level) {
+      if (level >= kMaxTreeLevels) return hipErrorUnknown;
+      hipLaunchKernelGGL(k_collapse, dim3(cgrid), dim3(kBB), 0, st, jobs[level & 1], jc, level, jobs[(level + 1) & 1],
+                         counters, counters + 2, valA, tbox, nbox, child, cnt, nodes, cap, (uint32_t)n, order,
+                         counters + 3);
+    }
     PT_TRY(hipGetLastError());
-    PT_TRY(hipMemcpyAsync(&n_jobs, counters + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    PT_TRY(hipMemcpyAsync(&pending[0], jc + level % 3, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    PT_TRY(hipMemcpyAsync(&pending[1], jc + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     PT_TRY(hipStreamSynchronize(st));
-    n_jobs = std::min(n_jobs, cap);
-    cur ^= 1;
-    levels++;
   }
+  const int levels = (int)pending[1];
   hipLaunchKernelGGL(k_sorted_tris, dim3(grid_of(n)), dim3(kBB), 0, st, soup, prim, mat, valA, order, n, tris);
   uint32_t fin[4];
   PT_TRY(hipMemcpyAsync(fin, counters, sizeof(fin), hipMemcpyDeviceToHost, st));

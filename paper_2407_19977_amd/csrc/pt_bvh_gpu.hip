@@ -3,7 +3,9 @@
 //
 // Two builders share the first and last steps:
 //   1. triangle boxes, and the centroid bounds by a block reduction;
-//   2. 30-bit Morton codes (10 bits per axis) of the normalised centroids;
+//   2. 30-bit Morton codes (10 bits per axis) of the centroids in cubic
+//      cells (one scale, that of the centroid box's longest side, for all
+//      three axes, so that neighbours along the curve are near in space);
 //   3. an LSD radix sort of (code, index): four 8-bit passes, each a tile
 //      histogram, one scan over (digit, tile) and a stable scatter that ranks
 //      equal digits with wave ballots;
@@ -45,6 +47,9 @@ constexpr int kMaxTreeLevels = 128;          // bound on any walk or level loop 
 #define PT_PLOC_RADIUS 16
 #endif
 constexpr int kPlocRadius = PT_PLOC_RADIUS;  // clusters searched on either side
+#ifndef PT_MORTON_CUBE
+#define PT_MORTON_CUBE 1  // 1: Morton cells are cubes (one scale for the three axes), 0: one scale per axis
+#endif
 constexpr int kPlocMaxRounds = 4096;         // bound on the clustering rounds
 constexpr int kPlocBatch = 8;                // rounds enqueued between two reads of the cluster count
 constexpr int kCollapseBatch = 8;            // collapse levels enqueued between two reads of the job count
@@ -117,11 +122,15 @@ __global__ void k_init_bounds(uint32_t* cb) {
 __global__ __launch_bounds__(kBB) void k_morton(const float* __restrict__ box, int64_t n,
                                                 const uint32_t* __restrict__ cb, uint32_t* __restrict__ key,
                                                 uint32_t* __restrict__ val) {
-  float lo[3], sc[3];
+  float lo[3], sc[3], ext[3], emax = 0.0f;
   for (int k = 0; k < 3; ++k) {
     lo[k] = ord2f(cb[k]);
-    const float ext = ord2f(cb[3 + k]) - lo[k];
-    sc[k] = ext > 0.0f ? 1024.0f / ext : 0.0f;
+    ext[k] = ord2f(cb[3 + k]) - lo[k];
+    emax = fmaxf(emax, ext[k]);
+  }
+  for (int k = 0; k < 3; ++k) {
+    const float e = PT_MORTON_CUBE ? emax : ext[k];
+    sc[k] = e > 0.0f ? 1024.0f / e : 0.0f;
   }
   for (int64_t i = blockIdx.x * (int64_t)kBB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBB) {
     uint32_t q[3];

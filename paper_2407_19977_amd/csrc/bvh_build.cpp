@@ -5,8 +5,14 @@
 // 1. Binned SAH (32 bins per axis on centroid bounds, traversal cost 1,
 //    triangle cost 1) builds a binary tree with at most 4 triangles per leaf;
 //    large subtrees are built on parallel threads.
-// 2. The binary tree is collapsed into a 4-wide tree: a node repeatedly
-//    opens its largest-area internal child until it has four children.
+// 2. The binary tree is collapsed into a 4-wide tree by the least SAH cost
+//    (the dynamic program of Ylitie, Karras and Laine 2017 for wide BVHs):
+//    bottom-up, D(n, j) is the least cost of covering node n's subtree with
+//    at most j roots, a root costing its area times (one node step plus its
+//    children's costs) or, for a leaf, times its triangle count; top-down,
+//    each 4-wide node takes the roots of the best split of its four slots.
+//    (PT_COLLAPSE_DP 0: a node repeatedly opens its largest-area internal
+//    child until it has four children.)
 // 3. Nodes are written in depth-first order as 128-byte records with the four
 //    child boxes stored structure-of-arrays; triangles are written in leaf
 //    order as 48-byte records.
@@ -15,6 +21,7 @@
 #include "bvh_build.h"
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -172,6 +179,14 @@ struct Builder {
   }
 };
 
+#ifndef PT_COLLAPSE_DP
+#define PT_COLLAPSE_DP 1
+#endif
+// cost of a 4-wide node step relative to one triangle test, for the collapse
+#ifndef PT_COLLAPSE_NODE_COST
+#define PT_COLLAPSE_NODE_COST 1.0
+#endif
+
 struct Collapser {
   const std::vector<BNode>* bn;
   const std::vector<int32_t>* idx;
@@ -180,6 +195,63 @@ struct Collapser {
   int max_leaf = 0;
   double sah = 0.0;
   double root_area = 1.0;
+  // optimal collapse: D[n][j] the least SAH cost of covering binary node n's
+  // subtree with at most j roots (j = 1..4), dec[n][j] its split of the j
+  // slots between n's children (0, 0: n itself is the one root), sp[n] the
+  // split of n's four slots when n is a 4-wide node
+  std::vector<std::array<double, 5>> D;
+  std::vector<std::array<std::pair<int8_t, int8_t>, 5>> dec;
+  std::vector<std::pair<int8_t, int8_t>> sp;
+
+  void plan(int32_t b) {
+    const std::vector<BNode>& B = *bn;
+    const BNode& x = B[b];
+    const double a = x.box.area();
+    if (x.count > 0) {
+      for (int j = 1; j <= 4; ++j) {
+        D[b][j] = a * x.count;
+        dec[b][j] = {0, 0};
+      }
+      return;
+    }
+    plan(x.left);
+    plan(x.right);
+    double Ds[5] = {0, 0, 0, 0, 0};
+    std::pair<int8_t, int8_t> ks[5];
+    for (int j = 2; j <= 4; ++j) {
+      Ds[j] = std::numeric_limits<double>::infinity();
+      for (int kl = 1; kl < j; ++kl) {
+        const double c = D[x.left][kl] + D[x.right][j - kl];
+        if (c < Ds[j]) {
+          Ds[j] = c;
+          ks[j] = {(int8_t)kl, (int8_t)(j - kl)};
+        }
+      }
+    }
+    sp[b] = ks[4];
+    D[b][1] = a * PT_COLLAPSE_NODE_COST + Ds[4];
+    dec[b][1] = {0, 0};
+    for (int j = 2; j <= 4; ++j) {
+      if (Ds[j] < D[b][j - 1]) {
+        D[b][j] = Ds[j];
+        dec[b][j] = ks[j];
+      } else {
+        D[b][j] = D[b][j - 1];
+        dec[b][j] = dec[b][j - 1];
+      }
+    }
+  }
+
+  void roots(int32_t b, int j, int32_t* kids, int& nk) const {
+    const std::vector<BNode>& B = *bn;
+    const auto d = dec[b][j];
+    if (B[b].count > 0 || d.first == 0) {
+      kids[nk++] = b;
+      return;
+    }
+    roots(B[b].left, d.first, kids, nk);
+    roots(B[b].right, d.second, kids, nk);
+  }
 
   static void set_box(BVHNode& n, int c, const Box& b) {
     n.lo_x[c] = b.lo[0]; n.hi_x[c] = b.hi[0];
@@ -193,6 +265,9 @@ struct Collapser {
     int nk = 0;
     if (B[b].count > 0) {
       kids[nk++] = b;  // a lone leaf under a single-child root
+    } else if (PT_COLLAPSE_DP) {
+      roots(B[b].left, sp[b].first, kids, nk);
+      roots(B[b].right, sp[b].second, kids, nk);
     } else {
       kids[nk++] = B[b].left;
       kids[nk++] = B[b].right;
@@ -295,6 +370,12 @@ bool build_bvh4(const float* verts, const uint32_t* prim_ids, const uint32_t* ma
   C.idx = &B.idx;
   C.root_area = std::max(B.nodes[root].box.area(), 1e-30);
   C.out.reserve((size_t)n / 2 + 16);
+  if (PT_COLLAPSE_DP) {
+    C.D.resize(B.nodes.size());
+    C.dec.resize(B.nodes.size());
+    C.sp.resize(B.nodes.size(), {0, 0});
+    C.plan(root);
+  }
   C.emit(root, 1);
   out.nodes = std::move(C.out);
   out.depth = C.max_depth;

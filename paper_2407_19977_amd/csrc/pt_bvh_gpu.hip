@@ -19,10 +19,11 @@
 //      whose merged box has the least surface area, mutual nearest
 //      neighbours merge into a new node, the rest are compacted in order,
 //      until one cluster is left (a greedy bottom-up SAH tree);
-//   5. a top-down collapse to 128-byte BVH4 nodes, one launch per level: a
-//      node opens its largest-area children until it has four, subtrees of at
-//      most kMaxLeafTris triangles become leaves, their triangles placed in
-//      depth-first order;
+//   5. a top-down collapse to 128-byte BVH4 nodes, one launch per level, by
+//      least SAH cost (the dynamic program of Ylitie, Karras and Laine 2017,
+//      its costs computed where the binary nodes are made): a 4-wide node
+//      takes the roots of the best split of its four slots; leaf subtrees
+//      place their triangles in depth-first order;
 //   6. the 48-byte triangle records in that (leaf) order.
 // The result has the layout of the host builder's (root at node 0, empty
 // child slots kEmpty with zero boxes, meta[0] = child count); only the tree
@@ -53,6 +54,11 @@ constexpr int kPlocRadius = PT_PLOC_RADIUS;  // clusters searched on either side
 constexpr int kPlocMaxRounds = 4096;         // bound on the clustering rounds
 constexpr int kPlocBatch = 8;                // rounds enqueued between two reads of the cluster count
 constexpr int kCollapseBatch = 8;            // collapse levels enqueued between two reads of the job count
+#ifndef PT_GPU_COLLAPSE_DP
+#define PT_GPU_COLLAPSE_DP 1
+#endif
+// 1: BVH4 nodes by least SAH cost over the binary tree; 0: each node opens its largest-area children
+constexpr bool kGpuCollapseDp = PT_GPU_COLLAPSE_DP != 0;
 #ifndef PT_SAH_TRAVERSAL
 #define PT_SAH_TRAVERSAL 1.0
 #endif
@@ -290,12 +296,73 @@ __device__ inline void ref_box(uint32_t ref, const uint32_t* val, const float* t
   for (int k = 0; k < 6; ++k) b[k] = src[k];
 }
 
+__device__ inline uint32_t ref_count(uint32_t ref, const uint32_t* cnt) {
+  return (ref & kLeafRef) ? 1u : (cnt[ref] & ~kLeafBitCnt);
+}
+
+// the subtree of `ref` becomes one BVH4 leaf
+__device__ inline bool ref_is_leaf_subtree(uint32_t ref, const uint32_t* cnt) {
+  return (ref & kLeafRef) || (cnt[ref] & kLeafBitCnt);
+}
+
+// Collapse by least SAH cost (as the host builder's): per binary node o,
+// dp[4 o + j - 1] is the least cost of covering its subtree with at most
+// j = 1..4 roots (a root costs its area times one node step plus its
+// children's costs, a leaf its area times its triangles), and dsp[o] holds,
+// for j = 2..4 in bits 4 (j - 1) .. 4 (j - 1) + 3, the split of those slots
+// (left count in the low two bits, right count in the high two; 0: the node
+// is the one root), and in bits 16..19 the split of its own four slots when
+// it is a 4-wide node.
+__device__ inline void dp_of_ref(uint32_t ref, const float* dp, float tri_area, float D[4]) {
+  for (int j = 0; j < 4; ++j) D[j] = (ref & kLeafRef) ? tri_area : dp[4 * (size_t)ref + j];
+}
+
+__device__ inline void dp_node(uint32_t o, bool as_leaf, uint32_t c, float area, const float Da[4], const float Db[4],
+                               float* __restrict__ dp, uint32_t* __restrict__ dsp) {
+  if (as_leaf) {
+    for (int j = 0; j < 4; ++j) dp[4 * (size_t)o + j] = (float)c * area;
+    dsp[o] = 0u;
+    return;
+  }
+  float Ds[5];
+  uint32_t ks[5] = {0u, 0u, 0u, 0u, 0u};
+  for (int j = 2; j <= 4; ++j) {
+    Ds[j] = INFINITY;
+    for (int kl = 1; kl < j; ++kl) {
+      const float v = Da[kl - 1] + Db[j - kl - 1];
+      if (v < Ds[j]) {
+        Ds[j] = v;
+        ks[j] = (uint32_t)kl;
+      }
+    }
+  }
+  float best = kSahNode * area + Ds[4];
+  uint32_t dec = 0u, bits = 0u;
+  dp[4 * (size_t)o] = best;
+  for (int j = 2; j <= 4; ++j) {
+    if (Ds[j] < best) {
+      best = Ds[j];
+      dec = ks[j] | ((uint32_t)(j - (int)ks[j]) << 2);
+    }
+    dp[4 * (size_t)o + j - 1] = best;
+    bits |= dec << (4 * (j - 1));
+  }
+  bits |= (ks[4] | ((4u - ks[4]) << 2)) << 16;
+  dsp[o] = bits;
+}
+
+__device__ inline float half_area(const float b[6]) {
+  const float dx = b[3] - b[0], dy = b[4] - b[1], dz = b[5] - b[2];
+  return dx * dy + dy * dz + dz * dx;
+}
+
 // boxes bottom-up: the second arrival at a node merges both children's boxes
 __global__ __launch_bounds__(kBB) void k_boxes_up(int64_t n, const uint32_t* __restrict__ val,
                                                   const float* __restrict__ tbox, const uint2* __restrict__ child,
                                                   const int32_t* __restrict__ parent_leaf,
                                                   const int32_t* __restrict__ parent_int, float* nbox,
-                                                  uint32_t* flag) {
+                                                  uint32_t* flag, const uint32_t* __restrict__ cnt, float* dp,
+                                                  uint32_t* dsp) {
   for (int64_t i = blockIdx.x * (int64_t)kBB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBB) {
     int32_t p = n > 1 ? parent_leaf[i] : -1;
     // a radix tree over 30-bit codes and 32-bit indices is at most 63 levels deep; the bound only
@@ -307,27 +374,21 @@ __global__ __launch_bounds__(kBB) void k_boxes_up(int64_t n, const uint32_t* __r
       float a[6], b[6];
       ref_box(c.x, val, tbox, nbox, a);
       ref_box(c.y, val, tbox, nbox, b);
+      float u[6];
       for (int k = 0; k < 3; ++k) {
-        nbox[6 * (size_t)p + k] = fminf(a[k], b[k]);
-        nbox[6 * (size_t)p + 3 + k] = fmaxf(a[3 + k], b[3 + k]);
+        u[k] = fminf(a[k], b[k]);
+        u[3 + k] = fmaxf(a[3 + k], b[3 + k]);
+        nbox[6 * (size_t)p + k] = u[k];
+        nbox[6 * (size_t)p + 3 + k] = u[3 + k];
       }
+      float Da[4], Db[4];
+      dp_of_ref(c.x, dp, half_area(a), Da);
+      dp_of_ref(c.y, dp, half_area(b), Db);
+      const uint32_t cp = cnt[p];
+      dp_node((uint32_t)p, (cp & kLeafBitCnt) != 0u, cp & ~kLeafBitCnt, half_area(u), Da, Db, dp, dsp);
       p = parent_int[p];
     }
   }
-}
-
-__device__ inline uint32_t ref_count(uint32_t ref, const uint32_t* cnt) {
-  return (ref & kLeafRef) ? 1u : (cnt[ref] & ~kLeafBitCnt);
-}
-
-// the subtree of `ref` becomes one BVH4 leaf
-__device__ inline bool ref_is_leaf_subtree(uint32_t ref, const uint32_t* cnt) {
-  return (ref & kLeafRef) || (cnt[ref] & kLeafBitCnt);
-}
-
-__device__ inline float half_area(const float b[6]) {
-  const float dx = b[3] - b[0], dy = b[4] - b[1], dz = b[5] - b[2];
-  return dx * dy + dy * dz + dz * dx;
 }
 
 // ---- 4b. locally-ordered clustering.  Cluster i of a round: a binary-tree
@@ -409,6 +470,7 @@ __global__ __launch_bounds__(kBB) void k_ploc_merge(uint32_t* __restrict__ cid, 
                                                     const uint32_t* __restrict__ mc, const int32_t* __restrict__ nn,
                                                     uint2* __restrict__ child, float* __restrict__ nbox,
                                                     uint32_t* __restrict__ cnt, float* __restrict__ ncost,
+                                                    float* __restrict__ dp, uint32_t* __restrict__ dsp,
                                                     uint32_t* __restrict__ n_int, uint32_t cap,
                                                     uint32_t* __restrict__ keep, uint32_t* __restrict__ err) {
   const uint32_t m = mc[0];
@@ -446,6 +508,10 @@ __global__ __launch_bounds__(kBB) void k_ploc_merge(uint32_t* __restrict__ cid, 
     const float split = kSahNode * area + ca + cb, leaf = (float)c * area;
     const bool as_leaf = c <= (uint32_t)kMaxLeafTris && leaf <= split;
     ncost[o] = as_leaf ? leaf : split;
+    float Da[4], Db[4];
+    dp_of_ref(a, dp, half_area(ba), Da);
+    dp_of_ref(b, dp, half_area(bb), Db);
+    dp_node(o, as_leaf, c, area, Da, Db, dp, dsp);
     child[o] = make_uint2(a, b);
     cnt[o] = as_leaf ? (c | kLeafBitCnt) : c;
     cid[i] = o;
@@ -528,6 +594,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_ploc_finish(const uint32_t* 
                                                                 const uint32_t* __restrict__ mc,
                                                                 uint2* __restrict__ child, float* __restrict__ nbox,
                                                                 uint32_t* __restrict__ cnt, float* __restrict__ ncost,
+                                                                float* __restrict__ dp, uint32_t* __restrict__ dsp,
                                                                 uint32_t* __restrict__ n_int, uint32_t cap,
                                                                 uint4* __restrict__ jobs, uint32_t* __restrict__ err) {
   __shared__ float sb[kFinishMax * 6];
@@ -623,6 +690,10 @@ __global__ __launch_bounds__(kFinishThreads) void k_ploc_finish(const uint32_t* 
       const float split = kSahNode * area + ca + cb, leaf = (float)c * area;
       const bool as_leaf = c <= (uint32_t)kMaxLeafTris && leaf <= split;
       ncost[o] = as_leaf ? leaf : split;
+      float Da[4], Db[4];
+      dp_of_ref(a, dp, half_area(ba), Da);
+      dp_of_ref(b, dp, half_area(bb), Db);
+      dp_node(o, as_leaf, c, area, Da, Db, dp, dsp);
       child[o] = make_uint2(a, b);
       cnt[o] = as_leaf ? (c | kLeafBitCnt) : c;
       sid[i] = o;
@@ -669,12 +740,43 @@ __device__ inline void collapse_one(const uint4 job, uint4* __restrict__ next_jo
                                     uint32_t* __restrict__ n_nodes, uint32_t* __restrict__ max_leaf,
                                     const uint32_t* __restrict__ val, const float* __restrict__ tbox,
                                     const float* __restrict__ nbox, const uint2* __restrict__ child,
-                                    const uint32_t* __restrict__ cnt, BVHNode* __restrict__ out, uint32_t cap,
-                                    uint32_t n_tris, uint32_t* __restrict__ order, uint32_t* __restrict__ err) {
+                                    const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ dsp,
+                                    BVHNode* __restrict__ out, uint32_t cap, uint32_t n_tris,
+                                    uint32_t* __restrict__ order, uint32_t* __restrict__ err) {
   uint32_t kids[4];
   int nk = 0;
   if (ref_is_leaf_subtree(job.x, cnt)) {
     kids[nk++] = job.x;  // the whole tree is one leaf under a one-child root
+  } else if (kGpuCollapseDp) {
+    // the roots of the best split of the node's four slots, left before right
+    // (the slots of the entries on the stack never add up to more than four)
+    const uint2 c = child[job.x];
+    const uint32_t s4 = dsp[job.x] >> 16;
+    uint32_t stk_ref[4], stk_j[4];
+    int sp = 0;
+    stk_ref[sp] = c.y;
+    stk_j[sp++] = s4 >> 2;
+    stk_ref[sp] = c.x;
+    stk_j[sp++] = s4 & 3u;
+    while (sp > 0 && nk < 4) {
+      --sp;
+      const uint32_t y = stk_ref[sp], j = stk_j[sp];
+      if (ref_is_leaf_subtree(y, cnt) || j <= 1u || j > 4u) {
+        kids[nk++] = y;
+        continue;
+      }
+      const uint32_t d = (dsp[y] >> (4u * (j - 1u))) & 15u;
+      if ((d & 3u) == 0u || sp + 2 > 4) {
+        kids[nk++] = y;
+        continue;
+      }
+      const uint2 cc = child[y];
+      stk_ref[sp] = cc.y;
+      stk_j[sp++] = d >> 2;
+      stk_ref[sp] = cc.x;
+      stk_j[sp++] = d & 3u;
+    }
+    if (sp > 0) atomicOr(err, 32u);  // more roots than four slots: a malformed split
   } else {
     const uint2 c = child[job.x];
     kids[nk++] = c.x;
@@ -780,16 +882,17 @@ __global__ __launch_bounds__(kBB) void k_collapse(const uint4* __restrict__ jobs
                                                   uint32_t* __restrict__ max_leaf, const uint32_t* __restrict__ val,
                                                   const float* __restrict__ tbox, const float* __restrict__ nbox,
                                                   const uint2* __restrict__ child, const uint32_t* __restrict__ cnt,
-                                                  BVHNode* __restrict__ out, uint32_t cap, uint32_t n_tris,
-                                                  uint32_t* __restrict__ order, uint32_t* __restrict__ err) {
+                                                  const uint32_t* __restrict__ dsp, BVHNode* __restrict__ out,
+                                                  uint32_t cap, uint32_t n_tris, uint32_t* __restrict__ order,
+                                                  uint32_t* __restrict__ err) {
   const uint32_t n_jobs = min(jc[level % 3], cap);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     jc[(level + 2) % 3] = 0u;
     if (n_jobs) atomicMax(jc + 3, (uint32_t)(level + 1));
   }
   for (uint32_t j = blockIdx.x * kBB + threadIdx.x; j < n_jobs; j += gridDim.x * kBB)
-    collapse_one(jobs[j], next_jobs, jc + (level + 1) % 3, n_nodes, max_leaf, val, tbox, nbox, child, cnt, out, cap,
-                 n_tris, order, err);
+    collapse_one(jobs[j], next_jobs, jc + (level + 1) % 3, n_nodes, max_leaf, val, tbox, nbox, child, cnt, dsp, out,
+                 cap, n_tris, order, err);
 }
 
 // 6. triangle records in leaf order
@@ -842,7 +945,7 @@ struct Scratch {
 };
 
 // workspace bytes per triangle of one build: boxes, keys, tree, jobs, clusters (an upper bound)
-constexpr size_t kBuildBytesPerTri = 208;
+constexpr size_t kBuildBytesPerTri = 232;
 
 }  // namespace
 
@@ -877,6 +980,10 @@ hipError_t gpu_build_bvh4(const float* soup, const uint32_t* prim, const uint32_
   PT_TRY(S.get(&counters, 8));
   PT_TRY(S.get(&child, (size_t)ni));
   PT_TRY(S.get(&cnt, (size_t)ni));
+  float* dp = nullptr;
+  uint32_t* dsp = nullptr;
+  PT_TRY(S.get(&dp, (size_t)ni * 4));
+  PT_TRY(S.get(&dsp, (size_t)ni));
   PT_TRY(S.get(&order, (size_t)n));
   PT_TRY(S.get(&jobs[0], (size_t)n));
   PT_TRY(S.get(&jobs[1], (size_t)n));
@@ -904,7 +1011,7 @@ hipError_t gpu_build_bvh4(const float* soup, const uint32_t* prim, const uint32_
     hipLaunchKernelGGL(k_radix_tree, dim3(grid_of(n - 1)), dim3(kBB), 0, st, keyA, n, child, parent_leaf, parent_int,
                        cnt, counters + 3);
     hipLaunchKernelGGL(k_boxes_up, dim3(grid_of(n)), dim3(kBB), 0, st, n, valA, tbox, child, parent_leaf, parent_int,
-                       nbox, flag);
+                       nbox, flag, cnt, dp, dsp);
     const uint4 root = make_uint4(0u, 0u, 0u, 0u);
     PT_TRY(hipMemcpyAsync(jobs[0], &root, sizeof(root), hipMemcpyHostToDevice, st));
   } else if (n > 1) {
@@ -937,7 +1044,7 @@ hipError_t gpu_build_bvh4(const float* soup, const uint32_t* prim, const uint32_
         uint32_t* mc_out = mc + 2 * ((rounds & 1) ^ 1);
         hipLaunchKernelGGL(k_ploc_nn, dim3(blocks), dim3(kBB), 0, st, cbox[cur], mc_in, nn);
         hipLaunchKernelGGL(k_ploc_merge, dim3(grid_of(m)), dim3(kBB), 0, st, cid[cur], cbox[cur], mc_in, nn, child,
-                           nbox, cnt, ncost, counters + 4, (uint32_t)ni, keep, counters + 3);
+                           nbox, cnt, ncost, dp, dsp, counters + 4, (uint32_t)ni, keep, counters + 3);
         hipLaunchKernelGGL(k_ploc_count, dim3(blocks), dim3(kBB), 0, st, keep, mc_in, bc);
         hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, bc, (int64_t)blocks);
         hipLaunchKernelGGL(k_ploc_scatter, dim3(blocks), dim3(kBB), 0, st, cid[cur], cbox[cur], keep, mc_in, bc,
@@ -952,7 +1059,7 @@ hipError_t gpu_build_bvh4(const float* soup, const uint32_t* prim, const uint32_
     }
     // the last rounds (at most kFinishMax clusters) in one workgroup; it also writes the root's job
     hipLaunchKernelGGL(k_ploc_finish, dim3(1), dim3(kFinishThreads), 0, st, cid[cur], cbox[cur],
-                       mc + 2 * (rounds & 1), child, nbox, cnt, ncost, counters + 4, (uint32_t)ni, jobs[0],
+                       mc + 2 * (rounds & 1), child, nbox, cnt, ncost, dp, dsp, counters + 4, (uint32_t)ni, jobs[0],
                        counters + 3);
   } else {
     const uint4 root = make_uint4(kLeafRef, 0u, 0u, 0u);
@@ -973,7 +1080,7 @@ hipError_t gpu_build_bvh4(const float* soup, const uint32_t* prim, const uint32_
     for (int r = 0; r < kCollapseBatch; ++r, ++level) {
       if (level >= kMaxTreeLevels) return hipErrorUnknown;
       hipLaunchKernelGGL(k_collapse, dim3(cgrid), dim3(kBB), 0, st, jobs[level & 1], jc, level, jobs[(level + 1) & 1],
-                         counters, counters + 2, valA, tbox, nbox, child, cnt, nodes, cap, (uint32_t)n, order,
+                         counters, counters + 2, valA, tbox, nbox, child, cnt, dsp, nodes, cap, (uint32_t)n, order,
                          counters + 3);
     }
     PT_TRY(hipGetLastError());

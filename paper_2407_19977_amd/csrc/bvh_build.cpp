@@ -21,13 +21,13 @@
 #include "bvh_build.h"
 
 #include <algorithm>
-#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <future>
 #include <limits>
+#include <memory>
 
 namespace pt {
 namespace {
@@ -195,62 +195,72 @@ struct Collapser {
   int max_leaf = 0;
   double sah = 0.0;
   double root_area = 1.0;
-  // optimal collapse: D[n][j] the least SAH cost of covering binary node n's
-  // subtree with at most j roots (j = 1..4), dec[n][j] its split of the j
-  // slots between n's children (0, 0: n itself is the one root), sp[n] the
-  // split of n's four slots when n is a 4-wide node
-  std::vector<std::array<double, 5>> D;
-  std::vector<std::array<std::pair<int8_t, int8_t>, 5>> dec;
-  std::vector<std::pair<int8_t, int8_t>> sp;
+  // optimal collapse: D[4 n + j - 1] the least SAH cost of covering binary
+  // node n's subtree with at most j roots (j = 1..4); dec[n] packs, for
+  // j = 2..4 in bits 4 (j - 1) .. 4 (j - 1) + 3, the split of the j slots
+  // between n's children (left count in the low two bits, right count in the
+  // high two; 0: n itself is the one root), and in bits 16..19 the split of
+  // n's four slots when n is a 4-wide node (uninitialised storage: every
+  // planned node is written once)
+  std::unique_ptr<float[]> D;
+  std::unique_ptr<uint32_t[]> dec;
 
-  void plan(int32_t b) {
+  // the top levels' subtrees are planned on parallel threads (as they were built)
+  void plan(int32_t b, int level = 0) {
     const std::vector<BNode>& B = *bn;
     const BNode& x = B[b];
     const double a = x.box.area();
     if (x.count > 0) {
-      for (int j = 1; j <= 4; ++j) {
-        D[b][j] = a * x.count;
-        dec[b][j] = {0, 0};
-      }
+      for (int j = 0; j < 4; ++j) D[4 * (size_t)b + j] = (float)(a * x.count);
+      dec[b] = 0u;
       return;
     }
-    plan(x.left);
-    plan(x.right);
-    double Ds[5] = {0, 0, 0, 0, 0};
-    std::pair<int8_t, int8_t> ks[5];
+    if (level < 4) {
+      auto fl = std::async(std::launch::async, [&] { plan(x.left, level + 1); });
+      plan(x.right, level + 1);
+      fl.get();
+    } else {
+      plan(x.left, level + 1);
+      plan(x.right, level + 1);
+    }
+    const float* Dl = &D[4 * (size_t)x.left];
+    const float* Dr = &D[4 * (size_t)x.right];
+    float Ds[5] = {0, 0, 0, 0, 0};
+    uint32_t ks[5] = {0, 0, 0, 0, 0};
     for (int j = 2; j <= 4; ++j) {
-      Ds[j] = std::numeric_limits<double>::infinity();
+      Ds[j] = std::numeric_limits<float>::infinity();
       for (int kl = 1; kl < j; ++kl) {
-        const double c = D[x.left][kl] + D[x.right][j - kl];
+        const float c = Dl[kl - 1] + Dr[j - kl - 1];
         if (c < Ds[j]) {
           Ds[j] = c;
-          ks[j] = {(int8_t)kl, (int8_t)(j - kl)};
+          ks[j] = (uint32_t)kl | ((uint32_t)(j - kl) << 2);
         }
       }
     }
-    sp[b] = ks[4];
-    D[b][1] = a * PT_COLLAPSE_NODE_COST + Ds[4];
-    dec[b][1] = {0, 0};
+    float best = (float)(a * PT_COLLAPSE_NODE_COST) + Ds[4];
+    uint32_t d = 0u, bits = ks[4] << 16;
+    D[4 * (size_t)b] = best;
     for (int j = 2; j <= 4; ++j) {
-      if (Ds[j] < D[b][j - 1]) {
-        D[b][j] = Ds[j];
-        dec[b][j] = ks[j];
-      } else {
-        D[b][j] = D[b][j - 1];
-        dec[b][j] = dec[b][j - 1];
+      if (Ds[j] < best) {
+        best = Ds[j];
+        d = ks[j];
       }
+      D[4 * (size_t)b + j - 1] = best;
+      bits |= d << (4 * (j - 1));
     }
+    dec[b] = bits;
   }
 
+  // the roots that cover binary node b's subtree with at most j of them
   void roots(int32_t b, int j, int32_t* kids, int& nk) const {
     const std::vector<BNode>& B = *bn;
-    const auto d = dec[b][j];
-    if (B[b].count > 0 || d.first == 0) {
+    const uint32_t d = j >= 2 ? (dec[b] >> (4 * (j - 1))) & 15u : 0u;
+    if (B[b].count > 0 || (d & 3u) == 0u) {
       kids[nk++] = b;
       return;
     }
-    roots(B[b].left, d.first, kids, nk);
-    roots(B[b].right, d.second, kids, nk);
+    roots(B[b].left, (int)(d & 3u), kids, nk);
+    roots(B[b].right, (int)(d >> 2), kids, nk);
   }
 
   static void set_box(BVHNode& n, int c, const Box& b) {
@@ -266,8 +276,9 @@ struct Collapser {
     if (B[b].count > 0) {
       kids[nk++] = b;  // a lone leaf under a single-child root
     } else if (PT_COLLAPSE_DP) {
-      roots(B[b].left, sp[b].first, kids, nk);
-      roots(B[b].right, sp[b].second, kids, nk);
+      const uint32_t s4 = dec[b] >> 16;
+      roots(B[b].left, (int)(s4 & 3u), kids, nk);
+      roots(B[b].right, (int)(s4 >> 2), kids, nk);
     } else {
       kids[nk++] = B[b].left;
       kids[nk++] = B[b].right;
@@ -371,9 +382,8 @@ bool build_bvh4(const float* verts, const uint32_t* prim_ids, const uint32_t* ma
   C.root_area = std::max(B.nodes[root].box.area(), 1e-30);
   C.out.reserve((size_t)n / 2 + 16);
   if (PT_COLLAPSE_DP) {
-    C.D.resize(B.nodes.size());
-    C.dec.resize(B.nodes.size());
-    C.sp.resize(B.nodes.size(), {0, 0});
+    C.D.reset(new float[4 * B.nodes.size()]);
+    C.dec.reset(new uint32_t[B.nodes.size()]);
     C.plan(root);
   }
   C.emit(root, 1);

@@ -28,6 +28,8 @@
 #include <future>
 #include <limits>
 #include <memory>
+#include <mutex>
+#include <utility>
 
 namespace pt {
 namespace {
@@ -59,11 +61,43 @@ struct Box {
   }
 };
 
-struct BNode {
+struct BNode {  // trivial, so that its storage is not initialised before the build writes it
   Box box;
-  int32_t left = -1, right = -1;
-  int32_t first = 0, count = 0;  // count > 0: leaf
+  int32_t left, right;
+  int32_t first, count;  // count > 0: leaf
 };
+
+// vector storage whose resize leaves trivial elements uninitialised
+template <class T>
+struct DefaultInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = DefaultInitAlloc<U>;
+  };
+  DefaultInitAlloc() = default;
+  template <class U>
+  DefaultInitAlloc(const DefaultInitAlloc<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept {
+    ::new ((void*)p) U;
+  }
+  template <class U, class... A>
+  void construct(U* p, A&&... a) {
+    ::new ((void*)p) U(std::forward<A>(a)...);
+  }
+};
+using BNodeVec = std::vector<BNode, DefaultInitAlloc<BNode>>;
+
+// Run f(begin, end) over [0, n) in up to 16 chunks on parallel threads.
+template <class F>
+void parallel_chunks(int64_t n, F&& f) {
+  const int64_t chunks = std::min<int64_t>(16, std::max<int64_t>(1, n / 65536));
+  std::vector<std::future<void>> fs;
+  for (int64_t c = 1; c < chunks; ++c)
+    fs.push_back(std::async(std::launch::async, [&, c] { f(n * c / chunks, n * (c + 1) / chunks); }));
+  f(0, n / chunks);
+  for (auto& x : fs) x.get();
+}
 
 constexpr int kBins = 32;
 #ifndef PT_SAH_TRAVERSAL
@@ -71,11 +105,19 @@ constexpr int kBins = 32;
 #endif
 constexpr double kSahTraversal = PT_SAH_TRAVERSAL;  // cost of a node step relative to one triangle test
 
+// A triangle's box, centroid and index, moved with the partitions so that a
+// node's passes read its triangles in sequence (the partitions swap the same
+// positions as partitions of the bare indices would: the tree is the same).
+struct PrimRef {
+  Box box;
+  float c[3];
+  int32_t t;
+};
+
 struct Builder {
-  const std::vector<Box>* tb;
-  const std::vector<float>* cen;  // [n][3]
-  std::vector<int32_t> idx;
-  std::vector<BNode> nodes;
+  std::vector<PrimRef> pr;
+  std::vector<int32_t> idx;  // the triangles in leaf order, filled after the build
+  BNodeVec nodes;
   std::atomic<int32_t> next{0};
 
   int32_t alloc() { return next.fetch_add(1); }
@@ -83,13 +125,14 @@ struct Builder {
   int32_t build(int32_t first, int32_t count, int level) {
     int32_t id = alloc();
     BNode nd;
+    nd.left = nd.right = -1;
+    nd.first = nd.count = 0;
     Box cb;
     nd.box.clear();
     cb.clear();
     for (int32_t i = first; i < first + count; ++i) {
-      int32_t t = idx[i];
-      nd.box.grow((*tb)[t]);
-      cb.grow(&(*cen)[3 * (size_t)t]);
+      nd.box.grow(pr[(size_t)i].box);
+      cb.grow(pr[(size_t)i].c);
     }
     int best_axis = -1, best_bin = -1;
     double best_cost = std::numeric_limits<double>::infinity();
@@ -105,10 +148,10 @@ struct Builder {
       }
       double scale = kBins / (double)ext;
       for (int32_t i = first; i < first + count; ++i) {
-        int32_t t = idx[i];
-        int b = (int)(((double)(*cen)[3 * (size_t)t + ax] - cb.lo[ax]) * scale);
+        const PrimRef& q = pr[(size_t)i];
+        int b = (int)(((double)q.c[ax] - cb.lo[ax]) * scale);
         b = std::min(std::max(b, 0), kBins - 1);
-        bb[b].grow((*tb)[t]);
+        bb[b].grow(q.box);
         bc[b]++;
       }
       double ra[kBins];
@@ -151,12 +194,12 @@ struct Builder {
       float ext = cb.hi[best_axis] - cb.lo[best_axis];
       double scale = kBins / (double)ext;
       int ax = best_axis, sb = best_bin;
-      auto it = std::partition(idx.begin() + first, idx.begin() + first + count, [&](int32_t t) {
-        int b = (int)(((double)(*cen)[3 * (size_t)t + ax] - cb.lo[ax]) * scale);
+      auto it = std::partition(pr.begin() + first, pr.begin() + first + count, [&](const PrimRef& q) {
+        int b = (int)(((double)q.c[ax] - cb.lo[ax]) * scale);
         b = std::min(std::max(b, 0), kBins - 1);
         return b <= sb;
       });
-      mid = (int32_t)(it - idx.begin());
+      mid = (int32_t)(it - pr.begin());
       if (mid == first || mid == first + count) mid = first + count / 2;
     } else {
       // all centroids coincide: split the range in half
@@ -188,7 +231,7 @@ struct Builder {
 #endif
 
 struct Collapser {
-  const std::vector<BNode>* bn;
+  const BNodeVec* bn;
   const std::vector<int32_t>* idx;
   std::vector<BVHNode> out;
   int max_depth = 0;
@@ -207,7 +250,7 @@ struct Collapser {
 
   // the top levels' subtrees are planned on parallel threads (as they were built)
   void plan(int32_t b, int level = 0) {
-    const std::vector<BNode>& B = *bn;
+    const BNodeVec& B = *bn;
     const BNode& x = B[b];
     const double a = x.box.area();
     if (x.count > 0) {
@@ -253,7 +296,7 @@ struct Collapser {
 
   // the roots that cover binary node b's subtree with at most j of them
   void roots(int32_t b, int j, int32_t* kids, int& nk) const {
-    const std::vector<BNode>& B = *bn;
+    const BNodeVec& B = *bn;
     const uint32_t d = j >= 2 ? (dec[b] >> (4 * (j - 1))) & 15u : 0u;
     if (B[b].count > 0 || (d & 3u) == 0u) {
       kids[nk++] = b;
@@ -270,7 +313,7 @@ struct Collapser {
   }
 
   uint32_t emit(int32_t b, int depth) {
-    const std::vector<BNode>& B = *bn;
+    const BNodeVec& B = *bn;
     int32_t kids[4];
     int nk = 0;
     if (B[b].count > 0) {
@@ -346,35 +389,44 @@ bool build_bvh4(const float* verts, const uint32_t* prim_ids, const uint32_t* ma
     err = "too many triangles for one BVH (limit 2^27 - 1)";
     return false;
   }
-  std::vector<Box> tb((size_t)n);
-  std::vector<float> cen(3 * (size_t)n);
+  Builder B;
+  B.pr.resize((size_t)n);
   Box all;
   all.clear();
-  for (int64_t t = 0; t < n; ++t) {
-    Box b;
-    b.clear();
-    for (int v = 0; v < 3; ++v) {
-      const float* p = verts + 9 * t + 3 * v;
-      for (int k = 0; k < 3; ++k) {
-        if (!std::isfinite(p[k])) {
-          err = "non-finite vertex";
-          return false;
-        }
+  std::mutex mu;
+  bool finite = true;
+  parallel_chunks(n, [&](int64_t t0c, int64_t t1c) {
+    Box part;
+    part.clear();
+    bool ok = true;
+    for (int64_t t = t0c; t < t1c; ++t) {
+      Box b;
+      b.clear();
+      for (int v = 0; v < 3; ++v) {
+        const float* p = verts + 9 * t + 3 * v;
+        for (int k = 0; k < 3; ++k) ok = ok && std::isfinite(p[k]);
+        b.grow(p);
       }
-      b.grow(p);
+      PrimRef& q = B.pr[(size_t)t];
+      q.box = b;
+      for (int k = 0; k < 3; ++k) q.c[k] = 0.5f * (b.lo[k] + b.hi[k]);
+      q.t = (int32_t)t;
+      part.grow(b);
     }
-    tb[(size_t)t] = b;
-    all.grow(b);
-    for (int k = 0; k < 3; ++k) cen[3 * (size_t)t + k] = 0.5f * (b.lo[k] + b.hi[k]);
+    std::lock_guard<std::mutex> g(mu);
+    finite = finite && ok;
+    all.grow(part);
+  });
+  if (!finite) {
+    err = "non-finite vertex";
+    return false;
   }
-  Builder B;
-  B.tb = &tb;
-  B.cen = &cen;
-  B.idx.resize((size_t)n);
-  for (int64_t i = 0; i < n; ++i) B.idx[(size_t)i] = (int32_t)i;
   B.nodes.resize(2 * (size_t)n + 1);
   int32_t root = B.build(0, (int32_t)n, 0);
   B.nodes.resize((size_t)B.next.load());
+  B.idx.resize((size_t)n);
+  for (int64_t i = 0; i < n; ++i) B.idx[(size_t)i] = B.pr[(size_t)i].t;
+  std::vector<PrimRef>().swap(B.pr);
 
   Collapser C;
   C.bn = &B.nodes;
@@ -392,18 +444,20 @@ bool build_bvh4(const float* verts, const uint32_t* prim_ids, const uint32_t* ma
   out.max_leaf = C.max_leaf;
   out.sah_cost = C.sah;
   out.tris.resize((size_t)n);
-  for (int64_t i = 0; i < n; ++i) {
-    int32_t t = B.idx[(size_t)i];
-    const float* p = verts + 9 * (size_t)t;
-    TriRec r;
-    r.a = make_float4(p[0], p[1], p[2], 0.0f);
-    r.b = make_float4(p[3], p[4], p[5], 0.0f);
-    r.c = make_float4(p[6], p[7], p[8], 0.0f);
-    uint32_t pid = prim_ids[t], mid = mat_ids[t];
-    std::memcpy(&r.a.w, &pid, 4);
-    std::memcpy(&r.b.w, &mid, 4);
-    out.tris[(size_t)i] = r;
-  }
+  parallel_chunks(n, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
+      int32_t t = B.idx[(size_t)i];
+      const float* p = verts + 9 * (size_t)t;
+      TriRec r;
+      r.a = make_float4(p[0], p[1], p[2], 0.0f);
+      r.b = make_float4(p[3], p[4], p[5], 0.0f);
+      r.c = make_float4(p[6], p[7], p[8], 0.0f);
+      uint32_t pid = prim_ids[t], mid = mat_ids[t];
+      std::memcpy(&r.a.w, &pid, 4);
+      std::memcpy(&r.b.w, &mid, 4);
+      out.tris[(size_t)i] = r;
+    }
+  });
   for (int k = 0; k < 3; ++k) {
     out.lo[k] = all.lo[k];
     out.hi[k] = all.hi[k];
